@@ -1,0 +1,149 @@
+"""Pins for oracle.etd (Section 3 of the paper).
+
+* C = 0: ETD1 is forward Euler, ETD2RK is Heun's method (closed forms).
+* F = 0: one step is e^{hC} U (eigendecomposition route).
+* F independent of U and polynomial in t: ETD1 exact for constant F, ETD2RK
+  exact for linear F, ETD3RK / ETD4RK exact for quadratic F (exact solution
+  by the eigendecomposition of C and exact integrals).
+* Logistic reaction: step-halving shows order 1 (ETD1) and 2 (ETD2RK).
+* Section 4.2.1 peanut problem: second-order convergence and errors of the
+  size printed in Table 1 (tests/golden/table1_etd2rk.json).
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+import sympy
+
+from oracle.etd import etd1_step, etd2rk_step, etd3rk_step, etd4rk_step, logistic
+from oracle.geometry import Grid
+from oracle.operator import build_operator
+from oracle.phi import phi_combination, phi_scalar
+from paper_2209_15095_amd.inputs import peanut_level_set
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "table1_etd2rk.json")
+
+
+def _spd(n, seed, scale=5.0):
+    rng = np.random.default_rng(seed)
+    B = rng.standard_normal((n, n))
+    return -(B @ B.T) / n * scale
+
+
+def test_zero_operator_reduces_to_euler_and_heun():
+    n = 7
+    A = np.zeros((n, n))
+    rng = np.random.default_rng(0)
+    U = rng.uniform(0.1, 0.9, n)
+    f, _ = logistic(1.0, 1.0)
+    h = 0.3
+    assert np.allclose(etd1_step(A, h, U, f), U + h * f(U), rtol=1e-14, atol=1e-15)
+    heun = U + 0.5 * h * (f(U) + f(U + h * f(U)))
+    assert np.allclose(etd2rk_step(A, h, U, f), heun, rtol=1e-14, atol=1e-15)
+
+
+def test_zero_reaction_is_exponential():
+    A = _spd(20, 1)
+    U = np.random.default_rng(1).standard_normal(20)
+    lam, Q = np.linalg.eigh(A)
+    h = 0.37
+    exact = Q @ (np.exp(h * lam) * (Q.T @ U))
+    zero = lambda u, t=0.0: np.zeros_like(u)
+    for step in (etd1_step, etd2rk_step, etd3rk_step, etd4rk_step):
+        assert np.linalg.norm(step(A, h, U, zero) - exact) < 1e-13 * np.linalg.norm(exact)
+
+
+def _exact_poly_forcing(A, h, U, cs, t0):
+    """Exact U(t0+h) for U' = A U + sum_j cs[j] t^j (t absolute)."""
+    lam, Q = np.linalg.eigh(A)
+    # rewrite sum_j c_j (t0 + s)^j = sum_k d_k s^k, then
+    # U(h) = e^{hA}U + sum_k k! h^{k+1} phi_{k+1}(hA) d_k
+    deg = len(cs) - 1
+    d = [np.zeros_like(U) for _ in range(deg + 1)]
+    for j, c in enumerate(cs):
+        for k in range(j + 1):
+            d[k] = d[k] + math.comb(j, k) * t0 ** (j - k) * c
+    out = Q @ (np.exp(h * lam) * (Q.T @ U))
+    for k in range(deg + 1):
+        out += math.factorial(k) * h ** (k + 1) * (Q @ (phi_scalar(k + 1, h * lam) * (Q.T @ d[k])))
+    return out
+
+
+@pytest.mark.parametrize("step,deg", [(etd1_step, 0), (etd2rk_step, 1), (etd3rk_step, 2), (etd4rk_step, 2)])
+def test_exact_for_polynomial_forcing(step, deg):
+    n = 15
+    A = _spd(n, 2)
+    rng = np.random.default_rng(3)
+    U = rng.standard_normal(n)
+    cs = [rng.standard_normal(n) for _ in range(deg + 1)]
+    t0, h = 0.4, 0.25
+    F = lambda u, t: sum(c * t ** j for j, c in enumerate(cs))
+    got = step(A, h, U, F, t0)
+    ref = _exact_poly_forcing(A, h, U, cs, t0)
+    assert np.linalg.norm(got - ref) < 1e-12 * np.linalg.norm(ref)
+
+
+def test_logistic_temporal_orders():
+    g = Grid(2, (24, 24), (-1.5, -1.5), (1.5, 1.5))
+    X, Y = g.coords()
+    op = build_operator(g, np.hypot(X, Y) - 1.0, 1.0)
+    f, _ = logistic(1.0, 1.0)
+    U0 = op.gather(0.5 + 0.3 * np.cos(X) * np.sin(2 * Y))
+    T = 0.4
+
+    def run(step, nsteps):
+        U = U0.copy()
+        for _ in range(nsteps):
+            U = step(op.A, T / nsteps, U, f)
+        return U
+
+    for step, order in [(etd1_step, 1.0), (etd2rk_step, 2.0)]:
+        ref = run(step, 64)
+        e1 = np.linalg.norm(run(step, 4) - ref)
+        e2 = np.linalg.norm(run(step, 8) - ref)
+        assert abs(np.log2(e1 / e2) - order) < 0.25
+
+
+def _peanut_forcing():
+    x, y, t = sympy.symbols("x y t")
+    u = sympy.exp(-t) * (x ** 2 + y ** 2 - sympy.Rational(1, 4))
+    beta = sympy.Rational(1, 4) - x ** 2 - y ** 2
+    f = sympy.diff(u, t) - (sympy.diff(beta * sympy.diff(u, x), x) + sympy.diff(beta * sympy.diff(u, y), y))
+    # the source term derived by hand: exp(-t)(7 r^2 - 3/4)
+    assert sympy.simplify(f - sympy.exp(-t) * (7 * (x ** 2 + y ** 2) - sympy.Rational(3, 4))) == 0
+    return (sympy.lambdify((x, y, t), u, "numpy"), sympy.lambdify((x, y, t), f, "numpy"))
+
+
+def _peanut_errors(nodes, steps):
+    uf, ff = _peanut_forcing()
+    g = Grid(2, (nodes, nodes), (-1.0, -1.0), (1.0, 1.0))
+    X, Y = g.coords()
+    op = build_operator(g, peanut_level_set(X, Y), lambda P: 0.25 - P[:, 0] ** 2 - P[:, 1] ** 2)
+    Xc, Yc = op.gather(X), op.gather(Y)
+    T = 0.1
+    h = T / steps
+    method = "dense" if op.n < 1500 else "krylov"
+
+    def F(u, t):
+        return ff(Xc, Yc, t) + op.forcing(lambda P: uf(P[0], P[1], t))
+
+    U = uf(Xc, Yc, 0.0)
+    t = 0.0
+    for _ in range(steps):
+        U = etd2rk_step(op.A, h, U, F, t, method=method)
+        t += h
+    e = U - uf(Xc, Yc, T)
+    return np.abs(e).max(), np.sqrt(np.mean(e * e))
+
+
+def test_peanut_table1_etd2rk():
+    """Section 4.2.1, Table 1 (ETD2RK): same problem, dt = h, t = 0.1."""
+    rows = json.load(open(GOLDEN))["rows"]
+    got = [_peanut_errors(r["nodes"], r["steps"]) for r in rows[:3]]
+    for r, (linf, l2) in zip(rows[:3], got):
+        assert r["linf"] / 3.0 < linf < r["linf"] * 3.0, (r, linf)
+        assert r["l2"] / 4.0 < l2 < r["l2"] * 4.0, (r, l2)
+    order = np.log2(got[0][0] / got[2][0]) / 2.0
+    assert order > 1.5
