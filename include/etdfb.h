@@ -1,0 +1,170 @@
+/*
+ * libetdfb -- exponential time differencing on embedded-boundary domains
+ * with a level-set free boundary, for AMD Instinct MI355X (gfx950), FP64.
+ *
+ * Method: S. Liu and X. Liu, "Integration factor combined with level set
+ * method for reaction-diffusion systems with free boundary in high spatial
+ * dimensions", arXiv 2209.15095.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Arrays are DEVICE pointers to float64 in box layout [nz][ny][nx]
+ *   (x fastest; 2D: nz = 1).  Node (i,j,k) sits at lo + (i,j,k) * h with
+ *   h = (hi[0] - lo[0]) / (n[0] - 1), equal on every axis (Section 2,
+ *   eq. 2.3).  The caller owns every array; the library never frees or
+ *   reallocates them.  Arrays passed to one call must not overlap unless a
+ *   parameter says so.
+ * - The domain is where the level-set function rho < 0 (Section 4.3).
+ *   Computational points are inside points whose 2d face neighbours are all
+ *   inside; the other inside points are interior ghost points (Section 2).
+ *   Unknowns live on computational points only: vectors are READ only there
+ *   and WRITTEN as 0 at every other node.
+ * - Calls are asynchronous on the context's HIP stream and return a status
+ *   code (0 = ETD_OK, negative = error).  Argument errors are detected on
+ *   the host and returned at once.  Errors found on the device (Krylov
+ *   failure, non-finite data, domain at the box edge, barrier time-out) are
+ *   latched in the context and returned by etd_ctx_sync() and by the next
+ *   call that synchronises (any call given a non-NULL stats pointer).
+ * - One context serves one stream at a time; calls on one context must not
+ *   overlap.  Contexts are independent of each other.
+ */
+#ifndef ETDFB_H
+#define ETDFB_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes. */
+enum {
+  ETD_OK = 0,
+  ETD_ERR_INVALID = -1,      /* bad argument (host check) */
+  ETD_ERR_HIP = -2,          /* a HIP runtime call failed */
+  ETD_ERR_NO_DEVICE = -3,    /* no gfx950 device visible */
+  ETD_ERR_KRYLOV = -4,       /* Krylov method did not reach the tolerance */
+  ETD_ERR_NONFINITE = -5,    /* NaN/Inf met in a reduction */
+  ETD_ERR_DOMAIN = -6,       /* computational point within 2 layers of the box edge */
+  ETD_ERR_BARRIER = -7,      /* grid barrier timed out (kernel drained and exited) */
+  ETD_ERR_NO_GEOMETRY = -8   /* no geometry built on this context yet */
+};
+
+enum { ETD_SCHEME_ETD1 = 1, ETD_SCHEME_ETD2RK = 2 };
+
+/* Box grid: dim 2 or 3, n[d] nodes on [lo[d], hi[d]] per axis, equal spacing. */
+typedef struct {
+  int32_t dim;
+  int32_t n[3];
+  double lo[3];
+  double hi[3];
+} etd_grid;
+
+/* u_t = div(beta grad u) + u (a - b u) in the domain; boundary speed
+ * mu |grad u| along the outward normal (Section 1, eq. 1.1; Section 4.3). */
+typedef struct {
+  double beta;
+  double a;
+  double b;
+  double mu;
+} etd_physics;
+
+/* Adaptive Krylov options.  tol: local error per unit time relative to the
+ * solution norm (the paper's experiments use tolerance-driven adaptivity,
+ * Section 3.3).  m_min <= m <= m_max <= 64 Krylov dimensions, grown in steps
+ * of m_step; at most max_substeps time substeps per combination. */
+typedef struct {
+  double tol;
+  int32_t m_min;
+  int32_t m_max;
+  int32_t m_step;
+  int32_t max_substeps;
+} etd_krylov_opts;
+
+/* Statistics of the last device job of a context. */
+typedef struct {
+  int32_t substeps;
+  int32_t rejected;
+  int32_t matvecs;
+  int32_t m_last;
+  int32_t expms;
+  int32_t n_active_tiles;
+  int32_t n_unknowns;
+  int32_t status;
+  double err_est;
+  double t_done;
+} etd_stats;
+
+typedef struct etd_ctx etd_ctx;
+
+/* Create a context for one grid.  hip_stream: a hipStream_t (NULL = the
+ * default stream).  opts may be NULL (tol 1e-10, m 8..64 step 4, 64
+ * substeps).  Allocates all device workspaces for the worst case (every
+ * tile of the box active).  *out receives the context; returns ETD_OK,
+ * ETD_ERR_INVALID, ETD_ERR_NO_DEVICE or ETD_ERR_HIP. */
+int etd_ctx_create(const etd_grid* grid, const etd_physics* phys, const etd_krylov_opts* opts,
+                   void* hip_stream, etd_ctx** out);
+
+/* Free a context and its workspaces (synchronises its stream first). */
+int etd_ctx_destroy(etd_ctx* ctx);
+
+/* Switch the stream later calls are enqueued on. */
+int etd_ctx_set_stream(etd_ctx* ctx, void* hip_stream);
+
+/* Replace beta (the operator is beta times the beta = 1 operator, Section 2
+ * with constant beta); takes effect for later calls. */
+int etd_ctx_set_beta(etd_ctx* ctx, double beta);
+
+/* Classify the nodes of rho < 0 and build the operator coefficients
+ * (Section 2, Cases 1-3; eq. 2.4 and eqs. 2.5-2.6).  rho: device array of
+ * the box, read only.  Synchronises once to size the persistent launch.
+ * Returns ETD_ERR_DOMAIN when a computational point lies in the two outer
+ * box layers. */
+int etd_geometry_build(etd_ctx* ctx, const double* rho);
+
+/* out = A v: the embedded-boundary discretisation of div(beta grad .) of
+ * the last etd_geometry_build (Section 2: eq. 2.4 and the Case 2/3 ghost
+ * closures with homogeneous boundary data).  v, out: device box arrays
+ * (v read at computational points, out written everywhere, no aliasing). */
+int etd_operator_apply(etd_ctx* ctx, const double* v, double* out);
+
+/* out = sum_{k=0}^{p} phi_k(t A) b_k  (eq. 3.7 with A -> tA; standard
+ * phi_k: phi_0 = exp, phi_k(z) = (phi_{k-1}(z) - 1/(k-1)!)/z), A the
+ * operator of the last etd_geometry_build.  0 <= p <= 3, t >= 0.
+ * b: host array of p+1 device pointers (box layout, read at computational
+ * points).  out: device array (box), written everywhere; must not alias any
+ * b_k.  stats: NULL, or receives the statistics (synchronises). */
+int phi_combination_apply(etd_ctx* ctx, double t, int32_t p, const double* const* b, double* out,
+                          etd_stats* stats);
+
+/* Steps 1 and 2a of the free-boundary algorithm (Section 4.3): extend u
+ * from the computational points of rho by quadratic normal extrapolation,
+ * Stefan speed mu |grad u| extended off the interface, HJ-WENO5/TVD-RK3
+ * advection of rho over dt, reinitialisation if reinit != 0, then u is
+ * restricted to the computational points of the new rho.  rho and u are
+ * device box arrays updated in place.  Rebuilds the geometry for the new
+ * rho. */
+int levelset_advance(etd_ctx* ctx, double* rho, double* u, double dt, int32_t reinit);
+
+/* One time step of size h of u_t = A u + f(u) (Section 3: ETD1 or ETD2RK).
+ * rho == NULL: frozen domain (geometry of the last build).  rho != NULL:
+ * free boundary, levelset_advance(ctx, rho, u, h, reinit) first, then the
+ * ETD step on the new domain.  u: device box array, updated in place. */
+int etd_step(etd_ctx* ctx, int32_t scheme, double h, double* u, double* rho, int32_t reinit,
+             etd_stats* stats);
+
+/* Wait for the context's stream; return the first latched device error
+ * (and clear it), or ETD_OK. */
+int etd_ctx_sync(etd_ctx* ctx);
+
+/* Statistics of the last job (synchronises). */
+int etd_ctx_stats(etd_ctx* ctx, etd_stats* stats);
+
+/* Human-readable name of a status code (static string). */
+const char* etd_status_string(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ETDFB_H */

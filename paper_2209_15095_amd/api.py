@@ -1,0 +1,128 @@
+"""Python binding of libetdfb (same names as the C-ABI in include/etdfb.h).
+
+Argument marshalling only: tensors are torch float64 CUDA (HIP) tensors in
+box layout, passed by device pointer together with the current torch
+stream; every step of the computation runs in the library's HIP kernels.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import torch
+
+from . import _lib as L
+
+
+def _ptr(t: torch.Tensor) -> int:
+    return t.data_ptr()
+
+
+class Context:
+    """One etd_ctx: a grid, physics, Krylov options and device workspaces."""
+
+    def __init__(self, dim, n, lo, hi, beta=1.0, a=1.0, b=1.0, mu=0.0, tol=1e-10, m_min=8, m_max=64,
+                 m_step=4, max_substeps=64, stream=None):
+        self.lib = L.load()
+        g = L.EtdGrid()
+        g.dim = dim
+        for d in range(3):
+            g.n[d] = int(n[d]) if d < dim else 1
+            g.lo[d] = float(lo[d]) if d < dim else 0.0
+            g.hi[d] = float(hi[d]) if d < dim else 1.0
+        ph = L.EtdPhysics(float(beta), float(a), float(b), float(mu))
+        op = L.EtdKrylovOpts(float(tol), int(m_min), int(m_max), int(m_step), int(max_substeps))
+        self.dim = dim
+        self.shape = tuple(reversed([int(x) for x in n[:dim]]))
+        self.handle = C.c_void_p()
+        s = stream if stream is not None else torch.cuda.current_stream()
+        L.check(self.lib.etd_ctx_create(C.byref(g), C.byref(ph), C.byref(op), C.c_void_p(s.cuda_stream),
+                                        C.byref(self.handle)), "etd_ctx_create")
+        self._stream = s
+
+    @classmethod
+    def from_grid(cls, grid, **kw):
+        return cls(grid.dim, grid.n, grid.lo, grid.hi, **kw)
+
+    def _check_box(self, t: torch.Tensor, name: str):
+        if not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or not t.is_cuda:
+            raise TypeError(f"{name}: expected a float64 CUDA tensor")
+        if tuple(t.shape) != self.shape or not t.is_contiguous():
+            raise ValueError(f"{name}: expected a contiguous tensor of shape {self.shape}, got {tuple(t.shape)}")
+
+    def _sync_stream(self):
+        cur = torch.cuda.current_stream()
+        if cur.cuda_stream != self._stream.cuda_stream:
+            self._stream = cur
+            L.check(self.lib.etd_ctx_set_stream(self.handle, C.c_void_p(cur.cuda_stream)), "etd_ctx_set_stream")
+
+    def close(self):
+        if self.handle:
+            self.lib.etd_ctx_destroy(self.handle)
+            self.handle = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_beta(self, beta: float):
+        L.check(self.lib.etd_ctx_set_beta(self.handle, float(beta)), "etd_ctx_set_beta")
+
+    def geometry_build(self, rho: torch.Tensor):
+        self._check_box(rho, "rho")
+        self._sync_stream()
+        L.check(self.lib.etd_geometry_build(self.handle, C.c_void_p(_ptr(rho))), "etd_geometry_build")
+
+    def operator_apply(self, v: torch.Tensor, out=None):
+        """out = A v on the current geometry."""
+        self._check_box(v, "v")
+        if out is None:
+            out = torch.empty_like(v)
+        self._check_box(out, "out")
+        self._sync_stream()
+        L.check(self.lib.etd_operator_apply(self.handle, C.c_void_p(_ptr(v)), C.c_void_p(_ptr(out))),
+                "etd_operator_apply")
+        return out
+
+    def phi_combination_apply(self, t: float, bs, out=None, stats: bool = False):
+        """out = sum_k phi_k(t A) b_k on the current geometry."""
+        for i, b in enumerate(bs):
+            self._check_box(b, f"b[{i}]")
+        if out is None:
+            out = torch.empty_like(bs[0])
+        self._check_box(out, "out")
+        self._sync_stream()
+        arr = (C.c_void_p * len(bs))(*[_ptr(b) for b in bs])
+        st = L.EtdStats() if stats else None
+        L.check(self.lib.phi_combination_apply(self.handle, float(t), len(bs) - 1, arr, C.c_void_p(_ptr(out)),
+                                               C.byref(st) if st is not None else None),
+                "phi_combination_apply")
+        return (out, st.as_dict()) if stats else out
+
+    def levelset_advance(self, rho: torch.Tensor, u: torch.Tensor, dt: float, reinit: bool):
+        self._check_box(rho, "rho")
+        self._check_box(u, "u")
+        self._sync_stream()
+        L.check(self.lib.levelset_advance(self.handle, C.c_void_p(_ptr(rho)), C.c_void_p(_ptr(u)), float(dt),
+                                          int(bool(reinit))), "levelset_advance")
+
+    def etd_step(self, scheme: str, h: float, u: torch.Tensor, rho=None, reinit=False, stats=False):
+        code = {"etd1": L.ETD_SCHEME_ETD1, "etd2rk": L.ETD_SCHEME_ETD2RK}[scheme]
+        self._check_box(u, "u")
+        if rho is not None:
+            self._check_box(rho, "rho")
+        self._sync_stream()
+        st = L.EtdStats() if stats else None
+        L.check(self.lib.etd_step(self.handle, code, float(h), C.c_void_p(_ptr(u)),
+                                  C.c_void_p(_ptr(rho)) if rho is not None else None, int(bool(reinit)),
+                                  C.byref(st) if st is not None else None), "etd_step")
+        return st.as_dict() if stats else None
+
+    def sync(self):
+        L.check(self.lib.etd_ctx_sync(self.handle), "etd_ctx_sync")
+
+    def stats(self):
+        st = L.EtdStats()
+        L.check(self.lib.etd_ctx_stats(self.handle, C.byref(st)), "etd_ctx_stats")
+        return st.as_dict()

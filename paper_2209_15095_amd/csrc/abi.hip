@@ -1,0 +1,400 @@
+// C-ABI of libetdfb: context management, argument checks and the sequence
+// of launches behind each entry point declared in include/etdfb.h.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <vector>
+
+#include "../../include/etdfb.h"
+#include "etdfb_internal.h"
+#include "launch.h"
+#include "levelset.h"
+
+using namespace etdfb;
+
+struct etd_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  etd_grid grid{};
+  etd_physics phys{};
+  etd_krylov_opts opts{};
+  BoxHost box{};
+  int ntiles = 0;         // tiles of the box
+  size_t nodes = 0;       // nodes of the box
+  size_t ld = 0;          // doubles per workspace vector
+  // geometry
+  uint8_t* mask = nullptr;
+  int* tile_flag = nullptr;
+  int* tile_map = nullptr;
+  int* slot_tile = nullptr;
+  uint64_t* comp_bits = nullptr;
+  uint64_t* irr_bits = nullptr;
+  double* cdiag = nullptr;
+  int* counters = nullptr;   // [0] n_active, [1] status, [2..3] case counts
+  // persistent kernel state
+  double* ws = nullptr;
+  double* part = nullptr;
+  BarrierDev* bar = nullptr;
+  KrylovStateDev* st = nullptr;
+  int max_grid = 0;
+  int grid_blocks = 1;
+  int n_active_host = 0;
+  bool have_geometry = false;
+  // level-set scratch (box arrays)
+  LevelsetScratch ls{};
+  // pinned host mirror for small readbacks
+  int* h_counters = nullptr;
+  KrylovStateDev* h_state = nullptr;
+};
+
+namespace {
+
+int check_hip(hipError_t e) { return e == hipSuccess ? ETD_OK : ETD_ERR_HIP; }
+
+#define HIP_TRY(x)                         \
+  do {                                     \
+    hipError_t _e = (x);                   \
+    if (_e != hipSuccess) return ETD_ERR_HIP; \
+  } while (0)
+
+int n_active_ptr_offset = 0;
+
+GeomDev geom_view(const etd_ctx* c) {
+  GeomDev g{};
+  g.dim = c->box.dim;
+  g.nx = c->box.nx; g.ny = c->box.ny; g.nz = c->box.nz;
+  g.ntx = c->box.ntx; g.nty = c->box.nty; g.ntz = c->box.ntz;
+  g.tile_map = c->tile_map;
+  g.slot_tile = c->slot_tile;
+  g.comp_bits = c->comp_bits;
+  g.irr_bits = c->irr_bits;
+  g.cdiag = c->cdiag;
+  g.n_active = c->counters + 0;
+  g.coef = c->phys.beta / (c->box.dx * c->box.dx);
+  g.dx = c->box.dx;
+  return g;
+}
+
+KrylovDev krylov_params(const etd_ctx* c, int mode) {
+  KrylovDev P{};
+  P.g = geom_view(c);
+  P.ws = c->ws;
+  P.ld = c->ld;
+  P.part = c->part;
+  P.bar = c->bar;
+  P.status = c->counters + 1;
+  P.st = c->st;
+  P.tol = c->opts.tol;
+  P.m_min = c->opts.m_min;
+  P.m_max = c->opts.m_max;
+  P.m_step = c->opts.m_step;
+  P.max_substeps = c->opts.max_substeps;
+  P.ra = c->phys.a;
+  P.rb = c->phys.b;
+  P.mode = mode;
+  return P;
+}
+
+int run_krylov(etd_ctx* c, const KrylovDev& P) {
+  if (!c->have_geometry) return ETD_ERR_NO_GEOMETRY;
+  return check_hip(launch_krylov(c->box.dim, P, c->grid_blocks, c->stream));
+}
+
+int gather_to(etd_ctx* c, const double* box, int vec) {
+  int grid = c->n_active_host > 0 ? c->n_active_host : 1;
+  return check_hip(launch_gather(c->box, box, c->slot_tile, c->comp_bits, c->counters + 0,
+                                 c->ws + (size_t)vec * c->ld, grid, c->stream));
+}
+
+int scatter_from(etd_ctx* c, int vec, double* box) {
+  return check_hip(launch_scatter(c->box, c->ws + (size_t)vec * c->ld, c->tile_map, c->comp_bits, box,
+                                  c->stream));
+}
+
+int fill_stats(etd_ctx* c, etd_stats* s) {
+  HIP_TRY(hipMemcpyAsync(c->h_counters, c->counters, 4 * sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipMemcpyAsync(c->h_state, c->st, sizeof(KrylovStateDev), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  s->substeps = c->h_state->substeps;
+  s->rejected = c->h_state->rejected;
+  s->matvecs = c->h_state->matvecs;
+  s->m_last = c->h_state->m_last;
+  s->expms = c->h_state->expms;
+  s->n_active_tiles = c->h_counters[0];
+  s->n_unknowns = -1;
+  s->status = c->h_counters[1];
+  s->err_est = c->h_state->err_est;
+  s->t_done = c->h_state->t_done;
+  return ETD_OK;
+}
+
+int latched_status(etd_ctx* c) {
+  HIP_TRY(hipMemcpyAsync(c->h_counters, c->counters, 4 * sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  int st = c->h_counters[1];
+  if (st != 0) {
+    int zero = 0;
+    HIP_TRY(hipMemcpyAsync(c->counters + 1, &zero, sizeof(int), hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+  }
+  return st;
+}
+
+void free_all(etd_ctx* c) {
+  void* ptrs[] = {c->mask, c->tile_flag, c->tile_map, c->slot_tile, c->comp_bits, c->irr_bits, c->cdiag,
+                  c->counters, c->ws, c->part, c->bar, c->st};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  levelset_free(c->ls);
+  if (c->h_counters) (void)hipHostFree(c->h_counters);
+  if (c->h_state) (void)hipHostFree(c->h_state);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* etd_status_string(int s) {
+  switch (s) {
+    case ETD_OK: return "ok";
+    case ETD_ERR_INVALID: return "invalid argument";
+    case ETD_ERR_HIP: return "HIP runtime error";
+    case ETD_ERR_NO_DEVICE: return "no gfx950 device";
+    case ETD_ERR_KRYLOV: return "Krylov method did not reach the tolerance";
+    case ETD_ERR_NONFINITE: return "non-finite value in a reduction";
+    case ETD_ERR_DOMAIN: return "computational point within 2 layers of the box edge";
+    case ETD_ERR_BARRIER: return "grid barrier timed out";
+    case ETD_ERR_NO_GEOMETRY: return "no geometry built";
+    default: return "unknown status";
+  }
+}
+
+int etd_ctx_create(const etd_grid* grid, const etd_physics* phys, const etd_krylov_opts* opts,
+                   void* hip_stream, etd_ctx** out) {
+  if (!grid || !phys || !out) return ETD_ERR_INVALID;
+  *out = nullptr;
+  if (grid->dim != 2 && grid->dim != 3) return ETD_ERR_INVALID;
+  for (int d = 0; d < grid->dim; ++d) {
+    if (grid->n[d] < 5) return ETD_ERR_INVALID;
+    if (!(grid->hi[d] > grid->lo[d])) return ETD_ERR_INVALID;
+  }
+  const double dx = (grid->hi[0] - grid->lo[0]) / (grid->n[0] - 1);
+  for (int d = 1; d < grid->dim; ++d) {
+    const double dd = (grid->hi[d] - grid->lo[d]) / (grid->n[d] - 1);
+    if (fabs(dd - dx) > 1e-12 * dx) return ETD_ERR_INVALID;
+  }
+  if (!(phys->beta > 0.0) || !isfinite(phys->a) || !isfinite(phys->b) || !(phys->mu >= 0.0))
+    return ETD_ERR_INVALID;
+  etd_krylov_opts o{1e-10, 8, 64, 4, 64};
+  if (opts) o = *opts;
+  if (!(o.tol > 0.0) || o.m_min < 1 || o.m_max > MMAX_LIMIT || o.m_min > o.m_max || o.m_step < 1 ||
+      o.max_substeps < 1)
+    return ETD_ERR_INVALID;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return ETD_ERR_NO_DEVICE;
+  etd_ctx* c = new etd_ctx();
+  if (hipGetDevice(&c->device) != hipSuccess) { delete c; return ETD_ERR_NO_DEVICE; }
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, c->device) != hipSuccess) { delete c; return ETD_ERR_HIP; }
+  if (strncmp(prop.gcnArchName, "gfx950", 6) != 0) { delete c; return ETD_ERR_NO_DEVICE; }
+  c->stream = (hipStream_t)hip_stream;
+  c->grid = *grid;
+  c->phys = *phys;
+  c->opts = o;
+  BoxHost& b = c->box;
+  b.dim = grid->dim;
+  b.nx = grid->n[0];
+  b.ny = grid->n[1];
+  b.nz = grid->dim == 3 ? grid->n[2] : 1;
+  if (b.dim == 2) { b.tx = 32; b.ty = 8; b.tz = 1; } else { b.tx = 16; b.ty = 4; b.tz = 4; }
+  b.ntx = (b.nx + b.tx - 1) / b.tx;
+  b.nty = (b.ny + b.ty - 1) / b.ty;
+  b.ntz = (b.nz + b.tz - 1) / b.tz;
+  for (int d = 0; d < 3; ++d) b.lo[d] = d < grid->dim ? grid->lo[d] : 0.0;
+  b.dx = dx;
+  c->ntiles = b.ntx * b.nty * b.ntz;
+  c->nodes = (size_t)b.nx * b.ny * b.nz;
+  c->ld = (size_t)c->ntiles * TILE_PTS;
+  const int per_cu = krylov_max_blocks_per_cu(b.dim);
+  c->max_grid = per_cu * prop.multiProcessorCount;
+  if (c->max_grid < 1) { delete c; return ETD_ERR_HIP; }
+  bool ok = true;
+  ok &= hipMalloc(&c->mask, c->nodes) == hipSuccess;
+  ok &= hipMalloc(&c->tile_flag, sizeof(int) * c->ntiles) == hipSuccess;
+  ok &= hipMalloc(&c->tile_map, sizeof(int) * c->ntiles) == hipSuccess;
+  ok &= hipMalloc(&c->slot_tile, sizeof(int) * c->ntiles) == hipSuccess;
+  ok &= hipMalloc(&c->comp_bits, sizeof(uint64_t) * 4 * c->ntiles) == hipSuccess;
+  ok &= hipMalloc(&c->irr_bits, sizeof(uint64_t) * 4 * c->ntiles) == hipSuccess;
+  ok &= hipMalloc(&c->cdiag, sizeof(double) * c->ld) == hipSuccess;
+  ok &= hipMalloc(&c->counters, sizeof(int) * 8) == hipSuccess;
+  ok &= hipMalloc(&c->ws, sizeof(double) * c->ld * NVEC) == hipSuccess;
+  ok &= hipMalloc(&c->part, sizeof(double) * 2 * (size_t)c->max_grid * PART_STRIDE) == hipSuccess;
+  ok &= hipMalloc(&c->bar, sizeof(BarrierDev)) == hipSuccess;
+  ok &= hipMalloc(&c->st, sizeof(KrylovStateDev)) == hipSuccess;
+  ok &= hipHostMalloc(&c->h_counters, sizeof(int) * 8) == hipSuccess;
+  ok &= hipHostMalloc(&c->h_state, sizeof(KrylovStateDev)) == hipSuccess;
+  ok &= levelset_alloc(c->ls, c->nodes) == hipSuccess;
+  if (!ok) {
+    free_all(c);
+    delete c;
+    return ETD_ERR_HIP;
+  }
+  KrylovStateDev s0{};
+  for (int k = 0; k <= PMAX; ++k) {
+    s0.m_guess[k] = o.m_min;
+    s0.tau_frac[k] = 1.0;
+  }
+  int zeros[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  ok &= hipMemcpy(c->st, &s0, sizeof(s0), hipMemcpyHostToDevice) == hipSuccess;
+  ok &= hipMemcpy(c->counters, zeros, sizeof(zeros), hipMemcpyHostToDevice) == hipSuccess;
+  ok &= hipMemset(c->ws, 0, sizeof(double) * c->ld * NVEC) == hipSuccess;
+  ok &= hipMemset(c->bar, 0, sizeof(BarrierDev)) == hipSuccess;
+  ok &= hipDeviceSynchronize() == hipSuccess;
+  if (!ok) {
+    free_all(c);
+    delete c;
+    return ETD_ERR_HIP;
+  }
+  *out = c;
+  return ETD_OK;
+}
+
+int etd_ctx_destroy(etd_ctx* c) {
+  if (!c) return ETD_ERR_INVALID;
+  (void)hipStreamSynchronize(c->stream);
+  free_all(c);
+  delete c;
+  return ETD_OK;
+}
+
+int etd_ctx_set_stream(etd_ctx* c, void* s) {
+  if (!c) return ETD_ERR_INVALID;
+  c->stream = (hipStream_t)s;
+  return ETD_OK;
+}
+
+int etd_ctx_set_beta(etd_ctx* c, double beta) {
+  if (!c || !(beta > 0.0) || !isfinite(beta)) return ETD_ERR_INVALID;
+  c->phys.beta = beta;
+  return ETD_OK;
+}
+
+int etd_geometry_build(etd_ctx* c, const double* rho) {
+  if (!c || !rho) return ETD_ERR_INVALID;
+  HIP_TRY(launch_fill_int(c->tile_flag, c->ntiles, 0, c->stream));
+  HIP_TRY(launch_fill_int(c->counters + 2, 2, 0, c->stream));
+  HIP_TRY(launch_classify(c->box, rho, c->mask, c->tile_flag, c->counters + 1, c->stream));
+  HIP_TRY(launch_scan_tiles(c->tile_flag, c->ntiles, c->tile_map, c->slot_tile, c->counters + 0, c->stream));
+  HIP_TRY(launch_tile_coeff(c->box, rho, c->mask, c->tile_map, c->comp_bits, c->irr_bits, c->cdiag,
+                            c->counters + 2, c->ntiles, c->stream));
+  HIP_TRY(hipMemcpyAsync(c->h_counters, c->counters, 4 * sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  c->n_active_host = c->h_counters[0];
+  int g = c->n_active_host;
+  if (g < 1) g = 1;
+  if (g > c->max_grid) g = c->max_grid;
+  c->grid_blocks = g;
+  c->have_geometry = true;
+  if (c->h_counters[1] == ST_DOMAIN) {
+    int zero = 0;
+    HIP_TRY(hipMemcpyAsync(c->counters + 1, &zero, sizeof(int), hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    return ETD_ERR_DOMAIN;
+  }
+  return ETD_OK;
+}
+
+int etd_operator_apply(etd_ctx* c, const double* v, double* out) {
+  if (!c || !v || !out || v == out) return ETD_ERR_INVALID;
+  if (!c->have_geometry) return ETD_ERR_NO_GEOMETRY;
+  int r = gather_to(c, v, V_B0);
+  if (r) return r;
+  r = run_krylov(c, krylov_params(c, JOB_APPLY));
+  if (r) return r;
+  return scatter_from(c, V_U, out);
+}
+
+int phi_combination_apply(etd_ctx* c, double t, int32_t p, const double* const* b, double* out,
+                          etd_stats* stats) {
+  if (!c || !b || !out || p < 0 || p > PMAX || !(t >= 0.0) || !isfinite(t)) return ETD_ERR_INVALID;
+  for (int k = 0; k <= p; ++k) {
+    if (!b[k]) return ETD_ERR_INVALID;
+    if (b[k] == out) return ETD_ERR_INVALID;
+  }
+  if (!c->have_geometry) return ETD_ERR_NO_GEOMETRY;
+  for (int k = 0; k <= p; ++k) {
+    int r = gather_to(c, b[k], V_B0 + k);
+    if (r) return r;
+  }
+  KrylovDev P = krylov_params(c, JOB_PHI);
+  P.p = p;
+  P.t = t;
+  int r = run_krylov(c, P);
+  if (r) return r;
+  r = scatter_from(c, V_U, out);
+  if (r) return r;
+  if (stats) {
+    r = fill_stats(c, stats);
+    if (r) return r;
+    int st = latched_status(c);
+    if (st) return st;
+  }
+  return ETD_OK;
+}
+
+int levelset_advance(etd_ctx* c, double* rho, double* u, double dt, int32_t reinit) {
+  if (!c || !rho || !u || !(dt >= 0.0) || !isfinite(dt)) return ETD_ERR_INVALID;
+  if (!c->have_geometry) {
+    int r = etd_geometry_build(c, rho);
+    if (r) return r;
+  }
+  LevelsetArgs a{};
+  a.box = c->box;
+  a.mu = c->phys.mu;
+  a.dt = dt;
+  a.reinit = reinit;
+  a.mask = c->mask;
+  a.status = c->counters + 1;
+  HIP_TRY(levelset_run(a, c->ls, rho, u, c->stream));
+  return etd_geometry_build(c, rho);
+}
+
+int etd_step(etd_ctx* c, int32_t scheme, double h, double* u, double* rho, int32_t reinit,
+             etd_stats* stats) {
+  if (!c || !u || !(h >= 0.0) || !isfinite(h)) return ETD_ERR_INVALID;
+  if (scheme != ETD_SCHEME_ETD1 && scheme != ETD_SCHEME_ETD2RK) return ETD_ERR_INVALID;
+  if (rho) {
+    int r = levelset_advance(c, rho, u, h, reinit);
+    if (r) return r;
+  }
+  if (!c->have_geometry) return ETD_ERR_NO_GEOMETRY;
+  int r = gather_to(c, u, V_X0);
+  if (r) return r;
+  KrylovDev P = krylov_params(c, scheme == ETD_SCHEME_ETD1 ? JOB_ETD1 : JOB_ETD2RK);
+  P.h = h;
+  r = run_krylov(c, P);
+  if (r) return r;
+  r = scatter_from(c, V_U, u);
+  if (r) return r;
+  if (stats) {
+    r = fill_stats(c, stats);
+    if (r) return r;
+    int st = latched_status(c);
+    if (st) return st;
+  }
+  return ETD_OK;
+}
+
+int etd_ctx_sync(etd_ctx* c) {
+  if (!c) return ETD_ERR_INVALID;
+  return latched_status(c);
+}
+
+int etd_ctx_stats(etd_ctx* c, etd_stats* s) {
+  if (!c || !s) return ETD_ERR_INVALID;
+  return fill_stats(c, s);
+}
+
+}  // extern "C"

@@ -1,0 +1,165 @@
+// Device-side building blocks shared by the HIP kernels of libetdfb:
+// the active-tile layout, the grid barrier of the persistent kernels and
+// fixed-order (hence bitwise reproducible) reductions.
+//
+// Layout.  The box of n^d nodes is cut into tiles of 256 nodes
+// (2D: 32 x 8, 3D: 16 x 4 x 4, x fastest inside a tile).  Only tiles that
+// hold at least one computational point ("active" tiles) get storage; a
+// vector is `slot * 256 + local` over the active slots, in lexicographic tile
+// order.  Every vector is 0 at the non-computational nodes of active tiles,
+// and nodes of inactive tiles read as 0, so the stencil never needs a mask for
+// its neighbours.  Per active tile: a 256-bit mask of computational points, a
+// 256-bit mask of "irregular" points (a neighbour face of Case 2 or 3) and,
+// for irregular points only, the diagonal weight sum stored at slot*256+local.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "etdfb_internal.h"
+
+namespace etdfb {
+
+template <int DIM> struct TileShape;
+template <> struct TileShape<2> { static constexpr int X = 32, Y = 8, Z = 1; };
+template <> struct TileShape<3> { static constexpr int X = 16, Y = 4, Z = 4; };
+
+__device__ __forceinline__ bool bit_of(const uint64_t* bits, int slot, int l) {
+  return (bits[(size_t)slot * 4 + (l >> 6)] >> (l & 63)) & 1ull;
+}
+
+// Face-neighbour slots of a tile (order -x,+x,-y,+y,-z,+z); -1 if outside the
+// box or inactive.  Called by threads 0 .. 2*DIM-1.
+template <int DIM>
+__device__ __forceinline__ int face_neighbour_slot(const GeomDev& g, int slot, int dir) {
+  int t = g.slot_tile[slot];
+  int c[3] = {t % g.ntx, (t / g.ntx) % g.nty, t / (g.ntx * g.nty)};
+  int n[3] = {g.ntx, g.nty, g.ntz};
+  int d = dir >> 1;
+  c[d] += (dir & 1) ? 1 : -1;
+  if (c[d] < 0 || c[d] >= n[d]) return -1;
+  return g.tile_map[((size_t)c[2] * g.nty + c[1]) * g.ntx + c[0]];
+}
+
+// Sum of the 2*DIM face-neighbour values of local point l of `slot`.
+template <int DIM>
+__device__ __forceinline__ double neighbour_sum(const double* __restrict__ v, int slot, int l,
+                                                const int* nb) {
+  constexpr int X = TileShape<DIM>::X, Y = TileShape<DIM>::Y, Z = TileShape<DIM>::Z;
+  const int lx = l % X, ly = (l / X) % Y, lz = l / (X * Y);
+  const double* base = v + (size_t)slot * TILE_PTS;
+  double s = 0.0;
+  if (lx > 0) s += base[l - 1];
+  else if (nb[0] >= 0) s += v[(size_t)nb[0] * TILE_PTS + l + (X - 1)];
+  if (lx < X - 1) s += base[l + 1];
+  else if (nb[1] >= 0) s += v[(size_t)nb[1] * TILE_PTS + l - (X - 1)];
+  if (ly > 0) s += base[l - X];
+  else if (nb[2] >= 0) s += v[(size_t)nb[2] * TILE_PTS + l + X * (Y - 1)];
+  if (ly < Y - 1) s += base[l + X];
+  else if (nb[3] >= 0) s += v[(size_t)nb[3] * TILE_PTS + l - X * (Y - 1)];
+  if (DIM == 3) {
+    if (lz > 0) s += base[l - X * Y];
+    else if (nb[4] >= 0) s += v[(size_t)nb[4] * TILE_PTS + l + X * Y * (Z - 1)];
+    if (lz < Z - 1) s += base[l + X * Y];
+    else if (nb[5] >= 0) s += v[(size_t)nb[5] * TILE_PTS + l - X * Y * (Z - 1)];
+  }
+  return s;
+}
+
+// (A v) at local point l of `slot` (0 at non-computational points):
+// beta/h^2 * (sum of neighbours - c_p v_p), c_p = 2*DIM for regular points.
+template <int DIM>
+__device__ __forceinline__ double apply_A(const GeomDev& g, const double* __restrict__ v, int slot,
+                                          int l, const int* nb, bool comp, bool irr) {
+  if (!comp) return 0.0;
+  const double vp = v[(size_t)slot * TILE_PTS + l];
+  const double c = irr ? g.cdiag[(size_t)slot * TILE_PTS + l] : (double)(2 * DIM);
+  return g.coef * (neighbour_sum<DIM>(v, slot, l, nb) - c * vp);
+}
+
+// ---------------------------------------------------------------- barrier
+
+// Grid-wide barrier for a co-resident (cooperatively launched) grid.
+// Every thread publishes its stores at agent scope, thread 0 arrives on an
+// atomic counter and waits for the generation to advance.  The wait is
+// bounded: past SPIN_LIMIT polls the block raises the abort flag, and once
+// the flag is up every barrier returns at once, so all waves always exit.
+constexpr long SPIN_LIMIT = 1L << 24;
+
+__device__ __forceinline__ bool grid_barrier(BarrierDev* b, int nblocks) {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  __syncthreads();
+  __shared__ int s_abort;
+  if (threadIdx.x == 0) {
+    int ab = __hip_atomic_load(&b->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (!ab) {
+      unsigned gen = __hip_atomic_load(&b->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      unsigned prev = __hip_atomic_fetch_add(&b->count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+      if (prev == (unsigned)nblocks - 1u) {
+        __hip_atomic_store(&b->count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&b->gen, gen + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      } else {
+        long spins = 0;
+        while (__hip_atomic_load(&b->gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+          __builtin_amdgcn_s_sleep(1);
+          if (++spins > SPIN_LIMIT) {
+            __hip_atomic_store(&b->abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            break;
+          }
+          if (__hip_atomic_load(&b->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
+        }
+      }
+      ab = __hip_atomic_load(&b->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    s_abort = ab;
+  }
+  __syncthreads();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  return s_abort == 0;
+}
+
+// ---------------------------------------------------------------- reductions
+
+// Sum over a wavefront, fixed tree; the result is valid in lane 0.
+__device__ __forceinline__ double wave_sum_lane0(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  return v;
+}
+
+// Block (256 threads = 4 waves) sum of NR values; result in out[] for all
+// threads.  `scratch` holds at least 4*NR doubles.
+template <int NR>
+__device__ __forceinline__ void block_sum(double (&v)[NR], double* scratch) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < NR; ++k) {
+    double s = wave_sum_lane0(v[k]);
+    if (lane == 0) scratch[w * NR + k] = s;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < NR; ++k)
+    v[k] = ((scratch[k] + scratch[NR + k]) + scratch[2 * NR + k]) + scratch[3 * NR + k];
+  __syncthreads();
+}
+
+// Reduce the per-block partials of a pass (written before a grid barrier)
+// in fixed order; every block obtains bit-identical sums.
+template <int NR>
+__device__ __forceinline__ void grid_partials_sum(const double* __restrict__ part, int nblocks,
+                                                  double (&out)[NR], double* scratch) {
+  if (threadIdx.x < 64) {
+#pragma unroll
+    for (int k = 0; k < NR; ++k) {
+      double s = 0.0;
+      for (int b = threadIdx.x; b < nblocks; b += 64) s += part[(size_t)b * PART_STRIDE + k];
+      s = wave_sum_lane0(s);
+      if (threadIdx.x == 0) scratch[k] = s;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < NR; ++k) out[k] = scratch[k];
+  __syncthreads();
+}
+
+}  // namespace etdfb

@@ -1,0 +1,102 @@
+// Structures shared by the host side (context management, launches) and the
+// HIP kernels of libetdfb.  Plain data only; all pointers are device pointers.
+#pragma once
+#include <stddef.h>
+#include <stdint.h>
+
+namespace etdfb {
+
+constexpr int TILE_PTS = 256;       // nodes per tile
+constexpr int PART_STRIDE = 8;      // doubles per block in the partial-sum buffer
+constexpr int MMAX_LIMIT = 64;      // largest Krylov dimension
+constexpr int PMAX = 3;             // largest phi index in one combination
+constexpr int EXPM_NMAX = MMAX_LIMIT + PMAX + 2;   // augmented matrix bound
+constexpr int KBLOCK = 256;         // threads per block of the persistent kernels
+
+// Work vectors of the persistent kernel (indices into the workspace).
+enum VecIndex {
+  V_U = 0,     // running solution u(t_k) = W_0
+  V_W1 = 1,    // W_1 .. W_3 (phipm-style stage vectors)
+  V_W2 = 2,
+  V_W3 = 3,
+  V_B0 = 4,    // b_0 .. b_3 of a combination (compact layout)
+  V_B1 = 5,
+  V_B2 = 6,
+  V_B3 = 7,
+  V_X0 = 8,    // ETD: U_n
+  V_F = 9,     // ETD: scratch
+  V_T = 10,    // scratch
+  V_Q0 = 11,   // Krylov basis q_0 .. q_MMAX
+  NVEC = V_Q0 + MMAX_LIMIT + 1
+};
+
+struct BarrierDev {
+  unsigned count;
+  unsigned gen;
+  int abort;
+  int pad;
+};
+
+struct GeomDev {
+  int dim;
+  int nx, ny, nz;
+  int ntx, nty, ntz;
+  int pad0;
+  const int* tile_map;        // [ntz*nty*ntx] box tile -> slot, -1 inactive
+  const int* slot_tile;       // [cap] slot -> box tile index
+  const uint64_t* comp_bits;  // [cap*4]
+  const uint64_t* irr_bits;   // [cap*4]
+  const double* cdiag;        // [cap*256] diagonal weight sum at irregular points
+  const int* n_active;        // device scalar: number of active tiles
+  double coef;                // beta / h^2
+  double dx;
+};
+
+// Adaptive state carried across calls and the statistics of the last call.
+struct KrylovStateDev {
+  int m_guess[PMAX + 1];
+  double tau_frac[PMAX + 1];
+  int substeps, rejected, matvecs, m_last, expms, calls;
+  double err_est;
+  double t_done;
+};
+
+enum JobMode {
+  JOB_PHI = 0,        // out = sum_k phi_k(t A) b_k, b_k in V_B0..V_B3
+  JOB_ETD1 = 1,       // one ETD1 step of V_X0
+  JOB_ETD2RK = 2,     // one ETD2RK step of V_X0
+  JOB_ETD2RK_STAGE = 3, // only the first stage a of ETD2RK
+  JOB_APPLY = 4         // V_U = A V_B0
+};
+
+struct KrylovDev {
+  GeomDev g;
+  double* ws;                 // NVEC vectors of ld doubles
+  size_t ld;
+  double* part;               // 2 * gridDim * PART_STRIDE partial sums
+  BarrierDev* bar;
+  int* status;                // first error code (0 = ok)
+  KrylovStateDev* st;
+  double tol;
+  int m_min, m_max, m_step, max_substeps;
+  double ra, rb;              // logistic reaction u (a - b u)
+  int mode;
+  int p;
+  double t;                   // JOB_PHI: time t of phi_k(t A)
+  double h;                   // ETD step
+};
+
+// Status codes (mirror include/etdfb.h).
+enum {
+  ST_OK = 0,
+  ST_INVALID = -1,
+  ST_HIP = -2,
+  ST_NO_DEVICE = -3,
+  ST_KRYLOV = -4,
+  ST_NONFINITE = -5,
+  ST_DOMAIN = -6,
+  ST_BARRIER = -7,
+  ST_NO_GEOMETRY = -8
+};
+
+}  // namespace etdfb

@@ -1,0 +1,352 @@
+// Geometry build for the embedded-boundary operator (Section 2 of the paper)
+// and the box <-> tile-layout transfers.
+//
+// classify_kernel     inside <=> rho < 0; computational <=> inside and all
+//                     2d face neighbours inside (outer box layer never);
+//                     marks tiles that hold a computational point; a
+//                     computational point within 2 layers of the box edge is
+//                     a domain error.
+// scan_tiles_kernel   active tiles -> slots in lexicographic tile order.
+// tile_coeff_kernel   per active tile: computational / irregular bit masks and,
+//                     per computational point, the diagonal weight sum
+//                     c_p = sum over faces of 1 (Case 1), h/s = 1/(1+theta)
+//                     (Case 2), 1 - w_p (Case 3), so that
+//                     (A v)_p = beta/h^2 (sum_q v_q - c_p v_p).
+//
+// Case 3 weight (ghost q of p whose next node on the line is inside): the
+// linear interpolant through p and the closest boundary points x_G1 of q and
+// x_G2 of p.  w_p is the ratio of signed distances of q and p to the plane
+// (2D: line) through x_G1, x_G2 whose normal is the averaged level-set
+// normal made orthogonal to x_G2 - x_G1; closest points are one projection
+// step x - rho g/|g|^2 with g the central-difference gradient.  Degenerate
+// configurations use w_p = rho_q / rho_p.  In 2D this equals the paper's RBF
+// interpolant with a linear tail (eqs. 2.5-2.6), whose radial part vanishes
+// for three centres.
+#include <math.h>
+
+#include "device_common.h"
+#include "launch.h"
+
+namespace etdfb {
+
+struct BoxDev {
+  int dim, nx, ny, nz;
+  int ntx, nty, ntz;
+  int tx, ty, tz;      // tile shape
+  double lo[3];
+  double dx;
+};
+
+__device__ __forceinline__ size_t node_index(const BoxDev& b, int i, int j, int k) {
+  return ((size_t)k * b.ny + j) * b.nx + i;
+}
+
+__device__ __forceinline__ int tile_of(const BoxDev& b, int i, int j, int k) {
+  return ((k / b.tz) * b.nty + (j / b.ty)) * b.ntx + (i / b.tx);
+}
+
+__global__ void fill_int_kernel(int* p, size_t n, int v) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+__global__ void classify_kernel(BoxDev b, const double* __restrict__ rho, uint8_t* __restrict__ mask,
+                                int* __restrict__ tile_flag, int* __restrict__ status) {
+  const size_t total = (size_t)b.nx * b.ny * b.nz;
+  for (size_t id = blockIdx.x * (size_t)blockDim.x + threadIdx.x; id < total;
+       id += (size_t)gridDim.x * blockDim.x) {
+    const int i = (int)(id % b.nx);
+    const int j = (int)((id / b.nx) % b.ny);
+    const int k = (int)(id / ((size_t)b.nx * b.ny));
+    const bool inside = rho[id] < 0.0;
+    bool comp = inside;
+    if (comp) {
+      if (i == 0 || i == b.nx - 1 || j == 0 || j == b.ny - 1) comp = false;
+      if (b.dim == 3 && (k == 0 || k == b.nz - 1)) comp = false;
+    }
+    if (comp) {
+      comp = rho[id - 1] < 0.0 && rho[id + 1] < 0.0 && rho[id - b.nx] < 0.0 && rho[id + b.nx] < 0.0;
+      if (b.dim == 3) {
+        const size_t sz = (size_t)b.nx * b.ny;
+        comp = comp && rho[id - sz] < 0.0 && rho[id + sz] < 0.0;
+      }
+    }
+    mask[id] = comp ? 2 : (inside ? 1 : 0);
+    if (comp) {
+      tile_flag[tile_of(b, i, j, k)] = 1;
+      bool edge = i < 2 || i > b.nx - 3 || j < 2 || j > b.ny - 3;
+      if (b.dim == 3) edge = edge || k < 2 || k > b.nz - 3;
+      if (edge) atomicCAS(status, 0, ST_DOMAIN);
+    }
+  }
+}
+
+// One block of 1024 threads: exclusive scan of tile flags.
+__global__ __launch_bounds__(1024) void scan_tiles_kernel(const int* __restrict__ tile_flag, int ntiles,
+                                                          int* __restrict__ tile_map,
+                                                          int* __restrict__ slot_tile,
+                                                          int* __restrict__ n_active) {
+  __shared__ int warp_tot[16];
+  __shared__ int carry;
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  for (int base = 0; base < ntiles; base += 1024) {
+    const int t = base + threadIdx.x;
+    const int f = (t < ntiles) ? (tile_flag[t] != 0) : 0;
+    // inclusive scan within the wave
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    int x = f;
+    for (int off = 1; off < 64; off <<= 1) {
+      int y = __shfl_up(x, off, 64);
+      if (lane >= off) x += y;
+    }
+    if (lane == 63) warp_tot[w] = x;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int acc = 0;
+      for (int q = 0; q < 16; ++q) { int v = warp_tot[q]; warp_tot[q] = acc; acc += v; }
+    }
+    __syncthreads();
+    const int excl = carry + warp_tot[w] + x - f;
+    if (t < ntiles) {
+      tile_map[t] = f ? excl : -1;
+      if (f) slot_tile[excl] = t;
+    }
+    __syncthreads();
+    if (threadIdx.x == 1023) carry = excl + f;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *n_active = carry;
+}
+
+__device__ __forceinline__ void central_grad(const BoxDev& b, const double* __restrict__ rho, int i,
+                                             int j, int k, double g[3]) {
+  const size_t id = node_index(b, i, j, k);
+  const double inv = 1.0 / (2.0 * b.dx);
+  g[0] = (rho[id + 1] - rho[id - 1]) * inv;
+  g[1] = (rho[id + b.nx] - rho[id - b.nx]) * inv;
+  g[2] = 0.0;
+  if (b.dim == 3) {
+    const size_t sz = (size_t)b.nx * b.ny;
+    g[2] = (rho[id + sz] - rho[id - sz]) * inv;
+  }
+}
+
+__device__ double case3_weight(const BoxDev& b, const double* __restrict__ rho, const int p[3],
+                               const int q[3]) {
+  const int D = b.dim;
+  const double rp = rho[node_index(b, p[0], p[1], p[2])];
+  const double rq = rho[node_index(b, q[0], q[1], q[2])];
+  const double fallback = rq / rp;
+  double gp[3], gq[3];
+  central_grad(b, rho, p[0], p[1], p[2], gp);
+  central_grad(b, rho, q[0], q[1], q[2], gq);
+  double ggp = 0.0, ggq = 0.0;
+  for (int d = 0; d < D; ++d) { ggp += gp[d] * gp[d]; ggq += gq[d] * gq[d]; }
+  if (ggp < 1e-300 || ggq < 1e-300) return fallback;
+  double xp[3], xq[3], g1[3], g2[3];
+  for (int d = 0; d < D; ++d) {
+    xp[d] = b.lo[d] + b.dx * p[d];
+    xq[d] = b.lo[d] + b.dx * q[d];
+    g1[d] = xq[d] - rq * gq[d] / ggq;
+    g2[d] = xp[d] - rp * gp[d] / ggp;
+  }
+  const double np_ = sqrt(ggp), nq_ = sqrt(ggq);
+  double ng[3] = {0.0, 0.0, 0.0};
+  double nn = 0.0;
+  for (int d = 0; d < D; ++d) { ng[d] = gq[d] / nq_ + gp[d] / np_; nn += ng[d] * ng[d]; }
+  nn = sqrt(nn);
+  if (nn < 1e-12) return fallback;
+  double nbar[3];
+  for (int d = 0; d < D; ++d) nbar[d] = ng[d] / nn;
+  double t[3];
+  double L = 0.0;
+  for (int d = 0; d < D; ++d) { t[d] = g2[d] - g1[d]; L += t[d] * t[d]; }
+  L = sqrt(L);
+  double nu[3];
+  if (L < 1e-12 * b.dx) {
+    if (D == 2) return fallback;
+    for (int d = 0; d < D; ++d) nu[d] = nbar[d];
+  } else {
+    double dot = 0.0;
+    for (int d = 0; d < D; ++d) { t[d] /= L; dot += nbar[d] * t[d]; }
+    double nl = 0.0;
+    for (int d = 0; d < D; ++d) { nu[d] = nbar[d] - dot * t[d]; nl += nu[d] * nu[d]; }
+    nl = sqrt(nl);
+    if (nl < 1e-8) return fallback;
+    for (int d = 0; d < D; ++d) nu[d] /= nl;
+  }
+  double dp = 0.0, dq = 0.0;
+  for (int d = 0; d < D; ++d) { dp += (xp[d] - g1[d]) * nu[d]; dq += (xq[d] - g1[d]) * nu[d]; }
+  if (fabs(dp) < 1e-10 * b.dx) return fallback;
+  return dq / dp;
+}
+
+// grid = one block (256 threads) per box tile; inactive tiles return.
+__global__ __launch_bounds__(256) void tile_coeff_kernel(BoxDev b, const double* __restrict__ rho,
+                                                         const uint8_t* __restrict__ mask,
+                                                         const int* __restrict__ tile_map,
+                                                         uint64_t* __restrict__ comp_bits,
+                                                         uint64_t* __restrict__ irr_bits,
+                                                         double* __restrict__ cdiag,
+                                                         int* __restrict__ counts) {
+  const int t = blockIdx.x;
+  const int slot = tile_map[t];
+  if (slot < 0) return;
+  const int tcx = t % b.ntx, tcy = (t / b.ntx) % b.nty, tcz = t / (b.ntx * b.nty);
+  const int l = threadIdx.x;
+  const int lx = l % b.tx, ly = (l / b.tx) % b.ty, lz = l / (b.tx * b.ty);
+  const int i = tcx * b.tx + lx, j = tcy * b.ty + ly, k = tcz * b.tz + lz;
+  bool comp = false, irr = false;
+  double c = 0.0;
+  int n2 = 0, n3 = 0;
+  if (i < b.nx && j < b.ny && k < b.nz) {
+    const size_t id = node_index(b, i, j, k);
+    comp = mask[id] == 2;
+    bool edge = i < 2 || i > b.nx - 3 || j < 2 || j > b.ny - 3;
+    if (b.dim == 3) edge = edge || k < 2 || k > b.nz - 3;
+    if (comp && edge) {
+      // domain error (reported by classify_kernel); keep every read in the box
+      c = 2.0 * b.dim;
+    } else if (comp) {
+      const int p[3] = {i, j, k};
+      for (int d = 0; d < b.dim; ++d) {
+        for (int s = -1; s <= 1; s += 2) {
+          int q[3] = {i, j, k};
+          q[d] += s;
+          const size_t qi = node_index(b, q[0], q[1], q[2]);
+          if (mask[qi] == 2) {
+            c += 1.0;
+            continue;
+          }
+          irr = true;
+          int q2[3] = {q[0], q[1], q[2]};
+          q2[d] += s;
+          const double rq = rho[qi];
+          const double rq2 = rho[node_index(b, q2[0], q2[1], q2[2])];
+          if (!(rq2 < 0.0)) {
+            const double theta = rq / (rq - rq2);
+            c += 1.0 / (1.0 + theta);
+            ++n2;
+          } else {
+            c += 1.0 - case3_weight(b, rho, p, q);
+            ++n3;
+          }
+        }
+      }
+    }
+  }
+  const uint64_t cb = __ballot(comp);
+  const uint64_t ib = __ballot(irr);
+  if ((l & 63) == 0) {
+    comp_bits[(size_t)slot * 4 + (l >> 6)] = cb;
+    irr_bits[(size_t)slot * 4 + (l >> 6)] = ib;
+  }
+  cdiag[(size_t)slot * TILE_PTS + l] = c;
+  if (n2) atomicAdd(&counts[0], n2);
+  if (n3) atomicAdd(&counts[1], n3);
+}
+
+// box -> tile layout (0 at non-computational points).  grid >= cap tiles.
+__global__ __launch_bounds__(256) void gather_kernel(BoxDev b, const double* __restrict__ box,
+                                                     const int* __restrict__ slot_tile,
+                                                     const uint64_t* __restrict__ comp_bits,
+                                                     const int* __restrict__ n_active,
+                                                     double* __restrict__ vec) {
+  const int nact = *n_active;
+  for (int slot = blockIdx.x; slot < nact; slot += gridDim.x) {
+    const int t = slot_tile[slot];
+    const int l = threadIdx.x;
+    const int lx = l % b.tx, ly = (l / b.tx) % b.ty, lz = l / (b.tx * b.ty);
+    const int i = (t % b.ntx) * b.tx + lx;
+    const int j = ((t / b.ntx) % b.nty) * b.ty + ly;
+    const int k = (t / (b.ntx * b.nty)) * b.tz + lz;
+    double v = 0.0;
+    if (bit_of(comp_bits, slot, l)) v = box[node_index(b, i, j, k)];
+    vec[(size_t)slot * TILE_PTS + l] = v;
+  }
+}
+
+// tile layout -> box: computational nodes get the vector, all others 0.
+__global__ void scatter_kernel(BoxDev b, const double* __restrict__ vec, const int* __restrict__ tile_map,
+                               const uint64_t* __restrict__ comp_bits, double* __restrict__ box) {
+  const size_t total = (size_t)b.nx * b.ny * b.nz;
+  for (size_t id = blockIdx.x * (size_t)blockDim.x + threadIdx.x; id < total;
+       id += (size_t)gridDim.x * blockDim.x) {
+    const int i = (int)(id % b.nx);
+    const int j = (int)((id / b.nx) % b.ny);
+    const int k = (int)(id / ((size_t)b.nx * b.ny));
+    const int slot = tile_map[tile_of(b, i, j, k)];
+    double v = 0.0;
+    if (slot >= 0) {
+      const int l = (i % b.tx) + b.tx * ((j % b.ty) + b.ty * (k % b.tz));
+      if (bit_of(comp_bits, slot, l)) v = vec[(size_t)slot * TILE_PTS + l];
+    }
+    box[id] = v;
+  }
+}
+
+// ------------------------------------------------------------ launchers
+
+static BoxDev to_dev(const BoxHost& h) {
+  BoxDev b;
+  b.dim = h.dim; b.nx = h.nx; b.ny = h.ny; b.nz = h.nz;
+  b.ntx = h.ntx; b.nty = h.nty; b.ntz = h.ntz;
+  b.tx = h.tx; b.ty = h.ty; b.tz = h.tz;
+  for (int d = 0; d < 3; ++d) b.lo[d] = h.lo[d];
+  b.dx = h.dx;
+  return b;
+}
+
+static int blocks_for(size_t n, int bs) {
+  size_t g = (n + bs - 1) / bs;
+  if (g > 65536) g = 65536;
+  if (g < 1) g = 1;
+  return (int)g;
+}
+
+hipError_t launch_fill_int(int* p, size_t n, int v, hipStream_t s) {
+  hipLaunchKernelGGL(fill_int_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_classify(const BoxHost& b, const double* rho, uint8_t* mask, int* tile_flag,
+                           int* status, hipStream_t s) {
+  const size_t n = (size_t)b.nx * b.ny * b.nz;
+  hipLaunchKernelGGL(classify_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, to_dev(b), rho, mask,
+                     tile_flag, status);
+  return hipGetLastError();
+}
+
+hipError_t launch_scan_tiles(const int* tile_flag, int ntiles, int* tile_map, int* slot_tile,
+                             int* n_active, hipStream_t s) {
+  hipLaunchKernelGGL(scan_tiles_kernel, dim3(1), dim3(1024), 0, s, tile_flag, ntiles, tile_map, slot_tile,
+                     n_active);
+  return hipGetLastError();
+}
+
+hipError_t launch_tile_coeff(const BoxHost& b, const double* rho, const uint8_t* mask,
+                             const int* tile_map, uint64_t* comp_bits, uint64_t* irr_bits,
+                             double* cdiag, int* counts, int ntiles, hipStream_t s) {
+  hipLaunchKernelGGL(tile_coeff_kernel, dim3(ntiles), dim3(256), 0, s, to_dev(b), rho, mask, tile_map,
+                     comp_bits, irr_bits, cdiag, counts);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather(const BoxHost& b, const double* box, const int* slot_tile,
+                         const uint64_t* comp_bits, const int* n_active, double* vec, int grid,
+                         hipStream_t s) {
+  hipLaunchKernelGGL(gather_kernel, dim3(grid), dim3(256), 0, s, to_dev(b), box, slot_tile, comp_bits,
+                     n_active, vec);
+  return hipGetLastError();
+}
+
+hipError_t launch_scatter(const BoxHost& b, const double* vec, const int* tile_map,
+                          const uint64_t* comp_bits, double* box, hipStream_t s) {
+  const size_t n = (size_t)b.nx * b.ny * b.nz;
+  hipLaunchKernelGGL(scatter_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, to_dev(b), vec, tile_map,
+                     comp_bits, box);
+  return hipGetLastError();
+}
+
+}  // namespace etdfb

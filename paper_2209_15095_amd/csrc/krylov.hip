@@ -1,0 +1,592 @@
+// Persistent HIP kernel for sum_k phi_k(tA) b_k and the ETD steps built on it.
+//
+// What is computed (Section 3.3 of the paper, eq. 3.7 and its ODE form):
+// out = sum_{k=0}^{p} phi_k(tA) b_k is the time-t value of
+// u' = A u + sum_{k>=1} s^{k-1}/(k-1)! w_k, u(0) = b_0, w_k = b_k / t^k.
+// The paper evaluates it with an adaptive Krylov method of the phipm family
+// (incomplete orthogonalisation of length 2, which for the symmetric matrix
+// of Section 2 is the Lanczos recurrence).  Design used here:
+//
+// * Substeps t_j -> t_j + tau.  With W_0 = u(t_j) and
+//   W_k = A W_{k-1} + sum_{l=0}^{p-k} t_j^l/l! w_{k+l} (k = 1..p),
+//   u(t_j + tau) = sum_{k<p} tau^k/k! W_k + tau^p phi_p(tau A) W_p, since
+//   phi_k(z) = 1/k! + z phi_{k+1}(z).
+// * phi_p(tau A) W_p ~ |W_p| V_m phi_p(tau T_m) e_1 from m Lanczos steps
+//   started at W_p (basis kept unnormalised with its norms).
+// * phi_p(tau T) e_1 and phi_{p+1}(tau T) e_1 are columns of the exponential
+//   of the (m+p+1)^2 augmented matrix [[tau T, e_1, 0], [0, 0, I], [0, 0, 0]],
+//   computed in LDS by scaling, Taylor-Horner (X is sparse, so Horner is
+//   O(N^2) per term) and squaring.
+// * Error estimate |W_p| beta_m tau^{p+1} |e_m^T phi_{p+1}(tau T) e_1|
+//   (generalised residual); accept when it is below
+//   tol * tau/t * max(|u(t_j)|, tau^p |W_p| / p!).  Otherwise grow m in steps
+//   of m_step up to m_max, then shrink tau.
+//
+// Everything after the launch is decided on the device: every block reduces
+// the same per-block partials in the same order, so all blocks hold
+// bit-identical scalars and take identical branches (no host round trip, no
+// broadcast).  Blocks synchronise with the grid barrier of device_common.h.
+// FP64 throughout; no matrix cores (nothing here is a dense contraction
+// except the tiny in-LDS exponential).
+#include <math.h>
+
+#include "device_common.h"
+#include "launch.h"
+
+namespace etdfb {
+
+struct Ctl {
+  // Lanczos data of the current substep (written by thread 0, read by all)
+  double alpha[MMAX_LIMIT + 1];
+  double nrm[MMAX_LIMIT + 2];
+  double coef[MMAX_LIMIT + 1];
+  double red[8];
+  double scratch[4 * 8];
+  int nb[6];
+};
+
+template <int DIM>
+struct Engine {
+  const KrylovDev& P;
+  Ctl& c;
+  double* R;   // LDS EXPM_NMAX^2
+  double* S;   // LDS EXPM_NMAX^2
+  int nact;
+  int pass_no;
+  // control state: every thread of every block holds identical copies
+  int m_guess[PMAX + 1];
+  double tau_frac[PMAX + 1];
+  int substeps, rejected, matvecs, m_last, expms;
+  double err_est, t_done;
+  bool failed;
+  int iu;   // vector holding u(t_j) = W_0 (V_U or V_T, ping-pong with the combine output)
+
+  __device__ double* V(int i) const { return P.ws + (size_t)i * P.ld; }
+
+  __device__ void fail(int code) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) atomicCAS(P.status, 0, code);
+    failed = true;
+  }
+
+  // Close a pass: block sum of NR partials, publish, grid barrier, fixed-order
+  // grid reduction into out[].  Returns false if the barrier aborted.
+  template <int NR>
+  __device__ bool finish(double (&acc)[NR], double (&out)[NR]) {
+    block_sum<NR>(acc, c.scratch);
+    double* part = P.part + (size_t)(pass_no & 1) * gridDim.x * PART_STRIDE;
+    if (threadIdx.x == 0)
+      for (int k = 0; k < NR; ++k) part[(size_t)blockIdx.x * PART_STRIDE + k] = acc[k];
+    ++pass_no;
+    if (!grid_barrier(P.bar, gridDim.x)) {
+      if (threadIdx.x == 0) atomicCAS(P.status, 0, ST_BARRIER);
+      failed = true;
+      return false;
+    }
+    grid_partials_sum<NR>(part, gridDim.x, out, c.scratch);
+    for (int k = 0; k < NR; ++k)
+      if (!isfinite(out[k])) {
+        if (threadIdx.x == 0 && blockIdx.x == 0) atomicCAS(P.status, 0, ST_NONFINITE);
+        failed = true;
+        return false;
+      }
+    return true;
+  }
+
+  __device__ bool barrier() {
+    ++pass_no;
+    if (!grid_barrier(P.bar, gridDim.x)) {
+      if (threadIdx.x == 0) atomicCAS(P.status, 0, ST_BARRIER);
+      failed = true;
+      return false;
+    }
+    return true;
+  }
+
+  // Loop over the active tiles assigned to this block; f(slot, l, comp, irr).
+  template <class F>
+  __device__ void tiles(F&& f) {
+    for (int slot = blockIdx.x; slot < nact; slot += gridDim.x) {
+      if (threadIdx.x < 2 * DIM) c.nb[threadIdx.x] = face_neighbour_slot<DIM>(P.g, slot, threadIdx.x);
+      __syncthreads();
+      const int l = threadIdx.x;
+      const bool comp = bit_of(P.g.comp_bits, slot, l);
+      const bool irr = comp && bit_of(P.g.irr_bits, slot, l);
+      f(slot, l, comp, irr);
+      __syncthreads();
+    }
+  }
+
+  __device__ double react(double u) const { return u * (P.ra - P.rb * u); }
+
+  // ------------------------------------------------------------------ passes
+
+  // W_k = A W_{k-1} + sum_l c_l b_{k+l}; at k == p also |W_p|^2 and |U|^2.
+  __device__ bool setup_pass(int k, int p, double tj, double tend, double (&out)[2]) {
+    double cl[PMAX + 1];
+    double fact = 1.0, tpow = 1.0;
+    for (int l = 0; l <= p - k; ++l) {
+      if (l > 0) { fact *= l; tpow *= tj; }
+      cl[l] = tpow / fact / pow(tend, (double)(k + l));
+    }
+    const double* src = (k == 1) ? V(iu) : V(V_W1 + k - 2);
+    double* dst = (k == p) ? V(V_Q0) : V(V_W1 + k - 1);
+    double acc[2] = {0.0, 0.0};
+    tiles([&](int slot, int l, bool comp, bool irr) {
+      const size_t i = (size_t)slot * TILE_PTS + l;
+      double w = 0.0;
+      if (comp) {
+        w = apply_A<DIM>(P.g, src, slot, l, c.nb, comp, irr);
+        for (int j = 0; j <= p - k; ++j) w += cl[j] * V(V_B0 + k + j)[i];
+      }
+      dst[i] = w;
+      if (k == p) {
+        const double u = V(iu)[i];
+        acc[0] += w * w;
+        acc[1] += u * u;
+      }
+    });
+    if (k == p) return finish<2>(acc, out);
+    return barrier();
+  }
+
+  // p == 0: q_0 = U, norms.
+  __device__ bool copy_u_pass(double (&out)[2]) {
+    double acc[2] = {0.0, 0.0};
+    tiles([&](int slot, int l, bool comp, bool irr) {
+      const size_t i = (size_t)slot * TILE_PTS + l;
+      const double u = V(iu)[i];
+      V(V_Q0)[i] = u;
+      acc[0] += u * u;
+      acc[1] += u * u;
+    });
+    return finish<2>(acc, out);
+  }
+
+  // z = A q_i into q_{i+1}; <z, q_i>.
+  __device__ bool lanczos_a(int i, double& dot) {
+    const double* q = V(V_Q0 + i);
+    double* z = V(V_Q0 + i + 1);
+    double acc[1] = {0.0};
+    tiles([&](int slot, int l, bool comp, bool irr) {
+      const size_t idx = (size_t)slot * TILE_PTS + l;
+      const double zz = apply_A<DIM>(P.g, q, slot, l, c.nb, comp, irr);
+      z[idx] = zz;
+      acc[0] += zz * q[idx];
+    });
+    double out[1];
+    if (!finish<1>(acc, out)) return false;
+    dot = out[0];
+    return true;
+  }
+
+  // q_{i+1} = (z - alpha_i q_i)/n_i - (n_i/n_{i-1}) q_{i-1}; |q_{i+1}|^2.
+  __device__ bool lanczos_b(int i, double alpha, double& nn) {
+    const double* q = V(V_Q0 + i);
+    const double* qm = (i > 0) ? V(V_Q0 + i - 1) : nullptr;
+    double* z = V(V_Q0 + i + 1);
+    const double inv_n = 1.0 / c.nrm[i];
+    const double cm = (i > 0) ? c.nrm[i] / c.nrm[i - 1] : 0.0;
+    double acc[1] = {0.0};
+    tiles([&](int slot, int l, bool comp, bool irr) {
+      const size_t idx = (size_t)slot * TILE_PTS + l;
+      double w = (z[idx] - alpha * q[idx]) * inv_n;
+      if (i > 0) w -= cm * qm[idx];
+      if (!comp) w = 0.0;
+      z[idx] = w;
+      acc[0] += w * w;
+    });
+    double out[1];
+    if (!finish<1>(acc, out)) return false;
+    nn = out[0];
+    return true;
+  }
+
+  // out = sum_{k<p} tau^k/k! W_k + sum_i coef_i q_i into the buffer that is
+  // not iu; returns |out|^2 in nn.
+  __device__ bool combine_pass(int p, int m, double tau, double& nn) {
+    double ck[PMAX];
+    double f = 1.0, tp = 1.0;
+    for (int k = 0; k < p; ++k) {
+      if (k > 0) { f *= k; tp *= tau; }
+      ck[k] = tp / f;
+    }
+    const int io = (iu == V_U) ? V_T : V_U;
+    double acc[1] = {0.0};
+    tiles([&](int slot, int l, bool comp, bool irr) {
+      const size_t idx = (size_t)slot * TILE_PTS + l;
+      double u = 0.0;
+      if (comp) {
+        if (p > 0) {
+          u = V(iu)[idx];
+          for (int k = 1; k < p; ++k) u += ck[k] * V(V_W1 + k - 1)[idx];
+        }
+        for (int j = 0; j < m; ++j) u += c.coef[j] * V(V_Q0 + j)[idx];
+      }
+      V(io)[idx] = u;
+      acc[0] += u * u;
+    });
+    double out[1];
+    if (!finish<1>(acc, out)) return false;
+    nn = out[0];
+    return true;
+  }
+
+  // --------------------------------------------------------- small expm
+
+  // E = exp(X) in R, X the augmented matrix of size N = m + p + 1 built
+  // from tau, alpha[0..m-1], nrm[1..m-1].
+  __device__ void expm_aug(int m, int p, double tau) {
+    const int N = m + p + 1;
+    // 1-norm of X (column sums)
+    if (threadIdx.x == 0) {
+      double nx = 1.0;
+      for (int j = 0; j < m; ++j) {
+        double s = fabs(c.alpha[j]);
+        if (j > 0) s += c.nrm[j];
+        if (j < m - 1) s += c.nrm[j + 1];
+        nx = fmax(nx, tau * s);
+      }
+      c.red[0] = nx;
+    }
+    __syncthreads();
+    const double nx = c.red[0];
+    int sq = 0;
+    if (nx > 1.0) sq = (int)ceil(log2(nx));
+    const double scale = ldexp(1.0, -sq);
+    const int NN = N * N;
+    for (int e = threadIdx.x; e < NN; e += blockDim.x) R[e] = ((e / N) == (e % N)) ? 1.0 : 0.0;
+    __syncthreads();
+    double* A = R;
+    double* B = S;
+    constexpr int K = 20;
+    for (int k = K; k >= 1; --k) {
+      const double f = scale / (double)k;
+      for (int e = threadIdx.x; e < NN; e += blockDim.x) {
+        const int i = e / N, j = e % N;
+        double xr;
+        if (i < m) {
+          xr = c.alpha[i] * A[i * N + j];
+          if (i > 0) xr += c.nrm[i] * A[(i - 1) * N + j];
+          if (i < m - 1) xr += c.nrm[i + 1] * A[(i + 1) * N + j];
+          xr *= tau;
+          if (i == 0) xr += A[m * N + j];
+        } else if (i < m + p) {
+          xr = A[(i + 1) * N + j];
+        } else {
+          xr = 0.0;
+        }
+        B[e] = ((i == j) ? 1.0 : 0.0) + f * xr;
+      }
+      __syncthreads();
+      double* t = A; A = B; B = t;
+    }
+    for (int s = 0; s < sq; ++s) {
+      for (int e = threadIdx.x; e < NN; e += blockDim.x) {
+        const int i = e / N, j = e % N;
+        double acc = 0.0;
+        // lower-left block (rows >= m, cols < m) of every power is zero
+        const int l0 = (i >= m) ? m : 0;
+        for (int l = l0; l < N; ++l) acc += A[i * N + l] * A[l * N + j];
+        B[e] = acc;
+      }
+      __syncthreads();
+      double* t = A; A = B; B = t;
+    }
+    if (A != R) {
+      for (int e = threadIdx.x; e < NN; e += blockDim.x) R[e] = A[e];
+      __syncthreads();
+    }
+  }
+
+  // ------------------------------------------------------------ phi combo
+
+  // U <- sum_{k=0}^{p} phi_k(tend A) b_k with b_0 = U on entry and b_k (k>=1)
+  // in V_B0 + k.  Returns false on failure (status set).
+  __device__ bool phi_comb(int p, double tend) {
+    if (tend == 0.0) {
+      // phi_k(0) = 1/k!
+      double f = 1.0;
+      double ck[PMAX + 1];
+      for (int k = 0; k <= p; ++k) { if (k > 0) f *= k; ck[k] = 1.0 / f; }
+      tiles([&](int slot, int l, bool comp, bool irr) {
+        const size_t idx = (size_t)slot * TILE_PTS + l;
+        double u = V(iu)[idx];
+        for (int k = 1; k <= p; ++k) u += ck[k] * V(V_B0 + k)[idx];
+        V(iu)[idx] = comp ? u : 0.0;
+      });
+      return barrier();
+    }
+    const double tol = P.tol;
+    double tj = 0.0;
+    double tau = tend * tau_frac[p];
+    int m_target = m_guess[p];
+    int nsub = 0;
+    bool shrunk_any = false;
+    double fact_p = 1.0;
+    for (int k = 2; k <= p; ++k) fact_p *= k;
+    while (tj < tend) {
+      if (nsub >= P.max_substeps) { fail(ST_KRYLOV); return false; }
+      tau = fmin(tau, tend - tj);
+      if (tend - tj - tau <= 1e-13 * tend) tau = tend - tj;
+      // setup: W_1..W_p, q_0 = W_p, norms
+      double nrm2[2];
+      if (p == 0) {
+        if (!copy_u_pass(nrm2)) return false;
+      } else {
+        for (int k = 1; k <= p; ++k) {
+          double o[2];
+          if (!setup_pass(k, p, tj, tend, o)) return false;
+          if (k == p) { nrm2[0] = o[0]; nrm2[1] = o[1]; }
+        }
+        matvecs += p;
+      }
+      const double n0 = sqrt(nrm2[0]);
+      const double unorm = sqrt(nrm2[1]);
+      if (n0 == 0.0) {
+        // W_p = 0: the Krylov term vanishes exactly.
+        double nn;
+        if (!combine_pass(p, 0, tau, nn)) return false;
+        iu = (iu == V_U) ? V_T : V_U;
+        tj += tau;
+        ++nsub;
+        continue;
+      }
+      if (threadIdx.x == 0) c.nrm[0] = n0;
+      __syncthreads();
+      int m = 0;
+      bool breakdown = false;
+      double anorm = 0.0;
+      bool shrunk = false;
+      double err = 0.0, tol_loc = 0.0;
+      // error estimate of the current (m, tau); fills R with exp(X)
+      auto estimate = [&]() -> bool {
+        expm_aug(m, p, tau);
+        expms += 1;
+        const int N = m + p + 1;
+        const double phi_next_m = R[(m - 1) * N + (m + p)];
+        double taup = 1.0;
+        for (int k = 0; k < p; ++k) taup *= tau;
+        err = breakdown ? 0.0 : n0 * c.nrm[m] * taup * tau * fabs(phi_next_m);
+        const double ref = fmax(unorm, taup * n0 / fact_p);
+        tol_loc = tol * (tau / tend) * fmax(ref, 1e-300);
+        __syncthreads();
+        if (!isfinite(err)) { fail(ST_NONFINITE); return false; }
+        return true;
+      };
+      // tau^p |W_p| [phi_p(tau T) e_1]_j / n_j, from R = exp(X)
+      auto set_coef = [&]() {
+        const int N = m + p + 1;
+        const int col = (p >= 1) ? (m + p - 1) : 0;
+        double taup = 1.0;
+        for (int k = 0; k < p; ++k) taup *= tau;
+        if (threadIdx.x == 0)
+          for (int j = 0; j < m; ++j) c.coef[j] = taup * n0 * R[j * N + col] / c.nrm[j];
+        __syncthreads();
+      };
+      // Refine after a rejection with error ratio r > 1: more Krylov vectors
+      // while m < m_max, else a smaller tau.  Returns false on failure.
+      auto refine = [&](double r) -> bool {
+        if (m < P.m_max && !breakdown) {
+          rejected += 1;
+          m_target = min(m + P.m_step, P.m_max);
+          return true;
+        }
+        double fac = 0.9 * pow(r, -1.0 / (double)(m + 1));
+        fac = fmin(0.9, fmax(0.1, fac));
+        tau *= fac;
+        shrunk = true;
+        rejected += 1;
+        if (tau < 1e-12 * tend) { fail(ST_KRYLOV); return false; }
+        return true;
+      };
+      bool accept = false;
+      int tries = 0;
+      while (!accept) {
+        if (++tries > 400) { fail(ST_KRYLOV); return false; }
+        while (m < m_target && !breakdown) {
+          double dot, nn;
+          if (!lanczos_a(m, dot)) return false;
+          const double alpha = dot / (c.nrm[m] * c.nrm[m]);
+          if (!lanczos_b(m, alpha, nn)) return false;
+          matvecs += 1;
+          const double nb = sqrt(nn);
+          if (threadIdx.x == 0) {
+            c.alpha[m] = alpha;
+            c.nrm[m + 1] = nb;
+          }
+          anorm = fmax(anorm, fabs(alpha) + nb + (m > 0 ? c.nrm[m] : 0.0));
+          __syncthreads();
+          ++m;
+          if (nb <= 1e-13 * anorm) breakdown = true;
+        }
+        if (!estimate()) return false;
+        // first test against the input scale (no pass needed)
+        if (err > tol_loc) {
+          if (!refine(err / tol_loc)) return false;
+          continue;
+        }
+        // then against the norm of the candidate output
+        set_coef();
+        double nn_out;
+        if (!combine_pass(p, m, tau, nn_out)) return false;
+        const double tol_out = tol * (tau / tend) * fmax(sqrt(nn_out), 1e-300);
+        if (err <= tol_out) {
+          accept = true;
+        } else {
+          if (!refine(err / tol_out)) return false;
+        }
+      }
+      iu = (iu == V_U) ? V_T : V_U;
+      m_last = m;
+      err_est = err;
+      tj += tau;
+      ++nsub;
+      shrunk_any |= shrunk;
+      // next substep: keep tau after a shrink, else try the whole remainder
+      if (!shrunk) tau = tend;
+      m_target = max(P.m_min, m);
+    }
+    if (iu != V_U) {
+      if (!copy_pass(V_U, iu)) return false;
+      iu = V_U;
+    }
+    substeps += nsub;
+    m_guess[p] = max(P.m_min, min(P.m_max, m_last - P.m_step / 2));
+    tau_frac[p] = shrunk_any ? fmin(1.0, 1.25 * tau / tend) : 1.0;
+    t_done = tj;
+    return true;
+  }
+
+  // ------------------------------------------------------------ jobs
+
+  __device__ bool copy_pass(int dst, int src) {
+    tiles([&](int slot, int l, bool comp, bool irr) {
+      const size_t idx = (size_t)slot * TILE_PTS + l;
+      V(dst)[idx] = comp ? V(src)[idx] : 0.0;
+    });
+    return barrier();
+  }
+
+  __device__ void run() {
+    switch (P.mode) {
+      case JOB_PHI: {
+        if (!copy_pass(V_U, V_B0)) return;
+        phi_comb(P.p, P.t);
+        return;
+      }
+      case JOB_ETD1: {
+        const double h = P.h;
+        tiles([&](int slot, int l, bool comp, bool irr) {
+          const size_t idx = (size_t)slot * TILE_PTS + l;
+          const double u = comp ? V(V_X0)[idx] : 0.0;
+          V(V_B1)[idx] = comp ? h * react(u) : 0.0;
+          V(V_U)[idx] = u;
+        });
+        if (!barrier()) return;
+        phi_comb(1, h);
+        return;
+      }
+      case JOB_ETD2RK:
+      case JOB_ETD2RK_STAGE: {
+        const double h = P.h;
+        tiles([&](int slot, int l, bool comp, bool irr) {
+          const size_t idx = (size_t)slot * TILE_PTS + l;
+          const double u = comp ? V(V_X0)[idx] : 0.0;
+          V(V_B1)[idx] = comp ? h * react(u) : 0.0;
+          V(V_U)[idx] = u;
+        });
+        if (!barrier()) return;
+        if (!phi_comb(1, h)) return;
+        if (P.mode == JOB_ETD2RK_STAGE) return;
+        tiles([&](int slot, int l, bool comp, bool irr) {
+          const size_t idx = (size_t)slot * TILE_PTS + l;
+          const double a = V(V_U)[idx];
+          const double u = comp ? V(V_X0)[idx] : 0.0;
+          V(V_B2)[idx] = comp ? h * (react(a) - react(u)) : 0.0;
+          V(V_U)[idx] = u;
+        });
+        if (!barrier()) return;
+        phi_comb(2, h);
+        return;
+      }
+      case JOB_APPLY: {
+        tiles([&](int slot, int l, bool comp, bool irr) {
+          const size_t idx = (size_t)slot * TILE_PTS + l;
+          V(V_U)[idx] = apply_A<DIM>(P.g, V(V_B0), slot, l, c.nb, comp, irr);
+        });
+        barrier();
+        return;
+      }
+      default:
+        if (threadIdx.x == 0 && blockIdx.x == 0) atomicCAS(P.status, 0, ST_INVALID);
+        return;
+    }
+  }
+};
+
+template <int DIM>
+__global__ __launch_bounds__(KBLOCK) void krylov_kernel(KrylovDev P) {
+  __shared__ Ctl c;
+  __shared__ double R[EXPM_NMAX * EXPM_NMAX];
+  __shared__ double S[EXPM_NMAX * EXPM_NMAX];
+  Engine<DIM> e{P, c, R, S, *P.g.n_active, 0};
+  for (int k = 0; k <= PMAX; ++k) {
+    e.m_guess[k] = P.st->m_guess[k];
+    e.tau_frac[k] = P.st->tau_frac[k];
+  }
+  e.substeps = e.rejected = e.matvecs = e.m_last = e.expms = 0;
+  e.err_est = 0.0;
+  e.t_done = 0.0;
+  e.failed = false;
+  e.iu = V_U;
+  __syncthreads();
+  e.run();
+  __syncthreads();
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    for (int k = 0; k <= PMAX; ++k) {
+      P.st->m_guess[k] = e.m_guess[k];
+      P.st->tau_frac[k] = e.tau_frac[k];
+    }
+    P.st->substeps = e.substeps;
+    P.st->rejected = e.rejected;
+    P.st->matvecs = e.matvecs;
+    P.st->m_last = e.m_last;
+    P.st->expms = e.expms;
+    P.st->calls += 1;
+    P.st->err_est = e.err_est;
+    P.st->t_done = e.t_done;
+  }
+}
+
+// Reset the barrier state before a persistent launch (a kernel, not a
+// memset, so the sequence can sit inside a captured graph).
+__global__ void barrier_reset_kernel(BarrierDev* b) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    b->count = 0;
+    b->gen = 0;
+    b->abort = 0;
+  }
+}
+
+int krylov_max_blocks_per_cu(int dim) {
+  int nb = 0;
+  hipError_t e = (dim == 2)
+      ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, krylov_kernel<2>, KBLOCK, 0)
+      : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, krylov_kernel<3>, KBLOCK, 0);
+  if (e != hipSuccess) return 0;
+  return nb;
+}
+
+// Reset the barrier, then the cooperative launch (co-residency of all blocks
+// is what makes the grid barrier safe).
+hipError_t launch_krylov(int dim, const KrylovDev& P, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(barrier_reset_kernel, dim3(1), dim3(64), 0, s, P.bar);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  KrylovDev arg = P;
+  void* args[] = {&arg};
+  const void* fn = (dim == 2) ? (const void*)krylov_kernel<2> : (const void*)krylov_kernel<3>;
+  return hipLaunchCooperativeKernel(fn, dim3(grid), dim3(KBLOCK), args, 0, s);
+}
+
+}  // namespace etdfb
