@@ -95,6 +95,19 @@ typedef struct {
   double t_done;
 } etd_stats;
 
+/* Accumulated device timings (milliseconds, HIP events on the context's
+ * stream) and algorithmic traffic, for measurement. */
+typedef struct {
+  double krylov_ms;          /* persistent phi-combination / ETD launches */
+  double levelset_ms;        /* level-set sweep sequences */
+  double geometry_ms;        /* geometry builds */
+  double alg_bytes;          /* algorithmic HBM bytes of the Krylov launches */
+  int32_t krylov_launches;
+  int32_t levelset_calls;
+  int32_t geometry_calls;
+  int32_t n_unknowns;        /* computational points of the current geometry */
+} etd_profile;
+
 typedef struct etd_ctx etd_ctx;
 
 /* Create a context for one grid.  hip_stream: a hipStream_t (NULL = the
@@ -159,6 +172,12 @@ int etd_ctx_sync(etd_ctx* ctx);
 
 /* Statistics of the last job (synchronises). */
 int etd_ctx_stats(etd_ctx* ctx, etd_stats* stats);
+
+/* Enable (1) or disable (0) event timing of the launches of a context. */
+int etd_ctx_profile_enable(etd_ctx* ctx, int32_t enable);
+
+/* Synchronise and read the accumulated timings; reset != 0 clears them. */
+int etd_ctx_profile_read(etd_ctx* ctx, etd_profile* out, int32_t reset);
 
 /* Human-readable name of a status code (static string). */
 const char* etd_status_string(int status);

@@ -46,6 +46,15 @@ class EtdStats(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class EtdProfile(C.Structure):
+    _fields_ = [("krylov_ms", C.c_double), ("levelset_ms", C.c_double), ("geometry_ms", C.c_double),
+                ("alg_bytes", C.c_double), ("krylov_launches", C.c_int32), ("levelset_calls", C.c_int32),
+                ("geometry_calls", C.c_int32), ("n_unknowns", C.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 # name -> (restype, argtypes); the set of symbols include/etdfb.h declares
 SIGNATURES = {
     "etd_ctx_create": (C.c_int, [C.POINTER(EtdGrid), C.POINTER(EtdPhysics), C.POINTER(EtdKrylovOpts),
@@ -62,6 +71,8 @@ SIGNATURES = {
                            C.POINTER(EtdStats)]),
     "etd_ctx_sync": (C.c_int, [C.c_void_p]),
     "etd_ctx_stats": (C.c_int, [C.c_void_p, C.POINTER(EtdStats)]),
+    "etd_ctx_profile_enable": (C.c_int, [C.c_void_p, C.c_int32]),
+    "etd_ctx_profile_read": (C.c_int, [C.c_void_p, C.POINTER(EtdProfile), C.c_int32]),
     "etd_status_string": (C.c_char_p, [C.c_int]),
 }
 

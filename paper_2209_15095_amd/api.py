@@ -119,6 +119,14 @@ class Context:
                                   C.byref(st) if st is not None else None), "etd_step")
         return st.as_dict() if stats else None
 
+    def profile_enable(self, on: bool = True):
+        L.check(self.lib.etd_ctx_profile_enable(self.handle, int(bool(on))), "etd_ctx_profile_enable")
+
+    def profile_read(self, reset: bool = False):
+        pr = L.EtdProfile()
+        L.check(self.lib.etd_ctx_profile_read(self.handle, C.byref(pr), int(bool(reset))), "etd_ctx_profile_read")
+        return pr.as_dict()
+
     def sync(self):
         L.check(self.lib.etd_ctx_sync(self.handle), "etd_ctx_sync")
 

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <vector>
@@ -36,7 +37,10 @@ struct etd_ctx {
   // persistent kernel state
   double* ws = nullptr;
   double* part = nullptr;
+  unsigned* flags = nullptr;
   BarrierDev* bar = nullptr;
+  int n_cu = 0;
+  int tmax = 1;
   KrylovStateDev* st = nullptr;
   int max_grid = 0;
   int grid_blocks = 1;
@@ -47,9 +51,58 @@ struct etd_ctx {
   // pinned host mirror for small readbacks
   int* h_counters = nullptr;
   KrylovStateDev* h_state = nullptr;
+  // event timing
+  bool profiling = false;
+  struct Timer {
+    std::vector<hipEvent_t> start, stop;
+    size_t used = 0;
+    double ms = 0.0;
+    int count = 0;
+  } t_krylov, t_levelset, t_geometry;
 };
 
 namespace {
+
+hipError_t timer_begin(etd_ctx* c, etd_ctx::Timer& t) {
+  if (!c->profiling) return hipSuccess;
+  if (t.used == t.start.size()) {
+    hipEvent_t a, b;
+    hipError_t e = hipEventCreate(&a);
+    if (e != hipSuccess) return e;
+    e = hipEventCreate(&b);
+    if (e != hipSuccess) return e;
+    t.start.push_back(a);
+    t.stop.push_back(b);
+  }
+  return hipEventRecord(t.start[t.used], c->stream);
+}
+
+hipError_t timer_end(etd_ctx* c, etd_ctx::Timer& t) {
+  if (!c->profiling) return hipSuccess;
+  hipError_t e = hipEventRecord(t.stop[t.used], c->stream);
+  ++t.used;
+  return e;
+}
+
+// fold recorded pairs into ms (stream must be synchronised)
+hipError_t timer_collect(etd_ctx::Timer& t) {
+  for (size_t i = 0; i < t.used; ++i) {
+    float ms = 0.0f;
+    hipError_t e = hipEventElapsedTime(&ms, t.start[i], t.stop[i]);
+    if (e != hipSuccess) return e;
+    t.ms += ms;
+    ++t.count;
+  }
+  t.used = 0;
+  return hipSuccess;
+}
+
+void timer_free(etd_ctx::Timer& t) {
+  for (auto e : t.start) (void)hipEventDestroy(e);
+  for (auto e : t.stop) (void)hipEventDestroy(e);
+  t.start.clear();
+  t.stop.clear();
+}
 
 int check_hip(hipError_t e) { return e == hipSuccess ? ETD_OK : ETD_ERR_HIP; }
 
@@ -72,6 +125,7 @@ GeomDev geom_view(const etd_ctx* c) {
   g.irr_bits = c->irr_bits;
   g.cdiag = c->cdiag;
   g.n_active = c->counters + 0;
+  g.n_unknowns = c->counters + 4;
   g.coef = c->phys.beta / (c->box.dx * c->box.dx);
   g.dx = c->box.dx;
   return g;
@@ -83,7 +137,9 @@ KrylovDev krylov_params(const etd_ctx* c, int mode) {
   P.ws = c->ws;
   P.ld = c->ld;
   P.part = c->part;
+  P.flags = c->flags;
   P.bar = c->bar;
+  P.tmax = c->tmax;
   P.status = c->counters + 1;
   P.st = c->st;
   P.tol = c->opts.tol;
@@ -97,9 +153,43 @@ KrylovDev krylov_params(const etd_ctx* c, int mode) {
   return P;
 }
 
+// Grid of the persistent kernel: one block per active tile up to the number
+// of co-resident blocks; each block caches the metadata of its tiles in
+// dynamic LDS (tmax entries), which in turn bounds the blocks per CU.
+// ETDFB_GRID in the environment overrides the block count.
+void choose_launch(etd_ctx* c) {
+  const int nact = c->n_active_host > 0 ? c->n_active_host : 1;
+  int g = nact;
+  int tmax = 1;
+  for (int it = 0; it < 4; ++it) {
+    const int per_cu = krylov_max_blocks_per_cu(c->box.dim, tmax);
+    int gmax = per_cu * c->n_cu;
+    if (gmax > c->max_grid) gmax = c->max_grid;
+    if (gmax < 1) gmax = 1;
+    g = nact < gmax ? nact : gmax;
+    const int need = (nact + g - 1) / g;
+    const int nt = need > 256 ? 256 : need;
+    if (nt == tmax) break;
+    tmax = nt;
+  }
+  if (const char* env = getenv("ETDFB_GRID")) {
+    int v = atoi(env);
+    if (v >= 1 && v <= g) g = v;
+    const int need = (nact + g - 1) / g;
+    tmax = need > 256 ? 256 : need;
+    const int per_cu = krylov_max_blocks_per_cu(c->box.dim, tmax);
+    if (per_cu * c->n_cu < g) g = per_cu * c->n_cu;
+  }
+  c->grid_blocks = g;
+  c->tmax = tmax;
+}
+
 int run_krylov(etd_ctx* c, const KrylovDev& P) {
   if (!c->have_geometry) return ETD_ERR_NO_GEOMETRY;
-  return check_hip(launch_krylov(c->box.dim, P, c->grid_blocks, c->stream));
+  if (timer_begin(c, c->t_krylov) != hipSuccess) return ETD_ERR_HIP;
+  hipError_t e = launch_krylov(c->box.dim, P, c->grid_blocks, c->stream);
+  if (e != hipSuccess) return ETD_ERR_HIP;
+  return check_hip(timer_end(c, c->t_krylov));
 }
 
 int gather_to(etd_ctx* c, const double* box, int vec) {
@@ -114,7 +204,7 @@ int scatter_from(etd_ctx* c, int vec, double* box) {
 }
 
 int fill_stats(etd_ctx* c, etd_stats* s) {
-  HIP_TRY(hipMemcpyAsync(c->h_counters, c->counters, 4 * sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipMemcpyAsync(c->h_counters, c->counters, 8 * sizeof(int), hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(hipMemcpyAsync(c->h_state, c->st, sizeof(KrylovStateDev), hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(hipStreamSynchronize(c->stream));
   s->substeps = c->h_state->substeps;
@@ -123,7 +213,7 @@ int fill_stats(etd_ctx* c, etd_stats* s) {
   s->m_last = c->h_state->m_last;
   s->expms = c->h_state->expms;
   s->n_active_tiles = c->h_counters[0];
-  s->n_unknowns = -1;
+  s->n_unknowns = c->h_counters[4];
   s->status = c->h_counters[1];
   s->err_est = c->h_state->err_est;
   s->t_done = c->h_state->t_done;
@@ -144,10 +234,13 @@ int latched_status(etd_ctx* c) {
 
 void free_all(etd_ctx* c) {
   void* ptrs[] = {c->mask, c->tile_flag, c->tile_map, c->slot_tile, c->comp_bits, c->irr_bits, c->cdiag,
-                  c->counters, c->ws, c->part, c->bar, c->st};
+                  c->counters, c->ws, c->part, c->flags, c->bar, c->st};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   levelset_free(c->ls);
+  timer_free(c->t_krylov);
+  timer_free(c->t_levelset);
+  timer_free(c->t_geometry);
   if (c->h_counters) (void)hipHostFree(c->h_counters);
   if (c->h_state) (void)hipHostFree(c->h_state);
 }
@@ -217,7 +310,8 @@ int etd_ctx_create(const etd_grid* grid, const etd_physics* phys, const etd_kryl
   c->ntiles = b.ntx * b.nty * b.ntz;
   c->nodes = (size_t)b.nx * b.ny * b.nz;
   c->ld = (size_t)c->ntiles * TILE_PTS;
-  const int per_cu = krylov_max_blocks_per_cu(b.dim);
+  c->n_cu = prop.multiProcessorCount;
+  const int per_cu = krylov_max_blocks_per_cu(b.dim, 1);
   c->max_grid = per_cu * prop.multiProcessorCount;
   if (c->max_grid < 1) { delete c; return ETD_ERR_HIP; }
   bool ok = true;
@@ -231,6 +325,7 @@ int etd_ctx_create(const etd_grid* grid, const etd_physics* phys, const etd_kryl
   ok &= hipMalloc(&c->counters, sizeof(int) * 8) == hipSuccess;
   ok &= hipMalloc(&c->ws, sizeof(double) * c->ld * NVEC) == hipSuccess;
   ok &= hipMalloc(&c->part, sizeof(double) * 2 * (size_t)c->max_grid * PART_STRIDE) == hipSuccess;
+  ok &= hipMalloc(&c->flags, sizeof(unsigned) * (size_t)c->max_grid) == hipSuccess;
   ok &= hipMalloc(&c->bar, sizeof(BarrierDev)) == hipSuccess;
   ok &= hipMalloc(&c->st, sizeof(KrylovStateDev)) == hipSuccess;
   ok &= hipHostMalloc(&c->h_counters, sizeof(int) * 8) == hipSuccess;
@@ -283,19 +378,18 @@ int etd_ctx_set_beta(etd_ctx* c, double beta) {
 
 int etd_geometry_build(etd_ctx* c, const double* rho) {
   if (!c || !rho) return ETD_ERR_INVALID;
+  HIP_TRY(timer_begin(c, c->t_geometry));
   HIP_TRY(launch_fill_int(c->tile_flag, c->ntiles, 0, c->stream));
-  HIP_TRY(launch_fill_int(c->counters + 2, 2, 0, c->stream));
+  HIP_TRY(launch_fill_int(c->counters + 2, 3, 0, c->stream));
   HIP_TRY(launch_classify(c->box, rho, c->mask, c->tile_flag, c->counters + 1, c->stream));
   HIP_TRY(launch_scan_tiles(c->tile_flag, c->ntiles, c->tile_map, c->slot_tile, c->counters + 0, c->stream));
   HIP_TRY(launch_tile_coeff(c->box, rho, c->mask, c->tile_map, c->comp_bits, c->irr_bits, c->cdiag,
                             c->counters + 2, c->ntiles, c->stream));
-  HIP_TRY(hipMemcpyAsync(c->h_counters, c->counters, 4 * sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(timer_end(c, c->t_geometry));
+  HIP_TRY(hipMemcpyAsync(c->h_counters, c->counters, 8 * sizeof(int), hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(hipStreamSynchronize(c->stream));
   c->n_active_host = c->h_counters[0];
-  int g = c->n_active_host;
-  if (g < 1) g = 1;
-  if (g > c->max_grid) g = c->max_grid;
-  c->grid_blocks = g;
+  choose_launch(c);
   c->have_geometry = true;
   if (c->h_counters[1] == ST_DOMAIN) {
     int zero = 0;
@@ -357,7 +451,9 @@ int levelset_advance(etd_ctx* c, double* rho, double* u, double dt, int32_t rein
   a.reinit = reinit;
   a.mask = c->mask;
   a.status = c->counters + 1;
+  HIP_TRY(timer_begin(c, c->t_levelset));
   HIP_TRY(levelset_run(a, c->ls, rho, u, c->stream));
+  HIP_TRY(timer_end(c, c->t_levelset));
   return etd_geometry_build(c, rho);
 }
 
@@ -395,6 +491,38 @@ int etd_ctx_sync(etd_ctx* c) {
 int etd_ctx_stats(etd_ctx* c, etd_stats* s) {
   if (!c || !s) return ETD_ERR_INVALID;
   return fill_stats(c, s);
+}
+
+int etd_ctx_profile_enable(etd_ctx* c, int32_t enable) {
+  if (!c) return ETD_ERR_INVALID;
+  c->profiling = enable != 0;
+  return ETD_OK;
+}
+
+int etd_ctx_profile_read(etd_ctx* c, etd_profile* out, int32_t reset) {
+  if (!c || !out) return ETD_ERR_INVALID;
+  HIP_TRY(hipMemcpyAsync(c->h_state, c->st, sizeof(KrylovStateDev), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipMemcpyAsync(c->h_counters, c->counters, 8 * sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  HIP_TRY(timer_collect(c->t_krylov));
+  HIP_TRY(timer_collect(c->t_levelset));
+  HIP_TRY(timer_collect(c->t_geometry));
+  out->krylov_ms = c->t_krylov.ms;
+  out->levelset_ms = c->t_levelset.ms;
+  out->geometry_ms = c->t_geometry.ms;
+  out->krylov_launches = c->t_krylov.count;
+  out->levelset_calls = c->t_levelset.count;
+  out->geometry_calls = c->t_geometry.count;
+  out->alg_bytes = c->h_state->alg_bytes_total;
+  out->n_unknowns = c->h_counters[4];
+  if (reset) {
+    c->t_krylov.ms = c->t_levelset.ms = c->t_geometry.ms = 0.0;
+    c->t_krylov.count = c->t_levelset.count = c->t_geometry.count = 0;
+    const double zero = 0.0;
+    HIP_TRY(hipMemcpyAsync(&c->st->alg_bytes_total, &zero, sizeof(double), hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+  }
+  return ETD_OK;
 }
 
 }  // extern "C"

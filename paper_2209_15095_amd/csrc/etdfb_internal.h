@@ -12,6 +12,7 @@ constexpr int MMAX_LIMIT = 64;      // largest Krylov dimension
 constexpr int PMAX = 3;             // largest phi index in one combination
 constexpr int EXPM_NMAX = MMAX_LIMIT + PMAX + 2;   // augmented matrix bound
 constexpr int KBLOCK = 256;         // threads per block of the persistent kernels
+constexpr double NOT_COMP = -1e300; // coefficient sentinel of non-computational points
 
 // Work vectors of the persistent kernel (indices into the workspace).
 enum VecIndex {
@@ -46,8 +47,9 @@ struct GeomDev {
   const int* slot_tile;       // [cap] slot -> box tile index
   const uint64_t* comp_bits;  // [cap*4]
   const uint64_t* irr_bits;   // [cap*4]
-  const double* cdiag;        // [cap*256] diagonal weight sum at irregular points
+  const double* cdiag;        // [cap*256] diagonal weight sum c_p; NOT_COMP off the unknowns
   const int* n_active;        // device scalar: number of active tiles
+  const int* n_unknowns;      // device scalar: number of computational points
   double coef;                // beta / h^2
   double dx;
 };
@@ -59,6 +61,8 @@ struct KrylovStateDev {
   int substeps, rejected, matvecs, m_last, expms, calls;
   double err_est;
   double t_done;
+  double alg_bytes_per_unknown;   // algorithmic HBM bytes per unknown, last launch
+  double alg_bytes_total;         // accumulated over launches: bytes/unknown * unknowns
 };
 
 enum JobMode {
@@ -74,7 +78,9 @@ struct KrylovDev {
   double* ws;                 // NVEC vectors of ld doubles
   size_t ld;
   double* part;               // 2 * gridDim * PART_STRIDE partial sums
+  unsigned* flags;            // [gridDim] arrival generation of each block
   BarrierDev* bar;
+  int tmax;                   // tiles per block cached in dynamic LDS
   int* status;                // first error code (0 = ok)
   KrylovStateDev* st;
   double tol;

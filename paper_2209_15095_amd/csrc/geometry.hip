@@ -8,10 +8,11 @@
 //                     a domain error.
 // scan_tiles_kernel   active tiles -> slots in lexicographic tile order.
 // tile_coeff_kernel   per active tile: computational / irregular bit masks and,
-//                     per computational point, the diagonal weight sum
+//                     per point of the tile, the diagonal weight sum
 //                     c_p = sum over faces of 1 (Case 1), h/s = 1/(1+theta)
 //                     (Case 2), 1 - w_p (Case 3), so that
-//                     (A v)_p = beta/h^2 (sum_q v_q - c_p v_p).
+//                     (A v)_p = beta/h^2 (sum_q v_q - c_p v_p); NOT_COMP
+//                     marks the other points of the tile.
 //
 // Case 3 weight (ghost q of p whose next node on the line is inside): the
 // linear interpolant through p and the closest boundary points x_G1 of q and
@@ -242,9 +243,10 @@ __global__ __launch_bounds__(256) void tile_coeff_kernel(BoxDev b, const double*
     comp_bits[(size_t)slot * 4 + (l >> 6)] = cb;
     irr_bits[(size_t)slot * 4 + (l >> 6)] = ib;
   }
-  cdiag[(size_t)slot * TILE_PTS + l] = c;
+  cdiag[(size_t)slot * TILE_PTS + l] = comp ? c : NOT_COMP;
   if (n2) atomicAdd(&counts[0], n2);
   if (n3) atomicAdd(&counts[1], n3);
+  if ((l & 63) == 0) atomicAdd(&counts[2], __popcll(cb));
 }
 
 // box -> tile layout (0 at non-computational points).  grid >= cap tiles.

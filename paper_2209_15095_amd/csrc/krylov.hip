@@ -60,6 +60,10 @@ struct Engine {
   double err_est, t_done;
   bool failed;
   int iu;   // vector holding u(t_j) = W_0 (V_U or V_T, ping-pong with the combine output)
+  // Algorithmic HBM bytes per unknown moved so far: what the method must read
+  // and write per computational point (vectors only; neighbour re-reads,
+  // masks and tile padding are not counted).
+  double bpu;
 
   __device__ double* V(int i) const { return P.ws + (size_t)i * P.ld; }
 
@@ -145,6 +149,7 @@ struct Engine {
         acc[1] += u * u;
       }
     });
+    bpu += 8.0 * ((p - k + 1) + 2 + (k == p ? 1 : 0));
     if (k == p) return finish<2>(acc, out);
     return barrier();
   }
@@ -159,6 +164,7 @@ struct Engine {
       acc[0] += u * u;
       acc[1] += u * u;
     });
+    bpu += 16.0;
     return finish<2>(acc, out);
   }
 
@@ -173,6 +179,7 @@ struct Engine {
       z[idx] = zz;
       acc[0] += zz * q[idx];
     });
+    bpu += 24.0;
     double out[1];
     if (!finish<1>(acc, out)) return false;
     dot = out[0];
@@ -225,6 +232,7 @@ struct Engine {
       V(io)[idx] = u;
       acc[0] += u * u;
     });
+    bpu += 8.0 * (m + p + 1);
     double out[1];
     if (!finish<1>(acc, out)) return false;
     nn = out[0];
@@ -464,6 +472,7 @@ struct Engine {
       const size_t idx = (size_t)slot * TILE_PTS + l;
       V(dst)[idx] = comp ? V(src)[idx] : 0.0;
     });
+    bpu += 16.0;
     return barrier();
   }
 
@@ -482,6 +491,7 @@ struct Engine {
           V(V_B1)[idx] = comp ? h * react(u) : 0.0;
           V(V_U)[idx] = u;
         });
+        bpu += 24.0;
         if (!barrier()) return;
         phi_comb(1, h);
         return;
@@ -495,6 +505,7 @@ struct Engine {
           V(V_B1)[idx] = comp ? h * react(u) : 0.0;
           V(V_U)[idx] = u;
         });
+        bpu += 24.0;
         if (!barrier()) return;
         if (!phi_comb(1, h)) return;
         if (P.mode == JOB_ETD2RK_STAGE) return;
@@ -505,6 +516,7 @@ struct Engine {
           V(V_B2)[idx] = comp ? h * (react(a) - react(u)) : 0.0;
           V(V_U)[idx] = u;
         });
+        bpu += 32.0;
         if (!barrier()) return;
         phi_comb(2, h);
         return;
@@ -514,6 +526,7 @@ struct Engine {
           const size_t idx = (size_t)slot * TILE_PTS + l;
           V(V_U)[idx] = apply_A<DIM>(P.g, V(V_B0), slot, l, c.nb, comp, irr);
         });
+        bpu += 16.0;
         barrier();
         return;
       }
@@ -539,6 +552,7 @@ __global__ __launch_bounds__(KBLOCK) void krylov_kernel(KrylovDev P) {
   e.t_done = 0.0;
   e.failed = false;
   e.iu = V_U;
+  e.bpu = 0.0;
   __syncthreads();
   e.run();
   __syncthreads();
@@ -555,6 +569,8 @@ __global__ __launch_bounds__(KBLOCK) void krylov_kernel(KrylovDev P) {
     P.st->calls += 1;
     P.st->err_est = e.err_est;
     P.st->t_done = e.t_done;
+    P.st->alg_bytes_per_unknown = e.bpu;
+    P.st->alg_bytes_total += e.bpu * (double)(*P.g.n_unknowns);
   }
 }
 
@@ -568,7 +584,7 @@ __global__ void barrier_reset_kernel(BarrierDev* b) {
   }
 }
 
-int krylov_max_blocks_per_cu(int dim) {
+int krylov_max_blocks_per_cu(int dim, int /*tmax*/) {
   int nb = 0;
   hipError_t e = (dim == 2)
       ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, krylov_kernel<2>, KBLOCK, 0)
@@ -576,6 +592,8 @@ int krylov_max_blocks_per_cu(int dim) {
   if (e != hipSuccess) return 0;
   return nb;
 }
+
+size_t krylov_dyn_lds(int /*dim*/, int /*tmax*/) { return 0; }
 
 // Reset the barrier, then the cooperative launch (co-residency of all blocks
 // is what makes the grid barrier safe).

@@ -32,6 +32,7 @@ hipError_t launch_scatter(const BoxHost& b, const double* vec, const int* tile_m
 
 // krylov.hip
 hipError_t launch_krylov(int dim, const KrylovDev& P, int grid, hipStream_t s);
-int krylov_max_blocks_per_cu(int dim);
+int krylov_max_blocks_per_cu(int dim, int tmax);
+size_t krylov_dyn_lds(int dim, int tmax);
 
 }  // namespace etdfb
