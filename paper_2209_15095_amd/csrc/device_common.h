@@ -76,46 +76,9 @@ __device__ __forceinline__ double apply_A(const GeomDev& g, const double* __rest
   return g.coef * (neighbour_sum<DIM>(v, slot, l, nb) - c * vp);
 }
 
-// ---------------------------------------------------------------- barrier
-
-// Grid-wide barrier for a co-resident (cooperatively launched) grid.
-// Every thread publishes its stores at agent scope, thread 0 arrives on an
-// atomic counter and waits for the generation to advance.  The wait is
-// bounded: past SPIN_LIMIT polls the block raises the abort flag, and once
-// the flag is up every barrier returns at once, so all waves always exit.
+// Bound on the polls of a grid synchronisation before it gives up (and
+// raises the abort flag so that every block exits).
 constexpr long SPIN_LIMIT = 1L << 24;
-
-__device__ __forceinline__ bool grid_barrier(BarrierDev* b, int nblocks) {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-  __syncthreads();
-  __shared__ int s_abort;
-  if (threadIdx.x == 0) {
-    int ab = __hip_atomic_load(&b->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (!ab) {
-      unsigned gen = __hip_atomic_load(&b->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      unsigned prev = __hip_atomic_fetch_add(&b->count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-      if (prev == (unsigned)nblocks - 1u) {
-        __hip_atomic_store(&b->count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store(&b->gen, gen + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-      } else {
-        long spins = 0;
-        while (__hip_atomic_load(&b->gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
-          __builtin_amdgcn_s_sleep(1);
-          if (++spins > SPIN_LIMIT) {
-            __hip_atomic_store(&b->abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            break;
-          }
-          if (__hip_atomic_load(&b->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
-        }
-      }
-      ab = __hip_atomic_load(&b->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    s_abort = ab;
-  }
-  __syncthreads();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-  return s_abort == 0;
-}
 
 // ---------------------------------------------------------------- reductions
 
@@ -139,26 +102,6 @@ __device__ __forceinline__ void block_sum(double (&v)[NR], double* scratch) {
 #pragma unroll
   for (int k = 0; k < NR; ++k)
     v[k] = ((scratch[k] + scratch[NR + k]) + scratch[2 * NR + k]) + scratch[3 * NR + k];
-  __syncthreads();
-}
-
-// Reduce the per-block partials of a pass (written before a grid barrier)
-// in fixed order; every block obtains bit-identical sums.
-template <int NR>
-__device__ __forceinline__ void grid_partials_sum(const double* __restrict__ part, int nblocks,
-                                                  double (&out)[NR], double* scratch) {
-  if (threadIdx.x < 64) {
-#pragma unroll
-    for (int k = 0; k < NR; ++k) {
-      double s = 0.0;
-      for (int b = threadIdx.x; b < nblocks; b += 64) s += part[(size_t)b * PART_STRIDE + k];
-      s = wave_sum_lane0(s);
-      if (threadIdx.x == 0) scratch[k] = s;
-    }
-  }
-  __syncthreads();
-#pragma unroll
-  for (int k = 0; k < NR; ++k) out[k] = scratch[k];
   __syncthreads();
 }
 

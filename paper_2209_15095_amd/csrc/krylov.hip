@@ -43,9 +43,13 @@ struct Ctl {
   double red[8];
   double scratch[4 * 8];
   int nb[6];
+  int abort;
 };
 
-template <int DIM>
+// BATCH: every block runs its own instance (its own KrylovDev) and
+// synchronises only within the block; otherwise the whole grid works on one
+// instance and synchronises with the flag barrier below.
+template <int DIM, bool BATCH>
 struct Engine {
   const KrylovDev& P;
   Ctl& c;
@@ -68,37 +72,96 @@ struct Engine {
   __device__ double* V(int i) const { return P.ws + (size_t)i * P.ld; }
 
   __device__ void fail(int code) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) atomicCAS(P.status, 0, code);
+    if (threadIdx.x == 0 && (BATCH || blockIdx.x == 0)) atomicCAS(P.status, 0, code);
     failed = true;
   }
 
-  // Close a pass: block sum of NR partials, publish, grid barrier, fixed-order
-  // grid reduction into out[].  Returns false if the barrier aborted.
+  // Grid synchronisation fused with the reduction of NR per-block partials.
+  // Every wave waits for its own stores, one agent-scope release per block
+  // publishes them, lane 0 writes the block's partials and then its arrival
+  // generation into its own flag; wave 0 polls every flag (no contended
+  // atomic), acquires, and sums the partials in block order, so every block
+  // obtains bit-identical results.  Polls are bounded: past SPIN_LIMIT the
+  // abort flag goes up and every block leaves.
+  template <int NR>
+  __device__ bool grid_sync(const double (&acc)[NR], double (&out)[NR]) {
+    const int G = gridDim.x;
+    ++pass_no;
+    const unsigned gen = (unsigned)pass_no;
+    double* part = P.part + (size_t)(gen & 1u) * G * PART_STRIDE;
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (threadIdx.x < 64) {
+      const int lane = threadIdx.x;
+      if (lane == 0) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        for (int k = 0; k < NR; ++k) part[(size_t)blockIdx.x * PART_STRIDE + k] = acc[k];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __hip_atomic_store(&P.flags[blockIdx.x], gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+      long spins = 0;
+      int ab = 0;
+      while (true) {
+        bool mine = true;
+        for (int b = lane; b < G; b += 64)
+          mine &= (__hip_atomic_load(&P.flags[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= gen);
+        if (__ballot(!mine) == 0ull) break;
+        __builtin_amdgcn_s_sleep(1);
+        if ((++spins & 255) == 0) {
+          ab = __hip_atomic_load(&P.bar->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          if (ab) break;
+          if (spins > SPIN_LIMIT) {
+            if (lane == 0) __hip_atomic_store(&P.bar->abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            ab = 1;
+            break;
+          }
+        }
+      }
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      for (int k = 0; k < NR; ++k) {
+        double t = 0.0;
+        for (int b = lane; b < G; b += 64) t += part[(size_t)b * PART_STRIDE + k];
+        t = wave_sum_lane0(t);
+        if (lane == 0) c.red[k] = t;
+      }
+      if (lane == 0) c.abort = ab;
+    }
+    __syncthreads();
+    for (int k = 0; k < NR; ++k) out[k] = c.red[k];
+    const int ab = c.abort;
+    __syncthreads();
+    return ab == 0;
+  }
+
+  // Close a pass: block sum of NR partials, then (grid mode) the grid
+  // synchronisation with the fixed-order grid reduction into out[].
+  // Returns false on a barrier time-out or a non-finite sum (status set; every
+  // block takes the same exit).
   template <int NR>
   __device__ bool finish(double (&acc)[NR], double (&out)[NR]) {
     block_sum<NR>(acc, c.scratch);
-    double* part = P.part + (size_t)(pass_no & 1) * gridDim.x * PART_STRIDE;
-    if (threadIdx.x == 0)
-      for (int k = 0; k < NR; ++k) part[(size_t)blockIdx.x * PART_STRIDE + k] = acc[k];
-    ++pass_no;
-    if (!grid_barrier(P.bar, gridDim.x)) {
+    if (BATCH) {
+      for (int k = 0; k < NR; ++k) out[k] = acc[k];
+    } else if (!grid_sync<NR>(acc, out)) {
       if (threadIdx.x == 0) atomicCAS(P.status, 0, ST_BARRIER);
       failed = true;
       return false;
     }
-    grid_partials_sum<NR>(part, gridDim.x, out, c.scratch);
     for (int k = 0; k < NR; ++k)
       if (!isfinite(out[k])) {
-        if (threadIdx.x == 0 && blockIdx.x == 0) atomicCAS(P.status, 0, ST_NONFINITE);
-        failed = true;
+        fail(ST_NONFINITE);
         return false;
       }
     return true;
   }
 
   __device__ bool barrier() {
-    ++pass_no;
-    if (!grid_barrier(P.bar, gridDim.x)) {
+    if (BATCH) {
+      __syncthreads();
+      return true;
+    }
+    double a[1] = {0.0}, o[1];
+    if (!grid_sync<1>(a, o)) {
       if (threadIdx.x == 0) atomicCAS(P.status, 0, ST_BARRIER);
       failed = true;
       return false;
@@ -109,7 +172,9 @@ struct Engine {
   // Loop over the active tiles assigned to this block; f(slot, l, comp, irr).
   template <class F>
   __device__ void tiles(F&& f) {
-    for (int slot = blockIdx.x; slot < nact; slot += gridDim.x) {
+    const int s0 = BATCH ? 0 : (int)blockIdx.x;
+    const int ds = BATCH ? 1 : (int)gridDim.x;
+    for (int slot = s0; slot < nact; slot += ds) {
       if (threadIdx.x < 2 * DIM) c.nb[threadIdx.x] = face_neighbour_slot<DIM>(P.g, slot, threadIdx.x);
       __syncthreads();
       const int l = threadIdx.x;
@@ -537,12 +602,10 @@ struct Engine {
   }
 };
 
-template <int DIM>
-__global__ __launch_bounds__(KBLOCK) void krylov_kernel(KrylovDev P) {
-  __shared__ Ctl c;
-  __shared__ double R[EXPM_NMAX * EXPM_NMAX];
-  __shared__ double S[EXPM_NMAX * EXPM_NMAX];
-  Engine<DIM> e{P, c, R, S, *P.g.n_active, 0};
+// One block of the persistent kernel; c, R and S are the block's LDS.
+template <int DIM, bool BATCH>
+__device__ void krylov_body(const KrylovDev& P, Ctl& c, double* R, double* S) {
+  Engine<DIM, BATCH> e{P, c, R, S, *P.g.n_active, 0};
   for (int k = 0; k <= PMAX; ++k) {
     e.m_guess[k] = P.st->m_guess[k];
     e.tau_frac[k] = P.st->tau_frac[k];
@@ -556,7 +619,7 @@ __global__ __launch_bounds__(KBLOCK) void krylov_kernel(KrylovDev P) {
   __syncthreads();
   e.run();
   __syncthreads();
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
+  if (threadIdx.x == 0 && (BATCH || blockIdx.x == 0)) {
     for (int k = 0; k <= PMAX; ++k) {
       P.st->m_guess[k] = e.m_guess[k];
       P.st->tau_frac[k] = e.tau_frac[k];
@@ -574,9 +637,31 @@ __global__ __launch_bounds__(KBLOCK) void krylov_kernel(KrylovDev P) {
   }
 }
 
-// Reset the barrier state before a persistent launch (a kernel, not a
-// memset, so the sequence can sit inside a captured graph).
-__global__ void barrier_reset_kernel(BarrierDev* b) {
+// One instance over the whole (cooperatively launched) grid.
+template <int DIM>
+__global__ __launch_bounds__(KBLOCK) void krylov_kernel(KrylovDev P) {
+  __shared__ Ctl c;
+  __shared__ double R[EXPM_NMAX * EXPM_NMAX];
+  __shared__ double S[EXPM_NMAX * EXPM_NMAX];
+  krylov_body<DIM, false>(P, c, R, S);
+}
+
+// A batch: block b runs instance b of Ps[] (ordinary launch, no inter-block
+// dependency).
+template <int DIM>
+__global__ __launch_bounds__(KBLOCK) void krylov_batch_kernel(const KrylovDev* __restrict__ Ps, int count) {
+  __shared__ Ctl c;
+  __shared__ double R[EXPM_NMAX * EXPM_NMAX];
+  __shared__ double S[EXPM_NMAX * EXPM_NMAX];
+  if ((int)blockIdx.x >= count) return;
+  const KrylovDev P = Ps[blockIdx.x];
+  krylov_body<DIM, true>(P, c, R, S);
+}
+
+// Reset the synchronisation state before a persistent launch (a kernel, not
+// a memset, so the sequence can sit inside a captured graph).
+__global__ void sync_reset_kernel(BarrierDev* b, unsigned* flags, int n) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) flags[i] = 0u;
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     b->count = 0;
     b->gen = 0;
@@ -595,10 +680,19 @@ int krylov_max_blocks_per_cu(int dim, int /*tmax*/) {
 
 size_t krylov_dyn_lds(int /*dim*/, int /*tmax*/) { return 0; }
 
+// Batch of instances, one block each (Ps: device array of `count` KrylovDev).
+hipError_t launch_krylov_batch(int dim, const KrylovDev* Ps, int count, hipStream_t s) {
+  if (dim == 2)
+    hipLaunchKernelGGL(krylov_batch_kernel<2>, dim3(count), dim3(KBLOCK), 0, s, Ps, count);
+  else
+    hipLaunchKernelGGL(krylov_batch_kernel<3>, dim3(count), dim3(KBLOCK), 0, s, Ps, count);
+  return hipGetLastError();
+}
+
 // Reset the barrier, then the cooperative launch (co-residency of all blocks
 // is what makes the grid barrier safe).
 hipError_t launch_krylov(int dim, const KrylovDev& P, int grid, hipStream_t s) {
-  hipLaunchKernelGGL(barrier_reset_kernel, dim3(1), dim3(64), 0, s, P.bar);
+  hipLaunchKernelGGL(sync_reset_kernel, dim3(1), dim3(256), 0, s, P.bar, P.flags, grid);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   KrylovDev arg = P;

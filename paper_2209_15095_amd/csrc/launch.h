@@ -34,5 +34,6 @@ hipError_t launch_scatter(const BoxHost& b, const double* vec, const int* tile_m
 hipError_t launch_krylov(int dim, const KrylovDev& P, int grid, hipStream_t s);
 int krylov_max_blocks_per_cu(int dim, int tmax);
 size_t krylov_dyn_lds(int dim, int tmax);
+hipError_t launch_krylov_batch(int dim, const KrylovDev* Ps, int count, hipStream_t s);
 
 }  // namespace etdfb
