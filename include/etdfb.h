@@ -179,6 +179,51 @@ int etd_ctx_profile_enable(etd_ctx* ctx, int32_t enable);
 /* Synchronise and read the accumulated timings; reset != 0 clears them. */
 int etd_ctx_profile_read(etd_ctx* ctx, etd_profile* out, int32_t reset);
 
+/* ------------------------------------------------------------------ batch
+ * Many independent instances (each its own grid, domain, physics) advanced
+ * together: the free-boundary sweeps of all instances share one host
+ * synchronisation, and every ETD step of the batch is one persistent launch
+ * in which each instance is worked on by its own group of blocks, sized by
+ * its number of active tiles, synchronising only within the group.  The
+ * method per instance is exactly that of etd_step (Sections 3 and 4.3). */
+typedef struct etd_batch etd_batch;
+
+/* count instances; grids[i], phys[i] describe instance i (all grids of one
+ * dimension); opts as for etd_ctx_create (may be NULL, shared by all).
+ * Workspaces per instance as for etd_ctx_create. */
+int etd_batch_create(int32_t count, const etd_grid* grids, const etd_physics* phys,
+                     const etd_krylov_opts* opts, void* hip_stream, etd_batch** out);
+int etd_batch_destroy(etd_batch* batch);
+int etd_batch_set_stream(etd_batch* batch, void* hip_stream);
+
+/* At most max_blocks blocks per instance in the batched launch (0 = as many
+ * as its active tiles can use); 1 makes every instance a single block. */
+int etd_batch_set_group_limit(etd_batch* batch, int32_t max_blocks);
+
+/* etd_geometry_build for every instance; rho: host array of count device
+ * pointers.  One synchronisation for the whole batch.  ETD_ERR_DOMAIN if any
+ * instance has a computational point in its two outer box layers. */
+int etd_batch_geometry_build(etd_batch* batch, const double* const* rho);
+
+/* etd_step for every instance with the same scheme, h and reinit flag.
+ * u: host array of count device pointers (box arrays, updated in place).
+ * rho: NULL (frozen domains) or host array of count device pointers.
+ * stats: NULL, or an array of count etd_stats (synchronises). */
+int etd_batch_step(etd_batch* batch, int32_t scheme, double h, double* const* u, double* const* rho,
+                   int32_t reinit, etd_stats* stats);
+
+/* Wait for the stream; first latched device error over the instances (all
+ * cleared), or ETD_OK. */
+int etd_batch_sync(etd_batch* batch);
+
+/* Statistics of instance i's last job (synchronises). */
+int etd_batch_stats(etd_batch* batch, int32_t i, etd_stats* stats);
+
+/* Event timing of the batch launches; profile_read sums the algorithmic
+ * bytes and reports the unknowns over all instances. */
+int etd_batch_profile_enable(etd_batch* batch, int32_t enable);
+int etd_batch_profile_read(etd_batch* batch, etd_profile* out, int32_t reset);
+
 /* Human-readable name of a status code (static string). */
 const char* etd_status_string(int status);
 

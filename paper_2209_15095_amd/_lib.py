@@ -74,6 +74,18 @@ SIGNATURES = {
     "etd_ctx_profile_enable": (C.c_int, [C.c_void_p, C.c_int32]),
     "etd_ctx_profile_read": (C.c_int, [C.c_void_p, C.POINTER(EtdProfile), C.c_int32]),
     "etd_status_string": (C.c_char_p, [C.c_int]),
+    "etd_batch_create": (C.c_int, [C.c_int32, C.POINTER(EtdGrid), C.POINTER(EtdPhysics), C.POINTER(EtdKrylovOpts),
+                                   C.c_void_p, C.POINTER(C.c_void_p)]),
+    "etd_batch_destroy": (C.c_int, [C.c_void_p]),
+    "etd_batch_set_stream": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "etd_batch_set_group_limit": (C.c_int, [C.c_void_p, C.c_int32]),
+    "etd_batch_geometry_build": (C.c_int, [C.c_void_p, C.POINTER(C.c_void_p)]),
+    "etd_batch_step": (C.c_int, [C.c_void_p, C.c_int32, C.c_double, C.POINTER(C.c_void_p),
+                                 C.POINTER(C.c_void_p), C.c_int32, C.POINTER(EtdStats)]),
+    "etd_batch_sync": (C.c_int, [C.c_void_p]),
+    "etd_batch_stats": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(EtdStats)]),
+    "etd_batch_profile_enable": (C.c_int, [C.c_void_p, C.c_int32]),
+    "etd_batch_profile_read": (C.c_int, [C.c_void_p, C.POINTER(EtdProfile), C.c_int32]),
 }
 
 _lib = None

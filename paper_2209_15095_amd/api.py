@@ -134,3 +134,99 @@ class Context:
         st = L.EtdStats()
         L.check(self.lib.etd_ctx_stats(self.handle, C.byref(st)), "etd_ctx_stats")
         return st.as_dict()
+
+
+def _grid_struct(dim, n, lo, hi):
+    g = L.EtdGrid()
+    g.dim = dim
+    for d in range(3):
+        g.n[d] = int(n[d]) if d < dim else 1
+        g.lo[d] = float(lo[d]) if d < dim else 0.0
+        g.hi[d] = float(hi[d]) if d < dim else 1.0
+    return g
+
+
+class Batch:
+    """One etd_batch: independent instances advanced by shared launches.
+
+    grids: list of objects with dim, n, lo, hi; phys: list of dicts with
+    beta, a, b, mu (one per instance).
+    """
+
+    def __init__(self, grids, phys, tol=1e-10, m_min=8, m_max=64, m_step=4, max_substeps=64, stream=None):
+        self.lib = L.load()
+        n = len(grids)
+        if n < 1 or len(phys) != n:
+            raise ValueError("grids and phys must be non-empty lists of equal length")
+        ga = (L.EtdGrid * n)(*[_grid_struct(g.dim, g.n, g.lo, g.hi) for g in grids])
+        pa = (L.EtdPhysics * n)(*[L.EtdPhysics(float(p.get("beta", 1.0)), float(p.get("a", 1.0)),
+                                               float(p.get("b", 1.0)), float(p.get("mu", 0.0))) for p in phys])
+        op = L.EtdKrylovOpts(float(tol), int(m_min), int(m_max), int(m_step), int(max_substeps))
+        self.count = n
+        self.shapes = [tuple(reversed([int(x) for x in g.n[:g.dim]])) for g in grids]
+        self.handle = C.c_void_p()
+        s = stream if stream is not None else torch.cuda.current_stream()
+        L.check(self.lib.etd_batch_create(n, ga, pa, C.byref(op), C.c_void_p(s.cuda_stream), C.byref(self.handle)),
+                "etd_batch_create")
+        self._stream = s
+
+    def _ptrs(self, ts, name):
+        if len(ts) != self.count:
+            raise ValueError(f"{name}: expected {self.count} tensors")
+        for i, t in enumerate(ts):
+            if not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or not t.is_cuda:
+                raise TypeError(f"{name}[{i}]: expected a float64 CUDA tensor")
+            if tuple(t.shape) != self.shapes[i] or not t.is_contiguous():
+                raise ValueError(f"{name}[{i}]: expected a contiguous tensor of shape {self.shapes[i]}")
+        return (C.c_void_p * self.count)(*[_ptr(t) for t in ts])
+
+    def _sync_stream(self):
+        cur = torch.cuda.current_stream()
+        if cur.cuda_stream != self._stream.cuda_stream:
+            self._stream = cur
+            L.check(self.lib.etd_batch_set_stream(self.handle, C.c_void_p(cur.cuda_stream)), "etd_batch_set_stream")
+
+    def close(self):
+        if self.handle:
+            self.lib.etd_batch_destroy(self.handle)
+            self.handle = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_group_limit(self, max_blocks: int):
+        L.check(self.lib.etd_batch_set_group_limit(self.handle, int(max_blocks)), "etd_batch_set_group_limit")
+
+    def geometry_build(self, rhos):
+        arr = self._ptrs(rhos, "rho")
+        self._sync_stream()
+        L.check(self.lib.etd_batch_geometry_build(self.handle, arr), "etd_batch_geometry_build")
+
+    def step(self, scheme: str, h: float, us, rhos=None, reinit=False, stats=False):
+        code = {"etd1": L.ETD_SCHEME_ETD1, "etd2rk": L.ETD_SCHEME_ETD2RK}[scheme]
+        ua = self._ptrs(us, "u")
+        ra = self._ptrs(rhos, "rho") if rhos is not None else None
+        self._sync_stream()
+        st = (L.EtdStats * self.count)() if stats else None
+        L.check(self.lib.etd_batch_step(self.handle, code, float(h), ua, ra, int(bool(reinit)), st), "etd_batch_step")
+        return [x.as_dict() for x in st] if stats else None
+
+    def sync(self):
+        L.check(self.lib.etd_batch_sync(self.handle), "etd_batch_sync")
+
+    def stats(self, i: int):
+        st = L.EtdStats()
+        L.check(self.lib.etd_batch_stats(self.handle, int(i), C.byref(st)), "etd_batch_stats")
+        return st.as_dict()
+
+    def profile_enable(self, on: bool = True):
+        L.check(self.lib.etd_batch_profile_enable(self.handle, int(bool(on))), "etd_batch_profile_enable")
+
+    def profile_read(self, reset: bool = False):
+        pr = L.EtdProfile()
+        L.check(self.lib.etd_batch_profile_read(self.handle, C.byref(pr), int(bool(reset))), "etd_batch_profile_read")
+        return pr.as_dict()
+

@@ -33,6 +33,7 @@ struct etd_ctx {
   uint64_t* comp_bits = nullptr;
   uint64_t* irr_bits = nullptr;
   double* cdiag = nullptr;
+  int* nbr = nullptr;        // face-neighbour slots, NBR_STRIDE per slot
   int* counters = nullptr;   // [0] n_active, [1] status, [2..3] case counts
   // persistent kernel state
   double* ws = nullptr;
@@ -61,10 +62,28 @@ struct etd_ctx {
   } t_krylov, t_levelset, t_geometry;
 };
 
+struct etd_batch {
+  int count = 0;
+  int dim = 2;
+  hipStream_t stream = nullptr;
+  std::vector<etd_ctx*> inst;
+  int capacity = 1;           // co-resident blocks of the batched launch
+  int group_limit = 0;        // max blocks per instance (0: no limit)
+  int nchunks = 1;            // launches per step (instances per launch <= capacity)
+  KrylovDev* d_params = nullptr;
+  KrylovDev* h_params = nullptr;
+  int* d_blk = nullptr;       // block -> instance, capacity entries per chunk
+  int* h_blk = nullptr;
+  hipEvent_t staged = nullptr;
+  bool staged_pending = false;
+  bool profiling = false;
+  etd_ctx::Timer t_krylov, t_levelset, t_geometry;
+};
+
 namespace {
 
-hipError_t timer_begin(etd_ctx* c, etd_ctx::Timer& t) {
-  if (!c->profiling) return hipSuccess;
+hipError_t timer_begin(bool on, hipStream_t st, etd_ctx::Timer& t) {
+  if (!on) return hipSuccess;
   if (t.used == t.start.size()) {
     hipEvent_t a, b;
     hipError_t e = hipEventCreate(&a);
@@ -74,12 +93,12 @@ hipError_t timer_begin(etd_ctx* c, etd_ctx::Timer& t) {
     t.start.push_back(a);
     t.stop.push_back(b);
   }
-  return hipEventRecord(t.start[t.used], c->stream);
+  return hipEventRecord(t.start[t.used], st);
 }
 
-hipError_t timer_end(etd_ctx* c, etd_ctx::Timer& t) {
-  if (!c->profiling) return hipSuccess;
-  hipError_t e = hipEventRecord(t.stop[t.used], c->stream);
+hipError_t timer_end(bool on, hipStream_t st, etd_ctx::Timer& t) {
+  if (!on) return hipSuccess;
+  hipError_t e = hipEventRecord(t.stop[t.used], st);
   ++t.used;
   return e;
 }
@@ -112,7 +131,6 @@ int check_hip(hipError_t e) { return e == hipSuccess ? ETD_OK : ETD_ERR_HIP; }
     if (_e != hipSuccess) return ETD_ERR_HIP; \
   } while (0)
 
-int n_active_ptr_offset = 0;
 
 GeomDev geom_view(const etd_ctx* c) {
   GeomDev g{};
@@ -124,6 +142,7 @@ GeomDev geom_view(const etd_ctx* c) {
   g.comp_bits = c->comp_bits;
   g.irr_bits = c->irr_bits;
   g.cdiag = c->cdiag;
+  g.nbr = c->nbr;
   g.n_active = c->counters + 0;
   g.n_unknowns = c->counters + 4;
   g.coef = c->phys.beta / (c->box.dx * c->box.dx);
@@ -153,43 +172,27 @@ KrylovDev krylov_params(const etd_ctx* c, int mode) {
   return P;
 }
 
-// Grid of the persistent kernel: one block per active tile up to the number
-// of co-resident blocks; each block caches the metadata of its tiles in
-// dynamic LDS (tmax entries), which in turn bounds the blocks per CU.
-// ETDFB_GRID in the environment overrides the block count.
+// Grid of the persistent kernel: enough blocks for one loop trip over the
+// active tiles (KTILES tiles per block and trip), at most the number of
+// co-resident blocks.  ETDFB_GRID in the environment overrides the count.
 void choose_launch(etd_ctx* c) {
   const int nact = c->n_active_host > 0 ? c->n_active_host : 1;
-  int g = nact;
-  int tmax = 1;
-  for (int it = 0; it < 4; ++it) {
-    const int per_cu = krylov_max_blocks_per_cu(c->box.dim, tmax);
-    int gmax = per_cu * c->n_cu;
-    if (gmax > c->max_grid) gmax = c->max_grid;
-    if (gmax < 1) gmax = 1;
-    g = nact < gmax ? nact : gmax;
-    const int need = (nact + g - 1) / g;
-    const int nt = need > 256 ? 256 : need;
-    if (nt == tmax) break;
-    tmax = nt;
-  }
+  int g = (nact + KTILES - 1) / KTILES;
+  if (g > c->max_grid) g = c->max_grid;
   if (const char* env = getenv("ETDFB_GRID")) {
-    int v = atoi(env);
-    if (v >= 1 && v <= g) g = v;
-    const int need = (nact + g - 1) / g;
-    tmax = need > 256 ? 256 : need;
-    const int per_cu = krylov_max_blocks_per_cu(c->box.dim, tmax);
-    if (per_cu * c->n_cu < g) g = per_cu * c->n_cu;
+    const int v = atoi(env);
+    if (v >= 1 && v <= c->max_grid) g = v;
   }
-  c->grid_blocks = g;
-  c->tmax = tmax;
+  c->grid_blocks = g < 1 ? 1 : g;
+  c->tmax = 1;
 }
 
 int run_krylov(etd_ctx* c, const KrylovDev& P) {
   if (!c->have_geometry) return ETD_ERR_NO_GEOMETRY;
-  if (timer_begin(c, c->t_krylov) != hipSuccess) return ETD_ERR_HIP;
+  if (timer_begin(c->profiling, c->stream, c->t_krylov) != hipSuccess) return ETD_ERR_HIP;
   hipError_t e = launch_krylov(c->box.dim, P, c->grid_blocks, c->stream);
   if (e != hipSuccess) return ETD_ERR_HIP;
-  return check_hip(timer_end(c, c->t_krylov));
+  return check_hip(timer_end(c->profiling, c->stream, c->t_krylov));
 }
 
 int gather_to(etd_ctx* c, const double* box, int vec) {
@@ -232,9 +235,50 @@ int latched_status(etd_ctx* c) {
   return st;
 }
 
+// Geometry build (Section 2): classification, tile compaction, Case 1-3
+// coefficients and the face-neighbour table, then an asynchronous copy of
+// the counters to pinned memory.  geometry_finish() reads them after the
+// caller has synchronised the stream.
+int geometry_enqueue(etd_ctx* c, const double* rho) {
+  HIP_TRY(timer_begin(c->profiling, c->stream, c->t_geometry));
+  HIP_TRY(launch_fill_int(c->tile_flag, c->ntiles, 0, c->stream));
+  HIP_TRY(launch_fill_int(c->counters + 2, 3, 0, c->stream));
+  HIP_TRY(launch_classify(c->box, rho, c->mask, c->tile_flag, c->counters + 1, c->stream));
+  HIP_TRY(launch_scan_tiles(c->tile_flag, c->ntiles, c->tile_map, c->slot_tile, c->counters + 0, c->stream));
+  HIP_TRY(launch_tile_coeff(c->box, rho, c->mask, c->tile_map, c->comp_bits, c->irr_bits, c->cdiag,
+                            c->nbr, c->counters + 2, c->ntiles, c->stream));
+  HIP_TRY(timer_end(c->profiling, c->stream, c->t_geometry));
+  HIP_TRY(hipMemcpyAsync(c->h_counters, c->counters, 8 * sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  return ETD_OK;
+}
+
+int geometry_finish(etd_ctx* c) {
+  c->n_active_host = c->h_counters[0];
+  choose_launch(c);
+  c->have_geometry = true;
+  if (c->h_counters[1] == ST_DOMAIN) {
+    int zero = 0;
+    HIP_TRY(hipMemcpyAsync(c->counters + 1, &zero, sizeof(int), hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    return ETD_ERR_DOMAIN;
+  }
+  return ETD_OK;
+}
+
+LevelsetArgs levelset_args(const etd_ctx* c, double dt, int reinit) {
+  LevelsetArgs a{};
+  a.box = c->box;
+  a.mu = c->phys.mu;
+  a.dt = dt;
+  a.reinit = reinit;
+  a.mask = c->mask;
+  a.status = c->counters + 1;
+  return a;
+}
+
 void free_all(etd_ctx* c) {
   void* ptrs[] = {c->mask, c->tile_flag, c->tile_map, c->slot_tile, c->comp_bits, c->irr_bits, c->cdiag,
-                  c->counters, c->ws, c->part, c->flags, c->bar, c->st};
+                  c->nbr, c->counters, c->ws, c->part, c->flags, c->bar, c->st};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   levelset_free(c->ls);
@@ -322,6 +366,7 @@ int etd_ctx_create(const etd_grid* grid, const etd_physics* phys, const etd_kryl
   ok &= hipMalloc(&c->comp_bits, sizeof(uint64_t) * 4 * c->ntiles) == hipSuccess;
   ok &= hipMalloc(&c->irr_bits, sizeof(uint64_t) * 4 * c->ntiles) == hipSuccess;
   ok &= hipMalloc(&c->cdiag, sizeof(double) * c->ld) == hipSuccess;
+  ok &= hipMalloc(&c->nbr, sizeof(int) * NBR_STRIDE * (size_t)c->ntiles) == hipSuccess;
   ok &= hipMalloc(&c->counters, sizeof(int) * 8) == hipSuccess;
   ok &= hipMalloc(&c->ws, sizeof(double) * c->ld * NVEC) == hipSuccess;
   ok &= hipMalloc(&c->part, sizeof(double) * 2 * (size_t)c->max_grid * PART_STRIDE) == hipSuccess;
@@ -378,26 +423,10 @@ int etd_ctx_set_beta(etd_ctx* c, double beta) {
 
 int etd_geometry_build(etd_ctx* c, const double* rho) {
   if (!c || !rho) return ETD_ERR_INVALID;
-  HIP_TRY(timer_begin(c, c->t_geometry));
-  HIP_TRY(launch_fill_int(c->tile_flag, c->ntiles, 0, c->stream));
-  HIP_TRY(launch_fill_int(c->counters + 2, 3, 0, c->stream));
-  HIP_TRY(launch_classify(c->box, rho, c->mask, c->tile_flag, c->counters + 1, c->stream));
-  HIP_TRY(launch_scan_tiles(c->tile_flag, c->ntiles, c->tile_map, c->slot_tile, c->counters + 0, c->stream));
-  HIP_TRY(launch_tile_coeff(c->box, rho, c->mask, c->tile_map, c->comp_bits, c->irr_bits, c->cdiag,
-                            c->counters + 2, c->ntiles, c->stream));
-  HIP_TRY(timer_end(c, c->t_geometry));
-  HIP_TRY(hipMemcpyAsync(c->h_counters, c->counters, 8 * sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  int r = geometry_enqueue(c, rho);
+  if (r) return r;
   HIP_TRY(hipStreamSynchronize(c->stream));
-  c->n_active_host = c->h_counters[0];
-  choose_launch(c);
-  c->have_geometry = true;
-  if (c->h_counters[1] == ST_DOMAIN) {
-    int zero = 0;
-    HIP_TRY(hipMemcpyAsync(c->counters + 1, &zero, sizeof(int), hipMemcpyHostToDevice, c->stream));
-    HIP_TRY(hipStreamSynchronize(c->stream));
-    return ETD_ERR_DOMAIN;
-  }
-  return ETD_OK;
+  return geometry_finish(c);
 }
 
 int etd_operator_apply(etd_ctx* c, const double* v, double* out) {
@@ -444,16 +473,10 @@ int levelset_advance(etd_ctx* c, double* rho, double* u, double dt, int32_t rein
     int r = etd_geometry_build(c, rho);
     if (r) return r;
   }
-  LevelsetArgs a{};
-  a.box = c->box;
-  a.mu = c->phys.mu;
-  a.dt = dt;
-  a.reinit = reinit;
-  a.mask = c->mask;
-  a.status = c->counters + 1;
-  HIP_TRY(timer_begin(c, c->t_levelset));
+  const LevelsetArgs a = levelset_args(c, dt, reinit);
+  HIP_TRY(timer_begin(c->profiling, c->stream, c->t_levelset));
   HIP_TRY(levelset_run(a, c->ls, rho, u, c->stream));
-  HIP_TRY(timer_end(c, c->t_levelset));
+  HIP_TRY(timer_end(c->profiling, c->stream, c->t_levelset));
   return etd_geometry_build(c, rho);
 }
 
@@ -521,6 +544,279 @@ int etd_ctx_profile_read(etd_ctx* c, etd_profile* out, int32_t reset) {
     const double zero = 0.0;
     HIP_TRY(hipMemcpyAsync(&c->st->alg_bytes_total, &zero, sizeof(double), hipMemcpyHostToDevice, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
+  }
+  return ETD_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ batch
+
+namespace {
+
+void batch_free(etd_batch* B) {
+  for (etd_ctx* c : B->inst)
+    if (c) etd_ctx_destroy(c);
+  B->inst.clear();
+  if (B->d_params) (void)hipFree(B->d_params);
+  if (B->d_blk) (void)hipFree(B->d_blk);
+  if (B->h_params) (void)hipHostFree(B->h_params);
+  if (B->h_blk) (void)hipHostFree(B->h_blk);
+  if (B->staged) (void)hipEventDestroy(B->staged);
+  timer_free(B->t_krylov);
+  timer_free(B->t_levelset);
+  timer_free(B->t_geometry);
+}
+
+// One batched launch per chunk of at most `capacity` instances.  Every
+// instance gets one block; the remaining co-resident blocks go to the
+// instances in proportion to the blocks they could use (one loop trip over
+// their active tiles), capped by group_limit.  The launch is cooperative
+// when some instance has more than one block.
+int batch_run_krylov(etd_batch* B, int mode, double h) {
+  if (B->staged_pending) {
+    HIP_TRY(hipEventSynchronize(B->staged));
+    B->staged_pending = false;
+  }
+  HIP_TRY(timer_begin(B->profiling, B->stream, B->t_krylov));
+  const int C = B->capacity;
+  for (int ch = 0; ch < B->nchunks; ++ch) {
+    const int i0 = ch * C;
+    const int i1 = (i0 + C < B->count) ? i0 + C : B->count;
+    const int n = i1 - i0;
+    std::vector<int> want(n), g(n, 1);
+    long total_want = 0;
+    for (int i = 0; i < n; ++i) {
+      const int nact = B->inst[i0 + i]->n_active_host > 0 ? B->inst[i0 + i]->n_active_host : 1;
+      int w = (nact + KTILES - 1) / KTILES;
+      if (B->group_limit > 0 && w > B->group_limit) w = B->group_limit;
+      want[i] = w;
+      total_want += w - 1;
+    }
+    const long budget = C - n;
+    for (int i = 0; i < n; ++i) {
+      if (total_want <= budget) g[i] = want[i];
+      else g[i] = 1 + (int)((budget * (long)(want[i] - 1)) / (total_want > 0 ? total_want : 1));
+    }
+    int blocks = 0;
+    bool coop = false;
+    int* blk = B->h_blk + (size_t)ch * C;
+    for (int i = 0; i < n; ++i) {
+      KrylovDev P = krylov_params(B->inst[i0 + i], mode);
+      P.h = h;
+      P.g_first = blocks;
+      P.g_size = g[i];
+      B->h_params[i0 + i] = P;
+      for (int k = 0; k < g[i]; ++k) blk[blocks + k] = i;
+      blocks += g[i];
+      coop |= g[i] > 1;
+    }
+    HIP_TRY(hipMemcpyAsync(B->d_params + i0, B->h_params + i0, sizeof(KrylovDev) * n, hipMemcpyHostToDevice,
+                           B->stream));
+    HIP_TRY(hipMemcpyAsync(B->d_blk + (size_t)ch * C, blk, sizeof(int) * blocks, hipMemcpyHostToDevice,
+                           B->stream));
+    HIP_TRY(launch_krylov_group(B->dim, B->d_params + i0, n, B->d_blk + (size_t)ch * C, blocks, coop,
+                                B->stream));
+  }
+  HIP_TRY(hipEventRecord(B->staged, B->stream));
+  B->staged_pending = true;
+  HIP_TRY(timer_end(B->profiling, B->stream, B->t_krylov));
+  return ETD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int etd_batch_create(int32_t count, const etd_grid* grids, const etd_physics* phys,
+                     const etd_krylov_opts* opts, void* hip_stream, etd_batch** out) {
+  if (!out) return ETD_ERR_INVALID;
+  *out = nullptr;
+  if (count < 1 || !grids || !phys) return ETD_ERR_INVALID;
+  for (int i = 1; i < count; ++i)
+    if (grids[i].dim != grids[0].dim) return ETD_ERR_INVALID;
+  etd_batch* B = new etd_batch();
+  B->count = count;
+  B->dim = grids[0].dim;
+  B->stream = (hipStream_t)hip_stream;
+  B->inst.assign(count, nullptr);
+  for (int i = 0; i < count; ++i) {
+    const int r = etd_ctx_create(&grids[i], &phys[i], opts, hip_stream, &B->inst[i]);
+    if (r) {
+      batch_free(B);
+      delete B;
+      return r;
+    }
+  }
+  B->capacity = B->inst[0]->max_grid;
+  B->nchunks = (count + B->capacity - 1) / B->capacity;
+  bool ok = true;
+  ok &= hipMalloc(&B->d_params, sizeof(KrylovDev) * count) == hipSuccess;
+  ok &= hipHostMalloc(&B->h_params, sizeof(KrylovDev) * count) == hipSuccess;
+  ok &= hipMalloc(&B->d_blk, sizeof(int) * (size_t)B->capacity * B->nchunks) == hipSuccess;
+  ok &= hipHostMalloc(&B->h_blk, sizeof(int) * (size_t)B->capacity * B->nchunks) == hipSuccess;
+  ok &= hipEventCreate(&B->staged) == hipSuccess;
+  if (!ok) {
+    batch_free(B);
+    delete B;
+    return ETD_ERR_HIP;
+  }
+  *out = B;
+  return ETD_OK;
+}
+
+int etd_batch_destroy(etd_batch* B) {
+  if (!B) return ETD_ERR_INVALID;
+  (void)hipStreamSynchronize(B->stream);
+  batch_free(B);
+  delete B;
+  return ETD_OK;
+}
+
+int etd_batch_set_stream(etd_batch* B, void* s) {
+  if (!B) return ETD_ERR_INVALID;
+  B->stream = (hipStream_t)s;
+  for (etd_ctx* c : B->inst) c->stream = (hipStream_t)s;
+  return ETD_OK;
+}
+
+int etd_batch_set_group_limit(etd_batch* B, int32_t max_blocks) {
+  if (!B || max_blocks < 0) return ETD_ERR_INVALID;
+  B->group_limit = max_blocks;
+  return ETD_OK;
+}
+
+int etd_batch_geometry_build(etd_batch* B, const double* const* rho) {
+  if (!B || !rho) return ETD_ERR_INVALID;
+  for (int i = 0; i < B->count; ++i)
+    if (!rho[i]) return ETD_ERR_INVALID;
+  HIP_TRY(timer_begin(B->profiling, B->stream, B->t_geometry));
+  for (int i = 0; i < B->count; ++i) {
+    const int r = geometry_enqueue(B->inst[i], rho[i]);
+    if (r) return r;
+  }
+  HIP_TRY(timer_end(B->profiling, B->stream, B->t_geometry));
+  HIP_TRY(hipStreamSynchronize(B->stream));
+  int first = ETD_OK;
+  for (int i = 0; i < B->count; ++i) {
+    const int r = geometry_finish(B->inst[i]);
+    if (r && !first) first = r;
+  }
+  return first;
+}
+
+int etd_batch_step(etd_batch* B, int32_t scheme, double h, double* const* u, double* const* rho,
+                   int32_t reinit, etd_stats* stats) {
+  if (!B || !u || !(h >= 0.0) || !isfinite(h)) return ETD_ERR_INVALID;
+  if (scheme != ETD_SCHEME_ETD1 && scheme != ETD_SCHEME_ETD2RK) return ETD_ERR_INVALID;
+  for (int i = 0; i < B->count; ++i) {
+    if (!u[i]) return ETD_ERR_INVALID;
+    if (rho && !rho[i]) return ETD_ERR_INVALID;
+  }
+  if (rho) {
+    bool all = true;
+    for (etd_ctx* c : B->inst) all &= c->have_geometry;
+    if (!all) {
+      const int r = etd_batch_geometry_build(B, rho);
+      if (r) return r;
+    }
+    // level-set sweeps of every instance around one synchronisation
+    HIP_TRY(timer_begin(B->profiling, B->stream, B->t_levelset));
+    for (int i = 0; i < B->count; ++i) {
+      etd_ctx* c = B->inst[i];
+      HIP_TRY(levelset_begin(levelset_args(c, h, reinit), c->ls, rho[i], u[i], B->stream));
+    }
+    HIP_TRY(hipStreamSynchronize(B->stream));
+    for (int i = 0; i < B->count; ++i) {
+      etd_ctx* c = B->inst[i];
+      HIP_TRY(levelset_end(levelset_args(c, h, reinit), c->ls, rho[i], u[i], B->stream));
+    }
+    HIP_TRY(timer_end(B->profiling, B->stream, B->t_levelset));
+    const int r = etd_batch_geometry_build(B, rho);
+    if (r) return r;
+  }
+  for (etd_ctx* c : B->inst)
+    if (!c->have_geometry) return ETD_ERR_NO_GEOMETRY;
+  for (int i = 0; i < B->count; ++i) {
+    const int r = gather_to(B->inst[i], u[i], V_X0);
+    if (r) return r;
+  }
+  int r = batch_run_krylov(B, scheme == ETD_SCHEME_ETD1 ? JOB_ETD1 : JOB_ETD2RK, h);
+  if (r) return r;
+  for (int i = 0; i < B->count; ++i) {
+    r = scatter_from(B->inst[i], V_U, u[i]);
+    if (r) return r;
+  }
+  if (stats) {
+    for (int i = 0; i < B->count; ++i) {
+      r = fill_stats(B->inst[i], &stats[i]);
+      if (r) return r;
+    }
+    return etd_batch_sync(B);
+  }
+  return ETD_OK;
+}
+
+int etd_batch_sync(etd_batch* B) {
+  if (!B) return ETD_ERR_INVALID;
+  for (etd_ctx* c : B->inst)
+    HIP_TRY(hipMemcpyAsync(c->h_counters, c->counters, 4 * sizeof(int), hipMemcpyDeviceToHost, B->stream));
+  HIP_TRY(hipStreamSynchronize(B->stream));
+  int first = ETD_OK;
+  for (etd_ctx* c : B->inst) {
+    const int st = c->h_counters[1];
+    if (st != 0) {
+      if (!first) first = st;
+      int zero = 0;
+      HIP_TRY(hipMemcpyAsync(c->counters + 1, &zero, sizeof(int), hipMemcpyHostToDevice, B->stream));
+    }
+  }
+  HIP_TRY(hipStreamSynchronize(B->stream));
+  return first;
+}
+
+int etd_batch_stats(etd_batch* B, int32_t i, etd_stats* s) {
+  if (!B || !s || i < 0 || i >= B->count) return ETD_ERR_INVALID;
+  return fill_stats(B->inst[i], s);
+}
+
+int etd_batch_profile_enable(etd_batch* B, int32_t enable) {
+  if (!B) return ETD_ERR_INVALID;
+  B->profiling = enable != 0;
+  return ETD_OK;
+}
+
+int etd_batch_profile_read(etd_batch* B, etd_profile* out, int32_t reset) {
+  if (!B || !out) return ETD_ERR_INVALID;
+  for (etd_ctx* c : B->inst) {
+    HIP_TRY(hipMemcpyAsync(c->h_state, c->st, sizeof(KrylovStateDev), hipMemcpyDeviceToHost, B->stream));
+    HIP_TRY(hipMemcpyAsync(c->h_counters, c->counters, 8 * sizeof(int), hipMemcpyDeviceToHost, B->stream));
+  }
+  HIP_TRY(hipStreamSynchronize(B->stream));
+  HIP_TRY(timer_collect(B->t_krylov));
+  HIP_TRY(timer_collect(B->t_levelset));
+  HIP_TRY(timer_collect(B->t_geometry));
+  out->krylov_ms = B->t_krylov.ms;
+  out->levelset_ms = B->t_levelset.ms;
+  out->geometry_ms = B->t_geometry.ms;
+  out->krylov_launches = B->t_krylov.count;
+  out->levelset_calls = B->t_levelset.count;
+  out->geometry_calls = B->t_geometry.count;
+  double bytes = 0.0;
+  long unknowns = 0;
+  for (etd_ctx* c : B->inst) {
+    bytes += c->h_state->alg_bytes_total;
+    unknowns += c->h_counters[4];
+  }
+  out->alg_bytes = bytes;
+  out->n_unknowns = (int32_t)unknowns;
+  if (reset) {
+    B->t_krylov.ms = B->t_levelset.ms = B->t_geometry.ms = 0.0;
+    B->t_krylov.count = B->t_levelset.count = B->t_geometry.count = 0;
+    const double zero = 0.0;
+    for (etd_ctx* c : B->inst)
+      HIP_TRY(hipMemcpyAsync(&c->st->alg_bytes_total, &zero, sizeof(double), hipMemcpyHostToDevice, B->stream));
+    HIP_TRY(hipStreamSynchronize(B->stream));
   }
   return ETD_OK;
 }

@@ -19,6 +19,21 @@
 
 namespace etdfb {
 
+// Pointers typed in the global address space: device buffers accessed
+// through them compile to global (not flat) loads and stores.
+#if defined(__HIP_DEVICE_COMPILE__)
+template <class T>
+using gptr = __attribute__((address_space(1))) T*;
+#else
+template <class T>
+using gptr = T*;   // host pass: address spaces play no role
+#endif
+
+template <class T>
+__device__ __forceinline__ gptr<T> glb(T* p) {
+  return (gptr<T>)p;
+}
+
 template <int DIM> struct TileShape;
 template <> struct TileShape<2> { static constexpr int X = 32, Y = 8, Z = 1; };
 template <> struct TileShape<3> { static constexpr int X = 16, Y = 4, Z = 4; };
@@ -27,8 +42,8 @@ __device__ __forceinline__ bool bit_of(const uint64_t* bits, int slot, int l) {
   return (bits[(size_t)slot * 4 + (l >> 6)] >> (l & 63)) & 1ull;
 }
 
-// Face-neighbour slots of a tile (order -x,+x,-y,+y,-z,+z); -1 if outside the
-// box or inactive.  Called by threads 0 .. 2*DIM-1.
+// Face-neighbour slot of a tile in direction dir (order -x,+x,-y,+y,-z,+z);
+// -1 if outside the box or inactive.
 template <int DIM>
 __device__ __forceinline__ int face_neighbour_slot(const GeomDev& g, int slot, int dir) {
   int t = g.slot_tile[slot];
@@ -40,27 +55,28 @@ __device__ __forceinline__ int face_neighbour_slot(const GeomDev& g, int slot, i
   return g.tile_map[((size_t)c[2] * g.nty + c[1]) * g.ntx + c[0]];
 }
 
-// Sum of the 2*DIM face-neighbour values of local point l of `slot`.
-template <int DIM>
-__device__ __forceinline__ double neighbour_sum(const double* __restrict__ v, int slot, int l,
-                                                const int* nb) {
+// Sum of the 2*DIM face-neighbour values of local point l of `slot`; val(i)
+// gives the value at vector index i, nb[] the neighbour slots of the tile
+// (NBR_STRIDE entries per slot).  Summation order -x,+x,-y,+y,-z,+z.
+template <int DIM, class Val>
+__device__ __forceinline__ double neighbour_sum(int slot, int l, gptr<const int> nb, Val&& val) {
   constexpr int X = TileShape<DIM>::X, Y = TileShape<DIM>::Y, Z = TileShape<DIM>::Z;
   const int lx = l % X, ly = (l / X) % Y, lz = l / (X * Y);
-  const double* base = v + (size_t)slot * TILE_PTS;
+  const size_t base = (size_t)slot * TILE_PTS;
   double s = 0.0;
-  if (lx > 0) s += base[l - 1];
-  else if (nb[0] >= 0) s += v[(size_t)nb[0] * TILE_PTS + l + (X - 1)];
-  if (lx < X - 1) s += base[l + 1];
-  else if (nb[1] >= 0) s += v[(size_t)nb[1] * TILE_PTS + l - (X - 1)];
-  if (ly > 0) s += base[l - X];
-  else if (nb[2] >= 0) s += v[(size_t)nb[2] * TILE_PTS + l + X * (Y - 1)];
-  if (ly < Y - 1) s += base[l + X];
-  else if (nb[3] >= 0) s += v[(size_t)nb[3] * TILE_PTS + l - X * (Y - 1)];
+  if (lx > 0) s += val(base + l - 1);
+  else if (nb[0] >= 0) s += val((size_t)nb[0] * TILE_PTS + l + (X - 1));
+  if (lx < X - 1) s += val(base + l + 1);
+  else if (nb[1] >= 0) s += val((size_t)nb[1] * TILE_PTS + l - (X - 1));
+  if (ly > 0) s += val(base + l - X);
+  else if (nb[2] >= 0) s += val((size_t)nb[2] * TILE_PTS + l + X * (Y - 1));
+  if (ly < Y - 1) s += val(base + l + X);
+  else if (nb[3] >= 0) s += val((size_t)nb[3] * TILE_PTS + l - X * (Y - 1));
   if (DIM == 3) {
-    if (lz > 0) s += base[l - X * Y];
-    else if (nb[4] >= 0) s += v[(size_t)nb[4] * TILE_PTS + l + X * Y * (Z - 1)];
-    if (lz < Z - 1) s += base[l + X * Y];
-    else if (nb[5] >= 0) s += v[(size_t)nb[5] * TILE_PTS + l - X * Y * (Z - 1)];
+    if (lz > 0) s += val(base + l - X * Y);
+    else if (nb[4] >= 0) s += val((size_t)nb[4] * TILE_PTS + l + X * Y * (Z - 1));
+    if (lz < Z - 1) s += val(base + l + X * Y);
+    else if (nb[5] >= 0) s += val((size_t)nb[5] * TILE_PTS + l - X * Y * (Z - 1));
   }
   return s;
 }
@@ -68,12 +84,13 @@ __device__ __forceinline__ double neighbour_sum(const double* __restrict__ v, in
 // (A v) at local point l of `slot` (0 at non-computational points):
 // beta/h^2 * (sum of neighbours - c_p v_p), c_p = 2*DIM for regular points.
 template <int DIM>
-__device__ __forceinline__ double apply_A(const GeomDev& g, const double* __restrict__ v, int slot,
-                                          int l, const int* nb, bool comp, bool irr) {
+__device__ __forceinline__ double apply_A(const GeomDev& g, gptr<const double> v, int slot,
+                                          int l, gptr<const int> nb, bool comp, bool irr) {
   if (!comp) return 0.0;
-  const double vp = v[(size_t)slot * TILE_PTS + l];
-  const double c = irr ? g.cdiag[(size_t)slot * TILE_PTS + l] : (double)(2 * DIM);
-  return g.coef * (neighbour_sum<DIM>(v, slot, l, nb) - c * vp);
+  const size_t i = (size_t)slot * TILE_PTS + l;
+  const double vp = v[i];
+  const double c = irr ? glb(g.cdiag)[i] : (double)(2 * DIM);
+  return g.coef * (neighbour_sum<DIM>(slot, l, nb, [&](size_t j) { return v[j]; }) - c * vp);
 }
 
 // Bound on the polls of a grid synchronisation before it gives up (and
@@ -88,11 +105,12 @@ __device__ __forceinline__ double wave_sum_lane0(double v) {
   return v;
 }
 
-// Block (256 threads = 4 waves) sum of NR values; result in out[] for all
-// threads.  `scratch` holds at least 4*NR doubles.
+// Block sum of NR values over the NW = blockDim.x / 64 waves (fixed order);
+// result in v[] for all threads.  `scratch` holds at least NW*NR doubles.
 template <int NR>
 __device__ __forceinline__ void block_sum(double (&v)[NR], double* scratch) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int nw = blockDim.x >> 6;
 #pragma unroll
   for (int k = 0; k < NR; ++k) {
     double s = wave_sum_lane0(v[k]);
@@ -100,8 +118,11 @@ __device__ __forceinline__ void block_sum(double (&v)[NR], double* scratch) {
   }
   __syncthreads();
 #pragma unroll
-  for (int k = 0; k < NR; ++k)
-    v[k] = ((scratch[k] + scratch[NR + k]) + scratch[2 * NR + k]) + scratch[3 * NR + k];
+  for (int k = 0; k < NR; ++k) {
+    double t = scratch[k];
+    for (int q = 1; q < nw; ++q) t += scratch[q * NR + k];
+    v[k] = t;
+  }
   __syncthreads();
 }
 

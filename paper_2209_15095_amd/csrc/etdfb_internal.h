@@ -11,7 +11,9 @@ constexpr int PART_STRIDE = 8;      // doubles per block in the partial-sum buff
 constexpr int MMAX_LIMIT = 64;      // largest Krylov dimension
 constexpr int PMAX = 3;             // largest phi index in one combination
 constexpr int EXPM_NMAX = MMAX_LIMIT + PMAX + 2;   // augmented matrix bound
-constexpr int KBLOCK = 256;         // threads per block of the persistent kernels
+constexpr int KBLOCK = 1024;        // threads per block of the persistent kernels
+constexpr int NBR_STRIDE = 8;       // ints per slot in the face-neighbour table
+constexpr int KTILES = KBLOCK / TILE_PTS;  // tiles a block works on per loop trip
 constexpr double NOT_COMP = -1e300; // coefficient sentinel of non-computational points
 
 // Work vectors of the persistent kernel (indices into the workspace).
@@ -27,7 +29,9 @@ enum VecIndex {
   V_X0 = 8,    // ETD: U_n
   V_F = 9,     // ETD: scratch
   V_T = 10,    // scratch
-  V_Q0 = 11,   // Krylov basis q_0 .. q_MMAX
+  V_Z0 = 11,   // A q_k (two buffers, alternating)
+  V_Z1 = 12,
+  V_Q0 = 13,   // Krylov basis q_0 .. q_MMAX
   NVEC = V_Q0 + MMAX_LIMIT + 1
 };
 
@@ -48,6 +52,7 @@ struct GeomDev {
   const uint64_t* comp_bits;  // [cap*4]
   const uint64_t* irr_bits;   // [cap*4]
   const double* cdiag;        // [cap*256] diagonal weight sum c_p; NOT_COMP off the unknowns
+  const int* nbr;             // [cap*NBR_STRIDE] face-neighbour slots (-x,+x,-y,+y,-z,+z), -1 none
   const int* n_active;        // device scalar: number of active tiles
   const int* n_unknowns;      // device scalar: number of computational points
   double coef;                // beta / h^2
@@ -90,6 +95,7 @@ struct KrylovDev {
   int p;
   double t;                   // JOB_PHI: time t of phi_k(t A)
   double h;                   // ETD step
+  int g_first, g_size;        // blocks of this instance in the launch grid
 };
 
 // Status codes (mirror include/etdfb.h).

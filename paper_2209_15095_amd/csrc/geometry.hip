@@ -190,12 +190,25 @@ __global__ __launch_bounds__(256) void tile_coeff_kernel(BoxDev b, const double*
                                                          uint64_t* __restrict__ comp_bits,
                                                          uint64_t* __restrict__ irr_bits,
                                                          double* __restrict__ cdiag,
+                                                         int* __restrict__ nbr,
                                                          int* __restrict__ counts) {
   const int t = blockIdx.x;
   const int slot = tile_map[t];
   if (slot < 0) return;
   const int tcx = t % b.ntx, tcy = (t / b.ntx) % b.nty, tcz = t / (b.ntx * b.nty);
   const int l = threadIdx.x;
+  if (l < NBR_STRIDE) {
+    // face-neighbour slots of the tile (-x,+x,-y,+y,-z,+z), -1 outside / inactive
+    int s = -1;
+    if (l < 2 * b.dim) {
+      int cc[3] = {tcx, tcy, tcz};
+      const int nn[3] = {b.ntx, b.nty, b.ntz};
+      const int d = l >> 1;
+      cc[d] += (l & 1) ? 1 : -1;
+      if (cc[d] >= 0 && cc[d] < nn[d]) s = tile_map[((size_t)cc[2] * b.nty + cc[1]) * b.ntx + cc[0]];
+    }
+    nbr[(size_t)slot * NBR_STRIDE + l] = s;
+  }
   const int lx = l % b.tx, ly = (l / b.tx) % b.ty, lz = l / (b.tx * b.ty);
   const int i = tcx * b.tx + lx, j = tcy * b.ty + ly, k = tcz * b.tz + lz;
   bool comp = false, irr = false;
@@ -329,9 +342,9 @@ hipError_t launch_scan_tiles(const int* tile_flag, int ntiles, int* tile_map, in
 
 hipError_t launch_tile_coeff(const BoxHost& b, const double* rho, const uint8_t* mask,
                              const int* tile_map, uint64_t* comp_bits, uint64_t* irr_bits,
-                             double* cdiag, int* counts, int ntiles, hipStream_t s) {
+                             double* cdiag, int* nbr, int* counts, int ntiles, hipStream_t s) {
   hipLaunchKernelGGL(tile_coeff_kernel, dim3(ntiles), dim3(256), 0, s, to_dev(b), rho, mask, tile_map,
-                     comp_bits, irr_bits, cdiag, counts);
+                     comp_bits, irr_bits, cdiag, nbr, counts);
   return hipGetLastError();
 }
 

@@ -12,22 +12,27 @@
 //   u(t_j + tau) = sum_{k<p} tau^k/k! W_k + tau^p phi_p(tau A) W_p, since
 //   phi_k(z) = 1/k! + z phi_{k+1}(z).
 // * phi_p(tau A) W_p ~ |W_p| V_m phi_p(tau T_m) e_1 from m Lanczos steps
-//   started at W_p (basis kept unnormalised with its norms).
+//   started at W_p (basis kept unnormalised with its norms n_k).
+// * One grid synchronisation per Lanczos step: pass k forms
+//   q_k = (z_{k-1} - alpha_{k-1} q_{k-1}) / n_{k-1} - (n_{k-1}/n_{k-2}) q_{k-2}
+//   pointwise (z_{k-1} = A q_{k-1} from the previous pass), also at the face
+//   neighbours of each point, so z_k = A q_k follows in the same pass; its
+//   reduction yields both |q_k|^2 and <z_k, q_k>.
 // * phi_p(tau T) e_1 and phi_{p+1}(tau T) e_1 are columns of the exponential
 //   of the (m+p+1)^2 augmented matrix [[tau T, e_1, 0], [0, 0, I], [0, 0, 0]],
 //   computed in LDS by scaling, Taylor-Horner (X is sparse, so Horner is
 //   O(N^2) per term) and squaring.
-// * Error estimate |W_p| beta_m tau^{p+1} |e_m^T phi_{p+1}(tau T) e_1|
+// * Error estimate |W_p| n_m tau^{p+1} |e_m^T phi_{p+1}(tau T) e_1|
 //   (generalised residual); accept when it is below
-//   tol * tau/t * max(|u(t_j)|, tau^p |W_p| / p!).  Otherwise grow m in steps
-//   of m_step up to m_max, then shrink tau.
+//   tol * tau/t * max(|u(t_j)|, tau^p |W_p| / p!) and below
+//   tol * tau/t * |u(t_j + tau)|.  Otherwise grow m in steps of m_step up to
+//   m_max, then shrink tau.
 //
 // Everything after the launch is decided on the device: every block reduces
 // the same per-block partials in the same order, so all blocks hold
 // bit-identical scalars and take identical branches (no host round trip, no
-// broadcast).  Blocks synchronise with the grid barrier of device_common.h.
-// FP64 throughout; no matrix cores (nothing here is a dense contraction
-// except the tiny in-LDS exponential).
+// broadcast).  FP64 throughout; no matrix cores (nothing here is a dense
+// contraction except the tiny in-LDS exponential).
 #include <math.h>
 
 #include "device_common.h"
@@ -37,19 +42,23 @@ namespace etdfb {
 
 struct Ctl {
   // Lanczos data of the current substep (written by thread 0, read by all)
-  double alpha[MMAX_LIMIT + 1];
+  double alpha[MMAX_LIMIT + 2];
   double nrm[MMAX_LIMIT + 2];
   double coef[MMAX_LIMIT + 1];
   double red[8];
-  double scratch[4 * 8];
-  int nb[6];
+  double scratch[(KBLOCK / 64) * 4];
+  // adaptive state per p carried across calls (thread 0 writes)
+  double tau_frac[PMAX + 1];
+  int m_guess[PMAX + 1];
   int abort;
 };
 
-// BATCH: every block runs its own instance (its own KrylovDev) and
-// synchronises only within the block; otherwise the whole grid works on one
-// instance and synchronises with the flag barrier below.
-template <int DIM, bool BATCH>
+// An instance is worked on by a group of G co-resident blocks (lb = this
+// block's index in the group).  G == 1: the block synchronises only with
+// itself; G > 1: the group synchronises with the flag barrier below, on the
+// instance's own flags and partial sums, so groups of different instances
+// never wait for each other.
+template <int DIM>
 struct Engine {
   const KrylovDev& P;
   Ctl& c;
@@ -57,9 +66,8 @@ struct Engine {
   double* S;   // LDS EXPM_NMAX^2
   int nact;
   int pass_no;
+  int lb, G;
   // control state: every thread of every block holds identical copies
-  int m_guess[PMAX + 1];
-  double tau_frac[PMAX + 1];
   int substeps, rejected, matvecs, m_last, expms;
   double err_est, t_done;
   bool failed;
@@ -69,10 +77,10 @@ struct Engine {
   // masks and tile padding are not counted).
   double bpu;
 
-  __device__ double* V(int i) const { return P.ws + (size_t)i * P.ld; }
+  __device__ gptr<double> V(int i) const { return glb(P.ws) + (size_t)i * P.ld; }
 
   __device__ void fail(int code) {
-    if (threadIdx.x == 0 && (BATCH || blockIdx.x == 0)) atomicCAS(P.status, 0, code);
+    if (threadIdx.x == 0 && lb == 0) atomicCAS(P.status, 0, code);
     failed = true;
   }
 
@@ -85,19 +93,18 @@ struct Engine {
   // abort flag goes up and every block leaves.
   template <int NR>
   __device__ bool grid_sync(const double (&acc)[NR], double (&out)[NR]) {
-    const int G = gridDim.x;
     ++pass_no;
     const unsigned gen = (unsigned)pass_no;
-    double* part = P.part + (size_t)(gen & 1u) * G * PART_STRIDE;
+    gptr<double> part = glb(P.part) + (size_t)(gen & 1u) * G * PART_STRIDE;
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     if (threadIdx.x < 64) {
       const int lane = threadIdx.x;
       if (lane == 0) {
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        for (int k = 0; k < NR; ++k) part[(size_t)blockIdx.x * PART_STRIDE + k] = acc[k];
+        for (int k = 0; k < NR; ++k) part[(size_t)lb * PART_STRIDE + k] = acc[k];
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        __hip_atomic_store(&P.flags[blockIdx.x], gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&P.flags[lb], gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }
       long spins = 0;
       int ab = 0;
@@ -140,7 +147,7 @@ struct Engine {
   template <int NR>
   __device__ bool finish(double (&acc)[NR], double (&out)[NR]) {
     block_sum<NR>(acc, c.scratch);
-    if (BATCH) {
+    if (G == 1) {
       for (int k = 0; k < NR; ++k) out[k] = acc[k];
     } else if (!grid_sync<NR>(acc, out)) {
       if (threadIdx.x == 0) atomicCAS(P.status, 0, ST_BARRIER);
@@ -156,7 +163,7 @@ struct Engine {
   }
 
   __device__ bool barrier() {
-    if (BATCH) {
+    if (G == 1) {
       __syncthreads();
       return true;
     }
@@ -169,19 +176,20 @@ struct Engine {
     return true;
   }
 
-  // Loop over the active tiles assigned to this block; f(slot, l, comp, irr).
+  // Loop over the active tiles of this block (KTILES tiles per trip, one per
+  // 256 threads); f(slot, l, comp, irr, nb) with nb the tile's face-neighbour
+  // slots.  No block synchronisation inside: nothing is shared through LDS.
   template <class F>
   __device__ void tiles(F&& f) {
-    const int s0 = BATCH ? 0 : (int)blockIdx.x;
-    const int ds = BATCH ? 1 : (int)gridDim.x;
-    for (int slot = s0; slot < nact; slot += ds) {
-      if (threadIdx.x < 2 * DIM) c.nb[threadIdx.x] = face_neighbour_slot<DIM>(P.g, slot, threadIdx.x);
-      __syncthreads();
-      const int l = threadIdx.x;
-      const bool comp = bit_of(P.g.comp_bits, slot, l);
-      const bool irr = comp && bit_of(P.g.irr_bits, slot, l);
-      f(slot, l, comp, irr);
-      __syncthreads();
+    const int sub = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / TILE_PTS));
+    const int l = (int)(threadIdx.x % TILE_PTS);
+    for (int slot = lb * KTILES + sub; slot < nact; slot += G * KTILES) {
+      const int w = l >> 6;
+      const uint64_t cw = glb(P.g.comp_bits)[(size_t)slot * 4 + w];
+      const uint64_t iw = glb(P.g.irr_bits)[(size_t)slot * 4 + w];
+      const bool comp = (cw >> (l & 63)) & 1ull;
+      const bool irr = comp && ((iw >> (l & 63)) & 1ull);
+      f(slot, l, comp, irr, glb(P.g.nbr) + (size_t)slot * NBR_STRIDE);
     }
   }
 
@@ -193,19 +201,22 @@ struct Engine {
   __device__ bool setup_pass(int k, int p, double tj, double tend, double (&out)[2]) {
     double cl[PMAX + 1];
     double fact = 1.0, tpow = 1.0;
-    for (int l = 0; l <= p - k; ++l) {
+#pragma unroll
+    for (int l = 0; l <= PMAX; ++l) {
       if (l > 0) { fact *= l; tpow *= tj; }
-      cl[l] = tpow / fact / pow(tend, (double)(k + l));
+      cl[l] = (l <= p - k) ? tpow / fact / pow(tend, (double)(k + l)) : 0.0;
     }
-    const double* src = (k == 1) ? V(iu) : V(V_W1 + k - 2);
-    double* dst = (k == p) ? V(V_Q0) : V(V_W1 + k - 1);
+    gptr<const double> src = (k == 1) ? V(iu) : V(V_W1 + k - 2);
+    gptr<double> dst = (k == p) ? V(V_Q0) : V(V_W1 + k - 1);
     double acc[2] = {0.0, 0.0};
-    tiles([&](int slot, int l, bool comp, bool irr) {
+    tiles([&](int slot, int l, bool comp, bool irr, gptr<const int> nb) {
       const size_t i = (size_t)slot * TILE_PTS + l;
       double w = 0.0;
       if (comp) {
-        w = apply_A<DIM>(P.g, src, slot, l, c.nb, comp, irr);
-        for (int j = 0; j <= p - k; ++j) w += cl[j] * V(V_B0 + k + j)[i];
+        w = apply_A<DIM>(P.g, src, slot, l, nb, comp, irr);
+#pragma unroll
+        for (int j = 0; j <= PMAX; ++j)
+          if (j <= p - k) w += cl[j] * V(V_B0 + k + j)[i];
       }
       dst[i] = w;
       if (k == p) {
@@ -214,7 +225,7 @@ struct Engine {
         acc[1] += u * u;
       }
     });
-    bpu += 8.0 * ((p - k + 1) + 2 + (k == p ? 1 : 0));
+    bpu += 24.0 + 8.0 * (p - k + 1);
     if (k == p) return finish<2>(acc, out);
     return barrier();
   }
@@ -222,7 +233,7 @@ struct Engine {
   // p == 0: q_0 = U, norms.
   __device__ bool copy_u_pass(double (&out)[2]) {
     double acc[2] = {0.0, 0.0};
-    tiles([&](int slot, int l, bool comp, bool irr) {
+    tiles([&](int slot, int l, bool comp, bool irr, gptr<const int> nb) {
       const size_t i = (size_t)slot * TILE_PTS + l;
       const double u = V(iu)[i];
       V(V_Q0)[i] = u;
@@ -233,44 +244,57 @@ struct Engine {
     return finish<2>(acc, out);
   }
 
-  // z = A q_i into q_{i+1}; <z, q_i>.
-  __device__ bool lanczos_a(int i, double& dot) {
-    const double* q = V(V_Q0 + i);
-    double* z = V(V_Q0 + i + 1);
+  // Lanczos pass 0: z_0 = A q_0 into V_Z0; returns <z_0, q_0>.
+  __device__ bool lanczos_first(double& dot) {
+    gptr<const double> q = V(V_Q0);
+    gptr<double> z = V(V_Z0);
     double acc[1] = {0.0};
-    tiles([&](int slot, int l, bool comp, bool irr) {
+    tiles([&](int slot, int l, bool comp, bool irr, gptr<const int> nb) {
       const size_t idx = (size_t)slot * TILE_PTS + l;
-      const double zz = apply_A<DIM>(P.g, q, slot, l, c.nb, comp, irr);
+      const double zz = apply_A<DIM>(P.g, q, slot, l, nb, comp, irr);
       z[idx] = zz;
       acc[0] += zz * q[idx];
     });
-    bpu += 24.0;
     double out[1];
     if (!finish<1>(acc, out)) return false;
     dot = out[0];
     return true;
   }
 
-  // q_{i+1} = (z - alpha_i q_i)/n_i - (n_i/n_{i-1}) q_{i-1}; |q_{i+1}|^2.
-  __device__ bool lanczos_b(int i, double alpha, double& nn) {
-    const double* q = V(V_Q0 + i);
-    const double* qm = (i > 0) ? V(V_Q0 + i - 1) : nullptr;
-    double* z = V(V_Q0 + i + 1);
-    const double inv_n = 1.0 / c.nrm[i];
-    const double cm = (i > 0) ? c.nrm[i] / c.nrm[i - 1] : 0.0;
-    double acc[1] = {0.0};
-    tiles([&](int slot, int l, bool comp, bool irr) {
+  // Lanczos pass k >= 1: q_k from z_{k-1}, q_{k-1}, q_{k-2} (pointwise, also
+  // at the face neighbours), written to V_Q0 + k; z_k = A q_k into
+  // V_Z0 + (k & 1).  out = {|q_k|^2, <z_k, q_k>}.
+  __device__ bool lanczos_pass(int k, double (&out)[2]) {
+    gptr<const double> zp = V(V_Z0 + ((k - 1) & 1));
+    gptr<const double> q1 = V(V_Q0 + k - 1);
+    gptr<const double> q2 = V(V_Q0 + (k >= 2 ? k - 2 : 0));
+    gptr<double> qk = V(V_Q0 + k);
+    gptr<double> zk = V(V_Z0 + (k & 1));
+    const double alpha = c.alpha[k - 1];
+    const double inv_n = 1.0 / c.nrm[k - 1];
+    const double cm = (k >= 2) ? c.nrm[k - 1] / c.nrm[k - 2] : 0.0;
+    const bool two = k >= 2;
+    auto qv = [&](size_t i) -> double {
+      double w = (zp[i] - alpha * q1[i]) * inv_n;
+      if (two) w -= cm * q2[i];
+      return w;
+    };
+    double acc[2] = {0.0, 0.0};
+    tiles([&](int slot, int l, bool comp, bool irr, gptr<const int> nb) {
       const size_t idx = (size_t)slot * TILE_PTS + l;
-      double w = (z[idx] - alpha * q[idx]) * inv_n;
-      if (i > 0) w -= cm * qm[idx];
-      if (!comp) w = 0.0;
-      z[idx] = w;
-      acc[0] += w * w;
+      double q = 0.0, z = 0.0;
+      if (comp) {
+        q = qv(idx);
+        const double cp = irr ? glb(P.g.cdiag)[idx] : (double)(2 * DIM);
+        z = P.g.coef * (neighbour_sum<DIM>(slot, l, nb, qv) - cp * q);
+      }
+      qk[idx] = q;
+      zk[idx] = z;
+      acc[0] += q * q;
+      acc[1] += z * q;
     });
-    double out[1];
-    if (!finish<1>(acc, out)) return false;
-    nn = out[0];
-    return true;
+    bpu += 32.0;
+    return finish<2>(acc, out);
   }
 
   // out = sum_{k<p} tau^k/k! W_k + sum_i coef_i q_i into the buffer that is
@@ -278,19 +302,22 @@ struct Engine {
   __device__ bool combine_pass(int p, int m, double tau, double& nn) {
     double ck[PMAX];
     double f = 1.0, tp = 1.0;
-    for (int k = 0; k < p; ++k) {
+#pragma unroll
+    for (int k = 0; k < PMAX; ++k) {
       if (k > 0) { f *= k; tp *= tau; }
       ck[k] = tp / f;
     }
     const int io = (iu == V_U) ? V_T : V_U;
     double acc[1] = {0.0};
-    tiles([&](int slot, int l, bool comp, bool irr) {
+    tiles([&](int slot, int l, bool comp, bool irr, gptr<const int> nb) {
       const size_t idx = (size_t)slot * TILE_PTS + l;
       double u = 0.0;
       if (comp) {
         if (p > 0) {
           u = V(iu)[idx];
-          for (int k = 1; k < p; ++k) u += ck[k] * V(V_W1 + k - 1)[idx];
+#pragma unroll
+          for (int k = 1; k < PMAX; ++k)
+            if (k < p) u += ck[k] * V(V_W1 + k - 1)[idx];
         }
         for (int j = 0; j < m; ++j) u += c.coef[j] * V(V_Q0 + j)[idx];
       }
@@ -380,19 +407,22 @@ struct Engine {
       // phi_k(0) = 1/k!
       double f = 1.0;
       double ck[PMAX + 1];
-      for (int k = 0; k <= p; ++k) { if (k > 0) f *= k; ck[k] = 1.0 / f; }
-      tiles([&](int slot, int l, bool comp, bool irr) {
+#pragma unroll
+      for (int k = 0; k <= PMAX; ++k) { if (k > 0) f *= k; ck[k] = 1.0 / f; }
+      tiles([&](int slot, int l, bool comp, bool irr, gptr<const int> nb) {
         const size_t idx = (size_t)slot * TILE_PTS + l;
         double u = V(iu)[idx];
-        for (int k = 1; k <= p; ++k) u += ck[k] * V(V_B0 + k)[idx];
+#pragma unroll
+        for (int k = 1; k <= PMAX; ++k)
+          if (k <= p) u += ck[k] * V(V_B0 + k)[idx];
         V(iu)[idx] = comp ? u : 0.0;
       });
       return barrier();
     }
     const double tol = P.tol;
     double tj = 0.0;
-    double tau = tend * tau_frac[p];
-    int m_target = m_guess[p];
+    double tau = tend * c.tau_frac[p];
+    int m_target = c.m_guess[p];
     int nsub = 0;
     bool shrunk_any = false;
     double fact_p = 1.0;
@@ -427,6 +457,7 @@ struct Engine {
       if (threadIdx.x == 0) c.nrm[0] = n0;
       __syncthreads();
       int m = 0;
+      bool started = false;   // Lanczos pass 0 done for this substep
       bool breakdown = false;
       double anorm = 0.0;
       bool shrunk = false;
@@ -477,17 +508,25 @@ struct Engine {
       while (!accept) {
         if (++tries > 400) { fail(ST_KRYLOV); return false; }
         while (m < m_target && !breakdown) {
-          double dot, nn;
-          if (!lanczos_a(m, dot)) return false;
-          const double alpha = dot / (c.nrm[m] * c.nrm[m]);
-          if (!lanczos_b(m, alpha, nn)) return false;
-          matvecs += 1;
-          const double nb = sqrt(nn);
-          if (threadIdx.x == 0) {
-            c.alpha[m] = alpha;
-            c.nrm[m + 1] = nb;
+          if (m == 0 && !started) {
+            double dot;
+            if (!lanczos_first(dot)) return false;
+            matvecs += 1;
+            if (threadIdx.x == 0) c.alpha[0] = dot / (n0 * n0);
+            __syncthreads();
+            started = true;
           }
-          anorm = fmax(anorm, fabs(alpha) + nb + (m > 0 ? c.nrm[m] : 0.0));
+          double o[2];
+          if (!lanczos_pass(m + 1, o)) return false;
+          matvecs += 1;
+          const double nb = sqrt(o[0]);
+          const double alpha_next = (o[0] > 0.0) ? o[1] / o[0] : 0.0;
+          anorm = fmax(anorm, fabs(c.alpha[m]) + nb + (m > 0 ? c.nrm[m] : 0.0));
+          __syncthreads();
+          if (threadIdx.x == 0) {
+            c.nrm[m + 1] = nb;
+            c.alpha[m + 1] = alpha_next;
+          }
           __syncthreads();
           ++m;
           if (nb <= 1e-13 * anorm) breakdown = true;
@@ -524,8 +563,12 @@ struct Engine {
       iu = V_U;
     }
     substeps += nsub;
-    m_guess[p] = max(P.m_min, min(P.m_max, m_last - P.m_step / 2));
-    tau_frac[p] = shrunk_any ? fmin(1.0, 1.25 * tau / tend) : 1.0;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      c.m_guess[p] = max(P.m_min, min(P.m_max, m_last - P.m_step / 2));
+      c.tau_frac[p] = shrunk_any ? fmin(1.0, 1.25 * tau / tend) : 1.0;
+    }
+    __syncthreads();
     t_done = tj;
     return true;
   }
@@ -533,7 +576,7 @@ struct Engine {
   // ------------------------------------------------------------ jobs
 
   __device__ bool copy_pass(int dst, int src) {
-    tiles([&](int slot, int l, bool comp, bool irr) {
+    tiles([&](int slot, int l, bool comp, bool irr, gptr<const int> nb) {
       const size_t idx = (size_t)slot * TILE_PTS + l;
       V(dst)[idx] = comp ? V(src)[idx] : 0.0;
     });
@@ -541,74 +584,77 @@ struct Engine {
     return barrier();
   }
 
+  // Inputs of stage `stage` of the job: V_U = b_0 and V_B0 + k = b_k
+  // (k >= 1) of the combination sum_k phi_k(t A) b_k, its p and t.
+  __device__ bool assemble(int mode, int stage, int& p, double& t) {
+    if (mode == JOB_PHI) {
+      p = P.p;
+      t = P.t;
+      return copy_pass(V_U, V_B0);
+    }
+    const double h = P.h;
+    t = h;
+    if (stage == 0) {
+      // ETD1 / first ETD2RK stage: b_0 = U_n, b_1 = h F(U_n)
+      p = 1;
+      tiles([&](int slot, int l, bool comp, bool irr, gptr<const int> nb) {
+        const size_t idx = (size_t)slot * TILE_PTS + l;
+        const double u = comp ? V(V_X0)[idx] : 0.0;
+        V(V_B1)[idx] = comp ? h * react(u) : 0.0;
+        V(V_U)[idx] = u;
+      });
+      bpu += 24.0;
+    } else {
+      // ETD2RK final stage: b_0 = U_n, b_1 = h F(U_n), b_2 = h (F(a) - F(U_n))
+      p = 2;
+      tiles([&](int slot, int l, bool comp, bool irr, gptr<const int> nb) {
+        const size_t idx = (size_t)slot * TILE_PTS + l;
+        const double a = V(V_U)[idx];
+        const double u = comp ? V(V_X0)[idx] : 0.0;
+        V(V_B2)[idx] = comp ? h * (react(a) - react(u)) : 0.0;
+        V(V_U)[idx] = u;
+      });
+      bpu += 32.0;
+    }
+    return barrier();
+  }
+
   __device__ void run() {
-    switch (P.mode) {
-      case JOB_PHI: {
-        if (!copy_pass(V_U, V_B0)) return;
-        phi_comb(P.p, P.t);
-        return;
-      }
-      case JOB_ETD1: {
-        const double h = P.h;
-        tiles([&](int slot, int l, bool comp, bool irr) {
-          const size_t idx = (size_t)slot * TILE_PTS + l;
-          const double u = comp ? V(V_X0)[idx] : 0.0;
-          V(V_B1)[idx] = comp ? h * react(u) : 0.0;
-          V(V_U)[idx] = u;
-        });
-        bpu += 24.0;
-        if (!barrier()) return;
-        phi_comb(1, h);
-        return;
-      }
-      case JOB_ETD2RK:
-      case JOB_ETD2RK_STAGE: {
-        const double h = P.h;
-        tiles([&](int slot, int l, bool comp, bool irr) {
-          const size_t idx = (size_t)slot * TILE_PTS + l;
-          const double u = comp ? V(V_X0)[idx] : 0.0;
-          V(V_B1)[idx] = comp ? h * react(u) : 0.0;
-          V(V_U)[idx] = u;
-        });
-        bpu += 24.0;
-        if (!barrier()) return;
-        if (!phi_comb(1, h)) return;
-        if (P.mode == JOB_ETD2RK_STAGE) return;
-        tiles([&](int slot, int l, bool comp, bool irr) {
-          const size_t idx = (size_t)slot * TILE_PTS + l;
-          const double a = V(V_U)[idx];
-          const double u = comp ? V(V_X0)[idx] : 0.0;
-          V(V_B2)[idx] = comp ? h * (react(a) - react(u)) : 0.0;
-          V(V_U)[idx] = u;
-        });
-        bpu += 32.0;
-        if (!barrier()) return;
-        phi_comb(2, h);
-        return;
-      }
-      case JOB_APPLY: {
-        tiles([&](int slot, int l, bool comp, bool irr) {
-          const size_t idx = (size_t)slot * TILE_PTS + l;
-          V(V_U)[idx] = apply_A<DIM>(P.g, V(V_B0), slot, l, c.nb, comp, irr);
-        });
-        bpu += 16.0;
-        barrier();
-        return;
-      }
-      default:
-        if (threadIdx.x == 0 && blockIdx.x == 0) atomicCAS(P.status, 0, ST_INVALID);
-        return;
+    const int mode = P.mode;
+    if (mode == JOB_APPLY) {
+      tiles([&](int slot, int l, bool comp, bool irr, gptr<const int> nb) {
+        const size_t idx = (size_t)slot * TILE_PTS + l;
+        V(V_U)[idx] = apply_A<DIM>(P.g, V(V_B0), slot, l, nb, comp, irr);
+      });
+      bpu += 16.0;
+      barrier();
+      return;
+    }
+    if (mode != JOB_PHI && mode != JOB_ETD1 && mode != JOB_ETD2RK && mode != JOB_ETD2RK_STAGE) {
+      if (threadIdx.x == 0 && lb == 0) atomicCAS(P.status, 0, ST_INVALID);
+      return;
+    }
+    // one phi_comb call site for every job (keeps the engine inlined)
+    const int nstage = (mode == JOB_ETD2RK) ? 2 : 1;
+    for (int stage = 0; stage < nstage; ++stage) {
+      int p = 0;
+      double t = 0.0;
+      if (!assemble(mode, stage, p, t)) return;
+      if (!phi_comb(p, t)) return;
     }
   }
 };
 
-// One block of the persistent kernel; c, R and S are the block's LDS.
-template <int DIM, bool BATCH>
-__device__ void krylov_body(const KrylovDev& P, Ctl& c, double* R, double* S) {
-  Engine<DIM, BATCH> e{P, c, R, S, *P.g.n_active, 0};
+// One block of the persistent kernel (block lb of a group of G working on
+// instance P); c, R and S are the block's LDS.
+template <int DIM>
+__device__ __forceinline__ void krylov_body(const KrylovDev& P, int lb, int G, Ctl& c, double* R, double* S) {
+  Engine<DIM> e{P, c, R, S, *P.g.n_active, 0, lb, G};
   for (int k = 0; k <= PMAX; ++k) {
-    e.m_guess[k] = P.st->m_guess[k];
-    e.tau_frac[k] = P.st->tau_frac[k];
+    if (threadIdx.x == 0) {
+      c.m_guess[k] = P.st->m_guess[k];
+      c.tau_frac[k] = P.st->tau_frac[k];
+    }
   }
   e.substeps = e.rejected = e.matvecs = e.m_last = e.expms = 0;
   e.err_est = 0.0;
@@ -619,10 +665,10 @@ __device__ void krylov_body(const KrylovDev& P, Ctl& c, double* R, double* S) {
   __syncthreads();
   e.run();
   __syncthreads();
-  if (threadIdx.x == 0 && (BATCH || blockIdx.x == 0)) {
+  if (threadIdx.x == 0 && lb == 0) {
     for (int k = 0; k <= PMAX; ++k) {
-      P.st->m_guess[k] = e.m_guess[k];
-      P.st->tau_frac[k] = e.tau_frac[k];
+      P.st->m_guess[k] = c.m_guess[k];
+      P.st->tau_frac[k] = c.tau_frac[k];
     }
     P.st->substeps = e.substeps;
     P.st->rejected = e.rejected;
@@ -643,19 +689,25 @@ __global__ __launch_bounds__(KBLOCK) void krylov_kernel(KrylovDev P) {
   __shared__ Ctl c;
   __shared__ double R[EXPM_NMAX * EXPM_NMAX];
   __shared__ double S[EXPM_NMAX * EXPM_NMAX];
-  krylov_body<DIM, false>(P, c, R, S);
+  // parameters in LDS: the engine refers to them by reference, and a
+  // reference to a kernel argument would force a private-memory copy
+  __shared__ KrylovDev sP;
+  if (threadIdx.x == 0) sP = P;
+  __syncthreads();
+  krylov_body<DIM>(sP, (int)blockIdx.x, (int)gridDim.x, c, R, S);
 }
 
-// A batch: block b runs instance b of Ps[] (ordinary launch, no inter-block
-// dependency).
+// A batch of instances: block b belongs to instance blk_inst[b], whose
+// group is blocks Ps[i].g_first .. Ps[i].g_first + Ps[i].g_size - 1.  The
+// launch is cooperative whenever a group has more than one block.
 template <int DIM>
-__global__ __launch_bounds__(KBLOCK) void krylov_batch_kernel(const KrylovDev* __restrict__ Ps, int count) {
+__global__ __launch_bounds__(KBLOCK) void krylov_group_kernel(const KrylovDev* __restrict__ Ps,
+                                                              const int* __restrict__ blk_inst) {
   __shared__ Ctl c;
   __shared__ double R[EXPM_NMAX * EXPM_NMAX];
   __shared__ double S[EXPM_NMAX * EXPM_NMAX];
-  if ((int)blockIdx.x >= count) return;
-  const KrylovDev P = Ps[blockIdx.x];
-  krylov_body<DIM, true>(P, c, R, S);
+  const KrylovDev& P = Ps[blk_inst[blockIdx.x]];
+  krylov_body<DIM>(P, (int)blockIdx.x - P.g_first, P.g_size, c, R, S);
 }
 
 // Reset the synchronisation state before a persistent launch (a kernel, not
@@ -669,24 +721,53 @@ __global__ void sync_reset_kernel(BarrierDev* b, unsigned* flags, int n) {
   }
 }
 
+// Same for every instance of a batch (block i resets instance i).
+__global__ void sync_reset_group_kernel(const KrylovDev* __restrict__ Ps, int count) {
+  if ((int)blockIdx.x >= count) return;
+  const KrylovDev& P = Ps[blockIdx.x];
+  for (int i = threadIdx.x; i < P.g_size; i += blockDim.x) P.flags[i] = 0u;
+  if (threadIdx.x == 0) {
+    P.bar->count = 0;
+    P.bar->gen = 0;
+    P.bar->abort = 0;
+  }
+}
+
 int krylov_max_blocks_per_cu(int dim, int /*tmax*/) {
   int nb = 0;
   hipError_t e = (dim == 2)
       ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, krylov_kernel<2>, KBLOCK, 0)
       : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, krylov_kernel<3>, KBLOCK, 0);
   if (e != hipSuccess) return 0;
-  return nb;
+  int ng = 0;
+  e = (dim == 2) ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&ng, krylov_group_kernel<2>, KBLOCK, 0)
+                 : hipOccupancyMaxActiveBlocksPerMultiprocessor(&ng, krylov_group_kernel<3>, KBLOCK, 0);
+  if (e != hipSuccess) return 0;
+  return ng < nb ? ng : nb;
 }
 
 size_t krylov_dyn_lds(int /*dim*/, int /*tmax*/) { return 0; }
 
-// Batch of instances, one block each (Ps: device array of `count` KrylovDev).
-hipError_t launch_krylov_batch(int dim, const KrylovDev* Ps, int count, hipStream_t s) {
-  if (dim == 2)
-    hipLaunchKernelGGL(krylov_batch_kernel<2>, dim3(count), dim3(KBLOCK), 0, s, Ps, count);
-  else
-    hipLaunchKernelGGL(krylov_batch_kernel<3>, dim3(count), dim3(KBLOCK), 0, s, Ps, count);
-  return hipGetLastError();
+// A batch (Ps, blk_inst: device arrays of `count` parameter sets and
+// `blocks` instance indices).  `cooperative` when some group has more than
+// one block: the runtime then guarantees co-residency of the whole grid.
+hipError_t launch_krylov_group(int dim, const KrylovDev* Ps, int count, const int* blk_inst, int blocks,
+                               bool cooperative, hipStream_t s) {
+  hipLaunchKernelGGL(sync_reset_group_kernel, dim3(count), dim3(256), 0, s, Ps, count);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (!cooperative) {
+    if (dim == 2)
+      hipLaunchKernelGGL(krylov_group_kernel<2>, dim3(blocks), dim3(KBLOCK), 0, s, Ps, blk_inst);
+    else
+      hipLaunchKernelGGL(krylov_group_kernel<3>, dim3(blocks), dim3(KBLOCK), 0, s, Ps, blk_inst);
+    return hipGetLastError();
+  }
+  const KrylovDev* a0 = Ps;
+  const int* a1 = blk_inst;
+  void* args[] = {&a0, &a1};
+  const void* fn = (dim == 2) ? (const void*)krylov_group_kernel<2> : (const void*)krylov_group_kernel<3>;
+  return hipLaunchCooperativeKernel(fn, dim3(blocks), dim3(KBLOCK), args, 0, s);
 }
 
 // Reset the barrier, then the cooperative launch (co-residency of all blocks
@@ -696,6 +777,8 @@ hipError_t launch_krylov(int dim, const KrylovDev& P, int grid, hipStream_t s) {
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   KrylovDev arg = P;
+  arg.g_first = 0;
+  arg.g_size = grid;
   void* args[] = {&arg};
   const void* fn = (dim == 2) ? (const void*)krylov_kernel<2> : (const void*)krylov_kernel<3>;
   return hipLaunchCooperativeKernel(fn, dim3(grid), dim3(KBLOCK), args, 0, s);

@@ -23,7 +23,7 @@ hipError_t launch_scan_tiles(const int* tile_flag, int ntiles, int* tile_map, in
                              int* n_active, hipStream_t s);
 hipError_t launch_tile_coeff(const BoxHost& b, const double* rho, const uint8_t* mask,
                              const int* tile_map, uint64_t* comp_bits, uint64_t* irr_bits,
-                             double* cdiag, int* counts, int ntiles, hipStream_t s);
+                             double* cdiag, int* nbr, int* counts, int ntiles, hipStream_t s);
 hipError_t launch_gather(const BoxHost& b, const double* box, const int* slot_tile,
                          const uint64_t* comp_bits, const int* n_active, double* vec, int grid,
                          hipStream_t s);
@@ -34,6 +34,7 @@ hipError_t launch_scatter(const BoxHost& b, const double* vec, const int* tile_m
 hipError_t launch_krylov(int dim, const KrylovDev& P, int grid, hipStream_t s);
 int krylov_max_blocks_per_cu(int dim, int tmax);
 size_t krylov_dyn_lds(int dim, int tmax);
-hipError_t launch_krylov_batch(int dim, const KrylovDev* Ps, int count, hipStream_t s);
+hipError_t launch_krylov_group(int dim, const KrylovDev* Ps, int count, const int* blk_inst, int blocks,
+                               bool cooperative, hipStream_t s);
 
 }  // namespace etdfb

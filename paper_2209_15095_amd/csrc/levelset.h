@@ -33,8 +33,14 @@ constexpr int REINIT_ITERS = 10;
 
 hipError_t levelset_alloc(LevelsetScratch& s, size_t nodes);
 void levelset_free(LevelsetScratch& s);
-// Steps 1 + 2a on rho and u (box arrays, updated in place).
+// Steps 1 + 2a on rho and u (box arrays, updated in place): levelset_begin,
+// a synchronisation of the stream, levelset_end.  The two halves let a batch
+// share one synchronisation between many instances.
 hipError_t levelset_run(const LevelsetArgs& a, LevelsetScratch& s, double* rho, double* u,
+                        hipStream_t stream);
+hipError_t levelset_begin(const LevelsetArgs& a, LevelsetScratch& s, double* rho, double* u,
+                          hipStream_t stream);
+hipError_t levelset_end(const LevelsetArgs& a, LevelsetScratch& s, double* rho, double* u,
                         hipStream_t stream);
 
 }  // namespace etdfb

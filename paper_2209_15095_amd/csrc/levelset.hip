@@ -316,43 +316,48 @@ void levelset_free(LevelsetScratch& s) {
   s = LevelsetScratch{};
 }
 
-hipError_t levelset_run(const LevelsetArgs& a, LevelsetScratch& s, double* rho, double* u,
-                        hipStream_t st) {
-  LB b{a.box.dim, a.box.nx, a.box.ny, a.box.nz, a.box.dx};
-  const size_t n = s.nodes;
-  double* nx = s.buf + 0 * n;
-  double* ny = s.buf + 1 * n;
-  double* nz = s.buf + 2 * n;
-  double* u0 = s.buf + 3 * n;    // u (extended)
-  double* un = s.buf + 4 * n;
-  double* unn = s.buf + 5 * n;
-  double* tmp = s.buf + 6 * n;
-  double* V = s.buf + 7 * n;
-  double* r1 = s.buf + 8 * n;
-  double* r2 = s.buf + 9 * n;
-  double* Sg = s.buf + 10 * n;
-  double* r0 = s.buf + 11 * n;
-  const int G = grid_for(n);
-  const dim3 B(256);
+// Box arrays of the level-set scratch.
+struct LsBufs {
+  double *nx, *ny, *nz, *u0, *un, *unn, *tmp, *V, *r1, *r2, *Sg, *r0;
+  explicit LsBufs(const LevelsetScratch& s) {
+    double* p[12];
+    for (int i = 0; i < 12; ++i) p[i] = s.buf + (size_t)i * s.nodes;
+    nx = p[0]; ny = p[1]; nz = p[2];
+    u0 = p[3];   // u (extended)
+    un = p[4]; unn = p[5]; tmp = p[6]; V = p[7];
+    r1 = p[8]; r2 = p[9]; Sg = p[10]; r0 = p[11];
+  }
+};
+
 #define L(kernel, ...)                                            \
   do {                                                            \
     hipLaunchKernelGGL(kernel, dim3(G), B, 0, st, __VA_ARGS__);   \
     hipError_t _e = hipGetLastError();                            \
     if (_e != hipSuccess) return _e;                              \
   } while (0)
+
+// Steps 1 up to the maximum speed: normals, known sets, Aslam extrapolation,
+// Stefan speed and its extension; max V is copied (asynchronously) to the
+// pinned host word s.h_vmax.
+hipError_t levelset_begin(const LevelsetArgs& a, LevelsetScratch& s, double* rho, double* u,
+                          hipStream_t st) {
+  LB b{a.box.dim, a.box.nx, a.box.ny, a.box.nz, a.box.dx};
+  const LsBufs q(s);
+  const int G = grid_for(s.nodes);
+  const dim3 B(256);
   // normals and known sets of the current domain
-  L(normals_kernel, b, rho, nx, ny, nz);
-  L(known0_kernel, b, rho, u, s.known, u0);
+  L(normals_kernel, b, rho, q.nx, q.ny, q.nz);
+  L(known0_kernel, b, rho, u, s.known, q.u0);
   L(known_next_kernel, b, s.known, 0, 1);
   L(known_next_kernel, b, s.known, 1, 2);
-  L(central_dir_kernel, b, u0, nx, ny, nz, s.known, 1, un);
-  L(central_dir_kernel, b, un, nx, ny, nz, s.known, 2, unn);
+  L(central_dir_kernel, b, q.u0, q.nx, q.ny, q.nz, s.known, 1, q.un);
+  L(central_dir_kernel, b, q.un, q.nx, q.ny, q.nz, s.known, 2, q.unn);
   // Aslam: u_nn, u_n, u (ping-pong through tmp)
-  auto extend = [&](double*& v, const double* src, int bit, int iters) -> hipError_t {
+  auto extend = [&](double* v, const double* src, int bit, int iters) -> hipError_t {
     double* x = v;
-    double* y = tmp;
+    double* y = q.tmp;
     for (int it = 0; it < iters; ++it) {
-      hipLaunchKernelGGL(extend_kernel, dim3(G), B, 0, st, b, x, y, nx, ny, nz, src, s.known, bit,
+      hipLaunchKernelGGL(extend_kernel, dim3(G), B, 0, st, b, x, y, q.nx, q.ny, q.nz, src, s.known, bit,
                          (const double*)nullptr);
       hipError_t e = hipGetLastError();
       if (e != hipSuccess) return e;
@@ -365,49 +370,67 @@ hipError_t levelset_run(const LevelsetArgs& a, LevelsetScratch& s, double* rho, 
     return hipSuccess;
   };
   hipError_t e;
-  if ((e = extend(unn, nullptr, 2, ASLAM_ITERS)) != hipSuccess) return e;
-  if ((e = extend(un, unn, 1, ASLAM_ITERS)) != hipSuccess) return e;
-  if ((e = extend(u0, un, 0, ASLAM_ITERS)) != hipSuccess) return e;
+  if ((e = extend(q.unn, nullptr, 2, ASLAM_ITERS)) != hipSuccess) return e;
+  if ((e = extend(q.un, q.unn, 1, ASLAM_ITERS)) != hipSuccess) return e;
+  if ((e = extend(q.u0, q.un, 0, ASLAM_ITERS)) != hipSuccess) return e;
   // Stefan speed on the band, then constant extension along sign(rho) n
-  L(velocity_kernel, b, u0, rho, a.mu, s.known, V);
+  L(velocity_kernel, b, q.u0, rho, a.mu, s.known, q.V);
   {
-    double* x = V;
-    double* y = tmp;
+    double* x = q.V;
+    double* y = q.tmp;
     for (int it = 0; it < VEL_ITERS; ++it) {
-      L(extend_kernel, b, x, y, nx, ny, nz, (const double*)nullptr, s.known, 3, (const double*)rho);
+      L(extend_kernel, b, x, y, q.nx, q.ny, q.nz, (const double*)nullptr, s.known, 3, (const double*)rho);
       double* t = x; x = y; y = t;
     }
-    if (x != V) L(copy_kernel, b, x, V);
+    if (x != q.V) L(copy_kernel, b, x, q.V);
   }
   // number of advection substeps from max V (one readback)
   hipLaunchKernelGGL(zero_kernel, dim3(1), dim3(64), 0, st, s.vmax);
-  L(max_kernel, b, V, s.vmax);
+  L(max_kernel, b, q.V, s.vmax);
   if ((e = hipMemcpyAsync(s.h_vmax, s.vmax, sizeof(double), hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
-  if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
+  return hipSuccess;
+}
+
+// The rest of the step (the caller has synchronised the stream, so s.h_vmax
+// holds max V): advection substeps, reinitialisation, restriction of u.
+hipError_t levelset_end(const LevelsetArgs& a, LevelsetScratch& s, double* rho, double* u,
+                        hipStream_t st) {
+  LB b{a.box.dim, a.box.nx, a.box.ny, a.box.nz, a.box.dx};
+  const LsBufs q(s);
+  const int G = grid_for(s.nodes);
+  const dim3 B(256);
   const double vmax = *s.h_vmax;
   int nsub = (int)ceil(vmax * a.dt / (0.5 * b.h));
   if (nsub < 1) nsub = 1;
   const double ds = a.dt / nsub;
   // TVD-RK3 advection; rho (user array) is the running state
-  for (int q = 0; q < nsub; ++q) {
-    L(copy_kernel, b, rho, r0);
-    L(rk_stage_kernel, b, r0, r0, r1, V, (const double*)nullptr, ds, 0.0, 1.0);
-    L(rk_stage_kernel, b, r0, r1, r2, V, (const double*)nullptr, ds, 0.75, 0.25);
-    L(rk_stage_kernel, b, r0, r2, rho, V, (const double*)nullptr, ds, 1.0 / 3.0, 2.0 / 3.0);
+  for (int it = 0; it < nsub; ++it) {
+    L(copy_kernel, b, rho, q.r0);
+    L(rk_stage_kernel, b, q.r0, q.r0, q.r1, q.V, (const double*)nullptr, ds, 0.0, 1.0);
+    L(rk_stage_kernel, b, q.r0, q.r1, q.r2, q.V, (const double*)nullptr, ds, 0.75, 0.25);
+    L(rk_stage_kernel, b, q.r0, q.r2, rho, q.V, (const double*)nullptr, ds, 1.0 / 3.0, 2.0 / 3.0);
   }
   if (a.reinit) {
-    L(sign_kernel, b, rho, Sg);
+    L(sign_kernel, b, rho, q.Sg);
     const double dtau = 0.5 * b.h;
-    for (int q = 0; q < REINIT_ITERS; ++q) {
-      L(copy_kernel, b, rho, r0);
-      L(rk_stage_kernel, b, r0, r0, r1, (const double*)nullptr, Sg, dtau, 0.0, 1.0);
-      L(rk_stage_kernel, b, r0, r1, r2, (const double*)nullptr, Sg, dtau, 0.75, 0.25);
-      L(rk_stage_kernel, b, r0, r2, rho, (const double*)nullptr, Sg, dtau, 1.0 / 3.0, 2.0 / 3.0);
+    for (int it = 0; it < REINIT_ITERS; ++it) {
+      L(copy_kernel, b, rho, q.r0);
+      L(rk_stage_kernel, b, q.r0, q.r0, q.r1, (const double*)nullptr, q.Sg, dtau, 0.0, 1.0);
+      L(rk_stage_kernel, b, q.r0, q.r1, q.r2, (const double*)nullptr, q.Sg, dtau, 0.75, 0.25);
+      L(rk_stage_kernel, b, q.r0, q.r2, rho, (const double*)nullptr, q.Sg, dtau, 1.0 / 3.0, 2.0 / 3.0);
     }
   }
-  L(restrict_kernel, b, rho, u0, u);
-#undef L
+  L(restrict_kernel, b, rho, q.u0, u);
   return hipSuccess;
+}
+#undef L
+
+hipError_t levelset_run(const LevelsetArgs& a, LevelsetScratch& s, double* rho, double* u,
+                        hipStream_t st) {
+  hipError_t e = levelset_begin(a, s, rho, u, st);
+  if (e != hipSuccess) return e;
+  if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
+  return levelset_end(a, s, rho, u, st);
 }
 
 }  // namespace etdfb

@@ -74,3 +74,23 @@ def test_host_argument_checks(lib):
     assert lib.phi_combination_apply(None, 0.1, 1, None, None, None) == L.ETD_ERR_INVALID
     assert lib.levelset_advance(None, None, None, 0.1, 0) == L.ETD_ERR_INVALID
     assert lib.etd_operator_apply(None, None, None) == L.ETD_ERR_INVALID
+
+
+def test_batch_host_argument_checks(lib):
+    h = C.c_void_p()
+    g = (L.EtdGrid * 2)()
+    for i in range(2):
+        g[i].dim = 2
+        g[i].n[0] = g[i].n[1] = 64
+        g[i].lo[0] = g[i].lo[1] = -1.0
+        g[i].hi[0] = g[i].hi[1] = 1.0
+    ph = (L.EtdPhysics * 2)(L.EtdPhysics(1.0, 1.0, 1.0, 0.0), L.EtdPhysics(1.0, 1.0, 1.0, 0.0))
+    assert lib.etd_batch_create(0, g, ph, None, None, C.byref(h)) == L.ETD_ERR_INVALID
+    assert lib.etd_batch_create(2, None, ph, None, None, C.byref(h)) == L.ETD_ERR_INVALID
+    g[1].dim = 3   # mixed dimensions
+    assert lib.etd_batch_create(2, g, ph, None, None, C.byref(h)) == L.ETD_ERR_INVALID
+    assert lib.etd_batch_destroy(None) == L.ETD_ERR_INVALID
+    assert lib.etd_batch_sync(None) == L.ETD_ERR_INVALID
+    assert lib.etd_batch_step(None, 2, 0.1, None, None, 0, None) == L.ETD_ERR_INVALID
+    assert lib.etd_batch_geometry_build(None, None) == L.ETD_ERR_INVALID
+    assert lib.etd_batch_set_group_limit(None, 1) == L.ETD_ERR_INVALID
