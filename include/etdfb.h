@@ -166,6 +166,18 @@ int levelset_advance(etd_ctx* ctx, double* rho, double* u, double dt, int32_t re
 int etd_step(etd_ctx* ctx, int32_t scheme, double h, double* u, double* rho, int32_t reinit,
              etd_stats* stats);
 
+/* Discrete adjoint of one ETD2RK step (Section 3.2) on the frozen domain of
+ * the last etd_geometry_build, for the loss gradient of a step-by-step
+ * backward sweep.  A is symmetric (Section 2) and equals beta A_1 for the
+ * constant beta.  u_n: the forward state U_n (device box array);
+ * gbar_np1: dL/dU_{n+1} (device box array); both read at computational
+ * points.  gbar_n: receives dL/dU_n (device box array, written everywhere;
+ * may be the same array as gbar_np1, not u_n).  dL_dbeta: device scalar to
+ * which this step's dL/dbeta is added (stream-ordered).  scheme must be
+ * ETD_SCHEME_ETD2RK.  Six phi-combinations in one persistent launch. */
+int etd_adjoint_step(etd_ctx* ctx, int32_t scheme, double h, const double* u_n, const double* gbar_np1,
+                     double* gbar_n, double* dL_dbeta);
+
 /* Wait for the context's stream; return the first latched device error
  * (and clear it), or ETD_OK. */
 int etd_ctx_sync(etd_ctx* ctx);

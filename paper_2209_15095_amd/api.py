@@ -119,6 +119,24 @@ class Context:
                                   C.byref(st) if st is not None else None), "etd_step")
         return st.as_dict() if stats else None
 
+    def adjoint_step(self, h: float, u_n: torch.Tensor, gbar_np1: torch.Tensor, dbeta: torch.Tensor,
+                     gbar_n=None, scheme: str = "etd2rk"):
+        """gbar_n = dL/dU_n from gbar_np1 = dL/dU_{n+1}; dbeta (0-dim float64
+        CUDA tensor) accumulates dL/dbeta.  Returns gbar_n."""
+        code = {"etd1": L.ETD_SCHEME_ETD1, "etd2rk": L.ETD_SCHEME_ETD2RK}[scheme]
+        self._check_box(u_n, "u_n")
+        self._check_box(gbar_np1, "gbar_np1")
+        if gbar_n is None:
+            gbar_n = torch.empty_like(gbar_np1)
+        self._check_box(gbar_n, "gbar_n")
+        if dbeta.dtype != torch.float64 or not dbeta.is_cuda or dbeta.numel() != 1:
+            raise TypeError("dbeta: expected a one-element float64 CUDA tensor")
+        self._sync_stream()
+        L.check(self.lib.etd_adjoint_step(self.handle, code, float(h), C.c_void_p(_ptr(u_n)),
+                                          C.c_void_p(_ptr(gbar_np1)), C.c_void_p(_ptr(gbar_n)),
+                                          C.c_void_p(_ptr(dbeta))), "etd_adjoint_step")
+        return gbar_n
+
     def profile_enable(self, on: bool = True):
         L.check(self.lib.etd_ctx_profile_enable(self.handle, int(bool(on))), "etd_ctx_profile_enable")
 
@@ -229,4 +247,46 @@ class Batch:
         pr = L.EtdProfile()
         L.check(self.lib.etd_batch_profile_read(self.handle, C.byref(pr), int(bool(reset))), "etd_batch_profile_read")
         return pr.as_dict()
+
+
+class ETDSolve(torch.autograd.Function):
+    """u_T = ETD2RK^steps(u0) on a frozen domain, differentiable in u0 and beta.
+
+    Forward keeps a checkpoint every `checkpoint_every` steps; backward
+    recomputes each segment from its checkpoint and runs the discrete
+    adjoint (etd_adjoint_step) step by step in reverse.  Call as
+    ETDSolve.apply(u0, beta, context, h, steps, checkpoint_every) with a
+    Context whose geometry is built; beta is a one-element float64 tensor.
+    """
+
+    @staticmethod
+    def forward(fctx, u0, beta, context, h, steps, checkpoint_every=8):
+        context.set_beta(float(beta.detach().reshape(-1)[0].item()))
+        u = u0.detach().clone()
+        ckpt = {0: u.clone()}
+        for n in range(steps):
+            context.etd_step("etd2rk", h, u)
+            if (n + 1) % checkpoint_every == 0 and n + 1 < steps:
+                ckpt[n + 1] = u.clone()
+        fctx.context, fctx.h, fctx.steps, fctx.every = context, h, steps, checkpoint_every
+        fctx.ckpt = ckpt
+        fctx.beta_shape = beta.shape
+        return u
+
+    @staticmethod
+    def backward(fctx, grad_out):
+        context, h, steps, every = fctx.context, fctx.h, fctx.steps, fctx.every
+        g = grad_out.detach().contiguous().clone()
+        dbeta = torch.zeros(1, dtype=torch.float64, device=g.device)
+        starts = sorted(fctx.ckpt)
+        for s0 in reversed(starts):
+            e = min(s0 + every, steps)
+            states = [fctx.ckpt[s0].clone()]
+            for n in range(s0, e - 1):
+                u = states[-1].clone()
+                context.etd_step("etd2rk", h, u)
+                states.append(u)
+            for n in range(e - 1, s0 - 1, -1):
+                context.adjoint_step(h, states[n - s0], g, dbeta, gbar_n=g)
+        return g, dbeta.reshape(fctx.beta_shape), None, None, None, None
 

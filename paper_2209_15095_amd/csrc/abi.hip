@@ -506,6 +506,24 @@ int etd_step(etd_ctx* c, int32_t scheme, double h, double* u, double* rho, int32
   return ETD_OK;
 }
 
+int etd_adjoint_step(etd_ctx* c, int32_t scheme, double h, const double* u_n, const double* gbar_np1,
+                     double* gbar_n, double* dL_dbeta) {
+  if (!c || !u_n || !gbar_np1 || !gbar_n || !dL_dbeta || !(h >= 0.0) || !isfinite(h)) return ETD_ERR_INVALID;
+  if (scheme != ETD_SCHEME_ETD2RK || gbar_n == u_n) return ETD_ERR_INVALID;
+  if (!c->have_geometry) return ETD_ERR_NO_GEOMETRY;
+  int r = gather_to(c, u_n, V_X0);
+  if (r) return r;
+  r = gather_to(c, gbar_np1, V_G);
+  if (r) return r;
+  KrylovDev P = krylov_params(c, JOB_ADJ_ETD2RK);
+  P.h = h;
+  P.beta = c->phys.beta;
+  P.dbeta = dL_dbeta;
+  r = run_krylov(c, P);
+  if (r) return r;
+  return scatter_from(c, V_U, gbar_n);
+}
+
 int etd_ctx_sync(etd_ctx* c) {
   if (!c) return ETD_ERR_INVALID;
   return latched_status(c);

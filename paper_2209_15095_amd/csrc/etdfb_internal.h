@@ -31,7 +31,11 @@ enum VecIndex {
   V_T = 10,    // scratch
   V_Z0 = 11,   // A q_k (two buffers, alternating)
   V_Z1 = 12,
-  V_Q0 = 13,   // Krylov basis q_0 .. q_MMAX
+  V_G = 13,    // adjoint: dL/dU_{n+1}
+  V_A = 14,    // adjoint: ETD2RK stage a
+  V_AB = 15,   // adjoint: abar = f'(a) h phi_2(hA) g
+  V_S = 16,    // adjoint: f'(U_n) s
+  V_Q0 = 17,   // Krylov basis q_0 .. q_MMAX
   NVEC = V_Q0 + MMAX_LIMIT + 1
 };
 
@@ -75,7 +79,8 @@ enum JobMode {
   JOB_ETD1 = 1,       // one ETD1 step of V_X0
   JOB_ETD2RK = 2,     // one ETD2RK step of V_X0
   JOB_ETD2RK_STAGE = 3, // only the first stage a of ETD2RK
-  JOB_APPLY = 4         // V_U = A V_B0
+  JOB_APPLY = 4,        // V_U = A V_B0
+  JOB_ADJ_ETD2RK = 5    // adjoint of one ETD2RK step: V_U = dL/dU_n from V_G, V_X0; *dbeta += dL/dbeta
 };
 
 struct KrylovDev {
@@ -94,6 +99,8 @@ struct KrylovDev {
   int mode;
   int p;
   double t;                   // JOB_PHI: time t of phi_k(t A)
+  double beta;                // JOB_ADJ_ETD2RK: beta (A = beta A_1)
+  double* dbeta;              // JOB_ADJ_ETD2RK: device scalar, dL/dbeta accumulated
   double h;                   // ETD step
   int g_first, g_size;        // blocks of this instance in the launch grid
 };

@@ -584,8 +584,58 @@ struct Engine {
     return barrier();
   }
 
+  __device__ double dreact(double u) const { return P.ra - 2.0 * P.rb * u; }
+
+  // Number of phi-combinations of a job.
+  __device__ int stages(int mode) const {
+    switch (mode) {
+      case JOB_ETD2RK: return 2;
+      case JOB_ADJ_ETD2RK: return 6;
+      default: return 1;
+    }
+  }
+
+  // Pointwise pass over the computational points: f(idx) at every point of
+  // the active tiles (f sees comp), then a barrier.
+  template <class F>
+  __device__ bool pointwise(double bytes, F&& f) {
+    tiles([&](int slot, int l, bool comp, bool irr, gptr<const int> nb) {
+      f((size_t)slot * TILE_PTS + l, comp);
+    });
+    bpu += bytes;
+    return barrier();
+  }
+
+  // <V(vb), A V(va)> over the unknowns.
+  __device__ bool dot_A_pass(int va, int vb, double& out) {
+    gptr<const double> a = V(va);
+    gptr<const double> b = V(vb);
+    double acc[1] = {0.0};
+    tiles([&](int slot, int l, bool comp, bool irr, gptr<const int> nb) {
+      const size_t idx = (size_t)slot * TILE_PTS + l;
+      acc[0] += b[idx] * apply_A<DIM>(P.g, a, slot, l, nb, comp, irr);
+    });
+    bpu += 16.0;
+    double o[1];
+    if (!finish<1>(acc, o)) return false;
+    out = o[0];
+    return true;
+  }
+
   // Inputs of stage `stage` of the job: V_U = b_0 and V_B0 + k = b_k
   // (k >= 1) of the combination sum_k phi_k(t A) b_k, its p and t.
+  //
+  // Adjoint of ETD2RK (A symmetric, A = beta A_1, g = dL/dU_{n+1},
+  // F = f(U_n), a the stage, abar = f'(a) h phi_2 g):
+  //   stage 0: a = phi_0 U_n + phi_1 hF                   -> V_A
+  //   stage 1: phi_2 g                                    -> abar in V_AB
+  //   stage 2: v_s = phi_0 U_n + phi_1 hF - phi_2 hF      -> <abar, A v_s>
+  //   stage 3: v_f = phi_0 U_n + phi_1 hF + phi_2 (h(f(a)-F) - hF)
+  //                  - phi_3 2h(f(a)-F)                   -> <g, A v_f>
+  //   stage 4: s = phi_1 h(g + abar) - phi_2 hg           -> f'(U_n) s in V_S
+  //   stage 5: phi_0 (g + abar); + V_S                    -> dL/dU_n in V_U
+  // and dL/dbeta += (h/beta)(<g, A v_f> + <abar, A v_s>), from
+  // d/dbeta phi_k(h beta A_1) = (h/beta) A (phi_k - k phi_{k+1})(hA).
   __device__ bool assemble(int mode, int stage, int& p, double& t) {
     if (mode == JOB_PHI) {
       p = P.p;
@@ -594,29 +644,103 @@ struct Engine {
     }
     const double h = P.h;
     t = h;
+    gptr<double> U = V(V_U);
+    gptr<double> B1 = V(V_B1);
+    gptr<double> B2 = V(V_B2);
+    gptr<double> B3 = V(V_B3);
+    gptr<const double> X = V(V_X0);
+    gptr<const double> G = V(V_G);
+    gptr<const double> Aa = V(V_A);
+    gptr<const double> AB = V(V_AB);
+    if (mode == JOB_ADJ_ETD2RK) {
+      switch (stage) {
+        case 0:
+        case 2:
+        case 3:
+          p = (stage == 0) ? 1 : (stage == 2 ? 2 : 3);
+          return pointwise(stage == 0 ? 24.0 : (stage == 2 ? 32.0 : 48.0), [&](size_t i, bool comp) {
+            const double u = comp ? X[i] : 0.0;
+            const double hF = comp ? h * react(u) : 0.0;
+            U[i] = u;
+            B1[i] = hF;
+            if (stage == 2) B2[i] = -hF;
+            if (stage == 3) {
+              const double d = comp ? h * (react(Aa[i]) - react(u)) : 0.0;
+              B2[i] = d - hF;
+              B3[i] = -2.0 * d;
+            }
+          });
+        case 1:
+          p = 2;
+          return pointwise(32.0, [&](size_t i, bool comp) {
+            U[i] = 0.0;
+            B1[i] = 0.0;
+            B2[i] = comp ? G[i] : 0.0;
+          });
+        case 4:
+          p = 2;
+          return pointwise(40.0, [&](size_t i, bool comp) {
+            const double g = comp ? G[i] : 0.0;
+            U[i] = 0.0;
+            B1[i] = comp ? h * (g + AB[i]) : 0.0;
+            B2[i] = -h * g;
+          });
+        default:
+          p = 0;
+          return pointwise(24.0, [&](size_t i, bool comp) { U[i] = comp ? G[i] + AB[i] : 0.0; });
+      }
+    }
     if (stage == 0) {
       // ETD1 / first ETD2RK stage: b_0 = U_n, b_1 = h F(U_n)
       p = 1;
-      tiles([&](int slot, int l, bool comp, bool irr, gptr<const int> nb) {
-        const size_t idx = (size_t)slot * TILE_PTS + l;
-        const double u = comp ? V(V_X0)[idx] : 0.0;
-        V(V_B1)[idx] = comp ? h * react(u) : 0.0;
-        V(V_U)[idx] = u;
+      return pointwise(24.0, [&](size_t i, bool comp) {
+        const double u = comp ? X[i] : 0.0;
+        B1[i] = comp ? h * react(u) : 0.0;
+        U[i] = u;
       });
-      bpu += 24.0;
-    } else {
-      // ETD2RK final stage: b_0 = U_n, b_1 = h F(U_n), b_2 = h (F(a) - F(U_n))
-      p = 2;
-      tiles([&](int slot, int l, bool comp, bool irr, gptr<const int> nb) {
-        const size_t idx = (size_t)slot * TILE_PTS + l;
-        const double a = V(V_U)[idx];
-        const double u = comp ? V(V_X0)[idx] : 0.0;
-        V(V_B2)[idx] = comp ? h * (react(a) - react(u)) : 0.0;
-        V(V_U)[idx] = u;
-      });
-      bpu += 32.0;
     }
-    return barrier();
+    // ETD2RK final stage: b_0 = U_n, b_1 = h F(U_n), b_2 = h (F(a) - F(U_n))
+    p = 2;
+    return pointwise(32.0, [&](size_t i, bool comp) {
+      const double a = U[i];
+      const double u = comp ? X[i] : 0.0;
+      B2[i] = comp ? h * (react(a) - react(u)) : 0.0;
+      U[i] = u;
+    });
+  }
+
+  // What a stage leaves behind once its combination is in V_U.
+  __device__ bool post(int mode, int stage, double& dsum) {
+    if (mode != JOB_ADJ_ETD2RK) return true;
+    const double h = P.h;
+    gptr<double> U = V(V_U);
+    switch (stage) {
+      case 0: {
+        gptr<double> Aa = V(V_A);
+        return pointwise(16.0, [&](size_t i, bool comp) { Aa[i] = U[i]; });
+      }
+      case 1: {
+        gptr<double> AB = V(V_AB);
+        gptr<const double> Aa = V(V_A);
+        return pointwise(24.0, [&](size_t i, bool comp) { AB[i] = comp ? dreact(Aa[i]) * h * U[i] : 0.0; });
+      }
+      case 2:
+      case 3: {
+        double d = 0.0;
+        if (!dot_A_pass(V_U, stage == 2 ? V_AB : V_G, d)) return false;
+        dsum += d;
+        return true;
+      }
+      case 4: {
+        gptr<double> Sv = V(V_S);
+        gptr<const double> X = V(V_X0);
+        return pointwise(24.0, [&](size_t i, bool comp) { Sv[i] = comp ? dreact(X[i]) * U[i] : 0.0; });
+      }
+      default: {
+        gptr<const double> Sv = V(V_S);
+        return pointwise(24.0, [&](size_t i, bool comp) { U[i] = comp ? U[i] + Sv[i] : 0.0; });
+      }
+    }
   }
 
   __device__ void run() {
@@ -630,18 +754,22 @@ struct Engine {
       barrier();
       return;
     }
-    if (mode != JOB_PHI && mode != JOB_ETD1 && mode != JOB_ETD2RK && mode != JOB_ETD2RK_STAGE) {
+    if (mode != JOB_PHI && mode != JOB_ETD1 && mode != JOB_ETD2RK && mode != JOB_ETD2RK_STAGE &&
+        mode != JOB_ADJ_ETD2RK) {
       if (threadIdx.x == 0 && lb == 0) atomicCAS(P.status, 0, ST_INVALID);
       return;
     }
     // one phi_comb call site for every job (keeps the engine inlined)
-    const int nstage = (mode == JOB_ETD2RK) ? 2 : 1;
+    const int nstage = stages(mode);
+    double dsum = 0.0;
     for (int stage = 0; stage < nstage; ++stage) {
       int p = 0;
       double t = 0.0;
       if (!assemble(mode, stage, p, t)) return;
       if (!phi_comb(p, t)) return;
+      if (!post(mode, stage, dsum)) return;
     }
+    if (mode == JOB_ADJ_ETD2RK && threadIdx.x == 0 && lb == 0) *P.dbeta += (P.h / P.beta) * dsum;
   }
 };
 

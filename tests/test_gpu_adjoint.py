@@ -1,0 +1,159 @@
+"""GPU parity of the discrete ETD2RK adjoint (etd_adjoint_step, ETDSolve).
+
+* One adjoint step on 2D and 3D domains against the oracle's adjoint step
+  (dense phi-functions): dL/dU_n to 1e-9 relative L2 and dL/dbeta to 1e-9
+  relative, at Krylov tolerance 1e-12 (dL/dbeta contracts with A, which
+  amplifies the Krylov error of the combinations by up to |A|, so the
+  tighter tolerance keeps the comparison about the algebra), and dL/dU_n at
+  the default tolerance 1e-10 to 1e-9.
+* The checkpointed autograd wrapper against the oracle's full gradient on
+  the 64^2 disk (10 steps, checkpoints every 4).
+* The 96^3 sphere workload in full (40 steps, checkpoints every 8): the
+  adjoint gradient against central finite differences of GPU forward runs
+  at tolerance 1e-13, in a random direction of U_0 (eps 1e-4) and in beta
+  (eps 1e-5); the steps balance the O(eps^2) truncation against the Krylov
+  noise of the forward runs (~ tol |U|^2 / eps).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle.adjoint import adjoint_step, gradient
+from oracle.etd import logistic
+from oracle.geometry import Grid
+from oracle.operator import build_operator
+from paper_2209_15095_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(f"[gpu-adjoint] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def ogrid(g):
+    return Grid(g.dim, tuple(g.n), tuple(g.lo), tuple(g.hi))
+
+
+def ctx_for(grid, **kw):
+    from paper_2209_15095_amd.api import Context
+    return Context(grid.dim, grid.n, grid.lo, grid.hi, **kw)
+
+
+def small_ellipsoid3d(n=32):
+    g = inputs.GridSpec(3, (n, n, n), (-4.0,) * 3, (4.0,) * 3)
+    X, Y, Z = g.coords()
+    return g, inputs.sdf_prolate_spheroid(X, Y, Z, 3.0, 2.0)
+
+
+@pytest.mark.parametrize("case", ["fisher64", "ellipsoid3d"])
+@pytest.mark.parametrize("tol", [1e-12, 1e-10])
+def test_adjoint_step_parity(case, tol):
+    say(f"adjoint step {case} tol {tol}")
+    if case == "fisher64":
+        w = inputs.fisher64()
+        g, rho = w.grid, w.rho0
+    else:
+        g, rho = small_ellipsoid3d()
+    beta, h = 1.3, 0.05
+    op = build_operator(ogrid(g), rho, beta)
+    rng = np.random.default_rng(3)
+    un = np.where(op.comp, rng.uniform(0.2, 0.8, rho.shape), 0.0)
+    gb = rng.standard_normal(rho.shape)
+    f, df = logistic(1.0, 1.0)
+    gU, dbeta = adjoint_step(op.A, beta, h, op.gather(un), op.gather(gb), f, df, method="dense")
+    ctx = ctx_for(g, beta=beta, tol=tol)
+    ctx.geometry_build(dev(rho))
+    db = torch.zeros(1, dtype=torch.float64, device="cuda")
+    out = ctx.adjoint_step(h, dev(un), dev(gb), db)
+    torch.cuda.synchronize()
+    o = out.cpu().numpy()
+    dbg = float(db.cpu()[0])
+    say(f"  grad rel {rel_l2(o[op.comp], gU):.3e}  dbeta {dbg:.12e} vs {dbeta:.12e}")
+    assert np.all(o[~op.comp] == 0.0)
+    assert rel_l2(o[op.comp], gU) <= 1e-9
+    if tol <= 1e-12:
+        assert abs(dbg - dbeta) <= 1e-9 * abs(dbeta)
+    ctx.close()
+
+
+def test_etdsolve_gradient_matches_oracle():
+    from paper_2209_15095_amd.api import ETDSolve
+    say("ETDSolve fisher64 frozen, 10 steps, checkpoints every 4")
+    w = inputs.fisher64()
+    beta, h, steps = 0.9, 0.02, 10
+    op1 = build_operator(ogrid(w.grid), w.rho0, 1.0)
+    rng = np.random.default_rng(4)
+    u0 = np.where(op1.comp, rng.uniform(0.2, 0.8, w.rho0.shape), 0.0)
+    f, df = logistic(1.0, 1.0)
+    L, gU, gb = gradient(beta * op1.A, beta, h, op1.gather(u0), steps, f, df, method="dense")
+    ctx = ctx_for(w.grid, beta=beta, tol=1e-12)
+    ctx.geometry_build(dev(w.rho0))
+    u0t = dev(u0).requires_grad_(True)
+    bt = torch.tensor([beta], dtype=torch.float64, device="cuda", requires_grad=True)
+    uT = ETDSolve.apply(u0t, bt, ctx, h, steps, 4)
+    loss = (uT * uT).sum()
+    loss.backward()
+    torch.cuda.synchronize()
+    gg = u0t.grad.cpu().numpy()
+    say(f"  L {float(loss):.12e} vs {L:.12e}; grad rel {rel_l2(gg[op1.comp], gU):.3e}; "
+        f"dbeta {float(bt.grad[0]):.10e} vs {gb:.10e}")
+    assert abs(float(loss) - L) <= 1e-10 * L
+    assert rel_l2(gg[op1.comp], gU) <= 1e-9
+    assert np.all(gg[~op1.comp] == 0.0)
+    assert abs(float(bt.grad[0]) - gb) <= 1e-9 * abs(gb)
+    ctx.close()
+
+
+def test_adjoint_sphere96_finite_differences():
+    from paper_2209_15095_amd.api import ETDSolve
+    w = inputs.sphere96()
+    steps, every = w.steps, w.extra["checkpoint_every"]
+    say(f"sphere96: {steps} steps, checkpoints every {every}")
+    ctx = ctx_for(w.grid, beta=w.beta, tol=1e-12)
+    ctx.geometry_build(dev(w.rho0))
+    u0t = dev(w.u0).requires_grad_(True)
+    bt = torch.tensor([w.beta], dtype=torch.float64, device="cuda", requires_grad=True)
+    uT = ETDSolve.apply(u0t, bt, ctx, w.h, steps, every)
+    loss = (uT * uT).sum()
+    loss.backward()
+    torch.cuda.synchronize()
+    grad = u0t.grad.detach()
+    dbeta = float(bt.grad[0])
+    ctx.close()
+    # forward runs for finite differences at a tight tolerance
+    fctx = ctx_for(w.grid, beta=w.beta, tol=1e-13)
+    fctx.geometry_build(dev(w.rho0))
+    comp = (grad != 0).cpu().numpy() | (w.u0 != 0)
+    rng = np.random.default_rng(7)
+    d = dev(np.where(comp, rng.standard_normal(w.u0.shape), 0.0))
+
+    def L(u0, beta):
+        fctx.set_beta(beta)
+        u = u0.clone()
+        for _ in range(steps):
+            fctx.etd_step("etd2rk", w.h, u)
+        return float((u * u).sum())
+
+    # eps: truncation O(eps^2) against Krylov noise ~ tol |U|^2 / eps
+    eps_u, eps_b = 1e-4, 1e-5
+    base = dev(w.u0)
+    fd_u = (L(base + eps_u * d, w.beta) - L(base - eps_u * d, w.beta)) / (2 * eps_u)
+    fd_b = (L(base, w.beta + eps_b) - L(base, w.beta - eps_b)) / (2 * eps_b)
+    ad_u = float((grad * d).sum())
+    say(f"  direction: adjoint {ad_u:.10e} fd {fd_u:.10e}; beta: adjoint {dbeta:.10e} fd {fd_b:.10e}")
+    fctx.close()
+    assert abs(ad_u - fd_u) <= 1e-6 * abs(fd_u)
+    assert abs(dbeta - fd_b) <= 1e-6 * abs(fd_b)
