@@ -17,6 +17,13 @@ by the kernel itself and time from HIP events on the stream it runs on.
 The CPU baseline is the oracle (plain NumPy/SciPy, test infrastructure) on a
 bounded sample of the same workload.
 
+Other workloads (not the headline line): --workload batch64 (64 random
+stars advanced by the batched entry points; value = sum of n^2 over the
+instances times steps per second), --workload sphere96 (one gradient of the
+96^3 frozen-domain loss: 40 forward steps, checkpointed backward with the
+discrete adjoint; value = n^3 times 40 per second of the whole gradient),
+and the bandwidth-scale frozen-domain runs disk4097 and sphere385.
+
 Usage: python bench.py [--gpus 1] [--steps 200] [--warmup 5] [--workload star512]
 """
 from __future__ import annotations
@@ -75,6 +82,160 @@ def cpu_baseline(w, steps: int):
             "seconds": dt}
 
 
+def roofline_obj(prof, kernel, alg_key="alg_bytes"):
+    kern_s = prof["krylov_ms"] * 1e-3
+    achieved = prof[alg_key] / kern_s / 1e9 if kern_s > 0 else 0.0
+    return {
+        "bound": "hbm",
+        "kernel": kernel,
+        "achieved": achieved,
+        "peak": PEAK_HBM_GBS,
+        "unit": "GB/s",
+        "frac": achieved / PEAK_HBM_GBS,
+        "alg_bytes_per_launch": prof[alg_key] / max(prof["krylov_launches"], 1),
+        "avg_launch_ms": prof["krylov_ms"] / max(prof["krylov_launches"], 1),
+    }
+
+
+def cpu_baseline_batch(ws, steps: int, count: int):
+    """Oracle on the first `count` instances for `steps` steps."""
+    import numpy as np
+
+    from oracle.freeboundary import free_boundary_step
+    from oracle.geometry import Grid
+
+    pts = 0
+    t0 = time.perf_counter()
+    for w in ws[:count]:
+        g = Grid(w.grid.dim, tuple(w.grid.n), tuple(w.grid.lo), tuple(w.grid.hi))
+        rho, u = w.rho0.copy(), w.u0.copy()
+        for m in range(steps):
+            rho, u, _ = free_boundary_step(g, rho, u, w.h, w.beta, w.mu, w.a, w.b, scheme=w.scheme,
+                                           reinit=(m + 1) % w.reinit_every == 0, method="krylov")
+        pts += int(np.prod(w.grid.n[: w.grid.dim])) * steps
+    dt = time.perf_counter() - t0
+    return {"value": pts / dt, "unit": "grid-point steps/s", "cores": 1, "host_cpus": os.cpu_count(),
+            "kind": "oracle", "seconds": dt,
+            "sample": f"first {steps} steps of the first {count} instances, single-threaded NumPy/SciPy"}
+
+
+def bench_batch(args):
+    import numpy as np
+    import torch
+
+    from paper_2209_15095_amd import inputs
+    from paper_2209_15095_amd.api import Batch
+
+    ws = inputs.batch64()
+    pts = sum(int(np.prod(w.grid.n[:2])) for w in ws)
+    log(f"[bench] batch64: {len(ws)} instances, {pts} grid points, steps {args.steps}")
+    b = Batch([w.grid for w in ws], [dict(beta=w.beta, a=w.a, b=w.b, mu=w.mu) for w in ws])
+    rho0 = [torch.from_numpy(w.rho0).cuda() for w in ws]
+    u0 = [torch.from_numpy(w.u0).cuda() for w in ws]
+    rhos = [r.clone() for r in rho0]
+    us = [u.clone() for u in u0]
+
+    def run(n):
+        for m in range(n):
+            b.step("etd2rk", ws[0].h, us, rhos, reinit=(m + 1) % ws[0].reinit_every == 0)
+
+    b.geometry_build(rhos)
+    run(args.warmup)
+    b.sync()
+    for r, r0 in zip(rhos, rho0):
+        r.copy_(r0)
+    for u, v0 in zip(us, u0):
+        u.copy_(v0)
+    b.geometry_build(rhos)
+    b.profile_enable(True)
+    b.profile_read(reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    run(args.steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    b.sync()
+    prof = b.profile_read()
+    b.close()
+    out = {
+        "metric": "grid-point ETD steps/s at Krylov tol 1e-10",
+        "value": pts * args.steps / wall,
+        "unit": "grid-point steps/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": 1e3 * wall / max(args.steps, 1),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "batch64", "instances": len(ws), "grid_points": pts,
+                   "scheme": "etd2rk", "h": ws[0].h, "mu": ws[0].mu, "free_boundary": True,
+                   "reinit_every": ws[0].reinit_every, "krylov_tol": 1e-10},
+        "unknown_steps_per_s": prof["n_unknowns"] * args.steps / wall,
+        "breakdown_ms_per_step": {k: prof[k + "_ms"] / max(args.steps, 1)
+                                  for k in ("krylov", "levelset", "geometry")},
+        "roofline": roofline_obj(prof, "krylov_group_kernel<2> (batched persistent ETD2RK step)"),
+    }
+    out["roofline"]["traffic"] = None
+    if not args.no_cpu_baseline:
+        log("[bench] cpu baseline: oracle on 4 instances x 2 steps")
+        out["cpu_baseline"] = cpu_baseline_batch(ws, 2, 4)
+    else:
+        out["cpu_baseline"] = None
+    print(json.dumps(out), flush=True)
+
+
+def bench_adjoint(args):
+    import numpy as np
+    import torch
+
+    from paper_2209_15095_amd import inputs
+    from paper_2209_15095_amd.api import Context, ETDSolve
+
+    w = inputs.sphere96()
+    steps, every = w.steps, w.extra["checkpoint_every"]
+    npts = int(np.prod(w.grid.n[:3]))
+    ctx = Context.from_grid(w.grid, beta=w.beta, a=w.a, b=w.b, mu=w.mu, tol=1e-10)
+    ctx.geometry_build(torch.from_numpy(w.rho0).cuda())
+    u0 = torch.from_numpy(w.u0).cuda()
+
+    def grad_once():
+        u = u0.clone().requires_grad_(True)
+        bt = torch.tensor([w.beta], dtype=torch.float64, device="cuda", requires_grad=True)
+        uT = ETDSolve.apply(u, bt, ctx, w.h, steps, every)
+        (uT * uT).sum().backward()
+        return u.grad, bt.grad
+
+    reps = max(1, args.steps // steps)
+    log(f"[bench] sphere96 gradient: {steps} steps, checkpoints every {every}, {reps} repetitions")
+    for _ in range(max(1, args.warmup // 5)):
+        grad_once()
+    ctx.sync()
+    ctx.profile_enable(True)
+    ctx.profile_read(reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        grad_once()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    prof = ctx.profile_read()
+    ctx.close()
+    out = {
+        "metric": "grid-point ETD steps/s at Krylov tol 1e-10 (gradient: forward + adjoint)",
+        "value": npts * steps * reps / wall,
+        "unit": "grid-point steps/s",
+        "n_gpus": 1, "steps": steps * reps, "warmup": args.warmup,
+        "ms_per_step": 1e3 * wall / (steps * reps),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "sphere96", "grid": list(w.grid.n[:3]), "scheme": "etd2rk", "h": w.h,
+                   "steps": steps, "checkpoint_every": every, "free_boundary": False, "krylov_tol": 1e-10},
+        "ms_per_gradient": 1e3 * wall / reps,
+        "roofline": roofline_obj(prof, "krylov_kernel<3> (forward steps, recomputation, adjoint steps)"),
+        "cpu_baseline": None,
+    }
+    out["roofline"]["traffic"] = None
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -97,6 +258,10 @@ def main():
     from paper_2209_15095_amd import inputs
     from paper_2209_15095_amd.api import Context
 
+    if args.workload == "batch64":
+        return bench_batch(args)
+    if args.workload == "sphere96":
+        return bench_adjoint(args)
     if args.copy_probe > 0:
         n = args.copy_probe * (1 << 20) // 8
         src = torch.ones(n, dtype=torch.float64, device="cuda")
