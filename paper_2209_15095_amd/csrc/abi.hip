@@ -34,7 +34,10 @@ struct etd_ctx {
   uint64_t* irr_bits = nullptr;
   double* cdiag = nullptr;
   int* nbr = nullptr;        // face-neighbour slots, NBR_STRIDE per slot
-  int* counters = nullptr;   // [0] n_active, [1] status, [2..3] case counts
+  int* tile_vb = nullptr;    // tiles with a node |rho| < h
+  int* band_tmp = nullptr;   // 3 * ntiles: dilation passes and map
+  int* band_list = nullptr;  // level-set band tiles
+  int* counters = nullptr;   // [0] n_active, [1] status, [2..3] case counts, [4] unknowns, [5] band tiles
   // persistent kernel state
   double* ws = nullptr;
   double* part = nullptr;
@@ -47,8 +50,10 @@ struct etd_ctx {
   int grid_blocks = 1;
   int n_active_host = 0;
   bool have_geometry = false;
-  // level-set scratch (box arrays)
+  // level-set scratch (box arrays) and its one-instance table
   LevelsetScratch ls{};
+  LevelsetBatch lsb{};
+  int nband_host = 0;
   // pinned host mirror for small readbacks
   int* h_counters = nullptr;
   KrylovStateDev* h_state = nullptr;
@@ -72,6 +77,7 @@ struct etd_batch {
   int nchunks = 1;            // launches per step (instances per launch <= capacity)
   KrylovDev* d_params = nullptr;
   KrylovDev* h_params = nullptr;
+  LevelsetBatch lsb{};        // level-set table of all instances
   int* d_blk = nullptr;       // block -> instance, capacity entries per chunk
   int* h_blk = nullptr;
   hipEvent_t staged = nullptr;
@@ -242,11 +248,15 @@ int latched_status(etd_ctx* c) {
 int geometry_enqueue(etd_ctx* c, const double* rho) {
   HIP_TRY(timer_begin(c->profiling, c->stream, c->t_geometry));
   HIP_TRY(launch_fill_int(c->tile_flag, c->ntiles, 0, c->stream));
+  HIP_TRY(launch_fill_int(c->tile_vb, c->ntiles, 0, c->stream));
   HIP_TRY(launch_fill_int(c->counters + 2, 3, 0, c->stream));
-  HIP_TRY(launch_classify(c->box, rho, c->mask, c->tile_flag, c->counters + 1, c->stream));
+  HIP_TRY(launch_classify(c->box, rho, c->mask, c->tile_flag, c->tile_vb, c->counters + 1, c->stream));
   HIP_TRY(launch_scan_tiles(c->tile_flag, c->ntiles, c->tile_map, c->slot_tile, c->counters + 0, c->stream));
   HIP_TRY(launch_tile_coeff(c->box, rho, c->mask, c->tile_map, c->comp_bits, c->irr_bits, c->cdiag,
                             c->nbr, c->counters + 2, c->ntiles, c->stream));
+  HIP_TRY(launch_band(c->box, c->tile_flag, c->tile_vb, BAND_ASLAM, BAND_SPEED, c->band_tmp,
+                      c->band_tmp + c->ntiles, c->band_tmp + 2 * (size_t)c->ntiles, c->band_list, c->counters + 5,
+                      c->stream));
   HIP_TRY(timer_end(c->profiling, c->stream, c->t_geometry));
   HIP_TRY(hipMemcpyAsync(c->h_counters, c->counters, 8 * sizeof(int), hipMemcpyDeviceToHost, c->stream));
   return ETD_OK;
@@ -254,6 +264,7 @@ int geometry_enqueue(etd_ctx* c, const double* rho) {
 
 int geometry_finish(etd_ctx* c) {
   c->n_active_host = c->h_counters[0];
+  c->nband_host = c->h_counters[5];
   choose_launch(c);
   c->have_geometry = true;
   if (c->h_counters[1] == ST_DOMAIN) {
@@ -265,23 +276,31 @@ int geometry_finish(etd_ctx* c) {
   return ETD_OK;
 }
 
-LevelsetArgs levelset_args(const etd_ctx* c, double dt, int reinit) {
-  LevelsetArgs a{};
-  a.box = c->box;
-  a.mu = c->phys.mu;
-  a.dt = dt;
-  a.reinit = reinit;
-  a.mask = c->mask;
-  a.status = c->counters + 1;
-  return a;
+// The level-set view of a context (its scratch, band and the user arrays).
+LsInst levelset_inst(const etd_ctx* c, double* rho, double* u) {
+  LsInst I{};
+  I.dim = c->box.dim;
+  I.nx = c->box.nx; I.ny = c->box.ny; I.nz = c->box.nz;
+  I.ntx = c->box.ntx; I.nty = c->box.nty; I.ntz = c->box.ntz;
+  I.nband = c->nband_host;
+  I.h = c->box.dx;
+  I.mu = c->phys.mu;
+  I.rho = rho;
+  I.u = u;
+  I.buf = c->ls.buf;
+  I.nodes = c->ls.nodes;
+  I.known = c->ls.known;
+  I.band = c->band_list;
+  return I;
 }
 
 void free_all(etd_ctx* c) {
   void* ptrs[] = {c->mask, c->tile_flag, c->tile_map, c->slot_tile, c->comp_bits, c->irr_bits, c->cdiag,
-                  c->nbr, c->counters, c->ws, c->part, c->flags, c->bar, c->st};
+                  c->nbr, c->tile_vb, c->band_tmp, c->band_list, c->counters, c->ws, c->part, c->flags, c->bar, c->st};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   levelset_free(c->ls);
+  levelset_batch_free(c->lsb);
   timer_free(c->t_krylov);
   timer_free(c->t_levelset);
   timer_free(c->t_geometry);
@@ -367,6 +386,9 @@ int etd_ctx_create(const etd_grid* grid, const etd_physics* phys, const etd_kryl
   ok &= hipMalloc(&c->irr_bits, sizeof(uint64_t) * 4 * c->ntiles) == hipSuccess;
   ok &= hipMalloc(&c->cdiag, sizeof(double) * c->ld) == hipSuccess;
   ok &= hipMalloc(&c->nbr, sizeof(int) * NBR_STRIDE * (size_t)c->ntiles) == hipSuccess;
+  ok &= hipMalloc(&c->tile_vb, sizeof(int) * (size_t)c->ntiles) == hipSuccess;
+  ok &= hipMalloc(&c->band_tmp, sizeof(int) * 3 * (size_t)c->ntiles) == hipSuccess;
+  ok &= hipMalloc(&c->band_list, sizeof(int) * (size_t)c->ntiles) == hipSuccess;
   ok &= hipMalloc(&c->counters, sizeof(int) * 8) == hipSuccess;
   ok &= hipMalloc(&c->ws, sizeof(double) * c->ld * NVEC) == hipSuccess;
   ok &= hipMalloc(&c->part, sizeof(double) * 2 * (size_t)c->max_grid * PART_STRIDE) == hipSuccess;
@@ -376,6 +398,7 @@ int etd_ctx_create(const etd_grid* grid, const etd_physics* phys, const etd_kryl
   ok &= hipHostMalloc(&c->h_counters, sizeof(int) * 8) == hipSuccess;
   ok &= hipHostMalloc(&c->h_state, sizeof(KrylovStateDev)) == hipSuccess;
   ok &= levelset_alloc(c->ls, c->nodes) == hipSuccess;
+  ok &= levelset_batch_alloc(c->lsb, 1, b.dim) == hipSuccess;
   if (!ok) {
     free_all(c);
     delete c;
@@ -473,9 +496,11 @@ int levelset_advance(etd_ctx* c, double* rho, double* u, double dt, int32_t rein
     int r = etd_geometry_build(c, rho);
     if (r) return r;
   }
-  const LevelsetArgs a = levelset_args(c, dt, reinit);
+  c->lsb.h_inst[0] = levelset_inst(c, rho, u);
   HIP_TRY(timer_begin(c->profiling, c->stream, c->t_levelset));
-  HIP_TRY(levelset_run(a, c->ls, rho, u, c->stream));
+  HIP_TRY(levelset_begin(c->lsb, dt, reinit, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  HIP_TRY(levelset_end(c->lsb, c->stream));
   HIP_TRY(timer_end(c->profiling, c->stream, c->t_levelset));
   return etd_geometry_build(c, rho);
 }
@@ -581,6 +606,7 @@ void batch_free(etd_batch* B) {
   if (B->h_params) (void)hipHostFree(B->h_params);
   if (B->h_blk) (void)hipHostFree(B->h_blk);
   if (B->staged) (void)hipEventDestroy(B->staged);
+  levelset_batch_free(B->lsb);
   timer_free(B->t_krylov);
   timer_free(B->t_levelset);
   timer_free(B->t_geometry);
@@ -674,6 +700,7 @@ int etd_batch_create(int32_t count, const etd_grid* grids, const etd_physics* ph
   ok &= hipMalloc(&B->d_blk, sizeof(int) * (size_t)B->capacity * B->nchunks) == hipSuccess;
   ok &= hipHostMalloc(&B->h_blk, sizeof(int) * (size_t)B->capacity * B->nchunks) == hipSuccess;
   ok &= hipEventCreate(&B->staged) == hipSuccess;
+  ok &= levelset_batch_alloc(B->lsb, count, B->dim) == hipSuccess;
   if (!ok) {
     batch_free(B);
     delete B;
@@ -738,17 +765,12 @@ int etd_batch_step(etd_batch* B, int32_t scheme, double h, double* const* u, dou
       const int r = etd_batch_geometry_build(B, rho);
       if (r) return r;
     }
-    // level-set sweeps of every instance around one synchronisation
+    // level-set sweeps of every instance in shared launches, one synchronisation
+    for (int i = 0; i < B->count; ++i) B->lsb.h_inst[i] = levelset_inst(B->inst[i], rho[i], u[i]);
     HIP_TRY(timer_begin(B->profiling, B->stream, B->t_levelset));
-    for (int i = 0; i < B->count; ++i) {
-      etd_ctx* c = B->inst[i];
-      HIP_TRY(levelset_begin(levelset_args(c, h, reinit), c->ls, rho[i], u[i], B->stream));
-    }
+    HIP_TRY(levelset_begin(B->lsb, h, reinit, B->stream));
     HIP_TRY(hipStreamSynchronize(B->stream));
-    for (int i = 0; i < B->count; ++i) {
-      etd_ctx* c = B->inst[i];
-      HIP_TRY(levelset_end(levelset_args(c, h, reinit), c->ls, rho[i], u[i], B->stream));
-    }
+    HIP_TRY(levelset_end(B->lsb, B->stream));
     HIP_TRY(timer_end(B->profiling, B->stream, B->t_levelset));
     const int r = etd_batch_geometry_build(B, rho);
     if (r) return r;

@@ -52,7 +52,7 @@ __global__ void fill_int_kernel(int* p, size_t n, int v) {
 }
 
 __global__ void classify_kernel(BoxDev b, const double* __restrict__ rho, uint8_t* __restrict__ mask,
-                                int* __restrict__ tile_flag, int* __restrict__ status) {
+                                int* __restrict__ tile_flag, int* __restrict__ tile_vb, int* __restrict__ status) {
   const size_t total = (size_t)b.nx * b.ny * b.nz;
   for (size_t id = blockIdx.x * (size_t)blockDim.x + threadIdx.x; id < total;
        id += (size_t)gridDim.x * blockDim.x) {
@@ -73,6 +73,7 @@ __global__ void classify_kernel(BoxDev b, const double* __restrict__ rho, uint8_
       }
     }
     mask[id] = comp ? 2 : (inside ? 1 : 0);
+    if (fabs(rho[id]) < b.dx) tile_vb[tile_of(b, i, j, k)] = 1;   // a node of the speed band
     if (comp) {
       tile_flag[tile_of(b, i, j, k)] = 1;
       bool edge = i < 2 || i > b.nx - 3 || j < 2 || j > b.ny - 3;
@@ -118,6 +119,32 @@ __global__ __launch_bounds__(1024) void scan_tiles_kernel(const int* __restrict_
     __syncthreads();
   }
   if (threadIdx.x == 0) *n_active = carry;
+}
+
+// Narrow band of the level-set sweeps, one axis of a separable dilation on
+// the tile grid: bit 0 spreads `ra` tiles from tiles with a computational
+// point, bit 1 spreads `rv` tiles from tiles with a speed-band node.  The
+// first pass (axis 0) reads the two flag arrays, later passes the bits.
+__global__ void band_dilate_kernel(BoxDev b, const int* __restrict__ comp_flag, const int* __restrict__ vb_flag,
+                                   const int* __restrict__ in, int* __restrict__ out, int axis, int ra, int rv) {
+  const int ntiles = b.ntx * b.nty * b.ntz;
+  const int n[3] = {b.ntx, b.nty, b.ntz};
+  const int r = ra > rv ? ra : rv;
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < ntiles; t += gridDim.x * blockDim.x) {
+    int c[3] = {t % b.ntx, (t / b.ntx) % b.nty, t / (b.ntx * b.nty)};
+    const int c0 = c[axis];
+    int bits = 0;
+    for (int d = -r; d <= r; ++d) {
+      const int x = c0 + d;
+      if (x < 0 || x >= n[axis]) continue;
+      c[axis] = x;
+      const int tn = (c[2] * b.nty + c[1]) * b.ntx + c[0];
+      const int src = (axis == 0) ? ((comp_flag[tn] != 0 ? 1 : 0) | (vb_flag[tn] != 0 ? 2 : 0)) : in[tn];
+      if (d >= -ra && d <= ra) bits |= src & 1;
+      if (d >= -rv && d <= rv) bits |= src & 2;
+    }
+    out[t] = bits;
+  }
 }
 
 __device__ __forceinline__ void central_grad(const BoxDev& b, const double* __restrict__ rho, int i,
@@ -326,10 +353,32 @@ hipError_t launch_fill_int(int* p, size_t n, int v, hipStream_t s) {
 }
 
 hipError_t launch_classify(const BoxHost& b, const double* rho, uint8_t* mask, int* tile_flag,
-                           int* status, hipStream_t s) {
+                           int* tile_vb, int* status, hipStream_t s) {
   const size_t n = (size_t)b.nx * b.ny * b.nz;
   hipLaunchKernelGGL(classify_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, to_dev(b), rho, mask,
-                     tile_flag, status);
+                     tile_flag, tile_vb, status);
+  return hipGetLastError();
+}
+
+hipError_t launch_band(const BoxHost& b, const int* comp_flag, const int* vb_flag, int band_nodes_comp,
+                       int band_nodes_speed, int* tmp0, int* tmp1, int* band_map, int* band_list, int* nband,
+                       hipStream_t s) {
+  const int ntiles = b.ntx * b.nty * b.ntz;
+  const int t[3] = {b.tx, b.ty, b.tz};
+  const BoxDev bd = to_dev(b);
+  int* in = tmp0;
+  int* out = tmp1;
+  for (int axis = 0; axis < b.dim; ++axis) {
+    const int ra = (band_nodes_comp + t[axis] - 1) / t[axis];
+    const int rv = (band_nodes_speed + t[axis] - 1) / t[axis];
+    hipLaunchKernelGGL(band_dilate_kernel, dim3(blocks_for(ntiles, 256)), dim3(256), 0, s, bd, comp_flag,
+                       vb_flag, (const int*)in, out, axis, ra, rv);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    int* x = in; in = out; out = x;
+  }
+  hipLaunchKernelGGL(scan_tiles_kernel, dim3(1), dim3(1024), 0, s, (const int*)in, ntiles, band_map, band_list,
+                     nband);
   return hipGetLastError();
 }
 

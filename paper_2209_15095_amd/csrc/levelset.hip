@@ -1,7 +1,8 @@
 // Level-set sweeps that move the free boundary (Section 4.3 of the paper,
-// Algorithm Steps 1-2).  Box layout, one thread per node, Jacobi updates
-// (every node from the previous iterate, so the result does not depend on
-// scheduling), nearest-node values beyond the box edge.
+// Algorithm Steps 1-2).  Box layout, one thread per node, 256-node tiles
+// (one tile per block), Jacobi updates (every node from the previous
+// iterate, so the result does not depend on scheduling), nearest-node values
+// beyond the box edge.  Band and whole-box launches: see levelset.h.
 //
 // Readings of the paper's unspecified details (shared with the CPU oracle):
 // * normals n = grad rho / max(|grad rho|, 1e-12), central differences;
@@ -20,6 +21,7 @@
 // * finally u = u_ext on the computational points of the new rho, else 0.
 #include <math.h>
 
+#include "device_common.h"
 #include "levelset.h"
 
 namespace etdfb {
@@ -28,179 +30,227 @@ namespace {
 
 constexpr double WENO_EPS = 1e-6;
 
-struct LB {
-  int dim, nx, ny, nz;
-  double h;
+// box arrays of LevelsetScratch::buf
+enum { A_NX = 0, A_NY = 1, A_NZ = 2, A_E0 = 3, A_E1 = 4, A_E2 = 5, A_E3 = 6, A_V = 7,
+       A_R0 = 8, A_R1 = 9, A_R2 = 10, A_S = 11, A_COUNT = 12 };
+
+struct Where {
+  const LsInst* I;
+  int local;     // tile index within the instance's list
+  int i, j, k;
+  size_t id;
+  bool in;       // node inside the box
 };
+
+// Block -> instance (largest i with off[i] <= blockIdx.x) -> tile -> node.
+template <int DIM>
+__device__ __forceinline__ Where locate(const LsInst* __restrict__ insts, const int* __restrict__ off, int count,
+                                       bool band) {
+  const int* o = band ? off : off + count + 1;
+  const int b = (int)blockIdx.x;
+  int lo = 0, hi = count - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (o[mid] <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  Where w;
+  w.I = insts + lo;
+  w.local = b - o[lo];
+  const LsInst& I = *w.I;
+  const int t = band ? I.band[w.local] : w.local;
+  constexpr int X = TileShape<DIM>::X, Y = TileShape<DIM>::Y;
+  const int tx = t % I.ntx, ty = (t / I.ntx) % I.nty, tz = t / (I.ntx * I.nty);
+  const int l = threadIdx.x;
+  w.i = tx * X + l % X;
+  w.j = ty * Y + (l / X) % Y;
+  w.k = tz * TileShape<DIM>::Z + l / (X * Y);
+  w.in = w.i < I.nx && w.j < I.ny && w.k < I.nz;
+  w.id = ((size_t)w.k * I.ny + w.j) * I.nx + w.i;
+  return w;
+}
+
+__device__ __forceinline__ gptr<double> arr(const LsInst& I, int a) { return glb(I.buf) + (size_t)a * I.nodes; }
 
 __device__ __forceinline__ int clampi(int v, int n) { return v < 0 ? 0 : (v >= n ? n - 1 : v); }
 
-__device__ __forceinline__ void coords(const LB& b, size_t id, int& i, int& j, int& k) {
-  i = (int)(id % b.nx);
-  j = (int)((id / b.nx) % b.ny);
-  k = (int)(id / ((size_t)b.nx * b.ny));
+// index of the node shifted by s along axis d, clamped to the box
+__device__ __forceinline__ size_t shifted(const LsInst& I, const Where& w, int d, int s) {
+  int i = w.i, j = w.j, k = w.k;
+  if (d == 0) i = clampi(i + s, I.nx);
+  else if (d == 1) j = clampi(j + s, I.ny);
+  else k = clampi(k + s, I.nz);
+  return ((size_t)k * I.ny + j) * I.nx + i;
 }
 
-// value of a at (i,j,k) shifted by s along spatial axis d, clamped
-__device__ __forceinline__ double at(const LB& b, const double* __restrict__ a, int i, int j, int k, int d,
-                                     int s) {
-  if (d == 0) i = clampi(i + s, b.nx);
-  else if (d == 1) j = clampi(j + s, b.ny);
-  else k = clampi(k + s, b.nz);
-  return a[((size_t)k * b.ny + j) * b.nx + i];
-}
-
-__device__ __forceinline__ uint8_t atm(const LB& b, const uint8_t* __restrict__ a, int i, int j, int k, int d,
-                                       int s) {
-  if (d == 0) i = clampi(i + s, b.nx);
-  else if (d == 1) j = clampi(j + s, b.ny);
-  else k = clampi(k + s, b.nz);
-  return a[((size_t)k * b.ny + j) * b.nx + i];
-}
-
-#define GRID_LOOP(b)                                                                  \
-  const size_t total = (size_t)(b).nx * (b).ny * (b).nz;                             \
-  for (size_t id = blockIdx.x * (size_t)blockDim.x + threadIdx.x; id < total;        \
-       id += (size_t)gridDim.x * blockDim.x)
-
-__global__ void normals_kernel(LB b, const double* __restrict__ rho, double* __restrict__ nx,
-                               double* __restrict__ ny, double* __restrict__ nz) {
-  GRID_LOOP(b) {
-    int i, j, k;
-    coords(b, id, i, j, k);
-    double g[3] = {0.0, 0.0, 0.0};
-    for (int d = 0; d < b.dim; ++d) g[d] = (at(b, rho, i, j, k, d, 1) - at(b, rho, i, j, k, d, -1)) / (2.0 * b.h);
-    double mag = 0.0;
-    for (int d = 0; d < b.dim; ++d) mag += g[d] * g[d];
-    mag = fmax(sqrt(mag), 1e-12);
-    nx[id] = g[0] / mag;
-    ny[id] = g[1] / mag;
-    if (b.dim == 3) nz[id] = g[2] / mag;
+// computational point of rho (inside, not on the box edge, 2d neighbours inside)
+template <int DIM>
+__device__ __forceinline__ bool comp_point(const LsInst& I, const Where& w, gptr<const double> rho) {
+  bool c = rho[w.id] < 0.0;
+  if (c) {
+    if (w.i == 0 || w.i == I.nx - 1 || w.j == 0 || w.j == I.ny - 1) c = false;
+    if (DIM == 3 && (w.k == 0 || w.k == I.nz - 1)) c = false;
   }
+  for (int d = 0; d < DIM && c; ++d) c = rho[shifted(I, w, d, -1)] < 0.0 && rho[shifted(I, w, d, 1)] < 0.0;
+  return c;
 }
 
-// bit 0: K0 (computational points of rho), also u0 = K0 ? u : 0
-__global__ void known0_kernel(LB b, const double* __restrict__ rho, const double* __restrict__ u,
-                              uint8_t* __restrict__ known, double* __restrict__ u0) {
-  GRID_LOOP(b) {
-    int i, j, k;
-    coords(b, id, i, j, k);
-    bool c = rho[id] < 0.0;
-    if (c) {
-      if (i == 0 || i == b.nx - 1 || j == 0 || j == b.ny - 1) c = false;
-      if (b.dim == 3 && (k == 0 || k == b.nz - 1)) c = false;
-    }
-    if (c)
-      for (int d = 0; d < b.dim && c; ++d)
-        c = at(b, rho, i, j, k, d, -1) < 0.0 && at(b, rho, i, j, k, d, 1) < 0.0;
-    known[id] = c ? 1 : 0;
-    u0[id] = c ? u[id] : 0.0;
-  }
+// ------------------------------------------------------------ Step 1: u_ext
+
+// whole box: the extrapolation arrays and the speed start at 0
+template <int DIM>
+__global__ __launch_bounds__(256) void zero_kernel(const LsInst* __restrict__ insts, const int* __restrict__ off,
+                                                   int count) {
+  const Where w = locate<DIM>(insts, off, count, false);
+  if (!w.in) return;
+  const LsInst& I = *w.I;
+  for (int a = A_E0; a <= A_V; ++a) arr(I, a)[w.id] = 0.0;
 }
 
-// bit `dst` = bit `src` at the node and all 2d (clamped) neighbours
-__global__ void known_next_kernel(LB b, uint8_t* __restrict__ known, int src, int dst) {
-  GRID_LOOP(b) {
-    int i, j, k;
-    coords(b, id, i, j, k);
-    bool c = (known[id] >> src) & 1;
-    for (int d = 0; d < b.dim && c; ++d)
-      c = ((atm(b, known, i, j, k, d, -1) >> src) & 1) && ((atm(b, known, i, j, k, d, 1) >> src) & 1);
-    if (c) known[id] |= (uint8_t)(1u << dst);
-  }
+// band: normals, K0 (bit 0), E0 = K0 ? u : 0; resets the instance's max speed
+template <int DIM>
+__global__ __launch_bounds__(256) void init_kernel(const LsInst* __restrict__ insts, const int* __restrict__ off,
+                                                   int count) {
+  const Where w = locate<DIM>(insts, off, count, true);
+  const LsInst& I = *w.I;
+  if (w.local == 0 && threadIdx.x == 0) *glb(I.vmax) = 0.0;
+  if (!w.in) return;
+  gptr<const double> rho = glb((const double*)I.rho);
+  double g[3] = {0.0, 0.0, 0.0};
+  for (int d = 0; d < DIM; ++d) g[d] = (rho[shifted(I, w, d, 1)] - rho[shifted(I, w, d, -1)]) / (2.0 * I.h);
+  double mag = 0.0;
+  for (int d = 0; d < DIM; ++d) mag += g[d] * g[d];
+  mag = fmax(sqrt(mag), 1e-12);
+  for (int d = 0; d < DIM; ++d) arr(I, A_NX + d)[w.id] = g[d] / mag;
+  const bool c = comp_point<DIM>(I, w, rho);
+  glb(I.known)[w.id] = c ? 1 : 0;
+  arr(I, A_E0)[w.id] = c ? glb((const double*)I.u)[w.id] : 0.0;
 }
 
-// dst = known(bit) ? n . central grad(src) : 0
-__global__ void central_dir_kernel(LB b, const double* __restrict__ src, const double* __restrict__ nx,
-                                   const double* __restrict__ ny, const double* __restrict__ nz,
-                                   const uint8_t* __restrict__ known, int bit, double* __restrict__ dst) {
-  GRID_LOOP(b) {
-    int i, j, k;
-    coords(b, id, i, j, k);
-    double v = 0.0;
-    if ((known[id] >> bit) & 1) {
-      const double* n[3] = {nx, ny, nz};
-      for (int d = 0; d < b.dim; ++d)
-        v += n[d][id] * ((at(b, src, i, j, k, d, 1) - at(b, src, i, j, k, d, -1)) / (2.0 * b.h));
-    }
-    dst[id] = v;
-  }
+// bit `src` at the node and its 2d (clamped) neighbours
+template <int DIM>
+__device__ __forceinline__ bool known_all(const LsInst& I, const Where& w, int src) {
+  gptr<const uint8_t> kn = glb((const uint8_t*)I.known);
+  bool c = (kn[w.id] >> src) & 1;
+  for (int d = 0; d < DIM && c; ++d)
+    c = ((kn[shifted(I, w, d, -1)] >> src) & 1) && ((kn[shifted(I, w, d, 1)] >> src) & 1);
+  return c;
 }
 
-// one Jacobi sweep of v <- v - dtau (a.grad v - src) off the known set;
-// a = sgn * n (sgn = 1, or sign(rho) when sgn_rho != nullptr)
-__global__ void extend_kernel(LB b, const double* __restrict__ v, double* __restrict__ out,
-                              const double* __restrict__ nx, const double* __restrict__ ny,
-                              const double* __restrict__ nz, const double* __restrict__ src,
-                              const uint8_t* __restrict__ known, int bit,
-                              const double* __restrict__ sgn_rho) {
-  GRID_LOOP(b) {
-    int i, j, k;
-    coords(b, id, i, j, k);
-    const double vc = v[id];
-    if ((known[id] >> bit) & 1) {
-      out[id] = vc;
-      continue;
-    }
-    double sg = 1.0;
-    if (sgn_rho) {
-      const double r = sgn_rho[id];
-      sg = (r > 0.0) ? 1.0 : ((r < 0.0) ? -1.0 : 0.0);
-    }
-    const double* n[3] = {nx, ny, nz};
-    double up = 0.0;
-    for (int d = 0; d < b.dim; ++d) {
-      const double a = sg * n[d][id];
-      up += fmax(a, 0.0) * (vc - at(b, v, i, j, k, d, -1)) + fmin(a, 0.0) * (at(b, v, i, j, k, d, 1) - vc);
-    }
-    up = up / b.h;
-    const double s = src ? src[id] : 0.0;
-    out[id] = vc - (0.5 * b.h) * (up - s);
-  }
+// n . (central gradient of a) at the node
+template <int DIM>
+__device__ __forceinline__ double dir_deriv(const LsInst& I, const Where& w, gptr<const double> a) {
+  double v = 0.0;
+  for (int d = 0; d < DIM; ++d)
+    v += arr(I, A_NX + d)[w.id] * ((a[shifted(I, w, d, 1)] - a[shifted(I, w, d, -1)]) / (2.0 * I.h));
+  return v;
 }
 
-// V = band ? mu |central grad u| : 0; band (|rho| < h) into bit 3; vmax reduction
-__global__ void velocity_kernel(LB b, const double* __restrict__ u, const double* __restrict__ rho, double mu,
-                                uint8_t* __restrict__ known, double* __restrict__ V) {
-  GRID_LOOP(b) {
-    int i, j, k;
-    coords(b, id, i, j, k);
-    const bool band = fabs(rho[id]) < b.h;
-    double v = 0.0;
-    if (band) {
-      double s = 0.0;
-      for (int d = 0; d < b.dim; ++d) {
-        const double g = (at(b, u, i, j, k, d, 1) - at(b, u, i, j, k, d, -1)) / (2.0 * b.h);
-        s += g * g;
-      }
-      v = mu * sqrt(s);
-      known[id] |= 8;
+// band: K1 (bit 1)
+template <int DIM>
+__global__ __launch_bounds__(256) void known1_kernel(const LsInst* __restrict__ insts, const int* __restrict__ off,
+                                                     int count) {
+  const Where w = locate<DIM>(insts, off, count, true);
+  if (!w.in) return;
+  const LsInst& I = *w.I;
+  if (known_all<DIM>(I, w, 0)) glb(I.known)[w.id] |= (uint8_t)2;
+}
+
+// band: K2 (bit 2) and E1 = K1 ? n . grad E0 : 0
+template <int DIM>
+__global__ __launch_bounds__(256) void known2_un_kernel(const LsInst* __restrict__ insts,
+                                                        const int* __restrict__ off, int count) {
+  const Where w = locate<DIM>(insts, off, count, true);
+  if (!w.in) return;
+  const LsInst& I = *w.I;
+  const bool k1 = (glb((const uint8_t*)I.known)[w.id] >> 1) & 1;
+  if (known_all<DIM>(I, w, 1)) glb(I.known)[w.id] |= (uint8_t)4;
+  arr(I, A_E1)[w.id] = k1 ? dir_deriv<DIM>(I, w, arr(I, A_E0)) : 0.0;
+}
+
+// band: E2 = K2 ? n . grad E1 : 0
+template <int DIM>
+__global__ __launch_bounds__(256) void unn_kernel(const LsInst* __restrict__ insts, const int* __restrict__ off,
+                                                  int count) {
+  const Where w = locate<DIM>(insts, off, count, true);
+  if (!w.in) return;
+  const LsInst& I = *w.I;
+  const bool k2 = (glb((const uint8_t*)I.known)[w.id] >> 2) & 1;
+  arr(I, A_E2)[w.id] = k2 ? dir_deriv<DIM>(I, w, arr(I, A_E1)) : 0.0;
+}
+
+// band: one Jacobi sweep out = v - dtau (a.grad v - src) off the known set
+// (bit), a = sgn * n, sgn = 1 or sign(rho) (speed extension); with
+// do_max, also the instance's maximum of out (non-negative values).
+template <int DIM>
+__global__ __launch_bounds__(256) void extend_kernel(const LsInst* __restrict__ insts, const int* __restrict__ off,
+                                                     int count, int v_arr, int out_arr, int src_arr, int bit,
+                                                     int sign_rho, int do_max) {
+  const Where w = locate<DIM>(insts, off, count, true);
+  const LsInst& I = *w.I;
+  double res = 0.0;
+  if (w.in) {
+    gptr<const double> v = arr(I, v_arr);
+    const double vc = v[w.id];
+    if ((glb((const uint8_t*)I.known)[w.id] >> bit) & 1) {
+      res = vc;
     } else {
-      known[id] &= (uint8_t)~8u;
+      double sg = 1.0;
+      if (sign_rho) {
+        const double r = glb((const double*)I.rho)[w.id];
+        sg = (r > 0.0) ? 1.0 : ((r < 0.0) ? -1.0 : 0.0);
+      }
+      double up = 0.0;
+      for (int d = 0; d < DIM; ++d) {
+        const double a = sg * arr(I, A_NX + d)[w.id];
+        up += fmax(a, 0.0) * (vc - v[shifted(I, w, d, -1)]) + fmin(a, 0.0) * (v[shifted(I, w, d, 1)] - vc);
+      }
+      up = up / I.h;
+      const double s = (src_arr >= 0) ? arr(I, src_arr)[w.id] : 0.0;
+      res = vc - (0.5 * I.h) * (up - s);
     }
-    V[id] = v;
+    arr(I, out_arr)[w.id] = res;
   }
-}
-
-__global__ void max_kernel(LB b, const double* __restrict__ V, double* __restrict__ out) {
-  __shared__ double sm[256];
-  double m = 0.0;
-  GRID_LOOP(b) { m = fmax(m, V[id]); }
-  sm[threadIdx.x] = m;
-  __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if (threadIdx.x < s) sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + s]);
+  if (do_max) {
+    __shared__ double sm[256];
+    sm[threadIdx.x] = w.in ? res : 0.0;
     __syncthreads();
-  }
-  if (threadIdx.x == 0) {
+    for (int s = 128; s > 0; s >>= 1) {
+      if ((int)threadIdx.x < s) sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + s]);
+      __syncthreads();
+    }
     // max of non-negative doubles: integer order equals value order
-    atomicMax((unsigned long long*)out, (unsigned long long)__double_as_longlong(sm[0]));
+    if (threadIdx.x == 0)
+      atomicMax((unsigned long long*)I.vmax, (unsigned long long)__double_as_longlong(sm[0]));
   }
 }
 
-__global__ void zero_kernel(double* p) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) *p = 0.0;
+// band: V = (|rho| < h) ? mu |central grad u_ext| : 0; speed band into bit 3
+template <int DIM>
+__global__ __launch_bounds__(256) void velocity_kernel(const LsInst* __restrict__ insts,
+                                                       const int* __restrict__ off, int count, int uext_arr) {
+  const Where w = locate<DIM>(insts, off, count, true);
+  if (!w.in) return;
+  const LsInst& I = *w.I;
+  gptr<const double> ue = arr(I, uext_arr);
+  gptr<uint8_t> kn = glb(I.known);
+  const bool band = fabs(glb((const double*)I.rho)[w.id]) < I.h;
+  double v = 0.0;
+  if (band) {
+    double s = 0.0;
+    for (int d = 0; d < DIM; ++d) {
+      const double g = (ue[shifted(I, w, d, 1)] - ue[shifted(I, w, d, -1)]) / (2.0 * I.h);
+      s += g * g;
+    }
+    v = I.mu * sqrt(s);
+    kn[w.id] |= (uint8_t)8;
+  } else {
+    kn[w.id] &= (uint8_t)~8u;
+  }
+  arr(I, A_V)[w.id] = v;
 }
+
+// ------------------------------------------------------------ Step 2: WENO
 
 __device__ __forceinline__ double weno5(double v1, double v2, double v3, double v4, double v5) {
   const double p1 = v1 / 3.0 - 7.0 * v2 / 6.0 + 11.0 * v3 / 6.0;
@@ -220,13 +270,14 @@ __device__ __forceinline__ double weno5(double v1, double v2, double v3, double 
 }
 
 // Godunov |grad phi| for speed sign sg (+1 / -1 / 0), HJ-WENO5 derivatives
-__device__ double godunov(const LB& b, const double* __restrict__ phi, int i, int j, int k, double sg) {
+template <int DIM>
+__device__ double godunov(const LsInst& I, const Where& w, gptr<const double> phi, double sg) {
   double accp = 0.0, accn = 0.0;
-  for (int d = 0; d < b.dim; ++d) {
+  for (int d = 0; d < DIM; ++d) {
     double f[7];
-    for (int s = -3; s <= 3; ++s) f[s + 3] = at(b, phi, i, j, k, d, s);
+    for (int s = -3; s <= 3; ++s) f[s + 3] = phi[shifted(I, w, d, s)];
     double dd[6];
-    for (int q = 0; q < 6; ++q) dd[q] = (f[q + 1] - f[q]) / b.h;
+    for (int q = 0; q < 6; ++q) dd[q] = (f[q + 1] - f[q]) / I.h;
     const double dm = weno5(dd[0], dd[1], dd[2], dd[3], dd[4]);
     const double dp = weno5(dd[5], dd[4], dd[3], dd[2], dd[1]);
     const double a = fmax(dm, 0.0), bb = fmin(dp, 0.0);
@@ -239,198 +290,230 @@ __device__ double godunov(const LB& b, const double* __restrict__ phi, int i, in
   return 0.0;
 }
 
-// TVD-RK3 stage: out = c0 * base + c1 * (in - dt * L(in)), with
-// L = V G(in) (advection, S == nullptr) or S (G_sign(S)(in) - 1) (reinit)
-__global__ void rk_stage_kernel(LB b, const double* __restrict__ base, const double* __restrict__ in,
-                                double* __restrict__ out, const double* __restrict__ V,
-                                const double* __restrict__ S, double dt, double c0, double c1) {
-  GRID_LOOP(b) {
-    int i, j, k;
-    coords(b, id, i, j, k);
-    double L;
-    if (S) {
-      const double s = S[id];
-      const double sg = (s > 0.0) ? 1.0 : ((s < 0.0) ? -1.0 : 0.0);
-      L = s * (godunov(b, in, i, j, k, sg) - 1.0);
-    } else {
-      L = V[id] * godunov(b, in, i, j, k, 1.0);
+// Substeps of the advection of an instance (the host takes the same
+// formula on the same maximum speed).
+__device__ __forceinline__ int substeps(const LsInst& I, double dt) {
+  int n = (int)ceil(*glb((const double*)I.vmax) * dt / (0.5 * I.h));
+  return n < 1 ? 1 : n;
+}
+
+// One TVD-RK3 stage (1, 2, 3): out = c0 * R0 + c1 * (in - dt * L(in)) with
+// stage 1: in = rho, out = R1 (and R0 = rho); stage 2: in = R1, out = R2;
+// stage 3: in = R2, out = rho; L = V G(in) (advection, band launch, speed 0
+// gives L = 0) or S (G_sign(S)(in) - 1) (reinitialisation, whole box;
+// first != 0 computes S from rho).  Advection substep q runs only for
+// instances with more than q substeps.
+template <int DIM>
+__global__ __launch_bounds__(256) void rk_kernel(const LsInst* __restrict__ insts, const int* __restrict__ off,
+                                                 int count, int reinit, int stage, int q, double dt, int first) {
+  const Where w = locate<DIM>(insts, off, count, !reinit);
+  if (!w.in) return;
+  const LsInst& I = *w.I;
+  double step;
+  if (reinit) {
+    step = 0.5 * I.h;
+  } else {
+    const int ns = substeps(I, dt);
+    if (q >= ns) return;
+    step = dt / ns;
+  }
+  gptr<double> rho = glb(I.rho);
+  gptr<const double> in = (stage == 1) ? (gptr<const double>)rho : arr(I, stage == 2 ? A_R1 : A_R2);
+  double L;
+  if (reinit) {
+    if (first) {
+      const double r = rho[w.id];
+      arr(I, A_S)[w.id] = r / sqrt(r * r + I.h * I.h);
     }
-    const double stage = in[id] - dt * L;
-    out[id] = (c0 == 0.0) ? stage : c0 * base[id] + c1 * stage;
+    const double s = arr(I, A_S)[w.id];
+    const double sg = (s > 0.0) ? 1.0 : ((s < 0.0) ? -1.0 : 0.0);
+    L = s * (godunov<DIM>(I, w, in, sg) - 1.0);
+  } else {
+    const double V = arr(I, A_V)[w.id];
+    L = (V != 0.0) ? V * godunov<DIM>(I, w, in, 1.0) : 0.0;
+  }
+  const double cur = in[w.id];
+  const double st = cur - step * L;
+  if (stage == 1) {
+    arr(I, A_R0)[w.id] = cur;
+    arr(I, A_R1)[w.id] = st;
+  } else if (stage == 2) {
+    arr(I, A_R2)[w.id] = 0.75 * arr(I, A_R0)[w.id] + 0.25 * st;
+  } else {
+    rho[w.id] = (1.0 / 3.0) * arr(I, A_R0)[w.id] + (2.0 / 3.0) * st;
   }
 }
 
-__global__ void sign_kernel(LB b, const double* __restrict__ rho, double* __restrict__ S) {
-  GRID_LOOP(b) {
-    const double r = rho[id];
-    S[id] = r / sqrt(r * r + b.h * b.h);
+// whole box: u = comp(rho_new) ? u_ext : 0
+template <int DIM>
+__global__ __launch_bounds__(256) void restrict_kernel(const LsInst* __restrict__ insts,
+                                                       const int* __restrict__ off, int count, int uext_arr) {
+  const Where w = locate<DIM>(insts, off, count, false);
+  if (!w.in) return;
+  const LsInst& I = *w.I;
+  const bool c = comp_point<DIM>(I, w, glb((const double*)I.rho));
+  glb(I.u)[w.id] = c ? arr(I, uext_arr)[w.id] : 0.0;
+}
+
+template <int DIM>
+hipError_t begin_dim(LevelsetBatch& b, hipStream_t st) {
+  const int n = b.count;
+  const LsInst* I = b.d_inst;
+  const int* off = b.d_off;
+  const dim3 B(256);
+  const dim3 GB(b.total_band), GF(b.total_full);
+#define LB(kernel, ...)                                                        \
+  do {                                                                         \
+    if (b.total_band > 0) {                                                    \
+      hipLaunchKernelGGL(kernel<DIM>, GB, B, 0, st, I, off, n, ##__VA_ARGS__); \
+      hipError_t _e = hipGetLastError();                                       \
+      if (_e != hipSuccess) return _e;                                         \
+    }                                                                          \
+  } while (0)
+  hipLaunchKernelGGL(zero_kernel<DIM>, GF, B, 0, st, I, off, n);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  LB(init_kernel);
+  LB(known1_kernel);
+  LB(known2_un_kernel);
+  LB(unn_kernel);
+  // Aslam: u_nn (E2, ping-pong E3), u_n (E1, src u_nn), u (E0, src u_n); the
+  // results move through the free arrays (ASLAM_ITERS is odd)
+  int v = A_E2, t = A_E3;
+  for (int it = 0; it < ASLAM_ITERS; ++it) {
+    LB(extend_kernel, v, t, -1, 2, 0, 0);
+    const int x = v; v = t; t = x;
   }
-}
-
-__global__ void copy_kernel(LB b, const double* __restrict__ src, double* __restrict__ dst) {
-  GRID_LOOP(b) { dst[id] = src[id]; }
-}
-
-// u = comp(rho_new) ? u_ext : 0
-__global__ void restrict_kernel(LB b, const double* __restrict__ rho, const double* __restrict__ uext,
-                                double* __restrict__ u) {
-  GRID_LOOP(b) {
-    int i, j, k;
-    coords(b, id, i, j, k);
-    bool c = rho[id] < 0.0;
-    if (c) {
-      if (i == 0 || i == b.nx - 1 || j == 0 || j == b.ny - 1) c = false;
-      if (b.dim == 3 && (k == 0 || k == b.nz - 1)) c = false;
-    }
-    if (c)
-      for (int d = 0; d < b.dim && c; ++d)
-        c = at(b, rho, i, j, k, d, -1) < 0.0 && at(b, rho, i, j, k, d, 1) < 0.0;
-    u[id] = c ? uext[id] : 0.0;
+  const int unn = v;
+  v = A_E1;
+  t = (unn == A_E3) ? A_E2 : A_E3;
+  for (int it = 0; it < ASLAM_ITERS; ++it) {
+    LB(extend_kernel, v, t, unn, 1, 0, 0);
+    const int x = v; v = t; t = x;
   }
+  const int un = v;
+  v = A_E0;
+  t = (un == A_E1) ? A_E2 : A_E1;
+  if (t == unn) t = A_E3;
+  for (int it = 0; it < ASLAM_ITERS; ++it) {
+    LB(extend_kernel, v, t, un, 0, 0, 0);
+    const int x = v; v = t; t = x;
+  }
+  b.uext = v;
+  // Stefan speed, extension (even count: ends in V), maximum on the last sweep
+  LB(velocity_kernel, b.uext);
+  v = A_V;
+  t = (b.uext == A_E0) ? A_E1 : A_E0;
+  for (int it = 0; it < VEL_ITERS; ++it) {
+    LB(extend_kernel, v, t, -1, 3, 1, it == VEL_ITERS - 1 ? 1 : 0);
+    const int x = v; v = t; t = x;
+  }
+#undef LB
+  return hipSuccess;
 }
 
-int grid_for(size_t n) {
-  size_t g = (n + 255) / 256;
-  if (g > 8192) g = 8192;
-  return (int)(g < 1 ? 1 : g);
+template <int DIM>
+hipError_t end_dim(LevelsetBatch& b, hipStream_t st) {
+  const int n = b.count;
+  const LsInst* I = b.d_inst;
+  const int* off = b.d_off;
+  const dim3 B(256);
+  int nsub = 1;
+  for (int i = 0; i < n; ++i) {
+    int ns = (int)ceil(b.h_vmax[i] * b.dt / (0.5 * b.h_inst[i].h));
+    if (ns < 1) ns = 1;
+    if (ns > nsub) nsub = ns;
+  }
+  hipError_t e;
+  if (b.total_band > 0) {
+    for (int q = 0; q < nsub; ++q)
+      for (int s = 1; s <= 3; ++s) {
+        hipLaunchKernelGGL(rk_kernel<DIM>, dim3(b.total_band), B, 0, st, I, off, n, 0, s, q, b.dt, 0);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+      }
+  }
+  if (b.reinit) {
+    for (int it = 0; it < REINIT_ITERS; ++it)
+      for (int s = 1; s <= 3; ++s) {
+        hipLaunchKernelGGL(rk_kernel<DIM>, dim3(b.total_full), B, 0, st, I, off, n, 1, s, 0, 0.0,
+                           (it == 0 && s == 1) ? 1 : 0);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+      }
+  }
+  hipLaunchKernelGGL(restrict_kernel<DIM>, dim3(b.total_full), B, 0, st, I, off, n, b.uext);
+  return hipGetLastError();
 }
 
 }  // namespace
 
 hipError_t levelset_alloc(LevelsetScratch& s, size_t nodes) {
   s.nodes = nodes;
-  hipError_t e = hipMalloc(&s.buf, sizeof(double) * nodes * 12);
+  hipError_t e = hipMalloc(&s.buf, sizeof(double) * nodes * A_COUNT);
   if (e != hipSuccess) return e;
   e = hipMalloc(&s.known, nodes);
   if (e != hipSuccess) return e;
-  e = hipMalloc(&s.vmax, sizeof(double));
-  if (e != hipSuccess) return e;
-  return hipHostMalloc(&s.h_vmax, sizeof(double));
+  return hipMemset(s.known, 0, nodes);
 }
 
 void levelset_free(LevelsetScratch& s) {
   if (s.buf) (void)hipFree(s.buf);
   if (s.known) (void)hipFree(s.known);
-  if (s.vmax) (void)hipFree(s.vmax);
-  if (s.h_vmax) (void)hipHostFree(s.h_vmax);
   s = LevelsetScratch{};
 }
 
-// Box arrays of the level-set scratch.
-struct LsBufs {
-  double *nx, *ny, *nz, *u0, *un, *unn, *tmp, *V, *r1, *r2, *Sg, *r0;
-  explicit LsBufs(const LevelsetScratch& s) {
-    double* p[12];
-    for (int i = 0; i < 12; ++i) p[i] = s.buf + (size_t)i * s.nodes;
-    nx = p[0]; ny = p[1]; nz = p[2];
-    u0 = p[3];   // u (extended)
-    un = p[4]; unn = p[5]; tmp = p[6]; V = p[7];
-    r1 = p[8]; r2 = p[9]; Sg = p[10]; r0 = p[11];
-  }
-};
-
-#define L(kernel, ...)                                            \
-  do {                                                            \
-    hipLaunchKernelGGL(kernel, dim3(G), B, 0, st, __VA_ARGS__);   \
-    hipError_t _e = hipGetLastError();                            \
-    if (_e != hipSuccess) return _e;                              \
-  } while (0)
-
-// Steps 1 up to the maximum speed: normals, known sets, Aslam extrapolation,
-// Stefan speed and its extension; max V is copied (asynchronously) to the
-// pinned host word s.h_vmax.
-hipError_t levelset_begin(const LevelsetArgs& a, LevelsetScratch& s, double* rho, double* u,
-                          hipStream_t st) {
-  LB b{a.box.dim, a.box.nx, a.box.ny, a.box.nz, a.box.dx};
-  const LsBufs q(s);
-  const int G = grid_for(s.nodes);
-  const dim3 B(256);
-  // normals and known sets of the current domain
-  L(normals_kernel, b, rho, q.nx, q.ny, q.nz);
-  L(known0_kernel, b, rho, u, s.known, q.u0);
-  L(known_next_kernel, b, s.known, 0, 1);
-  L(known_next_kernel, b, s.known, 1, 2);
-  L(central_dir_kernel, b, q.u0, q.nx, q.ny, q.nz, s.known, 1, q.un);
-  L(central_dir_kernel, b, q.un, q.nx, q.ny, q.nz, s.known, 2, q.unn);
-  // Aslam: u_nn, u_n, u (ping-pong through tmp)
-  auto extend = [&](double* v, const double* src, int bit, int iters) -> hipError_t {
-    double* x = v;
-    double* y = q.tmp;
-    for (int it = 0; it < iters; ++it) {
-      hipLaunchKernelGGL(extend_kernel, dim3(G), B, 0, st, b, x, y, q.nx, q.ny, q.nz, src, s.known, bit,
-                         (const double*)nullptr);
-      hipError_t e = hipGetLastError();
-      if (e != hipSuccess) return e;
-      double* t = x; x = y; y = t;
-    }
-    if (x != v) {
-      hipLaunchKernelGGL(copy_kernel, dim3(G), B, 0, st, b, x, v);
-      return hipGetLastError();
-    }
-    return hipSuccess;
-  };
+hipError_t levelset_batch_alloc(LevelsetBatch& b, int count, int dim) {
+  b.count = count;
+  b.dim = dim;
   hipError_t e;
-  if ((e = extend(q.unn, nullptr, 2, ASLAM_ITERS)) != hipSuccess) return e;
-  if ((e = extend(q.un, q.unn, 1, ASLAM_ITERS)) != hipSuccess) return e;
-  if ((e = extend(q.u0, q.un, 0, ASLAM_ITERS)) != hipSuccess) return e;
-  // Stefan speed on the band, then constant extension along sign(rho) n
-  L(velocity_kernel, b, q.u0, rho, a.mu, s.known, q.V);
-  {
-    double* x = q.V;
-    double* y = q.tmp;
-    for (int it = 0; it < VEL_ITERS; ++it) {
-      L(extend_kernel, b, x, y, q.nx, q.ny, q.nz, (const double*)nullptr, s.known, 3, (const double*)rho);
-      double* t = x; x = y; y = t;
-    }
-    if (x != q.V) L(copy_kernel, b, x, q.V);
-  }
-  // number of advection substeps from max V (one readback)
-  hipLaunchKernelGGL(zero_kernel, dim3(1), dim3(64), 0, st, s.vmax);
-  L(max_kernel, b, q.V, s.vmax);
-  if ((e = hipMemcpyAsync(s.h_vmax, s.vmax, sizeof(double), hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
+  if ((e = hipMalloc(&b.d_inst, sizeof(LsInst) * count)) != hipSuccess) return e;
+  if ((e = hipHostMalloc(&b.h_inst, sizeof(LsInst) * count)) != hipSuccess) return e;
+  if ((e = hipMalloc(&b.d_off, sizeof(int) * 2 * (count + 1))) != hipSuccess) return e;
+  if ((e = hipHostMalloc(&b.h_off, sizeof(int) * 2 * (count + 1))) != hipSuccess) return e;
+  if ((e = hipMalloc(&b.d_vmax, sizeof(double) * count)) != hipSuccess) return e;
+  if ((e = hipHostMalloc(&b.h_vmax, sizeof(double) * count)) != hipSuccess) return e;
+  for (int i = 0; i < count; ++i) b.h_inst[i] = LsInst{};
   return hipSuccess;
 }
 
-// The rest of the step (the caller has synchronised the stream, so s.h_vmax
-// holds max V): advection substeps, reinitialisation, restriction of u.
-hipError_t levelset_end(const LevelsetArgs& a, LevelsetScratch& s, double* rho, double* u,
-                        hipStream_t st) {
-  LB b{a.box.dim, a.box.nx, a.box.ny, a.box.nz, a.box.dx};
-  const LsBufs q(s);
-  const int G = grid_for(s.nodes);
-  const dim3 B(256);
-  const double vmax = *s.h_vmax;
-  int nsub = (int)ceil(vmax * a.dt / (0.5 * b.h));
-  if (nsub < 1) nsub = 1;
-  const double ds = a.dt / nsub;
-  // TVD-RK3 advection; rho (user array) is the running state
-  for (int it = 0; it < nsub; ++it) {
-    L(copy_kernel, b, rho, q.r0);
-    L(rk_stage_kernel, b, q.r0, q.r0, q.r1, q.V, (const double*)nullptr, ds, 0.0, 1.0);
-    L(rk_stage_kernel, b, q.r0, q.r1, q.r2, q.V, (const double*)nullptr, ds, 0.75, 0.25);
-    L(rk_stage_kernel, b, q.r0, q.r2, rho, q.V, (const double*)nullptr, ds, 1.0 / 3.0, 2.0 / 3.0);
-  }
-  if (a.reinit) {
-    L(sign_kernel, b, rho, q.Sg);
-    const double dtau = 0.5 * b.h;
-    for (int it = 0; it < REINIT_ITERS; ++it) {
-      L(copy_kernel, b, rho, q.r0);
-      L(rk_stage_kernel, b, q.r0, q.r0, q.r1, (const double*)nullptr, q.Sg, dtau, 0.0, 1.0);
-      L(rk_stage_kernel, b, q.r0, q.r1, q.r2, (const double*)nullptr, q.Sg, dtau, 0.75, 0.25);
-      L(rk_stage_kernel, b, q.r0, q.r2, rho, (const double*)nullptr, q.Sg, dtau, 1.0 / 3.0, 2.0 / 3.0);
-    }
-  }
-  L(restrict_kernel, b, rho, q.u0, u);
-  return hipSuccess;
+void levelset_batch_free(LevelsetBatch& b) {
+  if (b.d_inst) (void)hipFree(b.d_inst);
+  if (b.h_inst) (void)hipHostFree(b.h_inst);
+  if (b.d_off) (void)hipFree(b.d_off);
+  if (b.h_off) (void)hipHostFree(b.h_off);
+  if (b.d_vmax) (void)hipFree(b.d_vmax);
+  if (b.h_vmax) (void)hipHostFree(b.h_vmax);
+  b = LevelsetBatch{};
 }
-#undef L
 
-hipError_t levelset_run(const LevelsetArgs& a, LevelsetScratch& s, double* rho, double* u,
-                        hipStream_t st) {
-  hipError_t e = levelset_begin(a, s, rho, u, st);
+hipError_t levelset_begin(LevelsetBatch& b, double dt, int reinit, hipStream_t st) {
+  const int n = b.count;
+  b.dt = dt;
+  b.reinit = reinit;
+  int band = 0, full = 0;
+  for (int i = 0; i < n; ++i) {
+    LsInst& I = b.h_inst[i];
+    I.vmax = b.d_vmax + i;
+    b.h_off[i] = band;
+    b.h_off[n + 1 + i] = full;
+    band += I.nband;
+    full += I.ntx * I.nty * I.ntz;
+  }
+  b.h_off[n] = band;
+  b.h_off[2 * n + 1] = full;
+  b.total_band = band;
+  b.total_full = full;
+  hipError_t e;
+  if ((e = hipMemcpyAsync(b.d_inst, b.h_inst, sizeof(LsInst) * n, hipMemcpyHostToDevice, st)) != hipSuccess)
+    return e;
+  if ((e = hipMemcpyAsync(b.d_off, b.h_off, sizeof(int) * 2 * (n + 1), hipMemcpyHostToDevice, st)) != hipSuccess)
+    return e;
+  e = (b.dim == 2) ? begin_dim<2>(b, st) : begin_dim<3>(b, st);
   if (e != hipSuccess) return e;
-  if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
-  return levelset_end(a, s, rho, u, st);
+  return hipMemcpyAsync(b.h_vmax, b.d_vmax, sizeof(double) * n, hipMemcpyDeviceToHost, st);
+}
+
+hipError_t levelset_end(LevelsetBatch& b, hipStream_t st) {
+  return (b.dim == 2) ? end_dim<2>(b, st) : end_dim<3>(b, st);
 }
 
 }  // namespace etdfb
