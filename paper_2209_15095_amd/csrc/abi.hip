@@ -15,6 +15,8 @@
 
 using namespace etdfb;
 
+constexpr int NCOUNTERS = 16;   // device counters of a context (see etd_ctx::counters)
+
 struct etd_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
@@ -35,9 +37,10 @@ struct etd_ctx {
   double* cdiag = nullptr;
   int* nbr = nullptr;        // face-neighbour slots, NBR_STRIDE per slot
   int* tile_vb = nullptr;    // tiles with a node |rho| < h
-  int* band_tmp = nullptr;   // 3 * ntiles: dilation passes and map
-  int* band_list = nullptr;  // level-set band tiles
-  int* counters = nullptr;   // [0] n_active, [1] status, [2..3] case counts, [4] unknowns, [5] band tiles
+  int* band_tmp = nullptr;   // 2 * ntiles: tile distance passes
+  int* band_list = nullptr;  // level-set tile lists, LS_NLIST * ntiles
+  int* counters = nullptr;   // [0] n_active, [1] status, [2..3] case counts, [4] unknowns,
+                             // [8..8+LS_NLIST) level-set list sizes
   // persistent kernel state
   double* ws = nullptr;
   double* part = nullptr;
@@ -53,7 +56,7 @@ struct etd_ctx {
   // level-set scratch (box arrays) and its one-instance table
   LevelsetScratch ls{};
   LevelsetBatch lsb{};
-  int nband_host = 0;
+  int nband_host[LS_NLIST] = {};
   // pinned host mirror for small readbacks
   int* h_counters = nullptr;
   KrylovStateDev* h_state = nullptr;
@@ -213,7 +216,7 @@ int scatter_from(etd_ctx* c, int vec, double* box) {
 }
 
 int fill_stats(etd_ctx* c, etd_stats* s) {
-  HIP_TRY(hipMemcpyAsync(c->h_counters, c->counters, 8 * sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipMemcpyAsync(c->h_counters, c->counters, NCOUNTERS * sizeof(int), hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(hipMemcpyAsync(c->h_state, c->st, sizeof(KrylovStateDev), hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(hipStreamSynchronize(c->stream));
   s->substeps = c->h_state->substeps;
@@ -254,17 +257,18 @@ int geometry_enqueue(etd_ctx* c, const double* rho) {
   HIP_TRY(launch_scan_tiles(c->tile_flag, c->ntiles, c->tile_map, c->slot_tile, c->counters + 0, c->stream));
   HIP_TRY(launch_tile_coeff(c->box, rho, c->mask, c->tile_map, c->comp_bits, c->irr_bits, c->cdiag,
                             c->nbr, c->counters + 2, c->ntiles, c->stream));
-  HIP_TRY(launch_band(c->box, c->tile_flag, c->tile_vb, BAND_ASLAM, BAND_SPEED, c->band_tmp,
-                      c->band_tmp + c->ntiles, c->band_tmp + 2 * (size_t)c->ntiles, c->band_list, c->counters + 5,
-                      c->stream));
+  static const int radii[5] = {ASLAM_ITERS + 1, 2 * ASLAM_ITERS + 1, 3 * ASLAM_ITERS + 1, VEL_ITERS + 1,
+                               VEL_ITERS + 4};
+  HIP_TRY(launch_band(c->box, c->tile_flag, c->tile_vb, radii, c->band_tmp, c->band_tmp + c->ntiles,
+                      c->band_list, c->counters + 8, c->stream));
   HIP_TRY(timer_end(c->profiling, c->stream, c->t_geometry));
-  HIP_TRY(hipMemcpyAsync(c->h_counters, c->counters, 8 * sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipMemcpyAsync(c->h_counters, c->counters, NCOUNTERS * sizeof(int), hipMemcpyDeviceToHost, c->stream));
   return ETD_OK;
 }
 
 int geometry_finish(etd_ctx* c) {
   c->n_active_host = c->h_counters[0];
-  c->nband_host = c->h_counters[5];
+  for (int q = 0; q < LS_NLIST; ++q) c->nband_host[q] = c->h_counters[8 + q];
   choose_launch(c);
   c->have_geometry = true;
   if (c->h_counters[1] == ST_DOMAIN) {
@@ -282,7 +286,7 @@ LsInst levelset_inst(const etd_ctx* c, double* rho, double* u) {
   I.dim = c->box.dim;
   I.nx = c->box.nx; I.ny = c->box.ny; I.nz = c->box.nz;
   I.ntx = c->box.ntx; I.nty = c->box.nty; I.ntz = c->box.ntz;
-  I.nband = c->nband_host;
+  for (int q = 0; q < LS_NLIST; ++q) I.nband[q] = c->nband_host[q];
   I.h = c->box.dx;
   I.mu = c->phys.mu;
   I.rho = rho;
@@ -387,15 +391,15 @@ int etd_ctx_create(const etd_grid* grid, const etd_physics* phys, const etd_kryl
   ok &= hipMalloc(&c->cdiag, sizeof(double) * c->ld) == hipSuccess;
   ok &= hipMalloc(&c->nbr, sizeof(int) * NBR_STRIDE * (size_t)c->ntiles) == hipSuccess;
   ok &= hipMalloc(&c->tile_vb, sizeof(int) * (size_t)c->ntiles) == hipSuccess;
-  ok &= hipMalloc(&c->band_tmp, sizeof(int) * 3 * (size_t)c->ntiles) == hipSuccess;
-  ok &= hipMalloc(&c->band_list, sizeof(int) * (size_t)c->ntiles) == hipSuccess;
-  ok &= hipMalloc(&c->counters, sizeof(int) * 8) == hipSuccess;
+  ok &= hipMalloc(&c->band_tmp, sizeof(int) * 2 * (size_t)c->ntiles) == hipSuccess;
+  ok &= hipMalloc(&c->band_list, sizeof(int) * LS_NLIST * (size_t)c->ntiles) == hipSuccess;
+  ok &= hipMalloc(&c->counters, sizeof(int) * NCOUNTERS) == hipSuccess;
   ok &= hipMalloc(&c->ws, sizeof(double) * c->ld * NVEC) == hipSuccess;
   ok &= hipMalloc(&c->part, sizeof(double) * 2 * (size_t)c->max_grid * PART_STRIDE) == hipSuccess;
   ok &= hipMalloc(&c->flags, sizeof(unsigned) * (size_t)c->max_grid) == hipSuccess;
   ok &= hipMalloc(&c->bar, sizeof(BarrierDev)) == hipSuccess;
   ok &= hipMalloc(&c->st, sizeof(KrylovStateDev)) == hipSuccess;
-  ok &= hipHostMalloc(&c->h_counters, sizeof(int) * 8) == hipSuccess;
+  ok &= hipHostMalloc(&c->h_counters, sizeof(int) * NCOUNTERS) == hipSuccess;
   ok &= hipHostMalloc(&c->h_state, sizeof(KrylovStateDev)) == hipSuccess;
   ok &= levelset_alloc(c->ls, c->nodes) == hipSuccess;
   ok &= levelset_batch_alloc(c->lsb, 1, b.dim) == hipSuccess;
@@ -409,7 +413,7 @@ int etd_ctx_create(const etd_grid* grid, const etd_physics* phys, const etd_kryl
     s0.m_guess[k] = o.m_min;
     s0.tau_frac[k] = 1.0;
   }
-  int zeros[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  int zeros[NCOUNTERS] = {};
   ok &= hipMemcpy(c->st, &s0, sizeof(s0), hipMemcpyHostToDevice) == hipSuccess;
   ok &= hipMemcpy(c->counters, zeros, sizeof(zeros), hipMemcpyHostToDevice) == hipSuccess;
   ok &= hipMemset(c->ws, 0, sizeof(double) * c->ld * NVEC) == hipSuccess;
@@ -568,7 +572,7 @@ int etd_ctx_profile_enable(etd_ctx* c, int32_t enable) {
 int etd_ctx_profile_read(etd_ctx* c, etd_profile* out, int32_t reset) {
   if (!c || !out) return ETD_ERR_INVALID;
   HIP_TRY(hipMemcpyAsync(c->h_state, c->st, sizeof(KrylovStateDev), hipMemcpyDeviceToHost, c->stream));
-  HIP_TRY(hipMemcpyAsync(c->h_counters, c->counters, 8 * sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipMemcpyAsync(c->h_counters, c->counters, NCOUNTERS * sizeof(int), hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(hipStreamSynchronize(c->stream));
   HIP_TRY(timer_collect(c->t_krylov));
   HIP_TRY(timer_collect(c->t_levelset));
@@ -830,7 +834,7 @@ int etd_batch_profile_read(etd_batch* B, etd_profile* out, int32_t reset) {
   if (!B || !out) return ETD_ERR_INVALID;
   for (etd_ctx* c : B->inst) {
     HIP_TRY(hipMemcpyAsync(c->h_state, c->st, sizeof(KrylovStateDev), hipMemcpyDeviceToHost, B->stream));
-    HIP_TRY(hipMemcpyAsync(c->h_counters, c->counters, 8 * sizeof(int), hipMemcpyDeviceToHost, B->stream));
+    HIP_TRY(hipMemcpyAsync(c->h_counters, c->counters, NCOUNTERS * sizeof(int), hipMemcpyDeviceToHost, B->stream));
   }
   HIP_TRY(hipStreamSynchronize(B->stream));
   HIP_TRY(timer_collect(B->t_krylov));

@@ -121,30 +121,92 @@ __global__ __launch_bounds__(1024) void scan_tiles_kernel(const int* __restrict_
   if (threadIdx.x == 0) *n_active = carry;
 }
 
-// Narrow band of the level-set sweeps, one axis of a separable dilation on
-// the tile grid: bit 0 spreads `ra` tiles from tiles with a computational
-// point, bit 1 spreads `rv` tiles from tiles with a speed-band node.  The
-// first pass (axis 0) reads the two flag arrays, later passes the bits.
-__global__ void band_dilate_kernel(BoxDev b, const int* __restrict__ comp_flag, const int* __restrict__ vb_flag,
-                                   const int* __restrict__ in, int* __restrict__ out, int axis, int ra, int rv) {
+// L1 distances on the tile grid (level-set bands), one axis of a separable
+// min-plus transform: the node gap between tiles k apart along an axis of
+// tile extent t is (k-1) t + 1 (0 for k = 0).  Packed per tile: distance
+// from a tile with a computational point in the low 16 bits, from a tile
+// with a node |rho| < h in the high 16 bits; the first pass (axis 0) starts
+// from the two flag arrays.
+__global__ void band_dist_kernel(BoxDev b, const int* __restrict__ comp_flag, const int* __restrict__ vb_flag,
+                                 const int* __restrict__ in, int* __restrict__ out, int axis, int r, int cap) {
   const int ntiles = b.ntx * b.nty * b.ntz;
   const int n[3] = {b.ntx, b.nty, b.ntz};
-  const int r = ra > rv ? ra : rv;
+  const int text[3] = {b.tx, b.ty, b.tz};
   for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < ntiles; t += gridDim.x * blockDim.x) {
     int c[3] = {t % b.ntx, (t / b.ntx) % b.nty, t / (b.ntx * b.nty)};
     const int c0 = c[axis];
-    int bits = 0;
+    int dc = cap, dv = cap;
     for (int d = -r; d <= r; ++d) {
       const int x = c0 + d;
       if (x < 0 || x >= n[axis]) continue;
       c[axis] = x;
       const int tn = (c[2] * b.nty + c[1]) * b.ntx + c[0];
-      const int src = (axis == 0) ? ((comp_flag[tn] != 0 ? 1 : 0) | (vb_flag[tn] != 0 ? 2 : 0)) : in[tn];
-      if (d >= -ra && d <= ra) bits |= src & 1;
-      if (d >= -rv && d <= rv) bits |= src & 2;
+      int sc, sv;
+      if (axis == 0) {
+        sc = comp_flag[tn] != 0 ? 0 : cap;
+        sv = vb_flag[tn] != 0 ? 0 : cap;
+      } else {
+        sc = in[tn] & 0xFFFF;
+        sv = in[tn] >> 16;
+      }
+      const int k = d < 0 ? -d : d;
+      const int gap = k == 0 ? 0 : (k - 1) * text[axis] + 1;
+      dc = min(dc, sc + gap);
+      dv = min(dv, sv + gap);
     }
-    out[t] = bits;
+    out[t] = min(dc, cap) | (min(dv, cap) << 16);
   }
+}
+
+// One block of 1024 threads: the tile lists of the level-set sweeps (in
+// tile order) from the packed distances, and their sizes.
+__global__ __launch_bounds__(1024) void band_lists_kernel(const int* __restrict__ dist, int ntiles,
+                                                          int* __restrict__ lists, int* __restrict__ counts,
+                                                          int ra1, int ra2, int ra3, int rv, int rr) {
+  constexpr int NL = 6;
+  __shared__ int wave_tot[16][NL];
+  __shared__ int carry[NL];
+  if (threadIdx.x < NL) carry[threadIdx.x] = 0;
+  __syncthreads();
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int base = 0; base < ntiles; base += 1024) {
+    const int t = base + threadIdx.x;
+    int f[NL] = {0, 0, 0, 0, 0, 0};
+    if (t < ntiles) {
+      const int dc = dist[t] & 0xFFFF, dv = dist[t] >> 16;
+      f[0] = dc <= ra1;
+      f[1] = dc <= ra2;
+      f[2] = dc <= ra3;
+      f[3] = dv <= rv;
+      f[4] = dv <= rr;
+      f[5] = f[2] || f[4];
+    }
+    int x[NL];
+    for (int q = 0; q < NL; ++q) {
+      x[q] = f[q];
+      for (int off = 1; off < 64; off <<= 1) {
+        const int y = __shfl_up(x[q], off, 64);
+        if (lane >= off) x[q] += y;
+      }
+      if (lane == 63) wave_tot[w][q] = x[q];
+    }
+    __syncthreads();
+    if (threadIdx.x < NL) {
+      int acc = 0;
+      for (int v = 0; v < 16; ++v) { const int y = wave_tot[v][threadIdx.x]; wave_tot[v][threadIdx.x] = acc; acc += y; }
+    }
+    __syncthreads();
+    int excl[NL];
+    for (int q = 0; q < NL; ++q) {
+      excl[q] = carry[q] + wave_tot[w][q] + x[q] - f[q];
+      if (t < ntiles && f[q]) lists[(size_t)q * ntiles + excl[q]] = t;
+    }
+    __syncthreads();
+    if (threadIdx.x == 1023)
+      for (int q = 0; q < NL; ++q) carry[q] = excl[q] + f[q];
+    __syncthreads();
+  }
+  if (threadIdx.x < NL) counts[threadIdx.x] = carry[threadIdx.x];
 }
 
 __device__ __forceinline__ void central_grad(const BoxDev& b, const double* __restrict__ rho, int i,
@@ -360,25 +422,25 @@ hipError_t launch_classify(const BoxHost& b, const double* rho, uint8_t* mask, i
   return hipGetLastError();
 }
 
-hipError_t launch_band(const BoxHost& b, const int* comp_flag, const int* vb_flag, int band_nodes_comp,
-                       int band_nodes_speed, int* tmp0, int* tmp1, int* band_map, int* band_list, int* nband,
-                       hipStream_t s) {
+hipError_t launch_band(const BoxHost& b, const int* comp_flag, const int* vb_flag, const int* radii, int* tmp0,
+                       int* tmp1, int* lists, int* counts, hipStream_t s) {
   const int ntiles = b.ntx * b.nty * b.ntz;
   const int t[3] = {b.tx, b.ty, b.tz};
   const BoxDev bd = to_dev(b);
+  int rmax = 0;
+  for (int q = 0; q < 5; ++q) rmax = radii[q] > rmax ? radii[q] : rmax;
   int* in = tmp0;
   int* out = tmp1;
   for (int axis = 0; axis < b.dim; ++axis) {
-    const int ra = (band_nodes_comp + t[axis] - 1) / t[axis];
-    const int rv = (band_nodes_speed + t[axis] - 1) / t[axis];
-    hipLaunchKernelGGL(band_dilate_kernel, dim3(blocks_for(ntiles, 256)), dim3(256), 0, s, bd, comp_flag,
-                       vb_flag, (const int*)in, out, axis, ra, rv);
+    const int r = (rmax - 1) / t[axis] + 1;   // tiles k apart are >= (k-1) t + 1 nodes apart
+    hipLaunchKernelGGL(band_dist_kernel, dim3(blocks_for(ntiles, 256)), dim3(256), 0, s, bd, comp_flag, vb_flag,
+                       (const int*)in, out, axis, r, 1000);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     int* x = in; in = out; out = x;
   }
-  hipLaunchKernelGGL(scan_tiles_kernel, dim3(1), dim3(1024), 0, s, (const int*)in, ntiles, band_map, band_list,
-                     nband);
+  hipLaunchKernelGGL(band_lists_kernel, dim3(1), dim3(1024), 0, s, (const int*)in, ntiles, lists, counts,
+                     radii[0], radii[1], radii[2], radii[3], radii[4]);
   return hipGetLastError();
 }
 

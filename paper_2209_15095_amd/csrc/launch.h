@@ -19,12 +19,12 @@ struct BoxHost {
 hipError_t launch_fill_int(int* p, size_t n, int v, hipStream_t s);
 hipError_t launch_classify(const BoxHost& b, const double* rho, uint8_t* mask, int* tile_flag,
                            int* tile_vb, int* status, hipStream_t s);
-// Level-set band: tiles within band_nodes_comp nodes (per axis) of a tile
-// with a computational point or band_nodes_speed nodes of a tile with a node
-// |rho| < h; list of their indices and count (device).
-hipError_t launch_band(const BoxHost& b, const int* comp_flag, const int* vb_flag, int band_nodes_comp,
-                       int band_nodes_speed, int* tmp0, int* tmp1, int* band_map, int* band_list, int* nband,
-                       hipStream_t s);
+// Level-set tile lists: L1 tile distances from the tiles with a
+// computational point and from those with a node |rho| < h, then the six
+// lists (radii[0..2] on the first distance, radii[3..4] on the second, and
+// the union of lists 2 and 4) into lists (6 * ntiles) and counts (6).
+hipError_t launch_band(const BoxHost& b, const int* comp_flag, const int* vb_flag, const int* radii, int* tmp0,
+                       int* tmp1, int* lists, int* counts, hipStream_t s);
 hipError_t launch_scan_tiles(const int* tile_flag, int ntiles, int* tile_map, int* slot_tile,
                              int* n_active, hipStream_t s);
 hipError_t launch_tile_coeff(const BoxHost& b, const double* rho, const uint8_t* mask,

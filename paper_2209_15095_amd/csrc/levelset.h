@@ -1,19 +1,23 @@
 // Level-set sweeps of the free-boundary step (Section 4.3 of the paper,
 // Algorithm Steps 1-2): host interface.
 //
-// The sweeps run on a narrow band of tiles (the tile layout of the operator:
-// 2D 32x8, 3D 16x4x4), built with the geometry: every tile within 46 nodes
-// (per axis) of a tile holding a computational point, or within 28 nodes of
-// a tile holding a node with |rho| < h.  Outside that band the extrapolated
-// u, its normal derivatives and the extended speed are exactly 0 (their
-// supports grow by one node per Jacobi sweep from the computational points:
-// 15 + 15 + 15 sweeps; the speed by 20 sweeps from |rho| < h), so the band
-// sweeps give the full-box values everywhere; the advection leaves rho
-// unchanged where the speed is 0.  Reinitialisation and the final
+// The sweeps run on bands of tiles (the tile layout of the operator: 2D
+// 32x8, 3D 16x4x4), built with the geometry from two L1 (Manhattan) tile
+// distances: from the tiles holding a computational point (Dc) and from the
+// tiles holding a node with |rho| < h (Dv); the distance between two tiles
+// is a lower bound of the node distance between them.  A Jacobi sweep
+// changes a node only where a face neighbour or its source is nonzero, so
+// the extrapolated u_nn, u_n, u are exactly 0 beyond 15, 30 and 45 nodes of
+// the computational points and the extended speed beyond 20 nodes of the
+// |rho| < h nodes: each stage sweeps only the tiles within that distance
+// plus one, and gives the whole-box values everywhere (the arrays are 0
+// elsewhere).  The advection changes rho only where the speed is nonzero and
+// reads its WENO stencil 3 nodes further.  Reinitialisation and the final
 // restriction of u cover the whole box.
 //
-// One launch per sweep serves a whole batch: block b works on band tile
-// b - off[i] of instance i, off[] being the prefix sums of the band sizes.
+// One launch per sweep serves a whole batch: block b works on tile
+// b - off[i] of the list of instance i, off[] being the prefix sums of the
+// list sizes.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -26,10 +30,18 @@ namespace etdfb {
 constexpr int ASLAM_ITERS = 15;
 constexpr int VEL_ITERS = 20;
 constexpr int REINIT_ITERS = 10;
-// Band radii in nodes (see above): 3 * ASLAM_ITERS + 1 and VEL_ITERS + 3
-// (WENO stencil) + 1, rounded up.
-constexpr int BAND_ASLAM = 46;
-constexpr int BAND_SPEED = 28;
+// Tile lists of a sweep (radii in nodes, see above).
+enum LsList {
+  LS_A1 = 0,    // Dc <= ASLAM_ITERS + 1: u_nn sweeps, known sets
+  LS_A2 = 1,    // Dc <= 2 ASLAM_ITERS + 1: u_n sweeps
+  LS_A3 = 2,    // Dc <= 3 ASLAM_ITERS + 1: u sweeps
+  LS_V = 3,     // Dv <= VEL_ITERS + 1: speed and its extension
+  LS_R = 4,     // Dv <= VEL_ITERS + 4: advection stages
+  LS_U = 5,     // A3 or R: normals and initial values
+  LS_NLIST = 6,
+  LS_FULL = 6   // every tile of the box
+};
+constexpr int LS_DIST_CAP = 1000;   // distances are capped here (beyond every radius)
 
 // Box-sized scratch arrays of one instance.
 struct LevelsetScratch {
@@ -42,14 +54,14 @@ struct LevelsetScratch {
 struct LsInst {
   int dim, nx, ny, nz;
   int ntx, nty, ntz;
-  int nband;                  // band tiles
+  int nband[LS_NLIST];        // tiles per list
   double h, mu;
   double* rho;                // user arrays (updated in place)
   double* u;
   double* buf;                // LevelsetScratch::buf
   size_t nodes;
   uint8_t* known;
-  const int* band;            // band tile indices (nband entries)
+  const int* band;            // lists, LS_NLIST blocks of ntx*nty*ntz entries
   double* vmax;               // set by levelset_begin
 };
 
@@ -59,12 +71,11 @@ struct LevelsetBatch {
   int dim = 2;
   LsInst* d_inst = nullptr;   // count
   LsInst* h_inst = nullptr;   // pinned, count (caller fills before levelset_begin)
-  int* d_off = nullptr;       // 2 * (count + 1): band offsets, then whole-box offsets
+  int* d_off = nullptr;       // (LS_NLIST + 1) * (count + 1): list offsets, then whole-box offsets
   int* h_off = nullptr;       // pinned
   double* d_vmax = nullptr;   // count maximum speeds
   double* h_vmax = nullptr;   // pinned mirror
-  int total_band = 0;
-  int total_full = 0;
+  int total[LS_NLIST + 1] = {};
   double dt = 0.0;
   int reinit = 0;
   int uext = 0;               // scratch array holding u_ext after levelset_begin

@@ -42,11 +42,12 @@ struct Where {
   bool in;       // node inside the box
 };
 
-// Block -> instance (largest i with off[i] <= blockIdx.x) -> tile -> node.
+// Block -> instance (largest i with off[i] <= blockIdx.x) -> tile of the
+// instance's list `list` (LS_FULL: every tile) -> node.
 template <int DIM>
 __device__ __forceinline__ Where locate(const LsInst* __restrict__ insts, const int* __restrict__ off, int count,
-                                       bool band) {
-  const int* o = band ? off : off + count + 1;
+                                       int list) {
+  const int* o = off + (size_t)list * (count + 1);
   const int b = (int)blockIdx.x;
   int lo = 0, hi = count - 1;
   while (lo < hi) {
@@ -58,7 +59,7 @@ __device__ __forceinline__ Where locate(const LsInst* __restrict__ insts, const 
   w.I = insts + lo;
   w.local = b - o[lo];
   const LsInst& I = *w.I;
-  const int t = band ? I.band[w.local] : w.local;
+  const int t = (list == LS_FULL) ? w.local : I.band[(size_t)list * (I.ntx * I.nty * I.ntz) + w.local];
   constexpr int X = TileShape<DIM>::X, Y = TileShape<DIM>::Y;
   const int tx = t % I.ntx, ty = (t / I.ntx) % I.nty, tz = t / (I.ntx * I.nty);
   const int l = threadIdx.x;
@@ -97,24 +98,26 @@ __device__ __forceinline__ bool comp_point(const LsInst& I, const Where& w, gptr
 
 // ------------------------------------------------------------ Step 1: u_ext
 
-// whole box: the extrapolation arrays and the speed start at 0
+// whole box: the extrapolation arrays, the speed and its ping-pong partner
+// start at 0, and so does the instance's maximum speed
 template <int DIM>
 __global__ __launch_bounds__(256) void zero_kernel(const LsInst* __restrict__ insts, const int* __restrict__ off,
                                                    int count) {
-  const Where w = locate<DIM>(insts, off, count, false);
-  if (!w.in) return;
-  const LsInst& I = *w.I;
-  for (int a = A_E0; a <= A_V; ++a) arr(I, a)[w.id] = 0.0;
-}
-
-// band: normals, K0 (bit 0), E0 = K0 ? u : 0; resets the instance's max speed
-template <int DIM>
-__global__ __launch_bounds__(256) void init_kernel(const LsInst* __restrict__ insts, const int* __restrict__ off,
-                                                   int count) {
-  const Where w = locate<DIM>(insts, off, count, true);
+  const Where w = locate<DIM>(insts, off, count, LS_FULL);
   const LsInst& I = *w.I;
   if (w.local == 0 && threadIdx.x == 0) *glb(I.vmax) = 0.0;
   if (!w.in) return;
+  for (int a = A_E0; a <= A_V; ++a) arr(I, a)[w.id] = 0.0;
+  arr(I, A_S)[w.id] = 0.0;
+}
+
+// list U: normals, K0 (bit 0, other bits cleared), E0 = K0 ? u : 0
+template <int DIM>
+__global__ __launch_bounds__(256) void init_kernel(const LsInst* __restrict__ insts, const int* __restrict__ off,
+                                                   int count) {
+  const Where w = locate<DIM>(insts, off, count, LS_U);
+  if (!w.in) return;
+  const LsInst& I = *w.I;
   gptr<const double> rho = glb((const double*)I.rho);
   double g[3] = {0.0, 0.0, 0.0};
   for (int d = 0; d < DIM; ++d) g[d] = (rho[shifted(I, w, d, 1)] - rho[shifted(I, w, d, -1)]) / (2.0 * I.h);
@@ -146,21 +149,21 @@ __device__ __forceinline__ double dir_deriv(const LsInst& I, const Where& w, gpt
   return v;
 }
 
-// band: K1 (bit 1)
+// list A1: K1 (bit 1)
 template <int DIM>
 __global__ __launch_bounds__(256) void known1_kernel(const LsInst* __restrict__ insts, const int* __restrict__ off,
                                                      int count) {
-  const Where w = locate<DIM>(insts, off, count, true);
+  const Where w = locate<DIM>(insts, off, count, LS_A1);
   if (!w.in) return;
   const LsInst& I = *w.I;
   if (known_all<DIM>(I, w, 0)) glb(I.known)[w.id] |= (uint8_t)2;
 }
 
-// band: K2 (bit 2) and E1 = K1 ? n . grad E0 : 0
+// list A1: K2 (bit 2) and E1 = K1 ? n . grad E0 : 0
 template <int DIM>
 __global__ __launch_bounds__(256) void known2_un_kernel(const LsInst* __restrict__ insts,
                                                         const int* __restrict__ off, int count) {
-  const Where w = locate<DIM>(insts, off, count, true);
+  const Where w = locate<DIM>(insts, off, count, LS_A1);
   if (!w.in) return;
   const LsInst& I = *w.I;
   const bool k1 = (glb((const uint8_t*)I.known)[w.id] >> 1) & 1;
@@ -168,25 +171,25 @@ __global__ __launch_bounds__(256) void known2_un_kernel(const LsInst* __restrict
   arr(I, A_E1)[w.id] = k1 ? dir_deriv<DIM>(I, w, arr(I, A_E0)) : 0.0;
 }
 
-// band: E2 = K2 ? n . grad E1 : 0
+// list A1: E2 = K2 ? n . grad E1 : 0
 template <int DIM>
 __global__ __launch_bounds__(256) void unn_kernel(const LsInst* __restrict__ insts, const int* __restrict__ off,
                                                   int count) {
-  const Where w = locate<DIM>(insts, off, count, true);
+  const Where w = locate<DIM>(insts, off, count, LS_A1);
   if (!w.in) return;
   const LsInst& I = *w.I;
   const bool k2 = (glb((const uint8_t*)I.known)[w.id] >> 2) & 1;
   arr(I, A_E2)[w.id] = k2 ? dir_deriv<DIM>(I, w, arr(I, A_E1)) : 0.0;
 }
 
-// band: one Jacobi sweep out = v - dtau (a.grad v - src) off the known set
+// one Jacobi sweep on `list`: out = v - dtau (a.grad v - src) off the known set
 // (bit), a = sgn * n, sgn = 1 or sign(rho) (speed extension); with
 // do_max, also the instance's maximum of out (non-negative values).
 template <int DIM>
 __global__ __launch_bounds__(256) void extend_kernel(const LsInst* __restrict__ insts, const int* __restrict__ off,
-                                                     int count, int v_arr, int out_arr, int src_arr, int bit,
-                                                     int sign_rho, int do_max) {
-  const Where w = locate<DIM>(insts, off, count, true);
+                                                     int count, int list, int v_arr, int out_arr, int src_arr,
+                                                     int bit, int sign_rho, int do_max) {
+  const Where w = locate<DIM>(insts, off, count, list);
   const LsInst& I = *w.I;
   double res = 0.0;
   if (w.in) {
@@ -225,11 +228,11 @@ __global__ __launch_bounds__(256) void extend_kernel(const LsInst* __restrict__ 
   }
 }
 
-// band: V = (|rho| < h) ? mu |central grad u_ext| : 0; speed band into bit 3
+// list V: V = (|rho| < h) ? mu |central grad u_ext| : 0; speed band into bit 3
 template <int DIM>
 __global__ __launch_bounds__(256) void velocity_kernel(const LsInst* __restrict__ insts,
                                                        const int* __restrict__ off, int count, int uext_arr) {
-  const Where w = locate<DIM>(insts, off, count, true);
+  const Where w = locate<DIM>(insts, off, count, LS_V);
   if (!w.in) return;
   const LsInst& I = *w.I;
   gptr<const double> ue = arr(I, uext_arr);
@@ -252,10 +255,14 @@ __global__ __launch_bounds__(256) void velocity_kernel(const LsInst* __restrict_
 
 // ------------------------------------------------------------ Step 2: WENO
 
+// Fifth-order WENO derivative from the five differences v1..v5 (Jiang-Peng
+// weights, eps 1e-6).  The nonlinear weights d_k / (eps + beta_k)^2 are
+// normalised through their common denominator, so one division remains.
 __device__ __forceinline__ double weno5(double v1, double v2, double v3, double v4, double v5) {
-  const double p1 = v1 / 3.0 - 7.0 * v2 / 6.0 + 11.0 * v3 / 6.0;
-  const double p2 = -v2 / 6.0 + 5.0 * v3 / 6.0 + v4 / 3.0;
-  const double p3 = v3 / 3.0 + 5.0 * v4 / 6.0 - v5 / 6.0;
+  constexpr double SIXTH = 1.0 / 6.0;
+  const double p1 = (2.0 * v1 - 7.0 * v2 + 11.0 * v3) * SIXTH;
+  const double p2 = (-v2 + 5.0 * v3 + 2.0 * v4) * SIXTH;
+  const double p3 = (2.0 * v3 + 5.0 * v4 - v5) * SIXTH;
   const double t1 = v1 - 2.0 * v2 + v3, t1b = v1 - 4.0 * v2 + 3.0 * v3;
   const double t2 = v2 - 2.0 * v3 + v4, t2b = v2 - v4;
   const double t3 = v3 - 2.0 * v4 + v5, t3b = 3.0 * v3 - 4.0 * v4 + v5;
@@ -263,21 +270,21 @@ __device__ __forceinline__ double weno5(double v1, double v2, double v3, double 
   const double s2 = 13.0 / 12.0 * (t2 * t2) + 0.25 * (t2b * t2b);
   const double s3 = 13.0 / 12.0 * (t3 * t3) + 0.25 * (t3b * t3b);
   const double e1 = s1 + WENO_EPS, e2 = s2 + WENO_EPS, e3 = s3 + WENO_EPS;
-  const double a1 = 0.1 / (e1 * e1);
-  const double a2 = 0.6 / (e2 * e2);
-  const double a3 = 0.3 / (e3 * e3);
-  return (a1 * p1 + a2 * p2 + a3 * p3) / (a1 + a2 + a3);
+  const double q1 = e1 * e1, q2 = e2 * e2, q3 = e3 * e3;
+  const double b1 = 0.1 * (q2 * q3), b2 = 0.6 * (q1 * q3), b3 = 0.3 * (q1 * q2);
+  return (b1 * p1 + b2 * p2 + b3 * p3) / (b1 + b2 + b3);
 }
 
 // Godunov |grad phi| for speed sign sg (+1 / -1 / 0), HJ-WENO5 derivatives
 template <int DIM>
 __device__ double godunov(const LsInst& I, const Where& w, gptr<const double> phi, double sg) {
   double accp = 0.0, accn = 0.0;
+  const double inv_h = 1.0 / I.h;
   for (int d = 0; d < DIM; ++d) {
     double f[7];
     for (int s = -3; s <= 3; ++s) f[s + 3] = phi[shifted(I, w, d, s)];
     double dd[6];
-    for (int q = 0; q < 6; ++q) dd[q] = (f[q + 1] - f[q]) / I.h;
+    for (int q = 0; q < 6; ++q) dd[q] = (f[q + 1] - f[q]) * inv_h;
     const double dm = weno5(dd[0], dd[1], dd[2], dd[3], dd[4]);
     const double dp = weno5(dd[5], dd[4], dd[3], dd[2], dd[1]);
     const double a = fmax(dm, 0.0), bb = fmin(dp, 0.0);
@@ -299,14 +306,14 @@ __device__ __forceinline__ int substeps(const LsInst& I, double dt) {
 
 // One TVD-RK3 stage (1, 2, 3): out = c0 * R0 + c1 * (in - dt * L(in)) with
 // stage 1: in = rho, out = R1 (and R0 = rho); stage 2: in = R1, out = R2;
-// stage 3: in = R2, out = rho; L = V G(in) (advection, band launch, speed 0
+// stage 3: in = R2, out = rho; L = V G(in) (advection, list R, speed 0
 // gives L = 0) or S (G_sign(S)(in) - 1) (reinitialisation, whole box;
 // first != 0 computes S from rho).  Advection substep q runs only for
 // instances with more than q substeps.
 template <int DIM>
 __global__ __launch_bounds__(256) void rk_kernel(const LsInst* __restrict__ insts, const int* __restrict__ off,
                                                  int count, int reinit, int stage, int q, double dt, int first) {
-  const Where w = locate<DIM>(insts, off, count, !reinit);
+  const Where w = locate<DIM>(insts, off, count, reinit ? LS_FULL : LS_R);
   if (!w.in) return;
   const LsInst& I = *w.I;
   double step;
@@ -348,7 +355,7 @@ __global__ __launch_bounds__(256) void rk_kernel(const LsInst* __restrict__ inst
 template <int DIM>
 __global__ __launch_bounds__(256) void restrict_kernel(const LsInst* __restrict__ insts,
                                                        const int* __restrict__ off, int count, int uext_arr) {
-  const Where w = locate<DIM>(insts, off, count, false);
+  const Where w = locate<DIM>(insts, off, count, LS_FULL);
   if (!w.in) return;
   const LsInst& I = *w.I;
   const bool c = comp_point<DIM>(I, w, glb((const double*)I.rho));
@@ -361,54 +368,45 @@ hipError_t begin_dim(LevelsetBatch& b, hipStream_t st) {
   const LsInst* I = b.d_inst;
   const int* off = b.d_off;
   const dim3 B(256);
-  const dim3 GB(b.total_band), GF(b.total_full);
-#define LB(kernel, ...)                                                        \
-  do {                                                                         \
-    if (b.total_band > 0) {                                                    \
-      hipLaunchKernelGGL(kernel<DIM>, GB, B, 0, st, I, off, n, ##__VA_ARGS__); \
-      hipError_t _e = hipGetLastError();                                       \
-      if (_e != hipSuccess) return _e;                                         \
-    }                                                                          \
+#define LL(list, kernel, ...)                                                                \
+  do {                                                                                       \
+    if (b.total[list] > 0) {                                                                 \
+      hipLaunchKernelGGL(kernel<DIM>, dim3(b.total[list]), B, 0, st, I, off, n, ##__VA_ARGS__); \
+      hipError_t _e = hipGetLastError();                                                     \
+      if (_e != hipSuccess) return _e;                                                       \
+    }                                                                                        \
   } while (0)
-  hipLaunchKernelGGL(zero_kernel<DIM>, GF, B, 0, st, I, off, n);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  LB(init_kernel);
-  LB(known1_kernel);
-  LB(known2_un_kernel);
-  LB(unn_kernel);
-  // Aslam: u_nn (E2, ping-pong E3), u_n (E1, src u_nn), u (E0, src u_n); the
-  // results move through the free arrays (ASLAM_ITERS is odd)
-  int v = A_E2, t = A_E3;
+  LL(LS_FULL, zero_kernel);
+  LL(LS_U, init_kernel);
+  LL(LS_A1, known1_kernel);
+  LL(LS_A1, known2_un_kernel);
+  LL(LS_A1, unn_kernel);
+  // Aslam: u_nn on A1 (E2 <-> E3, result E3), u_n on A2 (E1 <-> E2, src u_nn,
+  // result E2), u on A3 (E0 <-> E1, src u_n, result E1); ASLAM_ITERS is odd,
+  // and each partner array is 0 outside its stage's list
+  static_assert(ASLAM_ITERS % 2 == 1, "ping-pong bookkeeping assumes an odd sweep count");
   for (int it = 0; it < ASLAM_ITERS; ++it) {
-    LB(extend_kernel, v, t, -1, 2, 0, 0);
-    const int x = v; v = t; t = x;
+    const bool ev = (it % 2) == 0;
+    LL(LS_A1, extend_kernel, (int)LS_A1, ev ? A_E2 : A_E3, ev ? A_E3 : A_E2, -1, 2, 0, 0);
   }
-  const int unn = v;
-  v = A_E1;
-  t = (unn == A_E3) ? A_E2 : A_E3;
   for (int it = 0; it < ASLAM_ITERS; ++it) {
-    LB(extend_kernel, v, t, unn, 1, 0, 0);
-    const int x = v; v = t; t = x;
+    const bool ev = (it % 2) == 0;
+    LL(LS_A2, extend_kernel, (int)LS_A2, ev ? A_E1 : A_E2, ev ? A_E2 : A_E1, (int)A_E3, 1, 0, 0);
   }
-  const int un = v;
-  v = A_E0;
-  t = (un == A_E1) ? A_E2 : A_E1;
-  if (t == unn) t = A_E3;
   for (int it = 0; it < ASLAM_ITERS; ++it) {
-    LB(extend_kernel, v, t, un, 0, 0, 0);
-    const int x = v; v = t; t = x;
+    const bool ev = (it % 2) == 0;
+    LL(LS_A3, extend_kernel, (int)LS_A3, ev ? A_E0 : A_E1, ev ? A_E1 : A_E0, (int)A_E2, 0, 0, 0);
   }
-  b.uext = v;
-  // Stefan speed, extension (even count: ends in V), maximum on the last sweep
-  LB(velocity_kernel, b.uext);
-  v = A_V;
-  t = (b.uext == A_E0) ? A_E1 : A_E0;
+  b.uext = A_E1;
+  // Stefan speed, extension V <-> S (even count: ends in V), maximum on the
+  // last sweep
+  static_assert(VEL_ITERS % 2 == 0, "the speed extension must end in V");
+  LL(LS_V, velocity_kernel, b.uext);
   for (int it = 0; it < VEL_ITERS; ++it) {
-    LB(extend_kernel, v, t, -1, 3, 1, it == VEL_ITERS - 1 ? 1 : 0);
-    const int x = v; v = t; t = x;
+    const bool ev = (it % 2) == 0;
+    LL(LS_V, extend_kernel, (int)LS_V, ev ? A_V : A_S, ev ? A_S : A_V, -1, 3, 1, it == VEL_ITERS - 1 ? 1 : 0);
   }
-#undef LB
+#undef LL
   return hipSuccess;
 }
 
@@ -425,22 +423,22 @@ hipError_t end_dim(LevelsetBatch& b, hipStream_t st) {
     if (ns > nsub) nsub = ns;
   }
   hipError_t e;
-  if (b.total_band > 0) {
+  if (b.total[LS_R] > 0) {
     for (int q = 0; q < nsub; ++q)
       for (int s = 1; s <= 3; ++s) {
-        hipLaunchKernelGGL(rk_kernel<DIM>, dim3(b.total_band), B, 0, st, I, off, n, 0, s, q, b.dt, 0);
+        hipLaunchKernelGGL(rk_kernel<DIM>, dim3(b.total[LS_R]), B, 0, st, I, off, n, 0, s, q, b.dt, 0);
         if ((e = hipGetLastError()) != hipSuccess) return e;
       }
   }
   if (b.reinit) {
     for (int it = 0; it < REINIT_ITERS; ++it)
       for (int s = 1; s <= 3; ++s) {
-        hipLaunchKernelGGL(rk_kernel<DIM>, dim3(b.total_full), B, 0, st, I, off, n, 1, s, 0, 0.0,
+        hipLaunchKernelGGL(rk_kernel<DIM>, dim3(b.total[LS_FULL]), B, 0, st, I, off, n, 1, s, 0, 0.0,
                            (it == 0 && s == 1) ? 1 : 0);
         if ((e = hipGetLastError()) != hipSuccess) return e;
       }
   }
-  hipLaunchKernelGGL(restrict_kernel<DIM>, dim3(b.total_full), B, 0, st, I, off, n, b.uext);
+  hipLaunchKernelGGL(restrict_kernel<DIM>, dim3(b.total[LS_FULL]), B, 0, st, I, off, n, b.uext);
   return hipGetLastError();
 }
 
@@ -467,8 +465,8 @@ hipError_t levelset_batch_alloc(LevelsetBatch& b, int count, int dim) {
   hipError_t e;
   if ((e = hipMalloc(&b.d_inst, sizeof(LsInst) * count)) != hipSuccess) return e;
   if ((e = hipHostMalloc(&b.h_inst, sizeof(LsInst) * count)) != hipSuccess) return e;
-  if ((e = hipMalloc(&b.d_off, sizeof(int) * 2 * (count + 1))) != hipSuccess) return e;
-  if ((e = hipHostMalloc(&b.h_off, sizeof(int) * 2 * (count + 1))) != hipSuccess) return e;
+  if ((e = hipMalloc(&b.d_off, sizeof(int) * (LS_NLIST + 1) * (count + 1))) != hipSuccess) return e;
+  if ((e = hipHostMalloc(&b.h_off, sizeof(int) * (LS_NLIST + 1) * (count + 1))) != hipSuccess) return e;
   if ((e = hipMalloc(&b.d_vmax, sizeof(double) * count)) != hipSuccess) return e;
   if ((e = hipHostMalloc(&b.h_vmax, sizeof(double) * count)) != hipSuccess) return e;
   for (int i = 0; i < count; ++i) b.h_inst[i] = LsInst{};
@@ -489,23 +487,22 @@ hipError_t levelset_begin(LevelsetBatch& b, double dt, int reinit, hipStream_t s
   const int n = b.count;
   b.dt = dt;
   b.reinit = reinit;
-  int band = 0, full = 0;
-  for (int i = 0; i < n; ++i) {
-    LsInst& I = b.h_inst[i];
-    I.vmax = b.d_vmax + i;
-    b.h_off[i] = band;
-    b.h_off[n + 1 + i] = full;
-    band += I.nband;
-    full += I.ntx * I.nty * I.ntz;
+  for (int q = 0; q <= LS_NLIST; ++q) {
+    int acc = 0;
+    for (int i = 0; i < n; ++i) {
+      const LsInst& I = b.h_inst[i];
+      b.h_off[q * (n + 1) + i] = acc;
+      acc += (q == LS_FULL) ? I.ntx * I.nty * I.ntz : I.nband[q];
+    }
+    b.h_off[q * (n + 1) + n] = acc;
+    b.total[q] = acc;
   }
-  b.h_off[n] = band;
-  b.h_off[2 * n + 1] = full;
-  b.total_band = band;
-  b.total_full = full;
+  for (int i = 0; i < n; ++i) b.h_inst[i].vmax = b.d_vmax + i;
   hipError_t e;
   if ((e = hipMemcpyAsync(b.d_inst, b.h_inst, sizeof(LsInst) * n, hipMemcpyHostToDevice, st)) != hipSuccess)
     return e;
-  if ((e = hipMemcpyAsync(b.d_off, b.h_off, sizeof(int) * 2 * (n + 1), hipMemcpyHostToDevice, st)) != hipSuccess)
+  if ((e = hipMemcpyAsync(b.d_off, b.h_off, sizeof(int) * (LS_NLIST + 1) * (n + 1), hipMemcpyHostToDevice, st)) !=
+      hipSuccess)
     return e;
   e = (b.dim == 2) ? begin_dim<2>(b, st) : begin_dim<3>(b, st);
   if (e != hipSuccess) return e;
