@@ -352,6 +352,13 @@ def main():
             "levelset": prof["levelset_ms"] / max(args.steps, 1),
             "geometry": prof["geometry_ms"] / max(args.steps, 1),
         },
+        "krylov_device_ms_per_step": {
+            "whole": prof["krylov_device_ms"] / max(args.steps, 1),
+            "in_grid_sync": prof["krylov_sync_ms"] / max(args.steps, 1),
+            "in_expm": prof["krylov_expm_ms"] / max(args.steps, 1),
+            "syncs": prof["krylov_syncs"] / max(args.steps, 1),
+            "expms": prof["krylov_expms"] / max(args.steps, 1),
+        },
         "last_krylov_stats": st,
         "roofline": roofline,
     }

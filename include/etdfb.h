@@ -106,6 +106,13 @@ typedef struct {
   int32_t levelset_calls;
   int32_t geometry_calls;
   int32_t n_unknowns;        /* computational points of the current geometry */
+  /* inside the Krylov launches, from the device clock of block 0: whole
+   * launches, grid synchronisations (waiting included), small exponentials */
+  double krylov_device_ms;
+  double krylov_sync_ms;
+  double krylov_expm_ms;
+  int32_t krylov_syncs;
+  int32_t krylov_expms;
 } etd_profile;
 
 typedef struct etd_ctx etd_ctx;

@@ -47,6 +47,7 @@ struct etd_ctx {
   unsigned* flags = nullptr;
   BarrierDev* bar = nullptr;
   int n_cu = 0;
+  double clock_khz = 1.0;   // device wall clock (ticks per millisecond)
   int tmax = 1;
   KrylovStateDev* st = nullptr;
   int max_grid = 0;
@@ -133,6 +134,15 @@ void timer_free(etd_ctx::Timer& t) {
 }
 
 int check_hip(hipError_t e) { return e == hipSuccess ? ETD_OK : ETD_ERR_HIP; }
+
+// Zero the accumulated measurement fields of a device state (stream-ordered;
+// the source is a static host block, so it outlives the copy).
+hipError_t reset_counters(KrylovStateDev* st, hipStream_t s) {
+  static const KrylovStateDev zero{};
+  const size_t off = offsetof(KrylovStateDev, alg_bytes_total);
+  return hipMemcpyAsync((char*)st + off, (const char*)&zero + off, sizeof(KrylovStateDev) - off,
+                        hipMemcpyHostToDevice, s);
+}
 
 #define HIP_TRY(x)                         \
   do {                                     \
@@ -378,6 +388,11 @@ int etd_ctx_create(const etd_grid* grid, const etd_physics* phys, const etd_kryl
   c->nodes = (size_t)b.nx * b.ny * b.nz;
   c->ld = (size_t)c->ntiles * TILE_PTS;
   c->n_cu = prop.multiProcessorCount;
+  {
+    int khz = 0;
+    if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, c->device) == hipSuccess && khz > 0)
+      c->clock_khz = khz;
+  }
   const int per_cu = krylov_max_blocks_per_cu(b.dim, 1);
   c->max_grid = per_cu * prop.multiProcessorCount;
   if (c->max_grid < 1) { delete c; return ETD_ERR_HIP; }
@@ -585,11 +600,15 @@ int etd_ctx_profile_read(etd_ctx* c, etd_profile* out, int32_t reset) {
   out->geometry_calls = c->t_geometry.count;
   out->alg_bytes = c->h_state->alg_bytes_total;
   out->n_unknowns = c->h_counters[4];
+  out->krylov_device_ms = c->h_state->ticks_total / c->clock_khz;
+  out->krylov_sync_ms = c->h_state->ticks_sync / c->clock_khz;
+  out->krylov_expm_ms = c->h_state->ticks_expm / c->clock_khz;
+  out->krylov_syncs = c->h_state->syncs;
+  out->krylov_expms = c->h_state->expm_calls;
   if (reset) {
     c->t_krylov.ms = c->t_levelset.ms = c->t_geometry.ms = 0.0;
     c->t_krylov.count = c->t_levelset.count = c->t_geometry.count = 0;
-    const double zero = 0.0;
-    HIP_TRY(hipMemcpyAsync(&c->st->alg_bytes_total, &zero, sizeof(double), hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(reset_counters(c->st, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
   }
   return ETD_OK;
@@ -854,12 +873,17 @@ int etd_batch_profile_read(etd_batch* B, etd_profile* out, int32_t reset) {
   }
   out->alg_bytes = bytes;
   out->n_unknowns = (int32_t)unknowns;
+  // the instances run concurrently in one launch: report instance 0's clock
+  const etd_ctx* c0 = B->inst[0];
+  out->krylov_device_ms = c0->h_state->ticks_total / c0->clock_khz;
+  out->krylov_sync_ms = c0->h_state->ticks_sync / c0->clock_khz;
+  out->krylov_expm_ms = c0->h_state->ticks_expm / c0->clock_khz;
+  out->krylov_syncs = c0->h_state->syncs;
+  out->krylov_expms = c0->h_state->expm_calls;
   if (reset) {
     B->t_krylov.ms = B->t_levelset.ms = B->t_geometry.ms = 0.0;
     B->t_krylov.count = B->t_levelset.count = B->t_geometry.count = 0;
-    const double zero = 0.0;
-    for (etd_ctx* c : B->inst)
-      HIP_TRY(hipMemcpyAsync(&c->st->alg_bytes_total, &zero, sizeof(double), hipMemcpyHostToDevice, B->stream));
+    for (etd_ctx* c : B->inst) HIP_TRY(reset_counters(c->st, B->stream));
     HIP_TRY(hipStreamSynchronize(B->stream));
   }
   return ETD_OK;

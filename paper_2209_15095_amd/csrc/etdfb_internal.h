@@ -72,6 +72,10 @@ struct KrylovStateDev {
   double t_done;
   double alg_bytes_per_unknown;   // algorithmic HBM bytes per unknown, last launch
   double alg_bytes_total;         // accumulated over launches: bytes/unknown * unknowns
+  // device-clock ticks accumulated over launches (block 0 of the group):
+  // whole launch, inside grid synchronisations, inside the small exponentials
+  double ticks_total, ticks_sync, ticks_expm;
+  int syncs, expm_calls;
 };
 
 enum JobMode {

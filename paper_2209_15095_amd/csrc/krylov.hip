@@ -76,6 +76,10 @@ struct Engine {
   // and write per computational point (vectors only; neighbour re-reads,
   // masks and tile padding are not counted).
   double bpu;
+  // device-clock ticks spent in synchronisations and exponentials (kept by
+  // thread 0 of block 0 of the group)
+  unsigned long long tk_sync, tk_expm;
+  int n_sync;
 
   __device__ gptr<double> V(int i) const { return glb(P.ws) + (size_t)i * P.ld; }
 
@@ -93,6 +97,7 @@ struct Engine {
   // abort flag goes up and every block leaves.
   template <int NR>
   __device__ bool grid_sync(const double (&acc)[NR], double (&out)[NR]) {
+    const unsigned long long t_in = wall_clock64();
     ++pass_no;
     const unsigned gen = (unsigned)pass_no;
     gptr<double> part = glb(P.part) + (size_t)(gen & 1u) * G * PART_STRIDE;
@@ -137,6 +142,10 @@ struct Engine {
     for (int k = 0; k < NR; ++k) out[k] = c.red[k];
     const int ab = c.abort;
     __syncthreads();
+    if (threadIdx.x == 0 && lb == 0) {
+      tk_sync += wall_clock64() - t_in;
+      ++n_sync;
+    }
     return ab == 0;
   }
 
@@ -336,6 +345,7 @@ struct Engine {
   // E = exp(X) in R, X the augmented matrix of size N = m + p + 1 built
   // from tau, alpha[0..m-1], nrm[1..m-1].
   __device__ void expm_aug(int m, int p, double tau) {
+    const unsigned long long t_in = wall_clock64();
     const int N = m + p + 1;
     // 1-norm of X (column sums)
     if (threadIdx.x == 0) {
@@ -396,6 +406,7 @@ struct Engine {
       for (int e = threadIdx.x; e < NN; e += blockDim.x) R[e] = A[e];
       __syncthreads();
     }
+    if (threadIdx.x == 0 && lb == 0) tk_expm += wall_clock64() - t_in;
   }
 
   // ------------------------------------------------------------ phi combo
@@ -777,7 +788,10 @@ struct Engine {
 // instance P); c, R and S are the block's LDS.
 template <int DIM>
 __device__ __forceinline__ void krylov_body(const KrylovDev& P, int lb, int G, Ctl& c, double* R, double* S) {
+  const unsigned long long t_start = wall_clock64();
   Engine<DIM> e{P, c, R, S, *P.g.n_active, 0, lb, G};
+  e.tk_sync = e.tk_expm = 0;
+  e.n_sync = 0;
   for (int k = 0; k <= PMAX; ++k) {
     if (threadIdx.x == 0) {
       c.m_guess[k] = P.st->m_guess[k];
@@ -808,6 +822,11 @@ __device__ __forceinline__ void krylov_body(const KrylovDev& P, int lb, int G, C
     P.st->t_done = e.t_done;
     P.st->alg_bytes_per_unknown = e.bpu;
     P.st->alg_bytes_total += e.bpu * (double)(*P.g.n_unknowns);
+    P.st->ticks_total += (double)(wall_clock64() - t_start);
+    P.st->ticks_sync += (double)e.tk_sync;
+    P.st->ticks_expm += (double)e.tk_expm;
+    P.st->syncs += e.n_sync;
+    P.st->expm_calls += e.expms;
   }
 }
 
