@@ -185,21 +185,95 @@ struct Engine {
     return true;
   }
 
+  // One point of a loop trip: its tile slot and index, masks, and the
+  // indices of its 2d face neighbours (the point's own index where a
+  // neighbour does not exist, ok[] false), so that every load of a pass can
+  // be issued without a branch and the trip costs one memory round trip.
+  struct Tile {
+    int slot, l;
+    size_t idx;
+    bool comp, irr;
+    size_t ni[2 * DIM];
+    bool ok[2 * DIM];
+  };
+  // Per-wave metadata of a trip (prefetched one trip ahead).
+  struct Meta {
+    uint64_t cw, iw;
+    int nb[2 * DIM];
+  };
+
+  __device__ void load_meta(Meta& m, int slot, int w) const {
+    m.cw = glb(P.g.comp_bits)[(size_t)slot * 4 + w];
+    m.iw = glb(P.g.irr_bits)[(size_t)slot * 4 + w];
+    gptr<const int> nbp = glb(P.g.nbr) + (size_t)slot * NBR_STRIDE;
+#pragma unroll
+    for (int d = 0; d < 2 * DIM; ++d) m.nb[d] = nbp[d];
+  }
+
+  __device__ void make_tile(Tile& t, int slot, int l, const Meta& m) const {
+    constexpr int X = TileShape<DIM>::X, Y = TileShape<DIM>::Y, Z = TileShape<DIM>::Z;
+    t.slot = slot;
+    t.l = l;
+    t.idx = (size_t)slot * TILE_PTS + l;
+    t.comp = (m.cw >> (l & 63)) & 1ull;
+    t.irr = t.comp && ((m.iw >> (l & 63)) & 1ull);
+    const int lc[3] = {l % X, (l / X) % Y, l / (X * Y)};
+    const int ext[3] = {X, Y, Z};
+    const int str[3] = {1, X, X * Y};
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+      // -e_d: inside the tile, or the last layer of the neighbour tile
+      const bool in_lo = lc[d] > 0;
+      const int nlo = m.nb[2 * d];
+      t.ok[2 * d] = in_lo || nlo >= 0;
+      t.ni[2 * d] = in_lo ? t.idx - str[d]
+                          : (nlo >= 0 ? (size_t)nlo * TILE_PTS + l + str[d] * (ext[d] - 1) : t.idx);
+      // +e_d: inside the tile, or the first layer of the neighbour tile
+      const bool in_hi = lc[d] < ext[d] - 1;
+      const int nhi = m.nb[2 * d + 1];
+      t.ok[2 * d + 1] = in_hi || nhi >= 0;
+      t.ni[2 * d + 1] = in_hi ? t.idx + str[d]
+                              : (nhi >= 0 ? (size_t)nhi * TILE_PTS + l - str[d] * (ext[d] - 1) : t.idx);
+    }
+  }
+
   // Loop over the active tiles of this block (KTILES tiles per trip, one per
-  // 256 threads); f(slot, l, comp, irr, nb) with nb the tile's face-neighbour
-  // slots.  No block synchronisation inside: nothing is shared through LDS.
+  // 256 threads); f(tile point).  The next trip's metadata loads are issued
+  // before the current trip's data loads.  No block synchronisation inside:
+  // nothing is shared through LDS.
   template <class F>
   __device__ void tiles(F&& f) {
     const int sub = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / TILE_PTS));
     const int l = (int)(threadIdx.x % TILE_PTS);
-    for (int slot = lb * KTILES + sub; slot < nact; slot += G * KTILES) {
-      const int w = l >> 6;
-      const uint64_t cw = glb(P.g.comp_bits)[(size_t)slot * 4 + w];
-      const uint64_t iw = glb(P.g.irr_bits)[(size_t)slot * 4 + w];
-      const bool comp = (cw >> (l & 63)) & 1ull;
-      const bool irr = comp && ((iw >> (l & 63)) & 1ull);
-      f(slot, l, comp, irr, glb(P.g.nbr) + (size_t)slot * NBR_STRIDE);
+    const int w = __builtin_amdgcn_readfirstlane(l >> 6);
+    const int stride = G * KTILES;
+    int slot = lb * KTILES + sub;
+    Meta m;
+    if (slot < nact) load_meta(m, slot, w);
+    while (slot < nact) {
+      Tile t;
+      make_tile(t, slot, l, m);
+      const int next = slot + stride;
+      if (next < nact) load_meta(m, next, w);
+      f(t);
+      slot = next;
     }
+  }
+
+  // (A v) at the point: beta/h^2 (sum of neighbours - c_p v_p), 0 off the
+  // computational points.
+  __device__ __forceinline__ double Av(const Tile& t, gptr<const double> v) const {
+    double nv[2 * DIM];
+#pragma unroll
+    for (int d = 0; d < 2 * DIM; ++d) nv[d] = v[t.ni[d]];
+    const double vc = v[t.idx];
+    const double cd = glb(P.g.cdiag)[t.irr ? t.idx : 0];
+    __builtin_amdgcn_sched_barrier(0);
+    double s = 0.0;
+#pragma unroll
+    for (int d = 0; d < 2 * DIM; ++d) s += t.ok[d] ? nv[d] : 0.0;
+    const double cp = t.irr ? cd : (double)(2 * DIM);
+    return t.comp ? P.g.coef * (s - cp * vc) : 0.0;
   }
 
   __device__ double react(double u) const { return u * (P.ra - P.rb * u); }
@@ -218,11 +292,12 @@ struct Engine {
     gptr<const double> src = (k == 1) ? V(iu) : V(V_W1 + k - 2);
     gptr<double> dst = (k == p) ? V(V_Q0) : V(V_W1 + k - 1);
     double acc[2] = {0.0, 0.0};
-    tiles([&](int slot, int l, bool comp, bool irr, gptr<const int> nb) {
-      const size_t i = (size_t)slot * TILE_PTS + l;
+    tiles([&](const Tile& t) {
+      const bool comp = t.comp;
+      const size_t i = t.idx;
       double w = 0.0;
       if (comp) {
-        w = apply_A<DIM>(P.g, src, slot, l, nb, comp, irr);
+        w = Av(t, src);
 #pragma unroll
         for (int j = 0; j <= PMAX; ++j)
           if (j <= p - k) w += cl[j] * V(V_B0 + k + j)[i];
@@ -242,8 +317,9 @@ struct Engine {
   // p == 0: q_0 = U, norms.
   __device__ bool copy_u_pass(double (&out)[2]) {
     double acc[2] = {0.0, 0.0};
-    tiles([&](int slot, int l, bool comp, bool irr, gptr<const int> nb) {
-      const size_t i = (size_t)slot * TILE_PTS + l;
+    tiles([&](const Tile& t) {
+      const bool comp = t.comp;
+      const size_t i = t.idx;
       const double u = V(iu)[i];
       V(V_Q0)[i] = u;
       acc[0] += u * u;
@@ -258,9 +334,10 @@ struct Engine {
     gptr<const double> q = V(V_Q0);
     gptr<double> z = V(V_Z0);
     double acc[1] = {0.0};
-    tiles([&](int slot, int l, bool comp, bool irr, gptr<const int> nb) {
-      const size_t idx = (size_t)slot * TILE_PTS + l;
-      const double zz = apply_A<DIM>(P.g, q, slot, l, nb, comp, irr);
+    tiles([&](const Tile& t) {
+      const bool comp = t.comp;
+      const size_t idx = t.idx;
+      const double zz = Av(t, q);
       z[idx] = zz;
       acc[0] += zz * q[idx];
     });
@@ -281,24 +358,36 @@ struct Engine {
     gptr<double> zk = V(V_Z0 + (k & 1));
     const double alpha = c.alpha[k - 1];
     const double inv_n = 1.0 / c.nrm[k - 1];
+    // k = 1: cm = 0 and q2 = q_0, so the last term is an exact 0 (no branch)
     const double cm = (k >= 2) ? c.nrm[k - 1] / c.nrm[k - 2] : 0.0;
-    const bool two = k >= 2;
-    auto qv = [&](size_t i) -> double {
-      double w = (zp[i] - alpha * q1[i]) * inv_n;
-      if (two) w -= cm * q2[i];
-      return w;
-    };
+    constexpr int NP = 2 * DIM + 1;   // the point (last) and its face neighbours
     double acc[2] = {0.0, 0.0};
-    tiles([&](int slot, int l, bool comp, bool irr, gptr<const int> nb) {
-      const size_t idx = (size_t)slot * TILE_PTS + l;
-      double q = 0.0, z = 0.0;
-      if (comp) {
-        q = qv(idx);
-        const double cp = irr ? glb(P.g.cdiag)[idx] : (double)(2 * DIM);
-        z = P.g.coef * (neighbour_sum<DIM>(slot, l, nb, qv) - cp * q);
+    tiles([&](const Tile& t) {
+      // every load of the point first (one memory round trip), then the math
+      size_t ix[NP];
+#pragma unroll
+      for (int d = 0; d < 2 * DIM; ++d) ix[d] = t.ni[d];
+      ix[NP - 1] = t.idx;
+      double a[NP], b[NP], e[NP];
+#pragma unroll
+      for (int j = 0; j < NP; ++j) {
+        a[j] = zp[ix[j]];
+        b[j] = q1[ix[j]];
+        e[j] = q2[ix[j]];
       }
-      qk[idx] = q;
-      zk[idx] = z;
+      const double cd = glb(P.g.cdiag)[t.irr ? t.idx : 0];
+      __builtin_amdgcn_sched_barrier(0);
+      double qn[NP];
+#pragma unroll
+      for (int j = 0; j < NP; ++j) qn[j] = (a[j] - alpha * b[j]) * inv_n - cm * e[j];
+      double s = 0.0;
+#pragma unroll
+      for (int d = 0; d < 2 * DIM; ++d) s += t.ok[d] ? qn[d] : 0.0;
+      const double cp = t.irr ? cd : (double)(2 * DIM);
+      const double q = t.comp ? qn[NP - 1] : 0.0;
+      const double z = t.comp ? P.g.coef * (s - cp * q) : 0.0;
+      qk[t.idx] = q;
+      zk[t.idx] = z;
       acc[0] += q * q;
       acc[1] += z * q;
     });
@@ -318,8 +407,9 @@ struct Engine {
     }
     const int io = (iu == V_U) ? V_T : V_U;
     double acc[1] = {0.0};
-    tiles([&](int slot, int l, bool comp, bool irr, gptr<const int> nb) {
-      const size_t idx = (size_t)slot * TILE_PTS + l;
+    tiles([&](const Tile& t) {
+      const bool comp = t.comp;
+      const size_t idx = t.idx;
       double u = 0.0;
       if (comp) {
         if (p > 0) {
@@ -328,7 +418,17 @@ struct Engine {
           for (int k = 1; k < PMAX; ++k)
             if (k < p) u += ck[k] * V(V_W1 + k - 1)[idx];
         }
-        for (int j = 0; j < m; ++j) u += c.coef[j] * V(V_Q0 + j)[idx];
+        // four independent partial sums keep four basis loads in flight
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+        int j = 0;
+        for (; j + 4 <= m; j += 4) {
+          s0 += c.coef[j] * V(V_Q0 + j)[idx];
+          s1 += c.coef[j + 1] * V(V_Q0 + j + 1)[idx];
+          s2 += c.coef[j + 2] * V(V_Q0 + j + 2)[idx];
+          s3 += c.coef[j + 3] * V(V_Q0 + j + 3)[idx];
+        }
+        for (; j < m; ++j) s0 += c.coef[j] * V(V_Q0 + j)[idx];
+        u += (s0 + s1) + (s2 + s3);
       }
       V(io)[idx] = u;
       acc[0] += u * u;
@@ -420,8 +520,9 @@ struct Engine {
       double ck[PMAX + 1];
 #pragma unroll
       for (int k = 0; k <= PMAX; ++k) { if (k > 0) f *= k; ck[k] = 1.0 / f; }
-      tiles([&](int slot, int l, bool comp, bool irr, gptr<const int> nb) {
-        const size_t idx = (size_t)slot * TILE_PTS + l;
+      tiles([&](const Tile& t) {
+      const bool comp = t.comp;
+        const size_t idx = t.idx;
         double u = V(iu)[idx];
 #pragma unroll
         for (int k = 1; k <= PMAX; ++k)
@@ -587,8 +688,9 @@ struct Engine {
   // ------------------------------------------------------------ jobs
 
   __device__ bool copy_pass(int dst, int src) {
-    tiles([&](int slot, int l, bool comp, bool irr, gptr<const int> nb) {
-      const size_t idx = (size_t)slot * TILE_PTS + l;
+    tiles([&](const Tile& t) {
+      const bool comp = t.comp;
+      const size_t idx = t.idx;
       V(dst)[idx] = comp ? V(src)[idx] : 0.0;
     });
     bpu += 16.0;
@@ -610,9 +712,7 @@ struct Engine {
   // the active tiles (f sees comp), then a barrier.
   template <class F>
   __device__ bool pointwise(double bytes, F&& f) {
-    tiles([&](int slot, int l, bool comp, bool irr, gptr<const int> nb) {
-      f((size_t)slot * TILE_PTS + l, comp);
-    });
+    tiles([&](const Tile& t) { f(t.idx, t.comp); });
     bpu += bytes;
     return barrier();
   }
@@ -622,9 +722,10 @@ struct Engine {
     gptr<const double> a = V(va);
     gptr<const double> b = V(vb);
     double acc[1] = {0.0};
-    tiles([&](int slot, int l, bool comp, bool irr, gptr<const int> nb) {
-      const size_t idx = (size_t)slot * TILE_PTS + l;
-      acc[0] += b[idx] * apply_A<DIM>(P.g, a, slot, l, nb, comp, irr);
+    tiles([&](const Tile& t) {
+      const bool comp = t.comp;
+      const size_t idx = t.idx;
+      acc[0] += b[idx] * Av(t, a);
     });
     bpu += 16.0;
     double o[1];
@@ -757,9 +858,10 @@ struct Engine {
   __device__ void run() {
     const int mode = P.mode;
     if (mode == JOB_APPLY) {
-      tiles([&](int slot, int l, bool comp, bool irr, gptr<const int> nb) {
-        const size_t idx = (size_t)slot * TILE_PTS + l;
-        V(V_U)[idx] = apply_A<DIM>(P.g, V(V_B0), slot, l, nb, comp, irr);
+      tiles([&](const Tile& t) {
+      const bool comp = t.comp;
+        const size_t idx = t.idx;
+        V(V_U)[idx] = Av(t, V(V_B0));
       });
       bpu += 16.0;
       barrier();
