@@ -356,6 +356,7 @@ def main():
             "whole": prof["krylov_device_ms"] / max(args.steps, 1),
             "in_grid_sync": prof["krylov_sync_ms"] / max(args.steps, 1),
             "in_expm": prof["krylov_expm_ms"] / max(args.steps, 1),
+            "in_tile_loops": prof["krylov_tiles_ms"] / max(args.steps, 1),
             "syncs": prof["krylov_syncs"] / max(args.steps, 1),
             "expms": prof["krylov_expms"] / max(args.steps, 1),
         },

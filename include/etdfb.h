@@ -107,10 +107,12 @@ typedef struct {
   int32_t geometry_calls;
   int32_t n_unknowns;        /* computational points of the current geometry */
   /* inside the Krylov launches, from the device clock of block 0: whole
-   * launches, grid synchronisations (waiting included), small exponentials */
+   * launches, grid synchronisations (waiting included), small exponentials,
+   * tile loops of the passes */
   double krylov_device_ms;
   double krylov_sync_ms;
   double krylov_expm_ms;
+  double krylov_tiles_ms;
   int32_t krylov_syncs;
   int32_t krylov_expms;
 } etd_profile;

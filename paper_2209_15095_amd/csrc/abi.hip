@@ -603,6 +603,7 @@ int etd_ctx_profile_read(etd_ctx* c, etd_profile* out, int32_t reset) {
   out->krylov_device_ms = c->h_state->ticks_total / c->clock_khz;
   out->krylov_sync_ms = c->h_state->ticks_sync / c->clock_khz;
   out->krylov_expm_ms = c->h_state->ticks_expm / c->clock_khz;
+  out->krylov_tiles_ms = c->h_state->ticks_tiles / c->clock_khz;
   out->krylov_syncs = c->h_state->syncs;
   out->krylov_expms = c->h_state->expm_calls;
   if (reset) {
@@ -878,6 +879,7 @@ int etd_batch_profile_read(etd_batch* B, etd_profile* out, int32_t reset) {
   out->krylov_device_ms = c0->h_state->ticks_total / c0->clock_khz;
   out->krylov_sync_ms = c0->h_state->ticks_sync / c0->clock_khz;
   out->krylov_expm_ms = c0->h_state->ticks_expm / c0->clock_khz;
+  out->krylov_tiles_ms = c0->h_state->ticks_tiles / c0->clock_khz;
   out->krylov_syncs = c0->h_state->syncs;
   out->krylov_expms = c0->h_state->expm_calls;
   if (reset) {

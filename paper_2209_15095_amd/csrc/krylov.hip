@@ -40,7 +40,15 @@
 
 namespace etdfb {
 
+constexpr int META_TRIPS = 96;          // loop trips whose tile metadata a block keeps in LDS
+constexpr int NWAVE = KBLOCK / 64;
+
 struct Ctl {
+  // tile metadata of this block's first META_TRIPS loop trips (the same
+  // tiles every pass): mask words per wave, face-neighbour slots per tile
+  uint64_t mcw[META_TRIPS][NWAVE];
+  uint64_t miw[META_TRIPS][NWAVE];
+  int mnb[META_TRIPS][KTILES][6];
   // Lanczos data of the current substep (written by thread 0, read by all)
   double alpha[MMAX_LIMIT + 2];
   double nrm[MMAX_LIMIT + 2];
@@ -78,7 +86,7 @@ struct Engine {
   double bpu;
   // device-clock ticks spent in synchronisations and exponentials (kept by
   // thread 0 of block 0 of the group)
-  unsigned long long tk_sync, tk_expm;
+  unsigned long long tk_sync, tk_expm, tk_tiles;
   int n_sync;
 
   __device__ gptr<double> V(int i) const { return glb(P.ws) + (size_t)i * P.ld; }
@@ -191,9 +199,9 @@ struct Engine {
   // be issued without a branch and the trip costs one memory round trip.
   struct Tile {
     int slot, l;
-    size_t idx;
+    unsigned idx;
     bool comp, irr;
-    size_t ni[2 * DIM];
+    unsigned ni[2 * DIM];
     bool ok[2 * DIM];
   };
   // Per-wave metadata of a trip (prefetched one trip ahead).
@@ -202,9 +210,9 @@ struct Engine {
     int nb[2 * DIM];
   };
 
-  __device__ void load_meta(Meta& m, int slot, int w) const {
-    m.cw = glb(P.g.comp_bits)[(size_t)slot * 4 + w];
-    m.iw = glb(P.g.irr_bits)[(size_t)slot * 4 + w];
+  __device__ void load_meta(Meta& m, int slot, int wt) const {
+    m.cw = glb(P.g.comp_bits)[(size_t)slot * 4 + wt];
+    m.iw = glb(P.g.irr_bits)[(size_t)slot * 4 + wt];
     gptr<const int> nbp = glb(P.g.nbr) + (size_t)slot * NBR_STRIDE;
 #pragma unroll
     for (int d = 0; d < 2 * DIM; ++d) m.nb[d] = nbp[d];
@@ -214,7 +222,7 @@ struct Engine {
     constexpr int X = TileShape<DIM>::X, Y = TileShape<DIM>::Y, Z = TileShape<DIM>::Z;
     t.slot = slot;
     t.l = l;
-    t.idx = (size_t)slot * TILE_PTS + l;
+    t.idx = (unsigned)slot * TILE_PTS + l;
     t.comp = (m.cw >> (l & 63)) & 1ull;
     t.irr = t.comp && ((m.iw >> (l & 63)) & 1ull);
     const int lc[3] = {l % X, (l / X) % Y, l / (X * Y)};
@@ -227,37 +235,69 @@ struct Engine {
       const int nlo = m.nb[2 * d];
       t.ok[2 * d] = in_lo || nlo >= 0;
       t.ni[2 * d] = in_lo ? t.idx - str[d]
-                          : (nlo >= 0 ? (size_t)nlo * TILE_PTS + l + str[d] * (ext[d] - 1) : t.idx);
+                          : (nlo >= 0 ? (unsigned)nlo * TILE_PTS + l + str[d] * (ext[d] - 1) : t.idx);
       // +e_d: inside the tile, or the first layer of the neighbour tile
       const bool in_hi = lc[d] < ext[d] - 1;
       const int nhi = m.nb[2 * d + 1];
       t.ok[2 * d + 1] = in_hi || nhi >= 0;
       t.ni[2 * d + 1] = in_hi ? t.idx + str[d]
-                              : (nhi >= 0 ? (size_t)nhi * TILE_PTS + l - str[d] * (ext[d] - 1) : t.idx);
+                              : (nhi >= 0 ? (unsigned)nhi * TILE_PTS + l - str[d] * (ext[d] - 1) : t.idx);
     }
   }
 
+  // Metadata of loop trip r at `slot` for wave w (tile sub of the block):
+  // from LDS for the first META_TRIPS trips, else from global memory.
+  __device__ __forceinline__ void trip_meta(Meta& m, int r, int slot, int sub, int w) const {
+    if (r < META_TRIPS) {
+      m.cw = c.mcw[r][w];
+      m.iw = c.miw[r][w];
+#pragma unroll
+      for (int d = 0; d < 2 * DIM; ++d) m.nb[d] = c.mnb[r][sub][d];
+    } else {
+      load_meta(m, slot, w & 3);
+    }
+  }
+
+  // Fill the LDS metadata of this block's trips (once per launch).
+  __device__ void cache_meta() {
+    const int stride = G * KTILES;
+    const int sub = (int)(threadIdx.x / TILE_PTS);
+    const int l = (int)(threadIdx.x % TILE_PTS);
+    const int w = (int)(threadIdx.x >> 6);
+    for (int r = 0; r < META_TRIPS; ++r) {
+      const int slot = lb * KTILES + sub + r * stride;
+      if (slot >= nact) break;
+      if ((l & 63) == 0) {
+        c.mcw[r][w] = glb(P.g.comp_bits)[(size_t)slot * 4 + (l >> 6)];
+        c.miw[r][w] = glb(P.g.irr_bits)[(size_t)slot * 4 + (l >> 6)];
+      }
+      if (l < 2 * DIM) c.mnb[r][sub][l] = glb(P.g.nbr)[(size_t)slot * NBR_STRIDE + l];
+    }
+    __syncthreads();
+  }
+
   // Loop over the active tiles of this block (KTILES tiles per trip, one per
-  // 256 threads); f(tile point).  The next trip's metadata loads are issued
-  // before the current trip's data loads.  No block synchronisation inside:
-  // nothing is shared through LDS.
+  // 256 threads); f(tile point).  Metadata comes from LDS or is prefetched a
+  // trip ahead.  No block synchronisation inside: LDS is only read.
   template <class F>
   __device__ void tiles(F&& f) {
     const int sub = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / TILE_PTS));
     const int l = (int)(threadIdx.x % TILE_PTS);
-    const int w = __builtin_amdgcn_readfirstlane(l >> 6);
+    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int stride = G * KTILES;
     int slot = lb * KTILES + sub;
+    const unsigned long long t_in = wall_clock64();
     Meta m;
-    if (slot < nact) load_meta(m, slot, w);
-    while (slot < nact) {
+    if (slot < nact) trip_meta(m, 0, slot, sub, w);
+    for (int r = 0; slot < nact; ++r) {
       Tile t;
       make_tile(t, slot, l, m);
       const int next = slot + stride;
-      if (next < nact) load_meta(m, next, w);
+      if (next < nact) trip_meta(m, r + 1, next, sub, w);
       f(t);
       slot = next;
     }
+    if (threadIdx.x == 0 && lb == 0) tk_tiles += wall_clock64() - t_in;
   }
 
   // (A v) at the point: beta/h^2 (sum of neighbours - c_p v_p), 0 off the
@@ -364,7 +404,7 @@ struct Engine {
     double acc[2] = {0.0, 0.0};
     tiles([&](const Tile& t) {
       // every load of the point first (one memory round trip), then the math
-      size_t ix[NP];
+      unsigned ix[NP];
 #pragma unroll
       for (int d = 0; d < 2 * DIM; ++d) ix[d] = t.ni[d];
       ix[NP - 1] = t.idx;
@@ -856,6 +896,7 @@ struct Engine {
   }
 
   __device__ void run() {
+    cache_meta();
     const int mode = P.mode;
     if (mode == JOB_APPLY) {
       tiles([&](const Tile& t) {
@@ -892,7 +933,7 @@ template <int DIM>
 __device__ __forceinline__ void krylov_body(const KrylovDev& P, int lb, int G, Ctl& c, double* R, double* S) {
   const unsigned long long t_start = wall_clock64();
   Engine<DIM> e{P, c, R, S, *P.g.n_active, 0, lb, G};
-  e.tk_sync = e.tk_expm = 0;
+  e.tk_sync = e.tk_expm = e.tk_tiles = 0;
   e.n_sync = 0;
   for (int k = 0; k <= PMAX; ++k) {
     if (threadIdx.x == 0) {
@@ -927,6 +968,7 @@ __device__ __forceinline__ void krylov_body(const KrylovDev& P, int lb, int G, C
     P.st->ticks_total += (double)(wall_clock64() - t_start);
     P.st->ticks_sync += (double)e.tk_sync;
     P.st->ticks_expm += (double)e.tk_expm;
+    P.st->ticks_tiles += (double)e.tk_tiles;
     P.st->syncs += e.n_sync;
     P.st->expm_calls += e.expms;
   }
