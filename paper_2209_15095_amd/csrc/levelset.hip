@@ -228,6 +228,100 @@ __global__ __launch_bounds__(256) void extend_kernel(const LsInst* __restrict__ 
   }
 }
 
+// 2D only: SWEEP_GROUP Jacobi sweeps of extend_kernel in one launch.  The
+// block stages its tile plus a halo of SWEEP_GROUP nodes in LDS (values,
+// normals, source, known bit, sign of rho), sweeps there (the valid region
+// shrinks by one node per sweep) and writes the tile.  Halo nodes outside the
+// stage's list hold their whole-box values (0, see levelset.h), so the tile
+// gets exactly the values of `nsweep` single sweeps.
+constexpr int SWEEP_GROUP = 5;
+
+__global__ __launch_bounds__(256) void extend_group_kernel(const LsInst* __restrict__ insts,
+                                                           const int* __restrict__ off, int count, int list,
+                                                           int v_arr, int out_arr, int src_arr, int bit,
+                                                           int sign_rho, int do_max, int nsweep) {
+  constexpr int X = TileShape<2>::X, Y = TileShape<2>::Y, K = SWEEP_GROUP;
+  constexpr int RW = X + 2 * K, RH = Y + 2 * K, RN = RW * RH;
+  __shared__ double va[RN], vb[RN], snx[RN], sny[RN], ssrc[RN];
+  __shared__ uint8_t sfl[RN];   // bit 0: in the box, bit 1: known, bits 2-3: sign(rho) + 1
+  __shared__ double sm[256];
+  const Where w = locate<2>(insts, off, count, list);
+  const LsInst& I = *w.I;
+  const int ox = w.i - (int)(threadIdx.x % X), oy = w.j - (int)(threadIdx.x / X);   // tile origin
+  gptr<const double> v = arr(I, v_arr);
+  gptr<const double> nxg = arr(I, A_NX);
+  gptr<const double> nyg = arr(I, A_NY);
+  gptr<const uint8_t> kn = glb((const uint8_t*)I.known);
+  gptr<const double> rho = glb((const double*)I.rho);
+  for (int r = threadIdx.x; r < RN; r += blockDim.x) {
+    const int gi = ox - K + r % RW, gj = oy - K + r / RW;
+    uint8_t f = 0;
+    double x = 0.0, a = 0.0, b = 0.0, sc = 0.0;
+    if (gi >= 0 && gi < I.nx && gj >= 0 && gj < I.ny) {
+      const size_t id = (size_t)gj * I.nx + gi;
+      x = v[id];
+      a = nxg[id];
+      b = nyg[id];
+      sc = (src_arr >= 0) ? arr(I, src_arr)[id] : 0.0;
+      f = 1 | ((((kn[id] >> bit) & 1) != 0) ? 2 : 0);
+      if (sign_rho) {
+        const double rr = rho[id];
+        f |= (uint8_t)(((rr > 0.0) ? 2 : ((rr < 0.0) ? 0 : 1)) << 2);
+      } else {
+        f |= (uint8_t)(2 << 2);
+      }
+    }
+    va[r] = x;
+    snx[r] = a;
+    sny[r] = b;
+    ssrc[r] = sc;
+    sfl[r] = f;
+  }
+  __syncthreads();
+  const double dt = 0.5 * I.h;
+  double* cur = va;
+  double* nxt = vb;
+  for (int s = 0; s < nsweep; ++s) {
+    for (int r = threadIdx.x; r < RN; r += blockDim.x) {
+      const uint8_t f = sfl[r];
+      const double vc = cur[r];
+      double res = vc;
+      if ((f & 1) && !(f & 2)) {
+        const int x = r % RW, y = r / RW;
+        const int gi = ox - K + x, gj = oy - K + y;
+        // neighbours, clamped at the box edge; outside the region: the node itself
+        // (such nodes are beyond the valid region of this sweep)
+        const int rxm = (gi == 0 || x == 0) ? r : r - 1;
+        const int rxp = (gi == I.nx - 1 || x == RW - 1) ? r : r + 1;
+        const int rym = (gj == 0 || y == 0) ? r : r - RW;
+        const int ryp = (gj == I.ny - 1 || y == RH - 1) ? r : r + RW;
+        const double sg = (double)((f >> 2) & 3) - 1.0;
+        const double ax = sg * snx[r], ay = sg * sny[r];
+        double up = fmax(ax, 0.0) * (vc - cur[rxm]) + fmin(ax, 0.0) * (cur[rxp] - vc);
+        up += fmax(ay, 0.0) * (vc - cur[rym]) + fmin(ay, 0.0) * (cur[ryp] - vc);
+        up = up / I.h;
+        res = vc - dt * (up - ssrc[r]);
+      }
+      nxt[r] = res;
+    }
+    __syncthreads();
+    double* t = cur; cur = nxt; nxt = t;
+  }
+  const int l = threadIdx.x;
+  const double res = cur[(l / X + K) * RW + (l % X + K)];
+  if (w.in) arr(I, out_arr)[w.id] = res;
+  if (do_max) {
+    sm[threadIdx.x] = w.in ? res : 0.0;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+      if ((int)threadIdx.x < st) sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + st]);
+      __syncthreads();
+    }
+    if (threadIdx.x == 0)
+      atomicMax((unsigned long long*)I.vmax, (unsigned long long)__double_as_longlong(sm[0]));
+  }
+}
+
 // list V: V = (|rho| < h) ? mu |central grad u_ext| : 0; speed band into bit 3
 template <int DIM>
 __global__ __launch_bounds__(256) void velocity_kernel(const LsInst* __restrict__ insts,
@@ -382,30 +476,42 @@ hipError_t begin_dim(LevelsetBatch& b, hipStream_t st) {
   LL(LS_A1, known2_un_kernel);
   LL(LS_A1, unn_kernel);
   // Aslam: u_nn on A1 (E2 <-> E3, result E3), u_n on A2 (E1 <-> E2, src u_nn,
-  // result E2), u on A3 (E0 <-> E1, src u_n, result E1); ASLAM_ITERS is odd,
-  // and each partner array is 0 outside its stage's list
-  static_assert(ASLAM_ITERS % 2 == 1, "ping-pong bookkeeping assumes an odd sweep count");
-  for (int it = 0; it < ASLAM_ITERS; ++it) {
-    const bool ev = (it % 2) == 0;
-    LL(LS_A1, extend_kernel, (int)LS_A1, ev ? A_E2 : A_E3, ev ? A_E3 : A_E2, -1, 2, 0, 0);
-  }
-  for (int it = 0; it < ASLAM_ITERS; ++it) {
-    const bool ev = (it % 2) == 0;
-    LL(LS_A2, extend_kernel, (int)LS_A2, ev ? A_E1 : A_E2, ev ? A_E2 : A_E1, (int)A_E3, 1, 0, 0);
-  }
-  for (int it = 0; it < ASLAM_ITERS; ++it) {
-    const bool ev = (it % 2) == 0;
-    LL(LS_A3, extend_kernel, (int)LS_A3, ev ? A_E0 : A_E1, ev ? A_E1 : A_E0, (int)A_E2, 0, 0, 0);
-  }
-  b.uext = A_E1;
-  // Stefan speed, extension V <-> S (even count: ends in V), maximum on the
-  // last sweep
-  static_assert(VEL_ITERS % 2 == 0, "the speed extension must end in V");
+  // result E2), u on A3 (E0 <-> E1, src u_n, result E1); each stage's array
+  // alternates once per launch (2D: SWEEP_GROUP sweeps per launch, 3D: one),
+  // the launch counts per stage are odd, and each partner array is 0 outside
+  // its stage's list
+  const int group = (DIM == 2) ? SWEEP_GROUP : 1;
+  auto stage = [&](int list, int a0, int a1, int src, int bit, int sign_rho, int sweeps, int do_max) -> int {
+    int v = a0, t = a1;
+    for (int done = 0; done < sweeps;) {
+      const int ns = (sweeps - done < group) ? sweeps - done : group;
+      const int mx = (do_max && done + ns == sweeps) ? 1 : 0;
+      if (b.total[list] > 0) {
+        if (DIM == 2)
+          hipLaunchKernelGGL(extend_group_kernel, dim3(b.total[list]), B, 0, st, I, off, n, list, v, t, src, bit,
+                             sign_rho, mx, ns);
+        else
+          hipLaunchKernelGGL(extend_kernel<DIM>, dim3(b.total[list]), B, 0, st, I, off, n, list, v, t, src, bit,
+                             sign_rho, mx);
+        if (hipGetLastError() != hipSuccess) return -1;
+      }
+      done += ns;
+      const int x = v; v = t; t = x;
+    }
+    return v;
+  };
+  static_assert((ASLAM_ITERS + SWEEP_GROUP - 1) / SWEEP_GROUP % 2 == 1 && ASLAM_ITERS % 2 == 1,
+                "the Aslam stages must end in the partner array");
+  static_assert((VEL_ITERS + SWEEP_GROUP - 1) / SWEEP_GROUP % 2 == 0 && VEL_ITERS % 2 == 0,
+                "the speed extension must end in V");
+  const int unn = stage(LS_A1, A_E2, A_E3, -1, 2, 0, ASLAM_ITERS, 0);
+  const int un = stage(LS_A2, A_E1, A_E2, A_E3, 1, 0, ASLAM_ITERS, 0);
+  const int uext = stage(LS_A3, A_E0, A_E1, A_E2, 0, 0, ASLAM_ITERS, 0);
+  if (unn != A_E3 || un != A_E2 || uext != A_E1) return hipErrorUnknown;
+  b.uext = uext;
+  // Stefan speed, extension V <-> S (ends in V), maximum on the last sweep
   LL(LS_V, velocity_kernel, b.uext);
-  for (int it = 0; it < VEL_ITERS; ++it) {
-    const bool ev = (it % 2) == 0;
-    LL(LS_V, extend_kernel, (int)LS_V, ev ? A_V : A_S, ev ? A_S : A_V, -1, 3, 1, it == VEL_ITERS - 1 ? 1 : 0);
-  }
+  if (stage(LS_V, A_V, A_S, -1, 3, 1, VEL_ITERS, 1) != A_V) return hipErrorUnknown;
 #undef LL
   return hipSuccess;
 }
@@ -447,6 +553,9 @@ hipError_t end_dim(LevelsetBatch& b, hipStream_t st) {
 hipError_t levelset_alloc(LevelsetScratch& s, size_t nodes) {
   s.nodes = nodes;
   hipError_t e = hipMalloc(&s.buf, sizeof(double) * nodes * A_COUNT);
+  if (e != hipSuccess) return e;
+  // every array starts finite (sweeps may read arrays outside their lists)
+  e = hipMemset(s.buf, 0, sizeof(double) * nodes * A_COUNT);
   if (e != hipSuccess) return e;
   e = hipMalloc(&s.known, nodes);
   if (e != hipSuccess) return e;
