@@ -551,9 +551,12 @@ struct Engine {
 
   // ------------------------------------------------------------ phi combo
 
-  // U <- sum_{k=0}^{p} phi_k(tend A) b_k with b_0 = U on entry and b_k (k>=1)
-  // in V_B0 + k.  Returns false on failure (status set).
-  __device__ bool phi_comb(int p, double tend) {
+  // V_U <- sum_{k=0}^{p} phi_k(tend A) b_k with b_0 in vector b0 (not
+  // written) and b_k (k>=1) in V_B0 + k.  The substeps alternate between
+  // V_U and V_T, starting with V_U, so a single substep needs no copy.
+  // Returns false on failure (status set).
+  __device__ bool phi_comb(int p, double tend, int b0) {
+    iu = b0;
     if (tend == 0.0) {
       // phi_k(0) = 1/k!
       double f = 1.0;
@@ -561,14 +564,15 @@ struct Engine {
 #pragma unroll
       for (int k = 0; k <= PMAX; ++k) { if (k > 0) f *= k; ck[k] = 1.0 / f; }
       tiles([&](const Tile& t) {
-      const bool comp = t.comp;
         const size_t idx = t.idx;
         double u = V(iu)[idx];
 #pragma unroll
         for (int k = 1; k <= PMAX; ++k)
           if (k <= p) u += ck[k] * V(V_B0 + k)[idx];
-        V(iu)[idx] = comp ? u : 0.0;
+        V(V_U)[idx] = t.comp ? u : 0.0;
       });
+      bpu += 8.0 * (p + 2);
+      iu = V_U;
       return barrier();
     }
     const double tol = P.tol;
@@ -774,7 +778,7 @@ struct Engine {
     return true;
   }
 
-  // Inputs of stage `stage` of the job: V_U = b_0 and V_B0 + k = b_k
+  // Inputs of stage `stage` of the job: b_0 in vector b0 and b_k = V_B0 + k
   // (k >= 1) of the combination sum_k phi_k(t A) b_k, its p and t.
   //
   // Adjoint of ETD2RK (A symmetric, A = beta A_1, g = dL/dU_{n+1},
@@ -788,15 +792,19 @@ struct Engine {
   //   stage 5: phi_0 (g + abar); + V_S                    -> dL/dU_n in V_U
   // and dL/dbeta += (h/beta)(<g, A v_f> + <abar, A v_s>), from
   // d/dbeta phi_k(h beta A_1) = (h/beta) A (phi_k - k phi_{k+1})(hA).
-  __device__ bool assemble(int mode, int stage, int& p, double& t) {
+  __device__ bool assemble(int mode, int stage, int& p, double& t, int& b0) {
     if (mode == JOB_PHI) {
+      // the gathered inputs are in place
       p = P.p;
       t = P.t;
-      return copy_pass(V_U, V_B0);
+      b0 = V_B0;
+      return true;
     }
     const double h = P.h;
     t = h;
+    b0 = V_X0;
     gptr<double> U = V(V_U);
+    gptr<double> T0 = V(V_T);
     gptr<double> B1 = V(V_B1);
     gptr<double> B2 = V(V_B2);
     gptr<double> B3 = V(V_B3);
@@ -805,15 +813,16 @@ struct Engine {
     gptr<const double> Aa = V(V_A);
     gptr<const double> AB = V(V_AB);
     if (mode == JOB_ADJ_ETD2RK) {
+      // b_0 in V_T (stages 1, 4, 5) or U_n itself
+      b0 = (stage == 1 || stage == 4 || stage == 5) ? V_T : V_X0;
       switch (stage) {
         case 0:
         case 2:
         case 3:
           p = (stage == 0) ? 1 : (stage == 2 ? 2 : 3);
-          return pointwise(stage == 0 ? 24.0 : (stage == 2 ? 32.0 : 48.0), [&](size_t i, bool comp) {
+          return pointwise(stage == 0 ? 16.0 : (stage == 2 ? 24.0 : 40.0), [&](size_t i, bool comp) {
             const double u = comp ? X[i] : 0.0;
             const double hF = comp ? h * react(u) : 0.0;
-            U[i] = u;
             B1[i] = hF;
             if (stage == 2) B2[i] = -hF;
             if (stage == 3) {
@@ -825,7 +834,7 @@ struct Engine {
         case 1:
           p = 2;
           return pointwise(32.0, [&](size_t i, bool comp) {
-            U[i] = 0.0;
+            T0[i] = 0.0;
             B1[i] = 0.0;
             B2[i] = comp ? G[i] : 0.0;
           });
@@ -833,31 +842,25 @@ struct Engine {
           p = 2;
           return pointwise(40.0, [&](size_t i, bool comp) {
             const double g = comp ? G[i] : 0.0;
-            U[i] = 0.0;
+            T0[i] = 0.0;
             B1[i] = comp ? h * (g + AB[i]) : 0.0;
             B2[i] = -h * g;
           });
         default:
           p = 0;
-          return pointwise(24.0, [&](size_t i, bool comp) { U[i] = comp ? G[i] + AB[i] : 0.0; });
+          return pointwise(24.0, [&](size_t i, bool comp) { T0[i] = comp ? G[i] + AB[i] : 0.0; });
       }
     }
     if (stage == 0) {
       // ETD1 / first ETD2RK stage: b_0 = U_n, b_1 = h F(U_n)
       p = 1;
-      return pointwise(24.0, [&](size_t i, bool comp) {
-        const double u = comp ? X[i] : 0.0;
-        B1[i] = comp ? h * react(u) : 0.0;
-        U[i] = u;
-      });
+      return pointwise(16.0, [&](size_t i, bool comp) { B1[i] = comp ? h * react(X[i]) : 0.0; });
     }
-    // ETD2RK final stage: b_0 = U_n, b_1 = h F(U_n), b_2 = h (F(a) - F(U_n))
+    // ETD2RK final stage: b_0 = U_n, b_1 = h F(U_n), b_2 = h (F(a) - F(U_n)),
+    // a = the first stage (in V_U, overwritten once b_2 is formed)
     p = 2;
-    return pointwise(32.0, [&](size_t i, bool comp) {
-      const double a = U[i];
-      const double u = comp ? X[i] : 0.0;
-      B2[i] = comp ? h * (react(a) - react(u)) : 0.0;
-      U[i] = u;
+    return pointwise(24.0, [&](size_t i, bool comp) {
+      B2[i] = comp ? h * (react(U[i]) - react(X[i])) : 0.0;
     });
   }
 
@@ -917,10 +920,10 @@ struct Engine {
     const int nstage = stages(mode);
     double dsum = 0.0;
     for (int stage = 0; stage < nstage; ++stage) {
-      int p = 0;
+      int p = 0, b0 = V_U;
       double t = 0.0;
-      if (!assemble(mode, stage, p, t)) return;
-      if (!phi_comb(p, t)) return;
+      if (!assemble(mode, stage, p, t, b0)) return;
+      if (!phi_comb(p, t, b0)) return;
       if (!post(mode, stage, dsum)) return;
     }
     if (mode == JOB_ADJ_ETD2RK && threadIdx.x == 0 && lb == 0) *P.dbeta += (P.h / P.beta) * dsum;
