@@ -58,6 +58,8 @@ struct etd_ctx {
   LevelsetScratch ls{};
   LevelsetBatch lsb{};
   int nband_host[LS_NLIST] = {};
+  // geometry-build table of this context (one instance)
+  GeomBatch gb{};
   // pinned host mirror for small readbacks
   int* h_counters = nullptr;
   KrylovStateDev* h_state = nullptr;
@@ -82,6 +84,11 @@ struct etd_batch {
   KrylovDev* d_params = nullptr;
   KrylovDev* h_params = nullptr;
   LevelsetBatch lsb{};        // level-set table of all instances
+  GeomBatch gb{};             // geometry table of all instances
+  const double** h_uptr = nullptr;   // user box arrays of the current step (pinned)
+  const double** d_uptr = nullptr;
+  hipEvent_t uptr_done = nullptr;    // the last upload of h_uptr has been read
+  bool uptr_pending = false;
   int* d_blk = nullptr;       // block -> instance, capacity entries per chunk
   int* h_blk = nullptr;
   hipEvent_t staged = nullptr;
@@ -258,25 +265,44 @@ int latched_status(etd_ctx* c) {
 // coefficients and the face-neighbour table, then an asynchronous copy of
 // the counters to pinned memory.  geometry_finish() reads them after the
 // caller has synchronised the stream.
+const int GEOM_RADII[5] = {ASLAM_ITERS + 1, 2 * ASLAM_ITERS + 1, 3 * ASLAM_ITERS + 1, VEL_ITERS + 1,
+                           VEL_ITERS + 4};
+
+// One entry of a geometry table: the context's arrays.
+GeomInst geom_inst(const etd_ctx* c) {
+  GeomInst I{};
+  I.b = c->box;
+  I.mask = c->mask;
+  I.tile_flag = c->tile_flag;
+  I.tile_vb = c->tile_vb;
+  I.tile_map = c->tile_map;
+  I.slot_tile = c->slot_tile;
+  I.comp_bits = c->comp_bits;
+  I.irr_bits = c->irr_bits;
+  I.cdiag = c->cdiag;
+  I.nbr = c->nbr;
+  I.band_tmp = c->band_tmp;
+  I.band_list = c->band_list;
+  I.counters = c->counters;
+  I.ws = c->ws;
+  I.ld = c->ld;
+  I.nodes = c->nodes;
+  I.ntiles = c->ntiles;
+  return I;
+}
+
 int geometry_enqueue(etd_ctx* c, const double* rho) {
   HIP_TRY(timer_begin(c->profiling, c->stream, c->t_geometry));
-  HIP_TRY(launch_fill_int(c->tile_flag, c->ntiles, 0, c->stream));
-  HIP_TRY(launch_fill_int(c->tile_vb, c->ntiles, 0, c->stream));
-  HIP_TRY(launch_fill_int(c->counters + 2, 3, 0, c->stream));
-  HIP_TRY(launch_classify(c->box, rho, c->mask, c->tile_flag, c->tile_vb, c->counters + 1, c->stream));
-  HIP_TRY(launch_scan_tiles(c->tile_flag, c->ntiles, c->tile_map, c->slot_tile, c->counters + 0, c->stream));
-  HIP_TRY(launch_tile_coeff(c->box, rho, c->mask, c->tile_map, c->comp_bits, c->irr_bits, c->cdiag,
-                            c->nbr, c->counters + 2, c->ntiles, c->stream));
-  static const int radii[5] = {ASLAM_ITERS + 1, 2 * ASLAM_ITERS + 1, 3 * ASLAM_ITERS + 1, VEL_ITERS + 1,
-                               VEL_ITERS + 4};
-  HIP_TRY(launch_band(c->box, c->tile_flag, c->tile_vb, radii, c->band_tmp, c->band_tmp + c->ntiles,
-                      c->band_list, c->counters + 8, c->stream));
+  c->gb.h_tab[0].rho = rho;
+  HIP_TRY(launch_geometry(c->gb, GEOM_RADII, c->stream));
   HIP_TRY(timer_end(c->profiling, c->stream, c->t_geometry));
-  HIP_TRY(hipMemcpyAsync(c->h_counters, c->counters, NCOUNTERS * sizeof(int), hipMemcpyDeviceToHost, c->stream));
   return ETD_OK;
 }
 
-int geometry_finish(etd_ctx* c) {
+// After the build and a stream synchronisation: cnt holds the context's
+// NCOUNTERS counters.
+int geometry_finish(etd_ctx* c, const int* cnt) {
+  memcpy(c->h_counters, cnt, sizeof(int) * NCOUNTERS);
   c->n_active_host = c->h_counters[0];
   for (int q = 0; q < LS_NLIST; ++q) c->nband_host[q] = c->h_counters[8 + q];
   choose_launch(c);
@@ -315,6 +341,7 @@ void free_all(etd_ctx* c) {
     if (p) (void)hipFree(p);
   levelset_free(c->ls);
   levelset_batch_free(c->lsb);
+  geom_batch_free(c->gb);
   timer_free(c->t_krylov);
   timer_free(c->t_levelset);
   timer_free(c->t_geometry);
@@ -418,6 +445,7 @@ int etd_ctx_create(const etd_grid* grid, const etd_physics* phys, const etd_kryl
   ok &= hipHostMalloc(&c->h_state, sizeof(KrylovStateDev)) == hipSuccess;
   ok &= levelset_alloc(c->ls, c->nodes) == hipSuccess;
   ok &= levelset_batch_alloc(c->lsb, 1, b.dim) == hipSuccess;
+  ok &= geom_batch_alloc(c->gb, 1, NCOUNTERS) == hipSuccess;
   if (!ok) {
     free_all(c);
     delete c;
@@ -433,6 +461,10 @@ int etd_ctx_create(const etd_grid* grid, const etd_physics* phys, const etd_kryl
   ok &= hipMemcpy(c->counters, zeros, sizeof(zeros), hipMemcpyHostToDevice) == hipSuccess;
   ok &= hipMemset(c->ws, 0, sizeof(double) * c->ld * NVEC) == hipSuccess;
   ok &= hipMemset(c->bar, 0, sizeof(BarrierDev)) == hipSuccess;
+  if (ok) {
+    c->gb.h_tab[0] = geom_inst(c);
+    ok &= geom_batch_prefix(c->gb) == hipSuccess;
+  }
   ok &= hipDeviceSynchronize() == hipSuccess;
   if (!ok) {
     free_all(c);
@@ -468,7 +500,7 @@ int etd_geometry_build(etd_ctx* c, const double* rho) {
   int r = geometry_enqueue(c, rho);
   if (r) return r;
   HIP_TRY(hipStreamSynchronize(c->stream));
-  return geometry_finish(c);
+  return geometry_finish(c, c->gb.h_cnt);
 }
 
 int etd_operator_apply(etd_ctx* c, const double* v, double* out) {
@@ -630,7 +662,11 @@ void batch_free(etd_batch* B) {
   if (B->h_params) (void)hipHostFree(B->h_params);
   if (B->h_blk) (void)hipHostFree(B->h_blk);
   if (B->staged) (void)hipEventDestroy(B->staged);
+  if (B->uptr_done) (void)hipEventDestroy(B->uptr_done);
+  if (B->h_uptr) (void)hipHostFree(B->h_uptr);
+  if (B->d_uptr) (void)hipFree(B->d_uptr);
   levelset_batch_free(B->lsb);
+  geom_batch_free(B->gb);
   timer_free(B->t_krylov);
   timer_free(B->t_levelset);
   timer_free(B->t_geometry);
@@ -725,6 +761,14 @@ int etd_batch_create(int32_t count, const etd_grid* grids, const etd_physics* ph
   ok &= hipHostMalloc(&B->h_blk, sizeof(int) * (size_t)B->capacity * B->nchunks) == hipSuccess;
   ok &= hipEventCreate(&B->staged) == hipSuccess;
   ok &= levelset_batch_alloc(B->lsb, count, B->dim) == hipSuccess;
+  ok &= hipHostMalloc(&B->h_uptr, sizeof(double*) * count) == hipSuccess;
+  ok &= hipMalloc(&B->d_uptr, sizeof(double*) * count) == hipSuccess;
+  ok &= hipEventCreateWithFlags(&B->uptr_done, hipEventDisableTiming) == hipSuccess;
+  ok &= geom_batch_alloc(B->gb, count, NCOUNTERS) == hipSuccess;
+  if (ok) {
+    for (int i = 0; i < count; ++i) B->gb.h_tab[i] = geom_inst(B->inst[i]);
+    ok &= geom_batch_prefix(B->gb) == hipSuccess;
+  }
   if (!ok) {
     batch_free(B);
     delete B;
@@ -759,16 +803,16 @@ int etd_batch_geometry_build(etd_batch* B, const double* const* rho) {
   if (!B || !rho) return ETD_ERR_INVALID;
   for (int i = 0; i < B->count; ++i)
     if (!rho[i]) return ETD_ERR_INVALID;
+  // the table upload reads pinned memory: the previous build has been
+  // synchronised, so it may be rewritten
+  for (int i = 0; i < B->count; ++i) B->gb.h_tab[i].rho = rho[i];
   HIP_TRY(timer_begin(B->profiling, B->stream, B->t_geometry));
-  for (int i = 0; i < B->count; ++i) {
-    const int r = geometry_enqueue(B->inst[i], rho[i]);
-    if (r) return r;
-  }
+  HIP_TRY(launch_geometry(B->gb, GEOM_RADII, B->stream));
   HIP_TRY(timer_end(B->profiling, B->stream, B->t_geometry));
   HIP_TRY(hipStreamSynchronize(B->stream));
   int first = ETD_OK;
   for (int i = 0; i < B->count; ++i) {
-    const int r = geometry_finish(B->inst[i]);
+    const int r = geometry_finish(B->inst[i], B->gb.h_cnt + (size_t)i * NCOUNTERS);
     if (r && !first) first = r;
   }
   return first;
@@ -801,16 +845,20 @@ int etd_batch_step(etd_batch* B, int32_t scheme, double h, double* const* u, dou
   }
   for (etd_ctx* c : B->inst)
     if (!c->have_geometry) return ETD_ERR_NO_GEOMETRY;
-  for (int i = 0; i < B->count; ++i) {
-    const int r = gather_to(B->inst[i], u[i], V_X0);
-    if (r) return r;
+  // the box pointers of this step, uploaded from pinned memory once the
+  // previous upload has been read
+  if (B->uptr_pending) {
+    HIP_TRY(hipEventSynchronize(B->uptr_done));
+    B->uptr_pending = false;
   }
+  for (int i = 0; i < B->count; ++i) B->h_uptr[i] = u[i];
+  HIP_TRY(hipMemcpyAsync(B->d_uptr, B->h_uptr, sizeof(double*) * B->count, hipMemcpyHostToDevice, B->stream));
+  HIP_TRY(hipEventRecord(B->uptr_done, B->stream));
+  B->uptr_pending = true;
+  HIP_TRY(launch_gather_batch(B->gb, B->d_uptr, V_X0, B->stream));
   int r = batch_run_krylov(B, scheme == ETD_SCHEME_ETD1 ? JOB_ETD1 : JOB_ETD2RK, h);
   if (r) return r;
-  for (int i = 0; i < B->count; ++i) {
-    r = scatter_from(B->inst[i], V_U, u[i]);
-    if (r) return r;
-  }
+  HIP_TRY(launch_scatter_batch(B->gb, (double* const*)B->d_uptr, V_U, B->stream));
   if (stats) {
     for (int i = 0; i < B->count; ++i) {
       r = fill_stats(B->inst[i], &stats[i]);

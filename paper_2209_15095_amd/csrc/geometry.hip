@@ -24,19 +24,25 @@
 // interpolant with a linear tail (eqs. 2.5-2.6), whose radial part vanishes
 // for three centres.
 #include <math.h>
+#include <string.h>
 
 #include "device_common.h"
 #include "launch.h"
 
 namespace etdfb {
 
-struct BoxDev {
-  int dim, nx, ny, nz;
-  int ntx, nty, ntz;
-  int tx, ty, tz;      // tile shape
-  double lo[3];
-  double dx;
-};
+using BoxDev = BoxHost;   // plain box description, the same on both sides
+
+// Batched launches: block b of a launch over the instances of a table works
+// for instance i with pre[i] <= b < pre[i+1] on its block b - pre[i].
+__device__ __forceinline__ int instance_of(const int* __restrict__ pre, int count, int b) {
+  int lo = 0, hi = count;   // pre[lo] <= b < pre[hi]
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (pre[mid] <= b) lo = mid; else hi = mid;
+  }
+  return lo;
+}
 
 __device__ __forceinline__ size_t node_index(const BoxDev& b, int i, int j, int k) {
   return ((size_t)k * b.ny + j) * b.nx + i;
@@ -46,48 +52,66 @@ __device__ __forceinline__ int tile_of(const BoxDev& b, int i, int j, int k) {
   return ((k / b.tz) * b.nty + (j / b.ty)) * b.ntx + (i / b.tx);
 }
 
-__global__ void fill_int_kernel(int* p, size_t n, int v) {
-  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
-    p[i] = v;
-}
-
-__global__ void classify_kernel(BoxDev b, const double* __restrict__ rho, uint8_t* __restrict__ mask,
-                                int* __restrict__ tile_flag, int* __restrict__ tile_vb, int* __restrict__ status) {
-  const size_t total = (size_t)b.nx * b.ny * b.nz;
-  for (size_t id = blockIdx.x * (size_t)blockDim.x + threadIdx.x; id < total;
-       id += (size_t)gridDim.x * blockDim.x) {
-    const int i = (int)(id % b.nx);
-    const int j = (int)((id / b.nx) % b.ny);
-    const int k = (int)(id / ((size_t)b.nx * b.ny));
-    const bool inside = rho[id] < 0.0;
-    bool comp = inside;
-    if (comp) {
-      if (i == 0 || i == b.nx - 1 || j == 0 || j == b.ny - 1) comp = false;
-      if (b.dim == 3 && (k == 0 || k == b.nz - 1)) comp = false;
+__device__ __forceinline__ void classify_node(const BoxDev& b, const double* __restrict__ rho,
+                                              uint8_t* __restrict__ mask, int* __restrict__ tile_flag,
+                                              int* __restrict__ tile_vb, int* __restrict__ status, size_t id) {
+  const int i = (int)(id % b.nx);
+  const int j = (int)((id / b.nx) % b.ny);
+  const int k = (int)(id / ((size_t)b.nx * b.ny));
+  const bool inside = rho[id] < 0.0;
+  bool comp = inside;
+  if (comp) {
+    if (i == 0 || i == b.nx - 1 || j == 0 || j == b.ny - 1) comp = false;
+    if (b.dim == 3 && (k == 0 || k == b.nz - 1)) comp = false;
+  }
+  if (comp) {
+    comp = rho[id - 1] < 0.0 && rho[id + 1] < 0.0 && rho[id - b.nx] < 0.0 && rho[id + b.nx] < 0.0;
+    if (b.dim == 3) {
+      const size_t sz = (size_t)b.nx * b.ny;
+      comp = comp && rho[id - sz] < 0.0 && rho[id + sz] < 0.0;
     }
-    if (comp) {
-      comp = rho[id - 1] < 0.0 && rho[id + 1] < 0.0 && rho[id - b.nx] < 0.0 && rho[id + b.nx] < 0.0;
-      if (b.dim == 3) {
-        const size_t sz = (size_t)b.nx * b.ny;
-        comp = comp && rho[id - sz] < 0.0 && rho[id + sz] < 0.0;
-      }
-    }
-    mask[id] = comp ? 2 : (inside ? 1 : 0);
-    if (fabs(rho[id]) < b.dx) tile_vb[tile_of(b, i, j, k)] = 1;   // a node of the speed band
-    if (comp) {
-      tile_flag[tile_of(b, i, j, k)] = 1;
-      bool edge = i < 2 || i > b.nx - 3 || j < 2 || j > b.ny - 3;
-      if (b.dim == 3) edge = edge || k < 2 || k > b.nz - 3;
-      if (edge) atomicCAS(status, 0, ST_DOMAIN);
-    }
+  }
+  mask[id] = comp ? 2 : (inside ? 1 : 0);
+  if (fabs(rho[id]) < b.dx) tile_vb[tile_of(b, i, j, k)] = 1;   // a node of the speed band
+  if (comp) {
+    tile_flag[tile_of(b, i, j, k)] = 1;
+    bool edge = i < 2 || i > b.nx - 3 || j < 2 || j > b.ny - 3;
+    if (b.dim == 3) edge = edge || k < 2 || k > b.nz - 3;
+    if (edge) atomicCAS(status, 0, ST_DOMAIN);
   }
 }
 
-// One block of 1024 threads: exclusive scan of tile flags.
-__global__ __launch_bounds__(1024) void scan_tiles_kernel(const int* __restrict__ tile_flag, int ntiles,
-                                                          int* __restrict__ tile_map,
-                                                          int* __restrict__ slot_tile,
-                                                          int* __restrict__ n_active) {
+// Zero the tile flags and the per-build counters ([2..4]) of every instance;
+// blocks over ceil(ntiles / 256) per instance (prefix pre).
+__global__ __launch_bounds__(256) void geom_zero_kernel(const GeomInst* __restrict__ tab,
+                                                        const int* __restrict__ pre, int count) {
+  const int inst = instance_of(pre, count, (int)blockIdx.x);
+  const GeomInst& I = tab[inst];
+  const int t = (int)(blockIdx.x - pre[inst]) * 256 + (int)threadIdx.x;
+  if (t < I.ntiles) {
+    I.tile_flag[t] = 0;
+    I.tile_vb[t] = 0;
+  }
+  if (blockIdx.x == (unsigned)pre[inst] && threadIdx.x < 3) I.counters[2 + threadIdx.x] = 0;
+}
+
+// Classification, 256 nodes per block (prefix over ceil(nodes / 256)).
+__global__ __launch_bounds__(256) void classify_kernel(const GeomInst* __restrict__ tab,
+                                                       const int* __restrict__ pre, int count) {
+  const int inst = instance_of(pre, count, (int)blockIdx.x);
+  const GeomInst& I = tab[inst];
+  const size_t id = (size_t)(blockIdx.x - pre[inst]) * 256 + threadIdx.x;
+  if (id < I.nodes) classify_node(I.b, I.rho, I.mask, I.tile_flag, I.tile_vb, I.counters + 1, id);
+}
+
+// One block of 1024 threads per instance: exclusive scan of tile flags.
+__global__ __launch_bounds__(1024) void scan_tiles_kernel(const GeomInst* __restrict__ tab) {
+  const GeomInst& I = tab[blockIdx.x];
+  const int* __restrict__ tile_flag = I.tile_flag;
+  const int ntiles = I.ntiles;
+  int* __restrict__ tile_map = I.tile_map;
+  int* __restrict__ slot_tile = I.slot_tile;
+  int* __restrict__ n_active = I.counters + 0;
   __shared__ int warp_tot[16];
   __shared__ int carry;
   if (threadIdx.x == 0) carry = 0;
@@ -127,12 +151,27 @@ __global__ __launch_bounds__(1024) void scan_tiles_kernel(const int* __restrict_
 // from a tile with a computational point in the low 16 bits, from a tile
 // with a node |rho| < h in the high 16 bits; the first pass (axis 0) starts
 // from the two flag arrays.
-__global__ void band_dist_kernel(BoxDev b, const int* __restrict__ comp_flag, const int* __restrict__ vb_flag,
-                                 const int* __restrict__ in, int* __restrict__ out, int axis, int r, int cap) {
-  const int ntiles = b.ntx * b.nty * b.ntz;
+// Blocks over ceil(ntiles / 256) per instance (prefix pre); the pass of
+// axis a reads band_tmp[(a+1) % 2] (axis 0: the flags) and writes
+// band_tmp[a % 2], each half of the instance's 2 * ntiles scratch.  r: tile
+// radius per axis (3 entries).
+__global__ __launch_bounds__(256) void band_dist_kernel(const GeomInst* __restrict__ tab,
+                                                        const int* __restrict__ pre, int count, int axis,
+                                                        int r0, int r1, int r2, int cap) {
+  const int inst = instance_of(pre, count, (int)blockIdx.x);
+  const GeomInst& I = tab[inst];
+  const BoxDev& b = I.b;
+  const int ntiles = I.ntiles;
+  const int* __restrict__ comp_flag = I.tile_flag;
+  const int* __restrict__ vb_flag = I.tile_vb;
+  const int* __restrict__ in = I.band_tmp + (size_t)((axis + 1) & 1) * ntiles;
+  int* __restrict__ out = I.band_tmp + (size_t)(axis & 1) * ntiles;
+  const int r = axis == 0 ? r0 : (axis == 1 ? r1 : r2);
   const int n[3] = {b.ntx, b.nty, b.ntz};
   const int text[3] = {b.tx, b.ty, b.tz};
-  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < ntiles; t += gridDim.x * blockDim.x) {
+  {
+    const int t = (int)(blockIdx.x - pre[inst]) * 256 + (int)threadIdx.x;
+    if (t >= ntiles) return;
     int c[3] = {t % b.ntx, (t / b.ntx) % b.nty, t / (b.ntx * b.nty)};
     const int c0 = c[axis];
     int dc = cap, dv = cap;
@@ -160,9 +199,13 @@ __global__ void band_dist_kernel(BoxDev b, const int* __restrict__ comp_flag, co
 
 // One block of 1024 threads: the tile lists of the level-set sweeps (in
 // tile order) from the packed distances, and their sizes.
-__global__ __launch_bounds__(1024) void band_lists_kernel(const int* __restrict__ dist, int ntiles,
-                                                          int* __restrict__ lists, int* __restrict__ counts,
+__global__ __launch_bounds__(1024) void band_lists_kernel(const GeomInst* __restrict__ tab, int last_axis,
                                                           int ra1, int ra2, int ra3, int rv, int rr) {
+  const GeomInst& I = tab[blockIdx.x];
+  const int ntiles = I.ntiles;
+  const int* __restrict__ dist = I.band_tmp + (size_t)(last_axis & 1) * ntiles;
+  int* __restrict__ lists = I.band_list;
+  int* __restrict__ counts = I.counters + 8;
   constexpr int NL = 6;
   __shared__ int wave_tot[16][NL];
   __shared__ int carry[NL];
@@ -273,15 +316,20 @@ __device__ double case3_weight(const BoxDev& b, const double* __restrict__ rho, 
 }
 
 // grid = one block (256 threads) per box tile; inactive tiles return.
-__global__ __launch_bounds__(256) void tile_coeff_kernel(BoxDev b, const double* __restrict__ rho,
-                                                         const uint8_t* __restrict__ mask,
-                                                         const int* __restrict__ tile_map,
-                                                         uint64_t* __restrict__ comp_bits,
-                                                         uint64_t* __restrict__ irr_bits,
-                                                         double* __restrict__ cdiag,
-                                                         int* __restrict__ nbr,
-                                                         int* __restrict__ counts) {
-  const int t = blockIdx.x;
+__global__ __launch_bounds__(256) void tile_coeff_kernel(const GeomInst* __restrict__ tab,
+                                                         const int* __restrict__ pre, int count) {
+  const int inst = instance_of(pre, count, (int)blockIdx.x);
+  const GeomInst& I = tab[inst];
+  const BoxDev& b = I.b;
+  const double* __restrict__ rho = I.rho;
+  const uint8_t* __restrict__ mask = I.mask;
+  const int* __restrict__ tile_map = I.tile_map;
+  uint64_t* __restrict__ comp_bits = I.comp_bits;
+  uint64_t* __restrict__ irr_bits = I.irr_bits;
+  double* __restrict__ cdiag = I.cdiag;
+  int* __restrict__ nbr = I.nbr;
+  int* __restrict__ counts = I.counters + 2;
+  const int t = (int)(blockIdx.x - pre[inst]);
   const int slot = tile_map[t];
   if (slot < 0) return;
   const int tcx = t % b.ntx, tcy = (t / b.ntx) % b.nty, tcz = t / (b.ntx * b.nty);
@@ -352,23 +400,44 @@ __global__ __launch_bounds__(256) void tile_coeff_kernel(BoxDev b, const double*
 }
 
 // box -> tile layout (0 at non-computational points).  grid >= cap tiles.
+__device__ __forceinline__ void gather_tile(const BoxDev& b, const double* __restrict__ box,
+                                            const int* __restrict__ slot_tile,
+                                            const uint64_t* __restrict__ comp_bits, int slot,
+                                            double* __restrict__ vec) {
+  const int t = slot_tile[slot];
+  const int l = threadIdx.x;
+  const int lx = l % b.tx, ly = (l / b.tx) % b.ty, lz = l / (b.tx * b.ty);
+  const int i = (t % b.ntx) * b.tx + lx;
+  const int j = ((t / b.ntx) % b.nty) * b.ty + ly;
+  const int k = (t / (b.ntx * b.nty)) * b.tz + lz;
+  double v = 0.0;
+  if (bit_of(comp_bits, slot, l)) v = box[node_index(b, i, j, k)];
+  vec[(size_t)slot * TILE_PTS + l] = v;
+}
+
+__device__ __forceinline__ void scatter_node(const BoxDev& b, const double* __restrict__ vec,
+                                             const int* __restrict__ tile_map,
+                                             const uint64_t* __restrict__ comp_bits, double* __restrict__ box,
+                                             size_t id) {
+  const int i = (int)(id % b.nx);
+  const int j = (int)((id / b.nx) % b.ny);
+  const int k = (int)(id / ((size_t)b.nx * b.ny));
+  const int slot = tile_map[tile_of(b, i, j, k)];
+  double v = 0.0;
+  if (slot >= 0) {
+    const int l = (i % b.tx) + b.tx * ((j % b.ty) + b.ty * (k % b.tz));
+    if (bit_of(comp_bits, slot, l)) v = vec[(size_t)slot * TILE_PTS + l];
+  }
+  box[id] = v;
+}
+
 __global__ __launch_bounds__(256) void gather_kernel(BoxDev b, const double* __restrict__ box,
                                                      const int* __restrict__ slot_tile,
                                                      const uint64_t* __restrict__ comp_bits,
                                                      const int* __restrict__ n_active,
                                                      double* __restrict__ vec) {
   const int nact = *n_active;
-  for (int slot = blockIdx.x; slot < nact; slot += gridDim.x) {
-    const int t = slot_tile[slot];
-    const int l = threadIdx.x;
-    const int lx = l % b.tx, ly = (l / b.tx) % b.ty, lz = l / (b.tx * b.ty);
-    const int i = (t % b.ntx) * b.tx + lx;
-    const int j = ((t / b.ntx) % b.nty) * b.ty + ly;
-    const int k = (t / (b.ntx * b.nty)) * b.tz + lz;
-    double v = 0.0;
-    if (bit_of(comp_bits, slot, l)) v = box[node_index(b, i, j, k)];
-    vec[(size_t)slot * TILE_PTS + l] = v;
-  }
+  for (int slot = blockIdx.x; slot < nact; slot += gridDim.x) gather_tile(b, box, slot_tile, comp_bits, slot, vec);
 }
 
 // tile layout -> box: computational nodes get the vector, all others 0.
@@ -376,31 +445,41 @@ __global__ void scatter_kernel(BoxDev b, const double* __restrict__ vec, const i
                                const uint64_t* __restrict__ comp_bits, double* __restrict__ box) {
   const size_t total = (size_t)b.nx * b.ny * b.nz;
   for (size_t id = blockIdx.x * (size_t)blockDim.x + threadIdx.x; id < total;
-       id += (size_t)gridDim.x * blockDim.x) {
-    const int i = (int)(id % b.nx);
-    const int j = (int)((id / b.nx) % b.ny);
-    const int k = (int)(id / ((size_t)b.nx * b.ny));
-    const int slot = tile_map[tile_of(b, i, j, k)];
-    double v = 0.0;
-    if (slot >= 0) {
-      const int l = (i % b.tx) + b.tx * ((j % b.ty) + b.ty * (k % b.tz));
-      if (bit_of(comp_bits, slot, l)) v = vec[(size_t)slot * TILE_PTS + l];
-    }
-    box[id] = v;
-  }
+       id += (size_t)gridDim.x * blockDim.x)
+    scatter_node(b, vec, tile_map, comp_bits, box, id);
+}
+
+// Batched transfers between the user box arrays boxes[i] and vector `vec`
+// of each instance's workspace: gather with one block per box tile of each
+// instance (prefix pre; blocks past the active tiles return), scatter with
+// 256 nodes per block (prefix pre).
+__global__ __launch_bounds__(256) void gather_batch_kernel(const GeomInst* __restrict__ tab,
+                                                           const int* __restrict__ pre, int count,
+                                                           const double* const* __restrict__ boxes, int vec) {
+  const int inst = instance_of(pre, count, (int)blockIdx.x);
+  const GeomInst& I = tab[inst];
+  const int slot = (int)(blockIdx.x - pre[inst]);
+  if (slot >= I.counters[0]) return;
+  gather_tile(I.b, boxes[inst], I.slot_tile, I.comp_bits, slot, I.ws + (size_t)vec * I.ld);
+}
+
+__global__ __launch_bounds__(256) void scatter_batch_kernel(const GeomInst* __restrict__ tab,
+                                                            const int* __restrict__ pre, int count,
+                                                            double* const* __restrict__ boxes, int vec) {
+  const int inst = instance_of(pre, count, (int)blockIdx.x);
+  const GeomInst& I = tab[inst];
+  const size_t id = (size_t)(blockIdx.x - pre[inst]) * 256 + threadIdx.x;
+  if (id < I.nodes) scatter_node(I.b, I.ws + (size_t)vec * I.ld, I.tile_map, I.comp_bits, boxes[inst], id);
+}
+
+// Counters of every instance into one contiguous array (ncnt per instance).
+__global__ void collect_counters_kernel(const GeomInst* __restrict__ tab, int count, int ncnt,
+                                        int* __restrict__ out) {
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < count * ncnt; e += gridDim.x * blockDim.x)
+    out[e] = tab[e / ncnt].counters[e % ncnt];
 }
 
 // ------------------------------------------------------------ launchers
-
-static BoxDev to_dev(const BoxHost& h) {
-  BoxDev b;
-  b.dim = h.dim; b.nx = h.nx; b.ny = h.ny; b.nz = h.nz;
-  b.ntx = h.ntx; b.nty = h.nty; b.ntz = h.ntz;
-  b.tx = h.tx; b.ty = h.ty; b.tz = h.tz;
-  for (int d = 0; d < 3; ++d) b.lo[d] = h.lo[d];
-  b.dx = h.dx;
-  return b;
-}
 
 static int blocks_for(size_t n, int bs) {
   size_t g = (n + bs - 1) / bs;
@@ -409,69 +488,102 @@ static int blocks_for(size_t n, int bs) {
   return (int)g;
 }
 
-hipError_t launch_fill_int(int* p, size_t n, int v, hipStream_t s) {
-  hipLaunchKernelGGL(fill_int_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, p, n, v);
-  return hipGetLastError();
+hipError_t geom_batch_alloc(GeomBatch& gb, int count, int ncnt) {
+  gb = GeomBatch{};
+  gb.count = count;
+  gb.ncnt = ncnt;
+  hipError_t e;
+  if ((e = hipHostMalloc(&gb.h_tab, sizeof(GeomInst) * count)) != hipSuccess) return e;
+  if ((e = hipMalloc(&gb.d_tab, sizeof(GeomInst) * count)) != hipSuccess) return e;
+  if ((e = hipHostMalloc(&gb.h_pre, sizeof(int) * GEOM_NPRE * (count + 1))) != hipSuccess) return e;
+  if ((e = hipMalloc(&gb.d_pre, sizeof(int) * GEOM_NPRE * (count + 1))) != hipSuccess) return e;
+  if ((e = hipHostMalloc(&gb.h_cnt, sizeof(int) * ncnt * count)) != hipSuccess) return e;
+  if ((e = hipMalloc(&gb.d_cnt, sizeof(int) * ncnt * count)) != hipSuccess) return e;
+  memset(gb.h_tab, 0, sizeof(GeomInst) * count);
+  return hipSuccess;
 }
 
-hipError_t launch_classify(const BoxHost& b, const double* rho, uint8_t* mask, int* tile_flag,
-                           int* tile_vb, int* status, hipStream_t s) {
-  const size_t n = (size_t)b.nx * b.ny * b.nz;
-  hipLaunchKernelGGL(classify_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, to_dev(b), rho, mask,
-                     tile_flag, tile_vb, status);
-  return hipGetLastError();
+void geom_batch_free(GeomBatch& gb) {
+  if (gb.h_tab) (void)hipHostFree(gb.h_tab);
+  if (gb.d_tab) (void)hipFree(gb.d_tab);
+  if (gb.h_pre) (void)hipHostFree(gb.h_pre);
+  if (gb.d_pre) (void)hipFree(gb.d_pre);
+  if (gb.h_cnt) (void)hipHostFree(gb.h_cnt);
+  if (gb.d_cnt) (void)hipFree(gb.d_cnt);
+  gb = GeomBatch{};
 }
 
-hipError_t launch_band(const BoxHost& b, const int* comp_flag, const int* vb_flag, const int* radii, int* tmp0,
-                       int* tmp1, int* lists, int* counts, hipStream_t s) {
-  const int ntiles = b.ntx * b.nty * b.ntz;
-  const int t[3] = {b.tx, b.ty, b.tz};
-  const BoxDev bd = to_dev(b);
+// Block prefix sums of the table (sizes do not change after creation);
+// synchronous upload.
+hipError_t geom_batch_prefix(GeomBatch& gb) {
+  const int n = gb.count;
+  int* p = gb.h_pre;
+  for (int q = 0; q < GEOM_NPRE; ++q) p[q * (n + 1)] = 0;
+  for (int i = 0; i < n; ++i) {
+    const GeomInst& I = gb.h_tab[i];
+    const int per[GEOM_NPRE] = {(int)((I.nodes + 255) / 256), (I.ntiles + 255) / 256, I.ntiles};
+    for (int q = 0; q < GEOM_NPRE; ++q) p[q * (n + 1) + i + 1] = p[q * (n + 1) + i] + per[q];
+  }
+  for (int q = 0; q < GEOM_NPRE; ++q) gb.blocks[q] = p[q * (n + 1) + n];
+  return hipMemcpy(gb.d_pre, gb.h_pre, sizeof(int) * GEOM_NPRE * (n + 1), hipMemcpyHostToDevice);
+}
+
+static const int* pre_of(const GeomBatch& gb, int q) { return gb.d_pre + q * (gb.count + 1); }
+
+hipError_t launch_geometry(GeomBatch& gb, const int* radii, hipStream_t s) {
+  const int n = gb.count;
+  hipError_t e = hipMemcpyAsync(gb.d_tab, gb.h_tab, sizeof(GeomInst) * n, hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(geom_zero_kernel, dim3(gb.blocks[GEOM_PRE_T256]), dim3(256), 0, s, gb.d_tab,
+                     pre_of(gb, GEOM_PRE_T256), n);
+  hipLaunchKernelGGL(classify_kernel, dim3(gb.blocks[GEOM_PRE_NODE]), dim3(256), 0, s, gb.d_tab,
+                     pre_of(gb, GEOM_PRE_NODE), n);
+  hipLaunchKernelGGL(scan_tiles_kernel, dim3(n), dim3(1024), 0, s, gb.d_tab);
+  hipLaunchKernelGGL(tile_coeff_kernel, dim3(gb.blocks[GEOM_PRE_TILE]), dim3(256), 0, s, gb.d_tab,
+                     pre_of(gb, GEOM_PRE_TILE), n);
+  // tile radii of the distance passes: tiles k apart are >= (k-1) t + 1 nodes apart
   int rmax = 0;
   for (int q = 0; q < 5; ++q) rmax = radii[q] > rmax ? radii[q] : rmax;
-  int* in = tmp0;
-  int* out = tmp1;
-  for (int axis = 0; axis < b.dim; ++axis) {
-    const int r = (rmax - 1) / t[axis] + 1;   // tiles k apart are >= (k-1) t + 1 nodes apart
-    hipLaunchKernelGGL(band_dist_kernel, dim3(blocks_for(ntiles, 256)), dim3(256), 0, s, bd, comp_flag, vb_flag,
-                       (const int*)in, out, axis, r, 1000);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    int* x = in; in = out; out = x;
-  }
-  hipLaunchKernelGGL(band_lists_kernel, dim3(1), dim3(1024), 0, s, (const int*)in, ntiles, lists, counts,
-                     radii[0], radii[1], radii[2], radii[3], radii[4]);
+  const BoxHost& b0 = gb.h_tab[0].b;
+  const int dim = b0.dim;
+  const int t[3] = {b0.tx, b0.ty, b0.tz};
+  int r[3];
+  for (int a = 0; a < 3; ++a) r[a] = (rmax - 1) / t[a] + 1;
+  for (int axis = 0; axis < dim; ++axis)
+    hipLaunchKernelGGL(band_dist_kernel, dim3(gb.blocks[GEOM_PRE_T256]), dim3(256), 0, s, gb.d_tab,
+                       pre_of(gb, GEOM_PRE_T256), n, axis, r[0], r[1], r[2], 1000);
+  hipLaunchKernelGGL(band_lists_kernel, dim3(n), dim3(1024), 0, s, gb.d_tab, dim - 1, radii[0], radii[1],
+                     radii[2], radii[3], radii[4]);
+  hipLaunchKernelGGL(collect_counters_kernel, dim3(blocks_for((size_t)n * gb.ncnt, 256)), dim3(256), 0, s,
+                     gb.d_tab, n, gb.ncnt, gb.d_cnt);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  return hipMemcpyAsync(gb.h_cnt, gb.d_cnt, sizeof(int) * gb.ncnt * n, hipMemcpyDeviceToHost, s);
+}
+
+hipError_t launch_gather_batch(const GeomBatch& gb, const double* const* d_boxes, int vec, hipStream_t s) {
+  hipLaunchKernelGGL(gather_batch_kernel, dim3(gb.blocks[GEOM_PRE_TILE]), dim3(256), 0, s, gb.d_tab,
+                     pre_of(gb, GEOM_PRE_TILE), gb.count, d_boxes, vec);
   return hipGetLastError();
 }
 
-hipError_t launch_scan_tiles(const int* tile_flag, int ntiles, int* tile_map, int* slot_tile,
-                             int* n_active, hipStream_t s) {
-  hipLaunchKernelGGL(scan_tiles_kernel, dim3(1), dim3(1024), 0, s, tile_flag, ntiles, tile_map, slot_tile,
-                     n_active);
-  return hipGetLastError();
-}
-
-hipError_t launch_tile_coeff(const BoxHost& b, const double* rho, const uint8_t* mask,
-                             const int* tile_map, uint64_t* comp_bits, uint64_t* irr_bits,
-                             double* cdiag, int* nbr, int* counts, int ntiles, hipStream_t s) {
-  hipLaunchKernelGGL(tile_coeff_kernel, dim3(ntiles), dim3(256), 0, s, to_dev(b), rho, mask, tile_map,
-                     comp_bits, irr_bits, cdiag, nbr, counts);
+hipError_t launch_scatter_batch(const GeomBatch& gb, double* const* d_boxes, int vec, hipStream_t s) {
+  hipLaunchKernelGGL(scatter_batch_kernel, dim3(gb.blocks[GEOM_PRE_NODE]), dim3(256), 0, s, gb.d_tab,
+                     pre_of(gb, GEOM_PRE_NODE), gb.count, d_boxes, vec);
   return hipGetLastError();
 }
 
 hipError_t launch_gather(const BoxHost& b, const double* box, const int* slot_tile,
                          const uint64_t* comp_bits, const int* n_active, double* vec, int grid,
                          hipStream_t s) {
-  hipLaunchKernelGGL(gather_kernel, dim3(grid), dim3(256), 0, s, to_dev(b), box, slot_tile, comp_bits,
-                     n_active, vec);
+  hipLaunchKernelGGL(gather_kernel, dim3(grid), dim3(256), 0, s, b, box, slot_tile, comp_bits, n_active, vec);
   return hipGetLastError();
 }
 
 hipError_t launch_scatter(const BoxHost& b, const double* vec, const int* tile_map,
                           const uint64_t* comp_bits, double* box, hipStream_t s) {
   const size_t n = (size_t)b.nx * b.ny * b.nz;
-  hipLaunchKernelGGL(scatter_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, to_dev(b), vec, tile_map,
-                     comp_bits, box);
+  hipLaunchKernelGGL(scatter_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, b, vec, tile_map, comp_bits,
+                     box);
   return hipGetLastError();
 }
 

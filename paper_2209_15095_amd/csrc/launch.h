@@ -16,20 +16,60 @@ struct BoxHost {
 };
 
 // geometry.hip
-hipError_t launch_fill_int(int* p, size_t n, int v, hipStream_t s);
-hipError_t launch_classify(const BoxHost& b, const double* rho, uint8_t* mask, int* tile_flag,
-                           int* tile_vb, int* status, hipStream_t s);
-// Level-set tile lists: L1 tile distances from the tiles with a
-// computational point and from those with a node |rho| < h, then the six
-// lists (radii[0..2] on the first distance, radii[3..4] on the second, and
-// the union of lists 2 and 4) into lists (6 * ntiles) and counts (6).
-hipError_t launch_band(const BoxHost& b, const int* comp_flag, const int* vb_flag, const int* radii, int* tmp0,
-                       int* tmp1, int* lists, int* counts, hipStream_t s);
-hipError_t launch_scan_tiles(const int* tile_flag, int ntiles, int* tile_map, int* slot_tile,
-                             int* n_active, hipStream_t s);
-hipError_t launch_tile_coeff(const BoxHost& b, const double* rho, const uint8_t* mask,
-                             const int* tile_map, uint64_t* comp_bits, uint64_t* irr_bits,
-                             double* cdiag, int* nbr, int* counts, int ntiles, hipStream_t s);
+//
+// The geometry build works on a table of instances (a single context is a
+// table of one): per instance its box, level set and output arrays.
+struct GeomInst {
+  BoxHost b;
+  const double* rho;     // level set (box layout), set per build
+  uint8_t* mask;
+  int* tile_flag;        // tiles with a computational point
+  int* tile_vb;          // tiles with a node |rho| < h
+  int* tile_map;
+  int* slot_tile;
+  uint64_t* comp_bits;
+  uint64_t* irr_bits;
+  double* cdiag;
+  int* nbr;
+  int* band_tmp;         // 2 * ntiles
+  int* band_list;        // 6 * ntiles
+  int* counters;         // [0] active tiles, [1] status, [2..3] case counts, [4] unknowns, [8..13] lists
+  double* ws;            // workspace vectors (gather / scatter targets)
+  size_t ld;
+  size_t nodes;
+  int ntiles;
+  int pad;
+};
+
+enum { GEOM_PRE_NODE = 0, GEOM_PRE_T256 = 1, GEOM_PRE_TILE = 2, GEOM_NPRE = 3 };
+
+struct GeomBatch {
+  int count = 0;
+  int ncnt = 0;                  // counters per instance
+  GeomInst* h_tab = nullptr;     // pinned; uploaded by launch_geometry
+  GeomInst* d_tab = nullptr;
+  int* h_pre = nullptr;          // GEOM_NPRE block prefixes of count + 1 entries
+  int* d_pre = nullptr;
+  int blocks[GEOM_NPRE] = {};    // launch sizes
+  int* h_cnt = nullptr;          // collected counters (pinned), ncnt per instance
+  int* d_cnt = nullptr;
+};
+
+hipError_t geom_batch_alloc(GeomBatch& gb, int count, int ncnt);
+void geom_batch_free(GeomBatch& gb);
+// After the table's sizes are filled in: block prefixes (synchronous).
+hipError_t geom_batch_prefix(GeomBatch& gb);
+// Whole build of every instance (classification, tile scan, Case 1-3
+// coefficients and face neighbours, level-set tile distances and lists with
+// radii[0..4]), then the counters of all instances into gb.h_cnt
+// (asynchronous: read after synchronising the stream).  The table's rho
+// pointers must be set; the table is uploaded from pinned memory, so it
+// must not change before the stream has passed this call.
+hipError_t launch_geometry(GeomBatch& gb, const int* radii, hipStream_t s);
+// Batched box <-> workspace-vector transfers; d_boxes: device array of the
+// instances' box pointers.
+hipError_t launch_gather_batch(const GeomBatch& gb, const double* const* d_boxes, int vec, hipStream_t s);
+hipError_t launch_scatter_batch(const GeomBatch& gb, double* const* d_boxes, int vec, hipStream_t s);
 hipError_t launch_gather(const BoxHost& b, const double* box, const int* slot_tile,
                          const uint64_t* comp_bits, const int* n_active, double* vec, int grid,
                          hipStream_t s);
