@@ -240,6 +240,34 @@ int etd_batch_sync(etd_batch* batch);
 /* Statistics of instance i's last job (synchronises). */
 int etd_batch_stats(etd_batch* batch, int32_t i, etd_stats* stats);
 
+/* Frozen-domain steps replayed from a HIP graph: nsteps etd_batch_step
+ * calls with rho = NULL, each one graph launch (batched gather, the batched
+ * persistent Krylov launch, batched scatter) with no host work between
+ * steps.  The graph is recorded on the first call and kept while scheme, h,
+ * the u pointers, the geometry and the group limit stay the same (any change
+ * records it again).  Its parameters live in device buffers of the batch,
+ * so eager calls in between do not alter it.  Results are those of
+ * etd_batch_step with the same group limit (the same kernels and launch
+ * shape).  The Krylov launch in the graph is an ordinary kernel node: its
+ * blocks (at most the co-resident capacity) must all be resident, which
+ * holds when no other work shares the GPU; otherwise the group barrier's
+ * bounded wait ends the step with ETD_ERR_BARRIER (reported by
+ * etd_batch_sync) rather than hanging.  Asynchronous; ETD_ERR_NO_GEOMETRY
+ * before the first geometry build; ETD_ERR_INVALID if the batch needs more
+ * than one launch per step (more instances than co-resident blocks). */
+int etd_batch_graph_steps(etd_batch* batch, int32_t scheme, double h, double* const* u, int32_t nsteps);
+
+/* Autotuner of the Krylov block schedule: times the batched persistent
+ * launch of one frozen-domain step (scheme, h, the current u of every
+ * instance) for the group limits 1, 2, 4, 8, 16 and 0 (unlimited; see
+ * etd_batch_set_group_limit), trials timed runs each after one untimed
+ * run, and keeps the fastest as the batch's group limit.  The Krylov
+ * adaptive state of every instance and the u arrays are left as they were.
+ * limit_out (nullable): the chosen limit; ms_out (nullable, 6 doubles): mean
+ * ms per launch of each candidate in the order above.  Synchronises. */
+int etd_batch_autotune(etd_batch* batch, int32_t scheme, double h, double* const* u, int32_t trials,
+                       int32_t* limit_out, double* ms_out);
+
 /* Event timing of the batch launches; profile_read sums the algorithmic
  * bytes and reports the unknowns over all instances. */
 int etd_batch_profile_enable(etd_batch* batch, int32_t enable);

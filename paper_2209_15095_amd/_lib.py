@@ -88,6 +88,9 @@ SIGNATURES = {
     "etd_batch_step": (C.c_int, [C.c_void_p, C.c_int32, C.c_double, C.POINTER(C.c_void_p),
                                  C.POINTER(C.c_void_p), C.c_int32, C.POINTER(EtdStats)]),
     "etd_batch_sync": (C.c_int, [C.c_void_p]),
+    "etd_batch_graph_steps": (C.c_int, [C.c_void_p, C.c_int32, C.c_double, C.POINTER(C.c_void_p), C.c_int32]),
+    "etd_batch_autotune": (C.c_int, [C.c_void_p, C.c_int32, C.c_double, C.POINTER(C.c_void_p), C.c_int32,
+                                     C.POINTER(C.c_int32), C.POINTER(C.c_double)]),
     "etd_batch_stats": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(EtdStats)]),
     "etd_batch_profile_enable": (C.c_int, [C.c_void_p, C.c_int32]),
     "etd_batch_profile_read": (C.c_int, [C.c_void_p, C.POINTER(EtdProfile), C.c_int32]),

@@ -232,6 +232,28 @@ class Batch:
         L.check(self.lib.etd_batch_step(self.handle, code, float(h), ua, ra, int(bool(reinit)), st), "etd_batch_step")
         return [x.as_dict() for x in st] if stats else None
 
+    def graph_steps(self, scheme: str, h: float, us, nsteps: int = 1):
+        """nsteps frozen-domain steps, each one replay of a recorded HIP graph."""
+        code = {"etd1": L.ETD_SCHEME_ETD1, "etd2rk": L.ETD_SCHEME_ETD2RK}[scheme]
+        ua = self._ptrs(us, "u")
+        self._sync_stream()
+        L.check(self.lib.etd_batch_graph_steps(self.handle, code, float(h), ua, int(nsteps)),
+                "etd_batch_graph_steps")
+
+    AUTOTUNE_LIMITS = (1, 2, 4, 8, 16, 0)
+
+    def autotune(self, scheme: str, h: float, us, trials: int = 3):
+        """Pick the group limit (blocks per instance) with the fastest batched
+        Krylov launch; returns {"limit": chosen, "ms": {limit: mean ms}}."""
+        code = {"etd1": L.ETD_SCHEME_ETD1, "etd2rk": L.ETD_SCHEME_ETD2RK}[scheme]
+        ua = self._ptrs(us, "u")
+        self._sync_stream()
+        lim = C.c_int32()
+        ms = (C.c_double * 6)()
+        L.check(self.lib.etd_batch_autotune(self.handle, code, float(h), ua, int(trials), C.byref(lim), ms),
+                "etd_batch_autotune")
+        return {"limit": int(lim.value), "ms": dict(zip(self.AUTOTUNE_LIMITS, list(ms)))}
+
     def sync(self):
         L.check(self.lib.etd_batch_sync(self.handle), "etd_batch_sync")
 

@@ -89,6 +89,19 @@ struct etd_batch {
   const double** d_uptr = nullptr;
   hipEvent_t uptr_done = nullptr;    // the last upload of h_uptr has been read
   bool uptr_pending = false;
+  long geom_gen = 0;                 // geometry builds so far
+  // recorded frozen-domain step (etd_batch_graph_steps) and its key
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  hipStream_t cap_stream = nullptr;  // capture stream (default priority)
+  int g_scheme = 0;
+  double g_h = 0.0;
+  long g_geom = -1;
+  int g_limit = -1;
+  std::vector<double*> g_u;
+  KrylovDev* d_gparams = nullptr;    // graph-owned parameter copies
+  int* d_gblk = nullptr;
+  const double** d_guptr = nullptr;
   int* d_blk = nullptr;       // block -> instance, capacity entries per chunk
   int* h_blk = nullptr;
   hipEvent_t staged = nullptr;
@@ -653,6 +666,8 @@ int etd_ctx_profile_read(etd_ctx* c, etd_profile* out, int32_t reset) {
 
 namespace {
 
+void graph_drop(etd_batch* B);
+
 void batch_free(etd_batch* B) {
   for (etd_ctx* c : B->inst)
     if (c) etd_ctx_destroy(c);
@@ -667,16 +682,58 @@ void batch_free(etd_batch* B) {
   if (B->d_uptr) (void)hipFree(B->d_uptr);
   levelset_batch_free(B->lsb);
   geom_batch_free(B->gb);
+  graph_drop(B);
+  if (B->cap_stream) (void)hipStreamDestroy(B->cap_stream);
+  if (B->d_gparams) (void)hipFree(B->d_gparams);
+  if (B->d_gblk) (void)hipFree(B->d_gblk);
+  if (B->d_guptr) (void)hipFree(B->d_guptr);
   timer_free(B->t_krylov);
   timer_free(B->t_levelset);
   timer_free(B->t_geometry);
 }
 
-// One batched launch per chunk of at most `capacity` instances.  Every
-// instance gets one block; the remaining co-resident blocks go to the
+// Block schedule of chunk ch (instances i0 .. i0+n-1, at most `capacity`):
+// every instance gets one block; the remaining co-resident blocks go to the
 // instances in proportion to the blocks they could use (one loop trip over
-// their active tiles), capped by group_limit.  The launch is cooperative
-// when some instance has more than one block.
+// their active tiles), capped by group_limit.  Fills params[0..n) and
+// blk[0..blocks); returns the number of blocks, *coop whether some instance
+// has more than one block.
+int batch_schedule(const etd_batch* B, int ch, int mode, double h, KrylovDev* params, int* blk, bool* coop) {
+  const int C = B->capacity;
+  const int i0 = ch * C;
+  const int i1 = (i0 + C < B->count) ? i0 + C : B->count;
+  const int n = i1 - i0;
+  std::vector<int> want(n), g(n, 1);
+  long total_want = 0;
+  for (int i = 0; i < n; ++i) {
+    const int nact = B->inst[i0 + i]->n_active_host > 0 ? B->inst[i0 + i]->n_active_host : 1;
+    int w = (nact + KTILES - 1) / KTILES;
+    if (B->group_limit > 0 && w > B->group_limit) w = B->group_limit;
+    want[i] = w;
+    total_want += w - 1;
+  }
+  const long budget = C - n;
+  for (int i = 0; i < n; ++i) {
+    if (total_want <= budget) g[i] = want[i];
+    else g[i] = 1 + (int)((budget * (long)(want[i] - 1)) / (total_want > 0 ? total_want : 1));
+  }
+  int blocks = 0;
+  *coop = false;
+  for (int i = 0; i < n; ++i) {
+    KrylovDev P = krylov_params(B->inst[i0 + i], mode);
+    P.h = h;
+    P.g_first = blocks;
+    P.g_size = g[i];
+    params[i] = P;
+    for (int k = 0; k < g[i]; ++k) blk[blocks + k] = i;
+    blocks += g[i];
+    *coop |= g[i] > 1;
+  }
+  return blocks;
+}
+
+// One batched launch per chunk of at most `capacity` instances (schedule
+// above); cooperative when some instance has more than one block.
 int batch_run_krylov(etd_batch* B, int mode, double h) {
   if (B->staged_pending) {
     HIP_TRY(hipEventSynchronize(B->staged));
@@ -686,35 +743,10 @@ int batch_run_krylov(etd_batch* B, int mode, double h) {
   const int C = B->capacity;
   for (int ch = 0; ch < B->nchunks; ++ch) {
     const int i0 = ch * C;
-    const int i1 = (i0 + C < B->count) ? i0 + C : B->count;
-    const int n = i1 - i0;
-    std::vector<int> want(n), g(n, 1);
-    long total_want = 0;
-    for (int i = 0; i < n; ++i) {
-      const int nact = B->inst[i0 + i]->n_active_host > 0 ? B->inst[i0 + i]->n_active_host : 1;
-      int w = (nact + KTILES - 1) / KTILES;
-      if (B->group_limit > 0 && w > B->group_limit) w = B->group_limit;
-      want[i] = w;
-      total_want += w - 1;
-    }
-    const long budget = C - n;
-    for (int i = 0; i < n; ++i) {
-      if (total_want <= budget) g[i] = want[i];
-      else g[i] = 1 + (int)((budget * (long)(want[i] - 1)) / (total_want > 0 ? total_want : 1));
-    }
-    int blocks = 0;
+    const int n = ((i0 + C < B->count) ? i0 + C : B->count) - i0;
     bool coop = false;
     int* blk = B->h_blk + (size_t)ch * C;
-    for (int i = 0; i < n; ++i) {
-      KrylovDev P = krylov_params(B->inst[i0 + i], mode);
-      P.h = h;
-      P.g_first = blocks;
-      P.g_size = g[i];
-      B->h_params[i0 + i] = P;
-      for (int k = 0; k < g[i]; ++k) blk[blocks + k] = i;
-      blocks += g[i];
-      coop |= g[i] > 1;
-    }
+    const int blocks = batch_schedule(B, ch, mode, h, B->h_params + i0, blk, &coop);
     HIP_TRY(hipMemcpyAsync(B->d_params + i0, B->h_params + i0, sizeof(KrylovDev) * n, hipMemcpyHostToDevice,
                            B->stream));
     HIP_TRY(hipMemcpyAsync(B->d_blk + (size_t)ch * C, blk, sizeof(int) * blocks, hipMemcpyHostToDevice,
@@ -725,6 +757,58 @@ int batch_run_krylov(etd_batch* B, int mode, double h) {
   HIP_TRY(hipEventRecord(B->staged, B->stream));
   B->staged_pending = true;
   HIP_TRY(timer_end(B->profiling, B->stream, B->t_krylov));
+  return ETD_OK;
+}
+
+void graph_drop(etd_batch* B) {
+  if (B->gexec) (void)hipGraphExecDestroy(B->gexec);
+  if (B->graph) (void)hipGraphDestroy(B->graph);
+  B->gexec = nullptr;
+  B->graph = nullptr;
+  B->g_geom = -1;
+}
+
+// Record the frozen-domain step (scheme, h, u) as a graph: parameters into
+// the graph's own device buffers (synchronous copies), then the captured
+// gather, group-barrier reset, Krylov launch (an ordinary launch: its
+// blocks fit the co-resident capacity) and scatter.
+int graph_record(etd_batch* B, int scheme, double h, double* const* u) {
+  graph_drop(B);
+  const int n = B->count;
+  const int mode = scheme == ETD_SCHEME_ETD1 ? JOB_ETD1 : JOB_ETD2RK;
+  std::vector<KrylovDev> params(n);
+  std::vector<int> blk(B->capacity);
+  bool coop = false;
+  const int blocks = batch_schedule(B, 0, mode, h, params.data(), blk.data(), &coop);
+  HIP_TRY(hipStreamSynchronize(B->stream));
+  HIP_TRY(hipMemcpy(B->d_gparams, params.data(), sizeof(KrylovDev) * n, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(B->d_gblk, blk.data(), sizeof(int) * blocks, hipMemcpyHostToDevice));
+  std::vector<const double*> up(u, u + n);
+  HIP_TRY(hipMemcpy(B->d_guptr, up.data(), sizeof(double*) * n, hipMemcpyHostToDevice));
+  // recorded on the batch's own stream (the caller's may be the legacy
+  // default stream, which cannot be captured); replayed on the caller's
+  if (!B->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&B->cap_stream, hipStreamNonBlocking));
+  hipStream_t cs = B->cap_stream;
+  HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+  hipError_t e = launch_gather_batch(B->gb, B->d_guptr, V_X0, cs);
+  if (e == hipSuccess) e = launch_krylov_group(B->dim, B->d_gparams, n, B->d_gblk, blocks, false, cs);
+  if (e == hipSuccess) e = launch_scatter_batch(B->gb, (double* const*)B->d_guptr, V_U, cs);
+  hipGraph_t g = nullptr;
+  const hipError_t e2 = hipStreamEndCapture(cs, &g);
+  if (e != hipSuccess || e2 != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return ETD_ERR_HIP;
+  }
+  B->graph = g;
+  if (hipGraphInstantiate(&B->gexec, g, nullptr, nullptr, 0) != hipSuccess) {
+    graph_drop(B);
+    return ETD_ERR_HIP;
+  }
+  B->g_scheme = scheme;
+  B->g_h = h;
+  B->g_geom = B->geom_gen;
+  B->g_limit = B->group_limit;
+  B->g_u.assign(u, u + n);
   return ETD_OK;
 }
 
@@ -765,6 +849,9 @@ int etd_batch_create(int32_t count, const etd_grid* grids, const etd_physics* ph
   ok &= hipMalloc(&B->d_uptr, sizeof(double*) * count) == hipSuccess;
   ok &= hipEventCreateWithFlags(&B->uptr_done, hipEventDisableTiming) == hipSuccess;
   ok &= geom_batch_alloc(B->gb, count, NCOUNTERS) == hipSuccess;
+  ok &= hipMalloc(&B->d_gparams, sizeof(KrylovDev) * count) == hipSuccess;
+  ok &= hipMalloc(&B->d_gblk, sizeof(int) * (size_t)B->capacity) == hipSuccess;
+  ok &= hipMalloc(&B->d_guptr, sizeof(double*) * count) == hipSuccess;
   if (ok) {
     for (int i = 0; i < count; ++i) B->gb.h_tab[i] = geom_inst(B->inst[i]);
     ok &= geom_batch_prefix(B->gb) == hipSuccess;
@@ -810,6 +897,7 @@ int etd_batch_geometry_build(etd_batch* B, const double* const* rho) {
   HIP_TRY(launch_geometry(B->gb, GEOM_RADII, B->stream));
   HIP_TRY(timer_end(B->profiling, B->stream, B->t_geometry));
   HIP_TRY(hipStreamSynchronize(B->stream));
+  ++B->geom_gen;
   int first = ETD_OK;
   for (int i = 0; i < B->count; ++i) {
     const int r = geometry_finish(B->inst[i], B->gb.h_cnt + (size_t)i * NCOUNTERS);
@@ -867,6 +955,98 @@ int etd_batch_step(etd_batch* B, int32_t scheme, double h, double* const* u, dou
     return etd_batch_sync(B);
   }
   return ETD_OK;
+}
+
+int etd_batch_graph_steps(etd_batch* B, int32_t scheme, double h, double* const* u, int32_t nsteps) {
+  if (!B || !u || nsteps < 0 || !(h >= 0.0) || !isfinite(h)) return ETD_ERR_INVALID;
+  if (scheme != ETD_SCHEME_ETD1 && scheme != ETD_SCHEME_ETD2RK) return ETD_ERR_INVALID;
+  for (int i = 0; i < B->count; ++i)
+    if (!u[i]) return ETD_ERR_INVALID;
+  for (etd_ctx* c : B->inst)
+    if (!c->have_geometry) return ETD_ERR_NO_GEOMETRY;
+  if (B->nchunks != 1) return ETD_ERR_INVALID;
+  bool same = B->gexec && B->g_scheme == scheme && B->g_h == h && B->g_geom == B->geom_gen &&
+              B->g_limit == B->group_limit && (int)B->g_u.size() == B->count;
+  for (int i = 0; same && i < B->count; ++i) same = B->g_u[i] == u[i];
+  if (!same) {
+    const int r = graph_record(B, scheme, h, u);
+    if (r) return r;
+  }
+  HIP_TRY(timer_begin(B->profiling, B->stream, B->t_krylov));
+  for (int k = 0; k < nsteps; ++k) HIP_TRY(hipGraphLaunch(B->gexec, B->stream));
+  HIP_TRY(timer_end(B->profiling, B->stream, B->t_krylov));
+  return ETD_OK;
+}
+
+int etd_batch_autotune(etd_batch* B, int32_t scheme, double h, double* const* u, int32_t trials,
+                       int32_t* limit_out, double* ms_out) {
+  if (!B || !u || trials < 1 || !(h >= 0.0) || !isfinite(h)) return ETD_ERR_INVALID;
+  if (scheme != ETD_SCHEME_ETD1 && scheme != ETD_SCHEME_ETD2RK) return ETD_ERR_INVALID;
+  for (int i = 0; i < B->count; ++i)
+    if (!u[i]) return ETD_ERR_INVALID;
+  for (etd_ctx* c : B->inst)
+    if (!c->have_geometry) return ETD_ERR_NO_GEOMETRY;
+  const int mode = scheme == ETD_SCHEME_ETD1 ? JOB_ETD1 : JOB_ETD2RK;
+  const int n = B->count;
+  // inputs into the workspaces (as a frozen step would gather them)
+  HIP_TRY(hipStreamSynchronize(B->stream));
+  B->uptr_pending = false;
+  for (int i = 0; i < n; ++i) B->h_uptr[i] = u[i];
+  HIP_TRY(hipMemcpy(B->d_uptr, B->h_uptr, sizeof(double*) * n, hipMemcpyHostToDevice));
+  HIP_TRY(launch_gather_batch(B->gb, B->d_uptr, V_X0, B->stream));
+  // the adaptive state before the trials, restored before each run
+  KrylovStateDev* save = nullptr;
+  HIP_TRY(hipMalloc(&save, sizeof(KrylovStateDev) * n));
+  auto restore = [&](bool to_save) -> hipError_t {
+    for (int i = 0; i < n; ++i) {
+      hipError_t e = to_save ? hipMemcpyAsync(save + i, B->inst[i]->st, sizeof(KrylovStateDev),
+                                              hipMemcpyDeviceToDevice, B->stream)
+                             : hipMemcpyAsync(B->inst[i]->st, save + i, sizeof(KrylovStateDev),
+                                              hipMemcpyDeviceToDevice, B->stream);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  };
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  int result = ETD_OK;
+  const bool prof = B->profiling;
+  const int old_limit = B->group_limit;
+  static const int cand[6] = {1, 2, 4, 8, 16, 0};
+  double best = 1e300;
+  int best_limit = old_limit;
+  B->profiling = false;
+  if (restore(true) != hipSuccess || hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    result = ETD_ERR_HIP;
+  }
+  for (int q = 0; q < 6 && result == ETD_OK; ++q) {
+    B->group_limit = cand[q];
+    double sum = 0.0;
+    for (int rep = 0; rep <= trials && result == ETD_OK; ++rep) {
+      float ms = 0.0f;
+      if (restore(false) != hipSuccess || hipEventRecord(e0, B->stream) != hipSuccess) { result = ETD_ERR_HIP; break; }
+      const int r = batch_run_krylov(B, mode, h);
+      if (r) { result = r; break; }
+      if (hipEventRecord(e1, B->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+          hipEventElapsedTime(&ms, e0, e1) != hipSuccess) { result = ETD_ERR_HIP; break; }
+      if (rep > 0) sum += ms;
+    }
+    const double mean = sum / trials;
+    if (ms_out) ms_out[q] = mean;
+    if (result == ETD_OK && mean < best) {
+      best = mean;
+      best_limit = cand[q];
+    }
+  }
+  B->group_limit = result == ETD_OK ? best_limit : old_limit;
+  B->profiling = prof;
+  if (restore(false) != hipSuccess && result == ETD_OK) result = ETD_ERR_HIP;
+  if (hipStreamSynchronize(B->stream) != hipSuccess && result == ETD_OK) result = ETD_ERR_HIP;
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  (void)hipFree(save);
+  if (result == ETD_OK) result = etd_batch_sync(B);   // a device error in a trial
+  if (limit_out) *limit_out = B->group_limit;
+  return result;
 }
 
 int etd_batch_sync(etd_batch* B) {

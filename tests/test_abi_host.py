@@ -95,3 +95,5 @@ def test_batch_host_argument_checks(lib):
     assert lib.etd_batch_step(None, 2, 0.1, None, None, 0, None) == L.ETD_ERR_INVALID
     assert lib.etd_batch_geometry_build(None, None) == L.ETD_ERR_INVALID
     assert lib.etd_batch_set_group_limit(None, 1) == L.ETD_ERR_INVALID
+    assert lib.etd_batch_graph_steps(None, 2, 0.1, None, 1) == L.ETD_ERR_INVALID
+    assert lib.etd_batch_autotune(None, 2, 0.1, None, 1, None, None) == L.ETD_ERR_INVALID

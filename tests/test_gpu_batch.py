@@ -113,3 +113,63 @@ def test_batch_of_one_matches_etd_step():
     ctx.close()
     assert np.abs(out[0][0] - rho.cpu().numpy()).max() <= 1e-12
     assert rel_l2(out[0][1], u.cpu().numpy()) <= 1e-10
+
+
+def _frozen_batch(ws, limit=None):
+    from paper_2209_15095_amd.api import Batch
+    b = Batch([w.grid for w in ws], [dict(beta=w.beta, mu=0.0) for w in ws])
+    if limit is not None:
+        b.set_group_limit(limit)
+    b.geometry_build([dev(w.rho0) for w in ws])
+    return b, [dev(w.u0) for w in ws]
+
+
+def test_graph_steps_replay_eager_steps():
+    ws = inputs.batch64()[:12]
+    h = ws[0].h
+    say("graph replay: 12 frozen instances, 5 steps, eager work between replays")
+    a, ua = _frozen_batch(ws)
+    b, ub = _frozen_batch(ws)
+    ref = []
+    for k in range(5):
+        a.step("etd2rk", h, ua)
+        torch.cuda.synchronize()
+        ref.append([u.cpu().numpy() for u in ua])
+    # replays one at a time with the program's own work and synchronisations in between
+    for k in range(3):
+        b.graph_steps("etd2rk", h, ub, 1)
+        torch.cuda.synchronize()
+        junk = torch.randn(1 << 16, device="cuda", dtype=torch.float64).sum()
+        torch.cuda.synchronize()
+        got = [u.cpu().numpy() for u in ub]
+        assert all(np.array_equal(g, r) for g, r in zip(got, ref[k])), k
+        del junk
+    b.graph_steps("etd2rk", h, ub, 2)
+    b.sync()
+    got = [u.cpu().numpy() for u in ub]
+    assert all(np.array_equal(g, r) for g, r in zip(got, ref[4]))
+    a.close()
+    b.close()
+
+
+def test_autotune_leaves_state_and_chooses_a_limit():
+    ws = inputs.batch64()[:16]
+    h = ws[0].h
+    c, uc = _frozen_batch(ws)
+    before = [u.cpu().numpy() for u in uc]
+    res = c.autotune("etd2rk", h, uc, trials=2)
+    say(f"autotune: {res}")
+    assert res["limit"] in c.AUTOTUNE_LIMITS
+    assert all(ms > 0.0 for ms in res["ms"].values())
+    assert res["ms"][res["limit"]] == min(res["ms"].values())
+    assert all(np.array_equal(u.cpu().numpy(), v) for u, v in zip(uc, before))
+    # the tuned batch steps exactly as a fresh batch with that limit
+    d, ud = _frozen_batch(ws, limit=res["limit"])
+    for _ in range(2):
+        c.step("etd2rk", h, uc)
+        d.step("etd2rk", h, ud)
+    torch.cuda.synchronize()
+    for x, y in zip(uc, ud):
+        assert np.array_equal(x.cpu().numpy(), y.cpu().numpy())
+    c.close()
+    d.close()
