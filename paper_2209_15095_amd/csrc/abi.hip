@@ -208,6 +208,10 @@ KrylovDev krylov_params(const etd_ctx* c, int mode) {
   P.ra = c->phys.a;
   P.rb = c->phys.b;
   P.mode = mode;
+  // ETDFB_STAGE_MIN in the environment overrides the size from which the
+  // LDS-staged Lanczos pass is used (tests take it down to small problems)
+  P.stage_min = STAGE_MIN_TILES;
+  if (const char* env = getenv("ETDFB_STAGE_MIN")) P.stage_min = atoi(env);
   return P;
 }
 

@@ -34,6 +34,50 @@ __device__ __forceinline__ gptr<T> glb(T* p) {
   return (gptr<T>)p;
 }
 
+// Wave-uniform copies (lane 0's value) of a pointer and of a double: values
+// the compiler cannot prove uniform (read from LDS, say) then live in scalar
+// registers, and loads through the pointer take a scalar base address.
+template <class T>
+__device__ __forceinline__ gptr<T> uniform(gptr<T> p) {
+  const unsigned long long v = (unsigned long long)p;
+  const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)v);
+  const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(v >> 32));
+  return (gptr<T>)(((unsigned long long)hi << 32) | lo);
+}
+
+__device__ __forceinline__ double uniform(double x) {
+  const unsigned long long v = __double_as_longlong(x);
+  const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)v);
+  const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(v >> 32));
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// Element i of an array through a 32-bit byte offset (a scalar base plus one
+// offset register per lane).  Arrays addressed this way stay below 4 GiB.
+template <class T>
+__device__ __forceinline__ T at(gptr<const T> p, unsigned i) {
+  return *(gptr<const T>)((gptr<const char>)p + i * (unsigned)sizeof(T));
+}
+
+template <class T>
+__device__ __forceinline__ void put(gptr<T> p, unsigned i, T v) {
+  *(gptr<T>)((gptr<char>)p + i * (unsigned)sizeof(T)) = v;
+}
+
+// Pointers typed in the LDS address space (ds_ instructions, not flat).
+#if defined(__HIP_DEVICE_COMPILE__)
+template <class T>
+using lptr = __attribute__((address_space(3))) T*;
+#else
+template <class T>
+using lptr = T*;
+#endif
+
+template <class T>
+__device__ __forceinline__ lptr<T> lds(T* p) {
+  return (lptr<T>)p;
+}
+
 template <int DIM> struct TileShape;
 template <> struct TileShape<2> { static constexpr int X = 32, Y = 8, Z = 1; };
 template <> struct TileShape<3> { static constexpr int X = 16, Y = 4, Z = 4; };

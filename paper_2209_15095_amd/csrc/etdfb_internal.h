@@ -108,7 +108,13 @@ struct KrylovDev {
   double* dbeta;              // JOB_ADJ_ETD2RK: device scalar, dL/dbeta accumulated
   double h;                   // ETD step
   int g_first, g_size;        // blocks of this instance in the launch grid
+  int stage_min;              // fewest active tiles for the LDS-staged Lanczos pass
 };
+
+// Default of KrylovDev::stage_min: the LDS-staged Lanczos pass pays where
+// the vectors outgrow the L2 (2048 active tiles, 4 MiB per vector); below,
+// its two block barriers per loop trip cost more than the misses it saves.
+constexpr int STAGE_MIN_TILES = 2048;
 
 // Status codes (mirror include/etdfb.h).
 enum {

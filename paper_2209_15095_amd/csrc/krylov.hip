@@ -40,7 +40,7 @@
 
 namespace etdfb {
 
-constexpr int META_TRIPS = 96;          // loop trips whose tile metadata a block keeps in LDS
+constexpr int META_TRIPS = 128;         // loop trips whose tile metadata a block keeps in LDS
 constexpr int NWAVE = KBLOCK / 64;
 
 struct Ctl {
@@ -435,6 +435,180 @@ struct Engine {
     return finish<2>(acc, out);
   }
 
+  // The same Lanczos pass with each tile and its face halo staged in LDS
+  // (for blocks with several loop trips): every value of z_{k-1}, q_{k-1},
+  // q_{k-2} in a tile is read from memory once per pass and its neighbours
+  // from LDS, and the point values of the next trip are loaded one trip
+  // ahead.  The staging buffers are the exponential's buffers (R, S; no
+  // exponential runs during a pass).  Two block barriers per trip; every
+  // block runs the same number of trips for all its tiles.
+  __device__ bool lanczos_lds(int k, double (&out)[2]) {
+    constexpr int X = TileShape<DIM>::X, Y = TileShape<DIM>::Y, Z = TileShape<DIM>::Z;
+    constexpr int EX = X + 2, EY = Y + 2, EZ = DIM == 3 ? Z + 2 : 1;
+    constexpr int E = EX * EY * EZ;                       // staged box per array
+    constexpr int NH = DIM == 2 ? 2 * (X + Y) : 2 * (X * Y + X * Z + Y * Z);   // face halo nodes
+    constexpr int HR = (NH + TILE_PTS - 1) / TILE_PTS;   // halo nodes per thread
+    constexpr int PS = DIM == 3 ? EX * EY : 0;            // z stride in the staged box
+    static_assert(KTILES * 3 * E <= 2 * EXPM_NMAX * EXPM_NMAX, "staging exceeds the exponential buffers");
+    // everything the loop reads from the parameters, hoisted (wave-uniform
+    // registers; reads through the parameter reference in the loop would
+    // wait for every load in flight)
+    const gptr<const double> zp = uniform<const double>(V(V_Z0 + ((k - 1) & 1)));
+    const gptr<const double> q1 = uniform<const double>(V(V_Q0 + k - 1));
+    const gptr<const double> q2 = uniform<const double>(V(V_Q0 + (k >= 2 ? k - 2 : 0)));
+    const gptr<double> qk = uniform<double>(V(V_Q0 + k));
+    const gptr<double> zk = uniform<double>(V(V_Z0 + (k & 1)));
+    const gptr<const double> cdiag = uniform<const double>(glb(P.g.cdiag));
+    const double coef = uniform(P.g.coef);
+    const double alpha = uniform(c.alpha[k - 1]);
+    const double inv_n = uniform(1.0 / c.nrm[k - 1]);
+    const double cm = uniform((k >= 2) ? c.nrm[k - 1] / c.nrm[k - 2] : 0.0);
+    const int na = nact;
+    const int sub = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / TILE_PTS));
+    const int l = (int)(threadIdx.x % TILE_PTS);
+    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int lc[3] = {l % X, (l / X) % Y, l / (X * Y)};
+    const lptr<double> Lz = lds(R) + (size_t)sub * 3 * E;
+    const lptr<double> L1 = Lz + E;
+    const lptr<double> L2 = L1 + E;
+    const int pos = (lc[0] + 1) + EX * ((lc[1] + 1) + EY * (DIM == 3 ? lc[2] + 1 : 0));
+    // this thread's halo nodes: face, index in the neighbour tile, staged position
+    int hf[HR], hloc[HR], hpos[HR];
+#pragma unroll
+    for (int r = 0; r < HR; ++r) {
+      int h = l + r * TILE_PTS;
+      hf[r] = -1;
+      hloc[r] = 0;
+      hpos[r] = 0;
+      if (h >= NH) continue;
+      const int ext[3] = {X, Y, Z};
+      int f = 0;
+      for (; f < 2 * DIM; ++f) {
+        const int d = f >> 1;
+        const int a = d == 0 ? 1 : 0, b = d == 2 ? 1 : 2;
+        const int cnt = ext[a] * (DIM == 3 ? ext[b] : 1);
+        if (h < cnt) break;
+        h -= cnt;
+      }
+      const int d = f >> 1;
+      const int a = d == 0 ? 1 : 0, b = d == 2 ? 1 : 2;
+      int cc[3] = {0, 0, 0};     // position in this tile's frame
+      cc[a] = h % ext[a];
+      cc[b] = DIM == 3 ? h / ext[a] : 0;
+      cc[d] = (f & 1) ? ext[d] : -1;
+      int nc[3] = {cc[0], cc[1], cc[2]};   // position in the neighbour tile
+      nc[d] = (f & 1) ? 0 : ext[d] - 1;
+      hf[r] = f;
+      hloc[r] = nc[0] + X * (nc[1] + Y * nc[2]);
+      hpos[r] = (cc[0] + 1) + EX * ((cc[1] + 1) + EY * (DIM == 3 ? cc[2] + 1 : 0));
+    }
+    const int stride = G * KTILES;
+    const int base0 = lb * KTILES;
+    double acc[2] = {0.0, 0.0};
+    const unsigned long long t_in = wall_clock64();
+    // loads of trip r: the point and the halo nodes (0 where no tile)
+    double pz, p1, p2, hz[HR], h1[HR], h2[HR];
+    // metadata of trip r from the LDS cache (the caller uses this pass only
+    // while every trip is cached)
+    const lptr<const uint64_t> mcw = lds((const uint64_t*)&c.mcw[0][0]);
+    const lptr<const uint64_t> miw = lds((const uint64_t*)&c.miw[0][0]);
+    const lptr<const int> mnb = lds((const int*)&c.mnb[0][0][0]);
+    auto meta = [&](Meta& m, int r, int) {
+      m.cw = mcw[r * NWAVE + w];
+      m.iw = miw[r * NWAVE + w];
+#pragma unroll
+      for (int d = 0; d < 2 * DIM; ++d) m.nb[d] = mnb[(r * KTILES + sub) * 6 + d];
+    };
+    // (every load is issued, at element 0 where there is nothing to read,
+    // and the value selected afterwards: no branches, so the compiler can
+    // count the loads in flight and wait only for the ones it needs)
+    auto issue = [&](const Meta& m, int slot, bool valid) {
+      const unsigned i = valid ? (unsigned)slot * TILE_PTS + (unsigned)l : 0u;
+      const double a = at(zp, i), b = at(q1, i), e = at(q2, i);
+      double ha[HR], hb[HR], he[HR];
+      bool ok[HR];
+#pragma unroll
+      for (int r = 0; r < HR; ++r) {
+        int ns = -1;
+#pragma unroll
+        for (int f = 0; f < 2 * DIM; ++f) ns = hf[r] == f ? m.nb[f] : ns;
+        ok[r] = valid && hf[r] >= 0 && ns >= 0;
+        const unsigned j = ok[r] ? (unsigned)ns * TILE_PTS + (unsigned)hloc[r] : 0u;
+        ha[r] = at(zp, j);
+        hb[r] = at(q1, j);
+        he[r] = at(q2, j);
+      }
+      pz = valid ? a : 0.0;
+      p1 = valid ? b : 0.0;
+      p2 = valid ? e : 0.0;
+#pragma unroll
+      for (int r = 0; r < HR; ++r) {
+        hz[r] = ok[r] ? ha[r] : 0.0;
+        h1[r] = ok[r] ? hb[r] : 0.0;
+        h2[r] = ok[r] ? he[r] : 0.0;
+      }
+    };
+    if (base0 < na) {
+      Meta m;
+      int slot = base0 + sub;
+      bool valid = slot < na;
+      if (valid) meta(m, 0, slot);
+      issue(m, slot, valid);
+      for (int r = 0;; ++r) {
+        // stage this trip's values
+        __syncthreads();   // the previous trip's LDS reads are done
+        Lz[pos] = pz;
+        L1[pos] = p1;
+        L2[pos] = p2;
+#pragma unroll
+        for (int q = 0; q < HR; ++q)
+          if (hf[q] >= 0) {
+            Lz[hpos[q]] = hz[q];
+            L1[hpos[q]] = h1[q];
+            L2[hpos[q]] = h2[q];
+          }
+        Tile t;
+        if (valid) make_tile(t, slot, l, m);
+        // the next trip's loads
+        const int nslot = slot + stride;
+        const bool more = base0 + (r + 1) * stride < na;
+        const bool nvalid = nslot < na;
+        Meta mn = m;
+        if (nvalid) meta(mn, r + 1, nslot);
+        // c_p: read at irregular points, element 0 elsewhere (no branch)
+        const double cd = at(cdiag, (valid && t.irr) ? t.idx : 0u);
+        issue(mn, nslot, nvalid);
+        __syncthreads();
+        if (valid) {
+          constexpr int NS = 2 * DIM;
+          const int off[6] = {-1, 1, -EX, EX, -PS, PS};
+          double s = 0.0;
+#pragma unroll
+          for (int f = 0; f < NS; ++f) {
+            const int pn = pos + off[f];
+            s += (Lz[pn] - alpha * L1[pn]) * inv_n - cm * L2[pn];
+          }
+          const double qc = (Lz[pos] - alpha * L1[pos]) * inv_n - cm * L2[pos];
+          const double cp = t.irr ? cd : (double)(2 * DIM);
+          const double q = t.comp ? qc : 0.0;
+          const double z = t.comp ? coef * (s - cp * q) : 0.0;
+          put(qk, t.idx, q);
+          put(zk, t.idx, z);
+          acc[0] += q * q;
+          acc[1] += z * q;
+        }
+        if (!more) break;
+        slot = nslot;
+        valid = nvalid;
+        m = mn;
+      }
+      __syncthreads();   // LDS free for the exponential
+    }
+    if (threadIdx.x == 0 && lb == 0) tk_tiles += wall_clock64() - t_in;
+    bpu += 32.0;
+    return finish<2>(acc, out);
+  }
+
   // out = sum_{k<p} tau^k/k! W_k + sum_i coef_i q_i into the buffer that is
   // not iu; returns |out|^2 in nn.
   __device__ bool combine_pass(int p, int m, double tau, double& nn) {
@@ -673,7 +847,10 @@ struct Engine {
             started = true;
           }
           double o[2];
-          if (!lanczos_pass(m + 1, o)) return false;
+          // large vectors, several loop trips per block, all with cached
+          // metadata: the LDS-staged pass
+          const bool staged = nact >= P.stage_min && nact > G * KTILES && nact <= G * KTILES * META_TRIPS;
+          if (staged ? !lanczos_lds(m + 1, o) : !lanczos_pass(m + 1, o)) return false;
           matvecs += 1;
           const double nb = sqrt(o[0]);
           const double alpha_next = (o[0] > 0.0) ? o[1] / o[0] : 0.0;
@@ -981,8 +1158,11 @@ __device__ __forceinline__ void krylov_body(const KrylovDev& P, int lb, int G, C
 template <int DIM>
 __global__ __launch_bounds__(KBLOCK) void krylov_kernel(KrylovDev P) {
   __shared__ Ctl c;
-  __shared__ double R[EXPM_NMAX * EXPM_NMAX];
-  __shared__ double S[EXPM_NMAX * EXPM_NMAX];
+  // the two exponential buffers, contiguous: between exponentials the
+  // LDS-staged Lanczos pass uses them as its tile buffers
+  __shared__ double RS[2 * EXPM_NMAX * EXPM_NMAX];
+  double* R = RS;
+  double* S = RS + EXPM_NMAX * EXPM_NMAX;
   // parameters in LDS: the engine refers to them by reference, and a
   // reference to a kernel argument would force a private-memory copy
   __shared__ KrylovDev sP;
@@ -998,8 +1178,11 @@ template <int DIM>
 __global__ __launch_bounds__(KBLOCK) void krylov_group_kernel(const KrylovDev* __restrict__ Ps,
                                                               const int* __restrict__ blk_inst) {
   __shared__ Ctl c;
-  __shared__ double R[EXPM_NMAX * EXPM_NMAX];
-  __shared__ double S[EXPM_NMAX * EXPM_NMAX];
+  // the two exponential buffers, contiguous: between exponentials the
+  // LDS-staged Lanczos pass uses them as its tile buffers
+  __shared__ double RS[2 * EXPM_NMAX * EXPM_NMAX];
+  double* R = RS;
+  double* S = RS + EXPM_NMAX * EXPM_NMAX;
   const KrylovDev& P = Ps[blk_inst[blockIdx.x]];
   krylov_body<DIM>(P, (int)blockIdx.x - P.g_first, P.g_size, c, R, S);
 }
