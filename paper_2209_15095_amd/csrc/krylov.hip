@@ -632,17 +632,21 @@ struct Engine {
           for (int k = 1; k < PMAX; ++k)
             if (k < p) u += ck[k] * V(V_W1 + k - 1)[idx];
         }
-        // four independent partial sums keep four basis loads in flight
-        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+        // eight independent partial sums keep eight basis loads in flight
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0, s4 = 0.0, s5 = 0.0, s6 = 0.0, s7 = 0.0;
         int j = 0;
-        for (; j + 4 <= m; j += 4) {
+        for (; j + 8 <= m; j += 8) {
           s0 += c.coef[j] * V(V_Q0 + j)[idx];
           s1 += c.coef[j + 1] * V(V_Q0 + j + 1)[idx];
           s2 += c.coef[j + 2] * V(V_Q0 + j + 2)[idx];
           s3 += c.coef[j + 3] * V(V_Q0 + j + 3)[idx];
+          s4 += c.coef[j + 4] * V(V_Q0 + j + 4)[idx];
+          s5 += c.coef[j + 5] * V(V_Q0 + j + 5)[idx];
+          s6 += c.coef[j + 6] * V(V_Q0 + j + 6)[idx];
+          s7 += c.coef[j + 7] * V(V_Q0 + j + 7)[idx];
         }
         for (; j < m; ++j) s0 += c.coef[j] * V(V_Q0 + j)[idx];
-        u += (s0 + s1) + (s2 + s3);
+        u += ((s0 + s1) + (s2 + s3)) + ((s4 + s5) + (s6 + s7));
       }
       V(io)[idx] = u;
       acc[0] += u * u;

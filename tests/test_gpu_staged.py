@@ -131,3 +131,33 @@ def test_staged_etd2rk_steps_disk257():
     assert rel_l2(outs[0][op.comp], U) <= 1e-9
     assert rel_l2(outs[1][op.comp], U) <= 1e-9
     assert rel_l2(outs[0], outs[1]) <= 1e-12
+
+
+@pytest.mark.parametrize("name", ["disk4097", "sphere385"])
+def test_staged_matches_one_by_one_loads_at_full_size(name):
+    """The bandwidth-scale workloads in the launch bench.py times: one frozen
+    ETD2RK step with the staged Lanczos passes (their default at this size)
+    against the same step with the stencil loaded point by point (staging
+    switched off), to 1e-10 relative L2; both also against the step's
+    invariant u = 0 off the computational points."""
+    from paper_2209_15095_amd.api import Context
+    w = inputs.WORKLOADS[name]()
+    say(f"{name}: one ETD2RK step, staged against point-by-point stencil loads")
+    outs = []
+    for stage_min in ("2048", str(1 << 30)):
+        os.environ["ETDFB_STAGE_MIN"] = stage_min
+        ctx = Context.from_grid(w.grid, beta=w.beta, a=w.a, b=w.b, mu=w.mu)
+        ctx.geometry_build(dev(w.rho0))
+        ud = dev(w.u0)
+        st = ctx.etd_step(w.scheme, w.h, ud, stats=True)
+        torch.cuda.synchronize()
+        say(f"  stage_min {stage_min}: active tiles {st['n_active_tiles']} m {st['m_last']} "
+            f"substeps {st['substeps']}")
+        outs.append(ud.cpu().numpy())
+        del ud
+        ctx.close()
+    comp = outs[1] != 0.0
+    assert np.all(outs[0][~comp] == 0.0)
+    rel = rel_l2(outs[0], outs[1])
+    say(f"  rel L2 difference {rel:.3e}")
+    assert rel <= 1e-10
