@@ -48,7 +48,7 @@ struct Ctl {
   // tiles every pass): mask words per wave, face-neighbour slots per tile
   uint64_t mcw[META_TRIPS][NWAVE];
   uint64_t miw[META_TRIPS][NWAVE];
-  int mnb[META_TRIPS][KTILES][6];
+  int mnb[META_TRIPS][KTILES][8];   // face slots (-x,+x,-y,+y,-z,+z); 2D: then the diagonals
   // Lanczos data of the current substep (written by thread 0, read by all)
   double alpha[MMAX_LIMIT + 2];
   double nrm[MMAX_LIMIT + 2];
@@ -60,6 +60,182 @@ struct Ctl {
   int m_guess[PMAX + 1];
   int abort;
 };
+
+// The loop of the 2D z-free staged Lanczos pass (Engine::lanczos_zf2), a
+// function of its own so that its registers are allocated apart from the
+// rest of the persistent kernel.  acc receives this thread's partial sums of
+// |q_k|^2 and <A q_k, q_k>.
+__device__ __attribute__((noinline)) void zf2_loop(gptr<const double> q1, gptr<const double> q2,
+                                                   gptr<double> qk, gptr<const double> cdiag, double coef,
+                                                   double alpha, double inv_n, double cm, int na, int G,
+                                                   int lb, lptr<double> stage, lptr<const int> mnb,
+                                                   double* acc) {
+  constexpr int X = TileShape<2>::X, Y = TileShape<2>::Y;
+  constexpr int W2 = X + 4, H2 = Y + 4;   // q_{k-1} box (2-node halo)
+  constexpr int W1 = X + 2, H1 = Y + 2;   // q_{k-2}, c_p, q_k box (1-node halo)
+  constexpr int N2 = W2 * H2, N1 = W1 * H1;
+  constexpr int NH2 = 2 * 2 * (X + Y) + 4;   // two-node face halo and the diagonals
+  constexpr int NH1 = 2 * (X + Y);           // one-node face halo
+  constexpr int PER = N2 + N1 + 2 * N1;      // doubles per tile
+  static_assert(NH2 <= TILE_PTS && NH1 <= TILE_PTS, "one halo node per thread");
+  static_assert(KTILES * PER <= 2 * EXPM_NMAX * EXPM_NMAX, "staging exceeds the exponential buffers");
+  // arguments arrive in vector registers: back to wave-uniform values
+  q1 = uniform(q1);
+  q2 = uniform(q2);
+  qk = uniform(qk);
+  cdiag = uniform(cdiag);
+  coef = uniform(coef);
+  alpha = uniform(alpha);
+  inv_n = uniform(inv_n);
+  cm = uniform(cm);
+  na = __builtin_amdgcn_readfirstlane(na);
+  G = __builtin_amdgcn_readfirstlane(G);
+  lb = __builtin_amdgcn_readfirstlane(lb);
+  double a0 = 0.0, a1 = 0.0;
+    const int sub = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / TILE_PTS));
+    const int l = (int)(threadIdx.x % TILE_PTS);
+    const int lx = l % X, ly = l / X;
+    const lptr<double> L1 = stage + (size_t)sub * PER;    // q_{k-1}
+    const lptr<double> LC = L1 + N2;                        // c_p
+    const lptr<double> LQ = LC + N1;                        // q_{k-2}, then q_k (two halves)
+    const int o2 = (lx + 2) + W2 * (ly + 2);   // own point in the boxes
+    const int o1 = (lx + 1) + W1 * (ly + 1);
+    // two-node halo node of this thread: neighbour entry (0..3 faces,
+    // 4..7 diagonals), index in that tile, position in the q_{k-1} box
+    int h2n = -1, h2l = 0, h2p = 0;
+    if (l < NH2) {
+      int x, y, nx, ny;
+      if (l < 4 * Y) {                 // x faces, depths 1 and 2
+        const int side = l / (2 * Y), dd = 1 + (l / Y) % 2, row = l % Y;
+        x = side ? X - 1 + dd : -dd;
+        y = row;
+        nx = side ? dd - 1 : X - dd;
+        ny = row;
+        h2n = side;
+      } else if (l < 4 * Y + 4 * X) {  // y faces, depths 1 and 2
+        const int q = l - 4 * Y;
+        const int side = q / (2 * X), dd = 1 + (q / X) % 2, col = q % X;
+        x = col;
+        y = side ? Y - 1 + dd : -dd;
+        nx = col;
+        ny = side ? dd - 1 : Y - dd;
+        h2n = 2 + side;
+      } else {                         // diagonals -x-y, +x-y, -x+y, +x+y
+        const int q = l - 4 * Y - 4 * X;
+        const int sx = q & 1, sy = q >> 1;
+        x = sx ? X : -1;
+        y = sy ? Y : -1;
+        nx = sx ? 0 : X - 1;
+        ny = sy ? 0 : Y - 1;
+        h2n = 4 + q;
+      }
+      h2l = nx + X * ny;
+      h2p = (x + 2) + W2 * (y + 2);
+    }
+    // one-node face halo node of this thread
+    int h1n = -1, h1l = 0, h1p1 = 0, h1p2 = 0;
+    if (l < NH1) {
+      int x, y, nx, ny;
+      if (l < 2 * Y) {
+        const int side = l / Y, row = l % Y;
+        x = side ? X : -1;
+        y = row;
+        nx = side ? 0 : X - 1;
+        ny = row;
+        h1n = side;
+      } else {
+        const int q = l - 2 * Y;
+        const int side = q / X, col = q % X;
+        x = col;
+        y = side ? Y : -1;
+        nx = col;
+        ny = side ? 0 : Y - 1;
+        h1n = 2 + side;
+      }
+      h1l = nx + X * ny;
+      h1p1 = (x + 1) + W1 * (y + 1);
+      h1p2 = (x + 2) + W2 * (y + 2);
+    }
+    const int stride = G * KTILES;
+    const int base0 = lb * KTILES;
+    // loads of one trip (element 0 where there is nothing; selected after)
+    double a_q1, a_q2, a_cd, a_h2, a_h1q, a_h1c;
+    auto issue = [&](int r, int slot, bool valid) {
+      int nb[8];
+#pragma unroll
+      for (int d = 0; d < 8; ++d) nb[d] = valid ? mnb[(r * KTILES + sub) * 8 + d] : -1;
+      const unsigned i = valid ? (unsigned)slot * TILE_PTS + (unsigned)l : 0u;
+      int s2 = -1, s1 = -1;
+#pragma unroll
+      for (int d = 0; d < 8; ++d) {
+        s2 = h2n == d ? nb[d] : s2;
+        s1 = h1n == d ? nb[d] : s1;
+      }
+      const bool ok2 = s2 >= 0, ok1 = s1 >= 0;
+      const unsigned j2 = ok2 ? (unsigned)s2 * TILE_PTS + (unsigned)h2l : 0u;
+      const unsigned j1 = ok1 ? (unsigned)s1 * TILE_PTS + (unsigned)h1l : 0u;
+      const double v1 = at(q1, i), v2 = at(q2, i), vc = at(cdiag, i);
+      const double w2 = at(q1, j2), w1q = at(q2, j1), w1c = at(cdiag, j1);
+      a_q1 = valid ? v1 : 0.0;
+      a_q2 = valid ? v2 : 0.0;
+      a_cd = valid ? vc : NOT_COMP;
+      a_h2 = ok2 ? w2 : 0.0;
+      a_h1q = ok1 ? w1q : 0.0;
+      a_h1c = ok1 ? w1c : NOT_COMP;
+    };
+    // q_k at one node of the face-halo box (position p1 there, p2 in the
+    // q_{k-1} box), from the staged values
+    auto qnode = [&](int p1, int p2, lptr<double> Q) -> double {
+      const double cd = LC[p1];
+      const double v = L1[p2];
+      const double az = coef * (((L1[p2 - 1] + L1[p2 + 1]) + (L1[p2 - W2] + L1[p2 + W2])) - cd * v);
+      const double q = (az - alpha * v) * inv_n - cm * Q[p1];
+      return cd > -1e299 ? q : 0.0;   // NOT_COMP: not computational
+    };
+    if (base0 < na) {
+      int slot = base0 + sub;
+      bool valid = slot < na;
+      issue(0, slot, valid);
+      for (int r = 0;; ++r) {
+        const lptr<double> Q = LQ + (r & 1) * N1;
+        // stage (the previous trip's reads of this trip's buffers are behind
+        // the last barrier of the previous trip; q_k's half alternates)
+        L1[o2] = a_q1;
+        Q[o1] = a_q2;
+        LC[o1] = a_cd;
+        if (h2n >= 0) L1[h2p] = a_h2;
+        if (h1n >= 0) {
+          Q[h1p1] = a_h1q;
+          LC[h1p1] = a_h1c;
+        }
+        const int nslot = slot + stride;
+        const bool more = base0 + (r + 1) * stride < na;
+        const bool nvalid = nslot < na;
+        __syncthreads();
+        issue(r + 1 < META_TRIPS ? r + 1 : r, nslot, nvalid);
+        // q_k at the own point and at this thread's halo node (in place of q_{k-2})
+        const double cdo = LC[o1];
+        const double qo = qnode(o1, o2, Q);
+        const double qh = h1n >= 0 ? qnode(h1p1, h1p2, Q) : 0.0;
+        Q[o1] = qo;
+        if (h1n >= 0) Q[h1p1] = qh;
+        __syncthreads();
+        if (valid) {
+          const bool comp = cdo > -1e299;
+          const double z = comp ? coef * (((Q[o1 - 1] + Q[o1 + 1]) + (Q[o1 - W1] + Q[o1 + W1])) - cdo * qo) : 0.0;
+          put(qk, (unsigned)slot * TILE_PTS + (unsigned)l, qo);
+          a0 += qo * qo;
+          a1 += z * qo;
+        }
+        if (!more) break;
+        slot = nslot;
+        valid = nvalid;
+      }
+      __syncthreads();   // LDS free for the exponential
+    }
+  acc[0] = a0;
+  acc[1] = a1;
+}
 
 // An instance is worked on by a group of G co-resident blocks (lb = this
 // block's index in the group).  G == 1: the block synchronises only with
@@ -272,6 +448,17 @@ struct Engine {
         c.miw[r][w] = glb(P.g.irr_bits)[(size_t)slot * 4 + (l >> 6)];
       }
       if (l < 2 * DIM) c.mnb[r][sub][l] = glb(P.g.nbr)[(size_t)slot * NBR_STRIDE + l];
+      if (DIM == 2 && l >= 4 && l < 8) {
+        // diagonal tile (-x-y, +x-y, -x+y, +x+y) through an existing face
+        // neighbour (it matters only where one of them exists)
+        const int fx = (l - 4) & 1, fy = 2 + ((l - 4) >> 1);
+        const int nx = glb(P.g.nbr)[(size_t)slot * NBR_STRIDE + fx];
+        const int ny = glb(P.g.nbr)[(size_t)slot * NBR_STRIDE + fy];
+        int d = -1;
+        if (nx >= 0) d = glb(P.g.nbr)[(size_t)nx * NBR_STRIDE + fy];
+        else if (ny >= 0) d = glb(P.g.nbr)[(size_t)ny * NBR_STRIDE + fx];
+        c.mnb[r][sub][l] = d;
+      }
     }
     __syncthreads();
   }
@@ -517,7 +704,7 @@ struct Engine {
       m.cw = mcw[r * NWAVE + w];
       m.iw = miw[r * NWAVE + w];
 #pragma unroll
-      for (int d = 0; d < 2 * DIM; ++d) m.nb[d] = mnb[(r * KTILES + sub) * 6 + d];
+      for (int d = 0; d < 2 * DIM; ++d) m.nb[d] = mnb[(r * KTILES + sub) * 8 + d];
     };
     // (every load is issued, at element 0 where there is nothing to read,
     // and the value selected afterwards: no branches, so the compiler can
@@ -604,6 +791,27 @@ struct Engine {
       }
       __syncthreads();   // LDS free for the exponential
     }
+    if (threadIdx.x == 0 && lb == 0) tk_tiles += wall_clock64() - t_in;
+    bpu += 32.0;
+    return finish<2>(acc, out);
+  }
+
+  // 2D Lanczos pass without a stored A q, staged in LDS (large problems):
+  // q_{k-1} is staged on the tile and a two-node halo (with the four
+  // diagonal nodes), q_{k-2} and c_p on the tile and a one-node face halo;
+  // A q_{k-1} and then q_k follow on the tile and its face halo, and
+  // A q_k at the tile's points.  Reads q_{k-1}, q_{k-2}, c_p and writes q_k:
+  // 32 B per unknown from memory, the count of the measurement plan (the
+  // stored-A q pass moves 40 B).  c_p doubles as the computational mask
+  // (NOT_COMP elsewhere).  The q_k buffer alternates between two LDS halves
+  // by trip parity, so two block barriers per trip suffice.
+  __device__ bool lanczos_zf2(int k, double (&out)[2]) {
+    const unsigned long long t_in = wall_clock64();
+    double acc[2];
+    zf2_loop(uniform<const double>(V(V_Q0 + k - 1)), uniform<const double>(V(V_Q0 + (k >= 2 ? k - 2 : 0))),
+             uniform<double>(V(V_Q0 + k)), uniform<const double>(glb(P.g.cdiag)), P.g.coef, c.alpha[k - 1],
+             1.0 / c.nrm[k - 1], (k >= 2) ? c.nrm[k - 1] / c.nrm[k - 2] : 0.0, nact, G, lb, lds(R),
+             lds((const int*)&c.mnb[0][0][0]), acc);
     if (threadIdx.x == 0 && lb == 0) tk_tiles += wall_clock64() - t_in;
     bpu += 32.0;
     return finish<2>(acc, out);
@@ -854,7 +1062,11 @@ struct Engine {
           // large vectors, several loop trips per block, all with cached
           // metadata: the LDS-staged pass
           const bool staged = nact >= P.stage_min && nact > G * KTILES && nact <= G * KTILES * META_TRIPS;
-          if (staged ? !lanczos_lds(m + 1, o) : !lanczos_pass(m + 1, o)) return false;
+          bool ok;
+          if (staged && DIM == 2) ok = lanczos_zf2(m + 1, o);
+          else if (staged) ok = lanczos_lds(m + 1, o);
+          else ok = lanczos_pass(m + 1, o);
+          if (!ok) return false;
           matvecs += 1;
           const double nb = sqrt(o[0]);
           const double alpha_next = (o[0] > 0.0) ? o[1] / o[0] : 0.0;
