@@ -223,7 +223,8 @@ __device__ __attribute__((noinline)) void zf2_loop(gptr<const double> q1, gptr<c
         if (valid) {
           const bool comp = cdo > -1e299;
           const double z = comp ? coef * (((Q[o1 - 1] + Q[o1 + 1]) + (Q[o1 - W1] + Q[o1 + W1])) - cdo * qo) : 0.0;
-          put(qk, (unsigned)slot * TILE_PTS + (unsigned)l, qo);
+          // streaming store: q_k is read back only in the next pass
+          __builtin_nontemporal_store(qo, (gptr<double>)((gptr<char>)qk + ((unsigned)slot * TILE_PTS + (unsigned)l) * 8u));
           a0 += qo * qo;
           a1 += z * qo;
         }
