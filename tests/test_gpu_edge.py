@@ -1,0 +1,97 @@
+"""GPU edge cases of the boundary, against the oracle or exact values.
+
+* An empty domain (rho > 0 everywhere): no unknowns; etd_step and
+  phi_combination_apply return 0 everywhere without error.
+* A domain with a single computational point (A is 1x1): the
+  phi-combination against the oracle's dense route.
+* t = 0: sum_k b_k / k! exactly (phi_k(0) = 1/k!).
+* All-zero inputs: exactly 0 (the Krylov term vanishes, W_p = 0).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle.geometry import Grid
+from oracle.operator import build_operator
+from oracle.phi import phi_combination
+from paper_2209_15095_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+G = inputs.GridSpec(2, (48, 48), (-4.0, -4.0), (4.0, 4.0))
+DX = 8.0 / 47
+
+
+def say(msg):
+    print(f"[gpu-edge] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def ctx_for(rho):
+    from paper_2209_15095_amd.api import Context
+    ctx = Context(G.dim, G.n, G.lo, G.hi, beta=1.0)
+    ctx.geometry_build(dev(rho))
+    return ctx
+
+
+def test_empty_domain():
+    X, Y = G.coords()
+    rho = np.sqrt(X * X + Y * Y) + 1.0
+    ctx = ctx_for(rho)
+    u = dev(np.ones_like(rho))
+    st = ctx.etd_step("etd2rk", 0.01, u, stats=True)
+    say(f"empty: {st}")
+    assert st["n_unknowns"] == 0 and st["status"] == 0
+    assert float(u.abs().max()) == 0.0
+    bs = [dev(np.ones_like(rho)) for _ in range(3)]
+    out = ctx.phi_combination_apply(0.1, bs)
+    torch.cuda.synchronize()
+    assert float(out.abs().max()) == 0.0
+    ctx.close()
+
+
+def single_point_domain():
+    X, Y = G.coords()
+    rho = np.maximum(np.abs(X - 0.5 * DX), np.abs(Y - 0.5 * DX)) - 1.1 * DX
+    op = build_operator(Grid(2, tuple(G.n), tuple(G.lo), tuple(G.hi)), rho, 1.0)
+    assert op.n == 1
+    return rho, op
+
+
+def test_single_unknown():
+    rho, op = single_point_domain()
+    rng = np.random.default_rng(0)
+    bs = [np.where(op.comp, rng.standard_normal(rho.shape), 0.0) for _ in range(3)]
+    ctx = ctx_for(rho)
+    out, st = ctx.phi_combination_apply(0.3, [dev(b) for b in bs], stats=True)
+    o = out.cpu().numpy()
+    ref = phi_combination(op.A, 0.3, [op.gather(b) for b in bs], method="dense")
+    say(f"single unknown: {st}, out {o[op.comp]} ref {ref}")
+    assert np.all(o[~op.comp] == 0.0)
+    assert np.abs(o[op.comp] - ref).max() <= 1e-9 * np.abs(ref).max()
+    ctx.close()
+
+
+def test_time_zero_and_zero_inputs():
+    g = G
+    X, Y = g.coords()
+    rho = np.sqrt(X * X + Y * Y) - 2.5
+    op = build_operator(Grid(2, tuple(g.n), tuple(g.lo), tuple(g.hi)), rho, 1.0)
+    rng = np.random.default_rng(1)
+    bs = [np.where(op.comp, rng.standard_normal(rho.shape), 0.0) for _ in range(3)]
+    ctx = ctx_for(rho)
+    out = ctx.phi_combination_apply(0.0, [dev(b) for b in bs]).cpu().numpy()
+    exact = np.where(op.comp, bs[0] + bs[1] + 0.5 * bs[2], 0.0)
+    assert np.abs(out - exact).max() <= 1e-15 * np.abs(exact).max()
+    zs = [dev(np.zeros_like(rho)) for _ in range(3)]
+    outz, st = ctx.phi_combination_apply(0.3, zs, stats=True)
+    say(f"zero inputs: {st}")
+    assert float(outz.abs().max()) == 0.0 and st["status"] == 0
+    ctx.close()
