@@ -50,7 +50,10 @@ enum {
   ETD_ERR_NO_GEOMETRY = -8   /* no geometry built on this context yet */
 };
 
-enum { ETD_SCHEME_ETD1 = 1, ETD_SCHEME_ETD2RK = 2 };
+/* ETD1 (Section 3.1), ETD2RK, ETD3RK and ETD4RK (Section 3.2; the phi_3 of
+ * the paper's ETD3RK and ETD4RK formulas is 2 phi_3 in the standard
+ * normalisation phi_k(0) = 1/k! used by phi_combination_apply). */
+enum { ETD_SCHEME_ETD1 = 1, ETD_SCHEME_ETD2RK = 2, ETD_SCHEME_ETD3RK = 3, ETD_SCHEME_ETD4RK = 4 };
 
 /* Box grid: dim 2 or 3, n[d] nodes on [lo[d], hi[d]] per axis, equal spacing. */
 typedef struct {
@@ -168,7 +171,8 @@ int phi_combination_apply(etd_ctx* ctx, double t, int32_t p, const double* const
  * rho. */
 int levelset_advance(etd_ctx* ctx, double* rho, double* u, double dt, int32_t reinit);
 
-/* One time step of size h of u_t = A u + f(u) (Section 3: ETD1 or ETD2RK).
+/* One time step of size h of u_t = A u + f(u) (Section 3: ETD1, ETD2RK,
+ * ETD3RK or ETD4RK; 1, 2, 3 or 4 phi-combinations in one persistent launch).
  * rho == NULL: frozen domain (geometry of the last build).  rho != NULL:
  * free boundary, levelset_advance(ctx, rho, u, h, reinit) first, then the
  * ETD step on the new domain.  u: device box array, updated in place. */

@@ -21,6 +21,8 @@ ETD_ERR_NO_GEOMETRY = -8
 
 ETD_SCHEME_ETD1 = 1
 ETD_SCHEME_ETD2RK = 2
+ETD_SCHEME_ETD3RK = 3
+ETD_SCHEME_ETD4RK = 4
 
 
 class EtdGrid(C.Structure):

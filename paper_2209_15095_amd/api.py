@@ -17,6 +17,11 @@ def _ptr(t: torch.Tensor) -> int:
     return t.data_ptr()
 
 
+# ETD schemes of the boundary (Section 3)
+SCHEMES = {"etd1": L.ETD_SCHEME_ETD1, "etd2rk": L.ETD_SCHEME_ETD2RK, "etd3rk": L.ETD_SCHEME_ETD3RK,
+           "etd4rk": L.ETD_SCHEME_ETD4RK}
+
+
 class Context:
     """One etd_ctx: a grid, physics, Krylov options and device workspaces."""
 
@@ -108,7 +113,7 @@ class Context:
                                           int(bool(reinit))), "levelset_advance")
 
     def etd_step(self, scheme: str, h: float, u: torch.Tensor, rho=None, reinit=False, stats=False):
-        code = {"etd1": L.ETD_SCHEME_ETD1, "etd2rk": L.ETD_SCHEME_ETD2RK}[scheme]
+        code = SCHEMES[scheme]
         self._check_box(u, "u")
         if rho is not None:
             self._check_box(rho, "rho")
@@ -123,7 +128,7 @@ class Context:
                      gbar_n=None, scheme: str = "etd2rk"):
         """gbar_n = dL/dU_n from gbar_np1 = dL/dU_{n+1}; dbeta (0-dim float64
         CUDA tensor) accumulates dL/dbeta.  Returns gbar_n."""
-        code = {"etd1": L.ETD_SCHEME_ETD1, "etd2rk": L.ETD_SCHEME_ETD2RK}[scheme]
+        code = SCHEMES[scheme]
         self._check_box(u_n, "u_n")
         self._check_box(gbar_np1, "gbar_np1")
         if gbar_n is None:
@@ -224,7 +229,7 @@ class Batch:
         L.check(self.lib.etd_batch_geometry_build(self.handle, arr), "etd_batch_geometry_build")
 
     def step(self, scheme: str, h: float, us, rhos=None, reinit=False, stats=False):
-        code = {"etd1": L.ETD_SCHEME_ETD1, "etd2rk": L.ETD_SCHEME_ETD2RK}[scheme]
+        code = SCHEMES[scheme]
         ua = self._ptrs(us, "u")
         ra = self._ptrs(rhos, "rho") if rhos is not None else None
         self._sync_stream()
@@ -234,7 +239,7 @@ class Batch:
 
     def graph_steps(self, scheme: str, h: float, us, nsteps: int = 1):
         """nsteps frozen-domain steps, each one replay of a recorded HIP graph."""
-        code = {"etd1": L.ETD_SCHEME_ETD1, "etd2rk": L.ETD_SCHEME_ETD2RK}[scheme]
+        code = SCHEMES[scheme]
         ua = self._ptrs(us, "u")
         self._sync_stream()
         L.check(self.lib.etd_batch_graph_steps(self.handle, code, float(h), ua, int(nsteps)),
@@ -245,7 +250,7 @@ class Batch:
     def autotune(self, scheme: str, h: float, us, trials: int = 3):
         """Pick the group limit (blocks per instance) with the fastest batched
         Krylov launch; returns {"limit": chosen, "ms": {limit: mean ms}}."""
-        code = {"etd1": L.ETD_SCHEME_ETD1, "etd2rk": L.ETD_SCHEME_ETD2RK}[scheme]
+        code = SCHEMES[scheme]
         ua = self._ptrs(us, "u")
         self._sync_stream()
         lim = C.c_int32()

@@ -155,6 +155,16 @@ void timer_free(etd_ctx::Timer& t) {
 
 int check_hip(hipError_t e) { return e == hipSuccess ? ETD_OK : ETD_ERR_HIP; }
 
+// Persistent-kernel job of an ETD scheme (valid schemes only).
+int job_of(int scheme) {
+  switch (scheme) {
+    case ETD_SCHEME_ETD1: return JOB_ETD1;
+    case ETD_SCHEME_ETD3RK: return JOB_ETD3RK;
+    case ETD_SCHEME_ETD4RK: return JOB_ETD4RK;
+    default: return JOB_ETD2RK;
+  }
+}
+
 // Zero the accumulated measurement fields of a device state (stream-ordered;
 // the source is a static host block, so it outlives the copy).
 hipError_t reset_counters(KrylovStateDev* st, hipStream_t s) {
@@ -576,7 +586,7 @@ int levelset_advance(etd_ctx* c, double* rho, double* u, double dt, int32_t rein
 int etd_step(etd_ctx* c, int32_t scheme, double h, double* u, double* rho, int32_t reinit,
              etd_stats* stats) {
   if (!c || !u || !(h >= 0.0) || !isfinite(h)) return ETD_ERR_INVALID;
-  if (scheme != ETD_SCHEME_ETD1 && scheme != ETD_SCHEME_ETD2RK) return ETD_ERR_INVALID;
+  if (scheme < ETD_SCHEME_ETD1 || scheme > ETD_SCHEME_ETD4RK) return ETD_ERR_INVALID;
   if (rho) {
     int r = levelset_advance(c, rho, u, h, reinit);
     if (r) return r;
@@ -584,7 +594,7 @@ int etd_step(etd_ctx* c, int32_t scheme, double h, double* u, double* rho, int32
   if (!c->have_geometry) return ETD_ERR_NO_GEOMETRY;
   int r = gather_to(c, u, V_X0);
   if (r) return r;
-  KrylovDev P = krylov_params(c, scheme == ETD_SCHEME_ETD1 ? JOB_ETD1 : JOB_ETD2RK);
+  KrylovDev P = krylov_params(c, job_of(scheme));
   P.h = h;
   r = run_krylov(c, P);
   if (r) return r;
@@ -779,7 +789,7 @@ void graph_drop(etd_batch* B) {
 int graph_record(etd_batch* B, int scheme, double h, double* const* u) {
   graph_drop(B);
   const int n = B->count;
-  const int mode = scheme == ETD_SCHEME_ETD1 ? JOB_ETD1 : JOB_ETD2RK;
+  const int mode = job_of(scheme);
   std::vector<KrylovDev> params(n);
   std::vector<int> blk(B->capacity);
   bool coop = false;
@@ -913,7 +923,7 @@ int etd_batch_geometry_build(etd_batch* B, const double* const* rho) {
 int etd_batch_step(etd_batch* B, int32_t scheme, double h, double* const* u, double* const* rho,
                    int32_t reinit, etd_stats* stats) {
   if (!B || !u || !(h >= 0.0) || !isfinite(h)) return ETD_ERR_INVALID;
-  if (scheme != ETD_SCHEME_ETD1 && scheme != ETD_SCHEME_ETD2RK) return ETD_ERR_INVALID;
+  if (scheme < ETD_SCHEME_ETD1 || scheme > ETD_SCHEME_ETD4RK) return ETD_ERR_INVALID;
   for (int i = 0; i < B->count; ++i) {
     if (!u[i]) return ETD_ERR_INVALID;
     if (rho && !rho[i]) return ETD_ERR_INVALID;
@@ -948,7 +958,7 @@ int etd_batch_step(etd_batch* B, int32_t scheme, double h, double* const* u, dou
   HIP_TRY(hipEventRecord(B->uptr_done, B->stream));
   B->uptr_pending = true;
   HIP_TRY(launch_gather_batch(B->gb, B->d_uptr, V_X0, B->stream));
-  int r = batch_run_krylov(B, scheme == ETD_SCHEME_ETD1 ? JOB_ETD1 : JOB_ETD2RK, h);
+  int r = batch_run_krylov(B, job_of(scheme), h);
   if (r) return r;
   HIP_TRY(launch_scatter_batch(B->gb, (double* const*)B->d_uptr, V_U, B->stream));
   if (stats) {
@@ -963,7 +973,7 @@ int etd_batch_step(etd_batch* B, int32_t scheme, double h, double* const* u, dou
 
 int etd_batch_graph_steps(etd_batch* B, int32_t scheme, double h, double* const* u, int32_t nsteps) {
   if (!B || !u || nsteps < 0 || !(h >= 0.0) || !isfinite(h)) return ETD_ERR_INVALID;
-  if (scheme != ETD_SCHEME_ETD1 && scheme != ETD_SCHEME_ETD2RK) return ETD_ERR_INVALID;
+  if (scheme < ETD_SCHEME_ETD1 || scheme > ETD_SCHEME_ETD4RK) return ETD_ERR_INVALID;
   for (int i = 0; i < B->count; ++i)
     if (!u[i]) return ETD_ERR_INVALID;
   for (etd_ctx* c : B->inst)
@@ -985,12 +995,12 @@ int etd_batch_graph_steps(etd_batch* B, int32_t scheme, double h, double* const*
 int etd_batch_autotune(etd_batch* B, int32_t scheme, double h, double* const* u, int32_t trials,
                        int32_t* limit_out, double* ms_out) {
   if (!B || !u || trials < 1 || !(h >= 0.0) || !isfinite(h)) return ETD_ERR_INVALID;
-  if (scheme != ETD_SCHEME_ETD1 && scheme != ETD_SCHEME_ETD2RK) return ETD_ERR_INVALID;
+  if (scheme < ETD_SCHEME_ETD1 || scheme > ETD_SCHEME_ETD4RK) return ETD_ERR_INVALID;
   for (int i = 0; i < B->count; ++i)
     if (!u[i]) return ETD_ERR_INVALID;
   for (etd_ctx* c : B->inst)
     if (!c->have_geometry) return ETD_ERR_NO_GEOMETRY;
-  const int mode = scheme == ETD_SCHEME_ETD1 ? JOB_ETD1 : JOB_ETD2RK;
+  const int mode = job_of(scheme);
   const int n = B->count;
   // inputs into the workspaces (as a frozen step would gather them)
   HIP_TRY(hipStreamSynchronize(B->stream));

@@ -85,7 +85,9 @@ enum JobMode {
   JOB_ETD2RK = 2,     // one ETD2RK step of V_X0
   JOB_ETD2RK_STAGE = 3, // only the first stage a of ETD2RK
   JOB_APPLY = 4,        // V_U = A V_B0
-  JOB_ADJ_ETD2RK = 5    // adjoint of one ETD2RK step: V_U = dL/dU_n from V_G, V_X0; *dbeta += dL/dbeta
+  JOB_ADJ_ETD2RK = 5,   // adjoint of one ETD2RK step: V_U = dL/dU_n from V_G, V_X0; *dbeta += dL/dbeta
+  JOB_ETD3RK = 6,       // one ETD3RK step of V_X0
+  JOB_ETD4RK = 7        // one ETD4RK step of V_X0
 };
 
 struct KrylovDev {

@@ -266,9 +266,9 @@ struct Engine {
   unsigned long long tk_sync, tk_expm, tk_tiles;
   int n_sync;
 
-  __device__ gptr<double> V(int i) const { return glb(P.ws) + (size_t)i * P.ld; }
+  __device__ __forceinline__ gptr<double> V(int i) const { return glb(P.ws) + (size_t)i * P.ld; }
 
-  __device__ void fail(int code) {
+  __device__ __forceinline__ void fail(int code) {
     if (threadIdx.x == 0 && lb == 0) atomicCAS(P.status, 0, code);
     failed = true;
   }
@@ -281,7 +281,7 @@ struct Engine {
   // obtains bit-identical results.  Polls are bounded: past SPIN_LIMIT the
   // abort flag goes up and every block leaves.
   template <int NR>
-  __device__ bool grid_sync(const double (&acc)[NR], double (&out)[NR]) {
+  __device__ __forceinline__ bool grid_sync(const double (&acc)[NR], double (&out)[NR]) {
     const unsigned long long t_in = wall_clock64();
     ++pass_no;
     const unsigned gen = (unsigned)pass_no;
@@ -339,7 +339,7 @@ struct Engine {
   // Returns false on a barrier time-out or a non-finite sum (status set; every
   // block takes the same exit).
   template <int NR>
-  __device__ bool finish(double (&acc)[NR], double (&out)[NR]) {
+  __device__ __forceinline__ bool finish(double (&acc)[NR], double (&out)[NR]) {
     block_sum<NR>(acc, c.scratch);
     if (G == 1) {
       for (int k = 0; k < NR; ++k) out[k] = acc[k];
@@ -356,7 +356,7 @@ struct Engine {
     return true;
   }
 
-  __device__ bool barrier() {
+  __device__ __forceinline__ bool barrier() {
     if (G == 1) {
       __syncthreads();
       return true;
@@ -387,7 +387,7 @@ struct Engine {
     int nb[2 * DIM];
   };
 
-  __device__ void load_meta(Meta& m, int slot, int wt) const {
+  __device__ __forceinline__ void load_meta(Meta& m, int slot, int wt) const {
     m.cw = glb(P.g.comp_bits)[(size_t)slot * 4 + wt];
     m.iw = glb(P.g.irr_bits)[(size_t)slot * 4 + wt];
     gptr<const int> nbp = glb(P.g.nbr) + (size_t)slot * NBR_STRIDE;
@@ -395,7 +395,7 @@ struct Engine {
     for (int d = 0; d < 2 * DIM; ++d) m.nb[d] = nbp[d];
   }
 
-  __device__ void make_tile(Tile& t, int slot, int l, const Meta& m) const {
+  __device__ __forceinline__ void make_tile(Tile& t, int slot, int l, const Meta& m) const {
     constexpr int X = TileShape<DIM>::X, Y = TileShape<DIM>::Y, Z = TileShape<DIM>::Z;
     t.slot = slot;
     t.l = l;
@@ -436,7 +436,7 @@ struct Engine {
   }
 
   // Fill the LDS metadata of this block's trips (once per launch).
-  __device__ void cache_meta() {
+  __device__ __forceinline__ void cache_meta() {
     const int stride = G * KTILES;
     const int sub = (int)(threadIdx.x / TILE_PTS);
     const int l = (int)(threadIdx.x % TILE_PTS);
@@ -468,7 +468,7 @@ struct Engine {
   // 256 threads); f(tile point).  Metadata comes from LDS or is prefetched a
   // trip ahead.  No block synchronisation inside: LDS is only read.
   template <class F>
-  __device__ void tiles(F&& f) {
+  __device__ __forceinline__ void tiles(F&& f) {
     const int sub = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / TILE_PTS));
     const int l = (int)(threadIdx.x % TILE_PTS);
     const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
@@ -504,12 +504,12 @@ struct Engine {
     return t.comp ? P.g.coef * (s - cp * vc) : 0.0;
   }
 
-  __device__ double react(double u) const { return u * (P.ra - P.rb * u); }
+  __device__ __forceinline__ double react(double u) const { return u * (P.ra - P.rb * u); }
 
   // ------------------------------------------------------------------ passes
 
   // W_k = A W_{k-1} + sum_l c_l b_{k+l}; at k == p also |W_p|^2 and |U|^2.
-  __device__ bool setup_pass(int k, int p, double tj, double tend, double (&out)[2]) {
+  __device__ __forceinline__ bool setup_pass(int k, int p, double tj, double tend, double (&out)[2]) {
     double cl[PMAX + 1];
     double fact = 1.0, tpow = 1.0;
 #pragma unroll
@@ -543,7 +543,7 @@ struct Engine {
   }
 
   // p == 0: q_0 = U, norms.
-  __device__ bool copy_u_pass(double (&out)[2]) {
+  __device__ __forceinline__ bool copy_u_pass(double (&out)[2]) {
     double acc[2] = {0.0, 0.0};
     tiles([&](const Tile& t) {
       const bool comp = t.comp;
@@ -558,7 +558,7 @@ struct Engine {
   }
 
   // Lanczos pass 0: z_0 = A q_0 into V_Z0; returns <z_0, q_0>.
-  __device__ bool lanczos_first(double& dot) {
+  __device__ __forceinline__ bool lanczos_first(double& dot) {
     gptr<const double> q = V(V_Q0);
     gptr<double> z = V(V_Z0);
     double acc[1] = {0.0};
@@ -578,7 +578,7 @@ struct Engine {
   // Lanczos pass k >= 1: q_k from z_{k-1}, q_{k-1}, q_{k-2} (pointwise, also
   // at the face neighbours), written to V_Q0 + k; z_k = A q_k into
   // V_Z0 + (k & 1).  out = {|q_k|^2, <z_k, q_k>}.
-  __device__ bool lanczos_pass(int k, double (&out)[2]) {
+  __device__ __forceinline__ bool lanczos_pass(int k, double (&out)[2]) {
     gptr<const double> zp = V(V_Z0 + ((k - 1) & 1));
     gptr<const double> q1 = V(V_Q0 + k - 1);
     gptr<const double> q2 = V(V_Q0 + (k >= 2 ? k - 2 : 0));
@@ -630,7 +630,7 @@ struct Engine {
   // ahead.  The staging buffers are the exponential's buffers (R, S; no
   // exponential runs during a pass).  Two block barriers per trip; every
   // block runs the same number of trips for all its tiles.
-  __device__ bool lanczos_lds(int k, double (&out)[2]) {
+  __device__ __forceinline__ bool lanczos_lds(int k, double (&out)[2]) {
     constexpr int X = TileShape<DIM>::X, Y = TileShape<DIM>::Y, Z = TileShape<DIM>::Z;
     constexpr int EX = X + 2, EY = Y + 2, EZ = DIM == 3 ? Z + 2 : 1;
     constexpr int E = EX * EY * EZ;                       // staged box per array
@@ -806,7 +806,7 @@ struct Engine {
   // stored-A q pass moves 40 B).  c_p doubles as the computational mask
   // (NOT_COMP elsewhere).  The q_k buffer alternates between two LDS halves
   // by trip parity, so two block barriers per trip suffice.
-  __device__ bool lanczos_zf2(int k, double (&out)[2]) {
+  __device__ __forceinline__ bool lanczos_zf2(int k, double (&out)[2]) {
     const unsigned long long t_in = wall_clock64();
     double acc[2];
     zf2_loop(uniform<const double>(V(V_Q0 + k - 1)), uniform<const double>(V(V_Q0 + (k >= 2 ? k - 2 : 0))),
@@ -820,7 +820,7 @@ struct Engine {
 
   // out = sum_{k<p} tau^k/k! W_k + sum_i coef_i q_i into the buffer that is
   // not iu; returns |out|^2 in nn.
-  __device__ bool combine_pass(int p, int m, double tau, double& nn) {
+  __device__ __forceinline__ bool combine_pass(int p, int m, double tau, double& nn) {
     double ck[PMAX];
     double f = 1.0, tp = 1.0;
 #pragma unroll
@@ -871,7 +871,7 @@ struct Engine {
 
   // E = exp(X) in R, X the augmented matrix of size N = m + p + 1 built
   // from tau, alpha[0..m-1], nrm[1..m-1].
-  __device__ void expm_aug(int m, int p, double tau) {
+  __device__ __forceinline__ void expm_aug(int m, int p, double tau) {
     const unsigned long long t_in = wall_clock64();
     const int N = m + p + 1;
     // 1-norm of X (column sums)
@@ -942,7 +942,7 @@ struct Engine {
   // written) and b_k (k>=1) in V_B0 + k.  The substeps alternate between
   // V_U and V_T, starting with V_U, so a single substep needs no copy.
   // Returns false on failure (status set).
-  __device__ bool phi_comb(int p, double tend, int b0) {
+  __device__ __forceinline__ bool phi_comb(int p, double tend, int b0) {
     iu = b0;
     if (tend == 0.0) {
       // phi_k(0) = 1/k!
@@ -1125,7 +1125,7 @@ struct Engine {
 
   // ------------------------------------------------------------ jobs
 
-  __device__ bool copy_pass(int dst, int src) {
+  __device__ __forceinline__ bool copy_pass(int dst, int src) {
     tiles([&](const Tile& t) {
       const bool comp = t.comp;
       const size_t idx = t.idx;
@@ -1135,12 +1135,14 @@ struct Engine {
     return barrier();
   }
 
-  __device__ double dreact(double u) const { return P.ra - 2.0 * P.rb * u; }
+  __device__ __forceinline__ double dreact(double u) const { return P.ra - 2.0 * P.rb * u; }
 
   // Number of phi-combinations of a job.
-  __device__ int stages(int mode) const {
+  __device__ __forceinline__ int stages(int mode) const {
     switch (mode) {
       case JOB_ETD2RK: return 2;
+      case JOB_ETD3RK: return 3;
+      case JOB_ETD4RK: return 4;
       case JOB_ADJ_ETD2RK: return 6;
       default: return 1;
     }
@@ -1149,14 +1151,14 @@ struct Engine {
   // Pointwise pass over the computational points: f(idx) at every point of
   // the active tiles (f sees comp), then a barrier.
   template <class F>
-  __device__ bool pointwise(double bytes, F&& f) {
+  __device__ __forceinline__ bool pointwise(double bytes, F&& f) {
     tiles([&](const Tile& t) { f(t.idx, t.comp); });
     bpu += bytes;
     return barrier();
   }
 
   // <V(vb), A V(va)> over the unknowns.
-  __device__ bool dot_A_pass(int va, int vb, double& out) {
+  __device__ __forceinline__ bool dot_A_pass(int va, int vb, double& out) {
     gptr<const double> a = V(va);
     gptr<const double> b = V(vb);
     double acc[1] = {0.0};
@@ -1186,7 +1188,7 @@ struct Engine {
   //   stage 5: phi_0 (g + abar); + V_S                    -> dL/dU_n in V_U
   // and dL/dbeta += (h/beta)(<g, A v_f> + <abar, A v_s>), from
   // d/dbeta phi_k(h beta A_1) = (h/beta) A (phi_k - k phi_{k+1})(hA).
-  __device__ bool assemble(int mode, int stage, int& p, double& t, int& b0) {
+  __device__ __forceinline__ bool assemble(int mode, int stage, int& p, double& t, int& b0) {
     if (mode == JOB_PHI) {
       // the gathered inputs are in place
       p = P.p;
@@ -1245,6 +1247,55 @@ struct Engine {
           return pointwise(24.0, [&](size_t i, bool comp) { T0[i] = comp ? G[i] + AB[i] : 0.0; });
       }
     }
+    if (mode == JOB_ETD3RK || mode == JOB_ETD4RK) {
+      // ETD3RK (F_n = F(U_n), stage results a, b (, c)):
+      //   a = phi_0(h/2) U_n + phi_1(h/2) (h/2) F_n             -> V_A
+      //   b = phi_0 U_n + phi_1 h (2 F(a) - F_n)                  (in V_U)
+      //   U+ = phi_0 U_n + phi_1 h F_n + phi_2 h (-3F_n + 4F(a) - F(b))
+      //        + phi_3 2h (2F_n - 4F(a) + 2F(b))
+      // ETD4RK:
+      //   a = phi_0(h/2) U_n + phi_1(h/2) (h/2) F_n             -> V_A
+      //   b = phi_0(h/2) U_n + phi_1(h/2) (h/2) F(a)            -> V_AB
+      //   c = phi_0(h/2) a + phi_1(h/2) (h/2) (2F(b) - F_n)       (in V_U)
+      //   U+ = phi_0 U_n + phi_1 h F_n + phi_2 h (-3F_n + 2(F(a)+F(b)) - F(c))
+      //        + phi_3 2h (2F_n - 2(F(a)+F(b)) + 2F(c))
+      // (phi_3 standard; the paper's unnormalised phi_3 is 2 phi_3)
+      const int last = stages(mode) - 1;
+      if (stage < last) {
+        p = 1;
+        if (mode == JOB_ETD3RK && stage == 1) {
+          return pointwise(24.0, [&](size_t i, bool comp) {
+            B1[i] = comp ? h * (2.0 * react(Aa[i]) - react(X[i])) : 0.0;
+          });
+        }
+        t = 0.5 * h;
+        if (stage == 0)
+          return pointwise(16.0, [&](size_t i, bool comp) { B1[i] = comp ? 0.5 * h * react(X[i]) : 0.0; });
+        if (stage == 1)
+          return pointwise(16.0, [&](size_t i, bool comp) { B1[i] = comp ? 0.5 * h * react(Aa[i]) : 0.0; });
+        b0 = V_A;   // ETD4RK c starts from a
+        return pointwise(24.0, [&](size_t i, bool comp) {
+          B1[i] = comp ? 0.5 * h * (2.0 * react(AB[i]) - react(X[i])) : 0.0;
+        });
+      }
+      p = 3;
+      if (mode == JOB_ETD3RK) {
+        return pointwise(48.0, [&](size_t i, bool comp) {
+          const double fn = comp ? react(X[i]) : 0.0, fa = comp ? react(Aa[i]) : 0.0;
+          const double fb = comp ? react(U[i]) : 0.0;
+          B1[i] = h * fn;
+          B2[i] = h * (-3.0 * fn + 4.0 * fa - fb);
+          B3[i] = 2.0 * h * (2.0 * fn - 4.0 * fa + 2.0 * fb);
+        });
+      }
+      return pointwise(56.0, [&](size_t i, bool comp) {
+        const double fn = comp ? react(X[i]) : 0.0, fab = comp ? react(Aa[i]) + react(AB[i]) : 0.0;
+        const double fc = comp ? react(U[i]) : 0.0;
+        B1[i] = h * fn;
+        B2[i] = h * (-3.0 * fn + 2.0 * fab - fc);
+        B3[i] = 2.0 * h * (2.0 * fn - 2.0 * fab + 2.0 * fc);
+      });
+    }
     if (stage == 0) {
       // ETD1 / first ETD2RK stage: b_0 = U_n, b_1 = h F(U_n)
       p = 1;
@@ -1259,7 +1310,20 @@ struct Engine {
   }
 
   // What a stage leaves behind once its combination is in V_U.
-  __device__ bool post(int mode, int stage, double& dsum) {
+  __device__ __forceinline__ bool post(int mode, int stage, double& dsum) {
+    if (mode == JOB_ETD3RK || mode == JOB_ETD4RK) {
+      // keep a (and ETD4RK's b) for the later stages
+      gptr<const double> U = V(V_U);
+      if (stage == 0) {
+        gptr<double> Aa = V(V_A);
+        return pointwise(16.0, [&](size_t i, bool comp) { Aa[i] = U[i]; });
+      }
+      if (mode == JOB_ETD4RK && stage == 1) {
+        gptr<double> AB = V(V_AB);
+        return pointwise(16.0, [&](size_t i, bool comp) { AB[i] = U[i]; });
+      }
+      return true;
+    }
     if (mode != JOB_ADJ_ETD2RK) return true;
     const double h = P.h;
     gptr<double> U = V(V_U);
@@ -1292,7 +1356,7 @@ struct Engine {
     }
   }
 
-  __device__ void run() {
+  __device__ __forceinline__ void run() {
     cache_meta();
     const int mode = P.mode;
     if (mode == JOB_APPLY) {
@@ -1306,7 +1370,7 @@ struct Engine {
       return;
     }
     if (mode != JOB_PHI && mode != JOB_ETD1 && mode != JOB_ETD2RK && mode != JOB_ETD2RK_STAGE &&
-        mode != JOB_ADJ_ETD2RK) {
+        mode != JOB_ADJ_ETD2RK && mode != JOB_ETD3RK && mode != JOB_ETD4RK) {
       if (threadIdx.x == 0 && lb == 0) atomicCAS(P.status, 0, ST_INVALID);
       return;
     }

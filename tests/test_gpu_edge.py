@@ -5,6 +5,8 @@
 * A domain with a single computational point (A is 1x1): the
   phi-combination against the oracle's dense route.
 * t = 0: sum_k b_k / k! exactly (phi_k(0) = 1/k!).
+* Invalid scheme codes (and a non-ETD2RK adjoint) return ETD_ERR_INVALID
+  and leave u untouched.
 * All-zero inputs: exactly 0 (the Krylov term vanishes, W_p = 0).
 """
 import sys
@@ -94,4 +96,27 @@ def test_time_zero_and_zero_inputs():
     outz, st = ctx.phi_combination_apply(0.3, zs, stats=True)
     say(f"zero inputs: {st}")
     assert float(outz.abs().max()) == 0.0 and st["status"] == 0
+    ctx.close()
+
+
+def test_invalid_scheme_codes():
+    """Scheme codes outside ETD1..ETD4RK, and any scheme but ETD2RK for the
+    adjoint, return ETD_ERR_INVALID before any device work; u is untouched."""
+    from paper_2209_15095_amd import _lib as L
+    import ctypes as C
+    X, Y = G.coords()
+    rho = np.sqrt(X * X + Y * Y) - 2.5
+    ctx = ctx_for(rho)
+    u = dev(np.ones_like(rho))
+    for code in (0, 5, -1):
+        r = ctx.lib.etd_step(ctx.handle, code, 0.01, C.c_void_p(u.data_ptr()), None, 0, None)
+        assert r == L.ETD_ERR_INVALID, (code, r)
+    torch.cuda.synchronize()
+    assert float((u - 1.0).abs().max()) == 0.0
+    g = dev(np.ones_like(rho))
+    gn = torch.empty_like(g)
+    db = torch.zeros((), dtype=torch.float64, device="cuda")
+    r = ctx.lib.etd_adjoint_step(ctx.handle, L.ETD_SCHEME_ETD4RK, 0.01, C.c_void_p(u.data_ptr()),
+                                 C.c_void_p(g.data_ptr()), C.c_void_p(gn.data_ptr()), C.c_void_p(db.data_ptr()))
+    assert r == L.ETD_ERR_INVALID
     ctx.close()

@@ -122,7 +122,7 @@ def test_phi_combination_parity_stiff(case):
     ctx.close()
 
 
-@pytest.mark.parametrize("scheme", ["etd1", "etd2rk"])
+@pytest.mark.parametrize("scheme", ["etd1", "etd2rk", "etd3rk", "etd4rk"])
 @pytest.mark.parametrize("case", ["fisher64", "ellipsoid3d"])
 def test_etd_step_frozen_parity(scheme, case):
     say(f"etd_step frozen {case} {scheme}")
@@ -168,11 +168,15 @@ def test_levelset_advance_parity_2d():
     ctx.close()
 
 
-def test_free_boundary_fisher64_end_to_end():
-    """Config fisher64 in full: 10 ETD1 steps, mu = 1, moving boundary."""
-    say("free boundary fisher64 10 steps")
+@pytest.mark.parametrize("scheme", [None, "etd4rk"])
+def test_free_boundary_fisher64_end_to_end(scheme):
+    """Config fisher64 in full: 10 ETD1 steps, mu = 1, moving boundary; and
+    the same run with ETD4RK steps."""
+    say(f"free boundary fisher64 10 steps {scheme or 'etd1'}")
     from oracle.freeboundary import free_boundary_step
     w = inputs.fisher64()
+    if scheme is not None:
+        w.scheme = scheme
     og = ogrid(w.grid)
     rho, u = w.rho0.copy(), w.u0.copy()
     ctx = ctx_for(w.grid, beta=w.beta, mu=w.mu)
