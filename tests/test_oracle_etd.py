@@ -5,6 +5,9 @@
 * F independent of U and polynomial in t: ETD1 exact for constant F, ETD2RK
   exact for linear F, ETD3RK / ETD4RK exact for quadratic F (exact solution
   by the eigendecomposition of C and exact integrals).
+* ETD2 multistep (Section 3.1): C = 0 gives the two-step Adams-Bashforth
+  method; exact for F independent of U and linear in t; order 2 on the
+  logistic problem when started with one ETD2RK step.
 * Logistic reaction: step-halving shows order 1 (ETD1) and 2 (ETD2RK).
 * Section 4.2.1 peanut problem: second-order convergence and errors of the
   size printed in Table 1 (tests/golden/table1_etd2rk.json).
@@ -17,7 +20,7 @@ import numpy as np
 import pytest
 import sympy
 
-from oracle.etd import etd1_step, etd2rk_step, etd3rk_step, etd4rk_step, logistic
+from oracle.etd import etd1_step, etd2_step, etd2rk_step, etd3rk_step, etd4rk_step, logistic
 from oracle.geometry import Grid
 from oracle.operator import build_operator
 from oracle.phi import phi_combination, phi_scalar
@@ -104,6 +107,58 @@ def test_logistic_temporal_orders():
         e1 = np.linalg.norm(run(step, 4) - ref)
         e2 = np.linalg.norm(run(step, 8) - ref)
         assert abs(np.log2(e1 / e2) - order) < 0.25
+
+
+def test_etd2_multistep_zero_operator_is_adams_bashforth():
+    n = 6
+    A = np.zeros((n, n))
+    rng = np.random.default_rng(4)
+    U, Fn, Fm = (rng.standard_normal(n) for _ in range(3))
+    h = 0.2
+    ab2 = U + h * (1.5 * Fn - 0.5 * Fm)
+    assert np.allclose(etd2_step(A, h, U, Fn, Fm), ab2, rtol=1e-14, atol=1e-15)
+
+
+def test_etd2_multistep_exact_for_linear_forcing():
+    n = 15
+    A = _spd(n, 5)
+    rng = np.random.default_rng(6)
+    U = rng.standard_normal(n)
+    cs = [rng.standard_normal(n) for _ in range(2)]
+    t0, h = 0.4, 0.25
+    F = lambda t: cs[0] + cs[1] * t
+    got = etd2_step(A, h, U, F(t0), F(t0 - h))
+    ref = _exact_poly_forcing(A, h, U, cs, t0)
+    assert np.linalg.norm(got - ref) < 1e-12 * np.linalg.norm(ref)
+    # a quadratic term is not integrated exactly (the scheme interpolates F
+    # linearly through t0 - h and t0)
+    cq = cs + [rng.standard_normal(n)]
+    Fq = lambda t: cq[0] + cq[1] * t + cq[2] * t * t
+    got = etd2_step(A, h, U, Fq(t0), Fq(t0 - h))
+    assert np.linalg.norm(got - _exact_poly_forcing(A, h, U, cq, t0)) > 1e-6
+
+
+def test_etd2_multistep_second_order():
+    g = Grid(2, (24, 24), (-1.5, -1.5), (1.5, 1.5))
+    X, Y = g.coords()
+    op = build_operator(g, np.hypot(X, Y) - 1.0, 1.0)
+    f, _ = logistic(1.0, 1.0)
+    U0 = op.gather(0.5 + 0.3 * np.cos(X) * np.sin(2 * Y))
+    T = 0.4
+
+    def run(nsteps):
+        h = T / nsteps
+        U = etd2rk_step(op.A, h, U0, f)
+        Fm = f(U0)
+        for _ in range(nsteps - 1):
+            Fn = f(U)
+            U, Fm = etd2_step(op.A, h, U, Fn, Fm), Fn
+        return U
+
+    ref = run(512)
+    e1 = np.linalg.norm(run(4) - ref)
+    e2 = np.linalg.norm(run(8) - ref)
+    assert abs(np.log2(e1 / e2) - 2.0) < 0.25
 
 
 def _peanut_forcing():
