@@ -41,8 +41,9 @@ PEAK_HBM_GBS = 8000.0
 # workload and a hash of the kernel sources they were taken on.  A changed
 # kernel has no entry, and its traffic is reported as null.
 MEASURED_TRAFFIC = {
-    ("star512", "624b3d48cb5f2b12"): 30.40e6,
-    ("disk4097", "624b3d48cb5f2b12"): 29.51e9,
+    ("star512", "f35c55e251b9f402"): 32.31e6,
+    ("disk4097", "f35c55e251b9f402"): 29.58e9,
+    ("sphere385", "f35c55e251b9f402"): 42.55e9,
 }
 
 

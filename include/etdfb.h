@@ -179,6 +179,23 @@ int levelset_advance(etd_ctx* ctx, double* rho, double* u, double dt, int32_t re
 int etd_step(etd_ctx* ctx, int32_t scheme, double h, double* u, double* rho, int32_t reinit,
              etd_stats* stats);
 
+/* One ETD2 multistep step (Section 3.1, eq. 3.6 with s = 1):
+ * U_{n+1} = phi_0(hA) U_n + h phi_1(hA) F_n + h phi_2(hA) (F_n - F_{n-1}),
+ * F_n = f(U_n), one phi-combination in one persistent launch.
+ * f_prev: device box array owned by the caller.  On entry (first == 0) it
+ * holds F_{n-1} = f(U_{n-1}) at the computational points of the domain
+ * that U_n lives on (what the previous call left there); on return it holds
+ * F_n at the computational points of the domain of this step and 0
+ * elsewhere.  first != 0: f_prev is not read and the step is one ETD2RK step
+ * (Section 3.2), which starts the two-step recursion.  rho == NULL: frozen
+ * domain.  rho != NULL: free boundary as in etd_step; F_{n-1} is carried to
+ * the points that join the domain by the same quadratic normal
+ * extrapolation from the old computational points that carries u (Section
+ * 4.3, Step 2), then levelset_advance(ctx, rho, u, h, reinit) runs.  u:
+ * device box array, updated in place; f_prev must not alias u or rho. */
+int etd_multistep_step(etd_ctx* ctx, double h, double* u, double* f_prev, int32_t first, double* rho,
+                       int32_t reinit, etd_stats* stats);
+
 /* Discrete adjoint of one ETD2RK step (Section 3.2) on the frozen domain of
  * the last etd_geometry_build, for the loss gradient of a step-by-step
  * backward sweep.  A is symmetric (Section 2) and equals beta A_1 for the

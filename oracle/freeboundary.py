@@ -17,7 +17,7 @@ from __future__ import annotations
 import numpy as np
 
 from . import levelset as ls
-from .etd import etd_step, logistic
+from .etd import etd2_step, etd2rk_step, etd_step, logistic
 from .geometry import Grid, classify
 from .operator import build_operator
 
@@ -50,6 +50,35 @@ def free_boundary_step(grid: Grid, rho, u_box, h, beta=1.0, mu=1.0, a=1.0, b=1.0
     U = op.gather(u_new)
     U = etd_step(op.A, h, U, f, scheme, method=method)
     return rho_new, op.scatter(U), op
+
+
+def multistep_step(grid: Grid, rho, u_box, f_prev_box, h, beta=1.0, mu=1.0, a=1.0, b=1.0, first=False,
+                   reinit=False, frozen=False, method="auto"):
+    """One step with ETD2 multistep (Section 3.1) in the Section 4.3 algorithm.
+
+    f_prev_box holds F(U_{n-1}) on the computational points of the current
+    domain (not read when first).  On a moving domain it is carried to the
+    new computational points by the same quadratic normal extrapolation from
+    the old computational points that carries u (Step 2).  The first step is
+    one ETD2RK step.  Returns (rho_new, u_new_box, f_new_box, op), f_new_box
+    = F(U_n) on the new computational points and 0 elsewhere."""
+    if frozen:
+        rho_new, u_new, f_ext = rho, u_box, f_prev_box
+    else:
+        f_ext = None
+        if not first:
+            _, comp_old, _ = classify(grid, rho)
+            f_ext = ls.aslam_extrapolate(f_prev_box, comp_old, rho, grid.dx)
+        rho_new, u_new, _ = levelset_advance(grid, rho, u_box, h, mu, reinit)
+    op = build_operator(grid, rho_new, beta)
+    f, _ = logistic(a, b)
+    U = op.gather(u_new)
+    Fn = f(U)
+    if first:
+        U = etd2rk_step(op.A, h, U, f, method=method)
+    else:
+        U = etd2_step(op.A, h, U, Fn, op.gather(f_ext), method=method)
+    return rho_new, op.scatter(U), op.scatter(Fn), op
 
 
 def run(workload_grid: Grid, rho0, u0, steps, h, beta, mu, scheme, reinit_every=5,

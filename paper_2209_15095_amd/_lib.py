@@ -74,6 +74,8 @@ SIGNATURES = {
     "levelset_advance": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_int32]),
     "etd_step": (C.c_int, [C.c_void_p, C.c_int32, C.c_double, C.c_void_p, C.c_void_p, C.c_int32,
                            C.POINTER(EtdStats)]),
+    "etd_multistep_step": (C.c_int, [C.c_void_p, C.c_double, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p,
+                                     C.c_int32, C.POINTER(EtdStats)]),
     "etd_adjoint_step": (C.c_int, [C.c_void_p, C.c_int32, C.c_double, C.c_void_p, C.c_void_p, C.c_void_p,
                                    C.c_void_p]),
     "etd_ctx_sync": (C.c_int, [C.c_void_p]),

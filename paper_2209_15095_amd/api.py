@@ -124,6 +124,22 @@ class Context:
                                   C.byref(st) if st is not None else None), "etd_step")
         return st.as_dict() if stats else None
 
+    def multistep_step(self, h: float, u: torch.Tensor, f_prev: torch.Tensor, first: bool, rho=None,
+                       reinit=False, stats=False):
+        """One ETD2 multistep step (etd_multistep_step): u in place; f_prev
+        holds F(U_{n-1}) on entry (ignored when first) and F(U_n) on return."""
+        self._check_box(u, "u")
+        self._check_box(f_prev, "f_prev")
+        if rho is not None:
+            self._check_box(rho, "rho")
+        self._sync_stream()
+        st = L.EtdStats() if stats else None
+        L.check(self.lib.etd_multistep_step(self.handle, float(h), C.c_void_p(_ptr(u)), C.c_void_p(_ptr(f_prev)),
+                                            int(bool(first)),
+                                            C.c_void_p(_ptr(rho)) if rho is not None else None, int(bool(reinit)),
+                                            C.byref(st) if st is not None else None), "etd_multistep_step")
+        return st.as_dict() if stats else None
+
     def adjoint_step(self, h: float, u_n: torch.Tensor, gbar_np1: torch.Tensor, dbeta: torch.Tensor,
                      gbar_n=None, scheme: str = "etd2rk"):
         """gbar_n = dL/dU_n from gbar_np1 = dL/dU_{n+1}; dbeta (0-dim float64

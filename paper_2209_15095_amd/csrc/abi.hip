@@ -609,6 +609,50 @@ int etd_step(etd_ctx* c, int32_t scheme, double h, double* u, double* rho, int32
   return ETD_OK;
 }
 
+int etd_multistep_step(etd_ctx* c, double h, double* u, double* f_prev, int32_t first, double* rho,
+                       int32_t reinit, etd_stats* stats) {
+  if (!c || !u || !f_prev || f_prev == u || f_prev == rho || !(h >= 0.0) || !isfinite(h)) return ETD_ERR_INVALID;
+  if (rho) {
+    if (!c->have_geometry) {
+      int r = etd_geometry_build(c, rho);
+      if (r) return r;
+    }
+    if (!first) {
+      // F_{n-1} extended from the computational points of the current rho
+      c->lsb.h_inst[0] = levelset_inst(c, rho, f_prev);
+      HIP_TRY(timer_begin(c->profiling, c->stream, c->t_levelset));
+      HIP_TRY(levelset_extend(c->lsb, c->stream));
+      HIP_TRY(timer_end(c->profiling, c->stream, c->t_levelset));
+      HIP_TRY(hipStreamSynchronize(c->stream));   // h_inst is refilled next
+    }
+    int r = levelset_advance(c, rho, u, h, reinit);
+    if (r) return r;
+  }
+  if (!c->have_geometry) return ETD_ERR_NO_GEOMETRY;
+  int r = gather_to(c, u, V_X0);
+  if (r) return r;
+  if (!first) {
+    r = gather_to(c, f_prev, V_G);
+    if (r) return r;
+  }
+  KrylovDev P = krylov_params(c, JOB_ETD2);
+  P.h = h;
+  P.first = first ? 1 : 0;
+  r = run_krylov(c, P);
+  if (r) return r;
+  r = scatter_from(c, V_U, u);
+  if (r) return r;
+  r = scatter_from(c, V_G, f_prev);
+  if (r) return r;
+  if (stats) {
+    r = fill_stats(c, stats);
+    if (r) return r;
+    int st = latched_status(c);
+    if (st) return st;
+  }
+  return ETD_OK;
+}
+
 int etd_adjoint_step(etd_ctx* c, int32_t scheme, double h, const double* u_n, const double* gbar_np1,
                      double* gbar_n, double* dL_dbeta) {
   if (!c || !u_n || !gbar_np1 || !gbar_n || !dL_dbeta || !(h >= 0.0) || !isfinite(h)) return ETD_ERR_INVALID;

@@ -87,7 +87,8 @@ enum JobMode {
   JOB_APPLY = 4,        // V_U = A V_B0
   JOB_ADJ_ETD2RK = 5,   // adjoint of one ETD2RK step: V_U = dL/dU_n from V_G, V_X0; *dbeta += dL/dbeta
   JOB_ETD3RK = 6,       // one ETD3RK step of V_X0
-  JOB_ETD4RK = 7        // one ETD4RK step of V_X0
+  JOB_ETD4RK = 7,       // one ETD4RK step of V_X0
+  JOB_ETD2 = 8          // one ETD2 multistep step of V_X0; F(U_{n-1}) in V_G, replaced by F(U_n)
 };
 
 struct KrylovDev {
@@ -111,6 +112,7 @@ struct KrylovDev {
   double h;                   // ETD step
   int g_first, g_size;        // blocks of this instance in the launch grid
   int stage_min;              // fewest active tiles for the LDS-staged Lanczos pass
+  int first;                  // JOB_ETD2: no F(U_{n-1}) yet, take one ETD2RK step
 };
 
 // Default of KrylovDev::stage_min: the LDS-staged Lanczos pass pays where

@@ -1141,6 +1141,7 @@ struct Engine {
   __device__ __forceinline__ int stages(int mode) const {
     switch (mode) {
       case JOB_ETD2RK: return 2;
+      case JOB_ETD2: return P.first ? 2 : 1;
       case JOB_ETD3RK: return 3;
       case JOB_ETD4RK: return 4;
       case JOB_ADJ_ETD2RK: return 6;
@@ -1296,6 +1297,20 @@ struct Engine {
         B3[i] = 2.0 * h * (2.0 * fn - 2.0 * fab + 2.0 * fc);
       });
     }
+    if (mode == JOB_ETD2 && stage == 0) {
+      // ETD2 multistep: b_0 = U_n, b_1 = h F_n, b_2 = h (F_n - F_{n-1}),
+      // F_{n-1} read from V_G, which then keeps F_n for the next step.  The
+      // first step (no F_{n-1}) is an ETD2RK step; it stores F_n as well.
+      gptr<double> Gw = V(V_G);
+      const bool first = P.first != 0;
+      p = first ? 1 : 2;
+      return pointwise(first ? 24.0 : 40.0, [&](size_t i, bool comp) {
+        const double fn = comp ? react(X[i]) : 0.0;
+        B1[i] = h * fn;
+        if (!first) B2[i] = h * (fn - (comp ? Gw[i] : 0.0));
+        Gw[i] = fn;
+      });
+    }
     if (stage == 0) {
       // ETD1 / first ETD2RK stage: b_0 = U_n, b_1 = h F(U_n)
       p = 1;
@@ -1370,7 +1385,7 @@ struct Engine {
       return;
     }
     if (mode != JOB_PHI && mode != JOB_ETD1 && mode != JOB_ETD2RK && mode != JOB_ETD2RK_STAGE &&
-        mode != JOB_ADJ_ETD2RK && mode != JOB_ETD3RK && mode != JOB_ETD4RK) {
+        mode != JOB_ADJ_ETD2RK && mode != JOB_ETD3RK && mode != JOB_ETD4RK && mode != JOB_ETD2) {
       if (threadIdx.x == 0 && lb == 0) atomicCAS(P.status, 0, ST_INVALID);
       return;
     }

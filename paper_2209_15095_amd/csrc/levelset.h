@@ -93,5 +93,10 @@ void levelset_batch_free(LevelsetBatch& b);
 // reinitialisation (if reinit) and the restriction of u.
 hipError_t levelset_begin(LevelsetBatch& b, double dt, int reinit, hipStream_t stream);
 hipError_t levelset_end(LevelsetBatch& b, hipStream_t stream);
+// The extrapolation of Step 2 alone: each instance's u (any box field known
+// on the computational points of rho) is replaced, over the whole box, by its
+// quadratic normal extrapolation from those points; rho is not changed.  The
+// caller synchronises the stream before it refills h_inst.
+hipError_t levelset_extend(LevelsetBatch& b, hipStream_t stream);
 
 }  // namespace etdfb

@@ -445,19 +445,20 @@ __global__ __launch_bounds__(256) void rk_kernel(const LsInst* __restrict__ inst
   }
 }
 
-// whole box: u = comp(rho_new) ? u_ext : 0
+// whole box: u = comp(rho_new) ? u_ext : 0, or u = u_ext everywhere (all)
 template <int DIM>
 __global__ __launch_bounds__(256) void restrict_kernel(const LsInst* __restrict__ insts,
-                                                       const int* __restrict__ off, int count, int uext_arr) {
+                                                       const int* __restrict__ off, int count, int uext_arr,
+                                                       int all) {
   const Where w = locate<DIM>(insts, off, count, LS_FULL);
   if (!w.in) return;
   const LsInst& I = *w.I;
-  const bool c = comp_point<DIM>(I, w, glb((const double*)I.rho));
+  const bool c = all || comp_point<DIM>(I, w, glb((const double*)I.rho));
   glb(I.u)[w.id] = c ? arr(I, uext_arr)[w.id] : 0.0;
 }
 
 template <int DIM>
-hipError_t begin_dim(LevelsetBatch& b, hipStream_t st) {
+hipError_t begin_dim(LevelsetBatch& b, hipStream_t st, bool speed) {
   const int n = b.count;
   const LsInst* I = b.d_inst;
   const int* off = b.d_off;
@@ -509,6 +510,7 @@ hipError_t begin_dim(LevelsetBatch& b, hipStream_t st) {
   const int uext = stage(LS_A3, A_E0, A_E1, A_E2, 0, 0, ASLAM_ITERS, 0);
   if (unn != A_E3 || un != A_E2 || uext != A_E1) return hipErrorUnknown;
   b.uext = uext;
+  if (!speed) return hipSuccess;
   // Stefan speed, extension V <-> S (ends in V), maximum on the last sweep
   LL(LS_V, velocity_kernel, b.uext);
   if (stage(LS_V, A_V, A_S, -1, 3, 1, VEL_ITERS, 1) != A_V) return hipErrorUnknown;
@@ -544,7 +546,16 @@ hipError_t end_dim(LevelsetBatch& b, hipStream_t st) {
         if ((e = hipGetLastError()) != hipSuccess) return e;
       }
   }
-  hipLaunchKernelGGL(restrict_kernel<DIM>, dim3(b.total[LS_FULL]), B, 0, st, I, off, n, b.uext);
+  hipLaunchKernelGGL(restrict_kernel<DIM>, dim3(b.total[LS_FULL]), B, 0, st, I, off, n, b.uext, 0);
+  return hipGetLastError();
+}
+
+template <int DIM>
+hipError_t extend_dim(LevelsetBatch& b, hipStream_t st) {
+  hipError_t e = begin_dim<DIM>(b, st, false);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(restrict_kernel<DIM>, dim3(b.total[LS_FULL]), dim3(256), 0, st, b.d_inst, b.d_off, b.count,
+                     b.uext, 1);
   return hipGetLastError();
 }
 
@@ -592,10 +603,11 @@ void levelset_batch_free(LevelsetBatch& b) {
   b = LevelsetBatch{};
 }
 
-hipError_t levelset_begin(LevelsetBatch& b, double dt, int reinit, hipStream_t st) {
+namespace {
+
+// Launch offsets of the lists and the device copy of the instance table.
+hipError_t upload(LevelsetBatch& b, hipStream_t st) {
   const int n = b.count;
-  b.dt = dt;
-  b.reinit = reinit;
   for (int q = 0; q <= LS_NLIST; ++q) {
     int acc = 0;
     for (int i = 0; i < n; ++i) {
@@ -610,12 +622,25 @@ hipError_t levelset_begin(LevelsetBatch& b, double dt, int reinit, hipStream_t s
   hipError_t e;
   if ((e = hipMemcpyAsync(b.d_inst, b.h_inst, sizeof(LsInst) * n, hipMemcpyHostToDevice, st)) != hipSuccess)
     return e;
-  if ((e = hipMemcpyAsync(b.d_off, b.h_off, sizeof(int) * (LS_NLIST + 1) * (n + 1), hipMemcpyHostToDevice, st)) !=
-      hipSuccess)
-    return e;
-  e = (b.dim == 2) ? begin_dim<2>(b, st) : begin_dim<3>(b, st);
+  return hipMemcpyAsync(b.d_off, b.h_off, sizeof(int) * (LS_NLIST + 1) * (n + 1), hipMemcpyHostToDevice, st);
+}
+
+}  // namespace
+
+hipError_t levelset_begin(LevelsetBatch& b, double dt, int reinit, hipStream_t st) {
+  b.dt = dt;
+  b.reinit = reinit;
+  hipError_t e = upload(b, st);
   if (e != hipSuccess) return e;
-  return hipMemcpyAsync(b.h_vmax, b.d_vmax, sizeof(double) * n, hipMemcpyDeviceToHost, st);
+  e = (b.dim == 2) ? begin_dim<2>(b, st, true) : begin_dim<3>(b, st, true);
+  if (e != hipSuccess) return e;
+  return hipMemcpyAsync(b.h_vmax, b.d_vmax, sizeof(double) * b.count, hipMemcpyDeviceToHost, st);
+}
+
+hipError_t levelset_extend(LevelsetBatch& b, hipStream_t st) {
+  hipError_t e = upload(b, st);
+  if (e != hipSuccess) return e;
+  return (b.dim == 2) ? extend_dim<2>(b, st) : extend_dim<3>(b, st);
 }
 
 hipError_t levelset_end(LevelsetBatch& b, hipStream_t st) {

@@ -196,6 +196,68 @@ def test_free_boundary_fisher64_end_to_end(scheme):
     ctx.close()
 
 
+@pytest.mark.parametrize("case", ["fisher64", "ellipsoid3d"])
+def test_etd2_multistep_frozen_parity(case):
+    """ETD2 multistep (Section 3.1) on a frozen domain: an ETD2RK start,
+    then three two-step updates; u and the returned F(U_n) against the
+    oracle step by step."""
+    say(f"etd2 multistep frozen {case}")
+    from oracle.freeboundary import multistep_step
+    if case == "fisher64":
+        w = inputs.fisher64()
+        g, rho, u0 = w.grid, w.rho0, w.u0
+    else:
+        g, rho = small_ellipsoid3d()
+        u0 = np.where(rho < 0, np.random.default_rng(0).uniform(0.2, 0.8, rho.shape), 0.0)
+    og = ogrid(g)
+    ctx = ctx_for(g, beta=1.0)
+    ctx.geometry_build(dev(rho))
+    ud, fd = dev(u0), dev(np.full_like(u0, np.nan))
+    u, fp = u0.copy(), np.zeros_like(u0)
+    for k in range(4):
+        _, u, fp, op = multistep_step(og, rho, u, fp, 0.05, first=(k == 0), frozen=True)
+        st = ctx.multistep_step(0.05, ud, fd, first=(k == 0), stats=True)
+        say(f"  step {k} stats {st}")
+        ug, fg = host(ud), host(fd)
+        assert np.all(ug[~op.comp] == 0.0) and np.all(fg[~op.comp] == 0.0)
+        assert rel_l2(ug[op.comp], u[op.comp]) <= 1e-9
+        assert rel_l2(fg[op.comp], fp[op.comp]) <= 1e-9
+    ctx.close()
+
+
+def test_etd2_multistep_free_boundary_growing():
+    """ETD2 multistep steps on a moving boundary (the fisher64 grid and
+    initial data, mu = 2, h = 0.05, reinitialisation on step 4): the domain
+    grows (164, 184, 208, 208, 216 unknowns), so F(U_{n-1}) is carried to the
+    points that join it by the extrapolation that carries u."""
+    say("etd2 multistep free boundary, growing domain, 5 steps")
+    from oracle.freeboundary import multistep_step
+    w = inputs.fisher64()
+    og = ogrid(w.grid)
+    mu, h = 2.0, 0.05
+    rho, u, fp = w.rho0.copy(), w.u0.copy(), np.zeros_like(w.u0)
+    ctx = ctx_for(w.grid, beta=w.beta, mu=mu)
+    rd, ud, fd = dev(rho), dev(u), dev(np.zeros_like(u))
+    ctx.geometry_build(rd)
+    ns = []
+    for m in range(5):
+        reinit = m == 3
+        rho, u, fp, op = multistep_step(og, rho, u, fp, h, w.beta, mu, first=(m == 0), reinit=reinit,
+                                        method="dense")
+        ns.append(op.n)
+        ctx.multistep_step(h, ud, fd, first=(m == 0), rho=rd, reinit=reinit)
+    rg, ug, fg = host(rd), host(ud), host(fd)
+    _, comp_g, _ = classify(og, rg)
+    assert np.array_equal(comp_g, op.comp)
+    say(f"  unknowns {ns}  rho diff {np.abs(rg - rho).max():.3e}  "
+        f"u rel {rel_l2(ug[op.comp], u[op.comp]):.3e}  f rel {rel_l2(fg[op.comp], fp[op.comp]):.3e}")
+    assert ns[2] > ns[1] > ns[0] and ns[4] > ns[3]   # two-step updates that meet new points
+    assert np.abs(rg - rho).max() <= 1e-10
+    assert rel_l2(ug[op.comp], u[op.comp]) <= 1e-9
+    assert rel_l2(fg[op.comp], fp[op.comp]) <= 1e-9
+    ctx.close()
+
+
 def test_bitwise_deterministic():
     say("determinism")
     g, rho = small_star2d()
