@@ -63,12 +63,13 @@ struct Ctl {
 
 // The loop of the 2D z-free staged Lanczos pass (Engine::lanczos_zf2), a
 // function of its own so that its registers are allocated apart from the
-// rest of the persistent kernel.  acc receives this thread's partial sums of
+// rest of the persistent kernel.  tb is the block's tile range within a
+// trip (Engine::tile_block).  acc receives this thread's partial sums of
 // |q_k|^2 and <A q_k, q_k>.
 __device__ __attribute__((noinline)) void zf2_loop(gptr<const double> q1, gptr<const double> q2,
                                                    gptr<double> qk, gptr<const double> cdiag, double coef,
                                                    double alpha, double inv_n, double cm, int na, int G,
-                                                   int lb, lptr<double> stage, lptr<const int> mnb,
+                                                   int tb, lptr<double> stage, lptr<const int> mnb,
                                                    double* acc) {
   constexpr int X = TileShape<2>::X, Y = TileShape<2>::Y;
   constexpr int W2 = X + 4, H2 = Y + 4;   // q_{k-1} box (2-node halo)
@@ -90,7 +91,7 @@ __device__ __attribute__((noinline)) void zf2_loop(gptr<const double> q1, gptr<c
   cm = uniform(cm);
   na = __builtin_amdgcn_readfirstlane(na);
   G = __builtin_amdgcn_readfirstlane(G);
-  lb = __builtin_amdgcn_readfirstlane(lb);
+  tb = __builtin_amdgcn_readfirstlane(tb);
   double a0 = 0.0, a1 = 0.0;
     const int sub = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / TILE_PTS));
     const int l = (int)(threadIdx.x % TILE_PTS);
@@ -157,7 +158,7 @@ __device__ __attribute__((noinline)) void zf2_loop(gptr<const double> q1, gptr<c
       h1p2 = (x + 2) + W2 * (y + 2);
     }
     const int stride = G * KTILES;
-    const int base0 = lb * KTILES;
+    const int base0 = tb * KTILES;
     // loads of one trip (element 0 where there is nothing; selected after)
     double a_q1, a_q2, a_cd, a_h2, a_h1q, a_h1c;
     auto issue = [&](int r, int slot, bool valid) {
@@ -267,6 +268,16 @@ struct Engine {
   int n_sync;
 
   __device__ __forceinline__ gptr<double> V(int i) const { return glb(P.ws) + (size_t)i * P.ld; }
+
+  // Index of this block's range of KTILES tiles within a loop trip.  The
+  // hardware hands consecutive workgroups to the 8 XCDs in turn; numbering
+  // the ranges so that the blocks of one XCD take adjacent ranges keeps a
+  // tile and its nearest neighbours in the compacted order (the rest of its
+  // row, the neighbouring rows) under one L2.
+  __device__ __forceinline__ int tile_block() const {
+    if ((G & 7) != 0 || (P.g_first & 7) != 0) return lb;
+    return (lb & 7) * (G >> 3) + (lb >> 3);
+  }
 
   __device__ __forceinline__ void fail(int code) {
     if (threadIdx.x == 0 && lb == 0) atomicCAS(P.status, 0, code);
@@ -441,8 +452,9 @@ struct Engine {
     const int sub = (int)(threadIdx.x / TILE_PTS);
     const int l = (int)(threadIdx.x % TILE_PTS);
     const int w = (int)(threadIdx.x >> 6);
+    const int tb = tile_block();
     for (int r = 0; r < META_TRIPS; ++r) {
-      const int slot = lb * KTILES + sub + r * stride;
+      const int slot = tb * KTILES + sub + r * stride;
       if (slot >= nact) break;
       if ((l & 63) == 0) {
         c.mcw[r][w] = glb(P.g.comp_bits)[(size_t)slot * 4 + (l >> 6)];
@@ -473,7 +485,7 @@ struct Engine {
     const int l = (int)(threadIdx.x % TILE_PTS);
     const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int stride = G * KTILES;
-    int slot = lb * KTILES + sub;
+    int slot = tile_block() * KTILES + sub;
     const unsigned long long t_in = wall_clock64();
     Meta m;
     if (slot < nact) trip_meta(m, 0, slot, sub, w);
@@ -691,7 +703,7 @@ struct Engine {
       hpos[r] = (cc[0] + 1) + EX * ((cc[1] + 1) + EY * (DIM == 3 ? cc[2] + 1 : 0));
     }
     const int stride = G * KTILES;
-    const int base0 = lb * KTILES;
+    const int base0 = tile_block() * KTILES;
     double acc[2] = {0.0, 0.0};
     const unsigned long long t_in = wall_clock64();
     // loads of trip r: the point and the halo nodes (0 where no tile)
@@ -811,7 +823,7 @@ struct Engine {
     double acc[2];
     zf2_loop(uniform<const double>(V(V_Q0 + k - 1)), uniform<const double>(V(V_Q0 + (k >= 2 ? k - 2 : 0))),
              uniform<double>(V(V_Q0 + k)), uniform<const double>(glb(P.g.cdiag)), P.g.coef, c.alpha[k - 1],
-             1.0 / c.nrm[k - 1], (k >= 2) ? c.nrm[k - 1] / c.nrm[k - 2] : 0.0, nact, G, lb, lds(R),
+             1.0 / c.nrm[k - 1], (k >= 2) ? c.nrm[k - 1] / c.nrm[k - 2] : 0.0, nact, G, tile_block(), lds(R),
              lds((const int*)&c.mnb[0][0][0]), acc);
     if (threadIdx.x == 0 && lb == 0) tk_tiles += wall_clock64() - t_in;
     bpu += 32.0;
