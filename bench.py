@@ -41,9 +41,9 @@ PEAK_HBM_GBS = 8000.0
 # workload and a hash of the kernel sources they were taken on.  A changed
 # kernel has no entry, and its traffic is reported as null.
 MEASURED_TRAFFIC = {
-    ("star512", "f35c55e251b9f402"): 32.31e6,
-    ("disk4097", "f35c55e251b9f402"): 29.58e9,
-    ("sphere385", "f35c55e251b9f402"): 42.55e9,
+    ("star512", "2d3ed19dc73c5097"): 32.19e6,
+    ("disk4097", "2d3ed19dc73c5097"): 25.97e9,
+    ("sphere385", "2d3ed19dc73c5097"): 33.93e9,
 }
 
 
