@@ -179,7 +179,7 @@ int levelset_advance(etd_ctx* ctx, double* rho, double* u, double dt, int32_t re
 int etd_step(etd_ctx* ctx, int32_t scheme, double h, double* u, double* rho, int32_t reinit,
              etd_stats* stats);
 
-/* One ETD2 multistep step (Section 3.1, eq. 3.6 with s = 1):
+/* One ETD2 multistep step (Section 3.1, the ETD2 formula, eq. 3.6 with s = 2):
  * U_{n+1} = phi_0(hA) U_n + h phi_1(hA) F_n + h phi_2(hA) (F_n - F_{n-1}),
  * F_n = f(U_n), one phi-combination in one persistent launch.
  * f_prev: device box array owned by the caller.  On entry (first == 0) it
