@@ -5,8 +5,8 @@
 * F independent of U and polynomial in t: ETD1 exact for constant F, ETD2RK
   exact for linear F, ETD3RK / ETD4RK exact for quadratic F (exact solution
   by the eigendecomposition of C and exact integrals).
-* ETD2 multistep (Section 3.1): C = 0 gives the two-step Adams-Bashforth
-  method; exact for F independent of U and linear in t; order 2 on the
+* ETD2 multistep (Section 3.1): eq. 3.6 with s = 2 evaluated by quadrature
+  of its g_m integrals; C = 0 gives the two-step Adams-Bashforth method; exact for F independent of U and linear in t; order 2 on the
   logistic problem when started with one ETD2RK step.
 * Logistic reaction: step-halving shows order 1 (ETD1) and 2 (ETD2RK).
 * Section 4.2.1 peanut problem: second-order convergence and errors of the
@@ -117,6 +117,30 @@ def test_etd2_multistep_zero_operator_is_adams_bashforth():
     h = 0.2
     ab2 = U + h * (1.5 * Fn - 0.5 * Fm)
     assert np.allclose(etd2_step(A, h, U, Fn, Fm), ab2, rtol=1e-14, atol=1e-15)
+
+
+def test_etd2_multistep_is_eq_3_6_with_two_evaluations():
+    """Eq. 3.6 with s = 2 evaluated as printed: U e^{hC} + h (g_0 F_n +
+    g_1 (F_n - F_{n-1})), g_m = (-1)^m int_0^1 e^{(1-l)hC} binom(-l, m) dl,
+    the integrals by 40-point Gauss-Legendre over the eigenvalues of C."""
+    n = 12
+    A = _spd(n, 7)
+    rng = np.random.default_rng(8)
+    U, Fn, Fm = (rng.standard_normal(n) for _ in range(3))
+    h = 0.3
+    lam, Q = np.linalg.eigh(A)
+    x, wq = np.polynomial.legendre.leggauss(40)
+    l = 0.5 * (x + 1.0)
+    wq = 0.5 * wq
+    E = np.exp(np.outer(1.0 - l, h * lam))            # e^{(1-l) h lam}, quadrature node by eigenvalue
+    binom = [np.ones_like(l), -l]                       # binom(-l, 0), binom(-l, 1)
+    g = [(-1) ** m * (wq * binom[m]) @ E for m in range(2)]
+    diffs = [Fn, Fn - Fm]                               # sum_k (-1)^k binom(m, k) F_{n-k}
+    ref = Q @ (np.exp(h * lam) * (Q.T @ U))
+    for m in range(2):
+        ref = ref + h * (Q @ (g[m] * (Q.T @ diffs[m])))
+    got = etd2_step(A, h, U, Fn, Fm)
+    assert np.linalg.norm(got - ref) < 1e-12 * np.linalg.norm(ref)
 
 
 def test_etd2_multistep_exact_for_linear_forcing():
