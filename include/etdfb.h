@@ -254,6 +254,17 @@ int etd_batch_geometry_build(etd_batch* batch, const double* const* rho);
 int etd_batch_step(etd_batch* batch, int32_t scheme, double h, double* const* u, double* const* rho,
                    int32_t reinit, etd_stats* stats);
 
+/* etd_multistep_step for every instance with the same h, first and reinit
+ * flags (Section 3.1, the ETD2 formula; Section 4.3 on moving domains): one
+ * batched persistent launch of one ETD2 multistep step per instance.
+ * u, f_prev: host arrays of count device pointers (box arrays; f_prev[i]
+ * holds F(U_{n-1}) of instance i on entry unless first, F(U_n) on return;
+ * f_prev[i] must not alias u[i] or rho[i]).  rho: NULL (frozen domains) or
+ * host array of count device pointers.  stats: NULL, or an array of count
+ * etd_stats (synchronises). */
+int etd_batch_multistep_step(etd_batch* batch, double h, double* const* u, double* const* f_prev, int32_t first,
+                             double* const* rho, int32_t reinit, etd_stats* stats);
+
 /* Wait for the stream; first latched device error over the instances (all
  * cleared), or ETD_OK. */
 int etd_batch_sync(etd_batch* batch);

@@ -89,6 +89,8 @@ SIGNATURES = {
     "etd_batch_set_stream": (C.c_int, [C.c_void_p, C.c_void_p]),
     "etd_batch_set_group_limit": (C.c_int, [C.c_void_p, C.c_int32]),
     "etd_batch_geometry_build": (C.c_int, [C.c_void_p, C.POINTER(C.c_void_p)]),
+    "etd_batch_multistep_step": (C.c_int, [C.c_void_p, C.c_double, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
+                                           C.c_int32, C.POINTER(C.c_void_p), C.c_int32, C.POINTER(EtdStats)]),
     "etd_batch_step": (C.c_int, [C.c_void_p, C.c_int32, C.c_double, C.POINTER(C.c_void_p),
                                  C.POINTER(C.c_void_p), C.c_int32, C.POINTER(EtdStats)]),
     "etd_batch_sync": (C.c_int, [C.c_void_p]),

@@ -253,6 +253,19 @@ class Batch:
         L.check(self.lib.etd_batch_step(self.handle, code, float(h), ua, ra, int(bool(reinit)), st), "etd_batch_step")
         return [x.as_dict() for x in st] if stats else None
 
+    def multistep_step(self, h: float, us, fs, first: bool, rhos=None, reinit=False, stats=False):
+        """One ETD2 multistep step of every instance (etd_batch_multistep_step):
+        us in place; fs[i] holds F(U_{n-1}) on entry (ignored when first) and
+        F(U_n) on return."""
+        ua = self._ptrs(us, "u")
+        fa = self._ptrs(fs, "f_prev")
+        ra = self._ptrs(rhos, "rho") if rhos is not None else None
+        self._sync_stream()
+        st = (L.EtdStats * self.count)() if stats else None
+        L.check(self.lib.etd_batch_multistep_step(self.handle, float(h), ua, fa, int(bool(first)), ra,
+                                                  int(bool(reinit)), st), "etd_batch_multistep_step")
+        return [x.as_dict() for x in st] if stats else None
+
     def graph_steps(self, scheme: str, h: float, us, nsteps: int = 1):
         """nsteps frozen-domain steps, each one replay of a recorded HIP graph."""
         code = SCHEMES[scheme]

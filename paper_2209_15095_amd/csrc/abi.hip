@@ -85,8 +85,9 @@ struct etd_batch {
   KrylovDev* h_params = nullptr;
   LevelsetBatch lsb{};        // level-set table of all instances
   GeomBatch gb{};             // geometry table of all instances
-  const double** h_uptr = nullptr;   // user box arrays of the current step (pinned)
-  const double** d_uptr = nullptr;
+  const double** h_uptr = nullptr;   // user box arrays of the current step (pinned), 2 count:
+  const double** d_uptr = nullptr;   // u, then F(U_{n-1}) of a multistep step
+  int ms_first = 0;                  // KrylovDev::first of the multistep step being scheduled
   hipEvent_t uptr_done = nullptr;    // the last upload of h_uptr has been read
   bool uptr_pending = false;
   long geom_gen = 0;                 // geometry builds so far
@@ -780,6 +781,7 @@ int batch_schedule(const etd_batch* B, int ch, int mode, double h, KrylovDev* pa
   for (int i = 0; i < n; ++i) {
     KrylovDev P = krylov_params(B->inst[i0 + i], mode);
     P.h = h;
+    P.first = B->ms_first;
     P.g_first = blocks;
     P.g_size = g[i];
     params[i] = P;
@@ -903,8 +905,8 @@ int etd_batch_create(int32_t count, const etd_grid* grids, const etd_physics* ph
   ok &= hipHostMalloc(&B->h_blk, sizeof(int) * (size_t)B->capacity * B->nchunks) == hipSuccess;
   ok &= hipEventCreate(&B->staged) == hipSuccess;
   ok &= levelset_batch_alloc(B->lsb, count, B->dim) == hipSuccess;
-  ok &= hipHostMalloc(&B->h_uptr, sizeof(double*) * count) == hipSuccess;
-  ok &= hipMalloc(&B->d_uptr, sizeof(double*) * count) == hipSuccess;
+  ok &= hipHostMalloc(&B->h_uptr, sizeof(double*) * 2 * count) == hipSuccess;
+  ok &= hipMalloc(&B->d_uptr, sizeof(double*) * 2 * count) == hipSuccess;
   ok &= hipEventCreateWithFlags(&B->uptr_done, hipEventDisableTiming) == hipSuccess;
   ok &= geom_batch_alloc(B->gb, count, NCOUNTERS) == hipSuccess;
   ok &= hipMalloc(&B->d_gparams, sizeof(KrylovDev) * count) == hipSuccess;
@@ -964,6 +966,44 @@ int etd_batch_geometry_build(etd_batch* B, const double* const* rho) {
   return first;
 }
 
+// Upload the box pointers of this step (u, and f when not NULL) from pinned
+// memory once the previous upload has been read.
+static int upload_ptrs(etd_batch* B, double* const* u, double* const* f) {
+  if (B->uptr_pending) {
+    HIP_TRY(hipEventSynchronize(B->uptr_done));
+    B->uptr_pending = false;
+  }
+  const int n = B->count;
+  for (int i = 0; i < n; ++i) B->h_uptr[i] = u[i];
+  if (f)
+    for (int i = 0; i < n; ++i) B->h_uptr[n + i] = f[i];
+  HIP_TRY(hipMemcpyAsync(B->d_uptr, B->h_uptr, sizeof(double*) * (f ? 2 * n : n), hipMemcpyHostToDevice,
+                         B->stream));
+  HIP_TRY(hipEventRecord(B->uptr_done, B->stream));
+  B->uptr_pending = true;
+  return ETD_OK;
+}
+
+// Level-set Steps 1-2a of every instance in shared launches (one
+// synchronisation), then the geometry of the moved boundaries.
+static int batch_levelset(etd_batch* B, double h, double* const* u, double* const* rho, int32_t reinit) {
+  for (int i = 0; i < B->count; ++i) B->lsb.h_inst[i] = levelset_inst(B->inst[i], rho[i], u[i]);
+  HIP_TRY(timer_begin(B->profiling, B->stream, B->t_levelset));
+  HIP_TRY(levelset_begin(B->lsb, h, reinit, B->stream));
+  HIP_TRY(hipStreamSynchronize(B->stream));
+  HIP_TRY(levelset_end(B->lsb, B->stream));
+  HIP_TRY(timer_end(B->profiling, B->stream, B->t_levelset));
+  return etd_batch_geometry_build(B, rho);
+}
+
+static int batch_stats(etd_batch* B, etd_stats* stats) {
+  for (int i = 0; i < B->count; ++i) {
+    int r = fill_stats(B->inst[i], &stats[i]);
+    if (r) return r;
+  }
+  return etd_batch_sync(B);
+}
+
 int etd_batch_step(etd_batch* B, int32_t scheme, double h, double* const* u, double* const* rho,
                    int32_t reinit, etd_stats* stats) {
   if (!B || !u || !(h >= 0.0) || !isfinite(h)) return ETD_ERR_INVALID;
@@ -972,47 +1012,57 @@ int etd_batch_step(etd_batch* B, int32_t scheme, double h, double* const* u, dou
     if (!u[i]) return ETD_ERR_INVALID;
     if (rho && !rho[i]) return ETD_ERR_INVALID;
   }
+  int r;
   if (rho) {
     bool all = true;
     for (etd_ctx* c : B->inst) all &= c->have_geometry;
-    if (!all) {
-      const int r = etd_batch_geometry_build(B, rho);
-      if (r) return r;
-    }
-    // level-set sweeps of every instance in shared launches, one synchronisation
-    for (int i = 0; i < B->count; ++i) B->lsb.h_inst[i] = levelset_inst(B->inst[i], rho[i], u[i]);
-    HIP_TRY(timer_begin(B->profiling, B->stream, B->t_levelset));
-    HIP_TRY(levelset_begin(B->lsb, h, reinit, B->stream));
-    HIP_TRY(hipStreamSynchronize(B->stream));
-    HIP_TRY(levelset_end(B->lsb, B->stream));
-    HIP_TRY(timer_end(B->profiling, B->stream, B->t_levelset));
-    const int r = etd_batch_geometry_build(B, rho);
-    if (r) return r;
+    if (!all && (r = etd_batch_geometry_build(B, rho))) return r;
+    if ((r = batch_levelset(B, h, u, rho, reinit))) return r;
   }
   for (etd_ctx* c : B->inst)
     if (!c->have_geometry) return ETD_ERR_NO_GEOMETRY;
-  // the box pointers of this step, uploaded from pinned memory once the
-  // previous upload has been read
-  if (B->uptr_pending) {
-    HIP_TRY(hipEventSynchronize(B->uptr_done));
-    B->uptr_pending = false;
-  }
-  for (int i = 0; i < B->count; ++i) B->h_uptr[i] = u[i];
-  HIP_TRY(hipMemcpyAsync(B->d_uptr, B->h_uptr, sizeof(double*) * B->count, hipMemcpyHostToDevice, B->stream));
-  HIP_TRY(hipEventRecord(B->uptr_done, B->stream));
-  B->uptr_pending = true;
+  if ((r = upload_ptrs(B, u, nullptr))) return r;
   HIP_TRY(launch_gather_batch(B->gb, B->d_uptr, V_X0, B->stream));
-  int r = batch_run_krylov(B, job_of(scheme), h);
+  if ((r = batch_run_krylov(B, job_of(scheme), h))) return r;
+  HIP_TRY(launch_scatter_batch(B->gb, (double* const*)B->d_uptr, V_U, B->stream));
+  return stats ? batch_stats(B, stats) : ETD_OK;
+}
+
+int etd_batch_multistep_step(etd_batch* B, double h, double* const* u, double* const* f_prev, int32_t first,
+                             double* const* rho, int32_t reinit, etd_stats* stats) {
+  if (!B || !u || !f_prev || !(h >= 0.0) || !isfinite(h)) return ETD_ERR_INVALID;
+  for (int i = 0; i < B->count; ++i) {
+    if (!u[i] || !f_prev[i] || f_prev[i] == u[i]) return ETD_ERR_INVALID;
+    if (rho && (!rho[i] || f_prev[i] == rho[i])) return ETD_ERR_INVALID;
+  }
+  int r;
+  if (rho) {
+    bool all = true;
+    for (etd_ctx* c : B->inst) all &= c->have_geometry;
+    if (!all && (r = etd_batch_geometry_build(B, rho))) return r;
+    if (!first) {
+      // F_{n-1} of every instance extended from the computational points of
+      // its current rho, in shared launches
+      for (int i = 0; i < B->count; ++i) B->lsb.h_inst[i] = levelset_inst(B->inst[i], rho[i], f_prev[i]);
+      HIP_TRY(timer_begin(B->profiling, B->stream, B->t_levelset));
+      HIP_TRY(levelset_extend(B->lsb, B->stream));
+      HIP_TRY(timer_end(B->profiling, B->stream, B->t_levelset));
+      HIP_TRY(hipStreamSynchronize(B->stream));   // h_inst is refilled next
+    }
+    if ((r = batch_levelset(B, h, u, rho, reinit))) return r;
+  }
+  for (etd_ctx* c : B->inst)
+    if (!c->have_geometry) return ETD_ERR_NO_GEOMETRY;
+  if ((r = upload_ptrs(B, u, f_prev))) return r;
+  HIP_TRY(launch_gather_batch(B->gb, B->d_uptr, V_X0, B->stream));
+  if (!first) HIP_TRY(launch_gather_batch(B->gb, B->d_uptr + B->count, V_G, B->stream));
+  B->ms_first = first ? 1 : 0;
+  r = batch_run_krylov(B, JOB_ETD2, h);
+  B->ms_first = 0;
   if (r) return r;
   HIP_TRY(launch_scatter_batch(B->gb, (double* const*)B->d_uptr, V_U, B->stream));
-  if (stats) {
-    for (int i = 0; i < B->count; ++i) {
-      r = fill_stats(B->inst[i], &stats[i]);
-      if (r) return r;
-    }
-    return etd_batch_sync(B);
-  }
-  return ETD_OK;
+  HIP_TRY(launch_scatter_batch(B->gb, (double* const*)B->d_uptr + B->count, V_G, B->stream));
+  return stats ? batch_stats(B, stats) : ETD_OK;
 }
 
 int etd_batch_graph_steps(etd_batch* B, int32_t scheme, double h, double* const* u, int32_t nsteps) {

@@ -76,6 +76,7 @@ def test_host_argument_checks(lib):
     assert lib.etd_operator_apply(None, None, None) == L.ETD_ERR_INVALID
     assert lib.etd_adjoint_step(None, 2, 0.1, None, None, None, None) == L.ETD_ERR_INVALID
     assert lib.etd_multistep_step(None, 0.1, None, None, 1, None, 0, None) == L.ETD_ERR_INVALID
+    assert lib.etd_batch_multistep_step(None, 0.1, None, None, 1, None, 0, None) == L.ETD_ERR_INVALID
 
 
 def test_batch_host_argument_checks(lib):

@@ -173,3 +173,41 @@ def test_autotune_leaves_state_and_chooses_a_limit():
         assert np.array_equal(x.cpu().numpy(), y.cpu().numpy())
     c.close()
     d.close()
+
+
+def test_batch_multistep_growing_domains_match_oracle():
+    """etd_batch_multistep_step on two batch64 instances (n = 97 and 102,
+    their own beta) with mu = 2, h = 0.05: an ETD2RK start and two ETD2
+    multistep steps on growing domains, u, F(U_n) and rho against the
+    oracle's multistep_step instance by instance."""
+    from oracle.freeboundary import multistep_step
+    from paper_2209_15095_amd.api import Batch
+    ws = inputs.batch64()
+    ws = [ws[49], ws[22]]
+    mu, h, steps = 2.0, 0.05, 3
+    say(f"batch multistep: instances n={[w.grid.n[0] for w in ws]}")
+    b = Batch([w.grid for w in ws], [dict(beta=w.beta, mu=mu) for w in ws])
+    rhos = [dev(w.rho0) for w in ws]
+    us = [dev(w.u0) for w in ws]
+    fs = [dev(np.full_like(w.u0, np.nan)) for w in ws]
+    b.geometry_build(rhos)
+    for m in range(steps):
+        b.multistep_step(h, us, fs, first=(m == 0), rhos=rhos)
+    torch.cuda.synchronize()
+    for k, w in enumerate(ws):
+        og = ogrid(w.grid)
+        rho, u, fp, ns = w.rho0.copy(), w.u0.copy(), np.zeros_like(w.u0), []
+        for m in range(steps):
+            rho, u, fp, op = multistep_step(og, rho, u, fp, h, w.beta, mu, first=(m == 0))
+            ns.append(op.n)
+        rg, ug, fg = rhos[k].cpu().numpy(), us[k].cpu().numpy(), fs[k].cpu().numpy()
+        _, comp_g, _ = classify(og, rg)
+        say(f"  instance {k}: unknowns {ns}  rho diff {np.abs(rg - rho).max():.3e}  "
+            f"u rel {rel_l2(ug[op.comp], u[op.comp]):.3e}  f rel {rel_l2(fg[op.comp], fp[op.comp]):.3e}")
+        assert ns[1] > ns[0]
+        assert np.array_equal(comp_g, op.comp)
+        assert np.abs(rg - rho).max() <= 1e-10
+        assert rel_l2(ug[op.comp], u[op.comp]) <= 1e-9
+        assert rel_l2(fg[op.comp], fp[op.comp]) <= 1e-9
+        assert np.all(fg[~op.comp] == 0.0)
+    b.close()
