@@ -61,25 +61,30 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(w, steps: int):
+def cpu_baseline(w, steps: int, scheme: str):
     """Time the oracle on `steps` steps of the same workload (host cores)."""
     import numpy as np
 
-    from oracle.freeboundary import free_boundary_step
+    from oracle.freeboundary import free_boundary_step, multistep_step
     from oracle.geometry import Grid
 
     g = Grid(w.grid.dim, tuple(w.grid.n), tuple(w.grid.lo), tuple(w.grid.hi))
-    rho, u = w.rho0.copy(), w.u0.copy()
+    rho, u, fp = w.rho0.copy(), w.u0.copy(), np.zeros_like(w.u0)
     t0 = time.perf_counter()
     for m in range(steps):
         reinit = (m + 1) % w.reinit_every == 0
-        rho, u, _ = free_boundary_step(g, rho, u, w.h, w.beta, w.mu, w.a, w.b, scheme=w.scheme,
-                                       reinit=reinit, frozen=w.frozen, method="krylov")
+        if scheme == "etd2":
+            rho, u, fp, _ = multistep_step(g, rho, u, fp, w.h, w.beta, w.mu, w.a, w.b, first=(m == 0),
+                                           reinit=reinit, frozen=w.frozen, method="krylov")
+        else:
+            rho, u, _ = free_boundary_step(g, rho, u, w.h, w.beta, w.mu, w.a, w.b, scheme=scheme,
+                                           reinit=reinit, frozen=w.frozen, method="krylov")
     dt = time.perf_counter() - t0
     npts = int(np.prod(w.grid.n[: w.grid.dim]))
     return {"value": npts * steps / dt, "unit": "grid-point steps/s", "cores": 1,
             "host_cpus": os.cpu_count(), "kind": "oracle",
-            "sample": f"first {steps} of {w.steps} steps of {w.name} (free-boundary ETD2RK), "
+            "sample": f"first {steps} of {w.steps} steps of {w.name} ({'frozen' if w.frozen else 'free-boundary'} "
+                      f"{scheme.upper()}), "
                       f"single-threaded NumPy/SciPy, Krylov route for the phi-combinations",
             "seconds": dt}
 
@@ -316,6 +321,8 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="star512")
+    ap.add_argument("--scheme", default=None, choices=["etd1", "etd2", "etd2rk", "etd3rk", "etd4rk"],
+                    help="time-stepping scheme (default: the workload's); etd2 is ETD2 multistep")
     ap.add_argument("--cpu-steps", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0,
@@ -354,11 +361,17 @@ def main():
     u0 = torch.from_numpy(w.u0).cuda()
     rho = rho0.clone()
     u = u0.clone()
+    scheme = args.scheme or w.scheme
+    f_prev = torch.zeros_like(u) if scheme == "etd2" else None
 
     def run(nsteps):
         for m in range(nsteps):
             reinit = (m + 1) % w.reinit_every == 0
-            ctx.etd_step(w.scheme, w.h, u, rho=None if w.frozen else rho, reinit=reinit)
+            r = None if w.frozen else rho
+            if scheme == "etd2":
+                ctx.multistep_step(w.h, u, f_prev, first=(m == 0), rho=r, reinit=reinit)
+            else:
+                ctx.etd_step(scheme, w.h, u, rho=r, reinit=reinit)
 
     ctx.geometry_build(rho)
     run(args.warmup)
@@ -386,12 +399,12 @@ def main():
     per_launch_ms = prof["krylov_ms"] / max(prof["krylov_launches"], 1)
     roofline = {
         "bound": "hbm",
-        "kernel": f"krylov_kernel<{w.grid.dim}> (persistent Lanczos phi-combination / ETD2RK step)",
+        "kernel": f"krylov_kernel<{w.grid.dim}> (persistent Lanczos phi-combination / {scheme.upper()} step)",
         "achieved": achieved,
         "peak": PEAK_HBM_GBS,
         "unit": "GB/s",
         "frac": achieved / PEAK_HBM_GBS,
-        "traffic": MEASURED_TRAFFIC.get((w.name, kernel_source_hash())),
+        "traffic": MEASURED_TRAFFIC.get((w.name, kernel_source_hash())) if scheme == w.scheme else None,
         "traffic_unit": "bytes per launch",
         "alg_bytes_per_launch": prof["alg_bytes"] / max(prof["krylov_launches"], 1),
         "avg_launch_ms": per_launch_ms,
@@ -413,7 +426,7 @@ def main():
             "workload": w.name,
             "grid": list(w.grid.n[: w.grid.dim]),
             "box": [list(w.grid.lo[: w.grid.dim]), list(w.grid.hi[: w.grid.dim])],
-            "scheme": w.scheme,
+            "scheme": scheme,
             "h": w.h,
             "beta": w.beta,
             "mu": w.mu,
@@ -441,7 +454,7 @@ def main():
     }
     if not args.no_cpu_baseline:
         log(f"[bench] cpu baseline: oracle on {args.cpu_steps} steps")
-        out["cpu_baseline"] = cpu_baseline(w, args.cpu_steps)
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_steps, scheme)
     else:
         out["cpu_baseline"] = None
     ctx.close()
