@@ -58,8 +58,9 @@ def multistep_step(grid: Grid, rho, u_box, f_prev_box, h, beta=1.0, mu=1.0, a=1.
 
     f_prev_box holds F(U_{n-1}) on the computational points of the current
     domain (not read when first).  On a moving domain it is carried to the
-    new computational points by the same quadratic normal extrapolation from
-    the old computational points that carries u (Step 2).  The first step is
+    new computational points by the quadratic normal extrapolation from the
+    old computational points that carries u (Step 2), with ASLAM_F_ITERS
+    sweeps per stage (it is needed only where the boundary moved).  The first step is
     one ETD2RK step.  Returns (rho_new, u_new_box, f_new_box, op), f_new_box
     = F(U_n) on the new computational points and 0 elsewhere."""
     if frozen:
@@ -68,7 +69,7 @@ def multistep_step(grid: Grid, rho, u_box, f_prev_box, h, beta=1.0, mu=1.0, a=1.
         f_ext = None
         if not first:
             _, comp_old, _ = classify(grid, rho)
-            f_ext = ls.aslam_extrapolate(f_prev_box, comp_old, rho, grid.dx)
+            f_ext = ls.aslam_extrapolate(f_prev_box, comp_old, rho, grid.dx, iters=ls.ASLAM_F_ITERS)
         rho_new, u_new, _ = levelset_advance(grid, rho, u_box, h, mu, reinit)
     op = build_operator(grid, rho_new, beta)
     f, _ = logistic(a, b)

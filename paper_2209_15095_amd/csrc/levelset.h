@@ -28,6 +28,9 @@ namespace etdfb {
 // Iteration counts and pseudo-time steps of the sweeps (readings of the
 // paper's unspecified parameters; identical in the CPU oracle).
 constexpr int ASLAM_ITERS = 15;
+// Sweeps per stage of levelset_extend (F(U_{n-1}) of ETD2 multistep, needed
+// only where the boundary moved in one step; three stages reach 15 nodes).
+constexpr int ASLAM_F_ITERS = 5;
 constexpr int VEL_ITERS = 20;
 constexpr int REINIT_ITERS = 10;
 // Tile lists of a sweep (radii in nodes, see above).

@@ -501,13 +501,17 @@ hipError_t begin_dim(LevelsetBatch& b, hipStream_t st, bool speed) {
     }
     return v;
   };
+  static_assert((ASLAM_F_ITERS + SWEEP_GROUP - 1) / SWEEP_GROUP % 2 == 1 && ASLAM_F_ITERS % 2 == 1 &&
+                    ASLAM_F_ITERS <= ASLAM_ITERS,
+                "the extend-only Aslam stages must end in the partner array, within the lists");
   static_assert((ASLAM_ITERS + SWEEP_GROUP - 1) / SWEEP_GROUP % 2 == 1 && ASLAM_ITERS % 2 == 1,
                 "the Aslam stages must end in the partner array");
   static_assert((VEL_ITERS + SWEEP_GROUP - 1) / SWEEP_GROUP % 2 == 0 && VEL_ITERS % 2 == 0,
                 "the speed extension must end in V");
-  const int unn = stage(LS_A1, A_E2, A_E3, -1, 2, 0, ASLAM_ITERS, 0);
-  const int un = stage(LS_A2, A_E1, A_E2, A_E3, 1, 0, ASLAM_ITERS, 0);
-  const int uext = stage(LS_A3, A_E0, A_E1, A_E2, 0, 0, ASLAM_ITERS, 0);
+  const int iters = speed ? ASLAM_ITERS : ASLAM_F_ITERS;
+  const int unn = stage(LS_A1, A_E2, A_E3, -1, 2, 0, iters, 0);
+  const int un = stage(LS_A2, A_E1, A_E2, A_E3, 1, 0, iters, 0);
+  const int uext = stage(LS_A3, A_E0, A_E1, A_E2, 0, 0, iters, 0);
   if (unn != A_E3 || un != A_E2 || uext != A_E1) return hipErrorUnknown;
   b.uext = uext;
   if (!speed) return hipSuccess;
