@@ -189,10 +189,13 @@ int etd_step(etd_ctx* ctx, int32_t scheme, double h, double* u, double* rho, int
  * elsewhere.  first != 0: f_prev is not read and the step is one ETD2RK step
  * (Section 3.2), which starts the two-step recursion.  rho == NULL: frozen
  * domain.  rho != NULL: free boundary as in etd_step; F_{n-1} is carried to
- * the points that join the domain by the same quadratic normal
- * extrapolation from the old computational points that carries u (Section
- * 4.3, Step 2), then levelset_advance(ctx, rho, u, h, reinit) runs.  u:
- * device box array, updated in place; f_prev must not alias u or rho. */
+ * the points that join the domain by the quadratic normal extrapolation
+ * from the old computational points that carries u (Section 4.3, Step 2;
+ * 5 sweeps per stage, as it is needed only where the boundary moved), then
+ * levelset_advance(ctx, rho, u, h, reinit) runs.  u: device box array,
+ * updated in place.  ETD_ERR_INVALID (nothing done) for a NULL ctx, u or
+ * f_prev, f_prev aliasing u or rho, or h negative or not finite;
+ * ETD_ERR_NO_GEOMETRY for a frozen step before any geometry build. */
 int etd_multistep_step(etd_ctx* ctx, double h, double* u, double* f_prev, int32_t first, double* rho,
                        int32_t reinit, etd_stats* stats);
 
