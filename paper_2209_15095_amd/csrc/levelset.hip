@@ -508,10 +508,14 @@ hipError_t begin_dim(LevelsetBatch& b, hipStream_t st, bool speed) {
                 "the Aslam stages must end in the partner array");
   static_assert((VEL_ITERS + SWEEP_GROUP - 1) / SWEEP_GROUP % 2 == 0 && VEL_ITERS % 2 == 0,
                 "the speed extension must end in V");
+  // extend-only: three stages of ASLAM_F_ITERS sweeps reach 3 ASLAM_F_ITERS
+  // nodes, all inside list A1, so every stage sweeps A1 alone
+  static_assert(3 * ASLAM_F_ITERS <= ASLAM_ITERS, "the extend-only stages must stay inside list A1");
   const int iters = speed ? ASLAM_ITERS : ASLAM_F_ITERS;
+  const int l2 = speed ? LS_A2 : LS_A1, l3 = speed ? LS_A3 : LS_A1;
   const int unn = stage(LS_A1, A_E2, A_E3, -1, 2, 0, iters, 0);
-  const int un = stage(LS_A2, A_E1, A_E2, A_E3, 1, 0, iters, 0);
-  const int uext = stage(LS_A3, A_E0, A_E1, A_E2, 0, 0, iters, 0);
+  const int un = stage(l2, A_E1, A_E2, A_E3, 1, 0, iters, 0);
+  const int uext = stage(l3, A_E0, A_E1, A_E2, 0, 0, iters, 0);
   if (unn != A_E3 || un != A_E2 || uext != A_E1) return hipErrorUnknown;
   b.uext = uext;
   if (!speed) return hipSuccess;
