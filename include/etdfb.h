@@ -47,7 +47,8 @@ enum {
   ETD_ERR_NONFINITE = -5,    /* NaN/Inf met in a reduction */
   ETD_ERR_DOMAIN = -6,       /* computational point within 2 layers of the box edge */
   ETD_ERR_BARRIER = -7,      /* grid barrier timed out (kernel drained and exited) */
-  ETD_ERR_NO_GEOMETRY = -8   /* no geometry built on this context yet */
+  ETD_ERR_NO_GEOMETRY = -8,  /* no geometry built on this context yet */
+  ETD_ERR_FRONT = -9         /* the boundary would move more than one node in a step */
 };
 
 /* ETD1 (Section 3.1), ETD2RK, ETD3RK and ETD4RK (Section 3.2; the phi_3 of
@@ -168,7 +169,9 @@ int phi_combination_apply(etd_ctx* ctx, double t, int32_t p, const double* const
  * advection of rho over dt, reinitialisation if reinit != 0, then u is
  * restricted to the computational points of the new rho.  rho and u are
  * device box arrays updated in place.  Rebuilds the geometry for the new
- * rho. */
+ * rho.  The extrapolation serves fronts that move at most one node per
+ * step: when the maximum extended speed V gives V * dt > h, nothing is
+ * changed and ETD_ERR_FRONT is returned (take smaller steps). */
 int levelset_advance(etd_ctx* ctx, double* rho, double* u, double dt, int32_t reinit);
 
 /* One time step of size h of u_t = A u + f(u) (Section 3: ETD1, ETD2RK,
@@ -190,9 +193,9 @@ int etd_step(etd_ctx* ctx, int32_t scheme, double h, double* u, double* rho, int
  * (Section 3.2), which starts the two-step recursion.  rho == NULL: frozen
  * domain.  rho != NULL: free boundary as in etd_step; F_{n-1} is carried to
  * the points that join the domain by the quadratic normal extrapolation
- * from the old computational points that carries u (Section 4.3, Step 2;
- * 5 sweeps per stage, as it is needed only where the boundary moved), then
- * levelset_advance(ctx, rho, u, h, reinit) runs.  u: device box array,
+ * from the old computational points that carries u (Section 4.3, Step 2,
+ * the same sweeps), then levelset_advance(ctx, rho, u, h, reinit) runs
+ * (ETD_ERR_FRONT as there; f_prev then holds the extension).  u: device box array,
  * updated in place.  ETD_ERR_INVALID (nothing done) for a NULL ctx, u or
  * f_prev, f_prev aliasing u or rho, or h negative or not finite;
  * ETD_ERR_NO_GEOMETRY for a frozen step before any geometry build. */

@@ -9,8 +9,13 @@ step, reinitialised when asked, u is extended from the old computational
 points and restricted to the new ones, and the ETD step runs with the
 operator of the new domain.  A frozen domain (mu = 0) skips Step 1.
 
+A step whose maximum Stefan speed would move the boundary more than
+MAX_FRONT_NODES nodes raises FrontTooFast before rho or u change.
+
 Parity: "parity unpinned" as a coupled trajectory beyond the invariants of
-its parts (see oracle.levelset and oracle.etd).
+its parts (see oracle.levelset and oracle.etd); the extension of
+F(U_{n-1}) to the points that join the domain is pinned by the
+truncation-order bound of tests/test_oracle_levelset.py.
 """
 from __future__ import annotations
 
@@ -28,6 +33,7 @@ def levelset_advance(grid: Grid, rho, u_box, dt, mu, reinit: bool):
     _, comp_old, _ = classify(grid, rho)
     u_ext = ls.aslam_extrapolate(u_box, comp_old, rho, h)
     V = ls.stefan_velocity(u_ext, rho, h, mu)
+    ls.check_front_reach(V, dt, h)
     nsub = ls.advect_substeps(V, dt, h)
     rho_new = ls.advect(rho, V, dt, h)
     if reinit:
@@ -59,8 +65,8 @@ def multistep_step(grid: Grid, rho, u_box, f_prev_box, h, beta=1.0, mu=1.0, a=1.
     f_prev_box holds F(U_{n-1}) on the computational points of the current
     domain (not read when first).  On a moving domain it is carried to the
     new computational points by the quadratic normal extrapolation from the
-    old computational points that carries u (Step 2), with ASLAM_F_ITERS
-    sweeps per stage (it is needed only where the boundary moved).  The first step is
+    old computational points that carries u (Step 2), with the same sweeps.
+    The first step is
     one ETD2RK step.  Returns (rho_new, u_new_box, f_new_box, op), f_new_box
     = F(U_n) on the new computational points and 0 elsewhere."""
     if frozen:
@@ -69,7 +75,7 @@ def multistep_step(grid: Grid, rho, u_box, f_prev_box, h, beta=1.0, mu=1.0, a=1.
         f_ext = None
         if not first:
             _, comp_old, _ = classify(grid, rho)
-            f_ext = ls.aslam_extrapolate(f_prev_box, comp_old, rho, grid.dx, iters=ls.ASLAM_F_ITERS)
+            f_ext = ls.aslam_extrapolate(f_prev_box, comp_old, rho, grid.dx)
         rho_new, u_new, _ = levelset_advance(grid, rho, u_box, h, mu, reinit)
     op = build_operator(grid, rho_new, beta)
     f, _ = logistic(a, b)

@@ -18,6 +18,7 @@ ETD_ERR_NONFINITE = -5
 ETD_ERR_DOMAIN = -6
 ETD_ERR_BARRIER = -7
 ETD_ERR_NO_GEOMETRY = -8
+ETD_ERR_FRONT = -9
 
 ETD_SCHEME_ETD1 = 1
 ETD_SCHEME_ETD2RK = 2

@@ -37,6 +37,7 @@ class Context:
         ph = L.EtdPhysics(float(beta), float(a), float(b), float(mu))
         op = L.EtdKrylovOpts(float(tol), int(m_min), int(m_max), int(m_step), int(max_substeps))
         self.dim = dim
+        self.beta = float(beta)
         self.shape = tuple(reversed([int(x) for x in n[:dim]]))
         self.handle = C.c_void_p()
         s = stream if stream is not None else torch.cuda.current_stream()
@@ -73,6 +74,7 @@ class Context:
 
     def set_beta(self, beta: float):
         L.check(self.lib.etd_ctx_set_beta(self.handle, float(beta)), "etd_ctx_set_beta")
+        self.beta = float(beta)
 
     def geometry_build(self, rho: torch.Tensor):
         self._check_box(rho, "rho")
@@ -317,7 +319,8 @@ class ETDSolve(torch.autograd.Function):
 
     @staticmethod
     def forward(fctx, u0, beta, context, h, steps, checkpoint_every=8):
-        context.set_beta(float(beta.detach().reshape(-1)[0].item()))
+        beta_value = float(beta.detach().reshape(-1)[0].item())
+        context.set_beta(beta_value)
         u = u0.detach().clone()
         ckpt = {0: u.clone()}
         for n in range(steps):
@@ -327,6 +330,7 @@ class ETDSolve(torch.autograd.Function):
         fctx.context, fctx.h, fctx.steps, fctx.every = context, h, steps, checkpoint_every
         fctx.ckpt = ckpt
         fctx.beta_shape = beta.shape
+        fctx.beta_value = beta_value
         return u
 
     @staticmethod
@@ -335,14 +339,21 @@ class ETDSolve(torch.autograd.Function):
         g = grad_out.detach().contiguous().clone()
         dbeta = torch.zeros(1, dtype=torch.float64, device=g.device)
         starts = sorted(fctx.ckpt)
-        for s0 in reversed(starts):
-            e = min(s0 + every, steps)
-            states = [fctx.ckpt[s0].clone()]
-            for n in range(s0, e - 1):
-                u = states[-1].clone()
-                context.etd_step("etd2rk", h, u)
-                states.append(u)
-            for n in range(e - 1, s0 - 1, -1):
-                context.adjoint_step(h, states[n - s0], g, dbeta, gbar_n=g)
+        # the recomputation and the adjoint run at the forward's beta, whatever
+        # the context was set to in between; the caller's value is restored
+        beta_before = context.beta
+        context.set_beta(fctx.beta_value)
+        try:
+            for s0 in reversed(starts):
+                e = min(s0 + every, steps)
+                states = [fctx.ckpt[s0].clone()]
+                for n in range(s0, e - 1):
+                    u = states[-1].clone()
+                    context.etd_step("etd2rk", h, u)
+                    states.append(u)
+                for n in range(e - 1, s0 - 1, -1):
+                    context.adjoint_step(h, states[n - s0], g, dbeta, gbar_n=g)
+        finally:
+            context.set_beta(beta_before)
         return g, dbeta.reshape(fctx.beta_shape), None, None, None, None
 

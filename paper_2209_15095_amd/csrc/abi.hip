@@ -362,6 +362,15 @@ LsInst levelset_inst(const etd_ctx* c, double* rho, double* u) {
   return I;
 }
 
+// After levelset_begin and a synchronisation: some instance's maximum
+// extended speed would move its front more than LS_MAX_FRONT_NODES nodes
+// over dt (the extrapolation's reach; nothing has been changed yet).
+bool front_too_fast(const LevelsetBatch& b) {
+  for (int i = 0; i < b.count; ++i)
+    if (!(b.h_vmax[i] * b.dt <= LS_MAX_FRONT_NODES * b.h_inst[i].h)) return true;
+  return false;
+}
+
 void free_all(etd_ctx* c) {
   void* ptrs[] = {c->mask, c->tile_flag, c->tile_map, c->slot_tile, c->comp_bits, c->irr_bits, c->cdiag,
                   c->nbr, c->tile_vb, c->band_tmp, c->band_list, c->counters, c->ws, c->part, c->flags, c->bar, c->st};
@@ -392,6 +401,7 @@ const char* etd_status_string(int s) {
     case ETD_ERR_DOMAIN: return "computational point within 2 layers of the box edge";
     case ETD_ERR_BARRIER: return "grid barrier timed out";
     case ETD_ERR_NO_GEOMETRY: return "no geometry built";
+    case ETD_ERR_FRONT: return "boundary would move more than one node in one step";
     default: return "unknown status";
   }
 }
@@ -579,6 +589,7 @@ int levelset_advance(etd_ctx* c, double* rho, double* u, double dt, int32_t rein
   HIP_TRY(timer_begin(c->profiling, c->stream, c->t_levelset));
   HIP_TRY(levelset_begin(c->lsb, dt, reinit, c->stream));
   HIP_TRY(hipStreamSynchronize(c->stream));
+  if (front_too_fast(c->lsb)) return ETD_ERR_FRONT;
   HIP_TRY(levelset_end(c->lsb, c->stream));
   HIP_TRY(timer_end(c->profiling, c->stream, c->t_levelset));
   return etd_geometry_build(c, rho);
@@ -991,6 +1002,7 @@ static int batch_levelset(etd_batch* B, double h, double* const* u, double* cons
   HIP_TRY(timer_begin(B->profiling, B->stream, B->t_levelset));
   HIP_TRY(levelset_begin(B->lsb, h, reinit, B->stream));
   HIP_TRY(hipStreamSynchronize(B->stream));
+  if (front_too_fast(B->lsb)) return ETD_ERR_FRONT;
   HIP_TRY(levelset_end(B->lsb, B->stream));
   HIP_TRY(timer_end(B->profiling, B->stream, B->t_levelset));
   return etd_batch_geometry_build(B, rho);

@@ -28,9 +28,12 @@ namespace etdfb {
 // Iteration counts and pseudo-time steps of the sweeps (readings of the
 // paper's unspecified parameters; identical in the CPU oracle).
 constexpr int ASLAM_ITERS = 15;
-// Sweeps per stage of levelset_extend (F(U_{n-1}) of ETD2 multistep, needed
-// only where the boundary moved in one step; three stages reach 15 nodes).
-constexpr int ASLAM_F_ITERS = 5;
+// Largest front displacement per step (nodes) the extrapolation serves: with
+// ASLAM_ITERS sweeps per stage it has converged to truncation error at every
+// point that joins the domain when the boundary moves at most this far.  A
+// step with max V * dt > LS_MAX_FRONT_NODES * h is refused on the host
+// before rho or u change.
+constexpr int LS_MAX_FRONT_NODES = 1;
 constexpr int VEL_ITERS = 20;
 constexpr int REINIT_ITERS = 10;
 // Tile lists of a sweep (radii in nodes, see above).
@@ -96,10 +99,11 @@ void levelset_batch_free(LevelsetBatch& b);
 // reinitialisation (if reinit) and the restriction of u.
 hipError_t levelset_begin(LevelsetBatch& b, double dt, int reinit, hipStream_t stream);
 hipError_t levelset_end(LevelsetBatch& b, hipStream_t stream);
-// The extrapolation of Step 2 alone: each instance's u (any box field known
-// on the computational points of rho) is replaced, over the whole box, by its
-// quadratic normal extrapolation from those points; rho is not changed.  The
-// caller synchronises the stream before it refills h_inst.
+// The extrapolation of Step 2 alone (the same sweeps as for u): each
+// instance's u (any box field known on the computational points of rho) is
+// replaced, over the whole box, by its quadratic normal extrapolation from
+// those points; rho is not changed.  The caller synchronises the stream
+// before it refills h_inst.
 hipError_t levelset_extend(LevelsetBatch& b, hipStream_t stream);
 
 }  // namespace etdfb

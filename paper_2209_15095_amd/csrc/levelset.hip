@@ -501,18 +501,12 @@ hipError_t begin_dim(LevelsetBatch& b, hipStream_t st, bool speed) {
     }
     return v;
   };
-  static_assert((ASLAM_F_ITERS + SWEEP_GROUP - 1) / SWEEP_GROUP % 2 == 1 && ASLAM_F_ITERS % 2 == 1 &&
-                    ASLAM_F_ITERS <= ASLAM_ITERS,
-                "the extend-only Aslam stages must end in the partner array, within the lists");
   static_assert((ASLAM_ITERS + SWEEP_GROUP - 1) / SWEEP_GROUP % 2 == 1 && ASLAM_ITERS % 2 == 1,
                 "the Aslam stages must end in the partner array");
   static_assert((VEL_ITERS + SWEEP_GROUP - 1) / SWEEP_GROUP % 2 == 0 && VEL_ITERS % 2 == 0,
                 "the speed extension must end in V");
-  // extend-only: three stages of ASLAM_F_ITERS sweeps reach 3 ASLAM_F_ITERS
-  // nodes, all inside list A1, so every stage sweeps A1 alone
-  static_assert(3 * ASLAM_F_ITERS <= ASLAM_ITERS, "the extend-only stages must stay inside list A1");
-  const int iters = speed ? ASLAM_ITERS : ASLAM_F_ITERS;
-  const int l2 = speed ? LS_A2 : LS_A1, l3 = speed ? LS_A3 : LS_A1;
+  const int iters = ASLAM_ITERS;
+  const int l2 = LS_A2, l3 = LS_A3;
   const int unn = stage(LS_A1, A_E2, A_E3, -1, 2, 0, iters, 0);
   const int un = stage(l2, A_E1, A_E2, A_E3, 1, 0, iters, 0);
   const int uext = stage(l3, A_E0, A_E1, A_E2, 0, 0, iters, 0);

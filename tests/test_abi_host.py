@@ -42,7 +42,7 @@ def test_library_exports_every_declared_symbol(lib):
 
 
 def test_status_strings(lib):
-    for code in range(0, -9, -1):
+    for code in range(0, -10, -1):
         s = lib.etd_status_string(code).decode()
         assert s and s != "unknown status"
     assert lib.etd_status_string(-99).decode() == "unknown status"

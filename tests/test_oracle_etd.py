@@ -1,6 +1,11 @@
 """Pins for oracle.etd (Section 3 of the paper).
 
-* C = 0: ETD1 is forward Euler, ETD2RK is Heun's method (closed forms).
+* C = 0: ETD1 is forward Euler, ETD2RK is Heun's method, ETD3RK is Kutta's
+  third-order method and ETD4RK the classical fourth-order Runge-Kutta
+  method (closed forms; F depends on U, so every stage value is tested).
+* Diagonal C: ETD3RK and ETD4RK equal the ETDRK3 / ETDRK4 schemes of Cox and
+  Matthews (J. Comput. Phys. 176, 2002) written in their own form, with the
+  coefficients as explicit functions of hc per eigenvalue c.
 * F = 0: one step is e^{hC} U (eigendecomposition route).
 * F independent of U and polynomial in t: ETD1 exact for constant F, ETD2RK
   exact for linear F, ETD3RK / ETD4RK exact for quadratic F (exact solution
@@ -8,7 +13,10 @@
 * ETD2 multistep (Section 3.1): eq. 3.6 with s = 2 evaluated by quadrature
   of its g_m integrals; C = 0 gives the two-step Adams-Bashforth method; exact for F independent of U and linear in t; order 2 on the
   logistic problem when started with one ETD2RK step.
-* Logistic reaction: step-halving shows order 1 (ETD1) and 2 (ETD2RK).
+* Logistic reaction: step-halving shows order 1 (ETD1) and 2 (ETD2RK) on the
+  embedded-boundary operator, and orders 3 (ETD3RK) and 4 (ETD4RK) on a
+  non-stiff symmetric operator (on the stiff embedded-boundary operator the
+  higher-order schemes show the order reduction known for stiff problems).
 * Section 4.2.1 peanut problem: second-order convergence and errors of the
   size printed in Table 1 (tests/golden/table1_etd2rk.json).
 """
@@ -45,6 +53,53 @@ def test_zero_operator_reduces_to_euler_and_heun():
     assert np.allclose(etd1_step(A, h, U, f), U + h * f(U), rtol=1e-14, atol=1e-15)
     heun = U + 0.5 * h * (f(U) + f(U + h * f(U)))
     assert np.allclose(etd2rk_step(A, h, U, f), heun, rtol=1e-14, atol=1e-15)
+
+
+def test_zero_operator_reduces_to_kutta_rk3_and_classical_rk4():
+    """C = 0 and U-dependent F: ETD3RK is Kutta's third-order method and
+    ETD4RK the classical fourth-order Runge-Kutta method."""
+    n = 9
+    A = np.zeros((n, n))
+    rng = np.random.default_rng(11)
+    U = rng.uniform(0.1, 0.9, n)
+    f, _ = logistic(1.3, 0.7)
+    h = 0.35
+    k1 = f(U)
+    k2 = f(U + 0.5 * h * k1)
+    k3 = f(U + h * (2.0 * k2 - k1))
+    kutta = U + h * (k1 + 4.0 * k2 + k3) / 6.0
+    assert np.allclose(etd3rk_step(A, h, U, f), kutta, rtol=1e-14, atol=1e-15)
+    k3 = f(U + 0.5 * h * k2)
+    k4 = f(U + h * k3)
+    rk4 = U + h * (k1 + 2.0 * k2 + 2.0 * k3 + k4) / 6.0
+    assert np.allclose(etd4rk_step(A, h, U, f), rk4, rtol=1e-14, atol=1e-15)
+
+
+def test_higher_order_match_cox_matthews_on_diagonal_operator():
+    """Diagonal C = diag(c), logistic F: the ETDRK3 and ETDRK4 formulas of
+    Cox and Matthews (2002) per component, coefficients in closed form in
+    z = hc (no phi-function routine involved)."""
+    rng = np.random.default_rng(5)
+    n = 12
+    c = -rng.uniform(0.5, 6.0, n)
+    A = np.diag(c)
+    U = rng.uniform(0.1, 0.9, n)
+    f, _ = logistic(1.0, 1.0)
+    h = 0.4
+    z = h * c
+    E, E2 = np.exp(z), np.exp(0.5 * z)
+    q1 = (-4.0 - z + E * (4.0 - 3.0 * z + z * z)) / (h * h * c ** 3)
+    q2 = (2.0 + z + E * (-2.0 + z)) / (h * h * c ** 3)
+    q3 = (-4.0 - 3.0 * z - z * z + E * (4.0 - z)) / (h * h * c ** 3)
+    a = E2 * U + (E2 - 1.0) * f(U) / c
+    b3 = E * U + (E - 1.0) * (2.0 * f(a) - f(U)) / c
+    cm3 = E * U + q1 * f(U) + 4.0 * q2 * f(a) + q3 * f(b3)
+    b4 = E2 * U + (E2 - 1.0) * f(a) / c
+    c4 = E2 * a + (E2 - 1.0) * (2.0 * f(b4) - f(U)) / c
+    cm4 = E * U + q1 * f(U) + 2.0 * q2 * (f(a) + f(b4)) + q3 * f(c4)
+    for method in ("dense", "eigh"):
+        assert np.abs(etd3rk_step(A, h, U, f, method=method) - cm3).max() < 1e-12 * np.abs(cm3).max()
+        assert np.abs(etd4rk_step(A, h, U, f, method=method) - cm4).max() < 1e-12 * np.abs(cm4).max()
 
 
 def test_zero_reaction_is_exponential():
@@ -107,6 +162,30 @@ def test_logistic_temporal_orders():
         e1 = np.linalg.norm(run(step, 4) - ref)
         e2 = np.linalg.norm(run(step, 8) - ref)
         assert abs(np.log2(e1 / e2) - order) < 0.25
+
+
+def test_higher_order_temporal_orders():
+    """Step halving on U' = C U + u(1 - u), C symmetric negative definite of
+    moderate norm: orders 3 (ETD3RK) and 4 (ETD4RK)."""
+    rng = np.random.default_rng(7)
+    n = 10
+    B = rng.standard_normal((n, n))
+    A = -(B @ B.T) / n * 2.0
+    f, _ = logistic(1.0, 1.0)
+    U0 = rng.uniform(0.2, 0.8, n)
+    T = 1.0
+
+    def run(step, nsteps):
+        U = U0.copy()
+        for _ in range(nsteps):
+            U = step(A, T / nsteps, U, f, method="dense")
+        return U
+
+    for step, order in [(etd2rk_step, 2.0), (etd3rk_step, 3.0), (etd4rk_step, 4.0)]:
+        ref = run(step, 256)
+        e1 = np.linalg.norm(run(step, 8) - ref)
+        e2 = np.linalg.norm(run(step, 16) - ref)
+        assert abs(np.log2(e1 / e2) - order) < 0.3, (step.__name__, np.log2(e1 / e2))
 
 
 def test_etd2_multistep_zero_operator_is_adams_bashforth():
