@@ -50,14 +50,14 @@ import math
 
 import numpy as np
 
-ASLAM_ITERS = 15
+ASLAM_ITERS = 25
 # Largest front displacement per step, in nodes, that the extrapolation
 # serves: with ASLAM_ITERS sweeps per stage the extension has converged to
 # within truncation error at every point that joins the domain when the
 # boundary moves at most this far (tests/test_oracle_levelset.py); a step
 # whose maximum speed would move it farther (max V * dt > MAX_FRONT_NODES h)
 # is refused.
-MAX_FRONT_NODES = 1
+MAX_FRONT_NODES = 2
 VEL_ITERS = 20
 REINIT_ITERS = 10
 WENO_EPS = 1e-6

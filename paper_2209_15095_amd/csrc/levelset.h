@@ -7,7 +7,7 @@
 // tiles holding a node with |rho| < h (Dv); the distance between two tiles
 // is a lower bound of the node distance between them.  A Jacobi sweep
 // changes a node only where a face neighbour or its source is nonzero, so
-// the extrapolated u_nn, u_n, u are exactly 0 beyond 15, 30 and 45 nodes of
+// the extrapolated u_nn, u_n, u are exactly 0 beyond 25, 50 and 75 nodes of
 // the computational points and the extended speed beyond 20 nodes of the
 // |rho| < h nodes: each stage sweeps only the tiles within that distance
 // plus one, and gives the whole-box values everywhere (the arrays are 0
@@ -27,13 +27,13 @@ namespace etdfb {
 
 // Iteration counts and pseudo-time steps of the sweeps (readings of the
 // paper's unspecified parameters; identical in the CPU oracle).
-constexpr int ASLAM_ITERS = 15;
+constexpr int ASLAM_ITERS = 25;
 // Largest front displacement per step (nodes) the extrapolation serves: with
 // ASLAM_ITERS sweeps per stage it has converged to truncation error at every
 // point that joins the domain when the boundary moves at most this far.  A
 // step with max V * dt > LS_MAX_FRONT_NODES * h is refused on the host
 // before rho or u change.
-constexpr int LS_MAX_FRONT_NODES = 1;
+constexpr int LS_MAX_FRONT_NODES = 2;
 constexpr int VEL_ITERS = 20;
 constexpr int REINIT_ITERS = 10;
 // Tile lists of a sweep (radii in nodes, see above).

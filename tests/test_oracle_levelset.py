@@ -133,18 +133,18 @@ def _grown_extension_error(n, grow, shape, iters=ls.ASLAM_ITERS):
 
 
 @pytest.mark.parametrize("shape", ["disk", "flower"])
-@pytest.mark.parametrize("grow", [0.5, float(ls.MAX_FRONT_NODES)])
+@pytest.mark.parametrize("grow", [1.0, float(ls.MAX_FRONT_NODES)])
 def test_extension_converges_at_points_joining_the_domain(shape, grow):
     """Section 4.3, Step 2 (used for u and, by ETD2 multistep, for F(U_{n-1})):
     where the boundary moves by up to MAX_FRONT_NODES cells, the
     ASLAM_ITERS-sweep extension of a smooth field matches the field at every
     point that joins the domain to within truncation error, C dx^2 with C
-    of the size of its second derivatives, at three resolutions (an
+    of the size of its second derivatives, at four resolutions (an
     extension with too few sweeps to converge there misses by 10 to 1000
-    times that)."""
+    times that: 15 sweeps reach 79 dx^2 at two cells, 641^2)."""
     for n in (81, 161, 321, 641):
         err, dx = _grown_extension_error(n, grow, shape)
-        assert err < 6.0 * dx * dx, (n, err / (dx * dx))
+        assert err < 4.0 * dx * dx, (n, err / (dx * dx))
 
 
 def test_front_reach_guard():
