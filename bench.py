@@ -1,30 +1,37 @@
 #!/usr/bin/env python
 """Benchmark of the ETD / embedded-boundary / level-set hot path on one MI355X.
 
-Default workload (star512): 2D free boundary on a 512 x 512 grid over
-[-16,16]^2, initial domain the star r = 3 + 0.5 cos(5 theta) (exact signed
-distance), u0 = 0.5 inside, beta = 1, mu = 2, logistic f = u(1-u), ETD2RK
-with h = 0.005 and adaptive Krylov tolerance 1e-10, level-set advection by
-the extended Stefan speed each step and reinitialisation every 5 steps;
-200 steps make the whole configuration.
+Default workload (ellipsoid192, the largest single-GPU free-boundary
+configuration): 3D free boundary on a 192^3 grid over [-10,10]^3, initial
+domain the prolate spheroid with semi-axes (3,2,2) (exact signed distance),
+u0 ~ U[0.2,0.8] inside (seed 0), beta = 1, mu = 1, logistic f = u(1-u),
+ETD2RK with h = 0.01 and adaptive Krylov tolerance 1e-10, level-set
+advection by the extended Stefan speed each step and reinitialisation every
+5 steps; 50 steps make the whole configuration.
 
 A step is one call of etd_step: level-set sweeps, geometry rebuild and the
-two phi-combinations of ETD2RK.  `value` is box grid points times steps per
-second (n^2 * K / wall seconds, inputs resident in HBM when the clock
-starts).  The roofline object reports the dominant kernel (the persistent
-Krylov kernel) against the 8 TB/s HBM peak, with algorithmic bytes counted
-by the kernel itself and time from HIP events on the stream it runs on.
-The CPU baseline is the oracle (plain NumPy/SciPy, test infrastructure) on a
-bounded sample of the same workload.
+two phi-combinations of ETD2RK.  `value` counts box nodes: n^3 times steps
+per second (inputs resident in HBM when the clock starts);
+`unknown_steps_per_s` counts the computational points (the ODE unknowns)
+instead.  The roofline object reports the stencil-Krylov loop (the
+persistent Krylov kernel) against the 8 TB/s HBM peak, with algorithmic
+bytes counted by the kernel itself and time from HIP events on the stream it
+runs on; `roofline_scale` reports the same kernel, measured in the same
+process, on the two bandwidth-scale frozen domains (disk4097: 4097^2 disk,
+11.6 M unknowns; sphere385: 385^3 ball, 25 M unknowns), where the loop is
+bound by HBM rather than by synchronisation latency.  The CPU baseline is
+the oracle (plain NumPy/SciPy, test infrastructure) on the first step of
+the same workload.
 
-Other workloads (not the headline line): --workload batch64 (64 random
-stars advanced by the batched entry points; value = sum of n^2 over the
-instances times steps per second), --workload sphere96 (one gradient of the
-96^3 frozen-domain loss: 40 forward steps, checkpointed backward with the
-discrete adjoint; value = n^3 times 40 per second of the whole gradient),
-and the bandwidth-scale frozen-domain runs disk4097 and sphere385.
+Other workloads (not the headline line): --workload star512 (512^2 star,
+200 steps), batch64 (64 random stars advanced by the batched entry points;
+value = sum of n^2 over the instances times steps per second), sphere96 (one
+gradient of the 96^3 frozen-domain loss: 40 forward steps, checkpointed
+backward with the discrete adjoint; value = n^3 times 40 per second of the
+whole gradient), batch64_frozen (graph-replayed batched steps), and the
+bandwidth-scale frozen-domain runs disk4097 and sphere385 on their own.
 
-Usage: python bench.py [--gpus 1] [--steps 200] [--warmup 5] [--workload star512]
+Usage: python bench.py [--gpus 1] [--steps 50] [--warmup 5] [--workload ellipsoid192]
 """
 from __future__ import annotations
 
@@ -62,13 +69,20 @@ def log(*a):
 
 
 def cpu_baseline(w, steps: int, scheme: str):
-    """Time the oracle on `steps` steps of the same workload (host cores)."""
+    """Time the oracle on the first `steps` steps of the same workload (host
+    cores), the pieces of each step in the order of
+    oracle.freeboundary.free_boundary_step / multistep_step, with a progress
+    line after each."""
     import numpy as np
 
-    from oracle.freeboundary import free_boundary_step, multistep_step
+    from oracle.etd import etd_step, logistic
+    from oracle.freeboundary import levelset_advance as o_levelset_advance
+    from oracle.freeboundary import multistep_step
     from oracle.geometry import Grid
+    from oracle.operator import build_operator
 
     g = Grid(w.grid.dim, tuple(w.grid.n), tuple(w.grid.lo), tuple(w.grid.hi))
+    f, _ = logistic(w.a, w.b)
     rho, u, fp = w.rho0.copy(), w.u0.copy(), np.zeros_like(w.u0)
     t0 = time.perf_counter()
     for m in range(steps):
@@ -76,16 +90,22 @@ def cpu_baseline(w, steps: int, scheme: str):
         if scheme == "etd2":
             rho, u, fp, _ = multistep_step(g, rho, u, fp, w.h, w.beta, w.mu, w.a, w.b, first=(m == 0),
                                            reinit=reinit, frozen=w.frozen, method="krylov")
-        else:
-            rho, u, _ = free_boundary_step(g, rho, u, w.h, w.beta, w.mu, w.a, w.b, scheme=scheme,
-                                           reinit=reinit, frozen=w.frozen, method="krylov")
+            log(f"[bench] cpu baseline: step {m + 1} done ({time.perf_counter() - t0:.1f} s)")
+            continue
+        if not w.frozen:
+            rho, u, _ = o_levelset_advance(g, rho, u, w.h, w.mu, reinit)
+            log(f"[bench] cpu baseline: step {m + 1} level set done ({time.perf_counter() - t0:.1f} s)")
+        op = build_operator(g, rho, w.beta)
+        U = etd_step(op.A, w.h, op.gather(u), f, scheme, method="krylov")
+        u = op.scatter(U)
+        log(f"[bench] cpu baseline: step {m + 1} ETD done ({time.perf_counter() - t0:.1f} s)")
     dt = time.perf_counter() - t0
     npts = int(np.prod(w.grid.n[: w.grid.dim]))
     return {"value": npts * steps / dt, "unit": "grid-point steps/s", "cores": 1,
             "host_cpus": os.cpu_count(), "kind": "oracle",
             "sample": f"first {steps} of {w.steps} steps of {w.name} ({'frozen' if w.frozen else 'free-boundary'} "
-                      f"{scheme.upper()}), "
-                      f"single-threaded NumPy/SciPy, Krylov route for the phi-combinations",
+                      f"{scheme.upper()}, level set included), single-threaded NumPy/SciPy, Krylov route for the "
+                      f"phi-combinations",
             "seconds": dt}
 
 
@@ -315,16 +335,101 @@ def bench_batch_graph(args):
     print(json.dumps(out), flush=True)
 
 
+def run_single(w, scheme, steps, warmup):
+    """Warm-up steps, then `steps` timed steps of workload w from its initial
+    state on one context.  Returns (wall seconds, profile, last stats)."""
+    import torch
+
+    from paper_2209_15095_amd.api import Context
+
+    ctx = Context.from_grid(w.grid, beta=w.beta, a=w.a, b=w.b, mu=w.mu, tol=1e-10)
+    try:
+        rho0 = torch.from_numpy(w.rho0).cuda()
+        u0 = torch.from_numpy(w.u0).cuda()
+        rho = rho0.clone()
+        u = u0.clone()
+        f_prev = torch.zeros_like(u) if scheme == "etd2" else None
+
+        def run(nsteps):
+            for m in range(nsteps):
+                reinit = (m + 1) % w.reinit_every == 0
+                r = None if w.frozen else rho
+                if scheme == "etd2":
+                    ctx.multistep_step(w.h, u, f_prev, first=(m == 0), rho=r, reinit=reinit)
+                else:
+                    ctx.etd_step(scheme, w.h, u, rho=r, reinit=reinit)
+
+        ctx.geometry_build(rho)
+        run(warmup)
+        ctx.sync()
+        # timed run from the initial state
+        rho.copy_(rho0)
+        u.copy_(u0)
+        ctx.geometry_build(rho)
+        ctx.profile_enable(True)
+        ctx.profile_read(reset=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        run(steps)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        ctx.sync()
+        prof = ctx.profile_read()
+        st = ctx.stats()
+    finally:
+        ctx.close()
+    del rho0, u0, rho, u, f_prev
+    return wall, prof, st
+
+
+def krylov_roofline(w, scheme, prof):
+    """Roofline object of the persistent Krylov kernel from a profile."""
+    kern_s = prof["krylov_ms"] * 1e-3
+    achieved = prof["alg_bytes"] / kern_s / 1e9 if kern_s > 0 else 0.0
+    return {
+        "bound": "hbm",
+        "kernel": f"krylov_kernel<{w.grid.dim}> (persistent Lanczos phi-combination / {scheme.upper()} step)",
+        "achieved": achieved,
+        "peak": PEAK_HBM_GBS,
+        "unit": "GB/s",
+        "frac": achieved / PEAK_HBM_GBS,
+        "traffic": MEASURED_TRAFFIC.get((w.name, kernel_source_hash())) if scheme == w.scheme else None,
+        "traffic_unit": "bytes per launch",
+        "alg_bytes_per_launch": prof["alg_bytes"] / max(prof["krylov_launches"], 1),
+        "avg_launch_ms": prof["krylov_ms"] / max(prof["krylov_launches"], 1),
+    }
+
+
+def roofline_scale(steps: int = 2):
+    """The Krylov kernel on the bandwidth-scale frozen domains (one warm-up
+    step, then `steps` timed steps each)."""
+    from paper_2209_15095_amd import inputs
+
+    out = {}
+    for name in ("disk4097", "sphere385"):
+        w = inputs.WORKLOADS[name]()
+        log(f"[bench] roofline scale: {name} ({steps} ETD2RK steps)")
+        wall, prof, st = run_single(w, "etd2rk", steps, 1)
+        r = krylov_roofline(w, "etd2rk", prof)
+        r["n_unknowns"] = prof["n_unknowns"]
+        r["ms_per_step"] = 1e3 * wall / steps
+        r["m_last"] = st["m_last"]
+        out[name] = r
+        del w
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--steps", type=int, default=None, help="timed steps (default: the workload's own count)")
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="star512")
+    ap.add_argument("--workload", default="ellipsoid192")
     ap.add_argument("--scheme", default=None, choices=["etd1", "etd2", "etd2rk", "etd3rk", "etd4rk"],
                     help="time-stepping scheme (default: the workload's); etd2 is ETD2 multistep")
-    ap.add_argument("--cpu-steps", type=int, default=10)
+    ap.add_argument("--cpu-steps", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-scale", action="store_true", help="skip the bandwidth-scale roofline runs")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="MiB: run 3 plain device copies of this size first (counter calibration)")
     args = ap.parse_args()
@@ -337,13 +442,15 @@ def main():
     import torch
 
     from paper_2209_15095_amd import inputs
-    from paper_2209_15095_amd.api import Context
 
     if args.workload == "batch64":
+        args.steps = args.steps or 100
         return bench_batch(args)
     if args.workload == "batch64_frozen":
+        args.steps = args.steps or 100
         return bench_batch_graph(args)
     if args.workload == "sphere96":
+        args.steps = args.steps or 40
         return bench_adjoint(args)
     if args.copy_probe > 0:
         n = args.copy_probe * (1 << 20) // 8
@@ -354,69 +461,21 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     w = inputs.WORKLOADS[args.workload]()
+    steps = args.steps or w.steps
     npts = int(np.prod(w.grid.n[: w.grid.dim]))
-    log(f"[bench] workload {w.name} grid {w.grid.n[:w.grid.dim]} steps {args.steps} warmup {args.warmup}")
-    ctx = Context.from_grid(w.grid, beta=w.beta, a=w.a, b=w.b, mu=w.mu, tol=1e-10)
-    rho0 = torch.from_numpy(w.rho0).cuda()
-    u0 = torch.from_numpy(w.u0).cuda()
-    rho = rho0.clone()
-    u = u0.clone()
     scheme = args.scheme or w.scheme
-    f_prev = torch.zeros_like(u) if scheme == "etd2" else None
-
-    def run(nsteps):
-        for m in range(nsteps):
-            reinit = (m + 1) % w.reinit_every == 0
-            r = None if w.frozen else rho
-            if scheme == "etd2":
-                ctx.multistep_step(w.h, u, f_prev, first=(m == 0), rho=r, reinit=reinit)
-            else:
-                ctx.etd_step(scheme, w.h, u, rho=r, reinit=reinit)
-
-    ctx.geometry_build(rho)
-    run(args.warmup)
-    ctx.sync()
-    # timed run from the initial state
-    rho.copy_(rho0)
-    u.copy_(u0)
-    ctx.geometry_build(rho)
-    ctx.profile_enable(True)
-    ctx.profile_read(reset=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    run(args.steps)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ctx.sync()
-    prof = ctx.profile_read()
-    st = ctx.stats()
-    wall = t1 - t0
-    ms_per_step = 1e3 * wall / max(args.steps, 1)
-    # average unknowns over the run is not tracked; use the final geometry
+    log(f"[bench] workload {w.name} grid {w.grid.n[:w.grid.dim]} steps {steps} warmup {args.warmup}")
+    wall, prof, st = run_single(w, scheme, steps, args.warmup)
+    log(f"[bench] {w.name}: {1e3 * wall / steps:.3f} ms/step")
     n_unknowns = prof["n_unknowns"]
-    kern_s = prof["krylov_ms"] * 1e-3
-    achieved = prof["alg_bytes"] / kern_s / 1e9 if kern_s > 0 else 0.0
-    per_launch_ms = prof["krylov_ms"] / max(prof["krylov_launches"], 1)
-    roofline = {
-        "bound": "hbm",
-        "kernel": f"krylov_kernel<{w.grid.dim}> (persistent Lanczos phi-combination / {scheme.upper()} step)",
-        "achieved": achieved,
-        "peak": PEAK_HBM_GBS,
-        "unit": "GB/s",
-        "frac": achieved / PEAK_HBM_GBS,
-        "traffic": MEASURED_TRAFFIC.get((w.name, kernel_source_hash())) if scheme == w.scheme else None,
-        "traffic_unit": "bytes per launch",
-        "alg_bytes_per_launch": prof["alg_bytes"] / max(prof["krylov_launches"], 1),
-        "avg_launch_ms": per_launch_ms,
-    }
     out = {
         "metric": "grid-point ETD steps/s at Krylov tol 1e-10",
-        "value": npts * args.steps / wall,
+        "value": npts * steps / wall,
         "unit": "grid-point steps/s",
         "n_gpus": 1,
-        "steps": args.steps,
+        "steps": steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": 1e3 * wall / steps,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -434,30 +493,35 @@ def main():
             "reinit_every": w.reinit_every,
             "krylov_tol": 1e-10,
         },
-        "unknown_steps_per_s": n_unknowns * args.steps / wall,
+        "value_counts": "box nodes (n^d) per step; unknown_steps_per_s counts computational points",
+        # the unknowns of the last geometry (the domain grows over the run)
+        "unknown_steps_per_s": n_unknowns * steps / wall,
         "n_unknowns_final": n_unknowns,
         "breakdown_ms_per_step": {
-            "krylov": prof["krylov_ms"] / max(args.steps, 1),
-            "levelset": prof["levelset_ms"] / max(args.steps, 1),
-            "geometry": prof["geometry_ms"] / max(args.steps, 1),
+            "krylov": prof["krylov_ms"] / steps,
+            "levelset": prof["levelset_ms"] / steps,
+            "geometry": prof["geometry_ms"] / steps,
         },
         "krylov_device_ms_per_step": {
-            "whole": prof["krylov_device_ms"] / max(args.steps, 1),
-            "in_grid_sync": prof["krylov_sync_ms"] / max(args.steps, 1),
-            "in_expm": prof["krylov_expm_ms"] / max(args.steps, 1),
-            "in_tile_loops": prof["krylov_tiles_ms"] / max(args.steps, 1),
-            "syncs": prof["krylov_syncs"] / max(args.steps, 1),
-            "expms": prof["krylov_expms"] / max(args.steps, 1),
+            "whole": prof["krylov_device_ms"] / steps,
+            "in_grid_sync": prof["krylov_sync_ms"] / steps,
+            "in_expm": prof["krylov_expm_ms"] / steps,
+            "in_tile_loops": prof["krylov_tiles_ms"] / steps,
+            "syncs": prof["krylov_syncs"] / steps,
+            "expms": prof["krylov_expms"] / steps,
         },
         "last_krylov_stats": st,
-        "roofline": roofline,
+        "roofline": krylov_roofline(w, scheme, prof),
     }
-    if not args.no_cpu_baseline:
-        log(f"[bench] cpu baseline: oracle on {args.cpu_steps} steps")
+    if not args.no_scale and w.name == "ellipsoid192" and scheme == w.scheme:
+        out["roofline_scale"] = roofline_scale()
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    if not args.no_cpu_baseline and args.cpu_steps > 0:
+        log(f"[bench] cpu baseline: oracle on {args.cpu_steps} step(s)")
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_steps, scheme)
     else:
         out["cpu_baseline"] = None
-    ctx.close()
     print(json.dumps(out), flush=True)
 
 

@@ -8,6 +8,9 @@
   the default tolerance 1e-10 to 1e-9.
 * The checkpointed autograd wrapper against the oracle's full gradient on
   the 64^2 disk (10 steps, checkpoints every 4).
+* The 96^3 sphere workload's first checkpoint segment (8 steps) against the
+  oracle's gradient (stored by tests/golden/make_sphere96_gradient.py), and
+  a backward that follows a forward at another beta on the same context.
 * The 96^3 sphere workload in full (40 steps, checkpoints every 8): the
   adjoint gradient against central finite differences of GPU forward runs
   at tolerance 1e-13, in a random direction of U_0 (eps 1e-4) and in beta
@@ -157,3 +160,81 @@ def test_adjoint_sphere96_finite_differences():
     fctx.close()
     assert abs(ad_u - fd_u) <= 1e-6 * abs(fd_u)
     assert abs(dbeta - fd_b) <= 1e-6 * abs(fd_b)
+
+
+def test_sphere96_first_segment_gradient_matches_oracle():
+    """The 96^3 workload's first checkpoint segment (8 ETD2RK steps, loss
+    sum U_8^2) against the oracle's gradient, stored by
+    tests/golden/make_sphere96_gradient.py (about 12 minutes of oracle
+    time): L, dL/dbeta, |dL/dU_0| and 2048 sampled entries to 1e-9 relative,
+    and the projections on 8 seeded Gaussian vectors (which see every entry)
+    to a few 1e-9 of |dL/dU_0|."""
+    import json
+    import os
+
+    from paper_2209_15095_amd.api import ETDSolve
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "sphere96_gradient_segment.json")))
+    w = inputs.sphere96()
+    steps = gold["steps"]
+    op = build_operator(ogrid(w.grid), w.rho0, w.beta)
+    assert op.n == gold["n_unknowns"]
+    say(f"sphere96 first segment: {steps} steps, N {op.n}")
+    ctx = ctx_for(w.grid, beta=w.beta, tol=1e-12)
+    ctx.geometry_build(dev(w.rho0))
+    u0t = dev(w.u0).requires_grad_(True)
+    bt = torch.tensor([w.beta], dtype=torch.float64, device="cuda", requires_grad=True)
+    uT = ETDSolve.apply(u0t, bt, ctx, w.h, steps, steps)
+    loss = (uT * uT).sum()
+    loss.backward()
+    torch.cuda.synchronize()
+    g = u0t.grad.detach().cpu().numpy()[op.comp]
+    L, db = float(loss.detach()), float(bt.grad[0])
+    ctx.close()
+    gn = float(np.linalg.norm(g))
+    idx = np.asarray(gold["sample_index"])
+    sample_rel = rel_l2(g[idx], np.asarray(gold["sample_grad"]))
+    proj = [float(np.random.default_rng(100 + k).standard_normal(op.n) @ g) for k in range(len(gold["projections"]))]
+    dproj = max(abs(a - b) for a, b in zip(proj, gold["projections"])) / gold["grad_norm"]
+    say(f"  L rel {abs(L - gold['L']) / gold['L']:.2e}  dbeta rel {abs(db - gold['dL_dbeta']) / abs(gold['dL_dbeta']):.2e}"
+        f"  |g| rel {abs(gn - gold['grad_norm']) / gold['grad_norm']:.2e}  sample rel {sample_rel:.2e}"
+        f"  projections {dproj:.2e} |g|")
+    assert abs(L - gold["L"]) <= 1e-10 * gold["L"]
+    assert abs(db - gold["dL_dbeta"]) <= 1e-9 * abs(gold["dL_dbeta"])
+    assert abs(gn - gold["grad_norm"]) <= 1e-9 * gold["grad_norm"]
+    assert sample_rel <= 1e-9
+    assert dproj <= 4e-9
+
+
+def test_etdsolve_backward_uses_the_forward_beta():
+    """A forward at beta, another forward at beta + eps on the same context
+    (as a finite-difference probe would run), then the backward of the first:
+    its gradient is the oracle's at beta, and the context's beta is left as
+    the caller set it."""
+    from paper_2209_15095_amd.api import ETDSolve
+    say("ETDSolve: backward after a forward at another beta")
+    w = inputs.fisher64()
+    beta, h, steps = 0.9, 0.02, 6
+    op1 = build_operator(ogrid(w.grid), w.rho0, 1.0)
+    rng = np.random.default_rng(5)
+    u0 = np.where(op1.comp, rng.uniform(0.2, 0.8, w.rho0.shape), 0.0)
+    f, df = logistic(1.0, 1.0)
+    L, gU, gb = gradient(beta * op1.A, beta, h, op1.gather(u0), steps, f, df, method="dense")
+    ctx = ctx_for(w.grid, beta=beta, tol=1e-12)
+    ctx.geometry_build(dev(w.rho0))
+    u0t = dev(u0).requires_grad_(True)
+    bt = torch.tensor([beta], dtype=torch.float64, device="cuda", requires_grad=True)
+    uT = ETDSolve.apply(u0t, bt, ctx, h, steps, 4)
+    loss = (uT * uT).sum()
+    with torch.no_grad():
+        other = ETDSolve.apply(dev(u0), torch.tensor([beta + 0.3], dtype=torch.float64, device="cuda"), ctx, h,
+                               steps, 4)
+    assert ctx.beta == beta + 0.3
+    loss.backward()
+    torch.cuda.synchronize()
+    gg = u0t.grad.cpu().numpy()
+    say(f"  grad rel {rel_l2(gg[op1.comp], gU):.3e}; dbeta {float(bt.grad[0]):.10e} vs {gb:.10e}")
+    assert ctx.beta == beta + 0.3
+    assert rel_l2(gg[op1.comp], gU) <= 1e-9
+    assert abs(float(bt.grad[0]) - gb) <= 1e-9 * abs(gb)
+    del other
+    ctx.close()

@@ -2,10 +2,9 @@
 
 The batch of 64 randomly perturbed stars (seeded draws: side n in
 [96, 384], radius, five Fourier modes, beta in [0.5, 2]; box [-8, 8]^2,
-ETD2RK h = 0.005, mu = 1) is advanced on the GPU; instances with the
-smallest, the largest and a middle grid are compared with the oracle run
-instance by instance (1e-9 relative L2 over computational points, level set
-to 1e-10, masks equal).  The one-block-per-instance launch (group limit 1)
+ETD2RK h = 0.005, mu = 1) is advanced on the GPU for two free-boundary steps;
+every instance is compared with the oracle run instance by instance (1e-9
+relative L2 over computational points, level set to 1e-10, masks equal).  The one-block-per-instance launch (group limit 1)
 must agree with the grouped launch to rounding, and a batch of one with
 etd_step.
 """
@@ -66,14 +65,12 @@ def batch_result():
     return ws, out
 
 
-def test_batch64_sampled_instances_match_oracle(batch_result):
+def test_batch64_every_instance_matches_oracle(batch_result):
+    """All 64 instances, each run by the oracle for the same free-boundary
+    steps (about 1 s of host time per instance)."""
     ws, out = batch_result
-    sizes = [w.grid.n[0] for w in ws]
-    order = np.argsort(sizes)
-    pick = [int(order[0]), int(order[len(order) // 2]), int(order[-1])]
-    for i in pick:
-        w = ws[i]
-        say(f"oracle instance {i} n={w.grid.n[0]} beta={w.beta:.3f}")
+    worst_u, worst_rho = 0.0, 0.0
+    for i, w in enumerate(ws):
         og = ogrid(w.grid)
         rho, u = w.rho0.copy(), w.u0.copy()
         for m in range(STEPS):
@@ -81,11 +78,14 @@ def test_batch64_sampled_instances_match_oracle(batch_result):
                                             reinit=((m + 1) % 5 == 0 or m == STEPS - 1), method="krylov")
         rg, ug = out[i]
         _, comp_g, _ = classify(og, rg)
-        assert np.array_equal(comp_g, op.comp)
-        say(f"  rho diff {np.abs(rg - rho).max():.3e}  u rel {rel_l2(ug[op.comp], u[op.comp]):.3e}")
-        assert np.abs(rg - rho).max() <= 1e-10
-        assert rel_l2(ug[op.comp], u[op.comp]) <= 1e-9
-        assert np.all(ug[~op.comp] == 0.0)
+        du, dr = rel_l2(ug[op.comp], u[op.comp]), float(np.abs(rg - rho).max())
+        worst_u, worst_rho = max(worst_u, du), max(worst_rho, dr)
+        if i % 8 == 7:
+            say(f"  instances 0..{i}: worst rho diff {worst_rho:.3e}, worst u rel {worst_u:.3e}")
+        assert np.array_equal(comp_g, op.comp), i
+        assert dr <= 1e-10, (i, dr)
+        assert du <= 1e-9, (i, du)
+        assert np.all(ug[~op.comp] == 0.0), i
 
 
 def test_batch_single_block_groups_agree(batch_result):

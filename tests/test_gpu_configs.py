@@ -5,10 +5,11 @@
   (masks equal, rho to 1e-10, u to 1e-9 relative L2).
 * ellipsoid192 (192^3 prolate spheroid, 38,824 unknowns): classification
   equal to the oracle's, the operator to rounding, one frozen ETD2RK step
-  against the oracle's Krylov route to 1e-9 (the oracle's level-set sweeps
-  over 7 million nodes take minutes, so the full-size level set is checked by
-  a property instead: with V >= 0 and no reinitialisation rho can only
-  decrease, and the domain only grows).
+  against the oracle's Krylov route to 1e-9, and the first free-boundary step
+  of the workload (level set, geometry, ETD2RK) against the oracle's (masks
+  equal, rho to 1e-10, u to 1e-9 relative L2); also a property of the
+  full-size level set: with V >= 0 and no reinitialisation rho can only
+  decrease, and the domain only grows.
 * The 3D level-set step against the oracle at 64^3 (with reinitialisation)
   and a 3D free-boundary run of 4 steps at 48^3.
 """
@@ -109,6 +110,36 @@ def test_ellipsoid192_geometry_operator_and_step(ellipsoid):
     assert st["n_unknowns"] == op.n
     assert rel_l2(ug[op.comp], U) <= 1e-9
     ctx.close()
+
+
+def test_ellipsoid192_free_boundary_step_full_size(ellipsoid):
+    """The first step of the workload at 192^3 (level set, geometry, ETD2RK)
+    against the oracle's, in the oracle's order (its level set over the
+    whole box takes about 2 minutes of host time)."""
+    import time
+
+    w = ellipsoid
+    og = ogrid(w.grid)
+    ctx = ctx_for(w.grid, beta=w.beta, a=w.a, b=w.b, mu=w.mu)
+    rd, ud = dev(w.rho0), dev(w.u0)
+    ctx.geometry_build(rd)
+    ctx.etd_step("etd2rk", w.h, ud, rho=rd, reinit=False)
+    rg, ug = host(rd), host(ud)
+    ctx.close()
+    say("ellipsoid192 full step: GPU done, oracle level set (whole box)")
+    t0 = time.time()
+    rho1, u1, _ = oracle_levelset_advance(og, w.rho0, w.u0, w.h, w.mu, False)
+    say(f"  oracle level set {time.time() - t0:.0f} s; operator and ETD2RK (Krylov route)")
+    op = build_operator(og, rho1, w.beta)
+    f, _ = logistic(w.a, w.b)
+    U = oracle_etd_step(op.A, w.h, op.gather(u1), f, "etd2rk", method="krylov")
+    say(f"  oracle step {time.time() - t0:.0f} s; N {op.n}")
+    _, comp_g, _ = classify(og, rg)
+    say(f"  rho diff {np.abs(rg - rho1).max():.3e}  u rel {rel_l2(ug[op.comp], U):.3e}")
+    assert np.array_equal(comp_g, op.comp)
+    assert np.abs(rg - rho1).max() <= 1e-10
+    assert rel_l2(ug[op.comp], U) <= 1e-9
+    assert np.all(ug[~op.comp] == 0.0)
 
 
 def test_ellipsoid192_levelset_monotone(ellipsoid):
