@@ -148,6 +148,37 @@ int etd_ctx_set_beta(etd_ctx* ctx, double beta);
  * box layers. */
 int etd_geometry_build(etd_ctx* ctx, const double* rho);
 
+/* Variable beta(x) (Section 2, eq. 2.4 with beta at the face midpoints; the
+ * Case 2/3 closures as for etd_geometry_build): classify rho and build the
+ * operator with face coefficients, and the boundary taps of non-homogeneous
+ * Dirichlet data.  beta_face: host array of dim device pointers; entry d is
+ * a box array whose value at node x is beta(x + h/2 e_d) (the midpoint of
+ * the face between the node and its +e_d neighbour; read only at faces of
+ * computational points).  Later calls use this operator (A is no longer
+ * beta times a fixed matrix: etd_ctx_set_beta and etd_adjoint_step return
+ * ETD_ERR_INVALID) until the next etd_geometry_build; free-boundary calls
+ * (rho != NULL) return ETD_ERR_INVALID meanwhile.  Synchronises.  Device
+ * buffers for the face coefficients and taps are allocated on the first
+ * call.  Errors as etd_geometry_build. */
+int etd_geometry_build_var(etd_ctx* ctx, const double* rho, const double* const* beta_face);
+
+/* Boundary points of the Dirichlet data in the discretisation of the last
+ * etd_geometry_build_var (Section 2: the interface crossing of each Case 2
+ * face, the closest boundary points x_G1, x_G2 of each Case 3 face), in the
+ * order etd_forcing_assemble reads their values.  *count receives their
+ * number; points (host, may be NULL) receives dim coordinates per point
+ * when capacity >= *count (else ETD_ERR_INVALID).  ETD_ERR_NO_GEOMETRY
+ * without a variable-beta geometry. */
+int etd_boundary_taps(etd_ctx* ctx, int32_t capacity, double* points, int32_t* count);
+
+/* The forcing of u_t = A u + G: out = src + g, where g is the boundary term
+ * of the Dirichlet data (Section 2, Cases 2 and 3: each tap's weight times
+ * ub at that tap), at the computational points; 0 elsewhere.  ub: device
+ * array of the data at the points of etd_boundary_taps (may be NULL when
+ * there are none); src: device box array or NULL (0); out: device box
+ * array, must not alias src or ub.  Asynchronous. */
+int etd_forcing_assemble(etd_ctx* ctx, const double* ub, const double* src, double* out);
+
 /* out = A v: the embedded-boundary discretisation of div(beta grad .) of
  * the last etd_geometry_build (Section 2: eq. 2.4 and the Case 2/3 ghost
  * closures with homogeneous boundary data).  v, out: device box arrays
@@ -181,6 +212,17 @@ int levelset_advance(etd_ctx* ctx, double* rho, double* u, double dt, int32_t re
  * ETD step on the new domain.  u: device box array, updated in place. */
 int etd_step(etd_ctx* ctx, int32_t scheme, double h, double* u, double* rho, int32_t reinit,
              etd_stats* stats);
+
+/* One step of size h of u_t = A u + f(u) + G(t) on the frozen domain of the
+ * last geometry build (Section 3 schemes as etd_step; G is the forcing of
+ * a source and Dirichlet data, e.g. from etd_forcing_assemble, as in the
+ * accuracy test of Section 4.2).  g: host array of 3 device box arrays,
+ * G(t_n), G(t_n + h/2), G(t_n + h), read at computational points; ETD1
+ * reads g[0], ETD2RK g[0] and g[2], ETD3RK and ETD4RK all three (unread
+ * entries may be NULL).  u: device box array, updated in place; must not
+ * alias a g entry read.  ETD_ERR_INVALID for a bad scheme, h, or a NULL
+ * entry that is read; ETD_ERR_NO_GEOMETRY before any build. */
+int etd_step_forced(etd_ctx* ctx, int32_t scheme, double h, double* u, const double* const* g, etd_stats* stats);
 
 /* One ETD2 multistep step (Section 3.1, the ETD2 formula, eq. 3.6 with s = 2):
  * U_{n+1} = phi_0(hA) U_n + h phi_1(hA) F_n + h phi_2(hA) (F_n - F_{n-1}),

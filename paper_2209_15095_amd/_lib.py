@@ -70,6 +70,11 @@ SIGNATURES = {
     "etd_ctx_set_beta": (C.c_int, [C.c_void_p, C.c_double]),
     "etd_geometry_build": (C.c_int, [C.c_void_p, C.c_void_p]),
     "etd_operator_apply": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "etd_geometry_build_var": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(C.c_void_p)]),
+    "etd_boundary_taps": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int32)]),
+    "etd_forcing_assemble": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "etd_step_forced": (C.c_int, [C.c_void_p, C.c_int32, C.c_double, C.c_void_p, C.POINTER(C.c_void_p),
+                                  C.POINTER(EtdStats)]),
     "phi_combination_apply": (C.c_int, [C.c_void_p, C.c_double, C.c_int32, C.POINTER(C.c_void_p), C.c_void_p,
                                         C.POINTER(EtdStats)]),
     "levelset_advance": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_int32]),

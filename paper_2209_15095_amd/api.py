@@ -81,6 +81,58 @@ class Context:
         self._sync_stream()
         L.check(self.lib.etd_geometry_build(self.handle, C.c_void_p(_ptr(rho))), "etd_geometry_build")
 
+    def geometry_build_var(self, rho: torch.Tensor, beta_face):
+        """Variable-beta geometry: beta_face[d] holds beta(x + h/2 e_d) at each node x."""
+        self._check_box(rho, "rho")
+        if len(beta_face) != self.dim:
+            raise ValueError(f"beta_face: expected {self.dim} box tensors")
+        for d, b in enumerate(beta_face):
+            self._check_box(b, f"beta_face[{d}]")
+        self._sync_stream()
+        arr = (C.c_void_p * self.dim)(*[_ptr(b) for b in beta_face])
+        L.check(self.lib.etd_geometry_build_var(self.handle, C.c_void_p(_ptr(rho)), arr), "etd_geometry_build_var")
+
+    def boundary_taps(self):
+        """(count, dim) float64 numpy array of the Dirichlet data points."""
+        import numpy as np
+        n = C.c_int32()
+        L.check(self.lib.etd_boundary_taps(self.handle, 0, None, C.byref(n)), "etd_boundary_taps")
+        pts = np.zeros((max(n.value, 1), self.dim))
+        L.check(self.lib.etd_boundary_taps(self.handle, n.value, pts.ctypes.data_as(C.POINTER(C.c_double)),
+                                           C.byref(n)), "etd_boundary_taps")
+        return pts[: n.value]
+
+    def forcing_assemble(self, ub, src=None, out=None):
+        """out = src + boundary forcing of the data ub (one value per tap)."""
+        if ub is not None and (ub.dtype != torch.float64 or not ub.is_cuda or not ub.is_contiguous()):
+            raise TypeError("ub: expected a contiguous float64 CUDA tensor")
+        if src is not None:
+            self._check_box(src, "src")
+        if out is None:
+            out = torch.empty(self.shape, dtype=torch.float64, device="cuda")
+        self._check_box(out, "out")
+        self._sync_stream()
+        L.check(self.lib.etd_forcing_assemble(self.handle, C.c_void_p(_ptr(ub)) if ub is not None else None,
+                                              C.c_void_p(_ptr(src)) if src is not None else None,
+                                              C.c_void_p(_ptr(out))), "etd_forcing_assemble")
+        return out
+
+    def etd_step_forced(self, scheme: str, h: float, u: torch.Tensor, g, stats=False):
+        """One step of u_t = A u + f(u) + G(t); g = [G(t_n), G(t_n + h/2), G(t_n + h)] (None where unused)."""
+        code = SCHEMES[scheme]
+        self._check_box(u, "u")
+        if len(g) != 3:
+            raise ValueError("g: expected [G(t_n), G(t_n + h/2), G(t_n + h)]")
+        for k, t in enumerate(g):
+            if t is not None:
+                self._check_box(t, f"g[{k}]")
+        self._sync_stream()
+        arr = (C.c_void_p * 3)(*[_ptr(t) if t is not None else None for t in g])
+        st = L.EtdStats() if stats else None
+        L.check(self.lib.etd_step_forced(self.handle, code, float(h), C.c_void_p(_ptr(u)), arr,
+                                         C.byref(st) if st is not None else None), "etd_step_forced")
+        return st.as_dict() if stats else None
+
     def operator_apply(self, v: torch.Tensor, out=None):
         """out = A v on the current geometry."""
         self._check_box(v, "v")

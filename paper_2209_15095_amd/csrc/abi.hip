@@ -60,6 +60,17 @@ struct etd_ctx {
   int nband_host[LS_NLIST] = {};
   // geometry-build table of this context (one instance)
   GeomBatch gb{};
+  // variable beta and Dirichlet data (etd_geometry_build_var; allocated on
+  // its first call): face coefficients and diagonal, boundary taps and their
+  // compact numbering
+  bool var_mode = false;
+  double* vcoef = nullptr;
+  int* tap_n = nullptr;
+  double* tap_coef = nullptr;
+  double* tap_pt = nullptr;
+  int* tap_off = nullptr;
+  int ntaps = 0;
+  std::vector<double> h_tap_pts;   // compact tap points, dim per tap
   // pinned host mirror for small readbacks
   int* h_counters = nullptr;
   KrylovStateDev* h_state = nullptr;
@@ -197,6 +208,8 @@ GeomDev geom_view(const etd_ctx* c) {
   g.n_unknowns = c->counters + 4;
   g.coef = c->phys.beta / (c->box.dx * c->box.dx);
   g.dx = c->box.dx;
+  g.vcoef = c->var_mode ? c->vcoef : nullptr;
+  g.vld = c->ld;
   return g;
 }
 
@@ -373,7 +386,8 @@ bool front_too_fast(const LevelsetBatch& b) {
 
 void free_all(etd_ctx* c) {
   void* ptrs[] = {c->mask, c->tile_flag, c->tile_map, c->slot_tile, c->comp_bits, c->irr_bits, c->cdiag,
-                  c->nbr, c->tile_vb, c->band_tmp, c->band_list, c->counters, c->ws, c->part, c->flags, c->bar, c->st};
+                  c->nbr, c->tile_vb, c->band_tmp, c->band_list, c->counters, c->ws, c->part, c->flags, c->bar, c->st,
+                  c->vcoef, c->tap_n, c->tap_coef, c->tap_pt, c->tap_off};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   levelset_free(c->ls);
@@ -529,16 +543,86 @@ int etd_ctx_set_stream(etd_ctx* c, void* s) {
 
 int etd_ctx_set_beta(etd_ctx* c, double beta) {
   if (!c || !(beta > 0.0) || !isfinite(beta)) return ETD_ERR_INVALID;
+  if (c->var_mode) return ETD_ERR_INVALID;
   c->phys.beta = beta;
   return ETD_OK;
 }
 
 int etd_geometry_build(etd_ctx* c, const double* rho) {
   if (!c || !rho) return ETD_ERR_INVALID;
+  c->var_mode = false;
   int r = geometry_enqueue(c, rho);
   if (r) return r;
   HIP_TRY(hipStreamSynchronize(c->stream));
   return geometry_finish(c, c->gb.h_cnt);
+}
+
+int etd_geometry_build_var(etd_ctx* c, const double* rho, const double* const* beta_face) {
+  if (!c || !rho || !beta_face) return ETD_ERR_INVALID;
+  for (int d = 0; d < c->box.dim; ++d)
+    if (!beta_face[d]) return ETD_ERR_INVALID;
+  if (!c->vcoef) {
+    const size_t ld = c->ld;
+    bool ok = true;
+    ok &= hipMalloc(&c->vcoef, sizeof(double) * ld * (2 * c->box.dim + 1)) == hipSuccess;
+    ok &= hipMalloc(&c->tap_n, sizeof(int) * ld) == hipSuccess;
+    ok &= hipMalloc(&c->tap_coef, sizeof(double) * ld * TAPS_PER) == hipSuccess;
+    ok &= hipMalloc(&c->tap_pt, sizeof(double) * ld * TAPS_PER * 3) == hipSuccess;
+    ok &= hipMalloc(&c->tap_off, sizeof(int) * ld) == hipSuccess;
+    if (!ok) return ETD_ERR_HIP;
+  }
+  c->var_mode = false;
+  GeomInst& I = c->gb.h_tab[0];
+  for (int d = 0; d < 3; ++d) I.beta_face[d] = d < c->box.dim ? beta_face[d] : nullptr;
+  I.vcoef = c->vcoef;
+  I.tap_n = c->tap_n;
+  I.tap_coef = c->tap_coef;
+  I.tap_pt = c->tap_pt;
+  int r = geometry_enqueue(c, rho);
+  if (r) return r;
+  HIP_TRY(launch_geometry_var(c->gb, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  for (int d = 0; d < 3; ++d) I.beta_face[d] = nullptr;
+  r = geometry_finish(c, c->gb.h_cnt);
+  if (r) return r;
+  // compact tap numbering (point order: slot, local index, tap), on the host
+  const size_t npts = (size_t)c->n_active_host * TILE_PTS;
+  std::vector<int> tn(npts), off(npts);
+  std::vector<double> pts(npts * TAPS_PER * 3);
+  if (npts) {
+    HIP_TRY(hipMemcpy(tn.data(), c->tap_n, sizeof(int) * npts, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(pts.data(), c->tap_pt, sizeof(double) * npts * TAPS_PER * 3, hipMemcpyDeviceToHost));
+  }
+  int acc = 0;
+  c->h_tap_pts.clear();
+  for (size_t p = 0; p < npts; ++p) {
+    off[p] = acc;
+    for (int k = 0; k < tn[p]; ++k)
+      for (int d = 0; d < c->box.dim; ++d) c->h_tap_pts.push_back(pts[(p * TAPS_PER + k) * 3 + d]);
+    acc += tn[p];
+  }
+  c->ntaps = acc;
+  if (npts) HIP_TRY(hipMemcpy(c->tap_off, off.data(), sizeof(int) * npts, hipMemcpyHostToDevice));
+  c->var_mode = true;
+  return ETD_OK;
+}
+
+int etd_boundary_taps(etd_ctx* c, int32_t capacity, double* points, int32_t* count) {
+  if (!c || !count || capacity < 0) return ETD_ERR_INVALID;
+  if (!c->var_mode) return ETD_ERR_NO_GEOMETRY;
+  *count = c->ntaps;
+  if (points) {
+    if (capacity < c->ntaps) return ETD_ERR_INVALID;
+    memcpy(points, c->h_tap_pts.data(), sizeof(double) * c->h_tap_pts.size());
+  }
+  return ETD_OK;
+}
+
+int etd_forcing_assemble(etd_ctx* c, const double* ub, const double* src, double* out) {
+  if (!c || !out || (c->ntaps > 0 && !ub) || out == src || (const double*)out == ub) return ETD_ERR_INVALID;
+  if (!c->var_mode) return ETD_ERR_NO_GEOMETRY;
+  return check_hip(launch_forcing(c->box, c->tile_map, c->comp_bits, c->tap_n, c->tap_coef, c->tap_off, ub, src,
+                                  out, c->stream));
 }
 
 int etd_operator_apply(etd_ctx* c, const double* v, double* out) {
@@ -581,6 +665,7 @@ int phi_combination_apply(etd_ctx* c, double t, int32_t p, const double* const* 
 
 int levelset_advance(etd_ctx* c, double* rho, double* u, double dt, int32_t reinit) {
   if (!c || !rho || !u || !(dt >= 0.0) || !isfinite(dt)) return ETD_ERR_INVALID;
+  if (c->var_mode) return ETD_ERR_INVALID;
   if (!c->have_geometry) {
     int r = etd_geometry_build(c, rho);
     if (r) return r;
@@ -621,9 +706,40 @@ int etd_step(etd_ctx* c, int32_t scheme, double h, double* u, double* rho, int32
   return ETD_OK;
 }
 
+int etd_step_forced(etd_ctx* c, int32_t scheme, double h, double* u, const double* const* g, etd_stats* stats) {
+  if (!c || !u || !g || !(h >= 0.0) || !isfinite(h)) return ETD_ERR_INVALID;
+  if (scheme < ETD_SCHEME_ETD1 || scheme > ETD_SCHEME_ETD4RK) return ETD_ERR_INVALID;
+  // the stage times each scheme evaluates F at: 0 = t_n, 1 = t_n + h/2, 2 = t_n + h
+  const bool need[3] = {true, scheme >= ETD_SCHEME_ETD3RK, scheme >= ETD_SCHEME_ETD2RK};
+  for (int k = 0; k < 3; ++k) {
+    if (need[k] && !g[k]) return ETD_ERR_INVALID;
+    if (need[k] && g[k] == u) return ETD_ERR_INVALID;
+  }
+  if (!c->have_geometry) return ETD_ERR_NO_GEOMETRY;
+  int r = gather_to(c, u, V_X0);
+  if (r) return r;
+  for (int k = 0; k < 3; ++k)
+    if (need[k] && (r = gather_to(c, g[k], V_FG0 + k))) return r;
+  KrylovDev P = krylov_params(c, job_of(scheme));
+  P.h = h;
+  P.forced = 1;
+  r = run_krylov(c, P);
+  if (r) return r;
+  r = scatter_from(c, V_U, u);
+  if (r) return r;
+  if (stats) {
+    r = fill_stats(c, stats);
+    if (r) return r;
+    int st = latched_status(c);
+    if (st) return st;
+  }
+  return ETD_OK;
+}
+
 int etd_multistep_step(etd_ctx* c, double h, double* u, double* f_prev, int32_t first, double* rho,
                        int32_t reinit, etd_stats* stats) {
   if (!c || !u || !f_prev || f_prev == u || f_prev == rho || !(h >= 0.0) || !isfinite(h)) return ETD_ERR_INVALID;
+  if (rho && c->var_mode) return ETD_ERR_INVALID;
   if (rho) {
     if (!c->have_geometry) {
       int r = etd_geometry_build(c, rho);
@@ -668,7 +784,7 @@ int etd_multistep_step(etd_ctx* c, double h, double* u, double* f_prev, int32_t 
 int etd_adjoint_step(etd_ctx* c, int32_t scheme, double h, const double* u_n, const double* gbar_np1,
                      double* gbar_n, double* dL_dbeta) {
   if (!c || !u_n || !gbar_np1 || !gbar_n || !dL_dbeta || !(h >= 0.0) || !isfinite(h)) return ETD_ERR_INVALID;
-  if (scheme != ETD_SCHEME_ETD2RK || gbar_n == u_n) return ETD_ERR_INVALID;
+  if (scheme != ETD_SCHEME_ETD2RK || gbar_n == u_n || c->var_mode) return ETD_ERR_INVALID;
   if (!c->have_geometry) return ETD_ERR_NO_GEOMETRY;
   int r = gather_to(c, u_n, V_X0);
   if (r) return r;

@@ -35,7 +35,10 @@ enum VecIndex {
   V_A = 14,    // adjoint: ETD2RK stage a
   V_AB = 15,   // adjoint: abar = f'(a) h phi_2(hA) g
   V_S = 16,    // adjoint: f'(U_n) s
-  V_Q0 = 17,   // Krylov basis q_0 .. q_MMAX
+  V_FG0 = 17,  // forced steps: G(t_n), G(t_n + h/2), G(t_n + h) (source + boundary forcing)
+  V_FG1 = 18,
+  V_FG2 = 19,
+  V_Q0 = 20,   // Krylov basis q_0 .. q_MMAX
   NVEC = V_Q0 + MMAX_LIMIT + 1
 };
 
@@ -61,6 +64,11 @@ struct GeomDev {
   const int* n_unknowns;      // device scalar: number of computational points
   double coef;                // beta / h^2
   double dx;
+  // variable beta (NULL for a constant beta): 2d face coefficients
+  // beta_face / h^2 (-x,+x,-y,+y,-z,+z) and the diagonal, each a vector of
+  // the workspace length: (A v)_p = sum_f w_f(p) v_{p+f} + dg(p) v_p
+  const double* vcoef;
+  size_t vld;
 };
 
 // Adaptive state carried across calls and the statistics of the last call.
@@ -113,6 +121,7 @@ struct KrylovDev {
   int g_first, g_size;        // blocks of this instance in the launch grid
   int stage_min;              // fewest active tiles for the LDS-staged Lanczos pass
   int first;                  // JOB_ETD2: no F(U_{n-1}) yet, take one ETD2RK step
+  int forced;                 // F(U, t) = f(U) + G(t), G of the stage times in V_FG0..V_FG2
 };
 
 // Default of KrylovDev::stage_min: the LDS-staged Lanczos pass pays where

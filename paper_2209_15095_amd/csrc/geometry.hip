@@ -315,6 +315,204 @@ __device__ double case3_weight(const BoxDev& b, const double* __restrict__ rho, 
   return dq / dp;
 }
 
+// Case 3 with boundary data: the weights of u_p and of the boundary values
+// at the closest points x_G1 (of q) and x_G2 (of p) in the ghost value
+// u_q = w_p u_p + w_1 u(x_G1) + w_2 u(x_G2), and the two points.  w_p is
+// case3_weight's.  2D: the linear interpolant through p, x_G1, x_G2 (the
+// paper's RBF with a linear tail, eqs. 2.5-2.6), so (w_p, w_1, w_2) are the
+// barycentric coordinates of q; 3D (the plane reading): the boundary part
+// 1 - w_p shared equally by the two points.  Degenerate configurations:
+// one point, x_G1 (or x_q when rho has no gradient at q), with weight
+// 1 - w_p (fallback != 0).
+__device__ void case3_taps(const BoxDev& b, const double* __restrict__ rho, const int p[3], const int q[3],
+                           double& wp, double& w1, double& w2, double g1[3], double g2[3], int& fallback) {
+  const int D = b.dim;
+  wp = case3_weight(b, rho, p, q);
+  const double rp = rho[node_index(b, p[0], p[1], p[2])];
+  const double rq = rho[node_index(b, q[0], q[1], q[2])];
+  double gp[3], gq[3];
+  central_grad(b, rho, p[0], p[1], p[2], gp);
+  central_grad(b, rho, q[0], q[1], q[2], gq);
+  double ggp = 0.0, ggq = 0.0;
+  for (int d = 0; d < D; ++d) { ggp += gp[d] * gp[d]; ggq += gq[d] * gq[d]; }
+  double xp[3] = {0.0, 0.0, 0.0}, xq[3] = {0.0, 0.0, 0.0};
+  for (int d = 0; d < 3; ++d) { g1[d] = 0.0; g2[d] = 0.0; }
+  for (int d = 0; d < D; ++d) {
+    xp[d] = b.lo[d] + b.dx * p[d];
+    xq[d] = b.lo[d] + b.dx * q[d];
+  }
+  const bool have_q = ggq >= 1e-300, have_p = ggp >= 1e-300;
+  for (int d = 0; d < D; ++d) {
+    g1[d] = have_q ? xq[d] - rq * gq[d] / ggq : xq[d];
+    g2[d] = have_p ? xp[d] - rp * gp[d] / ggp : xp[d];
+  }
+  // the non-degenerate cases of case3_weight, re-derived for the flag
+  fallback = 1;
+  if (have_q && have_p) {
+    const double np_ = sqrt(ggp), nq_ = sqrt(ggq);
+    double ng[3] = {0.0, 0.0, 0.0}, nn = 0.0;
+    for (int d = 0; d < D; ++d) { ng[d] = gq[d] / nq_ + gp[d] / np_; nn += ng[d] * ng[d]; }
+    nn = sqrt(nn);
+    if (nn >= 1e-12) {
+      double nbar[3], t[3], L = 0.0;
+      for (int d = 0; d < D; ++d) { nbar[d] = ng[d] / nn; t[d] = g2[d] - g1[d]; L += t[d] * t[d]; }
+      L = sqrt(L);
+      double nu[3];
+      bool ok = true;
+      if (L < 1e-12 * b.dx) {
+        if (D == 2) ok = false;
+        else for (int d = 0; d < D; ++d) nu[d] = nbar[d];
+      } else {
+        double dot = 0.0;
+        for (int d = 0; d < D; ++d) { t[d] /= L; dot += nbar[d] * t[d]; }
+        double nl = 0.0;
+        for (int d = 0; d < D; ++d) { nu[d] = nbar[d] - dot * t[d]; nl += nu[d] * nu[d]; }
+        nl = sqrt(nl);
+        if (nl < 1e-8) ok = false;
+        else for (int d = 0; d < D; ++d) nu[d] /= nl;
+      }
+      if (ok) {
+        double dp = 0.0;
+        for (int d = 0; d < D; ++d) dp += (xp[d] - g1[d]) * nu[d];
+        if (fabs(dp) >= 1e-10 * b.dx) fallback = 0;
+      }
+    }
+  }
+  if (fallback) {
+    w1 = 1.0 - wp;
+    w2 = 0.0;
+    return;
+  }
+  if (D == 3) {
+    w1 = 0.5 * (1.0 - wp);
+    w2 = 0.5 * (1.0 - wp);
+    return;
+  }
+  // 2D barycentric: q - g1 - w_p (p - g1) = w_2 (g2 - g1)
+  double num = 0.0, den = 0.0;
+  for (int d = 0; d < 2; ++d) {
+    const double e = g2[d] - g1[d];
+    num += ((xq[d] - g1[d]) - wp * (xp[d] - g1[d])) * e;
+    den += e * e;
+  }
+  w2 = num / den;
+  w1 = 1.0 - wp - w2;
+}
+
+// Variable beta (one instance; grid = one block per box tile, inactive tiles
+// return): for each computational point and face f = (d, -/+) in the order
+// -x,+x,-y,+y,-z,+z with beta_f = beta at the face midpoint:
+//   q computational: w_f = beta_f/h^2, diagonal -= beta_f/h^2 (eq. 2.4);
+//   Case 2: diagonal -= beta_f/(h s), tap beta_f/(h s) at the crossing;
+//   Case 3: diagonal -= beta_f (1 - w_p)/h^2, taps beta_f w_G/h^2 at x_G1, x_G2;
+// ghost faces have w_f = 0 (the neighbour is not an unknown).
+__global__ __launch_bounds__(256) void tile_var_kernel(const GeomInst* __restrict__ tab) {
+  const GeomInst& I = tab[0];
+  const BoxDev& b = I.b;
+  const double* __restrict__ rho = I.rho;
+  const uint8_t* __restrict__ mask = I.mask;
+  const int t = (int)blockIdx.x;
+  const int slot = I.tile_map[t];
+  if (slot < 0) return;
+  const int tcx = t % b.ntx, tcy = (t / b.ntx) % b.nty, tcz = t / (b.ntx * b.nty);
+  const int l = threadIdx.x;
+  const int lx = l % b.tx, ly = (l / b.tx) % b.ty, lz = l / (b.tx * b.ty);
+  const int i = tcx * b.tx + lx, j = tcy * b.ty + ly, k = tcz * b.tz + lz;
+  const size_t idx = (size_t)slot * TILE_PTS + l;
+  const int D = b.dim;
+  const double h2 = b.dx * b.dx;
+  double wf[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  double dg = 0.0;
+  int nt = 0;
+  bool comp = false;
+  if (i < b.nx && j < b.ny && k < b.nz) {
+    const size_t id = node_index(b, i, j, k);
+    comp = mask[id] == 2;
+    bool edge = i < 2 || i > b.nx - 3 || j < 2 || j > b.ny - 3;
+    if (D == 3) edge = edge || k < 2 || k > b.nz - 3;
+    if (comp && edge) comp = false;   // domain error (reported by classify_kernel)
+  }
+  if (comp) {
+    const int p[3] = {i, j, k};
+    for (int d = 0; d < D; ++d) {
+      for (int s = -1; s <= 1; s += 2) {
+        const int f = 2 * d + (s > 0 ? 1 : 0);
+        int q[3] = {i, j, k};
+        q[d] += s;
+        const size_t qi = node_index(b, q[0], q[1], q[2]);
+        const size_t lowi = s > 0 ? node_index(b, i, j, k) : qi;   // face midpoint = low node + h/2 e_d
+        const double bf = I.beta_face[d][lowi];
+        if (mask[qi] == 2) {
+          wf[f] = bf / h2;
+          dg -= bf / h2;
+          continue;
+        }
+        int q2[3] = {q[0], q[1], q[2]};
+        q2[d] += s;
+        const double rq = rho[qi];
+        const double rq2 = rho[node_index(b, q2[0], q2[1], q2[2])];
+        const size_t tb = idx * TAPS_PER;
+        if (!(rq2 < 0.0)) {
+          const double theta = rq / (rq - rq2);
+          const double dist = (1.0 + theta) * b.dx;
+          const double cf = bf / (b.dx * dist);
+          dg -= cf;
+          I.tap_coef[tb + nt] = cf;
+          for (int c = 0; c < 3; ++c) {
+            double x = c < D ? b.lo[c] + b.dx * q[c] : 0.0;
+            if (c == d) x += s * theta * b.dx;
+            I.tap_pt[(tb + nt) * 3 + c] = x;
+          }
+          ++nt;
+        } else {
+          double wp, w1, w2, g1[3], g2[3];
+          int fb;
+          case3_taps(b, rho, p, q, wp, w1, w2, g1, g2, fb);
+          dg -= bf * (1.0 - wp) / h2;
+          I.tap_coef[tb + nt] = bf * w1 / h2;
+          for (int c = 0; c < 3; ++c) I.tap_pt[(tb + nt) * 3 + c] = g1[c];
+          ++nt;
+          if (!fb) {
+            I.tap_coef[tb + nt] = bf * w2 / h2;
+            for (int c = 0; c < 3; ++c) I.tap_pt[(tb + nt) * 3 + c] = g2[c];
+            ++nt;
+          }
+        }
+      }
+    }
+  }
+  for (int f = 0; f < 2 * D; ++f) I.vcoef[(size_t)f * I.ld + idx] = wf[f];
+  I.vcoef[(size_t)(2 * D) * I.ld + idx] = comp ? dg : 0.0;
+  I.tap_n[idx] = nt;
+}
+
+// Forcing vector in box layout: at computational points the sum of the
+// point's taps coef * ub (in tap order), then plus src; 0 elsewhere.
+__global__ void forcing_kernel(BoxDev b, const int* __restrict__ tile_map, const uint64_t* __restrict__ comp_bits,
+                               const int* __restrict__ tap_n, const double* __restrict__ tap_coef,
+                               const int* __restrict__ tap_off, const double* __restrict__ ub,
+                               const double* __restrict__ src, double* __restrict__ out) {
+  const size_t total = (size_t)b.nx * b.ny * b.nz;
+  for (size_t id = blockIdx.x * (size_t)blockDim.x + threadIdx.x; id < total; id += (size_t)gridDim.x * blockDim.x) {
+    const int i = (int)(id % b.nx);
+    const int j = (int)((id / b.nx) % b.ny);
+    const int k = (int)(id / ((size_t)b.nx * b.ny));
+    const int slot = tile_map[tile_of(b, i, j, k)];
+    double v = 0.0;
+    if (slot >= 0) {
+      const int l = (i % b.tx) + b.tx * ((j % b.ty) + b.ty * (k % b.tz));
+      if (bit_of(comp_bits, slot, l)) {
+        const size_t idx = (size_t)slot * TILE_PTS + l;
+        double g = 0.0;
+        const int n = tap_n[idx];
+        for (int q = 0; q < n; ++q) g += tap_coef[idx * TAPS_PER + q] * ub[tap_off[idx] + q];
+        v = src ? src[id] + g : g;
+      }
+    }
+    out[id] = v;
+  }
+}
+
 // grid = one block (256 threads) per box tile; inactive tiles return.
 __global__ __launch_bounds__(256) void tile_coeff_kernel(const GeomInst* __restrict__ tab,
                                                          const int* __restrict__ pre, int count) {
@@ -558,6 +756,20 @@ hipError_t launch_geometry(GeomBatch& gb, const int* radii, hipStream_t s) {
                      gb.d_tab, n, gb.ncnt, gb.d_cnt);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   return hipMemcpyAsync(gb.h_cnt, gb.d_cnt, sizeof(int) * gb.ncnt * n, hipMemcpyDeviceToHost, s);
+}
+
+hipError_t launch_geometry_var(GeomBatch& gb, hipStream_t s) {
+  hipLaunchKernelGGL(tile_var_kernel, dim3(gb.h_tab[0].ntiles), dim3(256), 0, s, gb.d_tab);
+  return hipGetLastError();
+}
+
+hipError_t launch_forcing(const BoxHost& b, const int* tile_map, const uint64_t* comp_bits, const int* tap_n,
+                          const double* tap_coef, const int* tap_off, const double* ub, const double* src,
+                          double* out, hipStream_t s) {
+  const size_t total = (size_t)b.nx * b.ny * b.nz;
+  hipLaunchKernelGGL(forcing_kernel, dim3(blocks_for(total, 256)), dim3(256), 0, s, b, tile_map, comp_bits, tap_n,
+                     tap_coef, tap_off, ub, src, out);
+  return hipGetLastError();
 }
 
 hipError_t launch_gather_batch(const GeomBatch& gb, const double* const* d_boxes, int vec, hipStream_t s) {

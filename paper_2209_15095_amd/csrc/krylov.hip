@@ -500,6 +500,17 @@ struct Engine {
     if (threadIdx.x == 0 && lb == 0) tk_tiles += wall_clock64() - t_in;
   }
 
+  // Variable beta: sum_f w_f v_f + dg v_p from the face values nv (order
+  // -x,+x,-y,+y,-z,+z; a missing neighbour is a non-computational point,
+  // whose value is 0) and the point's value vc.
+  __device__ __forceinline__ double var_stencil(const Tile& t, const double (&nv)[2 * DIM], double vc) const {
+    gptr<const double> w = glb(P.g.vcoef);
+    double s = 0.0;
+#pragma unroll
+    for (int f = 0; f < 2 * DIM; ++f) s += t.ok[f] ? w[(size_t)f * P.g.vld + t.idx] * nv[f] : 0.0;
+    return s + w[(size_t)(2 * DIM) * P.g.vld + t.idx] * vc;
+  }
+
   // (A v) at the point: beta/h^2 (sum of neighbours - c_p v_p), 0 off the
   // computational points.
   __device__ __forceinline__ double Av(const Tile& t, gptr<const double> v) const {
@@ -507,6 +518,7 @@ struct Engine {
 #pragma unroll
     for (int d = 0; d < 2 * DIM; ++d) nv[d] = v[t.ni[d]];
     const double vc = v[t.idx];
+    if (P.g.vcoef) return t.comp ? var_stencil(t, nv, vc) : 0.0;
     const double cd = glb(P.g.cdiag)[t.irr ? t.idx : 0];
     __builtin_amdgcn_sched_barrier(0);
     double s = 0.0;
@@ -517,6 +529,13 @@ struct Engine {
   }
 
   __device__ __forceinline__ double react(double u) const { return u * (P.ra - P.rb * u); }
+
+  // F(U, t) at point i for stage time k (0: t_n, 1: t_n + h/2, 2: t_n + h):
+  // the reaction, plus the caller's forcing G(t) (source and Dirichlet
+  // boundary terms) in a forced step.
+  __device__ __forceinline__ double Ft(double u, size_t i, int k) const {
+    return P.forced ? react(u) + V(V_FG0 + k)[i] : react(u);
+  }
 
   // ------------------------------------------------------------------ passes
 
@@ -625,7 +644,15 @@ struct Engine {
       for (int d = 0; d < 2 * DIM; ++d) s += t.ok[d] ? qn[d] : 0.0;
       const double cp = t.irr ? cd : (double)(2 * DIM);
       const double q = t.comp ? qn[NP - 1] : 0.0;
-      const double z = t.comp ? P.g.coef * (s - cp * q) : 0.0;
+      double z;
+      if (P.g.vcoef) {
+        double qf[2 * DIM];
+#pragma unroll
+        for (int d = 0; d < 2 * DIM; ++d) qf[d] = qn[d];
+        z = t.comp ? var_stencil(t, qf, q) : 0.0;
+      } else {
+        z = t.comp ? P.g.coef * (s - cp * q) : 0.0;
+      }
       qk[t.idx] = q;
       zk[t.idx] = z;
       acc[0] += q * q;
@@ -1074,7 +1101,8 @@ struct Engine {
           double o[2];
           // large vectors, several loop trips per block, all with cached
           // metadata: the LDS-staged pass
-          const bool staged = nact >= P.stage_min && nact > G * KTILES && nact <= G * KTILES * META_TRIPS;
+          const bool staged = nact >= P.stage_min && nact > G * KTILES && nact <= G * KTILES * META_TRIPS &&
+                              P.g.vcoef == nullptr;
           bool ok;
           if (staged && DIM == 2) ok = lanczos_zf2(m + 1, o);
           else if (staged) ok = lanczos_lds(m + 1, o);
@@ -1278,32 +1306,32 @@ struct Engine {
         p = 1;
         if (mode == JOB_ETD3RK && stage == 1) {
           return pointwise(24.0, [&](size_t i, bool comp) {
-            B1[i] = comp ? h * (2.0 * react(Aa[i]) - react(X[i])) : 0.0;
+            B1[i] = comp ? h * (2.0 * Ft(Aa[i], i, 1) - Ft(X[i], i, 0)) : 0.0;
           });
         }
         t = 0.5 * h;
         if (stage == 0)
-          return pointwise(16.0, [&](size_t i, bool comp) { B1[i] = comp ? 0.5 * h * react(X[i]) : 0.0; });
+          return pointwise(16.0, [&](size_t i, bool comp) { B1[i] = comp ? 0.5 * h * Ft(X[i], i, 0) : 0.0; });
         if (stage == 1)
-          return pointwise(16.0, [&](size_t i, bool comp) { B1[i] = comp ? 0.5 * h * react(Aa[i]) : 0.0; });
+          return pointwise(16.0, [&](size_t i, bool comp) { B1[i] = comp ? 0.5 * h * Ft(Aa[i], i, 1) : 0.0; });
         b0 = V_A;   // ETD4RK c starts from a
         return pointwise(24.0, [&](size_t i, bool comp) {
-          B1[i] = comp ? 0.5 * h * (2.0 * react(AB[i]) - react(X[i])) : 0.0;
+          B1[i] = comp ? 0.5 * h * (2.0 * Ft(AB[i], i, 1) - Ft(X[i], i, 0)) : 0.0;
         });
       }
       p = 3;
       if (mode == JOB_ETD3RK) {
         return pointwise(48.0, [&](size_t i, bool comp) {
-          const double fn = comp ? react(X[i]) : 0.0, fa = comp ? react(Aa[i]) : 0.0;
-          const double fb = comp ? react(U[i]) : 0.0;
+          const double fn = comp ? Ft(X[i], i, 0) : 0.0, fa = comp ? Ft(Aa[i], i, 1) : 0.0;
+          const double fb = comp ? Ft(U[i], i, 2) : 0.0;
           B1[i] = h * fn;
           B2[i] = h * (-3.0 * fn + 4.0 * fa - fb);
           B3[i] = 2.0 * h * (2.0 * fn - 4.0 * fa + 2.0 * fb);
         });
       }
       return pointwise(56.0, [&](size_t i, bool comp) {
-        const double fn = comp ? react(X[i]) : 0.0, fab = comp ? react(Aa[i]) + react(AB[i]) : 0.0;
-        const double fc = comp ? react(U[i]) : 0.0;
+        const double fn = comp ? Ft(X[i], i, 0) : 0.0, fab = comp ? Ft(Aa[i], i, 1) + Ft(AB[i], i, 1) : 0.0;
+        const double fc = comp ? Ft(U[i], i, 2) : 0.0;
         B1[i] = h * fn;
         B2[i] = h * (-3.0 * fn + 2.0 * fab - fc);
         B3[i] = 2.0 * h * (2.0 * fn - 2.0 * fab + 2.0 * fc);
@@ -1317,7 +1345,7 @@ struct Engine {
       const bool first = P.first != 0;
       p = first ? 1 : 2;
       return pointwise(first ? 24.0 : 40.0, [&](size_t i, bool comp) {
-        const double fn = comp ? react(X[i]) : 0.0;
+        const double fn = comp ? Ft(X[i], i, 0) : 0.0;
         B1[i] = h * fn;
         if (!first) B2[i] = h * (fn - (comp ? Gw[i] : 0.0));
         Gw[i] = fn;
@@ -1326,13 +1354,13 @@ struct Engine {
     if (stage == 0) {
       // ETD1 / first ETD2RK stage: b_0 = U_n, b_1 = h F(U_n)
       p = 1;
-      return pointwise(16.0, [&](size_t i, bool comp) { B1[i] = comp ? h * react(X[i]) : 0.0; });
+      return pointwise(16.0, [&](size_t i, bool comp) { B1[i] = comp ? h * Ft(X[i], i, 0) : 0.0; });
     }
     // ETD2RK final stage: b_0 = U_n, b_1 = h F(U_n), b_2 = h (F(a) - F(U_n)),
     // a = the first stage (in V_U, overwritten once b_2 is formed)
     p = 2;
     return pointwise(24.0, [&](size_t i, bool comp) {
-      B2[i] = comp ? h * (react(U[i]) - react(X[i])) : 0.0;
+      B2[i] = comp ? h * (Ft(U[i], i, 2) - Ft(X[i], i, 0)) : 0.0;
     });
   }
 

@@ -39,7 +39,20 @@ struct GeomInst {
   size_t nodes;
   int ntiles;
   int pad;
+  // variable beta (set for etd_geometry_build_var only): beta at the face
+  // midpoints node + h/2 e_d (box arrays, d < dim); outputs: the 2d face
+  // coefficients and the diagonal (vcoef, 2d+1 vectors of ld), and per
+  // point up to TAPS_PER boundary taps (count, coefficient, point)
+  const double* beta_face[3];
+  double* vcoef;
+  int* tap_n;
+  double* tap_coef;
+  double* tap_pt;
 };
+
+// Boundary taps per computational point: two per face (Case 3 has two
+// boundary points, Case 2 one).
+constexpr int TAPS_PER = 12;
 
 enum { GEOM_PRE_NODE = 0, GEOM_PRE_T256 = 1, GEOM_PRE_TILE = 2, GEOM_NPRE = 3 };
 
@@ -66,6 +79,14 @@ hipError_t geom_batch_prefix(GeomBatch& gb);
 // pointers must be set; the table is uploaded from pinned memory, so it
 // must not change before the stream has passed this call.
 hipError_t launch_geometry(GeomBatch& gb, const int* radii, hipStream_t s);
+// After launch_geometry of a one-instance table whose beta_face, vcoef and
+// tap arrays are set: the variable-beta coefficients and boundary taps.
+hipError_t launch_geometry_var(GeomBatch& gb, hipStream_t s);
+// out (box) = src + sum over the taps of coef * ub[tap_off[p] + k] at the
+// computational points (src may be NULL), 0 elsewhere.
+hipError_t launch_forcing(const BoxHost& b, const int* tile_map, const uint64_t* comp_bits, const int* tap_n,
+                          const double* tap_coef, const int* tap_off, const double* ub, const double* src,
+                          double* out, hipStream_t s);
 // Batched box <-> workspace-vector transfers; d_boxes: device array of the
 // instances' box pointers.
 hipError_t launch_gather_batch(const GeomBatch& gb, const double* const* d_boxes, int vec, hipStream_t s);
