@@ -73,6 +73,17 @@ typedef struct {
   double mu;
 } etd_physics;
 
+/* Multi-species systems (Section 3, eq. 3.1 with u in R^m): m <= 4
+ * components share the diffusion operator and react pointwise,
+ * f_s(u) = u_s (a[s] - sum_j b[s*ETD_MAX_SPECIES + j] u_j) (the logistic
+ * reaction of etd_physics for m = 1). */
+#define ETD_MAX_SPECIES 4
+typedef struct {
+  int32_t m;
+  double a[ETD_MAX_SPECIES];
+  double b[ETD_MAX_SPECIES * ETD_MAX_SPECIES];
+} etd_species;
+
 /* Adaptive Krylov options.  tol: local error per unit time relative to the
  * solution norm (the paper's experiments use tolerance-driven adaptivity,
  * Section 3.3).  m_min <= m <= m_max <= 64 Krylov dimensions, grown in steps
@@ -130,6 +141,24 @@ typedef struct etd_ctx etd_ctx;
  * ETD_ERR_INVALID, ETD_ERR_NO_DEVICE or ETD_ERR_HIP. */
 int etd_ctx_create(const etd_grid* grid, const etd_physics* phys, const etd_krylov_opts* opts,
                    void* hip_stream, etd_ctx** out);
+
+/* Create a context for m species (etd_species; Section 3, eq. 3.1):
+ * phys gives beta (shared by the species) and mu; its a and b are not used.
+ * The discretised system is C = I_m (x) A, one Krylov space for all
+ * species (its inner products sum over them).  Workspaces are m times those
+ * of etd_ctx_create.  Such a context serves etd_geometry_build (frozen
+ * domains), etd_step_species, sync, stats and profiling; every other call
+ * returns ETD_ERR_INVALID.  ETD_ERR_INVALID for m outside 1..4 or
+ * non-finite coefficients. */
+int etd_ctx_create_species(const etd_grid* grid, const etd_physics* phys, const etd_species* species,
+                           const etd_krylov_opts* opts, void* hip_stream, etd_ctx** out);
+
+/* One step of size h of the m-species system u_t = A u + f(u) (ETD1,
+ * ETD2RK, ETD3RK or ETD4RK as in etd_step, Section 3, every stage one
+ * combination on all species) on the frozen domain of the last geometry
+ * build.  u: host array of m device box arrays (distinct), updated in
+ * place. */
+int etd_step_species(etd_ctx* ctx, int32_t scheme, double h, double* const* u, etd_stats* stats);
 
 /* Free a context and its workspaces (synchronises its stream first). */
 int etd_ctx_destroy(etd_ctx* ctx);

@@ -34,6 +34,14 @@ class EtdPhysics(C.Structure):
     _fields_ = [("beta", C.c_double), ("a", C.c_double), ("b", C.c_double), ("mu", C.c_double)]
 
 
+ETD_MAX_SPECIES = 4
+
+
+class EtdSpecies(C.Structure):
+    _fields_ = [("m", C.c_int32), ("a", C.c_double * ETD_MAX_SPECIES),
+                ("b", C.c_double * (ETD_MAX_SPECIES * ETD_MAX_SPECIES))]
+
+
 class EtdKrylovOpts(C.Structure):
     _fields_ = [("tol", C.c_double), ("m_min", C.c_int32), ("m_max", C.c_int32), ("m_step", C.c_int32),
                 ("max_substeps", C.c_int32)]
@@ -65,6 +73,9 @@ class EtdProfile(C.Structure):
 SIGNATURES = {
     "etd_ctx_create": (C.c_int, [C.POINTER(EtdGrid), C.POINTER(EtdPhysics), C.POINTER(EtdKrylovOpts),
                                  C.c_void_p, C.POINTER(C.c_void_p)]),
+    "etd_ctx_create_species": (C.c_int, [C.POINTER(EtdGrid), C.POINTER(EtdPhysics), C.POINTER(EtdSpecies),
+                                         C.POINTER(EtdKrylovOpts), C.c_void_p, C.POINTER(C.c_void_p)]),
+    "etd_step_species": (C.c_int, [C.c_void_p, C.c_int32, C.c_double, C.POINTER(C.c_void_p), C.POINTER(EtdStats)]),
     "etd_ctx_destroy": (C.c_int, [C.c_void_p]),
     "etd_ctx_set_stream": (C.c_int, [C.c_void_p, C.c_void_p]),
     "etd_ctx_set_beta": (C.c_int, [C.c_void_p, C.c_double]),

@@ -26,7 +26,9 @@ class Context:
     """One etd_ctx: a grid, physics, Krylov options and device workspaces."""
 
     def __init__(self, dim, n, lo, hi, beta=1.0, a=1.0, b=1.0, mu=0.0, tol=1e-10, m_min=8, m_max=64,
-                 m_step=4, max_substeps=64, stream=None):
+                 m_step=4, max_substeps=64, stream=None, species=None):
+        """species: None (scalar u), or (a, B) of an m-species Lotka-Volterra
+        reaction f_s(u) = u_s (a[s] - sum_j B[s][j] u_j), m <= 4."""
         self.lib = L.load()
         g = L.EtdGrid()
         g.dim = dim
@@ -41,8 +43,23 @@ class Context:
         self.shape = tuple(reversed([int(x) for x in n[:dim]]))
         self.handle = C.c_void_p()
         s = stream if stream is not None else torch.cuda.current_stream()
-        L.check(self.lib.etd_ctx_create(C.byref(g), C.byref(ph), C.byref(op), C.c_void_p(s.cuda_stream),
-                                        C.byref(self.handle)), "etd_ctx_create")
+        self.species = 1
+        if species is None:
+            L.check(self.lib.etd_ctx_create(C.byref(g), C.byref(ph), C.byref(op), C.c_void_p(s.cuda_stream),
+                                            C.byref(self.handle)), "etd_ctx_create")
+        else:
+            sa, sb = species
+            m = len(sa)
+            sp = L.EtdSpecies()
+            sp.m = m
+            for i in range(m):
+                sp.a[i] = float(sa[i])
+                for j in range(m):
+                    sp.b[i * L.ETD_MAX_SPECIES + j] = float(sb[i][j])
+            L.check(self.lib.etd_ctx_create_species(C.byref(g), C.byref(ph), C.byref(sp), C.byref(op),
+                                                    C.c_void_p(s.cuda_stream), C.byref(self.handle)),
+                    "etd_ctx_create_species")
+            self.species = m
         self._stream = s
 
     @classmethod
@@ -176,6 +193,20 @@ class Context:
         L.check(self.lib.etd_step(self.handle, code, float(h), C.c_void_p(_ptr(u)),
                                   C.c_void_p(_ptr(rho)) if rho is not None else None, int(bool(reinit)),
                                   C.byref(st) if st is not None else None), "etd_step")
+        return st.as_dict() if stats else None
+
+    def etd_step_species(self, scheme: str, h: float, us, stats=False):
+        """One step of the m-species system (etd_step_species); us: m box tensors, in place."""
+        code = SCHEMES[scheme]
+        if len(us) != self.species:
+            raise ValueError(f"us: expected {self.species} tensors")
+        for k, t in enumerate(us):
+            self._check_box(t, f"u[{k}]")
+        self._sync_stream()
+        arr = (C.c_void_p * self.species)(*[_ptr(t) for t in us])
+        st = L.EtdStats() if stats else None
+        L.check(self.lib.etd_step_species(self.handle, code, float(h), arr, C.byref(st) if st is not None else None),
+                "etd_step_species")
         return st.as_dict() if stats else None
 
     def multistep_step(self, h: float, u: torch.Tensor, f_prev: torch.Tensor, first: bool, rho=None,

@@ -19,6 +19,10 @@ constexpr int NCOUNTERS = 16;   // device counters of a context (see etd_ctx::co
 
 struct etd_ctx {
   int device = 0;
+  // components of u (eq. 3.1 with u in R^m) and their Lotka-Volterra reaction
+  int species = 1;
+  double sp_a[MAX_SPECIES] = {};
+  double sp_b[MAX_SPECIES * MAX_SPECIES] = {};
   hipStream_t stream = nullptr;
   etd_grid grid{};
   etd_physics phys{};
@@ -204,8 +208,8 @@ GeomDev geom_view(const etd_ctx* c) {
   g.irr_bits = c->irr_bits;
   g.cdiag = c->cdiag;
   g.nbr = c->nbr;
-  g.n_active = c->counters + 0;
-  g.n_unknowns = c->counters + 4;
+  g.n_active = c->counters + (c->species > 1 ? 5 : 0);
+  g.n_unknowns = c->counters + (c->species > 1 ? 6 : 4);
   g.coef = c->phys.beta / (c->box.dx * c->box.dx);
   g.dx = c->box.dx;
   g.vcoef = c->var_mode ? c->vcoef : nullptr;
@@ -232,6 +236,9 @@ KrylovDev krylov_params(const etd_ctx* c, int mode) {
   P.ra = c->phys.a;
   P.rb = c->phys.b;
   P.mode = mode;
+  P.species = c->species;
+  for (int s = 0; s < MAX_SPECIES; ++s) P.sa[s] = c->sp_a[s];
+  for (int s = 0; s < MAX_SPECIES * MAX_SPECIES; ++s) P.sb[s] = c->sp_b[s];
   // ETDFB_STAGE_MIN in the environment overrides the size from which the
   // LDS-staged Lanczos pass is used (tests take it down to small problems)
   P.stage_min = STAGE_MIN_TILES;
@@ -243,7 +250,7 @@ KrylovDev krylov_params(const etd_ctx* c, int mode) {
 // active tiles (KTILES tiles per block and trip), at most the number of
 // co-resident blocks.  ETDFB_GRID in the environment overrides the count.
 void choose_launch(etd_ctx* c) {
-  const int nact = c->n_active_host > 0 ? c->n_active_host : 1;
+  const int nact = c->n_active_host > 0 ? c->n_active_host * c->species : 1;
   int g = (nact + KTILES - 1) / KTILES;
   if (g > c->max_grid) g = c->max_grid;
   if (const char* env = getenv("ETDFB_GRID")) {
@@ -282,8 +289,9 @@ int fill_stats(etd_ctx* c, etd_stats* s) {
   s->matvecs = c->h_state->matvecs;
   s->m_last = c->h_state->m_last;
   s->expms = c->h_state->expms;
-  s->n_active_tiles = c->h_counters[0];
-  s->n_unknowns = c->h_counters[4];
+  // the unknowns of the (stacked) system: m copies of the tiles and points
+  s->n_active_tiles = c->h_counters[c->species > 1 ? 5 : 0];
+  s->n_unknowns = c->h_counters[c->species > 1 ? 6 : 4];
   s->status = c->h_counters[1];
   s->err_est = c->h_state->err_est;
   s->t_done = c->h_state->t_done;
@@ -336,6 +344,7 @@ int geometry_enqueue(etd_ctx* c, const double* rho) {
   HIP_TRY(timer_begin(c->profiling, c->stream, c->t_geometry));
   c->gb.h_tab[0].rho = rho;
   HIP_TRY(launch_geometry(c->gb, GEOM_RADII, c->stream));
+  if (c->species > 1) HIP_TRY(launch_replicate_species(c->gb, c->species, c->stream));
   HIP_TRY(timer_end(c->profiling, c->stream, c->t_geometry));
   return ETD_OK;
 }
@@ -420,8 +429,13 @@ const char* etd_status_string(int s) {
   }
 }
 
-int etd_ctx_create(const etd_grid* grid, const etd_physics* phys, const etd_krylov_opts* opts,
-                   void* hip_stream, etd_ctx** out) {
+}  // extern "C"
+
+namespace {
+
+// Context creation for `species` components (1: the scalar problem).
+int ctx_create(const etd_grid* grid, const etd_physics* phys, const etd_krylov_opts* opts, void* hip_stream,
+               const etd_species* sp, etd_ctx** out) {
   if (!grid || !phys || !out) return ETD_ERR_INVALID;
   *out = nullptr;
   if (grid->dim != 2 && grid->dim != 3) return ETD_ERR_INVALID;
@@ -444,6 +458,13 @@ int etd_ctx_create(const etd_grid* grid, const etd_physics* phys, const etd_kryl
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return ETD_ERR_NO_DEVICE;
   etd_ctx* c = new etd_ctx();
+  if (sp) {
+    c->species = sp->m;
+    for (int s = 0; s < sp->m; ++s) {
+      c->sp_a[s] = sp->a[s];
+      for (int j = 0; j < sp->m; ++j) c->sp_b[s * MAX_SPECIES + j] = sp->b[s * ETD_MAX_SPECIES + j];
+    }
+  }
   if (hipGetDevice(&c->device) != hipSuccess) { delete c; return ETD_ERR_NO_DEVICE; }
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, c->device) != hipSuccess) { delete c; return ETD_ERR_HIP; }
@@ -465,7 +486,9 @@ int etd_ctx_create(const etd_grid* grid, const etd_physics* phys, const etd_kryl
   b.dx = dx;
   c->ntiles = b.ntx * b.nty * b.ntz;
   c->nodes = (size_t)b.nx * b.ny * b.nz;
-  c->ld = (size_t)c->ntiles * TILE_PTS;
+  // every species has its copy of the active tiles in the vectors
+  const size_t ktiles = (size_t)c->ntiles * c->species;
+  c->ld = ktiles * TILE_PTS;
   c->n_cu = prop.multiProcessorCount;
   {
     int khz = 0;
@@ -479,11 +502,11 @@ int etd_ctx_create(const etd_grid* grid, const etd_physics* phys, const etd_kryl
   ok &= hipMalloc(&c->mask, c->nodes) == hipSuccess;
   ok &= hipMalloc(&c->tile_flag, sizeof(int) * c->ntiles) == hipSuccess;
   ok &= hipMalloc(&c->tile_map, sizeof(int) * c->ntiles) == hipSuccess;
-  ok &= hipMalloc(&c->slot_tile, sizeof(int) * c->ntiles) == hipSuccess;
-  ok &= hipMalloc(&c->comp_bits, sizeof(uint64_t) * 4 * c->ntiles) == hipSuccess;
-  ok &= hipMalloc(&c->irr_bits, sizeof(uint64_t) * 4 * c->ntiles) == hipSuccess;
+  ok &= hipMalloc(&c->slot_tile, sizeof(int) * ktiles) == hipSuccess;
+  ok &= hipMalloc(&c->comp_bits, sizeof(uint64_t) * 4 * ktiles) == hipSuccess;
+  ok &= hipMalloc(&c->irr_bits, sizeof(uint64_t) * 4 * ktiles) == hipSuccess;
   ok &= hipMalloc(&c->cdiag, sizeof(double) * c->ld) == hipSuccess;
-  ok &= hipMalloc(&c->nbr, sizeof(int) * NBR_STRIDE * (size_t)c->ntiles) == hipSuccess;
+  ok &= hipMalloc(&c->nbr, sizeof(int) * NBR_STRIDE * ktiles) == hipSuccess;
   ok &= hipMalloc(&c->tile_vb, sizeof(int) * (size_t)c->ntiles) == hipSuccess;
   ok &= hipMalloc(&c->band_tmp, sizeof(int) * 2 * (size_t)c->ntiles) == hipSuccess;
   ok &= hipMalloc(&c->band_list, sizeof(int) * LS_NLIST * (size_t)c->ntiles) == hipSuccess;
@@ -527,6 +550,57 @@ int etd_ctx_create(const etd_grid* grid, const etd_physics* phys, const etd_kryl
   return ETD_OK;
 }
 
+}  // namespace
+
+extern "C" {
+
+int etd_ctx_create(const etd_grid* grid, const etd_physics* phys, const etd_krylov_opts* opts,
+                   void* hip_stream, etd_ctx** out) {
+  return ctx_create(grid, phys, opts, hip_stream, nullptr, out);
+}
+
+int etd_ctx_create_species(const etd_grid* grid, const etd_physics* phys, const etd_species* sp,
+                           const etd_krylov_opts* opts, void* hip_stream, etd_ctx** out) {
+  if (out) *out = nullptr;
+  if (!sp || sp->m < 1 || sp->m > ETD_MAX_SPECIES) return ETD_ERR_INVALID;
+  for (int s = 0; s < sp->m; ++s) {
+    if (!isfinite(sp->a[s])) return ETD_ERR_INVALID;
+    for (int j = 0; j < sp->m; ++j)
+      if (!isfinite(sp->b[s * ETD_MAX_SPECIES + j])) return ETD_ERR_INVALID;
+  }
+  return ctx_create(grid, phys, opts, hip_stream, sp, out);
+}
+
+int etd_step_species(etd_ctx* c, int32_t scheme, double h, double* const* u, etd_stats* stats) {
+  if (!c || !u || !(h >= 0.0) || !isfinite(h)) return ETD_ERR_INVALID;
+  if (scheme < ETD_SCHEME_ETD1 || scheme > ETD_SCHEME_ETD4RK) return ETD_ERR_INVALID;
+  for (int s = 0; s < c->species; ++s) {
+    if (!u[s]) return ETD_ERR_INVALID;
+    for (int j = 0; j < s; ++j)
+      if (u[j] == u[s]) return ETD_ERR_INVALID;
+  }
+  if (!c->have_geometry) return ETD_ERR_NO_GEOMETRY;
+  const size_t stride = (size_t)c->n_active_host * TILE_PTS;
+  const int grid = c->n_active_host > 0 ? c->n_active_host : 1;
+  for (int s = 0; s < c->species; ++s)
+    HIP_TRY(launch_gather(c->box, u[s], c->slot_tile, c->comp_bits, c->counters + 0,
+                          c->ws + (size_t)V_X0 * c->ld + s * stride, grid, c->stream));
+  KrylovDev P = krylov_params(c, job_of(scheme));
+  P.h = h;
+  int r = run_krylov(c, P);
+  if (r) return r;
+  for (int s = 0; s < c->species; ++s)
+    HIP_TRY(launch_scatter(c->box, c->ws + (size_t)V_U * c->ld + s * stride, c->tile_map, c->comp_bits, u[s],
+                           c->stream));
+  if (stats) {
+    r = fill_stats(c, stats);
+    if (r) return r;
+    int st = latched_status(c);
+    if (st) return st;
+  }
+  return ETD_OK;
+}
+
 int etd_ctx_destroy(etd_ctx* c) {
   if (!c) return ETD_ERR_INVALID;
   (void)hipStreamSynchronize(c->stream);
@@ -558,7 +632,7 @@ int etd_geometry_build(etd_ctx* c, const double* rho) {
 }
 
 int etd_geometry_build_var(etd_ctx* c, const double* rho, const double* const* beta_face) {
-  if (!c || !rho || !beta_face) return ETD_ERR_INVALID;
+  if (!c || !rho || !beta_face || c->species > 1) return ETD_ERR_INVALID;
   for (int d = 0; d < c->box.dim; ++d)
     if (!beta_face[d]) return ETD_ERR_INVALID;
   if (!c->vcoef) {
@@ -626,7 +700,7 @@ int etd_forcing_assemble(etd_ctx* c, const double* ub, const double* src, double
 }
 
 int etd_operator_apply(etd_ctx* c, const double* v, double* out) {
-  if (!c || !v || !out || v == out) return ETD_ERR_INVALID;
+  if (!c || !v || !out || v == out || c->species > 1) return ETD_ERR_INVALID;
   if (!c->have_geometry) return ETD_ERR_NO_GEOMETRY;
   int r = gather_to(c, v, V_B0);
   if (r) return r;
@@ -637,7 +711,7 @@ int etd_operator_apply(etd_ctx* c, const double* v, double* out) {
 
 int phi_combination_apply(etd_ctx* c, double t, int32_t p, const double* const* b, double* out,
                           etd_stats* stats) {
-  if (!c || !b || !out || p < 0 || p > PMAX || !(t >= 0.0) || !isfinite(t)) return ETD_ERR_INVALID;
+  if (!c || !b || !out || p < 0 || p > PMAX || !(t >= 0.0) || !isfinite(t) || c->species > 1) return ETD_ERR_INVALID;
   for (int k = 0; k <= p; ++k) {
     if (!b[k]) return ETD_ERR_INVALID;
     if (b[k] == out) return ETD_ERR_INVALID;
@@ -665,7 +739,7 @@ int phi_combination_apply(etd_ctx* c, double t, int32_t p, const double* const* 
 
 int levelset_advance(etd_ctx* c, double* rho, double* u, double dt, int32_t reinit) {
   if (!c || !rho || !u || !(dt >= 0.0) || !isfinite(dt)) return ETD_ERR_INVALID;
-  if (c->var_mode) return ETD_ERR_INVALID;
+  if (c->var_mode || c->species > 1) return ETD_ERR_INVALID;
   if (!c->have_geometry) {
     int r = etd_geometry_build(c, rho);
     if (r) return r;
@@ -682,7 +756,7 @@ int levelset_advance(etd_ctx* c, double* rho, double* u, double dt, int32_t rein
 
 int etd_step(etd_ctx* c, int32_t scheme, double h, double* u, double* rho, int32_t reinit,
              etd_stats* stats) {
-  if (!c || !u || !(h >= 0.0) || !isfinite(h)) return ETD_ERR_INVALID;
+  if (!c || !u || !(h >= 0.0) || !isfinite(h) || c->species > 1) return ETD_ERR_INVALID;
   if (scheme < ETD_SCHEME_ETD1 || scheme > ETD_SCHEME_ETD4RK) return ETD_ERR_INVALID;
   if (rho) {
     int r = levelset_advance(c, rho, u, h, reinit);
@@ -707,7 +781,7 @@ int etd_step(etd_ctx* c, int32_t scheme, double h, double* u, double* rho, int32
 }
 
 int etd_step_forced(etd_ctx* c, int32_t scheme, double h, double* u, const double* const* g, etd_stats* stats) {
-  if (!c || !u || !g || !(h >= 0.0) || !isfinite(h)) return ETD_ERR_INVALID;
+  if (!c || !u || !g || !(h >= 0.0) || !isfinite(h) || c->species > 1) return ETD_ERR_INVALID;
   if (scheme < ETD_SCHEME_ETD1 || scheme > ETD_SCHEME_ETD4RK) return ETD_ERR_INVALID;
   // the stage times each scheme evaluates F at: 0 = t_n, 1 = t_n + h/2, 2 = t_n + h
   const bool need[3] = {true, scheme >= ETD_SCHEME_ETD3RK, scheme >= ETD_SCHEME_ETD2RK};
@@ -739,7 +813,7 @@ int etd_step_forced(etd_ctx* c, int32_t scheme, double h, double* u, const doubl
 int etd_multistep_step(etd_ctx* c, double h, double* u, double* f_prev, int32_t first, double* rho,
                        int32_t reinit, etd_stats* stats) {
   if (!c || !u || !f_prev || f_prev == u || f_prev == rho || !(h >= 0.0) || !isfinite(h)) return ETD_ERR_INVALID;
-  if (rho && c->var_mode) return ETD_ERR_INVALID;
+  if ((rho && c->var_mode) || c->species > 1) return ETD_ERR_INVALID;
   if (rho) {
     if (!c->have_geometry) {
       int r = etd_geometry_build(c, rho);
@@ -784,7 +858,7 @@ int etd_multistep_step(etd_ctx* c, double h, double* u, double* f_prev, int32_t 
 int etd_adjoint_step(etd_ctx* c, int32_t scheme, double h, const double* u_n, const double* gbar_np1,
                      double* gbar_n, double* dL_dbeta) {
   if (!c || !u_n || !gbar_np1 || !gbar_n || !dL_dbeta || !(h >= 0.0) || !isfinite(h)) return ETD_ERR_INVALID;
-  if (scheme != ETD_SCHEME_ETD2RK || gbar_n == u_n || c->var_mode) return ETD_ERR_INVALID;
+  if (scheme != ETD_SCHEME_ETD2RK || gbar_n == u_n || c->var_mode || c->species > 1) return ETD_ERR_INVALID;
   if (!c->have_geometry) return ETD_ERR_NO_GEOMETRY;
   int r = gather_to(c, u_n, V_X0);
   if (r) return r;
@@ -830,7 +904,7 @@ int etd_ctx_profile_read(etd_ctx* c, etd_profile* out, int32_t reset) {
   out->levelset_calls = c->t_levelset.count;
   out->geometry_calls = c->t_geometry.count;
   out->alg_bytes = c->h_state->alg_bytes_total;
-  out->n_unknowns = c->h_counters[4];
+  out->n_unknowns = c->h_counters[c->species > 1 ? 6 : 4];
   out->krylov_device_ms = c->h_state->ticks_total / c->clock_khz;
   out->krylov_sync_ms = c->h_state->ticks_sync / c->clock_khz;
   out->krylov_expm_ms = c->h_state->ticks_expm / c->clock_khz;

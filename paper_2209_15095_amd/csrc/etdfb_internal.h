@@ -15,6 +15,7 @@ constexpr int KBLOCK = 1024;        // threads per block of the persistent kerne
 constexpr int NBR_STRIDE = 8;       // ints per slot in the face-neighbour table
 constexpr int KTILES = KBLOCK / TILE_PTS;  // tiles a block works on per loop trip
 constexpr double NOT_COMP = -1e300; // coefficient sentinel of non-computational points
+constexpr int MAX_SPECIES = 4;      // components of u in a multi-species context
 
 // Work vectors of the persistent kernel (indices into the workspace).
 enum VecIndex {
@@ -122,6 +123,12 @@ struct KrylovDev {
   int stage_min;              // fewest active tiles for the LDS-staged Lanczos pass
   int first;                  // JOB_ETD2: no F(U_{n-1}) yet, take one ETD2RK step
   int forced;                 // F(U, t) = f(U) + G(t), G of the stage times in V_FG0..V_FG2
+  // m > 1 species: the active tiles are repeated m times (species s in
+  // slots s*n .. s*n + n - 1 of the n base slots), f_s(u) = u_s (sa[s] -
+  // sum_j sb[s][j] u_j)
+  int species;
+  double sa[MAX_SPECIES];
+  double sb[MAX_SPECIES * MAX_SPECIES];
 };
 
 // Default of KrylovDev::stage_min: the LDS-staged Lanczos pass pays where

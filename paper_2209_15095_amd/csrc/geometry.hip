@@ -758,6 +758,39 @@ hipError_t launch_geometry(GeomBatch& gb, const int* radii, hipStream_t s) {
   return hipMemcpyAsync(gb.h_cnt, gb.d_cnt, sizeof(int) * gb.ncnt * n, hipMemcpyDeviceToHost, s);
 }
 
+// m species (one instance): slots n .. m n - 1 repeat the n base slots (masks,
+// diagonal weights, the tile of each slot; face-neighbour slots shifted into
+// the same copy), counters[5] = m n and counters[6] = m N.
+__global__ void replicate_species_kernel(const GeomInst* __restrict__ tab, int m) {
+  const GeomInst& I = tab[0];
+  const int n = I.counters[0];
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    I.counters[5] = m * n;
+    I.counters[6] = m * I.counters[4];
+  }
+  const long total = (long)(m - 1) * n * TILE_PTS;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
+    const int slot = n + (int)(e / TILE_PTS);
+    const int l = (int)(e % TILE_PTS);
+    const int base = slot % n, sp = slot / n;
+    I.cdiag[(size_t)slot * TILE_PTS + l] = I.cdiag[(size_t)base * TILE_PTS + l];
+    if (l < 4) {
+      I.comp_bits[(size_t)slot * 4 + l] = I.comp_bits[(size_t)base * 4 + l];
+      I.irr_bits[(size_t)slot * 4 + l] = I.irr_bits[(size_t)base * 4 + l];
+    }
+    if (l < NBR_STRIDE) {
+      const int nb = I.nbr[(size_t)base * NBR_STRIDE + l];
+      I.nbr[(size_t)slot * NBR_STRIDE + l] = nb >= 0 ? nb + sp * n : -1;
+    }
+    if (l == 0) I.slot_tile[slot] = I.slot_tile[base];
+  }
+}
+
+hipError_t launch_replicate_species(GeomBatch& gb, int m, hipStream_t s) {
+  hipLaunchKernelGGL(replicate_species_kernel, dim3(1024), dim3(256), 0, s, gb.d_tab, m);
+  return hipGetLastError();
+}
+
 hipError_t launch_geometry_var(GeomBatch& gb, hipStream_t s) {
   hipLaunchKernelGGL(tile_var_kernel, dim3(gb.h_tab[0].ntiles), dim3(256), 0, s, gb.d_tab);
   return hipGetLastError();

@@ -258,6 +258,7 @@ struct Engine {
   double err_est, t_done;
   bool failed;
   int iu;   // vector holding u(t_j) = W_0 (V_U or V_T, ping-pong with the combine output)
+  size_t sp_stride;   // index distance between the copies of one node in consecutive species
   // Algorithmic HBM bytes per unknown moved so far: what the method must read
   // and write per computational point (vectors only; neighbour re-reads,
   // masks and tile padding are not counted).
@@ -530,10 +531,21 @@ struct Engine {
 
   __device__ __forceinline__ double react(double u) const { return u * (P.ra - P.rb * u); }
 
-  // F(U, t) at point i for stage time k (0: t_n, 1: t_n + h/2, 2: t_n + h):
-  // the reaction, plus the caller's forcing G(t) (source and Dirichlet
-  // boundary terms) in a forced step.
-  __device__ __forceinline__ double Ft(double u, size_t i, int k) const {
+  // F(U, t) at point i of state vector arr for stage time k (0: t_n,
+  // 1: t_n + h/2, 2: t_n + h): the reaction, plus the caller's forcing G(t)
+  // (source and Dirichlet boundary terms) in a forced step; with several
+  // species the Lotka-Volterra reaction of the point's species, which reads
+  // every species at the node (eq. 3.1 with u in R^m).
+  __device__ __forceinline__ double Ft(gptr<const double> arr, size_t i, int k) const {
+    const double u = arr[i];
+    if (P.species > 1) {
+      // species s of the point, and the same node in species 0
+      const int s = (int)(i / sp_stride);
+      const size_t base = i - (size_t)s * sp_stride;
+      double acc = P.sa[s];
+      for (int j = 0; j < P.species; ++j) acc -= P.sb[s * MAX_SPECIES + j] * arr[base + (size_t)j * sp_stride];
+      return u * acc;
+    }
     return P.forced ? react(u) + V(V_FG0 + k)[i] : react(u);
   }
 
@@ -1306,32 +1318,32 @@ struct Engine {
         p = 1;
         if (mode == JOB_ETD3RK && stage == 1) {
           return pointwise(24.0, [&](size_t i, bool comp) {
-            B1[i] = comp ? h * (2.0 * Ft(Aa[i], i, 1) - Ft(X[i], i, 0)) : 0.0;
+            B1[i] = comp ? h * (2.0 * Ft(Aa, i, 1) - Ft(X, i, 0)) : 0.0;
           });
         }
         t = 0.5 * h;
         if (stage == 0)
-          return pointwise(16.0, [&](size_t i, bool comp) { B1[i] = comp ? 0.5 * h * Ft(X[i], i, 0) : 0.0; });
+          return pointwise(16.0, [&](size_t i, bool comp) { B1[i] = comp ? 0.5 * h * Ft(X, i, 0) : 0.0; });
         if (stage == 1)
-          return pointwise(16.0, [&](size_t i, bool comp) { B1[i] = comp ? 0.5 * h * Ft(Aa[i], i, 1) : 0.0; });
+          return pointwise(16.0, [&](size_t i, bool comp) { B1[i] = comp ? 0.5 * h * Ft(Aa, i, 1) : 0.0; });
         b0 = V_A;   // ETD4RK c starts from a
         return pointwise(24.0, [&](size_t i, bool comp) {
-          B1[i] = comp ? 0.5 * h * (2.0 * Ft(AB[i], i, 1) - Ft(X[i], i, 0)) : 0.0;
+          B1[i] = comp ? 0.5 * h * (2.0 * Ft(AB, i, 1) - Ft(X, i, 0)) : 0.0;
         });
       }
       p = 3;
       if (mode == JOB_ETD3RK) {
         return pointwise(48.0, [&](size_t i, bool comp) {
-          const double fn = comp ? Ft(X[i], i, 0) : 0.0, fa = comp ? Ft(Aa[i], i, 1) : 0.0;
-          const double fb = comp ? Ft(U[i], i, 2) : 0.0;
+          const double fn = comp ? Ft(X, i, 0) : 0.0, fa = comp ? Ft(Aa, i, 1) : 0.0;
+          const double fb = comp ? Ft(U, i, 2) : 0.0;
           B1[i] = h * fn;
           B2[i] = h * (-3.0 * fn + 4.0 * fa - fb);
           B3[i] = 2.0 * h * (2.0 * fn - 4.0 * fa + 2.0 * fb);
         });
       }
       return pointwise(56.0, [&](size_t i, bool comp) {
-        const double fn = comp ? Ft(X[i], i, 0) : 0.0, fab = comp ? Ft(Aa[i], i, 1) + Ft(AB[i], i, 1) : 0.0;
-        const double fc = comp ? Ft(U[i], i, 2) : 0.0;
+        const double fn = comp ? Ft(X, i, 0) : 0.0, fab = comp ? Ft(Aa, i, 1) + Ft(AB, i, 1) : 0.0;
+        const double fc = comp ? Ft(U, i, 2) : 0.0;
         B1[i] = h * fn;
         B2[i] = h * (-3.0 * fn + 2.0 * fab - fc);
         B3[i] = 2.0 * h * (2.0 * fn - 2.0 * fab + 2.0 * fc);
@@ -1345,7 +1357,7 @@ struct Engine {
       const bool first = P.first != 0;
       p = first ? 1 : 2;
       return pointwise(first ? 24.0 : 40.0, [&](size_t i, bool comp) {
-        const double fn = comp ? Ft(X[i], i, 0) : 0.0;
+        const double fn = comp ? Ft(X, i, 0) : 0.0;
         B1[i] = h * fn;
         if (!first) B2[i] = h * (fn - (comp ? Gw[i] : 0.0));
         Gw[i] = fn;
@@ -1354,13 +1366,13 @@ struct Engine {
     if (stage == 0) {
       // ETD1 / first ETD2RK stage: b_0 = U_n, b_1 = h F(U_n)
       p = 1;
-      return pointwise(16.0, [&](size_t i, bool comp) { B1[i] = comp ? h * Ft(X[i], i, 0) : 0.0; });
+      return pointwise(16.0, [&](size_t i, bool comp) { B1[i] = comp ? h * Ft(X, i, 0) : 0.0; });
     }
     // ETD2RK final stage: b_0 = U_n, b_1 = h F(U_n), b_2 = h (F(a) - F(U_n)),
     // a = the first stage (in V_U, overwritten once b_2 is formed)
     p = 2;
     return pointwise(24.0, [&](size_t i, bool comp) {
-      B2[i] = comp ? h * (Ft(U[i], i, 2) - Ft(X[i], i, 0)) : 0.0;
+      B2[i] = comp ? h * (Ft(U, i, 2) - Ft(X, i, 0)) : 0.0;
     });
   }
 
@@ -1463,6 +1475,7 @@ __device__ __forceinline__ void krylov_body(const KrylovDev& P, int lb, int G, C
   e.failed = false;
   e.iu = V_U;
   e.bpu = 0.0;
+  e.sp_stride = (size_t)(e.nact / (P.species > 1 ? P.species : 1)) * TILE_PTS;
   __syncthreads();
   e.run();
   __syncthreads();

@@ -82,6 +82,10 @@ hipError_t launch_geometry(GeomBatch& gb, const int* radii, hipStream_t s);
 // After launch_geometry of a one-instance table whose beta_face, vcoef and
 // tap arrays are set: the variable-beta coefficients and boundary taps.
 hipError_t launch_geometry_var(GeomBatch& gb, hipStream_t s);
+// After launch_geometry of a one-instance table: repeat the active tiles for
+// m species (the face-neighbour slots of copy s point into copy s); the
+// Krylov tile and unknown counts go to counters[5] and [6].
+hipError_t launch_replicate_species(GeomBatch& gb, int m, hipStream_t s);
 // out (box) = src + sum over the taps of coef * ub[tap_off[p] + k] at the
 // computational points (src may be NULL), 0 elsewhere.
 hipError_t launch_forcing(const BoxHost& b, const int* tile_map, const uint64_t* comp_bits, const int* tap_n,
