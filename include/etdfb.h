@@ -382,6 +382,29 @@ int etd_batch_autotune(etd_batch* batch, int32_t scheme, double h, double* const
 int etd_batch_profile_enable(etd_batch* batch, int32_t enable);
 int etd_batch_profile_read(etd_batch* batch, etd_profile* out, int32_t reset);
 
+/* ------------------------------------------------ allocation-free entry
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * phi_combination_apply without a context.  out = sum_{k=0}^{p} phi_k(t A) b_k
+ * for the operator of the domain rho < 0 on `grid` with the constant beta
+ * (the same kernels and arguments as etd_geometry_build followed by
+ * phi_combination_apply; opts may be NULL for the defaults).  Every buffer
+ * the kernels use lives in one static device array of
+ * ETD_STATIC_SCRATCH_BYTES per GPU, held until the process ends; grids of at
+ * most ETD_STATIC_MAX_TILES tiles (2D 32 x 8, 3D 16 x 4 x 4 nodes each, e.g.
+ * 128 x 128 or 32 x 32 x 16 nodes) fit, larger ones return ETD_ERR_INVALID
+ * before any device work.  Calls no allocating routine; the caller passes
+ * inputs and outputs (device box arrays as for phi_combination_apply).
+ * Synchronises the stream (twice: after the geometry, and at the end) and
+ * returns the first device error of the call.  All calls on one GPU share
+ * its array: calls that overlap on one GPU (several host threads or
+ * streams) race and must not be made. */
+#define ETD_STATIC_MAX_TILES 64
+#define ETD_STATIC_SCRATCH_BYTES (12u << 20)
+int phi_combination_apply_static(const etd_grid* grid, double beta, const double* rho, double t, int32_t p,
+                                 const double* const* b, double* out, const etd_krylov_opts* opts,
+                                 void* hip_stream);
+
 /* Human-readable name of a status code (static string). */
 const char* etd_status_string(int status);
 

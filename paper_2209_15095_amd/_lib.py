@@ -20,6 +20,9 @@ ETD_ERR_BARRIER = -7
 ETD_ERR_NO_GEOMETRY = -8
 ETD_ERR_FRONT = -9
 
+ETD_STATIC_MAX_TILES = 64
+ETD_STATIC_SCRATCH_BYTES = 12 << 20
+
 ETD_SCHEME_ETD1 = 1
 ETD_SCHEME_ETD2RK = 2
 ETD_SCHEME_ETD3RK = 3
@@ -100,6 +103,9 @@ SIGNATURES = {
     "etd_ctx_profile_enable": (C.c_int, [C.c_void_p, C.c_int32]),
     "etd_ctx_profile_read": (C.c_int, [C.c_void_p, C.POINTER(EtdProfile), C.c_int32]),
     "etd_status_string": (C.c_char_p, [C.c_int]),
+    "phi_combination_apply_static": (C.c_int, [C.POINTER(EtdGrid), C.c_double, C.c_void_p, C.c_double, C.c_int32,
+                                               C.POINTER(C.c_void_p), C.c_void_p, C.POINTER(EtdKrylovOpts),
+                                               C.c_void_p]),
     "etd_batch_create": (C.c_int, [C.c_int32, C.POINTER(EtdGrid), C.POINTER(EtdPhysics), C.POINTER(EtdKrylovOpts),
                                    C.c_void_p, C.POINTER(C.c_void_p)]),
     "etd_batch_destroy": (C.c_int, [C.c_void_p]),

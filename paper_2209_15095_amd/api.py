@@ -390,6 +390,27 @@ class Batch:
         return pr.as_dict()
 
 
+def phi_combination_apply_static(grid, beta: float, rho: torch.Tensor, t: float, bs, out: torch.Tensor,
+                                 tol=1e-10, m_min=8, m_max=64, m_step=4, max_substeps=64):
+    """out = sum_k phi_k(t A) b_k without a context (phi_combination_apply_static):
+    no device memory is allocated by the call (out must be given)."""
+    lib = L.load()
+    g = _grid_struct(grid.dim, grid.n, grid.lo, grid.hi)
+    shape = tuple(reversed([int(x) for x in grid.n[: grid.dim]]))
+    for name, tt in [("rho", rho), ("out", out)] + [(f"b[{i}]", b) for i, b in enumerate(bs)]:
+        if not isinstance(tt, torch.Tensor) or tt.dtype != torch.float64 or not tt.is_cuda:
+            raise TypeError(f"{name}: expected a float64 CUDA tensor")
+        if tuple(tt.shape) != shape or not tt.is_contiguous():
+            raise ValueError(f"{name}: expected a contiguous tensor of shape {shape}")
+    op = L.EtdKrylovOpts(float(tol), int(m_min), int(m_max), int(m_step), int(max_substeps))
+    arr = (C.c_void_p * len(bs))(*[_ptr(b) for b in bs])
+    s = torch.cuda.current_stream()
+    L.check(lib.phi_combination_apply_static(C.byref(g), float(beta), C.c_void_p(_ptr(rho)), float(t), len(bs) - 1,
+                                             arr, C.c_void_p(_ptr(out)), C.byref(op), C.c_void_p(s.cuda_stream)),
+            "phi_combination_apply_static")
+    return out
+
+
 class ETDSolve(torch.autograd.Function):
     """u_T = ETD2RK^steps(u0) on a frozen domain, differentiable in u0 and beta.
 

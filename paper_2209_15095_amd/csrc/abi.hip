@@ -6,6 +6,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <mutex>
 #include <vector>
 
 #include "../../include/etdfb.h"
@@ -1430,3 +1431,218 @@ int etd_batch_profile_read(etd_batch* B, etd_profile* out, int32_t reset) {
 }
 
 }  // extern "C"
+
+// ------------------------------------------------- allocation-free entry
+//
+// phi_combination_apply_static: the context's buffers (workspace vectors,
+// geometry tables, barrier flags, Krylov state, counters) all carved from
+// one file-scope device array.  Its device address is taken once per device
+// with hipGetSymbolAddress; host code never uses the array's name otherwise.
+
+namespace {
+
+constexpr int ST_TILES = ETD_STATIC_MAX_TILES;              // box tiles at most
+constexpr size_t ST_LD = (size_t)ST_TILES * TILE_PTS;        // doubles per vector
+constexpr int ST_GMAX = (ST_TILES + KTILES - 1) / KTILES;   // blocks of the persistent launch at most
+
+// Byte offsets of the carved buffers (256-byte aligned).
+struct StaticLayout {
+  size_t ws, cdiag, comp_bits, irr_bits, nbr, slot_tile, tile_map, tile_flag, tile_vb, band_tmp, band_list, mask,
+      counters, part, flags, bar, st, tab, pre, cnt, total;
+};
+
+constexpr size_t al256(size_t x) { return (x + 255) / 256 * 256; }
+
+constexpr StaticLayout static_layout() {
+  StaticLayout L{};
+  size_t o = 0;
+  auto take = [&o](size_t bytes) { const size_t at = o; o = al256(o + bytes); return at; };
+  L.ws = take(sizeof(double) * ST_LD * NVEC);
+  L.cdiag = take(sizeof(double) * ST_LD);
+  L.comp_bits = take(sizeof(uint64_t) * 4 * ST_TILES);
+  L.irr_bits = take(sizeof(uint64_t) * 4 * ST_TILES);
+  L.nbr = take(sizeof(int) * NBR_STRIDE * ST_TILES);
+  L.slot_tile = take(sizeof(int) * ST_TILES);
+  L.tile_map = take(sizeof(int) * ST_TILES);
+  L.tile_flag = take(sizeof(int) * ST_TILES);
+  L.tile_vb = take(sizeof(int) * ST_TILES);
+  L.band_tmp = take(sizeof(int) * 2 * ST_TILES);
+  L.band_list = take(sizeof(int) * LS_NLIST * ST_TILES);
+  L.mask = take(ST_LD);
+  L.counters = take(sizeof(int) * NCOUNTERS);
+  L.part = take(sizeof(double) * 2 * ST_GMAX * PART_STRIDE);
+  L.flags = take(sizeof(unsigned) * ST_GMAX);
+  L.bar = take(sizeof(BarrierDev));
+  L.st = take(sizeof(KrylovStateDev));
+  L.tab = take(sizeof(GeomInst));
+  L.pre = take(sizeof(int) * GEOM_NPRE * 2);
+  L.cnt = take(sizeof(int) * NCOUNTERS);
+  L.total = o;
+  return L;
+}
+
+constexpr StaticLayout SL = static_layout();
+static_assert(SL.total <= ETD_STATIC_SCRATCH_BYTES, "the carved buffers exceed the static scratch array");
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[ETD_STATIC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int ST_MAX_DEVICES = 64;
+std::mutex g_static_mu;
+void* g_static_ptr[ST_MAX_DEVICES] = {};   // device address of `scratch` per device
+int g_static_grid[ST_MAX_DEVICES] = {};    // co-resident blocks of the Krylov kernel per device
+
+// Address of this device's scratch array (device current), taken once.
+int static_scratch(int dev, char** out, int* max_grid) {
+  if (dev < 0 || dev >= ST_MAX_DEVICES) return ETD_ERR_NO_DEVICE;
+  std::lock_guard<std::mutex> lock(g_static_mu);
+  if (!g_static_ptr[dev]) {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return ETD_ERR_HIP;
+    if (strncmp(prop.gcnArchName, "gfx950", 6) != 0) return ETD_ERR_NO_DEVICE;
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return ETD_ERR_HIP;
+    g_static_grid[dev] = krylov_max_blocks_per_cu(2, 1) * prop.multiProcessorCount;
+    g_static_ptr[dev] = p;
+  }
+  *out = (char*)g_static_ptr[dev];
+  *max_grid = g_static_grid[dev];
+  return ETD_OK;
+}
+
+// Fresh state for a call: counters and the barrier cleared, the adaptive
+// Krylov state at its defaults (a kernel, no memset).
+__global__ void static_init_kernel(int* counters, BarrierDev* bar, KrylovStateDev* st, int m_min) {
+  const int i = threadIdx.x;
+  if (i < NCOUNTERS) counters[i] = 0;
+  if (i == 0) {
+    *bar = BarrierDev{};
+    KrylovStateDev s{};
+    for (int k = 0; k <= PMAX; ++k) {
+      s.m_guess[k] = m_min;
+      s.tau_frac[k] = 1.0;
+    }
+    *st = s;
+  }
+}
+
+}  // namespace
+
+extern "C" int phi_combination_apply_static(const etd_grid* grid, double beta, const double* rho, double t,
+                                            int32_t p, const double* const* b, double* out,
+                                            const etd_krylov_opts* opts, void* hip_stream) {
+  if (!grid || !rho || !b || !out || p < 0 || p > PMAX || !(t >= 0.0) || !isfinite(t)) return ETD_ERR_INVALID;
+  if (!(beta > 0.0) || !isfinite(beta)) return ETD_ERR_INVALID;
+  for (int k = 0; k <= p; ++k)
+    if (!b[k] || b[k] == out) return ETD_ERR_INVALID;
+  if (grid->dim != 2 && grid->dim != 3) return ETD_ERR_INVALID;
+  for (int d = 0; d < grid->dim; ++d)
+    if (grid->n[d] < 5 || !(grid->hi[d] > grid->lo[d])) return ETD_ERR_INVALID;
+  const double dx = (grid->hi[0] - grid->lo[0]) / (grid->n[0] - 1);
+  for (int d = 1; d < grid->dim; ++d)
+    if (fabs((grid->hi[d] - grid->lo[d]) / (grid->n[d] - 1) - dx) > 1e-12 * dx) return ETD_ERR_INVALID;
+  etd_krylov_opts o{1e-10, 8, 64, 4, 64};
+  if (opts) o = *opts;
+  if (!(o.tol > 0.0) || o.m_min < 1 || o.m_max > MMAX_LIMIT || o.m_min > o.m_max || o.m_step < 1 ||
+      o.max_substeps < 1)
+    return ETD_ERR_INVALID;
+  // the box and its tiles
+  etd_ctx c;
+  BoxHost& bx = c.box;
+  bx.dim = grid->dim;
+  bx.nx = grid->n[0];
+  bx.ny = grid->n[1];
+  bx.nz = grid->dim == 3 ? grid->n[2] : 1;
+  if (bx.dim == 2) { bx.tx = 32; bx.ty = 8; bx.tz = 1; } else { bx.tx = 16; bx.ty = 4; bx.tz = 4; }
+  bx.ntx = (bx.nx + bx.tx - 1) / bx.tx;
+  bx.nty = (bx.ny + bx.ty - 1) / bx.ty;
+  bx.ntz = (bx.nz + bx.tz - 1) / bx.tz;
+  for (int d = 0; d < 3; ++d) bx.lo[d] = d < grid->dim ? grid->lo[d] : 0.0;
+  bx.dx = dx;
+  if ((long)bx.ntx * bx.nty * bx.ntz > ST_TILES) return ETD_ERR_INVALID;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return ETD_ERR_NO_DEVICE;
+  char* base = nullptr;
+  int max_grid = 0;
+  int r = static_scratch(dev, &base, &max_grid);
+  if (r) return r;
+  // a context whose buffers are the carved pieces of the array
+  c.device = dev;
+  c.stream = (hipStream_t)hip_stream;
+  c.grid = *grid;
+  c.phys = etd_physics{beta, 0.0, 0.0, 0.0};
+  c.opts = o;
+  c.ntiles = bx.ntx * bx.nty * bx.ntz;
+  c.nodes = (size_t)bx.nx * bx.ny * bx.nz;
+  c.ld = ST_LD;
+  c.ws = (double*)(base + SL.ws);
+  c.cdiag = (double*)(base + SL.cdiag);
+  c.comp_bits = (uint64_t*)(base + SL.comp_bits);
+  c.irr_bits = (uint64_t*)(base + SL.irr_bits);
+  c.nbr = (int*)(base + SL.nbr);
+  c.slot_tile = (int*)(base + SL.slot_tile);
+  c.tile_map = (int*)(base + SL.tile_map);
+  c.tile_flag = (int*)(base + SL.tile_flag);
+  c.tile_vb = (int*)(base + SL.tile_vb);
+  c.band_tmp = (int*)(base + SL.band_tmp);
+  c.band_list = (int*)(base + SL.band_list);
+  c.mask = (uint8_t*)(base + SL.mask);
+  c.counters = (int*)(base + SL.counters);
+  c.part = (double*)(base + SL.part);
+  c.flags = (unsigned*)(base + SL.flags);
+  c.bar = (BarrierDev*)(base + SL.bar);
+  c.st = (KrylovStateDev*)(base + SL.st);
+  c.max_grid = max_grid < ST_GMAX ? max_grid : ST_GMAX;
+  // host-side mirrors on this call's stack (pageable: every copy into or
+  // out of them is complete at the synchronisations below)
+  int h_counters[NCOUNTERS] = {};
+  GeomInst tab{};
+  int h_pre[GEOM_NPRE * 2] = {};
+  int h_cnt[NCOUNTERS] = {};
+  c.h_counters = h_counters;
+  c.gb.count = 1;
+  c.gb.ncnt = NCOUNTERS;
+  c.gb.h_tab = &tab;
+  c.gb.d_tab = (GeomInst*)(base + SL.tab);
+  c.gb.h_pre = h_pre;
+  c.gb.d_pre = (int*)(base + SL.pre);
+  c.gb.h_cnt = h_cnt;
+  c.gb.d_cnt = (int*)(base + SL.cnt);
+  tab = geom_inst(&c);
+  int result = ETD_OK;
+  do {
+    // block prefixes: computed on the host, copied into the array
+    {
+      const int per[GEOM_NPRE] = {(int)((c.nodes + 255) / 256), (c.ntiles + 255) / 256, c.ntiles};
+      for (int q = 0; q < GEOM_NPRE; ++q) {
+        h_pre[q * 2] = 0;
+        h_pre[q * 2 + 1] = per[q];
+        c.gb.blocks[q] = per[q];
+      }
+      if (hipMemcpyAsync(c.gb.d_pre, h_pre, sizeof(h_pre), hipMemcpyHostToDevice, c.stream) != hipSuccess) {
+        result = ETD_ERR_HIP;
+        break;
+      }
+    }
+    hipLaunchKernelGGL(static_init_kernel, dim3(1), dim3(64), 0, c.stream, c.counters, c.bar, c.st, o.m_min);
+    if (hipGetLastError() != hipSuccess) { result = ETD_ERR_HIP; break; }
+    if ((result = geometry_enqueue(&c, rho))) break;
+    if (hipStreamSynchronize(c.stream) != hipSuccess) { result = ETD_ERR_HIP; break; }
+    if ((result = geometry_finish(&c, h_cnt))) break;
+    for (int k = 0; k <= p && !result; ++k) result = gather_to(&c, b[k], V_B0 + k);
+    if (result) break;
+    KrylovDev P = krylov_params(&c, JOB_PHI);
+    P.p = p;
+    P.t = t;
+    if ((result = run_krylov(&c, P))) break;
+    if ((result = scatter_from(&c, V_U, out))) break;
+    result = latched_status(&c);
+  } while (false);
+  // nothing may still read the stack mirrors
+  if (hipStreamSynchronize(c.stream) != hipSuccess && result == ETD_OK) result = ETD_ERR_HIP;
+  c.h_counters = nullptr;
+  return result;
+}
