@@ -53,8 +53,21 @@ enum {
 
 /* ETD1 (Section 3.1), ETD2RK, ETD3RK and ETD4RK (Section 3.2; the phi_3 of
  * the paper's ETD3RK and ETD4RK formulas is 2 phi_3 in the standard
- * normalisation phi_k(0) = 1/k! used by phi_combination_apply). */
-enum { ETD_SCHEME_ETD1 = 1, ETD_SCHEME_ETD2RK = 2, ETD_SCHEME_ETD3RK = 3, ETD_SCHEME_ETD4RK = 4 };
+ * normalisation phi_k(0) = 1/k! used by phi_combination_apply).  The
+ * _SIMUL variants compute the same schemes with the simultaneous output of
+ * Section 3.3 (as in phipm_simul_iom2): the ODE y' = A y + F_n, y(0) = U_n
+ * is integrated once over h, its value at h/2 (stage a, from the Krylov
+ * basis of the substep that holds h/2) and at h (the phi_0, phi_1 part of
+ * the last stage) come from that one integration, and the other stages are
+ * combinations with b_0 = 0 added to those values. */
+enum {
+  ETD_SCHEME_ETD1 = 1,
+  ETD_SCHEME_ETD2RK = 2,
+  ETD_SCHEME_ETD3RK = 3,
+  ETD_SCHEME_ETD4RK = 4,
+  ETD_SCHEME_ETD3RK_SIMUL = 5,
+  ETD_SCHEME_ETD4RK_SIMUL = 6
+};
 
 /* Box grid: dim 2 or 3, n[d] nodes on [lo[d], hi[d]] per axis, equal spacing. */
 typedef struct {
@@ -222,6 +235,18 @@ int etd_operator_apply(etd_ctx* ctx, const double* v, double* out);
  * b_k.  stats: NULL, or receives the statistics (synchronises). */
 int phi_combination_apply(etd_ctx* ctx, double t, int32_t p, const double* const* b, double* out,
                           etd_stats* stats);
+
+/* The combination at two times from one integration (Section 3.3, the
+ * simultaneous output of phipm_simul_iom2): out as phi_combination_apply
+ * at t, and out_mid = y(t_mid) of the same ODE y' = A y + sum_k
+ * s^{k-1}/(k-1)! b_k / t^k, y(0) = b_0, i.e.
+ * sum_k phi_k(t_mid A) (t_mid/t)^k b_k, for 0 < t_mid <= t.  out_mid comes
+ * from the Krylov basis of the substep that holds t_mid (one more small
+ * exponential and one combine pass, its error estimate held to the same
+ * tolerance).  out, out_mid: distinct device box arrays, not aliasing any
+ * b_k. */
+int phi_combination_apply_multi(etd_ctx* ctx, double t, int32_t p, const double* const* b, double t_mid,
+                                double* out_mid, double* out, etd_stats* stats);
 
 /* Steps 1 and 2a of the free-boundary algorithm (Section 4.3): extend u
  * from the computational points of rho by quadratic normal extrapolation,

@@ -204,6 +204,14 @@ def phi_combination_krylov(A, t: float, bs, m: int = 40, rtol: float = 1e-13,
         prev = cur
 
 
+def phi_combination_at(A, t: float, bs, s: float, method: str = "auto"):
+    """Value at time s of the ODE of Section 3.3 whose time-t value is
+    sum_k phi_k(tA) b_k: y' = A y + sum_{k>=1} tau^{k-1}/(k-1)! b_k / t^k,
+    y(0) = b_0, so y(s) = sum_k phi_k(sA) (s/t)^k b_k (intermediate output of
+    one integration, as the simultaneous evaluation of Section 3.3 uses)."""
+    return phi_combination(A, s, [(s / t) ** k * np.asarray(b) for k, b in enumerate(bs)], method)
+
+
 def phi_combination(A, t: float, bs, method: str = "auto"):
     """Dispatch: dense augmented expm for small N, Krylov otherwise."""
     n = np.asarray(bs[0]).shape[0]

@@ -27,6 +27,8 @@ ETD_SCHEME_ETD1 = 1
 ETD_SCHEME_ETD2RK = 2
 ETD_SCHEME_ETD3RK = 3
 ETD_SCHEME_ETD4RK = 4
+ETD_SCHEME_ETD3RK_SIMUL = 5
+ETD_SCHEME_ETD4RK_SIMUL = 6
 
 
 class EtdGrid(C.Structure):
@@ -91,6 +93,8 @@ SIGNATURES = {
                                   C.POINTER(EtdStats)]),
     "phi_combination_apply": (C.c_int, [C.c_void_p, C.c_double, C.c_int32, C.POINTER(C.c_void_p), C.c_void_p,
                                         C.POINTER(EtdStats)]),
+    "phi_combination_apply_multi": (C.c_int, [C.c_void_p, C.c_double, C.c_int32, C.POINTER(C.c_void_p), C.c_double,
+                                              C.c_void_p, C.c_void_p, C.POINTER(EtdStats)]),
     "levelset_advance": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_int32]),
     "etd_step": (C.c_int, [C.c_void_p, C.c_int32, C.c_double, C.c_void_p, C.c_void_p, C.c_int32,
                            C.POINTER(EtdStats)]),

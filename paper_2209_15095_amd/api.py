@@ -19,7 +19,8 @@ def _ptr(t: torch.Tensor) -> int:
 
 # ETD schemes of the boundary (Section 3)
 SCHEMES = {"etd1": L.ETD_SCHEME_ETD1, "etd2rk": L.ETD_SCHEME_ETD2RK, "etd3rk": L.ETD_SCHEME_ETD3RK,
-           "etd4rk": L.ETD_SCHEME_ETD4RK}
+           "etd4rk": L.ETD_SCHEME_ETD4RK, "etd3rk_simul": L.ETD_SCHEME_ETD3RK_SIMUL,
+           "etd4rk_simul": L.ETD_SCHEME_ETD4RK_SIMUL}
 
 
 class Context:
@@ -175,6 +176,23 @@ class Context:
                                                C.byref(st) if st is not None else None),
                 "phi_combination_apply")
         return (out, st.as_dict()) if stats else out
+
+    def phi_combination_apply_multi(self, t: float, bs, t_mid: float, out=None, out_mid=None, stats=False):
+        """(out at t, out_mid at t_mid) of the combination's ODE, from one integration."""
+        for i, b in enumerate(bs):
+            self._check_box(b, f"b[{i}]")
+        out = torch.empty_like(bs[0]) if out is None else out
+        out_mid = torch.empty_like(bs[0]) if out_mid is None else out_mid
+        self._check_box(out, "out")
+        self._check_box(out_mid, "out_mid")
+        self._sync_stream()
+        arr = (C.c_void_p * len(bs))(*[_ptr(b) for b in bs])
+        st = L.EtdStats() if stats else None
+        L.check(self.lib.phi_combination_apply_multi(self.handle, float(t), len(bs) - 1, arr, float(t_mid),
+                                                     C.c_void_p(_ptr(out_mid)), C.c_void_p(_ptr(out)),
+                                                     C.byref(st) if st is not None else None),
+                "phi_combination_apply_multi")
+        return (out, out_mid, st.as_dict()) if stats else (out, out_mid)
 
     def levelset_advance(self, rho: torch.Tensor, u: torch.Tensor, dt: float, reinit: bool):
         self._check_box(rho, "rho")

@@ -178,6 +178,8 @@ int job_of(int scheme) {
     case ETD_SCHEME_ETD1: return JOB_ETD1;
     case ETD_SCHEME_ETD3RK: return JOB_ETD3RK;
     case ETD_SCHEME_ETD4RK: return JOB_ETD4RK;
+    case ETD_SCHEME_ETD3RK_SIMUL: return JOB_ETD3RK_SIMUL;
+    case ETD_SCHEME_ETD4RK_SIMUL: return JOB_ETD4RK_SIMUL;
     default: return JOB_ETD2RK;
   }
 }
@@ -574,7 +576,7 @@ int etd_ctx_create_species(const etd_grid* grid, const etd_physics* phys, const 
 
 int etd_step_species(etd_ctx* c, int32_t scheme, double h, double* const* u, etd_stats* stats) {
   if (!c || !u || !(h >= 0.0) || !isfinite(h)) return ETD_ERR_INVALID;
-  if (scheme < ETD_SCHEME_ETD1 || scheme > ETD_SCHEME_ETD4RK) return ETD_ERR_INVALID;
+  if (scheme < ETD_SCHEME_ETD1 || scheme > ETD_SCHEME_ETD4RK_SIMUL) return ETD_ERR_INVALID;
   for (int s = 0; s < c->species; ++s) {
     if (!u[s]) return ETD_ERR_INVALID;
     for (int j = 0; j < s; ++j)
@@ -738,6 +740,35 @@ int phi_combination_apply(etd_ctx* c, double t, int32_t p, const double* const* 
   return ETD_OK;
 }
 
+int phi_combination_apply_multi(etd_ctx* c, double t, int32_t p, const double* const* b, double t_mid,
+                                double* out_mid, double* out, etd_stats* stats) {
+  if (!c || !b || !out || !out_mid || out == out_mid || p < 0 || p > PMAX || !(t > 0.0) || !isfinite(t) ||
+      !(t_mid > 0.0) || !(t_mid <= t) || c->species > 1)
+    return ETD_ERR_INVALID;
+  for (int k = 0; k <= p; ++k)
+    if (!b[k] || b[k] == out || b[k] == out_mid) return ETD_ERR_INVALID;
+  if (!c->have_geometry) return ETD_ERR_NO_GEOMETRY;
+  for (int k = 0; k <= p; ++k) {
+    int r = gather_to(c, b[k], V_B0 + k);
+    if (r) return r;
+  }
+  KrylovDev P = krylov_params(c, JOB_PHI);
+  P.p = p;
+  P.t = t;
+  P.t_mid = t_mid;
+  int r = run_krylov(c, P);
+  if (r) return r;
+  if ((r = scatter_from(c, V_U, out))) return r;
+  if ((r = scatter_from(c, V_F, out_mid))) return r;
+  if (stats) {
+    r = fill_stats(c, stats);
+    if (r) return r;
+    int st = latched_status(c);
+    if (st) return st;
+  }
+  return ETD_OK;
+}
+
 int levelset_advance(etd_ctx* c, double* rho, double* u, double dt, int32_t reinit) {
   if (!c || !rho || !u || !(dt >= 0.0) || !isfinite(dt)) return ETD_ERR_INVALID;
   if (c->var_mode || c->species > 1) return ETD_ERR_INVALID;
@@ -758,7 +789,7 @@ int levelset_advance(etd_ctx* c, double* rho, double* u, double dt, int32_t rein
 int etd_step(etd_ctx* c, int32_t scheme, double h, double* u, double* rho, int32_t reinit,
              etd_stats* stats) {
   if (!c || !u || !(h >= 0.0) || !isfinite(h) || c->species > 1) return ETD_ERR_INVALID;
-  if (scheme < ETD_SCHEME_ETD1 || scheme > ETD_SCHEME_ETD4RK) return ETD_ERR_INVALID;
+  if (scheme < ETD_SCHEME_ETD1 || scheme > ETD_SCHEME_ETD4RK_SIMUL) return ETD_ERR_INVALID;
   if (rho) {
     int r = levelset_advance(c, rho, u, h, reinit);
     if (r) return r;
@@ -783,7 +814,7 @@ int etd_step(etd_ctx* c, int32_t scheme, double h, double* u, double* rho, int32
 
 int etd_step_forced(etd_ctx* c, int32_t scheme, double h, double* u, const double* const* g, etd_stats* stats) {
   if (!c || !u || !g || !(h >= 0.0) || !isfinite(h) || c->species > 1) return ETD_ERR_INVALID;
-  if (scheme < ETD_SCHEME_ETD1 || scheme > ETD_SCHEME_ETD4RK) return ETD_ERR_INVALID;
+  if (scheme < ETD_SCHEME_ETD1 || scheme > ETD_SCHEME_ETD4RK_SIMUL) return ETD_ERR_INVALID;
   // the stage times each scheme evaluates F at: 0 = t_n, 1 = t_n + h/2, 2 = t_n + h
   const bool need[3] = {true, scheme >= ETD_SCHEME_ETD3RK, scheme >= ETD_SCHEME_ETD2RK};
   for (int k = 0; k < 3; ++k) {
@@ -1210,7 +1241,7 @@ static int batch_stats(etd_batch* B, etd_stats* stats) {
 int etd_batch_step(etd_batch* B, int32_t scheme, double h, double* const* u, double* const* rho,
                    int32_t reinit, etd_stats* stats) {
   if (!B || !u || !(h >= 0.0) || !isfinite(h)) return ETD_ERR_INVALID;
-  if (scheme < ETD_SCHEME_ETD1 || scheme > ETD_SCHEME_ETD4RK) return ETD_ERR_INVALID;
+  if (scheme < ETD_SCHEME_ETD1 || scheme > ETD_SCHEME_ETD4RK_SIMUL) return ETD_ERR_INVALID;
   for (int i = 0; i < B->count; ++i) {
     if (!u[i]) return ETD_ERR_INVALID;
     if (rho && !rho[i]) return ETD_ERR_INVALID;
@@ -1270,7 +1301,7 @@ int etd_batch_multistep_step(etd_batch* B, double h, double* const* u, double* c
 
 int etd_batch_graph_steps(etd_batch* B, int32_t scheme, double h, double* const* u, int32_t nsteps) {
   if (!B || !u || nsteps < 0 || !(h >= 0.0) || !isfinite(h)) return ETD_ERR_INVALID;
-  if (scheme < ETD_SCHEME_ETD1 || scheme > ETD_SCHEME_ETD4RK) return ETD_ERR_INVALID;
+  if (scheme < ETD_SCHEME_ETD1 || scheme > ETD_SCHEME_ETD4RK_SIMUL) return ETD_ERR_INVALID;
   for (int i = 0; i < B->count; ++i)
     if (!u[i]) return ETD_ERR_INVALID;
   for (etd_ctx* c : B->inst)
@@ -1292,7 +1323,7 @@ int etd_batch_graph_steps(etd_batch* B, int32_t scheme, double h, double* const*
 int etd_batch_autotune(etd_batch* B, int32_t scheme, double h, double* const* u, int32_t trials,
                        int32_t* limit_out, double* ms_out) {
   if (!B || !u || trials < 1 || !(h >= 0.0) || !isfinite(h)) return ETD_ERR_INVALID;
-  if (scheme < ETD_SCHEME_ETD1 || scheme > ETD_SCHEME_ETD4RK) return ETD_ERR_INVALID;
+  if (scheme < ETD_SCHEME_ETD1 || scheme > ETD_SCHEME_ETD4RK_SIMUL) return ETD_ERR_INVALID;
   for (int i = 0; i < B->count; ++i)
     if (!u[i]) return ETD_ERR_INVALID;
   for (etd_ctx* c : B->inst)

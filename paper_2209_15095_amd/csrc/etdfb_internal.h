@@ -97,7 +97,9 @@ enum JobMode {
   JOB_ADJ_ETD2RK = 5,   // adjoint of one ETD2RK step: V_U = dL/dU_n from V_G, V_X0; *dbeta += dL/dbeta
   JOB_ETD3RK = 6,       // one ETD3RK step of V_X0
   JOB_ETD4RK = 7,       // one ETD4RK step of V_X0
-  JOB_ETD2 = 8          // one ETD2 multistep step of V_X0; F(U_{n-1}) in V_G, replaced by F(U_n)
+  JOB_ETD2 = 8,         // one ETD2 multistep step of V_X0; F(U_{n-1}) in V_G, replaced by F(U_n)
+  JOB_ETD3RK_SIMUL = 9, // ETD3RK with stage a and the first-stage value at h from one integration
+  JOB_ETD4RK_SIMUL = 10 // the same for ETD4RK
 };
 
 struct KrylovDev {
@@ -116,6 +118,7 @@ struct KrylovDev {
   int mode;
   int p;
   double t;                   // JOB_PHI: time t of phi_k(t A)
+  double t_mid;               // JOB_PHI: 0, or the intermediate output time (into V_F)
   double beta;                // JOB_ADJ_ETD2RK: beta (A = beta A_1)
   double* dbeta;              // JOB_ADJ_ETD2RK: device scalar, dL/dbeta accumulated
   double h;                   // ETD step

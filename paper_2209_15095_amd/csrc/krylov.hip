@@ -259,6 +259,8 @@ struct Engine {
   bool failed;
   int iu;   // vector holding u(t_j) = W_0 (V_U or V_T, ping-pong with the combine output)
   size_t sp_stride;   // index distance between the copies of one node in consecutive species
+  double st_tmid;     // intermediate output of the current stage's combination (0: none)
+  int st_midvec;      // and its vector
   // Algorithmic HBM bytes per unknown moved so far: what the method must read
   // and write per computational point (vectors only; neighbour re-reads,
   // masks and tile padding are not counted).
@@ -869,9 +871,9 @@ struct Engine {
     return finish<2>(acc, out);
   }
 
-  // out = sum_{k<p} tau^k/k! W_k + sum_i coef_i q_i into the buffer that is
-  // not iu; returns |out|^2 in nn.
-  __device__ __forceinline__ bool combine_pass(int p, int m, double tau, double& nn) {
+  // out = sum_{k<p} tau^k/k! W_k + sum_i coef_i q_i into vector out_vec
+  // (default: the buffer that is not iu); returns |out|^2 in nn.
+  __device__ __forceinline__ bool combine_pass(int p, int m, double tau, double& nn, int out_vec = -1) {
     double ck[PMAX];
     double f = 1.0, tp = 1.0;
 #pragma unroll
@@ -879,7 +881,7 @@ struct Engine {
       if (k > 0) { f *= k; tp *= tau; }
       ck[k] = tp / f;
     }
-    const int io = (iu == V_U) ? V_T : V_U;
+    const int io = out_vec >= 0 ? out_vec : ((iu == V_U) ? V_T : V_U);
     double acc[1] = {0.0};
     tiles([&](const Tile& t) {
       const bool comp = t.comp;
@@ -992,9 +994,16 @@ struct Engine {
   // V_U <- sum_{k=0}^{p} phi_k(tend A) b_k with b_0 in vector b0 (not
   // written) and b_k (k>=1) in V_B0 + k.  The substeps alternate between
   // V_U and V_T, starting with V_U, so a single substep needs no copy.
+  // With 0 < t_mid <= tend, also the solution of the same ODE at t_mid,
+  // y(t_mid) = sum_k phi_k(t_mid A) (t_mid/tend)^k b_k, into vector
+  // mid_vec: from the Krylov basis of the substep that contains t_mid
+  // (simultaneous output, no extra Lanczos passes: one more small
+  // exponential at s = t_mid - t_j and one combine pass; the error
+  // estimate at s must pass the same two tests).
   // Returns false on failure (status set).
-  __device__ __forceinline__ bool phi_comb(int p, double tend, int b0) {
+  __device__ __forceinline__ bool phi_comb(int p, double tend, int b0, double t_mid = 0.0, int mid_vec = -1) {
     iu = b0;
+    if (mid_vec < 0 || !(t_mid > 0.0)) t_mid = 0.0;
     if (tend == 0.0) {
       // phi_k(0) = 1/k!
       double f = 1.0;
@@ -1011,7 +1020,7 @@ struct Engine {
       });
       bpu += 8.0 * (p + 2);
       iu = V_U;
-      return barrier();
+      return barrier() && (t_mid == 0.0 || copy_pass(mid_vec, V_U));
     }
     const double tol = P.tol;
     double tj = 0.0;
@@ -1039,11 +1048,15 @@ struct Engine {
       }
       const double n0 = sqrt(nrm2[0]);
       const double unorm = sqrt(nrm2[1]);
+      // this substep holds t_mid strictly inside: the output at s = t_mid - t_j
+      const bool mid_in = t_mid > tj && t_mid < tj + tau - 1e-13 * tend;
       if (n0 == 0.0) {
         // W_p = 0: the Krylov term vanishes exactly.
         double nn;
+        if (mid_in && !combine_pass(p, 0, t_mid - tj, nn, mid_vec)) return false;
         if (!combine_pass(p, 0, tau, nn)) return false;
         iu = (iu == V_U) ? V_T : V_U;
+        if (t_mid > tj && !mid_in && t_mid <= tj + tau + 1e-13 * tend && !copy_pass(mid_vec, iu)) return false;
         tj += tau;
         ++nsub;
         continue;
@@ -1144,13 +1157,39 @@ struct Engine {
         double nn_out;
         if (!combine_pass(p, m, tau, nn_out)) return false;
         const double tol_out = tol * (tau / tend) * fmax(sqrt(nn_out), 1e-300);
-        if (err <= tol_out) {
-          accept = true;
-        } else {
+        if (err > tol_out) {
           if (!refine(err / tol_out)) return false;
+          continue;
         }
+        // (tau may have shrunk since the substep began)
+        if (t_mid > tj && t_mid < tj + tau - 1e-13 * tend) {
+          // the intermediate output from the same basis, with the same tests
+          const double tau_full = tau, err_full = err;
+          tau = t_mid - tj;
+          if (!estimate()) return false;
+          const double ratio_in = err / tol_loc;
+          double ratio_out = 0.0;
+          if (ratio_in <= 1.0) {
+            set_coef();
+            double nn_mid;
+            if (!combine_pass(p, m, tau, nn_mid, mid_vec)) return false;
+            ratio_out = err / (tol * (tau / tend) * fmax(sqrt(nn_mid), 1e-300));
+          }
+          tau = tau_full;
+          err = err_full;
+          const double ratio = fmax(ratio_in, ratio_out);
+          if (ratio > 1.0) {
+            if (!refine(ratio)) return false;
+            continue;
+          }
+        }
+        accept = true;
       }
       iu = (iu == V_U) ? V_T : V_U;
+      // t_mid at the end of this substep: the output is the substep's result
+      if (t_mid > tj && t_mid >= tj + tau - 1e-13 * tend && t_mid <= tj + tau + 1e-13 * tend &&
+          !copy_pass(mid_vec, iu))
+        return false;
       m_last = m;
       err_est = err;
       tj += tau;
@@ -1196,6 +1235,8 @@ struct Engine {
       case JOB_ETD2: return P.first ? 2 : 1;
       case JOB_ETD3RK: return 3;
       case JOB_ETD4RK: return 4;
+      case JOB_ETD3RK_SIMUL: return 3;
+      case JOB_ETD4RK_SIMUL: return 4;
       case JOB_ADJ_ETD2RK: return 6;
       default: return 1;
     }
@@ -1242,11 +1283,17 @@ struct Engine {
   // and dL/dbeta += (h/beta)(<g, A v_f> + <abar, A v_s>), from
   // d/dbeta phi_k(h beta A_1) = (h/beta) A (phi_k - k phi_{k+1})(hA).
   __device__ __forceinline__ bool assemble(int mode, int stage, int& p, double& t, int& b0) {
+    st_tmid = 0.0;
+    st_midvec = -1;
     if (mode == JOB_PHI) {
       // the gathered inputs are in place
       p = P.p;
       t = P.t;
       b0 = V_B0;
+      if (P.t_mid > 0.0) {
+        st_tmid = P.t_mid;
+        st_midvec = V_F;
+      }
       return true;
     }
     const double h = P.h;
@@ -1299,6 +1346,60 @@ struct Engine {
           p = 0;
           return pointwise(24.0, [&](size_t i, bool comp) { T0[i] = comp ? G[i] + AB[i] : 0.0; });
       }
+    }
+    if (mode == JOB_ETD3RK_SIMUL || mode == JOB_ETD4RK_SIMUL) {
+      // The same schemes with the ODE y' = A y + F_n, y(0) = U_n integrated
+      // once over h: its value at h/2 is stage a (simultaneous output from
+      // the same Krylov basis) and its value e at h is the phi_0, phi_1 part
+      // of the final combination; the remaining stages are combinations
+      // with b_0 = 0 added to e or a (V_S holds the zero vector, V_F keeps e):
+      //   ETD3RK: b = e + phi_1(hA) 2h (F(a) - F_n)
+      //   ETD4RK: b = a + phi_1(hA/2) (h/2) (F(a) - F_n);  c as before
+      //   final  = e + phi_2 h (...) + phi_3 2h (...)   (as in the standard form)
+      const bool four = mode == JOB_ETD4RK_SIMUL;
+      gptr<double> Zv = V(V_S);
+      if (stage == 0) {
+        p = 1;
+        st_tmid = 0.5 * h;
+        st_midvec = V_A;
+        return pointwise(16.0, [&](size_t i, bool comp) { B1[i] = comp ? h * Ft(X, i, 0) : 0.0; });
+      }
+      if (stage == 1) {
+        p = 1;
+        b0 = V_S;
+        const double sc = four ? 0.5 * h : 2.0 * h;
+        if (four) t = 0.5 * h;
+        return pointwise(24.0, [&](size_t i, bool comp) {
+          Zv[i] = 0.0;
+          B1[i] = comp ? sc * (Ft(Aa, i, 1) - Ft(X, i, 0)) : 0.0;
+        });
+      }
+      if (four && stage == 2) {
+        p = 1;
+        t = 0.5 * h;
+        b0 = V_A;
+        return pointwise(24.0, [&](size_t i, bool comp) {
+          B1[i] = comp ? 0.5 * h * (2.0 * Ft(AB, i, 1) - Ft(X, i, 0)) : 0.0;
+        });
+      }
+      p = 3;
+      b0 = V_S;
+      if (!four) {
+        return pointwise(48.0, [&](size_t i, bool comp) {
+          const double fn = comp ? Ft(X, i, 0) : 0.0, fa = comp ? Ft(Aa, i, 1) : 0.0;
+          const double fb = comp ? Ft(U, i, 2) : 0.0;
+          B1[i] = 0.0;
+          B2[i] = h * (-3.0 * fn + 4.0 * fa - fb);
+          B3[i] = 2.0 * h * (2.0 * fn - 4.0 * fa + 2.0 * fb);
+        });
+      }
+      return pointwise(56.0, [&](size_t i, bool comp) {
+        const double fn = comp ? Ft(X, i, 0) : 0.0, fab = comp ? Ft(Aa, i, 1) + Ft(AB, i, 1) : 0.0;
+        const double fc = comp ? Ft(U, i, 2) : 0.0;
+        B1[i] = 0.0;
+        B2[i] = h * (-3.0 * fn + 2.0 * fab - fc);
+        B3[i] = 2.0 * h * (2.0 * fn - 2.0 * fab + 2.0 * fc);
+      });
     }
     if (mode == JOB_ETD3RK || mode == JOB_ETD4RK) {
       // ETD3RK (F_n = F(U_n), stage results a, b (, c)):
@@ -1378,6 +1479,25 @@ struct Engine {
 
   // What a stage leaves behind once its combination is in V_U.
   __device__ __forceinline__ bool post(int mode, int stage, double& dsum) {
+    if (mode == JOB_ETD3RK_SIMUL || mode == JOB_ETD4RK_SIMUL) {
+      const bool four = mode == JOB_ETD4RK_SIMUL;
+      gptr<double> U = V(V_U);
+      gptr<double> E = V(V_F);
+      const int last = stages(mode) - 1;
+      if (stage == 0) return pointwise(16.0, [&](size_t i, bool comp) { E[i] = U[i]; });   // e
+      if (stage == 1 && !four) return pointwise(24.0, [&](size_t i, bool comp) { U[i] += E[i]; });   // b
+      if (stage == 1) {
+        gptr<const double> Aa = V(V_A);
+        gptr<double> AB = V(V_AB);
+        return pointwise(32.0, [&](size_t i, bool comp) {   // b = a + ..., kept for c and the final
+          const double b = U[i] + Aa[i];
+          U[i] = b;
+          AB[i] = b;
+        });
+      }
+      if (stage == last) return pointwise(24.0, [&](size_t i, bool comp) { U[i] += E[i]; });   // U_{n+1}
+      return true;
+    }
     if (mode == JOB_ETD3RK || mode == JOB_ETD4RK) {
       // keep a (and ETD4RK's b) for the later stages
       gptr<const double> U = V(V_U);
@@ -1437,7 +1557,8 @@ struct Engine {
       return;
     }
     if (mode != JOB_PHI && mode != JOB_ETD1 && mode != JOB_ETD2RK && mode != JOB_ETD2RK_STAGE &&
-        mode != JOB_ADJ_ETD2RK && mode != JOB_ETD3RK && mode != JOB_ETD4RK && mode != JOB_ETD2) {
+        mode != JOB_ADJ_ETD2RK && mode != JOB_ETD3RK && mode != JOB_ETD4RK && mode != JOB_ETD2 &&
+        mode != JOB_ETD3RK_SIMUL && mode != JOB_ETD4RK_SIMUL) {
       if (threadIdx.x == 0 && lb == 0) atomicCAS(P.status, 0, ST_INVALID);
       return;
     }
@@ -1448,7 +1569,7 @@ struct Engine {
       int p = 0, b0 = V_U;
       double t = 0.0;
       if (!assemble(mode, stage, p, t, b0)) return;
-      if (!phi_comb(p, t, b0)) return;
+      if (!phi_comb(p, t, b0, st_tmid, st_midvec)) return;
       if (!post(mode, stage, dsum)) return;
     }
     if (mode == JOB_ADJ_ETD2RK && threadIdx.x == 0 && lb == 0) *P.dbeta += (P.h / P.beta) * dsum;

@@ -16,7 +16,7 @@ from oracle.etd import etd_step as oracle_etd_step, logistic
 from oracle.freeboundary import levelset_advance as oracle_levelset_advance
 from oracle.geometry import Grid, classify
 from oracle.operator import build_operator
-from oracle.phi import phi_combination
+from oracle.phi import phi_combination, phi_combination_at
 from paper_2209_15095_amd import inputs
 
 pytestmark = pytest.mark.gpu
@@ -103,6 +103,37 @@ def test_phi_combination_parity_fisher64(p, t):
     ctx.close()
 
 
+@pytest.mark.parametrize("case,t", [("fisher64", 0.05), ("star2d", 2.0), ("ellipsoid3d", 2.0)])
+@pytest.mark.parametrize("p", [0, 1, 3])
+def test_phi_combination_multi_parity(case, t, p):
+    """phi_combination_apply_multi: the value at t and at t_mid (inside a
+    substep, or at its end) from one integration, against the oracle's
+    phi_combination and phi_combination_at; t = 2 takes several substeps."""
+    if case == "fisher64":
+        w = inputs.fisher64()
+        g, rho = w.grid, w.rho0
+    else:
+        g, rho = small_star2d() if case == "star2d" else small_ellipsoid3d()
+    op = build_operator(ogrid(g), rho, 1.0)
+    rng = np.random.default_rng(8)
+    bs = [rng.standard_normal(rho.shape) for _ in range(p + 1)]
+    vs = [op.gather(b) for b in bs]
+    method = "dense" if op.n < 2500 else "krylov"
+    ctx = ctx_for(g, beta=1.0)
+    ctx.geometry_build(dev(rho))
+    for frac in (0.5, 0.3, 1.0):
+        ref = phi_combination(op.A, t, vs, method=method)
+        ref_mid = phi_combination_at(op.A, t, vs, frac * t, method=method)
+        out, mid, st = ctx.phi_combination_apply_multi(t, [dev(b) for b in bs], frac * t, stats=True)
+        out, mid = host(out), host(mid)
+        say(f"multi {case} p {p} t_mid {frac}t: substeps {st['substeps']} out {rel_l2(out[op.comp], ref):.2e} "
+            f"mid {rel_l2(mid[op.comp], ref_mid):.2e}")
+        assert rel_l2(out[op.comp], ref) <= 1e-9
+        assert rel_l2(mid[op.comp], ref_mid) <= 1e-9
+        assert np.all(mid[~op.comp] == 0.0)
+    ctx.close()
+
+
 @pytest.mark.parametrize("case", ["star2d", "ellipsoid3d"])
 def test_phi_combination_parity_stiff(case):
     """Large |tA| (several substeps / large m) on 2D and 3D domains."""
@@ -122,7 +153,7 @@ def test_phi_combination_parity_stiff(case):
     ctx.close()
 
 
-@pytest.mark.parametrize("scheme", ["etd1", "etd2rk", "etd3rk", "etd4rk"])
+@pytest.mark.parametrize("scheme", ["etd1", "etd2rk", "etd3rk", "etd4rk", "etd3rk_simul", "etd4rk_simul"])
 @pytest.mark.parametrize("case", ["fisher64", "ellipsoid3d"])
 def test_etd_step_frozen_parity(scheme, case):
     say(f"etd_step frozen {case} {scheme}")
@@ -140,7 +171,8 @@ def test_etd_step_frozen_parity(scheme, case):
     ctx.geometry_build(dev(rho))
     ud = dev(u0)
     for k in range(3):
-        U = oracle_etd_step(op.A, h, U, f, scheme, method="dense" if op.n < 2500 else "krylov")
+        # the _simul variants compute the same schemes (Section 3.3 simultaneous output)
+        U = oracle_etd_step(op.A, h, U, f, scheme.replace("_simul", ""), method="dense" if op.n < 2500 else "krylov")
         st = ctx.etd_step(scheme, h, ud, stats=True)
         say(f"  step {k} stats {st}")
     out = host(ud)
@@ -168,7 +200,7 @@ def test_levelset_advance_parity_2d():
     ctx.close()
 
 
-@pytest.mark.parametrize("scheme", [None, "etd4rk"])
+@pytest.mark.parametrize("scheme", [None, "etd4rk", "etd4rk_simul"])
 def test_free_boundary_fisher64_end_to_end(scheme):
     """Config fisher64 in full: 10 ETD1 steps, mu = 1, moving boundary; and
     the same run with ETD4RK steps."""
@@ -184,8 +216,8 @@ def test_free_boundary_fisher64_end_to_end(scheme):
     ctx.geometry_build(rd)
     for m in range(w.steps):
         reinit = (m + 1) % w.reinit_every == 0
-        rho, u, op = free_boundary_step(og, rho, u, w.h, w.beta, w.mu, scheme=w.scheme, reinit=reinit,
-                                        method="dense")
+        rho, u, op = free_boundary_step(og, rho, u, w.h, w.beta, w.mu, scheme=w.scheme.replace("_simul", ""),
+                                        reinit=reinit, method="dense")
         ctx.etd_step(w.scheme, w.h, ud, rho=rd, reinit=reinit)
     rg, ug = host(rd), host(ud)
     _, comp_g, _ = classify(og, rg)

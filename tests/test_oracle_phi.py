@@ -18,7 +18,7 @@ import numpy as np
 import pytest
 from scipy.integrate import quad, solve_ivp
 
-from oracle.phi import (phi_combination, phi_combination_dense, phi_combination_eigh,
+from oracle.phi import (phi_combination, phi_combination_at, phi_combination_dense, phi_combination_eigh,
                         phi_combination_krylov, phi_scalar)
 
 mpmath.mp.dps = 150
@@ -146,3 +146,28 @@ def test_dispatch_empty_and_zero():
     # t = 0: every phi_k(0 A) is 1/k! I
     got = phi_combination(A, 0.0, [b0, b0, b0])
     assert np.allclose(got, b0 * (1 + 1 + 0.5), rtol=1e-15)
+
+
+@pytest.mark.parametrize("p", [0, 1, 3])
+def test_intermediate_time_is_the_ode_solution(p):
+    """phi_combination_at: the ODE of Section 3.3 (its forcing scaled to end
+    at t) integrated by DOP853 to an intermediate time s."""
+    n = 25
+    rng = np.random.default_rng(9)
+    B = rng.standard_normal((n, n))
+    A = -(B @ B.T) / n * 8.0
+    bs = [rng.standard_normal(n) for _ in range(p + 1)]
+    t, s = 0.9, 0.37
+
+    def rhs(tau, y):
+        out = A @ y
+        for k in range(1, p + 1):
+            out = out + tau ** (k - 1) / math.factorial(k - 1) * bs[k] / t ** k
+        return out
+
+    sol = solve_ivp(rhs, (0.0, s), bs[0], method="DOP853", rtol=1e-13, atol=1e-14)
+    got = phi_combination_at(A, t, bs, s, method="dense")
+    assert np.linalg.norm(got - sol.y[:, -1]) <= 1e-10 * np.linalg.norm(sol.y[:, -1])
+    # at s = t it is the combination itself
+    assert np.allclose(phi_combination_at(A, t, bs, t, method="dense"), phi_combination(A, t, bs, method="dense"),
+                       rtol=1e-14, atol=1e-14)
