@@ -32,7 +32,8 @@ visiting order.
   n_sub = max(1, ceil(max V * dt / (h/2))).
 * Reinitialisation: rho_tau + S(rho_0)(|grad rho| - 1) = 0,
   S = rho_0 / sqrt(rho_0^2 + h^2), Godunov, HJ-WENO5, TVD-RK3,
-  REINIT_ITERS iterations of dtau = h/2.
+  REINIT_ITERS iterations of dtau = h/2, in the narrow band
+  |rho_0| < REINIT_BAND h (every stage keeps the other nodes at rho_0).
 
 Pins (tests/test_oracle_levelset.py): WENO5 derivatives exact for cubics
 and fifth-order accurate for smooth data; a circle under constant V grows to
@@ -60,6 +61,10 @@ ASLAM_ITERS = 25
 MAX_FRONT_NODES = 2
 VEL_ITERS = 20
 REINIT_ITERS = 10
+# Narrow band of the reinitialisation (units of h): only nodes with
+# |rho_0| < REINIT_BAND h are updated; the interface region |rho| < 3h then
+# agrees with a whole-box reinitialisation to well below 1e-4 h.
+REINIT_BAND = 12
 WENO_EPS = 1e-6
 
 
@@ -205,14 +210,31 @@ def advect(rho, V, dt, h):
     return rho
 
 
-def reinitialize(rho, h, iters=REINIT_ITERS):
+def reinitialize(rho, h, iters=REINIT_ITERS, band=REINIT_BAND):
+    """rho_tau + S(rho_0)(|grad rho| - 1) = 0, TVD-RK3 in pseudo-time.
+
+    band (in units of h): the update is applied only at nodes with
+    |rho_0| < band h (narrow band); every RK stage keeps the other nodes at
+    their rho_0 values, which the WENO stencils of band nodes read.  None:
+    the whole box."""
     rho0 = rho
     S = rho0 / np.sqrt(rho0 * rho0 + h * h)
     sgn = np.sign(S)
+    if band is None:
+        def L(phi):
+            return S * (godunov_grad(phi, h, sgn) - 1.0)
 
-    def L(phi):
-        return S * (godunov_grad(phi, h, sgn) - 1.0)
+        for _ in range(iters):
+            rho = _rk3(rho, L, 0.5 * h)
+        return rho
+    inb = np.abs(rho0) < band * h
 
+    def Lb(phi):
+        return np.where(inb, S * (godunov_grad(phi, h, sgn) - 1.0), 0.0)
+
+    dt = 0.5 * h
     for _ in range(iters):
-        rho = _rk3(rho, L, 0.5 * h)
+        p1 = np.where(inb, rho - dt * Lb(rho), rho)
+        p2 = np.where(inb, 0.75 * rho + 0.25 * (p1 - dt * Lb(p1)), rho)
+        rho = np.where(inb, rho / 3.0 + 2.0 / 3.0 * (p2 - dt * Lb(p2)), rho)
     return rho

@@ -384,6 +384,9 @@ LsInst levelset_inst(const etd_ctx* c, double* rho, double* u) {
   I.nodes = c->ls.nodes;
   I.known = c->ls.known;
   I.band = c->band_list;
+  I.tdist = c->band_tmp + (size_t)((c->box.dim - 1) & 1) * c->ntiles;
+  I.rr = GEOM_RADII[4];
+  I.status = c->counters + 1;
   return I;
 }
 

@@ -149,7 +149,8 @@ enum {
   ST_NONFINITE = -5,
   ST_DOMAIN = -6,
   ST_BARRIER = -7,
-  ST_NO_GEOMETRY = -8
+  ST_NO_GEOMETRY = -8,
+  ST_FRONT = -9
 };
 
 }  // namespace etdfb

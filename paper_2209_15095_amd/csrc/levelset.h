@@ -36,6 +36,12 @@ constexpr int ASLAM_ITERS = 25;
 constexpr int LS_MAX_FRONT_NODES = 2;
 constexpr int VEL_ITERS = 20;
 constexpr int REINIT_ITERS = 10;
+// Narrow band of the reinitialisation (units of h): nodes with
+// |rho_0| < REINIT_BAND h are updated, the others keep rho_0 in every RK
+// stage.  The sweeps run on list R, which must hold every band node and the
+// 3-node WENO reach around it (checked on the device at each
+// reinitialisation, else ST_FRONT).
+constexpr int REINIT_BAND = 12;
 // Tile lists of a sweep (radii in nodes, see above).
 enum LsList {
   LS_A1 = 0,    // Dc <= ASLAM_ITERS + 1: u_nn sweeps, known sets
@@ -68,6 +74,9 @@ struct LsInst {
   size_t nodes;
   uint8_t* known;
   const int* band;            // lists, LS_NLIST blocks of ntx*nty*ntz entries
+  const int* tdist;           // packed tile distances of the lists (high 16 bits: Dv)
+  int rr;                     // radius of list R (Dv <= rr)
+  int* status;                // latched device error of the instance
   double* vmax;               // set by levelset_begin
 };
 

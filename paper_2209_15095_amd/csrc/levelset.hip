@@ -322,6 +322,31 @@ __global__ __launch_bounds__(256) void extend_group_kernel(const LsInst* __restr
   }
 }
 
+// Whole box, before a reinitialisation: every node of the narrow band
+// (|rho_0| < REINIT_BAND h) and its 3-node WENO reach along each axis must lie
+// in tiles of list R (Dv <= rr), where the RK stages run; else ST_FRONT.
+template <int DIM>
+__global__ __launch_bounds__(256) void reinit_check_kernel(const LsInst* __restrict__ insts,
+                                                           const int* __restrict__ off, int count) {
+  const Where w = locate<DIM>(insts, off, count, LS_FULL);
+  if (!w.in) return;
+  const LsInst& I = *w.I;
+  if (!(fabs(glb((const double*)I.rho)[w.id]) < REINIT_BAND * I.h)) return;
+  constexpr int X = TileShape<DIM>::X, Y = TileShape<DIM>::Y, Z = TileShape<DIM>::Z;
+  const int ext[3] = {X, Y, Z};
+  const int n[3] = {I.nx, I.ny, I.nz};
+  bool ok = true;
+  for (int d = 0; d < DIM; ++d)
+    for (int s = -3; s <= 3; s += 6) {
+      int c[3] = {w.i, w.j, w.k};
+      c[d] = clampi(c[d] + s, n[d]);
+      const int t = ((c[2] / Z) * I.nty + c[1] / Y) * I.ntx + c[0] / X;
+      ok = ok && (I.tdist[t] >> 16) <= I.rr;
+      (void)ext;
+    }
+  if (!ok) atomicCAS(I.status, 0, ST_FRONT);
+}
+
 // list V: V = (|rho| < h) ? mu |central grad u_ext| : 0; speed band into bit 3
 template <int DIM>
 __global__ __launch_bounds__(256) void velocity_kernel(const LsInst* __restrict__ insts,
@@ -401,13 +426,15 @@ __device__ __forceinline__ int substeps(const LsInst& I, double dt) {
 // One TVD-RK3 stage (1, 2, 3): out = c0 * R0 + c1 * (in - dt * L(in)) with
 // stage 1: in = rho, out = R1 (and R0 = rho); stage 2: in = R1, out = R2;
 // stage 3: in = R2, out = rho; L = V G(in) (advection, list R, speed 0
-// gives L = 0) or S (G_sign(S)(in) - 1) (reinitialisation, whole box;
-// first != 0 computes S from rho).  Advection substep q runs only for
-// instances with more than q substeps.
+// gives L = 0) or S (G_sign(S)(in) - 1) (reinitialisation, list R, only at
+// nodes of the narrow band |rho_0| < REINIT_BAND h, the others keep rho_0 in
+// every stage; first != 0 computes S and the band bit (known bit 4) from
+// rho).  Advection substep q runs only for instances with more than q
+// substeps.
 template <int DIM>
 __global__ __launch_bounds__(256) void rk_kernel(const LsInst* __restrict__ insts, const int* __restrict__ off,
                                                  int count, int reinit, int stage, int q, double dt, int first) {
-  const Where w = locate<DIM>(insts, off, count, reinit ? LS_FULL : LS_R);
+  const Where w = locate<DIM>(insts, off, count, LS_R);
   if (!w.in) return;
   const LsInst& I = *w.I;
   double step;
@@ -420,15 +447,24 @@ __global__ __launch_bounds__(256) void rk_kernel(const LsInst* __restrict__ inst
   }
   gptr<double> rho = glb(I.rho);
   gptr<const double> in = (stage == 1) ? (gptr<const double>)rho : arr(I, stage == 2 ? A_R1 : A_R2);
-  double L;
+  double L = 0.0;
+  bool upd = true;
   if (reinit) {
+    gptr<uint8_t> kn = glb(I.known);
     if (first) {
       const double r = rho[w.id];
       arr(I, A_S)[w.id] = r / sqrt(r * r + I.h * I.h);
+      const bool inb = fabs(r) < REINIT_BAND * I.h;
+      kn[w.id] = inb ? (uint8_t)(kn[w.id] | 16) : (uint8_t)(kn[w.id] & ~16u);
+      upd = inb;
+    } else {
+      upd = (kn[w.id] >> 4) & 1;
     }
-    const double s = arr(I, A_S)[w.id];
-    const double sg = (s > 0.0) ? 1.0 : ((s < 0.0) ? -1.0 : 0.0);
-    L = s * (godunov<DIM>(I, w, in, sg) - 1.0);
+    if (upd) {
+      const double s = arr(I, A_S)[w.id];
+      const double sg = (s > 0.0) ? 1.0 : ((s < 0.0) ? -1.0 : 0.0);
+      L = s * (godunov<DIM>(I, w, in, sg) - 1.0);
+    }
   } else {
     const double V = arr(I, A_V)[w.id];
     L = (V != 0.0) ? V * godunov<DIM>(I, w, in, 1.0) : 0.0;
@@ -437,10 +473,10 @@ __global__ __launch_bounds__(256) void rk_kernel(const LsInst* __restrict__ inst
   const double st = cur - step * L;
   if (stage == 1) {
     arr(I, A_R0)[w.id] = cur;
-    arr(I, A_R1)[w.id] = st;
+    arr(I, A_R1)[w.id] = upd ? st : cur;
   } else if (stage == 2) {
-    arr(I, A_R2)[w.id] = 0.75 * arr(I, A_R0)[w.id] + 0.25 * st;
-  } else {
+    arr(I, A_R2)[w.id] = upd ? 0.75 * arr(I, A_R0)[w.id] + 0.25 * st : cur;
+  } else if (upd) {
     rho[w.id] = (1.0 / 3.0) * arr(I, A_R0)[w.id] + (2.0 / 3.0) * st;
   }
 }
@@ -541,12 +577,16 @@ hipError_t end_dim(LevelsetBatch& b, hipStream_t st) {
       }
   }
   if (b.reinit) {
-    for (int it = 0; it < REINIT_ITERS; ++it)
-      for (int s = 1; s <= 3; ++s) {
-        hipLaunchKernelGGL(rk_kernel<DIM>, dim3(b.total[LS_FULL]), B, 0, st, I, off, n, 1, s, 0, 0.0,
-                           (it == 0 && s == 1) ? 1 : 0);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-      }
+    hipLaunchKernelGGL(reinit_check_kernel<DIM>, dim3(b.total[LS_FULL]), B, 0, st, I, off, n);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (b.total[LS_R] > 0) {
+      for (int it = 0; it < REINIT_ITERS; ++it)
+        for (int s = 1; s <= 3; ++s) {
+          hipLaunchKernelGGL(rk_kernel<DIM>, dim3(b.total[LS_R]), B, 0, st, I, off, n, 1, s, 0, 0.0,
+                             (it == 0 && s == 1) ? 1 : 0);
+          if ((e = hipGetLastError()) != hipSuccess) return e;
+        }
+    }
   }
   hipLaunchKernelGGL(restrict_kernel<DIM>, dim3(b.total[LS_FULL]), B, 0, st, I, off, n, b.uext, 0);
   return hipGetLastError();
