@@ -48,7 +48,7 @@ enum {
   ETD_ERR_DOMAIN = -6,       /* computational point within 2 layers of the box edge */
   ETD_ERR_BARRIER = -7,      /* grid barrier timed out (kernel drained and exited) */
   ETD_ERR_NO_GEOMETRY = -8,  /* no geometry built on this context yet */
-  ETD_ERR_FRONT = -9         /* the boundary would move more than one node in a step */
+  ETD_ERR_FRONT = -9         /* boundary beyond the reach of the level-set sweeps (front speed, reads) */
 };
 
 /* ETD1 (Section 3.1), ETD2RK, ETD3RK and ETD4RK (Section 3.2; the phi_3 of

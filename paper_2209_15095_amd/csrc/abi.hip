@@ -16,7 +16,7 @@
 
 using namespace etdfb;
 
-constexpr int NCOUNTERS = 16;   // device counters of a context (see etd_ctx::counters)
+constexpr int NCOUNTERS = 96;   // device counters of a context (see etd_ctx::counters)
 
 struct etd_ctx {
   int device = 0;
@@ -43,9 +43,9 @@ struct etd_ctx {
   int* nbr = nullptr;        // face-neighbour slots, NBR_STRIDE per slot
   int* tile_vb = nullptr;    // tiles with a node |rho| < h
   int* band_tmp = nullptr;   // 2 * ntiles: tile distance passes
-  int* band_list = nullptr;  // level-set tile lists, LS_NLIST * ntiles
+  int* band_list = nullptr;  // level-set tile lists SC, SV, U, LS_NLISTS * ntiles
   int* counters = nullptr;   // [0] n_active, [1] status, [2..3] case counts, [4] unknowns,
-                             // [8..8+LS_NLIST) level-set list sizes
+                             // [LS_CNT_C..LS_NCOUNTERS) level-set list counts
   // persistent kernel state
   double* ws = nullptr;
   double* part = nullptr;
@@ -62,7 +62,9 @@ struct etd_ctx {
   // level-set scratch (box arrays) and its one-instance table
   LevelsetScratch ls{};
   LevelsetBatch lsb{};
-  int nband_host[LS_NLIST] = {};
+  int ncum_c[LS_C_MAX + 1] = {};   // level-set list counts of the last build
+  int ncum_v[LS_V_MAX + 1] = {};
+  int nu_host = 0;
   // geometry-build table of this context (one instance)
   GeomBatch gb{};
   // variable beta and Dirichlet data (etd_geometry_build_var; allocated on
@@ -317,8 +319,8 @@ int latched_status(etd_ctx* c) {
 // coefficients and the face-neighbour table, then an asynchronous copy of
 // the counters to pinned memory.  geometry_finish() reads them after the
 // caller has synchronised the stream.
-const int GEOM_RADII[5] = {ASLAM_ITERS + 1, 2 * ASLAM_ITERS + 1, 3 * ASLAM_ITERS + 1, VEL_ITERS + 1,
-                           VEL_ITERS + 4};
+const int GEOM_RADII[5] = {LS_C_MAX, LS_V_MAX, LS_CNT_C, LS_CNT_V, LS_CNT_U};
+static_assert(LS_NCOUNTERS <= NCOUNTERS, "the level-set list counts must fit the counters");
 
 // One entry of a geometry table: the context's arrays.
 GeomInst geom_inst(const etd_ctx* c) {
@@ -357,7 +359,9 @@ int geometry_enqueue(etd_ctx* c, const double* rho) {
 int geometry_finish(etd_ctx* c, const int* cnt) {
   memcpy(c->h_counters, cnt, sizeof(int) * NCOUNTERS);
   c->n_active_host = c->h_counters[0];
-  for (int q = 0; q < LS_NLIST; ++q) c->nband_host[q] = c->h_counters[8 + q];
+  for (int q = 0; q <= LS_C_MAX; ++q) c->ncum_c[q] = c->h_counters[LS_CNT_C + q];
+  for (int q = 0; q <= LS_V_MAX; ++q) c->ncum_v[q] = c->h_counters[LS_CNT_V + q];
+  c->nu_host = c->h_counters[LS_CNT_U];
   choose_launch(c);
   c->have_geometry = true;
   if (c->h_counters[1] == ST_DOMAIN) {
@@ -375,7 +379,9 @@ LsInst levelset_inst(const etd_ctx* c, double* rho, double* u) {
   I.dim = c->box.dim;
   I.nx = c->box.nx; I.ny = c->box.ny; I.nz = c->box.nz;
   I.ntx = c->box.ntx; I.nty = c->box.nty; I.ntz = c->box.ntz;
-  for (int q = 0; q < LS_NLIST; ++q) I.nband[q] = c->nband_host[q];
+  for (int q = 0; q <= LS_C_MAX; ++q) I.ncum_c[q] = c->ncum_c[q];
+  for (int q = 0; q <= LS_V_MAX; ++q) I.ncum_v[q] = c->ncum_v[q];
+  I.nu = c->nu_host;
   I.h = c->box.dx;
   I.mu = c->phys.mu;
   I.rho = rho;
@@ -383,9 +389,10 @@ LsInst levelset_inst(const etd_ctx* c, double* rho, double* u) {
   I.buf = c->ls.buf;
   I.nodes = c->ls.nodes;
   I.known = c->ls.known;
+  I.dist = c->ls.dist;
   I.band = c->band_list;
   I.tdist = c->band_tmp + (size_t)((c->box.dim - 1) & 1) * c->ntiles;
-  I.rr = GEOM_RADII[4];
+  I.rr = LS_V_MAX;
   I.status = c->counters + 1;
   return I;
 }
@@ -430,7 +437,7 @@ const char* etd_status_string(int s) {
     case ETD_ERR_DOMAIN: return "computational point within 2 layers of the box edge";
     case ETD_ERR_BARRIER: return "grid barrier timed out";
     case ETD_ERR_NO_GEOMETRY: return "no geometry built";
-    case ETD_ERR_FRONT: return "boundary would move more than one node in one step";
+    case ETD_ERR_FRONT: return "boundary moved beyond the reach of the level-set sweeps";
     default: return "unknown status";
   }
 }
@@ -515,7 +522,7 @@ int ctx_create(const etd_grid* grid, const etd_physics* phys, const etd_krylov_o
   ok &= hipMalloc(&c->nbr, sizeof(int) * NBR_STRIDE * ktiles) == hipSuccess;
   ok &= hipMalloc(&c->tile_vb, sizeof(int) * (size_t)c->ntiles) == hipSuccess;
   ok &= hipMalloc(&c->band_tmp, sizeof(int) * 2 * (size_t)c->ntiles) == hipSuccess;
-  ok &= hipMalloc(&c->band_list, sizeof(int) * LS_NLIST * (size_t)c->ntiles) == hipSuccess;
+  ok &= hipMalloc(&c->band_list, sizeof(int) * LS_NLISTS * (size_t)c->ntiles) == hipSuccess;
   ok &= hipMalloc(&c->counters, sizeof(int) * NCOUNTERS) == hipSuccess;
   ok &= hipMalloc(&c->ws, sizeof(double) * c->ld * NVEC) == hipSuccess;
   ok &= hipMalloc(&c->part, sizeof(double) * 2 * (size_t)c->max_grid * PART_STRIDE) == hipSuccess;
@@ -1501,7 +1508,7 @@ constexpr StaticLayout static_layout() {
   L.tile_flag = take(sizeof(int) * ST_TILES);
   L.tile_vb = take(sizeof(int) * ST_TILES);
   L.band_tmp = take(sizeof(int) * 2 * ST_TILES);
-  L.band_list = take(sizeof(int) * LS_NLIST * ST_TILES);
+  L.band_list = take(sizeof(int) * LS_NLISTS * ST_TILES);
   L.mask = take(ST_LD);
   L.counters = take(sizeof(int) * NCOUNTERS);
   L.part = take(sizeof(double) * 2 * ST_GMAX * PART_STRIDE);
@@ -1661,7 +1668,7 @@ extern "C" int phi_combination_apply_static(const etd_grid* grid, double beta, c
         break;
       }
     }
-    hipLaunchKernelGGL(static_init_kernel, dim3(1), dim3(64), 0, c.stream, c.counters, c.bar, c.st, o.m_min);
+    hipLaunchKernelGGL(static_init_kernel, dim3(1), dim3(NCOUNTERS), 0, c.stream, c.counters, c.bar, c.st, o.m_min);
     if (hipGetLastError() != hipSuccess) { result = ETD_ERR_HIP; break; }
     if ((result = geometry_enqueue(&c, rho))) break;
     if (hipStreamSynchronize(c.stream) != hipSuccess) { result = ETD_ERR_HIP; break; }

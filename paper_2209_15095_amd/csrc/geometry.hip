@@ -197,59 +197,47 @@ __global__ __launch_bounds__(256) void band_dist_kernel(const GeomInst* __restri
   }
 }
 
-// One block of 1024 threads: the tile lists of the level-set sweeps (in
-// tile order) from the packed distances, and their sizes.
-__global__ __launch_bounds__(1024) void band_lists_kernel(const GeomInst* __restrict__ tab, int last_axis,
-                                                          int ra1, int ra2, int ra3, int rv, int rr) {
+// One block of 1024 threads per instance: the level-set tile lists from the
+// packed distances.  SC: tiles with Dc <= cmax sorted by Dc; SV: tiles with
+// Dv <= vmax sorted by Dv (counting sort; the order within one distance is
+// that of the atomic cursors, which no result depends on); U: SC or SV.
+// The cumulative counts of SC and SV per radius go to counters[cnt_c + r]
+// and counters[cnt_v + r], the size of U to counters[cnt_u].
+__global__ __launch_bounds__(1024) void band_lists_kernel(const GeomInst* __restrict__ tab, int last_axis, int cmax,
+                                                          int vmax, int cnt_c, int cnt_v, int cnt_u) {
+  constexpr int NB = 128;   // histogram bins (>= cmax + 1, vmax + 1)
   const GeomInst& I = tab[blockIdx.x];
   const int ntiles = I.ntiles;
   const int* __restrict__ dist = I.band_tmp + (size_t)(last_axis & 1) * ntiles;
-  int* __restrict__ lists = I.band_list;
-  int* __restrict__ counts = I.counters + 8;
-  constexpr int NL = 6;
-  __shared__ int wave_tot[16][NL];
-  __shared__ int carry[NL];
-  if (threadIdx.x < NL) carry[threadIdx.x] = 0;
+  int* __restrict__ sc = I.band_list;
+  int* __restrict__ sv = I.band_list + ntiles;
+  int* __restrict__ su = I.band_list + 2 * (size_t)ntiles;
+  __shared__ int hc[NB], hv[NB], nu;
+  for (int q = threadIdx.x; q < NB; q += blockDim.x) { hc[q] = 0; hv[q] = 0; }
+  if (threadIdx.x == 0) nu = 0;
   __syncthreads();
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  for (int base = 0; base < ntiles; base += 1024) {
-    const int t = base + threadIdx.x;
-    int f[NL] = {0, 0, 0, 0, 0, 0};
-    if (t < ntiles) {
-      const int dc = dist[t] & 0xFFFF, dv = dist[t] >> 16;
-      f[0] = dc <= ra1;
-      f[1] = dc <= ra2;
-      f[2] = dc <= ra3;
-      f[3] = dv <= rv;
-      f[4] = dv <= rr;
-      f[5] = f[2] || f[4];
-    }
-    int x[NL];
-    for (int q = 0; q < NL; ++q) {
-      x[q] = f[q];
-      for (int off = 1; off < 64; off <<= 1) {
-        const int y = __shfl_up(x[q], off, 64);
-        if (lane >= off) x[q] += y;
-      }
-      if (lane == 63) wave_tot[w][q] = x[q];
-    }
-    __syncthreads();
-    if (threadIdx.x < NL) {
-      int acc = 0;
-      for (int v = 0; v < 16; ++v) { const int y = wave_tot[v][threadIdx.x]; wave_tot[v][threadIdx.x] = acc; acc += y; }
-    }
-    __syncthreads();
-    int excl[NL];
-    for (int q = 0; q < NL; ++q) {
-      excl[q] = carry[q] + wave_tot[w][q] + x[q] - f[q];
-      if (t < ntiles && f[q]) lists[(size_t)q * ntiles + excl[q]] = t;
-    }
-    __syncthreads();
-    if (threadIdx.x == 1023)
-      for (int q = 0; q < NL; ++q) carry[q] = excl[q] + f[q];
-    __syncthreads();
+  for (int t = threadIdx.x; t < ntiles; t += blockDim.x) {
+    const int dc = dist[t] & 0xFFFF, dv = dist[t] >> 16;
+    if (dc <= cmax) atomicAdd(&hc[dc], 1);
+    if (dv <= vmax) atomicAdd(&hv[dv], 1);
   }
-  if (threadIdx.x < NL) counts[threadIdx.x] = carry[threadIdx.x];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    // cumulative counts out, histograms -> start offsets
+    int a = 0;
+    for (int q = 0; q <= cmax; ++q) { const int c = hc[q]; hc[q] = a; a += c; I.counters[cnt_c + q] = a; }
+    a = 0;
+    for (int q = 0; q <= vmax; ++q) { const int c = hv[q]; hv[q] = a; a += c; I.counters[cnt_v + q] = a; }
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < ntiles; t += blockDim.x) {
+    const int dc = dist[t] & 0xFFFF, dv = dist[t] >> 16;
+    if (dc <= cmax) sc[atomicAdd(&hc[dc], 1)] = t;
+    if (dv <= vmax) sv[atomicAdd(&hv[dv], 1)] = t;
+    if (dc <= cmax || dv <= vmax) su[atomicAdd(&nu, 1)] = t;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) I.counters[cnt_u] = nu;
 }
 
 __device__ __forceinline__ void central_grad(const BoxDev& b, const double* __restrict__ rho, int i,
@@ -740,8 +728,7 @@ hipError_t launch_geometry(GeomBatch& gb, const int* radii, hipStream_t s) {
   hipLaunchKernelGGL(tile_coeff_kernel, dim3(gb.blocks[GEOM_PRE_TILE]), dim3(256), 0, s, gb.d_tab,
                      pre_of(gb, GEOM_PRE_TILE), n);
   // tile radii of the distance passes: tiles k apart are >= (k-1) t + 1 nodes apart
-  int rmax = 0;
-  for (int q = 0; q < 5; ++q) rmax = radii[q] > rmax ? radii[q] : rmax;
+  const int rmax = radii[0] > radii[1] ? radii[0] : radii[1];
   const BoxHost& b0 = gb.h_tab[0].b;
   const int dim = b0.dim;
   const int t[3] = {b0.tx, b0.ty, b0.tz};
@@ -750,8 +737,8 @@ hipError_t launch_geometry(GeomBatch& gb, const int* radii, hipStream_t s) {
   for (int axis = 0; axis < dim; ++axis)
     hipLaunchKernelGGL(band_dist_kernel, dim3(gb.blocks[GEOM_PRE_T256]), dim3(256), 0, s, gb.d_tab,
                        pre_of(gb, GEOM_PRE_T256), n, axis, r[0], r[1], r[2], 1000);
-  hipLaunchKernelGGL(band_lists_kernel, dim3(n), dim3(1024), 0, s, gb.d_tab, dim - 1, radii[0], radii[1],
-                     radii[2], radii[3], radii[4]);
+  hipLaunchKernelGGL(band_lists_kernel, dim3(n), dim3(1024), 0, s, gb.d_tab, dim - 1, radii[0], radii[1], radii[2],
+                     radii[3], radii[4]);
   hipLaunchKernelGGL(collect_counters_kernel, dim3(blocks_for((size_t)n * gb.ncnt, 256)), dim3(256), 0, s,
                      gb.d_tab, n, gb.ncnt, gb.d_cnt);
   if ((e = hipGetLastError()) != hipSuccess) return e;

@@ -32,8 +32,9 @@ struct GeomInst {
   double* cdiag;
   int* nbr;
   int* band_tmp;         // 2 * ntiles
-  int* band_list;        // 6 * ntiles
-  int* counters;         // [0] active tiles, [1] status, [2..3] case counts, [4] unknowns, [8..13] lists
+  int* band_list;        // 3 * ntiles: level-set lists SC, SV, U
+  int* counters;         // [0] active tiles, [1] status, [2..3] case counts, [4] unknowns, [5..6] species,
+                         // then the level-set list counts (levelset.h)
   double* ws;            // workspace vectors (gather / scatter targets)
   size_t ld;
   size_t nodes;
@@ -73,8 +74,10 @@ void geom_batch_free(GeomBatch& gb);
 // After the table's sizes are filled in: block prefixes (synchronous).
 hipError_t geom_batch_prefix(GeomBatch& gb);
 // Whole build of every instance (classification, tile scan, Case 1-3
-// coefficients and face neighbours, level-set tile distances and lists with
-// radii[0..4]), then the counters of all instances into gb.h_cnt
+// coefficients and face neighbours, level-set tile distances and sorted
+// lists: radii = {largest Dc, largest Dv, counter index of the cumulative
+// Dc counts, of the Dv counts, of the size of U}), then the counters of all
+// instances into gb.h_cnt
 // (asynchronous: read after synchronising the stream).  The table's rho
 // pointers must be set; the table is uploaded from pinned memory, so it
 // must not change before the stream has passed this call.

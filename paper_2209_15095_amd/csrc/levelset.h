@@ -7,13 +7,13 @@
 // tiles holding a node with |rho| < h (Dv); the distance between two tiles
 // is a lower bound of the node distance between them.  A Jacobi sweep
 // changes a node only where a face neighbour or its source is nonzero, so
-// the extrapolated u_nn, u_n, u are exactly 0 beyond 25, 50 and 75 nodes of
-// the computational points and the extended speed beyond 20 nodes of the
-// |rho| < h nodes: each stage sweeps only the tiles within that distance
-// plus one, and gives the whole-box values everywhere (the arrays are 0
-// elsewhere).  The advection changes rho only where the speed is nonzero and
-// reads its WENO stencil 3 nodes further.  Reinitialisation and the final
-// restriction of u cover the whole box.
+// after s sweeps u_nn is exactly 0 beyond s nodes of the computational
+// points, u_n beyond 25 + s, and the extended speed beyond s nodes of the
+// |rho| < h nodes: those sweeps process only the tiles within that distance
+// and give the whole-box values everywhere (the arrays are 0 elsewhere).
+// The last stage, u, is kept exact where it is read (see the lists below).
+// The advection changes rho only where the speed is nonzero and reads its
+// WENO stencil 3 nodes further; the reinitialisation acts on a narrow band.
 //
 // One launch per sweep serves a whole batch: block b works on tile
 // b - off[i] of the list of instance i, off[] being the prefix sums of the
@@ -42,38 +42,65 @@ constexpr int REINIT_ITERS = 10;
 // 3-node WENO reach around it (checked on the device at each
 // reinitialisation, else ST_FRONT).
 constexpr int REINIT_BAND = 12;
-// Tile lists of a sweep (radii in nodes, see above).
-enum LsList {
-  LS_A1 = 0,    // Dc <= ASLAM_ITERS + 1: u_nn sweeps, known sets
-  LS_A2 = 1,    // Dc <= 2 ASLAM_ITERS + 1: u_n sweeps
-  LS_A3 = 2,    // Dc <= 3 ASLAM_ITERS + 1: u sweeps
-  LS_V = 3,     // Dv <= VEL_ITERS + 1: speed and its extension
-  LS_R = 4,     // Dv <= VEL_ITERS + 4: advection stages
-  LS_U = 5,     // A3 or R: normals and initial values
-  LS_NLIST = 6,
-  LS_FULL = 6   // every tile of the box
+// Tile lists, built with the geometry: SC = tiles with Dc <= LS_C_MAX sorted
+// by Dc, SV = tiles with Dv <= LS_V_MAX sorted by Dv (so the tiles within a
+// radius r are a prefix, of cumulative count ncum_c[r] / ncum_v[r]), and
+// U = SC or SV in any order.  A sweep of an extension stage takes the
+// prefix its cone needs: the stages that grow from a known set (u_nn,
+// u_n, the speed) process only the tiles their values can reach after that
+// sweep (the arrays are 0 beyond, exactly as over the whole box); the last
+// stage (u) is needed only where it is read (the |rho| < h band and the
+// points that join the domain, within LS_READ_REACH nodes of the
+// computational points), so sweep s processes the tiles within
+// LS_READ_REACH + ASLAM_ITERS - s of them, and its values there equal the
+// whole-box ones.  An L1 distance to the computational points (dilated one
+// node per sweep of the u_nn stage, whose lists grow the same way) lets the
+// reading kernels check that every value they read lies in that region
+// (else ST_FRONT).  The reach covers the reads of the free-boundary
+// workloads with margin (at most 13 nodes, where detached pieces of a noisy
+// 3D domain form).
+constexpr int LS_READ_REACH = 20;
+constexpr int LS_C_MAX = 2 * ASLAM_ITERS + 1;   // the u_n stage's reach
+constexpr int LS_V_MAX = VEL_ITERS + 4;         // the speed's reach plus the WENO stencil
+enum LsList { LS_SC = 0, LS_SV = 1, LS_U = 2, LS_NLISTS = 3 };
+// Launch rows: the prefix of SC within radius r, of SV within r, list U, the whole box.
+enum LsRow {
+  LS_ROW_C = 0,
+  LS_ROW_V = LS_ROW_C + LS_C_MAX + 1,
+  LS_ROW_U = LS_ROW_V + LS_V_MAX + 1,
+  LS_ROW_FULL = LS_ROW_U + 1,
+  LS_NROWS = LS_ROW_FULL + 1
 };
 constexpr int LS_DIST_CAP = 1000;   // distances are capped here (beyond every radius)
+// geometry counters holding the cumulative list counts
+constexpr int LS_CNT_C = 16;                          // ncum_c[0..LS_C_MAX]
+constexpr int LS_CNT_V = LS_CNT_C + LS_C_MAX + 1;     // ncum_v[0..LS_V_MAX]
+constexpr int LS_CNT_U = LS_CNT_V + LS_V_MAX + 1;     // size of U
+constexpr int LS_NCOUNTERS = LS_CNT_U + 1;
 
 // Box-sized scratch arrays of one instance.
 struct LevelsetScratch {
   size_t nodes = 0;
   double* buf = nullptr;      // 12 box arrays of doubles
-  uint8_t* known = nullptr;   // bit 0: K0, bit 1: K1, bit 2: K2, bit 3: speed band
+  uint8_t* known = nullptr;   // bit 0: K0, bit 1: K1, bit 2: K2, bit 3: speed band, bit 4: reinit band
+  uint8_t* dist = nullptr;    // L1 distance to the computational points, capped (LS_READ_REACH + 1 beyond)
 };
 
 // One instance as the kernels see it (device copy in LevelsetBatch).
 struct LsInst {
   int dim, nx, ny, nz;
   int ntx, nty, ntz;
-  int nband[LS_NLIST];        // tiles per list
+  int ncum_c[LS_C_MAX + 1];   // tiles of SC within each radius
+  int ncum_v[LS_V_MAX + 1];   // tiles of SV within each radius
+  int nu;                     // tiles of U
   double h, mu;
   double* rho;                // user arrays (updated in place)
   double* u;
   double* buf;                // LevelsetScratch::buf
   size_t nodes;
   uint8_t* known;
-  const int* band;            // lists, LS_NLIST blocks of ntx*nty*ntz entries
+  const int* band;            // lists SC, SV, U, each a block of ntx*nty*ntz entries
+  uint8_t* dist;              // LevelsetScratch::dist
   const int* tdist;           // packed tile distances of the lists (high 16 bits: Dv)
   int rr;                     // radius of list R (Dv <= rr)
   int* status;                // latched device error of the instance
@@ -86,11 +113,11 @@ struct LevelsetBatch {
   int dim = 2;
   LsInst* d_inst = nullptr;   // count
   LsInst* h_inst = nullptr;   // pinned, count (caller fills before levelset_begin)
-  int* d_off = nullptr;       // (LS_NLIST + 1) * (count + 1): list offsets, then whole-box offsets
+  int* d_off = nullptr;       // LS_NROWS * (count + 1): block offsets of each launch row
   int* h_off = nullptr;       // pinned
   double* d_vmax = nullptr;   // count maximum speeds
   double* h_vmax = nullptr;   // pinned mirror
-  int total[LS_NLIST + 1] = {};
+  int total[LS_NROWS] = {};
   double dt = 0.0;
   int reinit = 0;
   int uext = 0;               // scratch array holding u_ext after levelset_begin

@@ -42,12 +42,14 @@ struct Where {
   bool in;       // node inside the box
 };
 
-// Block -> instance (largest i with off[i] <= blockIdx.x) -> tile of the
-// instance's list `list` (LS_FULL: every tile) -> node.
+// Block -> instance (largest i with off[i] <= blockIdx.x, off the launch
+// row's offsets) -> tile (row LS_ROW_C + r / LS_ROW_V + r: the prefix of the
+// sorted list SC / SV within radius r; LS_ROW_U: list U; LS_ROW_FULL: every
+// tile) -> node.
 template <int DIM>
 __device__ __forceinline__ Where locate(const LsInst* __restrict__ insts, const int* __restrict__ off, int count,
-                                       int list) {
-  const int* o = off + (size_t)list * (count + 1);
+                                       int row) {
+  const int* o = off + (size_t)row * (count + 1);
   const int b = (int)blockIdx.x;
   int lo = 0, hi = count - 1;
   while (lo < hi) {
@@ -59,7 +61,9 @@ __device__ __forceinline__ Where locate(const LsInst* __restrict__ insts, const 
   w.I = insts + lo;
   w.local = b - o[lo];
   const LsInst& I = *w.I;
-  const int t = (list == LS_FULL) ? w.local : I.band[(size_t)list * (I.ntx * I.nty * I.ntz) + w.local];
+  const size_t nt = (size_t)I.ntx * I.nty * I.ntz;
+  const int lst = row == LS_ROW_U ? LS_U : (row >= LS_ROW_V ? LS_SV : LS_SC);
+  const int t = (row == LS_ROW_FULL) ? w.local : I.band[(size_t)lst * nt + w.local];
   constexpr int X = TileShape<DIM>::X, Y = TileShape<DIM>::Y;
   const int tx = t % I.ntx, ty = (t / I.ntx) % I.nty, tz = t / (I.ntx * I.nty);
   const int l = threadIdx.x;
@@ -103,19 +107,20 @@ __device__ __forceinline__ bool comp_point(const LsInst& I, const Where& w, gptr
 template <int DIM>
 __global__ __launch_bounds__(256) void zero_kernel(const LsInst* __restrict__ insts, const int* __restrict__ off,
                                                    int count) {
-  const Where w = locate<DIM>(insts, off, count, LS_FULL);
+  const Where w = locate<DIM>(insts, off, count, LS_ROW_FULL);
   const LsInst& I = *w.I;
   if (w.local == 0 && threadIdx.x == 0) *glb(I.vmax) = 0.0;
   if (!w.in) return;
   for (int a = A_E0; a <= A_V; ++a) arr(I, a)[w.id] = 0.0;
   arr(I, A_S)[w.id] = 0.0;
+  glb(I.dist)[w.id] = 255;
 }
 
 // list U: normals, K0 (bit 0, other bits cleared), E0 = K0 ? u : 0
 template <int DIM>
 __global__ __launch_bounds__(256) void init_kernel(const LsInst* __restrict__ insts, const int* __restrict__ off,
                                                    int count) {
-  const Where w = locate<DIM>(insts, off, count, LS_U);
+  const Where w = locate<DIM>(insts, off, count, LS_ROW_U);
   if (!w.in) return;
   const LsInst& I = *w.I;
   gptr<const double> rho = glb((const double*)I.rho);
@@ -127,7 +132,15 @@ __global__ __launch_bounds__(256) void init_kernel(const LsInst* __restrict__ in
   for (int d = 0; d < DIM; ++d) arr(I, A_NX + d)[w.id] = g[d] / mag;
   const bool c = comp_point<DIM>(I, w, rho);
   glb(I.known)[w.id] = c ? 1 : 0;
+  glb(I.dist)[w.id] = c ? 0 : 255;
   arr(I, A_E0)[w.id] = c ? glb((const double*)I.u)[w.id] : 0.0;
+}
+
+// every read of the extended u (velocity, restriction) must fall within
+// LS_READ_REACH of the computational points, where it equals the whole-box
+// extension (see levelset.h)
+__device__ __forceinline__ bool in_reach(const LsInst& I, size_t id) {
+  return glb((const uint8_t*)I.dist)[id] <= LS_READ_REACH;
 }
 
 // bit `src` at the node and its 2d (clamped) neighbours
@@ -153,7 +166,7 @@ __device__ __forceinline__ double dir_deriv(const LsInst& I, const Where& w, gpt
 template <int DIM>
 __global__ __launch_bounds__(256) void known1_kernel(const LsInst* __restrict__ insts, const int* __restrict__ off,
                                                      int count) {
-  const Where w = locate<DIM>(insts, off, count, LS_A1);
+  const Where w = locate<DIM>(insts, off, count, LS_ROW_C + ASLAM_ITERS + 1);
   if (!w.in) return;
   const LsInst& I = *w.I;
   if (known_all<DIM>(I, w, 0)) glb(I.known)[w.id] |= (uint8_t)2;
@@ -163,7 +176,7 @@ __global__ __launch_bounds__(256) void known1_kernel(const LsInst* __restrict__ 
 template <int DIM>
 __global__ __launch_bounds__(256) void known2_un_kernel(const LsInst* __restrict__ insts,
                                                         const int* __restrict__ off, int count) {
-  const Where w = locate<DIM>(insts, off, count, LS_A1);
+  const Where w = locate<DIM>(insts, off, count, LS_ROW_C + ASLAM_ITERS + 1);
   if (!w.in) return;
   const LsInst& I = *w.I;
   const bool k1 = (glb((const uint8_t*)I.known)[w.id] >> 1) & 1;
@@ -175,7 +188,7 @@ __global__ __launch_bounds__(256) void known2_un_kernel(const LsInst* __restrict
 template <int DIM>
 __global__ __launch_bounds__(256) void unn_kernel(const LsInst* __restrict__ insts, const int* __restrict__ off,
                                                   int count) {
-  const Where w = locate<DIM>(insts, off, count, LS_A1);
+  const Where w = locate<DIM>(insts, off, count, LS_ROW_C + ASLAM_ITERS + 1);
   if (!w.in) return;
   const LsInst& I = *w.I;
   const bool k2 = (glb((const uint8_t*)I.known)[w.id] >> 2) & 1;
@@ -187,11 +200,25 @@ __global__ __launch_bounds__(256) void unn_kernel(const LsInst* __restrict__ ins
 // do_max, also the instance's maximum of out (non-negative values).
 template <int DIM>
 __global__ __launch_bounds__(256) void extend_kernel(const LsInst* __restrict__ insts, const int* __restrict__ off,
-                                                     int count, int list, int v_arr, int out_arr, int src_arr,
-                                                     int bit, int sign_rho, int do_max) {
-  const Where w = locate<DIM>(insts, off, count, list);
+                                                     int count, int row, int v_arr, int out_arr, int src_arr,
+                                                     int bit, int sign_rho, int do_max, int dil) {
+  const Where w = locate<DIM>(insts, off, count, row);
   const LsInst& I = *w.I;
   double res = 0.0;
+  if (w.in && dil) {
+    // one L1 dilation of the distance to the computational points, in place
+    // (a value only decreases, never below the true distance; after k
+    // sweeps every node within k holds its exact distance)
+    gptr<uint8_t> ds = glb(I.dist);
+    int m = ds[w.id];
+    if (m > 0) {
+      for (int d = 0; d < DIM; ++d) {
+        m = min(m, (int)ds[shifted(I, w, d, -1)] + 1);
+        m = min(m, (int)ds[shifted(I, w, d, 1)] + 1);
+      }
+      ds[w.id] = (uint8_t)min(m, 255);
+    }
+  }
   if (w.in) {
     gptr<const double> v = arr(I, v_arr);
     const double vc = v[w.id];
@@ -237,15 +264,16 @@ __global__ __launch_bounds__(256) void extend_kernel(const LsInst* __restrict__ 
 constexpr int SWEEP_GROUP = 5;
 
 __global__ __launch_bounds__(256) void extend_group_kernel(const LsInst* __restrict__ insts,
-                                                           const int* __restrict__ off, int count, int list,
+                                                           const int* __restrict__ off, int count, int row,
                                                            int v_arr, int out_arr, int src_arr, int bit,
-                                                           int sign_rho, int do_max, int nsweep) {
+                                                           int sign_rho, int do_max, int nsweep, int dil) {
   constexpr int X = TileShape<2>::X, Y = TileShape<2>::Y, K = SWEEP_GROUP;
   constexpr int RW = X + 2 * K, RH = Y + 2 * K, RN = RW * RH;
   __shared__ double va[RN], vb[RN], snx[RN], sny[RN], ssrc[RN];
   __shared__ uint8_t sfl[RN];   // bit 0: in the box, bit 1: known, bits 2-3: sign(rho) + 1
+  __shared__ uint8_t sd[2][RN]; // dil: the distance to the computational points (dilated with the sweeps)
   __shared__ double sm[256];
-  const Where w = locate<2>(insts, off, count, list);
+  const Where w = locate<2>(insts, off, count, row);
   const LsInst& I = *w.I;
   const int ox = w.i - (int)(threadIdx.x % X), oy = w.j - (int)(threadIdx.x / X);   // tile origin
   gptr<const double> v = arr(I, v_arr);
@@ -276,6 +304,7 @@ __global__ __launch_bounds__(256) void extend_group_kernel(const LsInst* __restr
     sny[r] = b;
     ssrc[r] = sc;
     sfl[r] = f;
+    if (dil) sd[0][r] = (f & 1) ? glb((const uint8_t*)I.dist)[(size_t)gj * I.nx + gi] : (uint8_t)255;
   }
   __syncthreads();
   const double dt = 0.5 * I.h;
@@ -286,15 +315,21 @@ __global__ __launch_bounds__(256) void extend_group_kernel(const LsInst* __restr
       const uint8_t f = sfl[r];
       const double vc = cur[r];
       double res = vc;
+      const int x = r % RW, y = r / RW;
+      const int gi = ox - K + x, gj = oy - K + y;
+      // neighbours, clamped at the box edge; outside the region: the node itself
+      // (such nodes are beyond the valid region of this sweep)
+      const int rxm = (gi == 0 || x == 0) ? r : r - 1;
+      const int rxp = (gi == I.nx - 1 || x == RW - 1) ? r : r + 1;
+      const int rym = (gj == 0 || y == 0) ? r : r - RW;
+      const int ryp = (gj == I.ny - 1 || y == RH - 1) ? r : r + RW;
+      if (dil) {
+        const uint8_t* dc = sd[s & 1];
+        int m = dc[r];
+        m = min(m, min(min((int)dc[rxm], (int)dc[rxp]), min((int)dc[rym], (int)dc[ryp])) + 1);
+        sd[(s + 1) & 1][r] = (uint8_t)min(m, 255);
+      }
       if ((f & 1) && !(f & 2)) {
-        const int x = r % RW, y = r / RW;
-        const int gi = ox - K + x, gj = oy - K + y;
-        // neighbours, clamped at the box edge; outside the region: the node itself
-        // (such nodes are beyond the valid region of this sweep)
-        const int rxm = (gi == 0 || x == 0) ? r : r - 1;
-        const int rxp = (gi == I.nx - 1 || x == RW - 1) ? r : r + 1;
-        const int rym = (gj == 0 || y == 0) ? r : r - RW;
-        const int ryp = (gj == I.ny - 1 || y == RH - 1) ? r : r + RW;
         const double sg = (double)((f >> 2) & 3) - 1.0;
         const double ax = sg * snx[r], ay = sg * sny[r];
         double up = fmax(ax, 0.0) * (vc - cur[rxm]) + fmin(ax, 0.0) * (cur[rxp] - vc);
@@ -308,8 +343,10 @@ __global__ __launch_bounds__(256) void extend_group_kernel(const LsInst* __restr
     double* t = cur; cur = nxt; nxt = t;
   }
   const int l = threadIdx.x;
-  const double res = cur[(l / X + K) * RW + (l % X + K)];
+  const int rl = (l / X + K) * RW + (l % X + K);
+  const double res = cur[rl];
   if (w.in) arr(I, out_arr)[w.id] = res;
+  if (w.in && dil) glb(I.dist)[w.id] = sd[nsweep & 1][rl];
   if (do_max) {
     sm[threadIdx.x] = w.in ? res : 0.0;
     __syncthreads();
@@ -328,7 +365,7 @@ __global__ __launch_bounds__(256) void extend_group_kernel(const LsInst* __restr
 template <int DIM>
 __global__ __launch_bounds__(256) void reinit_check_kernel(const LsInst* __restrict__ insts,
                                                            const int* __restrict__ off, int count) {
-  const Where w = locate<DIM>(insts, off, count, LS_FULL);
+  const Where w = locate<DIM>(insts, off, count, LS_ROW_FULL);
   if (!w.in) return;
   const LsInst& I = *w.I;
   if (!(fabs(glb((const double*)I.rho)[w.id]) < REINIT_BAND * I.h)) return;
@@ -351,7 +388,7 @@ __global__ __launch_bounds__(256) void reinit_check_kernel(const LsInst* __restr
 template <int DIM>
 __global__ __launch_bounds__(256) void velocity_kernel(const LsInst* __restrict__ insts,
                                                        const int* __restrict__ off, int count, int uext_arr) {
-  const Where w = locate<DIM>(insts, off, count, LS_V);
+  const Where w = locate<DIM>(insts, off, count, LS_ROW_V + VEL_ITERS + 1);
   if (!w.in) return;
   const LsInst& I = *w.I;
   gptr<const double> ue = arr(I, uext_arr);
@@ -360,10 +397,14 @@ __global__ __launch_bounds__(256) void velocity_kernel(const LsInst* __restrict_
   double v = 0.0;
   if (band) {
     double s = 0.0;
+    bool reach = true;
     for (int d = 0; d < DIM; ++d) {
-      const double g = (ue[shifted(I, w, d, 1)] - ue[shifted(I, w, d, -1)]) / (2.0 * I.h);
+      const size_t ip = shifted(I, w, d, 1), im = shifted(I, w, d, -1);
+      reach = reach && in_reach(I, ip) && in_reach(I, im);
+      const double g = (ue[ip] - ue[im]) / (2.0 * I.h);
       s += g * g;
     }
+    if (!reach) atomicCAS(I.status, 0, ST_FRONT);
     v = I.mu * sqrt(s);
     kn[w.id] |= (uint8_t)8;
   } else {
@@ -434,7 +475,7 @@ __device__ __forceinline__ int substeps(const LsInst& I, double dt) {
 template <int DIM>
 __global__ __launch_bounds__(256) void rk_kernel(const LsInst* __restrict__ insts, const int* __restrict__ off,
                                                  int count, int reinit, int stage, int q, double dt, int first) {
-  const Where w = locate<DIM>(insts, off, count, LS_R);
+  const Where w = locate<DIM>(insts, off, count, LS_ROW_V + LS_V_MAX);
   if (!w.in) return;
   const LsInst& I = *w.I;
   double step;
@@ -481,15 +522,24 @@ __global__ __launch_bounds__(256) void rk_kernel(const LsInst* __restrict__ inst
   }
 }
 
-// whole box: u = comp(rho_new) ? u_ext : 0, or u = u_ext everywhere (all)
+// whole box: u = comp(rho_new) ? u_ext : 0 (a computational point beyond
+// the reach of the extension: ST_FRONT), or (all) u = u_ext within the reach
+// of the extension and 0 beyond (what the step reads of it)
 template <int DIM>
 __global__ __launch_bounds__(256) void restrict_kernel(const LsInst* __restrict__ insts,
                                                        const int* __restrict__ off, int count, int uext_arr,
                                                        int all) {
-  const Where w = locate<DIM>(insts, off, count, LS_FULL);
+  const Where w = locate<DIM>(insts, off, count, LS_ROW_FULL);
   if (!w.in) return;
   const LsInst& I = *w.I;
-  const bool c = all || comp_point<DIM>(I, w, glb((const double*)I.rho));
+  const bool reach = in_reach(I, w.id);
+  bool c;
+  if (all) {
+    c = reach;
+  } else {
+    c = comp_point<DIM>(I, w, glb((const double*)I.rho));
+    if (c && !reach) atomicCAS(I.status, 0, ST_FRONT);
+  }
   glb(I.u)[w.id] = c ? arr(I, uext_arr)[w.id] : 0.0;
 }
 
@@ -499,37 +549,43 @@ hipError_t begin_dim(LevelsetBatch& b, hipStream_t st, bool speed) {
   const LsInst* I = b.d_inst;
   const int* off = b.d_off;
   const dim3 B(256);
-#define LL(list, kernel, ...)                                                                \
+#define LL(row, kernel, ...)                                                                 \
   do {                                                                                       \
-    if (b.total[list] > 0) {                                                                 \
-      hipLaunchKernelGGL(kernel<DIM>, dim3(b.total[list]), B, 0, st, I, off, n, ##__VA_ARGS__); \
+    if (b.total[row] > 0) {                                                                  \
+      hipLaunchKernelGGL(kernel<DIM>, dim3(b.total[row]), B, 0, st, I, off, n, ##__VA_ARGS__); \
       hipError_t _e = hipGetLastError();                                                     \
       if (_e != hipSuccess) return _e;                                                       \
     }                                                                                        \
   } while (0)
-  LL(LS_FULL, zero_kernel);
-  LL(LS_U, init_kernel);
-  LL(LS_A1, known1_kernel);
-  LL(LS_A1, known2_un_kernel);
-  LL(LS_A1, unn_kernel);
-  // Aslam: u_nn on A1 (E2 <-> E3, result E3), u_n on A2 (E1 <-> E2, src u_nn,
-  // result E2), u on A3 (E0 <-> E1, src u_n, result E1); each stage's array
-  // alternates once per launch (2D: SWEEP_GROUP sweeps per launch, 3D: one),
-  // the launch counts per stage are odd, and each partner array is 0 outside
-  // its stage's list
+  LL(LS_ROW_FULL, zero_kernel);
+  LL(LS_ROW_U, init_kernel);
+  LL(LS_ROW_C + ASLAM_ITERS + 1, known1_kernel);
+  LL(LS_ROW_C + ASLAM_ITERS + 1, known2_un_kernel);
+  LL(LS_ROW_C + ASLAM_ITERS + 1, unn_kernel);
+  // Aslam: u_nn (E2 <-> E3, result E3), u_n (E1 <-> E2, src u_nn, result E2),
+  // u (E0 <-> E1, src u_n, result E1); each stage's array alternates once
+  // per launch (2D: SWEEP_GROUP sweeps per launch, 3D: one), and the launch
+  // counts per stage are odd.  row(s0, s1) gives the list prefix of a launch
+  // of sweeps s0..s1 (1-based) from the stage's cone (see levelset.h):
+  //   u_nn grows from K2:            radius s1
+  //   u_n grows from u_nn's support: radius ASLAM_ITERS + s1
+  //   u shrinks to the read region:  radius LS_READ_REACH + ASLAM_ITERS - s0 + 1
+  //   the speed grows from |rho| < h: SV radius s1
   const int group = (DIM == 2) ? SWEEP_GROUP : 1;
-  auto stage = [&](int list, int a0, int a1, int src, int bit, int sign_rho, int sweeps, int do_max) -> int {
+  auto stage = [&](auto row, int a0, int a1, int src, int bit, int sign_rho, int sweeps, int do_max,
+                   int dil) -> int {
     int v = a0, t = a1;
     for (int done = 0; done < sweeps;) {
       const int ns = (sweeps - done < group) ? sweeps - done : group;
       const int mx = (do_max && done + ns == sweeps) ? 1 : 0;
-      if (b.total[list] > 0) {
+      const int r = row(done + 1, done + ns);
+      if (b.total[r] > 0) {
         if (DIM == 2)
-          hipLaunchKernelGGL(extend_group_kernel, dim3(b.total[list]), B, 0, st, I, off, n, list, v, t, src, bit,
-                             sign_rho, mx, ns);
+          hipLaunchKernelGGL(extend_group_kernel, dim3(b.total[r]), B, 0, st, I, off, n, r, v, t, src, bit, sign_rho,
+                             mx, ns, dil);
         else
-          hipLaunchKernelGGL(extend_kernel<DIM>, dim3(b.total[list]), B, 0, st, I, off, n, list, v, t, src, bit,
-                             sign_rho, mx);
+          hipLaunchKernelGGL(extend_kernel<DIM>, dim3(b.total[r]), B, 0, st, I, off, n, r, v, t, src, bit, sign_rho,
+                             mx, dil);
         if (hipGetLastError() != hipSuccess) return -1;
       }
       done += ns;
@@ -541,17 +597,24 @@ hipError_t begin_dim(LevelsetBatch& b, hipStream_t st, bool speed) {
                 "the Aslam stages must end in the partner array");
   static_assert((VEL_ITERS + SWEEP_GROUP - 1) / SWEEP_GROUP % 2 == 0 && VEL_ITERS % 2 == 0,
                 "the speed extension must end in V");
-  const int iters = ASLAM_ITERS;
-  const int l2 = LS_A2, l3 = LS_A3;
-  const int unn = stage(LS_A1, A_E2, A_E3, -1, 2, 0, iters, 0);
-  const int un = stage(l2, A_E1, A_E2, A_E3, 1, 0, iters, 0);
-  const int uext = stage(l3, A_E0, A_E1, A_E2, 0, 0, iters, 0);
+  static_assert(LS_READ_REACH + ASLAM_ITERS <= LS_C_MAX, "the u stage's cone must lie in list SC");
+  static_assert(LS_READ_REACH <= ASLAM_ITERS, "the distance is dilated by the u_nn sweeps");
+  // the u_nn stage (lists growing one node per sweep from the computational
+  // points) also dilates the distance to them
+  auto cap = [](int r) { return r < LS_C_MAX ? r : LS_C_MAX; };
+  const int unn = stage([&](int, int s1) { return LS_ROW_C + cap(s1); }, A_E2, A_E3, -1, 2, 0, ASLAM_ITERS, 0, 1);
+  const int un = stage([&](int, int s1) { return LS_ROW_C + cap(ASLAM_ITERS + s1); }, A_E1, A_E2, A_E3, 1, 0,
+                       ASLAM_ITERS, 0, 0);
+  const int uext = stage([&](int s0, int) { return LS_ROW_C + cap(LS_READ_REACH + ASLAM_ITERS - s0 + 1); }, A_E0,
+                         A_E1, A_E2, 0, 0, ASLAM_ITERS, 0, 0);
   if (unn != A_E3 || un != A_E2 || uext != A_E1) return hipErrorUnknown;
   b.uext = uext;
   if (!speed) return hipSuccess;
   // Stefan speed, extension V <-> S (ends in V), maximum on the last sweep
-  LL(LS_V, velocity_kernel, b.uext);
-  if (stage(LS_V, A_V, A_S, -1, 3, 1, VEL_ITERS, 1) != A_V) return hipErrorUnknown;
+  LL(LS_ROW_V + VEL_ITERS + 1, velocity_kernel, b.uext);
+  auto vcap = [](int r) { return r < LS_V_MAX ? r : LS_V_MAX; };
+  if (stage([&](int, int s1) { return LS_ROW_V + vcap(s1); }, A_V, A_S, -1, 3, 1, VEL_ITERS, 1, 0) != A_V)
+    return hipErrorUnknown;
 #undef LL
   return hipSuccess;
 }
@@ -569,26 +632,27 @@ hipError_t end_dim(LevelsetBatch& b, hipStream_t st) {
     if (ns > nsub) nsub = ns;
   }
   hipError_t e;
-  if (b.total[LS_R] > 0) {
+  const int rrow = LS_ROW_V + LS_V_MAX;
+  if (b.total[rrow] > 0) {
     for (int q = 0; q < nsub; ++q)
       for (int s = 1; s <= 3; ++s) {
-        hipLaunchKernelGGL(rk_kernel<DIM>, dim3(b.total[LS_R]), B, 0, st, I, off, n, 0, s, q, b.dt, 0);
+        hipLaunchKernelGGL(rk_kernel<DIM>, dim3(b.total[rrow]), B, 0, st, I, off, n, 0, s, q, b.dt, 0);
         if ((e = hipGetLastError()) != hipSuccess) return e;
       }
   }
   if (b.reinit) {
-    hipLaunchKernelGGL(reinit_check_kernel<DIM>, dim3(b.total[LS_FULL]), B, 0, st, I, off, n);
+    hipLaunchKernelGGL(reinit_check_kernel<DIM>, dim3(b.total[LS_ROW_FULL]), B, 0, st, I, off, n);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    if (b.total[LS_R] > 0) {
+    if (b.total[rrow] > 0) {
       for (int it = 0; it < REINIT_ITERS; ++it)
         for (int s = 1; s <= 3; ++s) {
-          hipLaunchKernelGGL(rk_kernel<DIM>, dim3(b.total[LS_R]), B, 0, st, I, off, n, 1, s, 0, 0.0,
+          hipLaunchKernelGGL(rk_kernel<DIM>, dim3(b.total[rrow]), B, 0, st, I, off, n, 1, s, 0, 0.0,
                              (it == 0 && s == 1) ? 1 : 0);
           if ((e = hipGetLastError()) != hipSuccess) return e;
         }
     }
   }
-  hipLaunchKernelGGL(restrict_kernel<DIM>, dim3(b.total[LS_FULL]), B, 0, st, I, off, n, b.uext, 0);
+  hipLaunchKernelGGL(restrict_kernel<DIM>, dim3(b.total[LS_ROW_FULL]), B, 0, st, I, off, n, b.uext, 0);
   return hipGetLastError();
 }
 
@@ -596,7 +660,7 @@ template <int DIM>
 hipError_t extend_dim(LevelsetBatch& b, hipStream_t st) {
   hipError_t e = begin_dim<DIM>(b, st, false);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(restrict_kernel<DIM>, dim3(b.total[LS_FULL]), dim3(256), 0, st, b.d_inst, b.d_off, b.count,
+  hipLaunchKernelGGL(restrict_kernel<DIM>, dim3(b.total[LS_ROW_FULL]), dim3(256), 0, st, b.d_inst, b.d_off, b.count,
                      b.uext, 1);
   return hipGetLastError();
 }
@@ -612,12 +676,17 @@ hipError_t levelset_alloc(LevelsetScratch& s, size_t nodes) {
   if (e != hipSuccess) return e;
   e = hipMalloc(&s.known, nodes);
   if (e != hipSuccess) return e;
-  return hipMemset(s.known, 0, nodes);
+  e = hipMemset(s.known, 0, nodes);
+  if (e != hipSuccess) return e;
+  e = hipMalloc(&s.dist, nodes);
+  if (e != hipSuccess) return e;
+  return hipMemset(s.dist, 255, nodes);
 }
 
 void levelset_free(LevelsetScratch& s) {
   if (s.buf) (void)hipFree(s.buf);
   if (s.known) (void)hipFree(s.known);
+  if (s.dist) (void)hipFree(s.dist);
   s = LevelsetScratch{};
 }
 
@@ -627,8 +696,8 @@ hipError_t levelset_batch_alloc(LevelsetBatch& b, int count, int dim) {
   hipError_t e;
   if ((e = hipMalloc(&b.d_inst, sizeof(LsInst) * count)) != hipSuccess) return e;
   if ((e = hipHostMalloc(&b.h_inst, sizeof(LsInst) * count)) != hipSuccess) return e;
-  if ((e = hipMalloc(&b.d_off, sizeof(int) * (LS_NLIST + 1) * (count + 1))) != hipSuccess) return e;
-  if ((e = hipHostMalloc(&b.h_off, sizeof(int) * (LS_NLIST + 1) * (count + 1))) != hipSuccess) return e;
+  if ((e = hipMalloc(&b.d_off, sizeof(int) * LS_NROWS * (count + 1))) != hipSuccess) return e;
+  if ((e = hipHostMalloc(&b.h_off, sizeof(int) * LS_NROWS * (count + 1))) != hipSuccess) return e;
   if ((e = hipMalloc(&b.d_vmax, sizeof(double) * count)) != hipSuccess) return e;
   if ((e = hipHostMalloc(&b.h_vmax, sizeof(double) * count)) != hipSuccess) return e;
   for (int i = 0; i < count; ++i) b.h_inst[i] = LsInst{};
@@ -650,12 +719,15 @@ namespace {
 // Launch offsets of the lists and the device copy of the instance table.
 hipError_t upload(LevelsetBatch& b, hipStream_t st) {
   const int n = b.count;
-  for (int q = 0; q <= LS_NLIST; ++q) {
+  for (int q = 0; q < LS_NROWS; ++q) {
     int acc = 0;
     for (int i = 0; i < n; ++i) {
       const LsInst& I = b.h_inst[i];
       b.h_off[q * (n + 1) + i] = acc;
-      acc += (q == LS_FULL) ? I.ntx * I.nty * I.ntz : I.nband[q];
+      if (q == LS_ROW_FULL) acc += I.ntx * I.nty * I.ntz;
+      else if (q == LS_ROW_U) acc += I.nu;
+      else if (q >= LS_ROW_V) acc += I.ncum_v[q - LS_ROW_V];
+      else acc += I.ncum_c[q - LS_ROW_C];
     }
     b.h_off[q * (n + 1) + n] = acc;
     b.total[q] = acc;
@@ -664,7 +736,7 @@ hipError_t upload(LevelsetBatch& b, hipStream_t st) {
   hipError_t e;
   if ((e = hipMemcpyAsync(b.d_inst, b.h_inst, sizeof(LsInst) * n, hipMemcpyHostToDevice, st)) != hipSuccess)
     return e;
-  return hipMemcpyAsync(b.d_off, b.h_off, sizeof(int) * (LS_NLIST + 1) * (n + 1), hipMemcpyHostToDevice, st);
+  return hipMemcpyAsync(b.d_off, b.h_off, sizeof(int) * LS_NROWS * (n + 1), hipMemcpyHostToDevice, st);
 }
 
 }  // namespace
