@@ -506,7 +506,10 @@ def main():
             "whole": prof["krylov_device_ms"] / steps,
             "in_grid_sync": prof["krylov_sync_ms"] / steps,
             "in_expm": prof["krylov_expm_ms"] / steps,
-            "in_tile_loops": prof["krylov_tiles_ms"] / steps,
+            "in_passes": prof["krylov_pass_ms"] / steps,
+            "in_prologue": prof["krylov_prologue_ms"] / steps,
+            "other_control": (prof["krylov_device_ms"] - prof["krylov_sync_ms"] - prof["krylov_expm_ms"]
+                              - prof["krylov_pass_ms"] - prof["krylov_prologue_ms"]) / steps,
             "syncs": prof["krylov_syncs"] / steps,
             "expms": prof["krylov_expms"] / steps,
         },

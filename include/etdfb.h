@@ -136,11 +136,15 @@ typedef struct {
   int32_t n_unknowns;        /* computational points of the current geometry */
   /* inside the Krylov launches, from the device clock of block 0: whole
    * launches, grid synchronisations (waiting included), small exponentials,
-   * tile loops of the passes */
+   * passes over the tiles (from the start of a tile loop until every wave
+   * of the block has finished it and the block has reduced its partials),
+   * launch prologue (tile metadata into LDS); the rest is control between
+   * passes */
   double krylov_device_ms;
   double krylov_sync_ms;
   double krylov_expm_ms;
-  double krylov_tiles_ms;
+  double krylov_pass_ms;
+  double krylov_prologue_ms;
   int32_t krylov_syncs;
   int32_t krylov_expms;
 } etd_profile;

@@ -67,7 +67,7 @@ class EtdProfile(C.Structure):
                 ("alg_bytes", C.c_double), ("krylov_launches", C.c_int32), ("levelset_calls", C.c_int32),
                 ("geometry_calls", C.c_int32), ("n_unknowns", C.c_int32),
                 ("krylov_device_ms", C.c_double), ("krylov_sync_ms", C.c_double), ("krylov_expm_ms", C.c_double),
-                ("krylov_tiles_ms", C.c_double),
+                ("krylov_pass_ms", C.c_double), ("krylov_prologue_ms", C.c_double),
                 ("krylov_syncs", C.c_int32), ("krylov_expms", C.c_int32)]
 
     def as_dict(self):

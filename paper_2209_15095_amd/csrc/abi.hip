@@ -950,7 +950,8 @@ int etd_ctx_profile_read(etd_ctx* c, etd_profile* out, int32_t reset) {
   out->krylov_device_ms = c->h_state->ticks_total / c->clock_khz;
   out->krylov_sync_ms = c->h_state->ticks_sync / c->clock_khz;
   out->krylov_expm_ms = c->h_state->ticks_expm / c->clock_khz;
-  out->krylov_tiles_ms = c->h_state->ticks_tiles / c->clock_khz;
+  out->krylov_pass_ms = c->h_state->ticks_pass / c->clock_khz;
+  out->krylov_prologue_ms = c->h_state->ticks_pro / c->clock_khz;
   out->krylov_syncs = c->h_state->syncs;
   out->krylov_expms = c->h_state->expm_calls;
   if (reset) {
@@ -1459,7 +1460,8 @@ int etd_batch_profile_read(etd_batch* B, etd_profile* out, int32_t reset) {
   out->krylov_device_ms = c0->h_state->ticks_total / c0->clock_khz;
   out->krylov_sync_ms = c0->h_state->ticks_sync / c0->clock_khz;
   out->krylov_expm_ms = c0->h_state->ticks_expm / c0->clock_khz;
-  out->krylov_tiles_ms = c0->h_state->ticks_tiles / c0->clock_khz;
+  out->krylov_pass_ms = c0->h_state->ticks_pass / c0->clock_khz;
+  out->krylov_prologue_ms = c0->h_state->ticks_pro / c0->clock_khz;
   out->krylov_syncs = c0->h_state->syncs;
   out->krylov_expms = c0->h_state->expm_calls;
   if (reset) {

@@ -82,9 +82,9 @@ struct KrylovStateDev {
   double alg_bytes_per_unknown;   // algorithmic HBM bytes per unknown, last launch
   double alg_bytes_total;         // accumulated over launches: bytes/unknown * unknowns
   // device-clock ticks accumulated over launches (block 0 of the group):
-  // whole launch, inside grid synchronisations, inside the small
-  // exponentials, inside the tile loops of the passes
-  double ticks_total, ticks_sync, ticks_expm, ticks_tiles;
+  // whole launch, grid synchronisations, small exponentials, passes (tile
+  // loops and block reductions), launch prologue
+  double ticks_total, ticks_sync, ticks_expm, ticks_pass, ticks_pro;
   int syncs, expm_calls;
 };
 

@@ -265,9 +265,11 @@ struct Engine {
   // and write per computational point (vectors only; neighbour re-reads,
   // masks and tile padding are not counted).
   double bpu;
-  // device-clock ticks spent in synchronisations and exponentials (kept by
-  // thread 0 of block 0 of the group)
-  unsigned long long tk_sync, tk_expm, tk_tiles;
+  // device-clock ticks (kept by thread 0 of block 0 of the group): passes
+  // (from the start of a pass's tile loop until every wave of the block is
+  // done and the block has reduced its partials), grid synchronisations,
+  // small exponentials, the launch prologue; t_mark: start of the current pass
+  unsigned long long tk_sync, tk_expm, tk_pass, tk_pro, t_mark;
   int n_sync;
 
   __device__ __forceinline__ gptr<double> V(int i) const { return glb(P.ws) + (size_t)i * P.ld; }
@@ -288,11 +290,11 @@ struct Engine {
   }
 
   // Grid synchronisation fused with the reduction of NR per-block partials.
-  // Every wave waits for its own stores, one agent-scope release per block
-  // publishes them, lane 0 writes the block's partials and then its arrival
-  // generation into its own flag; wave 0 polls every flag (no contended
-  // atomic), acquires, and sums the partials in block order, so every block
-  // obtains bit-identical results.  Polls are bounded: past SPIN_LIMIT the
+  // Every wave waits for its own stores; lane 0 writes the block's partials,
+  // one agent-scope release publishes them with the pass's stores, then it
+  // writes its arrival generation into its own flag; wave 0 polls every flag
+  // (no contended atomic), acquires, and sums the partials in block order, so
+  // every block obtains bit-identical results.  Polls are bounded: past SPIN_LIMIT the
   // abort flag goes up and every block leaves.
   template <int NR>
   __device__ __forceinline__ bool grid_sync(const double (&acc)[NR], double (&out)[NR]) {
@@ -305,7 +307,6 @@ struct Engine {
     if (threadIdx.x < 64) {
       const int lane = threadIdx.x;
       if (lane == 0) {
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         for (int k = 0; k < NR; ++k) part[(size_t)lb * PART_STRIDE + k] = acc[k];
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         __hip_atomic_store(&P.flags[lb], gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -355,6 +356,7 @@ struct Engine {
   template <int NR>
   __device__ __forceinline__ bool finish(double (&acc)[NR], double (&out)[NR]) {
     block_sum<NR>(acc, c.scratch);
+    if (threadIdx.x == 0 && lb == 0) tk_pass += wall_clock64() - t_mark;
     if (G == 1) {
       for (int k = 0; k < NR; ++k) out[k] = acc[k];
     } else if (!grid_sync<NR>(acc, out)) {
@@ -371,10 +373,9 @@ struct Engine {
   }
 
   __device__ __forceinline__ bool barrier() {
-    if (G == 1) {
-      __syncthreads();
-      return true;
-    }
+    __syncthreads();
+    if (threadIdx.x == 0 && lb == 0) tk_pass += wall_clock64() - t_mark;
+    if (G == 1) return true;
     double a[1] = {0.0}, o[1];
     if (!grid_sync<1>(a, o)) {
       if (threadIdx.x == 0) atomicCAS(P.status, 0, ST_BARRIER);
@@ -489,7 +490,7 @@ struct Engine {
     const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int stride = G * KTILES;
     int slot = tile_block() * KTILES + sub;
-    const unsigned long long t_in = wall_clock64();
+    if (threadIdx.x == 0 && lb == 0) t_mark = wall_clock64();
     Meta m;
     if (slot < nact) trip_meta(m, 0, slot, sub, w);
     for (int r = 0; slot < nact; ++r) {
@@ -500,7 +501,6 @@ struct Engine {
       f(t);
       slot = next;
     }
-    if (threadIdx.x == 0 && lb == 0) tk_tiles += wall_clock64() - t_in;
   }
 
   // Variable beta: sum_f w_f v_f + dg v_p from the face values nv (order
@@ -746,7 +746,7 @@ struct Engine {
     const int stride = G * KTILES;
     const int base0 = tile_block() * KTILES;
     double acc[2] = {0.0, 0.0};
-    const unsigned long long t_in = wall_clock64();
+    if (threadIdx.x == 0 && lb == 0) t_mark = wall_clock64();
     // loads of trip r: the point and the halo nodes (0 where no tile)
     double pz, p1, p2, hz[HR], h1[HR], h2[HR];
     // metadata of trip r from the LDS cache (the caller uses this pass only
@@ -845,7 +845,6 @@ struct Engine {
       }
       __syncthreads();   // LDS free for the exponential
     }
-    if (threadIdx.x == 0 && lb == 0) tk_tiles += wall_clock64() - t_in;
     bpu += 32.0;
     return finish<2>(acc, out);
   }
@@ -860,13 +859,12 @@ struct Engine {
   // (NOT_COMP elsewhere).  The q_k buffer alternates between two LDS halves
   // by trip parity, so two block barriers per trip suffice.
   __device__ __forceinline__ bool lanczos_zf2(int k, double (&out)[2]) {
-    const unsigned long long t_in = wall_clock64();
+    if (threadIdx.x == 0 && lb == 0) t_mark = wall_clock64();
     double acc[2];
     zf2_loop(uniform<const double>(V(V_Q0 + k - 1)), uniform<const double>(V(V_Q0 + (k >= 2 ? k - 2 : 0))),
              uniform<double>(V(V_Q0 + k)), uniform<const double>(glb(P.g.cdiag)), P.g.coef, c.alpha[k - 1],
              1.0 / c.nrm[k - 1], (k >= 2) ? c.nrm[k - 1] / c.nrm[k - 2] : 0.0, nact, G, tile_block(), lds(R),
              lds((const int*)&c.mnb[0][0][0]), acc);
-    if (threadIdx.x == 0 && lb == 0) tk_tiles += wall_clock64() - t_in;
     bpu += 32.0;
     return finish<2>(acc, out);
   }
@@ -1543,8 +1541,9 @@ struct Engine {
     }
   }
 
-  __device__ __forceinline__ void run() {
+  __device__ __forceinline__ void run(unsigned long long t_start) {
     cache_meta();
+    if (threadIdx.x == 0 && lb == 0) tk_pro = wall_clock64() - t_start;
     const int mode = P.mode;
     if (mode == JOB_APPLY) {
       tiles([&](const Tile& t) {
@@ -1582,7 +1581,7 @@ template <int DIM>
 __device__ __forceinline__ void krylov_body(const KrylovDev& P, int lb, int G, Ctl& c, double* R, double* S) {
   const unsigned long long t_start = wall_clock64();
   Engine<DIM> e{P, c, R, S, *P.g.n_active, 0, lb, G};
-  e.tk_sync = e.tk_expm = e.tk_tiles = 0;
+  e.tk_sync = e.tk_expm = e.tk_pass = e.tk_pro = e.t_mark = 0;
   e.n_sync = 0;
   for (int k = 0; k <= PMAX; ++k) {
     if (threadIdx.x == 0) {
@@ -1598,7 +1597,7 @@ __device__ __forceinline__ void krylov_body(const KrylovDev& P, int lb, int G, C
   e.bpu = 0.0;
   e.sp_stride = (size_t)(e.nact / (P.species > 1 ? P.species : 1)) * TILE_PTS;
   __syncthreads();
-  e.run();
+  e.run(t_start);
   __syncthreads();
   if (threadIdx.x == 0 && lb == 0) {
     for (int k = 0; k <= PMAX; ++k) {
@@ -1618,7 +1617,8 @@ __device__ __forceinline__ void krylov_body(const KrylovDev& P, int lb, int G, C
     P.st->ticks_total += (double)(wall_clock64() - t_start);
     P.st->ticks_sync += (double)e.tk_sync;
     P.st->ticks_expm += (double)e.tk_expm;
-    P.st->ticks_tiles += (double)e.tk_tiles;
+    P.st->ticks_pass += (double)e.tk_pass;
+    P.st->ticks_pro += (double)e.tk_pro;
     P.st->syncs += e.n_sync;
     P.st->expm_calls += e.expms;
   }
