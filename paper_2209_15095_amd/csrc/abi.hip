@@ -280,7 +280,15 @@ int gather_to(etd_ctx* c, const double* box, int vec) {
                                  c->ws + (size_t)vec * c->ld, grid, c->stream));
 }
 
-int scatter_from(etd_ctx* c, int vec, double* box) {
+// tiles: box is already 0 at every node outside the active tiles (u after
+// a level-set step: the restriction wrote it over the whole box), so only
+// the active tiles are written.
+int scatter_from(etd_ctx* c, int vec, double* box, bool tiles = false) {
+  if (tiles) {
+    const int grid = c->n_active_host > 0 ? c->n_active_host : 1;
+    return check_hip(launch_scatter_tiles(c->box, c->ws + (size_t)vec * c->ld, c->slot_tile, c->comp_bits,
+                                          c->counters + 0, box, grid, c->stream));
+  }
   return check_hip(launch_scatter(c->box, c->ws + (size_t)vec * c->ld, c->tile_map, c->comp_bits, box,
                                   c->stream));
 }
@@ -374,7 +382,7 @@ int geometry_finish(etd_ctx* c, const int* cnt) {
 }
 
 // The level-set view of a context (its scratch, band and the user arrays).
-LsInst levelset_inst(const etd_ctx* c, double* rho, double* u) {
+LsInst levelset_inst(etd_ctx* c, double* rho, double* u) {
   LsInst I{};
   I.dim = c->box.dim;
   I.nx = c->box.nx; I.ny = c->box.ny; I.nz = c->box.nz;
@@ -394,6 +402,7 @@ LsInst levelset_inst(const etd_ctx* c, double* rho, double* u) {
   I.tdist = c->band_tmp + (size_t)((c->box.dim - 1) & 1) * c->ntiles;
   I.rr = LS_V_MAX;
   I.status = c->counters + 1;
+  I.host_dirty = &c->ls.dirty;
   return I;
 }
 
@@ -811,7 +820,7 @@ int etd_step(etd_ctx* c, int32_t scheme, double h, double* u, double* rho, int32
   P.h = h;
   r = run_krylov(c, P);
   if (r) return r;
-  r = scatter_from(c, V_U, u);
+  r = scatter_from(c, V_U, u, rho != nullptr);
   if (r) return r;
   if (stats) {
     r = fill_stats(c, stats);
@@ -884,7 +893,7 @@ int etd_multistep_step(etd_ctx* c, double h, double* u, double* f_prev, int32_t 
   P.first = first ? 1 : 0;
   r = run_krylov(c, P);
   if (r) return r;
-  r = scatter_from(c, V_U, u);
+  r = scatter_from(c, V_U, u, rho != nullptr);
   if (r) return r;
   r = scatter_from(c, V_G, f_prev);
   if (r) return r;
@@ -1659,11 +1668,11 @@ extern "C" int phi_combination_apply_static(const etd_grid* grid, double beta, c
   do {
     // block prefixes: computed on the host, copied into the array
     {
-      const int per[GEOM_NPRE] = {(int)((c.nodes + 255) / 256), (c.ntiles + 255) / 256, c.ntiles};
       for (int q = 0; q < GEOM_NPRE; ++q) {
+        const int per = geom_blocks_per(q, c.nodes, c.ntiles);
         h_pre[q * 2] = 0;
-        h_pre[q * 2 + 1] = per[q];
-        c.gb.blocks[q] = per[q];
+        h_pre[q * 2 + 1] = per;
+        c.gb.blocks[q] = per;
       }
       if (hipMemcpyAsync(c.gb.d_pre, h_pre, sizeof(h_pre), hipMemcpyHostToDevice, c.stream) != hipSuccess) {
         result = ETD_ERR_HIP;

@@ -501,11 +501,19 @@ __global__ void forcing_kernel(BoxDev b, const int* __restrict__ tile_map, const
   }
 }
 
-// grid = one block (256 threads) per box tile; inactive tiles return.
+// Blocks loop over the instance's active tiles (slots, after the scan).
+__device__ __forceinline__ void tile_coeff(const GeomInst& I, int slot);
+
 __global__ __launch_bounds__(256) void tile_coeff_kernel(const GeomInst* __restrict__ tab,
                                                          const int* __restrict__ pre, int count) {
   const int inst = instance_of(pre, count, (int)blockIdx.x);
   const GeomInst& I = tab[inst];
+  const int nblk = pre[inst + 1] - pre[inst];
+  const int nact = I.counters[0];
+  for (int slot = (int)blockIdx.x - pre[inst]; slot < nact; slot += nblk) tile_coeff(I, slot);
+}
+
+__device__ __forceinline__ void tile_coeff(const GeomInst& I, int slot) {
   const BoxDev& b = I.b;
   const double* __restrict__ rho = I.rho;
   const uint8_t* __restrict__ mask = I.mask;
@@ -515,9 +523,7 @@ __global__ __launch_bounds__(256) void tile_coeff_kernel(const GeomInst* __restr
   double* __restrict__ cdiag = I.cdiag;
   int* __restrict__ nbr = I.nbr;
   int* __restrict__ counts = I.counters + 2;
-  const int t = (int)(blockIdx.x - pre[inst]);
-  const int slot = tile_map[t];
-  if (slot < 0) return;
+  const int t = I.slot_tile[slot];
   const int tcx = t % b.ntx, tcy = (t / b.ntx) % b.nty, tcz = t / (b.ntx * b.nty);
   const int l = threadIdx.x;
   if (l < NBR_STRIDE) {
@@ -635,18 +641,39 @@ __global__ void scatter_kernel(BoxDev b, const double* __restrict__ vec, const i
     scatter_node(b, vec, tile_map, comp_bits, box, id);
 }
 
+// tile layout -> box over the active tiles only: computational nodes get the
+// vector, the tiles' other nodes 0; nodes outside the active tiles are not
+// written.
+__global__ __launch_bounds__(256) void scatter_tiles_kernel(BoxDev b, const double* __restrict__ vec,
+                                                            const int* __restrict__ slot_tile,
+                                                            const uint64_t* __restrict__ comp_bits,
+                                                            const int* __restrict__ n_active,
+                                                            double* __restrict__ box) {
+  const int nact = *n_active;
+  const int l = threadIdx.x;
+  const int lx = l % b.tx, ly = (l / b.tx) % b.ty, lz = l / (b.tx * b.ty);
+  for (int slot = blockIdx.x; slot < nact; slot += gridDim.x) {
+    const int t = slot_tile[slot];
+    const int i = (t % b.ntx) * b.tx + lx;
+    const int j = ((t / b.ntx) % b.nty) * b.ty + ly;
+    const int k = (t / (b.ntx * b.nty)) * b.tz + lz;
+    if (i < b.nx && j < b.ny && k < b.nz)
+      box[node_index(b, i, j, k)] = bit_of(comp_bits, slot, l) ? vec[(size_t)slot * TILE_PTS + l] : 0.0;
+  }
+}
+
 // Batched transfers between the user box arrays boxes[i] and vector `vec`
-// of each instance's workspace: gather with one block per box tile of each
-// instance (prefix pre; blocks past the active tiles return), scatter with
-// 256 nodes per block (prefix pre).
+// of each instance's workspace: gather with blocks looping over each
+// instance's active tiles (prefix pre), scatter with 256 nodes per block
+// (prefix pre).
 __global__ __launch_bounds__(256) void gather_batch_kernel(const GeomInst* __restrict__ tab,
                                                            const int* __restrict__ pre, int count,
                                                            const double* const* __restrict__ boxes, int vec) {
   const int inst = instance_of(pre, count, (int)blockIdx.x);
   const GeomInst& I = tab[inst];
-  const int slot = (int)(blockIdx.x - pre[inst]);
-  if (slot >= I.counters[0]) return;
-  gather_tile(I.b, boxes[inst], I.slot_tile, I.comp_bits, slot, I.ws + (size_t)vec * I.ld);
+  const int nblk = pre[inst + 1] - pre[inst];
+  for (int slot = (int)(blockIdx.x - pre[inst]); slot < I.counters[0]; slot += nblk)
+    gather_tile(I.b, boxes[inst], I.slot_tile, I.comp_bits, slot, I.ws + (size_t)vec * I.ld);
 }
 
 __global__ __launch_bounds__(256) void scatter_batch_kernel(const GeomInst* __restrict__ tab,
@@ -707,8 +734,7 @@ hipError_t geom_batch_prefix(GeomBatch& gb) {
   for (int q = 0; q < GEOM_NPRE; ++q) p[q * (n + 1)] = 0;
   for (int i = 0; i < n; ++i) {
     const GeomInst& I = gb.h_tab[i];
-    const int per[GEOM_NPRE] = {(int)((I.nodes + 255) / 256), (I.ntiles + 255) / 256, I.ntiles};
-    for (int q = 0; q < GEOM_NPRE; ++q) p[q * (n + 1) + i + 1] = p[q * (n + 1) + i] + per[q];
+    for (int q = 0; q < GEOM_NPRE; ++q) p[q * (n + 1) + i + 1] = p[q * (n + 1) + i] + geom_blocks_per(q, I.nodes, I.ntiles);
   }
   for (int q = 0; q < GEOM_NPRE; ++q) gb.blocks[q] = p[q * (n + 1) + n];
   return hipMemcpy(gb.d_pre, gb.h_pre, sizeof(int) * GEOM_NPRE * (n + 1), hipMemcpyHostToDevice);
@@ -808,6 +834,13 @@ hipError_t launch_gather(const BoxHost& b, const double* box, const int* slot_ti
                          const uint64_t* comp_bits, const int* n_active, double* vec, int grid,
                          hipStream_t s) {
   hipLaunchKernelGGL(gather_kernel, dim3(grid), dim3(256), 0, s, b, box, slot_tile, comp_bits, n_active, vec);
+  return hipGetLastError();
+}
+
+hipError_t launch_scatter_tiles(const BoxHost& b, const double* vec, const int* slot_tile,
+                                const uint64_t* comp_bits, const int* n_active, double* box, int grid,
+                                hipStream_t s) {
+  hipLaunchKernelGGL(scatter_tiles_kernel, dim3(grid), dim3(256), 0, s, b, vec, slot_tile, comp_bits, n_active, box);
   return hipGetLastError();
 }
 

@@ -55,7 +55,16 @@ struct GeomInst {
 // boundary points, Case 2 one).
 constexpr int TAPS_PER = 12;
 
+// Block prefixes of the batched geometry launches: 256 nodes per block,
+// 256 tiles per block, and blocks that loop over the active tiles (at most
+// GEOM_SLOT_BLOCKS per instance).
 enum { GEOM_PRE_NODE = 0, GEOM_PRE_T256 = 1, GEOM_PRE_TILE = 2, GEOM_NPRE = 3 };
+constexpr int GEOM_SLOT_BLOCKS = 2048;
+inline int geom_blocks_per(int q, size_t nodes, int ntiles) {
+  if (q == GEOM_PRE_NODE) return (int)((nodes + 255) / 256);
+  if (q == GEOM_PRE_T256) return (ntiles + 255) / 256;
+  return ntiles < GEOM_SLOT_BLOCKS ? ntiles : GEOM_SLOT_BLOCKS;
+}
 
 struct GeomBatch {
   int count = 0;
@@ -103,6 +112,10 @@ hipError_t launch_gather(const BoxHost& b, const double* box, const int* slot_ti
                          hipStream_t s);
 hipError_t launch_scatter(const BoxHost& b, const double* vec, const int* tile_map,
                           const uint64_t* comp_bits, double* box, hipStream_t s);
+// The active tiles only (the other nodes of box are left as they are).
+hipError_t launch_scatter_tiles(const BoxHost& b, const double* vec, const int* slot_tile,
+                                const uint64_t* comp_bits, const int* n_active, double* box, int grid,
+                                hipStream_t s);
 
 // krylov.hip
 hipError_t launch_krylov(int dim, const KrylovDev& P, int grid, hipStream_t s);

@@ -78,12 +78,19 @@ constexpr int LS_CNT_V = LS_CNT_C + LS_C_MAX + 1;     // ncum_v[0..LS_V_MAX]
 constexpr int LS_CNT_U = LS_CNT_V + LS_V_MAX + 1;     // size of U
 constexpr int LS_NCOUNTERS = LS_CNT_U + 1;
 
-// Box-sized scratch arrays of one instance.
+// Box-sized scratch arrays of one instance.  Between passes the extension
+// arrays hold 0 and the distance 255 at every node (the whole-box values the
+// sweeps on lists rely on): the restriction that ends a pass clears the
+// tiles of list U, the only ones the pass writes.  A pass that does not
+// reach its restriction (an error on the host between levelset_begin and
+// levelset_end) leaves the scratch dirty, and the next pass clears the
+// whole box first.
 struct LevelsetScratch {
   size_t nodes = 0;
   double* buf = nullptr;      // 12 box arrays of doubles
   uint8_t* known = nullptr;   // bit 0: K0, bit 1: K1, bit 2: K2, bit 3: speed band, bit 4: reinit band
   uint8_t* dist = nullptr;    // L1 distance to the computational points, capped (LS_READ_REACH + 1 beyond)
+  bool dirty = true;          // host flag: some node outside its list U may hold a nonzero value
 };
 
 // One instance as the kernels see it (device copy in LevelsetBatch).
@@ -105,6 +112,8 @@ struct LsInst {
   int rr;                     // radius of list R (Dv <= rr)
   int* status;                // latched device error of the instance
   double* vmax;               // set by levelset_begin
+  int dirty;                  // set by levelset_begin / levelset_extend: clear the whole box first
+  bool* host_dirty;           // LevelsetScratch::dirty (host address, never read on the device)
 };
 
 // Instance table and launch offsets of a batch of `count` instances.
@@ -121,6 +130,7 @@ struct LevelsetBatch {
   double dt = 0.0;
   int reinit = 0;
   int uext = 0;               // scratch array holding u_ext after levelset_begin
+  bool any_dirty = false;     // some instance's scratch is cleared over the whole box first
 };
 
 hipError_t levelset_alloc(LevelsetScratch& s, size_t nodes);

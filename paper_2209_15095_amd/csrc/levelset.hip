@@ -47,10 +47,9 @@ struct Where {
 // sorted list SC / SV within radius r; LS_ROW_U: list U; LS_ROW_FULL: every
 // tile) -> node.
 template <int DIM>
-__device__ __forceinline__ Where locate(const LsInst* __restrict__ insts, const int* __restrict__ off, int count,
-                                       int row) {
+__device__ __forceinline__ Where locate_at(const LsInst* __restrict__ insts, const int* __restrict__ off, int count,
+                                          int row, int b) {
   const int* o = off + (size_t)row * (count + 1);
-  const int b = (int)blockIdx.x;
   int lo = 0, hi = count - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
@@ -73,6 +72,12 @@ __device__ __forceinline__ Where locate(const LsInst* __restrict__ insts, const 
   w.in = w.i < I.nx && w.j < I.ny && w.k < I.nz;
   w.id = ((size_t)w.k * I.ny + w.j) * I.nx + w.i;
   return w;
+}
+
+template <int DIM>
+__device__ __forceinline__ Where locate(const LsInst* __restrict__ insts, const int* __restrict__ off, int count,
+                                       int row) {
+  return locate_at<DIM>(insts, off, count, row, (int)blockIdx.x);
 }
 
 __device__ __forceinline__ gptr<double> arr(const LsInst& I, int a) { return glb(I.buf) + (size_t)a * I.nodes; }
@@ -102,13 +107,15 @@ __device__ __forceinline__ bool comp_point(const LsInst& I, const Where& w, gptr
 
 // ------------------------------------------------------------ Step 1: u_ext
 
-// whole box: the extrapolation arrays, the speed and its ping-pong partner
-// start at 0, and so does the instance's maximum speed
+// whole box of the instances with a dirty scratch: the extrapolation arrays,
+// the speed and its ping-pong partner to 0, the distance to 255, and the
+// instance's maximum speed to 0
 template <int DIM>
 __global__ __launch_bounds__(256) void zero_kernel(const LsInst* __restrict__ insts, const int* __restrict__ off,
                                                    int count) {
   const Where w = locate<DIM>(insts, off, count, LS_ROW_FULL);
   const LsInst& I = *w.I;
+  if (!I.dirty) return;
   if (w.local == 0 && threadIdx.x == 0) *glb(I.vmax) = 0.0;
   if (!w.in) return;
   for (int a = A_E0; a <= A_V; ++a) arr(I, a)[w.id] = 0.0;
@@ -195,63 +202,123 @@ __global__ __launch_bounds__(256) void unn_kernel(const LsInst* __restrict__ ins
   arr(I, A_E2)[w.id] = k2 ? dir_deriv<DIM>(I, w, arr(I, A_E1)) : 0.0;
 }
 
+// Launch shape of the 3D sweeps: tiles per block, XCD-contiguous ranges.
+#ifndef EXT_NPT
+#define EXT_NPT 1
+#endif
+#ifndef EXT_XCD
+#define EXT_XCD 1
+#endif
+// grid of an extend_kernel launch over `total` tiles
+inline int ext_grid(int total) {
+  const int nvb = (total + EXT_NPT - 1) / EXT_NPT;
+  return EXT_XCD ? 8 * ((nvb + 7) / 8) : nvb;
+}
+
 // one Jacobi sweep on `list`: out = v - dtau (a.grad v - src) off the known set
 // (bit), a = sgn * n, sgn = 1 or sign(rho) (speed extension); with
-// do_max, also the instance's maximum of out (non-negative values).
-template <int DIM>
+// do_max, also the instance's maximum of out (non-negative values).  A
+// block serves NPT consecutive tiles of the launch row (one node of each per
+// thread); every load of all of them is issued before any arithmetic (the
+// update is computed everywhere and selected off the known set), so a block
+// waits for one round trip to memory after its tile lookups.
+template <int DIM, int NPT>
 __global__ __launch_bounds__(256) void extend_kernel(const LsInst* __restrict__ insts, const int* __restrict__ off,
                                                      int count, int row, int v_arr, int out_arr, int src_arr,
                                                      int bit, int sign_rho, int do_max, int dil) {
-  const Where w = locate<DIM>(insts, off, count, row);
-  const LsInst& I = *w.I;
-  double res = 0.0;
-  if (w.in && dil) {
-    // one L1 dilation of the distance to the computational points, in place
-    // (a value only decreases, never below the true distance; after k
-    // sweeps every node within k holds its exact distance)
-    gptr<uint8_t> ds = glb(I.dist);
-    int m = ds[w.id];
-    if (m > 0) {
-      for (int d = 0; d < DIM; ++d) {
-        m = min(m, (int)ds[shifted(I, w, d, -1)] + 1);
-        m = min(m, (int)ds[shifted(I, w, d, 1)] + 1);
-      }
-      ds[w.id] = (uint8_t)min(m, 255);
+  const int total = off[(size_t)row * (count + 1) + count];
+  // XCD-contiguous ranges: workgroups go to the 8 XCDs in turn, so block b
+  // takes entry (b % 8) * chunk + b / 8 of the row (grid 8 * chunk) and each
+  // XCD walks a contiguous range of the list, whose neighbouring tiles share
+  // halo lines in that XCD's L2.
+  const int nvb = (total + NPT - 1) / NPT;
+  const int chunk = EXT_XCD ? (nvb + 7) / 8 : 0;
+  const int bx = EXT_XCD ? ((int)blockIdx.x % 8) * chunk + (int)blockIdx.x / 8 : (int)blockIdx.x;
+  Where w[NPT];
+#pragma unroll
+  for (int q = 0; q < NPT; ++q) {
+    const int vb = bx * NPT + q;
+    if (vb < total) {
+      w[q] = locate_at<DIM>(insts, off, count, row, vb);
+    } else {
+      w[q].I = insts;
+      w[q].in = false;
+      w[q].id = 0;
+      w[q].i = w[q].j = w[q].k = 0;
     }
   }
-  if (w.in) {
+  size_t im[NPT][DIM], ip[NPT][DIM];
+  uint8_t kb[NPT];
+  double vc[NPT], vm[NPT][DIM], vp[NPT][DIM], nd[NPT][DIM], sr[NPT], rr[NPT];
+  int m[NPT];
+#pragma unroll
+  for (int q = 0; q < NPT; ++q) {
+    const LsInst& I = *w[q].I;
+    if (!w[q].in) continue;
     gptr<const double> v = arr(I, v_arr);
-    const double vc = v[w.id];
-    if ((glb((const uint8_t*)I.known)[w.id] >> bit) & 1) {
-      res = vc;
-    } else {
-      double sg = 1.0;
-      if (sign_rho) {
-        const double r = glb((const double*)I.rho)[w.id];
-        sg = (r > 0.0) ? 1.0 : ((r < 0.0) ? -1.0 : 0.0);
-      }
-      double up = 0.0;
-      for (int d = 0; d < DIM; ++d) {
-        const double a = sg * arr(I, A_NX + d)[w.id];
-        up += fmax(a, 0.0) * (vc - v[shifted(I, w, d, -1)]) + fmin(a, 0.0) * (v[shifted(I, w, d, 1)] - vc);
-      }
-      up = up / I.h;
-      const double s = (src_arr >= 0) ? arr(I, src_arr)[w.id] : 0.0;
-      res = vc - (0.5 * I.h) * (up - s);
+    for (int d = 0; d < DIM; ++d) {
+      im[q][d] = shifted(I, w[q], d, -1);
+      ip[q][d] = shifted(I, w[q], d, 1);
     }
-    arr(I, out_arr)[w.id] = res;
+    kb[q] = glb((const uint8_t*)I.known)[w[q].id];
+    vc[q] = v[w[q].id];
+    for (int d = 0; d < DIM; ++d) {
+      vm[q][d] = v[im[q][d]];
+      vp[q][d] = v[ip[q][d]];
+      nd[q][d] = arr(I, A_NX + d)[w[q].id];
+    }
+    sr[q] = (src_arr >= 0) ? arr(I, src_arr)[w[q].id] : 0.0;
+    rr[q] = sign_rho ? glb((const double*)I.rho)[w[q].id] : 1.0;
+    m[q] = 0;
+    if (dil) {
+      // one L1 dilation of the distance to the computational points, in
+      // place (a value only decreases, never below the true distance; after
+      // k sweeps every node within k holds its exact distance)
+      gptr<const uint8_t> ds = glb((const uint8_t*)I.dist);
+      int dn = 255;
+      for (int d = 0; d < DIM; ++d) dn = min(dn, min((int)ds[im[q][d]], (int)ds[ip[q][d]]));
+      m[q] = min((int)ds[w[q].id], dn + 1);
+    }
+  }
+  double res[NPT];
+#pragma unroll
+  for (int q = 0; q < NPT; ++q) {
+    res[q] = 0.0;
+    if (!w[q].in) continue;
+    const LsInst& I = *w[q].I;
+    const double sg = (rr[q] > 0.0) ? 1.0 : ((rr[q] < 0.0) ? -1.0 : 0.0);
+    double up = 0.0;
+    for (int d = 0; d < DIM; ++d) {
+      const double a = sg * nd[q][d];
+      up += fmax(a, 0.0) * (vc[q] - vm[q][d]) + fmin(a, 0.0) * (vp[q][d] - vc[q]);
+    }
+    up = up / I.h;
+    const double upd = vc[q] - (0.5 * I.h) * (up - sr[q]);
+    res[q] = ((kb[q] >> bit) & 1) ? vc[q] : upd;
+  }
+#pragma unroll
+  for (int q = 0; q < NPT; ++q) {
+    if (!w[q].in) continue;
+    const LsInst& I = *w[q].I;
+    arr(I, out_arr)[w[q].id] = res[q];
+    if (dil) glb(I.dist)[w[q].id] = (uint8_t)min(m[q], 255);
   }
   if (do_max) {
+    // per tile (each tile belongs to one instance)
     __shared__ double sm[256];
-    sm[threadIdx.x] = w.in ? res : 0.0;
-    __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-      if ((int)threadIdx.x < s) sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + s]);
+    for (int q = 0; q < NPT; ++q) {
+      if (bx * NPT + q >= total) break;   // uniform over the block
+      sm[threadIdx.x] = w[q].in ? res[q] : 0.0;
+      __syncthreads();
+      for (int st = 128; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + st]);
+        __syncthreads();
+      }
+      // max of non-negative doubles: integer order equals value order
+      if (threadIdx.x == 0)
+        atomicMax((unsigned long long*)w[q].I->vmax, (unsigned long long)__double_as_longlong(sm[0]));
       __syncthreads();
     }
-    // max of non-negative doubles: integer order equals value order
-    if (threadIdx.x == 0)
-      atomicMax((unsigned long long*)I.vmax, (unsigned long long)__double_as_longlong(sm[0]));
   }
 }
 
@@ -524,14 +591,19 @@ __global__ __launch_bounds__(256) void rk_kernel(const LsInst* __restrict__ inst
 
 // whole box: u = comp(rho_new) ? u_ext : 0 (a computational point beyond
 // the reach of the extension: ST_FRONT), or (all) u = u_ext within the reach
-// of the extension and 0 beyond (what the step reads of it)
+// of the extension and 0 beyond (what the step reads of it).  Then the
+// pass's own writes are cleared: on the tiles of list U (Dc <= LS_C_MAX or
+// Dv <= LS_V_MAX) the extension arrays, the speed and its partner go to 0
+// and the distance to 255 (each thread reads and clears its own node only),
+// and the maximum speed to 0.
 template <int DIM>
 __global__ __launch_bounds__(256) void restrict_kernel(const LsInst* __restrict__ insts,
                                                        const int* __restrict__ off, int count, int uext_arr,
                                                        int all) {
   const Where w = locate<DIM>(insts, off, count, LS_ROW_FULL);
-  if (!w.in) return;
   const LsInst& I = *w.I;
+  if (w.local == 0 && threadIdx.x == 0) *glb(I.vmax) = 0.0;
+  if (!w.in) return;
   const bool reach = in_reach(I, w.id);
   bool c;
   if (all) {
@@ -541,6 +613,18 @@ __global__ __launch_bounds__(256) void restrict_kernel(const LsInst* __restrict_
     if (c && !reach) atomicCAS(I.status, 0, ST_FRONT);
   }
   glb(I.u)[w.id] = c ? arr(I, uext_arr)[w.id] : 0.0;
+  const int td = I.tdist[w.local];
+  if ((td & 0xFFFF) <= LS_C_MAX || (td >> 16) <= LS_V_MAX) {
+    for (int a = A_E0; a <= A_V; ++a) arr(I, a)[w.id] = 0.0;
+    arr(I, A_S)[w.id] = 0.0;
+    glb(I.dist)[w.id] = 255;
+  }
+}
+
+// The restriction that clears every instance's list U is enqueued.
+void mark_clean(LevelsetBatch& b) {
+  for (int i = 0; i < b.count; ++i)
+    if (b.h_inst[i].host_dirty) *b.h_inst[i].host_dirty = false;
 }
 
 template <int DIM>
@@ -557,7 +641,7 @@ hipError_t begin_dim(LevelsetBatch& b, hipStream_t st, bool speed) {
       if (_e != hipSuccess) return _e;                                                       \
     }                                                                                        \
   } while (0)
-  LL(LS_ROW_FULL, zero_kernel);
+  if (b.any_dirty) LL(LS_ROW_FULL, zero_kernel);
   LL(LS_ROW_U, init_kernel);
   LL(LS_ROW_C + ASLAM_ITERS + 1, known1_kernel);
   LL(LS_ROW_C + ASLAM_ITERS + 1, known2_un_kernel);
@@ -584,8 +668,8 @@ hipError_t begin_dim(LevelsetBatch& b, hipStream_t st, bool speed) {
           hipLaunchKernelGGL(extend_group_kernel, dim3(b.total[r]), B, 0, st, I, off, n, r, v, t, src, bit, sign_rho,
                              mx, ns, dil);
         else
-          hipLaunchKernelGGL(extend_kernel<DIM>, dim3(b.total[r]), B, 0, st, I, off, n, r, v, t, src, bit, sign_rho,
-                             mx, dil);
+          hipLaunchKernelGGL((extend_kernel<DIM, EXT_NPT>), dim3(ext_grid(b.total[r])), B, 0, st, I, off, n, r, v, t,
+                             src, bit, sign_rho, mx, dil);
         if (hipGetLastError() != hipSuccess) return -1;
       }
       done += ns;
@@ -653,7 +737,9 @@ hipError_t end_dim(LevelsetBatch& b, hipStream_t st) {
     }
   }
   hipLaunchKernelGGL(restrict_kernel<DIM>, dim3(b.total[LS_ROW_FULL]), B, 0, st, I, off, n, b.uext, 0);
-  return hipGetLastError();
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  mark_clean(b);
+  return hipSuccess;
 }
 
 template <int DIM>
@@ -662,7 +748,9 @@ hipError_t extend_dim(LevelsetBatch& b, hipStream_t st) {
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(restrict_kernel<DIM>, dim3(b.total[LS_ROW_FULL]), dim3(256), 0, st, b.d_inst, b.d_off, b.count,
                      b.uext, 1);
-  return hipGetLastError();
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  mark_clean(b);
+  return hipSuccess;
 }
 
 }  // namespace
@@ -680,7 +768,9 @@ hipError_t levelset_alloc(LevelsetScratch& s, size_t nodes) {
   if (e != hipSuccess) return e;
   e = hipMalloc(&s.dist, nodes);
   if (e != hipSuccess) return e;
-  return hipMemset(s.dist, 255, nodes);
+  e = hipMemset(s.dist, 255, nodes);
+  s.dirty = e != hipSuccess;
+  return e;
 }
 
 void levelset_free(LevelsetScratch& s) {
@@ -700,6 +790,7 @@ hipError_t levelset_batch_alloc(LevelsetBatch& b, int count, int dim) {
   if ((e = hipHostMalloc(&b.h_off, sizeof(int) * LS_NROWS * (count + 1))) != hipSuccess) return e;
   if ((e = hipMalloc(&b.d_vmax, sizeof(double) * count)) != hipSuccess) return e;
   if ((e = hipHostMalloc(&b.h_vmax, sizeof(double) * count)) != hipSuccess) return e;
+  if ((e = hipMemset(b.d_vmax, 0, sizeof(double) * count)) != hipSuccess) return e;
   for (int i = 0; i < count; ++i) b.h_inst[i] = LsInst{};
   return hipSuccess;
 }
@@ -732,7 +823,15 @@ hipError_t upload(LevelsetBatch& b, hipStream_t st) {
     b.h_off[q * (n + 1) + n] = acc;
     b.total[q] = acc;
   }
-  for (int i = 0; i < n; ++i) b.h_inst[i].vmax = b.d_vmax + i;
+  b.any_dirty = false;
+  for (int i = 0; i < n; ++i) {
+    LsInst& I = b.h_inst[i];
+    I.vmax = b.d_vmax + i;
+    // an instance without a host flag is always cleared first
+    I.dirty = (!I.host_dirty || *I.host_dirty) ? 1 : 0;
+    b.any_dirty = b.any_dirty || I.dirty;
+    if (I.host_dirty) *I.host_dirty = true;   // until its restriction is enqueued
+  }
   hipError_t e;
   if ((e = hipMemcpyAsync(b.d_inst, b.h_inst, sizeof(LsInst) * n, hipMemcpyHostToDevice, st)) != hipSuccess)
     return e;

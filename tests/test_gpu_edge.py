@@ -8,6 +8,8 @@
 * Invalid scheme codes (and a non-ETD2RK adjoint) return ETD_ERR_INVALID
   and leave u untouched.
 * All-zero inputs: exactly 0 (the Krylov term vanishes, W_p = 0).
+* A free-boundary step refused for its front speed (2D and 3D) changes
+  nothing, and the steps after it match the oracle.
 """
 import sys
 
@@ -100,15 +102,16 @@ def test_time_zero_and_zero_inputs():
 
 
 def test_invalid_scheme_codes():
-    """Scheme codes outside ETD1..ETD4RK, and any scheme but ETD2RK for the
-    adjoint, return ETD_ERR_INVALID before any device work; u is untouched."""
+    """Scheme codes outside ETD1..ETD4RK_SIMUL, and any scheme but ETD2RK for
+    the adjoint, return ETD_ERR_INVALID before any device work; u is
+    untouched."""
     from paper_2209_15095_amd import _lib as L
     import ctypes as C
     X, Y = G.coords()
     rho = np.sqrt(X * X + Y * Y) - 2.5
     ctx = ctx_for(rho)
     u = dev(np.ones_like(rho))
-    for code in (0, 5, -1):
+    for code in (0, L.ETD_SCHEME_ETD4RK_SIMUL + 1, -1):
         r = ctx.lib.etd_step(ctx.handle, code, 0.01, C.c_void_p(u.data_ptr()), None, 0, None)
         assert r == L.ETD_ERR_INVALID, (code, r)
     torch.cuda.synchronize()
@@ -120,3 +123,49 @@ def test_invalid_scheme_codes():
                                  C.c_void_p(g.data_ptr()), C.c_void_p(gn.data_ptr()), C.c_void_p(db.data_ptr()))
     assert r == L.ETD_ERR_INVALID
     ctx.close()
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_refused_step_then_steps_match_oracle(dim):
+    """A free-boundary step whose speed would move the front more than
+    LS_MAX_FRONT_NODES nodes is refused (ETD_ERR_FRONT) with rho and u
+    unchanged; the steps that follow (which first clear the level-set
+    scratch the refused pass left) match the oracle's."""
+    from oracle.freeboundary import free_boundary_step
+    from oracle.geometry import classify
+    from paper_2209_15095_amd._lib import ETD_ERR_FRONT, EtdError
+    from paper_2209_15095_amd.api import Context
+    if dim == 2:
+        w = inputs.fisher64()
+        g, rho, u, mu, h, big = w.grid, w.rho0.copy(), w.u0.copy(), w.mu, w.h, 2.0
+    else:
+        g = inputs.GridSpec(3, (48, 48, 48), (-5.0,) * 3, (5.0,) * 3)
+        X, Y, Z = g.coords()
+        rho = inputs.sdf_prolate_spheroid(X, Y, Z, 2.5, 1.8)
+        u = np.where(rho < 0, np.random.default_rng(3).uniform(0.2, 0.8, rho.shape), 0.0)
+        mu, h, big = 1.0, 0.01, 5.0
+    og = Grid(g.dim, tuple(g.n), tuple(g.lo), tuple(g.hi))
+    ctx = Context(g.dim, g.n, g.lo, g.hi, beta=1.0, mu=mu)
+    rd, ud = dev(rho), dev(u)
+    ctx.geometry_build(rd)
+    say(f"refused step ({dim}D, dt {big}), then 3 steps of dt {h}")
+    with pytest.raises(EtdError) as ei:
+        ctx.etd_step("etd2rk", big, ud, rho=rd, reinit=False)
+    assert ei.value.code == ETD_ERR_FRONT
+    torch.cuda.synchronize()
+    assert np.array_equal(rd.cpu().numpy(), rho) and np.array_equal(ud.cpu().numpy(), u)
+    for m in range(3):
+        reinit = m == 2
+        rho, u, op = free_boundary_step(og, rho, u, h, 1.0, mu, scheme="etd2rk", reinit=reinit,
+                                        method="krylov")
+        ctx.etd_step("etd2rk", h, ud, rho=rd, reinit=reinit)
+    torch.cuda.synchronize()
+    rg, ug = rd.cpu().numpy(), ud.cpu().numpy()
+    ctx.close()
+    _, comp_g, _ = classify(og, rg)
+    err = np.linalg.norm(ug[op.comp] - u[op.comp]) / np.linalg.norm(u[op.comp])
+    say(f"  N {op.n} rho diff {np.abs(rg - rho).max():.3e}  u rel {err:.3e}")
+    assert np.array_equal(comp_g, op.comp)
+    assert np.abs(rg - rho).max() <= 1e-10
+    assert err <= 1e-9
+    assert np.all(ug[~op.comp] == 0.0)
