@@ -26,7 +26,10 @@
 //   (generalised residual); accept when it is below
 //   tol * tau/t * max(|u(t_j)|, tau^p |W_p| / p!) and below
 //   tol * tau/t * |u(t_j + tau)|.  Otherwise grow m in steps of m_step up to
-//   m_max, then shrink tau.
+//   m_max, then shrink tau.  A call starts at the dimension its previous
+//   call accepted last (one lower when that passed below 1 % of the
+//   tolerance), and at the fraction of t its last substep took after a
+//   shrink.
 //
 // Everything after the launch is decided on the device: every block reduces
 // the same per-block partials in the same order, so all blocks hold
@@ -58,6 +61,19 @@ struct Ctl {
   // adaptive state per p carried across calls (thread 0 writes)
   double tau_frac[PMAX + 1];
   int m_guess[PMAX + 1];
+  // statistics of the launch, kept by thread 0 (out of the registers the
+  // passes need): counters, the last accepted substep, algorithmic HBM
+  // bytes per unknown moved so far (what the method must read and write per
+  // computational point: vectors only; neighbour re-reads, masks and tile
+  // padding are not counted), device-clock ticks of block 0 (passes, from
+  // the start of a pass's tile loop until every wave of the block is done
+  // and the block has reduced its partials; grid synchronisations; small
+  // exponentials; the launch prologue; t_mark: start of the current pass)
+  struct Stats {
+    int substeps, rejected, matvecs, m_last, expms, n_sync;
+    double err_est, ratio_last, t_done, bpu;   // ratio_last: error / tolerance of the last accepted substep
+    unsigned long long tk_sync, tk_expm, tk_pass, tk_pro, t_mark;
+  } st;
   int abort;
 };
 
@@ -254,23 +270,19 @@ struct Engine {
   int pass_no;
   int lb, G;
   // control state: every thread of every block holds identical copies
-  int substeps, rejected, matvecs, m_last, expms;
-  double err_est, t_done;
   bool failed;
   int iu;   // vector holding u(t_j) = W_0 (V_U or V_T, ping-pong with the combine output)
   size_t sp_stride;   // index distance between the copies of one node in consecutive species
   double st_tmid;     // intermediate output of the current stage's combination (0: none)
   int st_midvec;      // and its vector
-  // Algorithmic HBM bytes per unknown moved so far: what the method must read
-  // and write per computational point (vectors only; neighbour re-reads,
-  // masks and tile padding are not counted).
-  double bpu;
-  // device-clock ticks (kept by thread 0 of block 0 of the group): passes
-  // (from the start of a pass's tile loop until every wave of the block is
-  // done and the block has reduced its partials), grid synchronisations,
-  // small exponentials, the launch prologue; t_mark: start of the current pass
-  unsigned long long tk_sync, tk_expm, tk_pass, tk_pro, t_mark;
-  int n_sync;
+
+  // statistics (thread 0 only)
+  __device__ __forceinline__ void count(int& f, int v) {
+    if (threadIdx.x == 0) f += v;
+  }
+  __device__ __forceinline__ void add_bytes(double b) {
+    if (threadIdx.x == 0) c.st.bpu += b;
+  }
 
   __device__ __forceinline__ gptr<double> V(int i) const { return glb(P.ws) + (size_t)i * P.ld; }
 
@@ -343,8 +355,8 @@ struct Engine {
     const int ab = c.abort;
     __syncthreads();
     if (threadIdx.x == 0 && lb == 0) {
-      tk_sync += wall_clock64() - t_in;
-      ++n_sync;
+      c.st.tk_sync += wall_clock64() - t_in;
+      ++c.st.n_sync;
     }
     return ab == 0;
   }
@@ -356,7 +368,7 @@ struct Engine {
   template <int NR>
   __device__ __forceinline__ bool finish(double (&acc)[NR], double (&out)[NR]) {
     block_sum<NR>(acc, c.scratch);
-    if (threadIdx.x == 0 && lb == 0) tk_pass += wall_clock64() - t_mark;
+    if (threadIdx.x == 0 && lb == 0) c.st.tk_pass += wall_clock64() - c.st.t_mark;
     if (G == 1) {
       for (int k = 0; k < NR; ++k) out[k] = acc[k];
     } else if (!grid_sync<NR>(acc, out)) {
@@ -374,7 +386,7 @@ struct Engine {
 
   __device__ __forceinline__ bool barrier() {
     __syncthreads();
-    if (threadIdx.x == 0 && lb == 0) tk_pass += wall_clock64() - t_mark;
+    if (threadIdx.x == 0 && lb == 0) c.st.tk_pass += wall_clock64() - c.st.t_mark;
     if (G == 1) return true;
     double a[1] = {0.0}, o[1];
     if (!grid_sync<1>(a, o)) {
@@ -490,7 +502,7 @@ struct Engine {
     const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int stride = G * KTILES;
     int slot = tile_block() * KTILES + sub;
-    if (threadIdx.x == 0 && lb == 0) t_mark = wall_clock64();
+    if (threadIdx.x == 0 && lb == 0) c.st.t_mark = wall_clock64();
     Meta m;
     if (slot < nact) trip_meta(m, 0, slot, sub, w);
     for (int r = 0; slot < nact; ++r) {
@@ -582,7 +594,7 @@ struct Engine {
         acc[1] += u * u;
       }
     });
-    bpu += 24.0 + 8.0 * (p - k + 1);
+    add_bytes(24.0 + 8.0 * (p - k + 1));
     if (k == p) return finish<2>(acc, out);
     return barrier();
   }
@@ -598,7 +610,7 @@ struct Engine {
       acc[0] += u * u;
       acc[1] += u * u;
     });
-    bpu += 16.0;
+    add_bytes(16.0);
     return finish<2>(acc, out);
   }
 
@@ -672,7 +684,7 @@ struct Engine {
       acc[0] += q * q;
       acc[1] += z * q;
     });
-    bpu += 32.0;
+    add_bytes(32.0);
     return finish<2>(acc, out);
   }
 
@@ -746,7 +758,7 @@ struct Engine {
     const int stride = G * KTILES;
     const int base0 = tile_block() * KTILES;
     double acc[2] = {0.0, 0.0};
-    if (threadIdx.x == 0 && lb == 0) t_mark = wall_clock64();
+    if (threadIdx.x == 0 && lb == 0) c.st.t_mark = wall_clock64();
     // loads of trip r: the point and the halo nodes (0 where no tile)
     double pz, p1, p2, hz[HR], h1[HR], h2[HR];
     // metadata of trip r from the LDS cache (the caller uses this pass only
@@ -845,7 +857,7 @@ struct Engine {
       }
       __syncthreads();   // LDS free for the exponential
     }
-    bpu += 32.0;
+    add_bytes(32.0);
     return finish<2>(acc, out);
   }
 
@@ -859,13 +871,13 @@ struct Engine {
   // (NOT_COMP elsewhere).  The q_k buffer alternates between two LDS halves
   // by trip parity, so two block barriers per trip suffice.
   __device__ __forceinline__ bool lanczos_zf2(int k, double (&out)[2]) {
-    if (threadIdx.x == 0 && lb == 0) t_mark = wall_clock64();
+    if (threadIdx.x == 0 && lb == 0) c.st.t_mark = wall_clock64();
     double acc[2];
     zf2_loop(uniform<const double>(V(V_Q0 + k - 1)), uniform<const double>(V(V_Q0 + (k >= 2 ? k - 2 : 0))),
              uniform<double>(V(V_Q0 + k)), uniform<const double>(glb(P.g.cdiag)), P.g.coef, c.alpha[k - 1],
              1.0 / c.nrm[k - 1], (k >= 2) ? c.nrm[k - 1] / c.nrm[k - 2] : 0.0, nact, G, tile_block(), lds(R),
              lds((const int*)&c.mnb[0][0][0]), acc);
-    bpu += 32.0;
+    add_bytes(32.0);
     return finish<2>(acc, out);
   }
 
@@ -911,7 +923,7 @@ struct Engine {
       V(io)[idx] = u;
       acc[0] += u * u;
     });
-    bpu += 8.0 * (m + p + 1);
+    add_bytes(8.0 * (m + p + 1));
     double out[1];
     if (!finish<1>(acc, out)) return false;
     nn = out[0];
@@ -984,7 +996,7 @@ struct Engine {
       for (int e = threadIdx.x; e < NN; e += blockDim.x) R[e] = A[e];
       __syncthreads();
     }
-    if (threadIdx.x == 0 && lb == 0) tk_expm += wall_clock64() - t_in;
+    if (threadIdx.x == 0 && lb == 0) c.st.tk_expm += wall_clock64() - t_in;
   }
 
   // ------------------------------------------------------------ phi combo
@@ -1016,7 +1028,7 @@ struct Engine {
           if (k <= p) u += ck[k] * V(V_B0 + k)[idx];
         V(V_U)[idx] = t.comp ? u : 0.0;
       });
-      bpu += 8.0 * (p + 2);
+      add_bytes(8.0 * (p + 2));
       iu = V_U;
       return barrier() && (t_mid == 0.0 || copy_pass(mid_vec, V_U));
     }
@@ -1042,7 +1054,7 @@ struct Engine {
           if (!setup_pass(k, p, tj, tend, o)) return false;
           if (k == p) { nrm2[0] = o[0]; nrm2[1] = o[1]; }
         }
-        matvecs += p;
+        count(c.st.matvecs, p);
       }
       const double n0 = sqrt(nrm2[0]);
       const double unorm = sqrt(nrm2[1]);
@@ -1070,7 +1082,7 @@ struct Engine {
       // error estimate of the current (m, tau); fills R with exp(X)
       auto estimate = [&]() -> bool {
         expm_aug(m, p, tau);
-        expms += 1;
+        count(c.st.expms, 1);
         const int N = m + p + 1;
         const double phi_next_m = R[(m - 1) * N + (m + p)];
         double taup = 1.0;
@@ -1096,7 +1108,7 @@ struct Engine {
       // while m < m_max, else a smaller tau.  Returns false on failure.
       auto refine = [&](double r) -> bool {
         if (m < P.m_max && !breakdown) {
-          rejected += 1;
+          count(c.st.rejected, 1);
           m_target = min(m + P.m_step, P.m_max);
           return true;
         }
@@ -1104,7 +1116,7 @@ struct Engine {
         fac = fmin(0.9, fmax(0.1, fac));
         tau *= fac;
         shrunk = true;
-        rejected += 1;
+        count(c.st.rejected, 1);
         if (tau < 1e-12 * tend) { fail(ST_KRYLOV); return false; }
         return true;
       };
@@ -1116,7 +1128,7 @@ struct Engine {
           if (m == 0 && !started) {
             double dot;
             if (!lanczos_first(dot)) return false;
-            matvecs += 1;
+            count(c.st.matvecs, 1);
             if (threadIdx.x == 0) c.alpha[0] = dot / (n0 * n0);
             __syncthreads();
             started = true;
@@ -1131,7 +1143,7 @@ struct Engine {
           else if (staged) ok = lanczos_lds(m + 1, o);
           else ok = lanczos_pass(m + 1, o);
           if (!ok) return false;
-          matvecs += 1;
+          count(c.st.matvecs, 1);
           const double nb = sqrt(o[0]);
           const double alpha_next = (o[0] > 0.0) ? o[1] / o[0] : 0.0;
           anorm = fmax(anorm, fabs(c.alpha[m]) + nb + (m > 0 ? c.nrm[m] : 0.0));
@@ -1188,8 +1200,11 @@ struct Engine {
       if (t_mid > tj && t_mid >= tj + tau - 1e-13 * tend && t_mid <= tj + tau + 1e-13 * tend &&
           !copy_pass(mid_vec, iu))
         return false;
-      m_last = m;
-      err_est = err;
+      if (threadIdx.x == 0) {
+        c.st.m_last = m;
+        c.st.err_est = err;
+        c.st.ratio_last = err / fmax(tol_loc, 1e-300);
+      }
       tj += tau;
       ++nsub;
       shrunk_any |= shrunk;
@@ -1201,14 +1216,16 @@ struct Engine {
       if (!copy_pass(V_U, iu)) return false;
       iu = V_U;
     }
-    substeps += nsub;
+    count(c.st.substeps, nsub);
     __syncthreads();
     if (threadIdx.x == 0) {
-      c.m_guess[p] = max(P.m_min, min(P.m_max, m_last - P.m_step / 2));
+      // the next call starts at the dimension that passed, one lower when
+      // it passed with a wide margin
+      c.m_guess[p] = max(P.m_min, min(P.m_max, c.st.ratio_last < 1e-2 ? c.st.m_last - 1 : c.st.m_last));
       c.tau_frac[p] = shrunk_any ? fmin(1.0, 1.25 * tau / tend) : 1.0;
     }
     __syncthreads();
-    t_done = tj;
+    if (threadIdx.x == 0) c.st.t_done = tj;
     return true;
   }
 
@@ -1220,7 +1237,7 @@ struct Engine {
       const size_t idx = t.idx;
       V(dst)[idx] = comp ? V(src)[idx] : 0.0;
     });
-    bpu += 16.0;
+    add_bytes(16.0);
     return barrier();
   }
 
@@ -1245,7 +1262,7 @@ struct Engine {
   template <class F>
   __device__ __forceinline__ bool pointwise(double bytes, F&& f) {
     tiles([&](const Tile& t) { f(t.idx, t.comp); });
-    bpu += bytes;
+    add_bytes(bytes);
     return barrier();
   }
 
@@ -1259,7 +1276,7 @@ struct Engine {
       const size_t idx = t.idx;
       acc[0] += b[idx] * Av(t, a);
     });
-    bpu += 16.0;
+    add_bytes(16.0);
     double o[1];
     if (!finish<1>(acc, o)) return false;
     out = o[0];
@@ -1543,7 +1560,7 @@ struct Engine {
 
   __device__ __forceinline__ void run(unsigned long long t_start) {
     cache_meta();
-    if (threadIdx.x == 0 && lb == 0) tk_pro = wall_clock64() - t_start;
+    if (threadIdx.x == 0 && lb == 0) c.st.tk_pro = wall_clock64() - t_start;
     const int mode = P.mode;
     if (mode == JOB_APPLY) {
       tiles([&](const Tile& t) {
@@ -1551,7 +1568,7 @@ struct Engine {
         const size_t idx = t.idx;
         V(V_U)[idx] = Av(t, V(V_B0));
       });
-      bpu += 16.0;
+      add_bytes(16.0);
       barrier();
       return;
     }
@@ -1581,20 +1598,15 @@ template <int DIM>
 __device__ __forceinline__ void krylov_body(const KrylovDev& P, int lb, int G, Ctl& c, double* R, double* S) {
   const unsigned long long t_start = wall_clock64();
   Engine<DIM> e{P, c, R, S, *P.g.n_active, 0, lb, G};
-  e.tk_sync = e.tk_expm = e.tk_pass = e.tk_pro = e.t_mark = 0;
-  e.n_sync = 0;
-  for (int k = 0; k <= PMAX; ++k) {
-    if (threadIdx.x == 0) {
+  if (threadIdx.x == 0) {
+    for (int k = 0; k <= PMAX; ++k) {
       c.m_guess[k] = P.st->m_guess[k];
       c.tau_frac[k] = P.st->tau_frac[k];
     }
+    c.st = Ctl::Stats{};
   }
-  e.substeps = e.rejected = e.matvecs = e.m_last = e.expms = 0;
-  e.err_est = 0.0;
-  e.t_done = 0.0;
   e.failed = false;
   e.iu = V_U;
-  e.bpu = 0.0;
   e.sp_stride = (size_t)(e.nact / (P.species > 1 ? P.species : 1)) * TILE_PTS;
   __syncthreads();
   e.run(t_start);
@@ -1604,23 +1616,24 @@ __device__ __forceinline__ void krylov_body(const KrylovDev& P, int lb, int G, C
       P.st->m_guess[k] = c.m_guess[k];
       P.st->tau_frac[k] = c.tau_frac[k];
     }
-    P.st->substeps = e.substeps;
-    P.st->rejected = e.rejected;
-    P.st->matvecs = e.matvecs;
-    P.st->m_last = e.m_last;
-    P.st->expms = e.expms;
+    const Ctl::Stats& s = c.st;
+    P.st->substeps = s.substeps;
+    P.st->rejected = s.rejected;
+    P.st->matvecs = s.matvecs;
+    P.st->m_last = s.m_last;
+    P.st->expms = s.expms;
     P.st->calls += 1;
-    P.st->err_est = e.err_est;
-    P.st->t_done = e.t_done;
-    P.st->alg_bytes_per_unknown = e.bpu;
-    P.st->alg_bytes_total += e.bpu * (double)(*P.g.n_unknowns);
+    P.st->err_est = s.err_est;
+    P.st->t_done = s.t_done;
+    P.st->alg_bytes_per_unknown = s.bpu;
+    P.st->alg_bytes_total += s.bpu * (double)(*P.g.n_unknowns);
     P.st->ticks_total += (double)(wall_clock64() - t_start);
-    P.st->ticks_sync += (double)e.tk_sync;
-    P.st->ticks_expm += (double)e.tk_expm;
-    P.st->ticks_pass += (double)e.tk_pass;
-    P.st->ticks_pro += (double)e.tk_pro;
-    P.st->syncs += e.n_sync;
-    P.st->expm_calls += e.expms;
+    P.st->ticks_sync += (double)s.tk_sync;
+    P.st->ticks_expm += (double)s.tk_expm;
+    P.st->ticks_pass += (double)s.tk_pass;
+    P.st->ticks_pro += (double)s.tk_pro;
+    P.st->syncs += s.n_sync;
+    P.st->expm_calls += s.expms;
   }
 }
 
