@@ -217,15 +217,21 @@ inline int ext_grid(int total) {
 
 // one Jacobi sweep on `list`: out = v - dtau (a.grad v - src) off the known set
 // (bit), a = sgn * n, sgn = 1 or sign(rho) (speed extension); with
-// do_max, also the instance's maximum of out (non-negative values).  A
-// block serves NPT consecutive tiles of the launch row (one node of each per
-// thread); every load of all of them is issued before any arithmetic (the
-// update is computed everywhere and selected off the known set), so a block
-// waits for one round trip to memory after its tile lookups.
+// do_max, also the instance's maximum of out (non-negative values).  With
+// dil, the sweep also dilates the L1 distance to the computational points
+// by one node, in place (a value only decreases, never below the true
+// distance; after k such sweeps every node within k holds its exact
+// distance).  With cone >= 0, only nodes within L1 distance cone of the
+// computational points are swept (the others are neither read nor
+// written): after the sweep's own dilation, or from the distance when it
+// is already exact that far.  A block serves NPT consecutive tiles of the
+// launch row (one node of each per thread); the loads of all of them are
+// issued before the arithmetic (the update is computed everywhere and
+// selected off the known set).
 template <int DIM, int NPT>
 __global__ __launch_bounds__(256) void extend_kernel(const LsInst* __restrict__ insts, const int* __restrict__ off,
                                                      int count, int row, int v_arr, int out_arr, int src_arr,
-                                                     int bit, int sign_rho, int do_max, int dil) {
+                                                     int bit, int sign_rho, int do_max, int dil, int cone) {
   const int total = off[(size_t)row * (count + 1) + count];
   // XCD-contiguous ranges: workgroups go to the 8 XCDs in turn, so block b
   // takes entry (b % 8) * chunk + b / 8 of the row (grid 8 * chunk) and each
@@ -248,18 +254,36 @@ __global__ __launch_bounds__(256) void extend_kernel(const LsInst* __restrict__ 
     }
   }
   size_t im[NPT][DIM], ip[NPT][DIM];
-  uint8_t kb[NPT];
-  double vc[NPT], vm[NPT][DIM], vp[NPT][DIM], nd[NPT][DIM], sr[NPT], rr[NPT];
   int m[NPT];
+  bool act[NPT];
 #pragma unroll
   for (int q = 0; q < NPT; ++q) {
-    const LsInst& I = *w[q].I;
+    act[q] = false;
+    m[q] = 0;
     if (!w[q].in) continue;
-    gptr<const double> v = arr(I, v_arr);
+    const LsInst& I = *w[q].I;
     for (int d = 0; d < DIM; ++d) {
       im[q][d] = shifted(I, w[q], d, -1);
       ip[q][d] = shifted(I, w[q], d, 1);
     }
+    if (dil || cone >= 0) {
+      gptr<const uint8_t> ds = glb((const uint8_t*)I.dist);
+      m[q] = ds[w[q].id];
+      if (dil) {
+        int dn = 255;
+        for (int d = 0; d < DIM; ++d) dn = min(dn, min((int)ds[im[q][d]], (int)ds[ip[q][d]]));
+        m[q] = min(m[q], dn + 1);
+      }
+    }
+    act[q] = cone < 0 || m[q] <= cone;
+  }
+  uint8_t kb[NPT];
+  double vc[NPT], vm[NPT][DIM], vp[NPT][DIM], nd[NPT][DIM], sr[NPT], rr[NPT];
+#pragma unroll
+  for (int q = 0; q < NPT; ++q) {
+    if (!act[q]) continue;
+    const LsInst& I = *w[q].I;
+    gptr<const double> v = arr(I, v_arr);
     kb[q] = glb((const uint8_t*)I.known)[w[q].id];
     vc[q] = v[w[q].id];
     for (int d = 0; d < DIM; ++d) {
@@ -269,22 +293,12 @@ __global__ __launch_bounds__(256) void extend_kernel(const LsInst* __restrict__ 
     }
     sr[q] = (src_arr >= 0) ? arr(I, src_arr)[w[q].id] : 0.0;
     rr[q] = sign_rho ? glb((const double*)I.rho)[w[q].id] : 1.0;
-    m[q] = 0;
-    if (dil) {
-      // one L1 dilation of the distance to the computational points, in
-      // place (a value only decreases, never below the true distance; after
-      // k sweeps every node within k holds its exact distance)
-      gptr<const uint8_t> ds = glb((const uint8_t*)I.dist);
-      int dn = 255;
-      for (int d = 0; d < DIM; ++d) dn = min(dn, min((int)ds[im[q][d]], (int)ds[ip[q][d]]));
-      m[q] = min((int)ds[w[q].id], dn + 1);
-    }
   }
   double res[NPT];
 #pragma unroll
   for (int q = 0; q < NPT; ++q) {
     res[q] = 0.0;
-    if (!w[q].in) continue;
+    if (!act[q]) continue;
     const LsInst& I = *w[q].I;
     const double sg = (rr[q] > 0.0) ? 1.0 : ((rr[q] < 0.0) ? -1.0 : 0.0);
     double up = 0.0;
@@ -300,7 +314,7 @@ __global__ __launch_bounds__(256) void extend_kernel(const LsInst* __restrict__ 
   for (int q = 0; q < NPT; ++q) {
     if (!w[q].in) continue;
     const LsInst& I = *w[q].I;
-    arr(I, out_arr)[w[q].id] = res[q];
+    if (act[q]) arr(I, out_arr)[w[q].id] = res[q];
     if (dil) glb(I.dist)[w[q].id] = (uint8_t)min(m[q], 255);
   }
   if (do_max) {
@@ -308,7 +322,7 @@ __global__ __launch_bounds__(256) void extend_kernel(const LsInst* __restrict__ 
     __shared__ double sm[256];
     for (int q = 0; q < NPT; ++q) {
       if (bx * NPT + q >= total) break;   // uniform over the block
-      sm[threadIdx.x] = w[q].in ? res[q] : 0.0;
+      sm[threadIdx.x] = act[q] ? res[q] : 0.0;
       __syncthreads();
       for (int st = 128; st > 0; st >>= 1) {
         if ((int)threadIdx.x < st) sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + st]);
@@ -656,7 +670,7 @@ hipError_t begin_dim(LevelsetBatch& b, hipStream_t st, bool speed) {
   //   u shrinks to the read region:  radius LS_READ_REACH + ASLAM_ITERS - s0 + 1
   //   the speed grows from |rho| < h: SV radius s1
   const int group = (DIM == 2) ? SWEEP_GROUP : 1;
-  auto stage = [&](auto row, int a0, int a1, int src, int bit, int sign_rho, int sweeps, int do_max,
+  auto stage = [&](auto row, auto cone, int a0, int a1, int src, int bit, int sign_rho, int sweeps, int do_max,
                    int dil) -> int {
     int v = a0, t = a1;
     for (int done = 0; done < sweeps;) {
@@ -669,7 +683,7 @@ hipError_t begin_dim(LevelsetBatch& b, hipStream_t st, bool speed) {
                              mx, ns, dil);
         else
           hipLaunchKernelGGL((extend_kernel<DIM, EXT_NPT>), dim3(ext_grid(b.total[r])), B, 0, st, I, off, n, r, v, t,
-                             src, bit, sign_rho, mx, dil);
+                             src, bit, sign_rho, mx, dil, cone(done + 1));
         if (hipGetLastError() != hipSuccess) return -1;
       }
       done += ns;
@@ -682,22 +696,31 @@ hipError_t begin_dim(LevelsetBatch& b, hipStream_t st, bool speed) {
   static_assert((VEL_ITERS + SWEEP_GROUP - 1) / SWEEP_GROUP % 2 == 0 && VEL_ITERS % 2 == 0,
                 "the speed extension must end in V");
   static_assert(LS_READ_REACH + ASLAM_ITERS <= LS_C_MAX, "the u stage's cone must lie in list SC");
-  static_assert(LS_READ_REACH <= ASLAM_ITERS, "the distance is dilated by the u_nn sweeps");
-  // the u_nn stage (lists growing one node per sweep from the computational
-  // points) also dilates the distance to them
+  static_assert(LS_READ_REACH <= ASLAM_ITERS, "the distance is dilated by the u_nn (and 3D: u_n) sweeps");
+  // The u_nn stage (lists growing one node per sweep from the computational
+  // points) also dilates the distance to them; in 3D so does the u_n stage,
+  // and every 3D Aslam sweep skips the nodes beyond its node cone (u_nn
+  // sweep s: distance <= s; u_n: ASLAM_ITERS + s; u: LS_READ_REACH +
+  // ASLAM_ITERS - s + 1, where the distance is exact after the 2 *
+  // ASLAM_ITERS dilations).  2D keeps the tile cones.
   auto cap = [](int r) { return r < LS_C_MAX ? r : LS_C_MAX; };
-  const int unn = stage([&](int, int s1) { return LS_ROW_C + cap(s1); }, A_E2, A_E3, -1, 2, 0, ASLAM_ITERS, 0, 1);
-  const int un = stage([&](int, int s1) { return LS_ROW_C + cap(ASLAM_ITERS + s1); }, A_E1, A_E2, A_E3, 1, 0,
-                       ASLAM_ITERS, 0, 0);
-  const int uext = stage([&](int s0, int) { return LS_ROW_C + cap(LS_READ_REACH + ASLAM_ITERS - s0 + 1); }, A_E0,
-                         A_E1, A_E2, 0, 0, ASLAM_ITERS, 0, 0);
+  const bool nc = DIM == 3;
+  auto no_cone = [](int) { return -1; };
+  const int unn = stage([&](int, int s1) { return LS_ROW_C + cap(s1); }, [&](int s) { return nc ? s : -1; }, A_E2, A_E3,
+                        -1, 2, 0, ASLAM_ITERS, 0, 1);
+  const int un = stage([&](int, int s1) { return LS_ROW_C + cap(ASLAM_ITERS + s1); },
+                       [&](int s) { return nc ? ASLAM_ITERS + s : -1; }, A_E1, A_E2, A_E3, 1, 0, ASLAM_ITERS, 0,
+                       nc ? 1 : 0);
+  const int uext = stage([&](int s0, int) { return LS_ROW_C + cap(LS_READ_REACH + ASLAM_ITERS - s0 + 1); },
+                         [&](int s) { return nc ? LS_READ_REACH + ASLAM_ITERS - s + 1 : -1; }, A_E0, A_E1, A_E2, 0, 0,
+                         ASLAM_ITERS, 0, 0);
   if (unn != A_E3 || un != A_E2 || uext != A_E1) return hipErrorUnknown;
   b.uext = uext;
   if (!speed) return hipSuccess;
   // Stefan speed, extension V <-> S (ends in V), maximum on the last sweep
   LL(LS_ROW_V + VEL_ITERS + 1, velocity_kernel, b.uext);
   auto vcap = [](int r) { return r < LS_V_MAX ? r : LS_V_MAX; };
-  if (stage([&](int, int s1) { return LS_ROW_V + vcap(s1); }, A_V, A_S, -1, 3, 1, VEL_ITERS, 1, 0) != A_V)
+  if (stage([&](int, int s1) { return LS_ROW_V + vcap(s1); }, no_cone, A_V, A_S, -1, 3, 1, VEL_ITERS, 1, 0) != A_V)
     return hipErrorUnknown;
 #undef LL
   return hipSuccess;
