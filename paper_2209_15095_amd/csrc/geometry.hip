@@ -586,9 +586,25 @@ __device__ __forceinline__ void tile_coeff(const GeomInst& I, int slot) {
     irr_bits[(size_t)slot * 4 + (l >> 6)] = ib;
   }
   cdiag[(size_t)slot * TILE_PTS + l] = comp ? c : NOT_COMP;
-  if (n2) atomicAdd(&counts[0], n2);
-  if (n3) atomicAdd(&counts[1], n3);
-  if ((l & 63) == 0) atomicAdd(&counts[2], __popcll(cb));
+  // Case 2 / Case 3 faces and computational points of the tile: one atomic
+  // per counter and tile (a contended global atomic per thread serialises)
+  __shared__ int red[3][4];
+  int a = n2, b3 = n3;
+  for (int o = 32; o > 0; o >>= 1) {
+    a += __shfl_xor(a, o, 64);
+    b3 += __shfl_xor(b3, o, 64);
+  }
+  if ((l & 63) == 0) {
+    red[0][l >> 6] = a;
+    red[1][l >> 6] = b3;
+    red[2][l >> 6] = __popcll(cb);
+  }
+  __syncthreads();
+  if (l < 3) {
+    const int v = red[l][0] + red[l][1] + red[l][2] + red[l][3];
+    if (v) atomicAdd(&counts[l], v);
+  }
+  __syncthreads();
 }
 
 // box -> tile layout (0 at non-computational points).  grid >= cap tiles.
