@@ -323,7 +323,8 @@ def bench_batch_graph(args):
                    "scheme": "etd2rk", "h": h, "free_boundary": False, "krylov_tol": 1e-10,
                    "graph_replay": True},
         "eager_ms_per_step": 1e3 * t_eager / max(args.steps, 1),
-        "autotune": {"group_limit": tune["limit"], "ms_per_launch": {str(k): v for k, v in tune["ms"].items()}},
+        "autotune": {"group_limit": tune["limit"], "stage_min": tune["stage_min"],
+                     "ms_per_launch": {f"{k[0]}/{k[1]}": v for k, v in tune["ms"].items()}},
         "unknown_steps_per_s": prof["n_unknowns"] * args.steps / wall,
         "roofline": roofline_obj(prof, "krylov_group_kernel<2> (graph-replayed step: gather, Krylov, scatter)"),
         "cpu_baseline": None,

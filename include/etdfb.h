@@ -348,6 +348,13 @@ int etd_batch_set_stream(etd_batch* batch, void* hip_stream);
  * as its active tiles can use); 1 makes every instance a single block. */
 int etd_batch_set_group_limit(etd_batch* batch, int32_t max_blocks);
 
+/* Tile schedule of the batched Krylov launch: an instance's Lanczos passes
+ * stage each tile and its face halo in LDS when it has at least min_tiles
+ * active tiles and its blocks take several loop trips (0: whenever they do;
+ * INT32_MAX: never; -1: the library's default, 2048).  Results agree with
+ * the unstaged passes to rounding (the same arithmetic per point). */
+int etd_batch_set_stage_min(etd_batch* batch, int32_t min_tiles);
+
 /* etd_geometry_build for every instance; rho: host array of count device
  * pointers.  One synchronisation for the whole batch.  ETD_ERR_DOMAIN if any
  * instance has a computational point in its two outer box layers. */
@@ -395,16 +402,46 @@ int etd_batch_stats(etd_batch* batch, int32_t i, etd_stats* stats);
  * than one launch per step (more instances than co-resident blocks). */
 int etd_batch_graph_steps(etd_batch* batch, int32_t scheme, double h, double* const* u, int32_t nsteps);
 
-/* Autotuner of the Krylov block schedule: times the batched persistent
- * launch of one frozen-domain step (scheme, h, the current u of every
- * instance) for the group limits 1, 2, 4, 8, 16 and 0 (unlimited; see
- * etd_batch_set_group_limit), trials timed runs each after one untimed
- * run, and keeps the fastest as the batch's group limit.  The Krylov
- * adaptive state of every instance and the u arrays are left as they were.
- * limit_out (nullable): the chosen limit; ms_out (nullable, 6 doubles): mean
- * ms per launch of each candidate in the order above.  Synchronises. */
+/* nsteps free-boundary steps of every instance (the method of etd_batch_step
+ * with rho: level set, Section 4.3; geometry, Section 2; the ETD step,
+ * Section 3), each one replay of a recorded HIP graph with no host work
+ * between steps.  Step k (0-based) is the global step step0 + k; it
+ * reinitialises rho when reinit_every > 0 and (step0 + k + 1) is a multiple
+ * of reinit_every (the schedule of eager steps with reinit = ((m + 1) %
+ * reinit_every == 0)).  Launch sizes are found on the device: every
+ * level-set launch loops over the tile lists that the step's geometry build
+ * left in device memory, the most advection substeps the front guard allows
+ * (4) are launched (each instance skips those beyond its own count), and
+ * the Krylov block
+ * schedule is the one of the active tiles when the graphs are recorded
+ * (kept for later steps; blocks loop over any number of active tiles).
+ * Two graphs (without and with the reinitialisation) are recorded on the
+ * first call and kept while scheme, h, the u and rho pointers, the group
+ * limit and the stage threshold stay the same.  Results are those of eager
+ * steps up to the order of the Krylov reductions (the block schedule).
+ * Errors are latched per instance and reported by etd_batch_sync; unlike
+ * etd_batch_step, a step whose front would move farther than the guard of
+ * the eager steps allows is not refused but latches ETD_ERR_FRONT, and the
+ * instance's arrays are undefined from that step on.  The Krylov launch is
+ * an ordinary kernel node (see etd_batch_graph_steps).  Asynchronous;
+ * ETD_ERR_INVALID if the batch needs more than one launch per step or
+ * u[i] == rho[i]. */
+int etd_batch_graph_free_steps(etd_batch* batch, int32_t scheme, double h, double* const* u, double* const* rho,
+                               int32_t reinit_every, int32_t step0, int32_t nsteps);
+
+/* Autotuner of the Krylov block and tile schedule: times the batched
+ * persistent launch of one frozen-domain step (scheme, h, the current u of
+ * every instance) for the ETD_AUTOTUNE_CANDIDATES pairs of a group limit
+ * (1, 2, 4, 8, 16, 0 = unlimited; see etd_batch_set_group_limit) and a
+ * stage threshold (0, 2048, INT32_MAX; see etd_batch_set_stage_min), limit
+ * major, trials timed runs each after one untimed run, and keeps the
+ * fastest pair.  The Krylov adaptive state of every instance and the u
+ * arrays are left as they were.  limit_out, stage_out (nullable): the
+ * chosen pair; ms_out (nullable, ETD_AUTOTUNE_CANDIDATES doubles): mean ms
+ * per launch of each candidate in the order above.  Synchronises. */
+#define ETD_AUTOTUNE_CANDIDATES 18
 int etd_batch_autotune(etd_batch* batch, int32_t scheme, double h, double* const* u, int32_t trials,
-                       int32_t* limit_out, double* ms_out);
+                       int32_t* limit_out, int32_t* stage_out, double* ms_out);
 
 /* Event timing of the batch launches; profile_read sums the algorithmic
  * bytes and reports the unknowns over all instances. */

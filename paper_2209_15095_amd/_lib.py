@@ -40,6 +40,7 @@ class EtdPhysics(C.Structure):
 
 
 ETD_MAX_SPECIES = 4
+ETD_AUTOTUNE_CANDIDATES = 18
 
 
 class EtdSpecies(C.Structure):
@@ -115,6 +116,7 @@ SIGNATURES = {
     "etd_batch_destroy": (C.c_int, [C.c_void_p]),
     "etd_batch_set_stream": (C.c_int, [C.c_void_p, C.c_void_p]),
     "etd_batch_set_group_limit": (C.c_int, [C.c_void_p, C.c_int32]),
+    "etd_batch_set_stage_min": (C.c_int, [C.c_void_p, C.c_int32]),
     "etd_batch_geometry_build": (C.c_int, [C.c_void_p, C.POINTER(C.c_void_p)]),
     "etd_batch_multistep_step": (C.c_int, [C.c_void_p, C.c_double, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
                                            C.c_int32, C.POINTER(C.c_void_p), C.c_int32, C.POINTER(EtdStats)]),
@@ -122,8 +124,10 @@ SIGNATURES = {
                                  C.POINTER(C.c_void_p), C.c_int32, C.POINTER(EtdStats)]),
     "etd_batch_sync": (C.c_int, [C.c_void_p]),
     "etd_batch_graph_steps": (C.c_int, [C.c_void_p, C.c_int32, C.c_double, C.POINTER(C.c_void_p), C.c_int32]),
+    "etd_batch_graph_free_steps": (C.c_int, [C.c_void_p, C.c_int32, C.c_double, C.POINTER(C.c_void_p),
+                                             C.POINTER(C.c_void_p), C.c_int32, C.c_int32, C.c_int32]),
     "etd_batch_autotune": (C.c_int, [C.c_void_p, C.c_int32, C.c_double, C.POINTER(C.c_void_p), C.c_int32,
-                                     C.POINTER(C.c_int32), C.POINTER(C.c_double)]),
+                                     C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_double)]),
     "etd_batch_stats": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(EtdStats)]),
     "etd_batch_profile_enable": (C.c_int, [C.c_void_p, C.c_int32]),
     "etd_batch_profile_read": (C.c_int, [C.c_void_p, C.POINTER(EtdProfile), C.c_int32]),

@@ -377,19 +377,39 @@ class Batch:
         L.check(self.lib.etd_batch_graph_steps(self.handle, code, float(h), ua, int(nsteps)),
                 "etd_batch_graph_steps")
 
+    def graph_free_steps(self, scheme: str, h: float, us, rhos, reinit_every: int = 0, step0: int = 0,
+                         nsteps: int = 1):
+        """nsteps free-boundary steps (global steps step0 .. step0 + nsteps - 1,
+        reinitialising rho after every reinit_every-th), each one replay of a
+        recorded HIP graph with launch sizes found on the device."""
+        code = SCHEMES[scheme]
+        ua = self._ptrs(us, "u")
+        ra = self._ptrs(rhos, "rho")
+        self._sync_stream()
+        L.check(self.lib.etd_batch_graph_free_steps(self.handle, code, float(h), ua, ra, int(reinit_every),
+                                                    int(step0), int(nsteps)), "etd_batch_graph_free_steps")
+
+    def set_stage_min(self, min_tiles: int):
+        L.check(self.lib.etd_batch_set_stage_min(self.handle, int(min_tiles)), "etd_batch_set_stage_min")
+
     AUTOTUNE_LIMITS = (1, 2, 4, 8, 16, 0)
+    AUTOTUNE_STAGES = (0, 2048, 2 ** 31 - 1)
 
     def autotune(self, scheme: str, h: float, us, trials: int = 3):
-        """Pick the group limit (blocks per instance) with the fastest batched
-        Krylov launch; returns {"limit": chosen, "ms": {limit: mean ms}}."""
+        """Pick the group limit (blocks per instance) and the stage threshold
+        (LDS-staged Lanczos passes from this many active tiles) with the
+        fastest batched Krylov launch; returns {"limit": chosen, "stage_min":
+        chosen, "ms": {(limit, stage_min): mean ms}}."""
         code = SCHEMES[scheme]
         ua = self._ptrs(us, "u")
         self._sync_stream()
         lim = C.c_int32()
-        ms = (C.c_double * 6)()
-        L.check(self.lib.etd_batch_autotune(self.handle, code, float(h), ua, int(trials), C.byref(lim), ms),
-                "etd_batch_autotune")
-        return {"limit": int(lim.value), "ms": dict(zip(self.AUTOTUNE_LIMITS, list(ms)))}
+        stg = C.c_int32()
+        ms = (C.c_double * L.ETD_AUTOTUNE_CANDIDATES)()
+        L.check(self.lib.etd_batch_autotune(self.handle, code, float(h), ua, int(trials), C.byref(lim),
+                                            C.byref(stg), ms), "etd_batch_autotune")
+        keys = [(l_, s_) for l_ in self.AUTOTUNE_LIMITS for s_ in self.AUTOTUNE_STAGES]
+        return {"limit": int(lim.value), "stage_min": int(stg.value), "ms": dict(zip(keys, list(ms)))}
 
     def sync(self):
         L.check(self.lib.etd_batch_sync(self.handle), "etd_batch_sync")

@@ -117,10 +117,32 @@ struct etd_batch {
   double g_h = 0.0;
   long g_geom = -1;
   int g_limit = -1;
+  int g_stage = -2;
   std::vector<double*> g_u;
   KrylovDev* d_gparams = nullptr;    // graph-owned parameter copies
   int* d_gblk = nullptr;
   const double** d_guptr = nullptr;
+  // recorded free-boundary step (etd_batch_graph_free_steps): without and
+  // with the reinitialisation, each with level-set and geometry tables,
+  // parameters and pointers of its own (an eager call rewrites the shared
+  // ones), and the key
+  hipGraph_t fgraph[2] = {nullptr, nullptr};
+  hipGraphExec_t fgexec[2] = {nullptr, nullptr};
+  LevelsetBatch flsb{};
+  GeomBatch fgb{};
+  bool f_alloc = false;
+  int f_scheme = 0;
+  double f_h = 0.0;
+  int f_limit = -1;
+  int f_stage = -2;
+  std::vector<double*> f_u, f_rho;
+  KrylovDev* d_fparams = nullptr;
+  int* d_fblk = nullptr;
+  const double** d_fuptr = nullptr;
+  // replayed free-boundary steps moved the boundaries on the device: the
+  // host's list sizes and active-tile counts are re-read before an eager call
+  bool host_stale = false;
+  int stage_min = -1;         // LDS-staged Lanczos pass from this many active tiles (-1: default)
   int* d_blk = nullptr;       // block -> instance, capacity entries per chunk
   int* h_blk = nullptr;
   hipEvent_t staged = nullptr;
@@ -402,6 +424,7 @@ LsInst levelset_inst(etd_ctx* c, double* rho, double* u) {
   I.tdist = c->band_tmp + (size_t)((c->box.dim - 1) & 1) * c->ntiles;
   I.rr = LS_V_MAX;
   I.status = c->counters + 1;
+  I.cnt = c->counters;
   I.host_dirty = &c->ls.dirty;
   return I;
 }
@@ -979,6 +1002,7 @@ int etd_ctx_profile_read(etd_ctx* c, etd_profile* out, int32_t reset) {
 namespace {
 
 void graph_drop(etd_batch* B);
+void fgraph_drop(etd_batch* B);
 
 void batch_free(etd_batch* B) {
   for (etd_ctx* c : B->inst)
@@ -999,6 +1023,12 @@ void batch_free(etd_batch* B) {
   if (B->d_gparams) (void)hipFree(B->d_gparams);
   if (B->d_gblk) (void)hipFree(B->d_gblk);
   if (B->d_guptr) (void)hipFree(B->d_guptr);
+  fgraph_drop(B);
+  levelset_batch_free(B->flsb);
+  geom_batch_free(B->fgb);
+  if (B->d_fparams) (void)hipFree(B->d_fparams);
+  if (B->d_fblk) (void)hipFree(B->d_fblk);
+  if (B->d_fuptr) (void)hipFree(B->d_fuptr);
   timer_free(B->t_krylov);
   timer_free(B->t_levelset);
   timer_free(B->t_geometry);
@@ -1035,6 +1065,7 @@ int batch_schedule(const etd_batch* B, int ch, int mode, double h, KrylovDev* pa
     KrylovDev P = krylov_params(B->inst[i0 + i], mode);
     P.h = h;
     P.first = B->ms_first;
+    if (B->stage_min >= 0) P.stage_min = B->stage_min;
     P.g_first = blocks;
     P.g_size = g[i];
     params[i] = P;
@@ -1121,7 +1152,107 @@ int graph_record(etd_batch* B, int scheme, double h, double* const* u) {
   B->g_h = h;
   B->g_geom = B->geom_gen;
   B->g_limit = B->group_limit;
+  B->g_stage = B->stage_min;
   B->g_u.assign(u, u + n);
+  return ETD_OK;
+}
+
+void fgraph_drop(etd_batch* B) {
+  for (int r = 0; r < 2; ++r) {
+    if (B->fgexec[r]) (void)hipGraphExecDestroy(B->fgexec[r]);
+    if (B->fgraph[r]) (void)hipGraphDestroy(B->fgraph[r]);
+    B->fgexec[r] = nullptr;
+    B->fgraph[r] = nullptr;
+  }
+  B->f_u.clear();
+  B->f_rho.clear();
+}
+
+// Record one free-boundary step of every instance (scheme, h; u and rho
+// updated in place) twice, without and with the reinitialisation: the
+// level set and the geometry device-sized (launch rows from the device
+// counters, fixed grids, the front guard checked on the device), then the
+// gather, the batched Krylov launch (the block schedule of the current
+// active tiles; an ordinary launch, as in graph_record) and the scatter.
+int graph_free_record(etd_batch* B, int scheme, double h, double* const* u, double* const* rho) {
+  fgraph_drop(B);
+  const int n = B->count;
+  if (!B->f_alloc) {
+    bool ok = levelset_batch_alloc(B->flsb, n, B->dim) == hipSuccess;
+    ok &= geom_batch_alloc(B->fgb, n, NCOUNTERS) == hipSuccess;
+    ok &= hipMalloc(&B->d_fparams, sizeof(KrylovDev) * n) == hipSuccess;
+    ok &= hipMalloc(&B->d_fblk, sizeof(int) * (size_t)B->capacity) == hipSuccess;
+    ok &= hipMalloc(&B->d_fuptr, sizeof(double*) * n) == hipSuccess;
+    if (!ok) return ETD_ERR_HIP;
+    for (int i = 0; i < n; ++i) B->fgb.h_tab[i] = geom_inst(B->inst[i]);
+    HIP_TRY(geom_batch_prefix(B->fgb));
+    B->f_alloc = true;
+  }
+  HIP_TRY(hipStreamSynchronize(B->stream));
+  for (int i = 0; i < n; ++i) {
+    B->fgb.h_tab[i].rho = rho[i];
+    B->flsb.h_inst[i] = levelset_inst(B->inst[i], rho[i], u[i]);
+  }
+  B->flsb.device_sized = true;
+  HIP_TRY(levelset_upload(B->flsb, B->stream));
+  HIP_TRY(geom_upload(B->fgb, B->stream));
+  const int mode = job_of(scheme);
+  std::vector<KrylovDev> params(n);
+  std::vector<int> blk(B->capacity);
+  bool coop = false;
+  const int blocks = batch_schedule(B, 0, mode, h, params.data(), blk.data(), &coop);
+  HIP_TRY(hipStreamSynchronize(B->stream));
+  HIP_TRY(hipMemcpy(B->d_fparams, params.data(), sizeof(KrylovDev) * n, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(B->d_fblk, blk.data(), sizeof(int) * blocks, hipMemcpyHostToDevice));
+  std::vector<const double*> up(u, u + n);
+  HIP_TRY(hipMemcpy(B->d_fuptr, up.data(), sizeof(double*) * n, hipMemcpyHostToDevice));
+  if (!B->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&B->cap_stream, hipStreamNonBlocking));
+  hipStream_t cs = B->cap_stream;
+  for (int r = 0; r < 2; ++r) {
+    HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    hipError_t e = levelset_begin(B->flsb, h, r, cs);
+    if (e == hipSuccess) e = levelset_end(B->flsb, cs);
+    if (e == hipSuccess) e = launch_geometry(B->fgb, GEOM_RADII, cs, true);
+    if (e == hipSuccess) e = launch_gather_batch(B->fgb, B->d_fuptr, V_X0, cs);
+    if (e == hipSuccess) e = launch_krylov_group(B->dim, B->d_fparams, n, B->d_fblk, blocks, false, cs);
+    if (e == hipSuccess) e = launch_scatter_batch(B->fgb, (double* const*)B->d_fuptr, V_U, cs);
+    hipGraph_t g = nullptr;
+    const hipError_t e2 = hipStreamEndCapture(cs, &g);
+    if (e != hipSuccess || e2 != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      fgraph_drop(B);
+      return ETD_ERR_HIP;
+    }
+    B->fgraph[r] = g;
+    if (hipGraphInstantiate(&B->fgexec[r], g, nullptr, nullptr, 0) != hipSuccess) {
+      fgraph_drop(B);
+      return ETD_ERR_HIP;
+    }
+  }
+  B->f_scheme = scheme;
+  B->f_h = h;
+  B->f_limit = B->group_limit;
+  B->f_stage = B->stage_min;
+  B->f_u.assign(u, u + n);
+  B->f_rho.assign(rho, rho + n);
+  return ETD_OK;
+}
+
+// After replayed free-boundary steps: the host's copies of every instance's
+// counters (active tiles, list sizes) from the device.
+int refresh_host(etd_batch* B) {
+  if (!B->host_stale) return ETD_OK;
+  for (etd_ctx* c : B->inst)
+    HIP_TRY(hipMemcpyAsync(c->h_counters, c->counters, NCOUNTERS * sizeof(int), hipMemcpyDeviceToHost, B->stream));
+  HIP_TRY(hipStreamSynchronize(B->stream));
+  for (etd_ctx* c : B->inst) {
+    c->n_active_host = c->h_counters[0];
+    for (int q = 0; q <= LS_C_MAX; ++q) c->ncum_c[q] = c->h_counters[LS_CNT_C + q];
+    for (int q = 0; q <= LS_V_MAX; ++q) c->ncum_v[q] = c->h_counters[LS_CNT_V + q];
+    c->nu_host = c->h_counters[LS_CNT_U];
+    choose_launch(c);
+  }
+  B->host_stale = false;
   return ETD_OK;
 }
 
@@ -1199,10 +1330,17 @@ int etd_batch_set_group_limit(etd_batch* B, int32_t max_blocks) {
   return ETD_OK;
 }
 
+int etd_batch_set_stage_min(etd_batch* B, int32_t min_tiles) {
+  if (!B || min_tiles < -1) return ETD_ERR_INVALID;
+  B->stage_min = min_tiles;
+  return ETD_OK;
+}
+
 int etd_batch_geometry_build(etd_batch* B, const double* const* rho) {
   if (!B || !rho) return ETD_ERR_INVALID;
   for (int i = 0; i < B->count; ++i)
     if (!rho[i]) return ETD_ERR_INVALID;
+  B->host_stale = false;   // the build refreshes the host's counters
   // the table upload reads pinned memory: the previous build has been
   // synchronised, so it may be rewritten
   for (int i = 0; i < B->count; ++i) B->gb.h_tab[i].rho = rho[i];
@@ -1267,6 +1405,7 @@ int etd_batch_step(etd_batch* B, int32_t scheme, double h, double* const* u, dou
     if (rho && !rho[i]) return ETD_ERR_INVALID;
   }
   int r;
+  if ((r = refresh_host(B))) return r;
   if (rho) {
     bool all = true;
     for (etd_ctx* c : B->inst) all &= c->have_geometry;
@@ -1290,6 +1429,7 @@ int etd_batch_multistep_step(etd_batch* B, double h, double* const* u, double* c
     if (rho && (!rho[i] || f_prev[i] == rho[i])) return ETD_ERR_INVALID;
   }
   int r;
+  if ((r = refresh_host(B))) return r;
   if (rho) {
     bool all = true;
     for (etd_ctx* c : B->inst) all &= c->have_geometry;
@@ -1327,8 +1467,10 @@ int etd_batch_graph_steps(etd_batch* B, int32_t scheme, double h, double* const*
   for (etd_ctx* c : B->inst)
     if (!c->have_geometry) return ETD_ERR_NO_GEOMETRY;
   if (B->nchunks != 1) return ETD_ERR_INVALID;
+  int rr = refresh_host(B);
+  if (rr) return rr;
   bool same = B->gexec && B->g_scheme == scheme && B->g_h == h && B->g_geom == B->geom_gen &&
-              B->g_limit == B->group_limit && (int)B->g_u.size() == B->count;
+              B->g_limit == B->group_limit && B->g_stage == B->stage_min && (int)B->g_u.size() == B->count;
   for (int i = 0; same && i < B->count; ++i) same = B->g_u[i] == u[i];
   if (!same) {
     const int r = graph_record(B, scheme, h, u);
@@ -1340,12 +1482,50 @@ int etd_batch_graph_steps(etd_batch* B, int32_t scheme, double h, double* const*
   return ETD_OK;
 }
 
+int etd_batch_graph_free_steps(etd_batch* B, int32_t scheme, double h, double* const* u, double* const* rho,
+                               int32_t reinit_every, int32_t step0, int32_t nsteps) {
+  if (!B || !u || !rho || nsteps < 0 || step0 < 0 || reinit_every < 0 || !(h >= 0.0) || !isfinite(h))
+    return ETD_ERR_INVALID;
+  if (scheme < ETD_SCHEME_ETD1 || scheme > ETD_SCHEME_ETD4RK_SIMUL) return ETD_ERR_INVALID;
+  for (int i = 0; i < B->count; ++i)
+    if (!u[i] || !rho[i] || u[i] == rho[i]) return ETD_ERR_INVALID;
+  if (B->nchunks != 1) return ETD_ERR_INVALID;
+  int r = refresh_host(B);
+  if (r) return r;
+  bool all = true;
+  for (etd_ctx* c : B->inst) all &= c->have_geometry;
+  if (!all && (r = etd_batch_geometry_build(B, rho))) return r;
+  bool same = B->fgexec[0] && B->fgexec[1] && B->f_scheme == scheme && B->f_h == h &&
+              B->f_limit == B->group_limit && B->f_stage == B->stage_min && (int)B->f_u.size() == B->count;
+  for (int i = 0; same && i < B->count; ++i) same = B->f_u[i] == u[i] && B->f_rho[i] == rho[i];
+  if (!same) {
+    const bool prof = B->profiling;
+    B->profiling = false;
+    r = graph_free_record(B, scheme, h, u, rho);
+    B->profiling = prof;
+    if (r) return r;
+  }
+  HIP_TRY(timer_begin(B->profiling, B->stream, B->t_krylov));
+  for (int k = 0; k < nsteps; ++k) {
+    const int reinit = (reinit_every > 0 && (step0 + k + 1) % reinit_every == 0) ? 1 : 0;
+    HIP_TRY(hipGraphLaunch(B->fgexec[reinit], B->stream));
+  }
+  HIP_TRY(timer_end(B->profiling, B->stream, B->t_krylov));
+  if (nsteps > 0) {
+    B->host_stale = true;
+    ++B->geom_gen;
+  }
+  return ETD_OK;
+}
+
 int etd_batch_autotune(etd_batch* B, int32_t scheme, double h, double* const* u, int32_t trials,
-                       int32_t* limit_out, double* ms_out) {
+                       int32_t* limit_out, int32_t* stage_out, double* ms_out) {
   if (!B || !u || trials < 1 || !(h >= 0.0) || !isfinite(h)) return ETD_ERR_INVALID;
   if (scheme < ETD_SCHEME_ETD1 || scheme > ETD_SCHEME_ETD4RK_SIMUL) return ETD_ERR_INVALID;
   for (int i = 0; i < B->count; ++i)
     if (!u[i]) return ETD_ERR_INVALID;
+  int rr = refresh_host(B);
+  if (rr) return rr;
   for (etd_ctx* c : B->inst)
     if (!c->have_geometry) return ETD_ERR_NO_GEOMETRY;
   const int mode = job_of(scheme);
@@ -1372,16 +1552,18 @@ int etd_batch_autotune(etd_batch* B, int32_t scheme, double h, double* const* u,
   hipEvent_t e0 = nullptr, e1 = nullptr;
   int result = ETD_OK;
   const bool prof = B->profiling;
-  const int old_limit = B->group_limit;
+  const int old_limit = B->group_limit, old_stage = B->stage_min;
   static const int cand[6] = {1, 2, 4, 8, 16, 0};
+  static const int stage_cand[3] = {0, STAGE_MIN_TILES, INT32_MAX};
   double best = 1e300;
-  int best_limit = old_limit;
+  int best_limit = old_limit, best_stage = old_stage;
   B->profiling = false;
   if (restore(true) != hipSuccess || hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
     result = ETD_ERR_HIP;
   }
-  for (int q = 0; q < 6 && result == ETD_OK; ++q) {
-    B->group_limit = cand[q];
+  for (int q = 0; q < ETD_AUTOTUNE_CANDIDATES && result == ETD_OK; ++q) {
+    B->group_limit = cand[q / 3];
+    B->stage_min = stage_cand[q % 3];
     double sum = 0.0;
     for (int rep = 0; rep <= trials && result == ETD_OK; ++rep) {
       float ms = 0.0f;
@@ -1396,10 +1578,12 @@ int etd_batch_autotune(etd_batch* B, int32_t scheme, double h, double* const* u,
     if (ms_out) ms_out[q] = mean;
     if (result == ETD_OK && mean < best) {
       best = mean;
-      best_limit = cand[q];
+      best_limit = B->group_limit;
+      best_stage = B->stage_min;
     }
   }
   B->group_limit = result == ETD_OK ? best_limit : old_limit;
+  B->stage_min = result == ETD_OK ? best_stage : old_stage;
   B->profiling = prof;
   if (restore(false) != hipSuccess && result == ETD_OK) result = ETD_ERR_HIP;
   if (hipStreamSynchronize(B->stream) != hipSuccess && result == ETD_OK) result = ETD_ERR_HIP;
@@ -1408,6 +1592,7 @@ int etd_batch_autotune(etd_batch* B, int32_t scheme, double h, double* const* u,
   (void)hipFree(save);
   if (result == ETD_OK) result = etd_batch_sync(B);   // a device error in a trial
   if (limit_out) *limit_out = B->group_limit;
+  if (stage_out) *stage_out = B->stage_min;
   return result;
 }
 

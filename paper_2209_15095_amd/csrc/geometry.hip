@@ -104,45 +104,56 @@ __global__ __launch_bounds__(256) void classify_kernel(const GeomInst* __restric
   if (id < I.nodes) classify_node(I.b, I.rho, I.mask, I.tile_flag, I.tile_vb, I.counters + 1, id);
 }
 
-// One block of 1024 threads per instance: exclusive scan of tile flags.
+// One block of 1024 threads per instance: exclusive scan of tile flags, in
+// chunks of SCAN_CHUNK tiles: the chunk's flags are loaded coalesced into
+// LDS (bytes), thread t counts the flags of its contiguous run of
+// SCAN_CHUNK / 1024 tiles there, one block scan gives each run its first
+// slot, and the run's slots are written in order.
+constexpr int SCAN_CHUNK = 32768;
+
 __global__ __launch_bounds__(1024) void scan_tiles_kernel(const GeomInst* __restrict__ tab) {
+  constexpr int RUN = SCAN_CHUNK / 1024;
   const GeomInst& I = tab[blockIdx.x];
   const int* __restrict__ tile_flag = I.tile_flag;
   const int ntiles = I.ntiles;
   int* __restrict__ tile_map = I.tile_map;
   int* __restrict__ slot_tile = I.slot_tile;
-  int* __restrict__ n_active = I.counters + 0;
-  __shared__ int warp_tot[16];
+  __shared__ uint8_t fl[SCAN_CHUNK];
+  __shared__ int wave_tot[16];
   __shared__ int carry;
   if (threadIdx.x == 0) carry = 0;
-  __syncthreads();
-  for (int base = 0; base < ntiles; base += 1024) {
-    const int t = base + threadIdx.x;
-    const int f = (t < ntiles) ? (tile_flag[t] != 0) : 0;
-    // inclusive scan within the wave
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    int x = f;
-    for (int off = 1; off < 64; off <<= 1) {
-      int y = __shfl_up(x, off, 64);
-      if (lane >= off) x += y;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int base = 0; base < ntiles; base += SCAN_CHUNK) {
+    const int n = min(SCAN_CHUNK, ntiles - base);
+#pragma unroll 8
+    for (int k = threadIdx.x; k < SCAN_CHUNK; k += 1024) fl[k] = (k < n && tile_flag[base + k] != 0) ? 1 : 0;
+    __syncthreads();
+    const int r0 = (int)threadIdx.x * RUN;
+    int cnt = 0;
+    for (int k = 0; k < RUN; ++k) cnt += fl[r0 + k];
+    int x = cnt;
+    for (int o = 1; o < 64; o <<= 1) {
+      const int y = __shfl_up(x, o, 64);
+      if (lane >= o) x += y;
     }
-    if (lane == 63) warp_tot[w] = x;
+    if (lane == 63) wave_tot[w] = x;
     __syncthreads();
     if (threadIdx.x == 0) {
-      int acc = 0;
-      for (int q = 0; q < 16; ++q) { int v = warp_tot[q]; warp_tot[q] = acc; acc += v; }
+      int acc = carry;
+      for (int q = 0; q < 16; ++q) { const int v = wave_tot[q]; wave_tot[q] = acc; acc += v; }
+      carry = acc;
     }
     __syncthreads();
-    const int excl = carry + warp_tot[w] + x - f;
-    if (t < ntiles) {
-      tile_map[t] = f ? excl : -1;
-      if (f) slot_tile[excl] = t;
+    int slot = wave_tot[w] + x - cnt;
+    for (int k = 0; k < RUN && r0 + k < n; ++k) {
+      const int t = base + r0 + k;
+      const bool f = fl[r0 + k] != 0;
+      tile_map[t] = f ? slot : -1;
+      if (f) slot_tile[slot++] = t;
     }
-    __syncthreads();
-    if (threadIdx.x == 1023) carry = excl + f;
     __syncthreads();
   }
-  if (threadIdx.x == 0) *n_active = carry;
+  if (threadIdx.x == 0) I.counters[0] = carry;   // active tiles
 }
 
 // L1 distances on the tile grid (level-set bands), one axis of a separable
@@ -758,10 +769,14 @@ hipError_t geom_batch_prefix(GeomBatch& gb) {
 
 static const int* pre_of(const GeomBatch& gb, int q) { return gb.d_pre + q * (gb.count + 1); }
 
-hipError_t launch_geometry(GeomBatch& gb, const int* radii, hipStream_t s) {
+hipError_t geom_upload(GeomBatch& gb, hipStream_t s) {
+  return hipMemcpyAsync(gb.d_tab, gb.h_tab, sizeof(GeomInst) * gb.count, hipMemcpyHostToDevice, s);
+}
+
+hipError_t launch_geometry(GeomBatch& gb, const int* radii, hipStream_t s, bool device_sized) {
   const int n = gb.count;
-  hipError_t e = hipMemcpyAsync(gb.d_tab, gb.h_tab, sizeof(GeomInst) * n, hipMemcpyHostToDevice, s);
-  if (e != hipSuccess) return e;
+  hipError_t e = hipSuccess;
+  if (!device_sized && (e = geom_upload(gb, s)) != hipSuccess) return e;
   hipLaunchKernelGGL(geom_zero_kernel, dim3(gb.blocks[GEOM_PRE_T256]), dim3(256), 0, s, gb.d_tab,
                      pre_of(gb, GEOM_PRE_T256), n);
   hipLaunchKernelGGL(classify_kernel, dim3(gb.blocks[GEOM_PRE_NODE]), dim3(256), 0, s, gb.d_tab,
@@ -781,6 +796,7 @@ hipError_t launch_geometry(GeomBatch& gb, const int* radii, hipStream_t s) {
                        pre_of(gb, GEOM_PRE_T256), n, axis, r[0], r[1], r[2], 1000);
   hipLaunchKernelGGL(band_lists_kernel, dim3(n), dim3(1024), 0, s, gb.d_tab, dim - 1, radii[0], radii[1], radii[2],
                      radii[3], radii[4]);
+  if ((e = hipGetLastError()) != hipSuccess || device_sized) return e;
   hipLaunchKernelGGL(collect_counters_kernel, dim3(blocks_for((size_t)n * gb.ncnt, 256)), dim3(256), 0, s,
                      gb.d_tab, n, gb.ncnt, gb.d_cnt);
   if ((e = hipGetLastError()) != hipSuccess) return e;

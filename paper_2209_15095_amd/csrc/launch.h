@@ -90,7 +90,11 @@ hipError_t geom_batch_prefix(GeomBatch& gb);
 // (asynchronous: read after synchronising the stream).  The table's rho
 // pointers must be set; the table is uploaded from pinned memory, so it
 // must not change before the stream has passed this call.
-hipError_t launch_geometry(GeomBatch& gb, const int* radii, hipStream_t s);
+hipError_t launch_geometry(GeomBatch& gb, const int* radii, hipStream_t s, bool device_sized = false);
+// Device-sized builds (for graph capture) neither upload the table nor copy
+// the counters back: geom_upload copies the table to the device beforehand
+// (asynchronous, from pinned memory).
+hipError_t geom_upload(GeomBatch& gb, hipStream_t s);
 // After launch_geometry of a one-instance table whose beta_face, vcoef and
 // tap arrays are set: the variable-beta coefficients and boundary taps.
 hipError_t launch_geometry_var(GeomBatch& gb, hipStream_t s);

@@ -15,9 +15,10 @@
 // The advection changes rho only where the speed is nonzero and reads its
 // WENO stencil 3 nodes further; the reinitialisation acts on a narrow band.
 //
-// One launch per sweep serves a whole batch: block b works on tile
+// One launch per sweep serves a whole batch: virtual block b works on tile
 // b - off[i] of the list of instance i, off[] being the prefix sums of the
-// list sizes.
+// list sizes; a launch's blocks loop over the virtual blocks of its row (the
+// row total is read on the device), so a launch needs no size from the host.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -34,6 +35,10 @@ constexpr int ASLAM_ITERS = 25;
 // step with max V * dt > LS_MAX_FRONT_NODES * h is refused on the host
 // before rho or u change.
 constexpr int LS_MAX_FRONT_NODES = 2;
+// Advection substeps: max(1, ceil(max V dt / (h/2))), at most this many
+// within the guard (graph replays launch this many and skip the rest on the
+// device).
+constexpr int LS_MAX_SUBSTEPS = 2 * LS_MAX_FRONT_NODES;
 constexpr int VEL_ITERS = 20;
 constexpr int REINIT_ITERS = 10;
 // Narrow band of the reinitialisation (units of h): nodes with
@@ -111,6 +116,7 @@ struct LsInst {
   const int* tdist;           // packed tile distances of the lists (high 16 bits: Dv)
   int rr;                     // radius of list R (Dv <= rr)
   int* status;                // latched device error of the instance
+  const int* cnt;             // the instance's geometry counters (list sizes, on the device)
   double* vmax;               // set by levelset_begin
   int dirty;                  // set by levelset_begin / levelset_extend: clear the whole box first
   bool* host_dirty;           // LevelsetScratch::dirty (host address, never read on the device)
@@ -131,6 +137,14 @@ struct LevelsetBatch {
   int reinit = 0;
   int uext = 0;               // scratch array holding u_ext after levelset_begin
   bool any_dirty = false;     // some instance's scratch is cleared over the whole box first
+  // Device-sized mode (for graph capture): the launch rows come from the
+  // geometry counters on the device, every launch has a fixed grid, the
+  // front guard is checked on the device (ST_FRONT latched, the step goes
+  // on), LS_MAX_SUBSTEPS advection substeps are launched, and nothing is
+  // copied to or from the host.  The instance table must be on the device
+  // (levelset_upload) before.
+  bool device_sized = false;
+  int max_tiles = 0;          // sum of the instances' box tiles (device-sized grids)
 };
 
 hipError_t levelset_alloc(LevelsetScratch& s, size_t nodes);
@@ -144,6 +158,10 @@ void levelset_batch_free(LevelsetBatch& b);
 // synchronised the stream, levelset_end enqueues the advection substeps, the
 // reinitialisation (if reinit) and the restriction of u.
 hipError_t levelset_begin(LevelsetBatch& b, double dt, int reinit, hipStream_t stream);
+// Device-sized mode: copy the instance table (h_inst, with dirty flags
+// taken as for a pass) to the device and clear every dirty scratch; the
+// caller synchronises the stream before capturing levelset_begin/end.
+hipError_t levelset_upload(LevelsetBatch& b, hipStream_t stream);
 hipError_t levelset_end(LevelsetBatch& b, hipStream_t stream);
 // The extrapolation of Step 2 alone (the same sweeps as for u): each
 // instance's u (any box field known on the computational points of rho) is

@@ -74,11 +74,13 @@ __device__ __forceinline__ Where locate_at(const LsInst* __restrict__ insts, con
   return w;
 }
 
-template <int DIM>
-__device__ __forceinline__ Where locate(const LsInst* __restrict__ insts, const int* __restrict__ off, int count,
-                                       int row) {
-  return locate_at<DIM>(insts, off, count, row, (int)blockIdx.x);
+// Virtual blocks of a launch row (the row's total, read on the device); a
+// launch's blocks loop over them, so any grid serves any list size.
+__device__ __forceinline__ int row_total(const int* __restrict__ off, int count, int row) {
+  return off[(size_t)row * (count + 1) + count];
 }
+#define FOR_VBLOCKS(ROW) \
+  for (int vb_ = (int)blockIdx.x, tot_ = row_total(off, count, (ROW)); vb_ < tot_; vb_ += (int)gridDim.x)
 
 __device__ __forceinline__ gptr<double> arr(const LsInst& I, int a) { return glb(I.buf) + (size_t)a * I.nodes; }
 
@@ -113,34 +115,38 @@ __device__ __forceinline__ bool comp_point(const LsInst& I, const Where& w, gptr
 template <int DIM>
 __global__ __launch_bounds__(256) void zero_kernel(const LsInst* __restrict__ insts, const int* __restrict__ off,
                                                    int count) {
-  const Where w = locate<DIM>(insts, off, count, LS_ROW_FULL);
-  const LsInst& I = *w.I;
-  if (!I.dirty) return;
-  if (w.local == 0 && threadIdx.x == 0) *glb(I.vmax) = 0.0;
-  if (!w.in) return;
-  for (int a = A_E0; a <= A_V; ++a) arr(I, a)[w.id] = 0.0;
-  arr(I, A_S)[w.id] = 0.0;
-  glb(I.dist)[w.id] = 255;
+  FOR_VBLOCKS(LS_ROW_FULL) {
+    const Where w = locate_at<DIM>(insts, off, count, LS_ROW_FULL, vb_);
+    const LsInst& I = *w.I;
+    if (!I.dirty) continue;
+    if (w.local == 0 && threadIdx.x == 0) *glb(I.vmax) = 0.0;
+    if (!w.in) continue;
+    for (int a = A_E0; a <= A_V; ++a) arr(I, a)[w.id] = 0.0;
+    arr(I, A_S)[w.id] = 0.0;
+    glb(I.dist)[w.id] = 255;
+  }
 }
 
 // list U: normals, K0 (bit 0, other bits cleared), E0 = K0 ? u : 0
 template <int DIM>
 __global__ __launch_bounds__(256) void init_kernel(const LsInst* __restrict__ insts, const int* __restrict__ off,
                                                    int count) {
-  const Where w = locate<DIM>(insts, off, count, LS_ROW_U);
-  if (!w.in) return;
-  const LsInst& I = *w.I;
-  gptr<const double> rho = glb((const double*)I.rho);
-  double g[3] = {0.0, 0.0, 0.0};
-  for (int d = 0; d < DIM; ++d) g[d] = (rho[shifted(I, w, d, 1)] - rho[shifted(I, w, d, -1)]) / (2.0 * I.h);
-  double mag = 0.0;
-  for (int d = 0; d < DIM; ++d) mag += g[d] * g[d];
-  mag = fmax(sqrt(mag), 1e-12);
-  for (int d = 0; d < DIM; ++d) arr(I, A_NX + d)[w.id] = g[d] / mag;
-  const bool c = comp_point<DIM>(I, w, rho);
-  glb(I.known)[w.id] = c ? 1 : 0;
-  glb(I.dist)[w.id] = c ? 0 : 255;
-  arr(I, A_E0)[w.id] = c ? glb((const double*)I.u)[w.id] : 0.0;
+  FOR_VBLOCKS(LS_ROW_U) {
+    const Where w = locate_at<DIM>(insts, off, count, LS_ROW_U, vb_);
+    if (!w.in) continue;
+    const LsInst& I = *w.I;
+    gptr<const double> rho = glb((const double*)I.rho);
+    double g[3] = {0.0, 0.0, 0.0};
+    for (int d = 0; d < DIM; ++d) g[d] = (rho[shifted(I, w, d, 1)] - rho[shifted(I, w, d, -1)]) / (2.0 * I.h);
+    double mag = 0.0;
+    for (int d = 0; d < DIM; ++d) mag += g[d] * g[d];
+    mag = fmax(sqrt(mag), 1e-12);
+    for (int d = 0; d < DIM; ++d) arr(I, A_NX + d)[w.id] = g[d] / mag;
+    const bool c = comp_point<DIM>(I, w, rho);
+    glb(I.known)[w.id] = c ? 1 : 0;
+    glb(I.dist)[w.id] = c ? 0 : 255;
+    arr(I, A_E0)[w.id] = c ? glb((const double*)I.u)[w.id] : 0.0;
+  }
 }
 
 // every read of the extended u (velocity, restriction) must fall within
@@ -173,33 +179,39 @@ __device__ __forceinline__ double dir_deriv(const LsInst& I, const Where& w, gpt
 template <int DIM>
 __global__ __launch_bounds__(256) void known1_kernel(const LsInst* __restrict__ insts, const int* __restrict__ off,
                                                      int count) {
-  const Where w = locate<DIM>(insts, off, count, LS_ROW_C + ASLAM_ITERS + 1);
-  if (!w.in) return;
-  const LsInst& I = *w.I;
-  if (known_all<DIM>(I, w, 0)) glb(I.known)[w.id] |= (uint8_t)2;
+  FOR_VBLOCKS(LS_ROW_C + ASLAM_ITERS + 1) {
+    const Where w = locate_at<DIM>(insts, off, count, LS_ROW_C + ASLAM_ITERS + 1, vb_);
+    if (!w.in) continue;
+    const LsInst& I = *w.I;
+    if (known_all<DIM>(I, w, 0)) glb(I.known)[w.id] |= (uint8_t)2;
+  }
 }
 
 // list A1: K2 (bit 2) and E1 = K1 ? n . grad E0 : 0
 template <int DIM>
 __global__ __launch_bounds__(256) void known2_un_kernel(const LsInst* __restrict__ insts,
                                                         const int* __restrict__ off, int count) {
-  const Where w = locate<DIM>(insts, off, count, LS_ROW_C + ASLAM_ITERS + 1);
-  if (!w.in) return;
-  const LsInst& I = *w.I;
-  const bool k1 = (glb((const uint8_t*)I.known)[w.id] >> 1) & 1;
-  if (known_all<DIM>(I, w, 1)) glb(I.known)[w.id] |= (uint8_t)4;
-  arr(I, A_E1)[w.id] = k1 ? dir_deriv<DIM>(I, w, arr(I, A_E0)) : 0.0;
+  FOR_VBLOCKS(LS_ROW_C + ASLAM_ITERS + 1) {
+    const Where w = locate_at<DIM>(insts, off, count, LS_ROW_C + ASLAM_ITERS + 1, vb_);
+    if (!w.in) continue;
+    const LsInst& I = *w.I;
+    const bool k1 = (glb((const uint8_t*)I.known)[w.id] >> 1) & 1;
+    if (known_all<DIM>(I, w, 1)) glb(I.known)[w.id] |= (uint8_t)4;
+    arr(I, A_E1)[w.id] = k1 ? dir_deriv<DIM>(I, w, arr(I, A_E0)) : 0.0;
+  }
 }
 
 // list A1: E2 = K2 ? n . grad E1 : 0
 template <int DIM>
 __global__ __launch_bounds__(256) void unn_kernel(const LsInst* __restrict__ insts, const int* __restrict__ off,
                                                   int count) {
-  const Where w = locate<DIM>(insts, off, count, LS_ROW_C + ASLAM_ITERS + 1);
-  if (!w.in) return;
-  const LsInst& I = *w.I;
-  const bool k2 = (glb((const uint8_t*)I.known)[w.id] >> 2) & 1;
-  arr(I, A_E2)[w.id] = k2 ? dir_deriv<DIM>(I, w, arr(I, A_E1)) : 0.0;
+  FOR_VBLOCKS(LS_ROW_C + ASLAM_ITERS + 1) {
+    const Where w = locate_at<DIM>(insts, off, count, LS_ROW_C + ASLAM_ITERS + 1, vb_);
+    if (!w.in) continue;
+    const LsInst& I = *w.I;
+    const bool k2 = (glb((const uint8_t*)I.known)[w.id] >> 2) & 1;
+    arr(I, A_E2)[w.id] = k2 ? dir_deriv<DIM>(I, w, arr(I, A_E1)) : 0.0;
+  }
 }
 
 // Launch shape of the 3D sweeps: tiles per block, XCD-contiguous ranges.
@@ -232,106 +244,110 @@ template <int DIM, int NPT>
 __global__ __launch_bounds__(256) void extend_kernel(const LsInst* __restrict__ insts, const int* __restrict__ off,
                                                      int count, int row, int v_arr, int out_arr, int src_arr,
                                                      int bit, int sign_rho, int do_max, int dil, int cone) {
-  const int total = off[(size_t)row * (count + 1) + count];
-  // XCD-contiguous ranges: workgroups go to the 8 XCDs in turn, so block b
-  // takes entry (b % 8) * chunk + b / 8 of the row (grid 8 * chunk) and each
-  // XCD walks a contiguous range of the list, whose neighbouring tiles share
-  // halo lines in that XCD's L2.
+  const int total = row_total(off, count, row);
+  // XCD-contiguous ranges: workgroups go to the 8 XCDs in turn, so virtual
+  // block v takes entry (v % 8) * chunk + v / 8 of the row (8 * chunk
+  // virtual blocks; grids are multiples of 8, so v % 8 is the XCD of the
+  // block that runs it) and each XCD walks a contiguous range of the list,
+  // whose neighbouring tiles share halo lines in that XCD's L2.
   const int nvb = (total + NPT - 1) / NPT;
   const int chunk = EXT_XCD ? (nvb + 7) / 8 : 0;
-  const int bx = EXT_XCD ? ((int)blockIdx.x % 8) * chunk + (int)blockIdx.x / 8 : (int)blockIdx.x;
-  Where w[NPT];
-#pragma unroll
-  for (int q = 0; q < NPT; ++q) {
-    const int vb = bx * NPT + q;
-    if (vb < total) {
-      w[q] = locate_at<DIM>(insts, off, count, row, vb);
-    } else {
-      w[q].I = insts;
-      w[q].in = false;
-      w[q].id = 0;
-      w[q].i = w[q].j = w[q].k = 0;
-    }
-  }
-  size_t im[NPT][DIM], ip[NPT][DIM];
-  int m[NPT];
-  bool act[NPT];
-#pragma unroll
-  for (int q = 0; q < NPT; ++q) {
-    act[q] = false;
-    m[q] = 0;
-    if (!w[q].in) continue;
-    const LsInst& I = *w[q].I;
-    for (int d = 0; d < DIM; ++d) {
-      im[q][d] = shifted(I, w[q], d, -1);
-      ip[q][d] = shifted(I, w[q], d, 1);
-    }
-    if (dil || cone >= 0) {
-      gptr<const uint8_t> ds = glb((const uint8_t*)I.dist);
-      m[q] = ds[w[q].id];
-      if (dil) {
-        int dn = 255;
-        for (int d = 0; d < DIM; ++d) dn = min(dn, min((int)ds[im[q][d]], (int)ds[ip[q][d]]));
-        m[q] = min(m[q], dn + 1);
+  const int span = EXT_XCD ? 8 * chunk : nvb;
+  for (int vx = (int)blockIdx.x; vx < span; vx += (int)gridDim.x) {
+    const int bx = EXT_XCD ? (vx % 8) * chunk + vx / 8 : vx;
+    Where w[NPT];
+  #pragma unroll
+    for (int q = 0; q < NPT; ++q) {
+      const int vb = bx * NPT + q;
+      if (vb < total) {
+        w[q] = locate_at<DIM>(insts, off, count, row, vb);
+      } else {
+        w[q].I = insts;
+        w[q].in = false;
+        w[q].id = 0;
+        w[q].i = w[q].j = w[q].k = 0;
       }
     }
-    act[q] = cone < 0 || m[q] <= cone;
-  }
-  uint8_t kb[NPT];
-  double vc[NPT], vm[NPT][DIM], vp[NPT][DIM], nd[NPT][DIM], sr[NPT], rr[NPT];
-#pragma unroll
-  for (int q = 0; q < NPT; ++q) {
-    if (!act[q]) continue;
-    const LsInst& I = *w[q].I;
-    gptr<const double> v = arr(I, v_arr);
-    kb[q] = glb((const uint8_t*)I.known)[w[q].id];
-    vc[q] = v[w[q].id];
-    for (int d = 0; d < DIM; ++d) {
-      vm[q][d] = v[im[q][d]];
-      vp[q][d] = v[ip[q][d]];
-      nd[q][d] = arr(I, A_NX + d)[w[q].id];
-    }
-    sr[q] = (src_arr >= 0) ? arr(I, src_arr)[w[q].id] : 0.0;
-    rr[q] = sign_rho ? glb((const double*)I.rho)[w[q].id] : 1.0;
-  }
-  double res[NPT];
-#pragma unroll
-  for (int q = 0; q < NPT; ++q) {
-    res[q] = 0.0;
-    if (!act[q]) continue;
-    const LsInst& I = *w[q].I;
-    const double sg = (rr[q] > 0.0) ? 1.0 : ((rr[q] < 0.0) ? -1.0 : 0.0);
-    double up = 0.0;
-    for (int d = 0; d < DIM; ++d) {
-      const double a = sg * nd[q][d];
-      up += fmax(a, 0.0) * (vc[q] - vm[q][d]) + fmin(a, 0.0) * (vp[q][d] - vc[q]);
-    }
-    up = up / I.h;
-    const double upd = vc[q] - (0.5 * I.h) * (up - sr[q]);
-    res[q] = ((kb[q] >> bit) & 1) ? vc[q] : upd;
-  }
-#pragma unroll
-  for (int q = 0; q < NPT; ++q) {
-    if (!w[q].in) continue;
-    const LsInst& I = *w[q].I;
-    if (act[q]) arr(I, out_arr)[w[q].id] = res[q];
-    if (dil) glb(I.dist)[w[q].id] = (uint8_t)min(m[q], 255);
-  }
-  if (do_max) {
-    // per tile (each tile belongs to one instance)
-    __shared__ double sm[256];
+    size_t im[NPT][DIM], ip[NPT][DIM];
+    int m[NPT];
+    bool act[NPT];
+  #pragma unroll
     for (int q = 0; q < NPT; ++q) {
-      if (bx * NPT + q >= total) break;   // uniform over the block
-      sm[threadIdx.x] = act[q] ? res[q] : 0.0;
-      __syncthreads();
-      for (int st = 128; st > 0; st >>= 1) {
-        if ((int)threadIdx.x < st) sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + st]);
+      act[q] = false;
+      m[q] = 0;
+      if (!w[q].in) continue;
+      const LsInst& I = *w[q].I;
+      for (int d = 0; d < DIM; ++d) {
+        im[q][d] = shifted(I, w[q], d, -1);
+        ip[q][d] = shifted(I, w[q], d, 1);
+      }
+      if (dil || cone >= 0) {
+        gptr<const uint8_t> ds = glb((const uint8_t*)I.dist);
+        m[q] = ds[w[q].id];
+        if (dil) {
+          int dn = 255;
+          for (int d = 0; d < DIM; ++d) dn = min(dn, min((int)ds[im[q][d]], (int)ds[ip[q][d]]));
+          m[q] = min(m[q], dn + 1);
+        }
+      }
+      act[q] = cone < 0 || m[q] <= cone;
+    }
+    uint8_t kb[NPT];
+    double vc[NPT], vm[NPT][DIM], vp[NPT][DIM], nd[NPT][DIM], sr[NPT], rr[NPT];
+  #pragma unroll
+    for (int q = 0; q < NPT; ++q) {
+      if (!act[q]) continue;
+      const LsInst& I = *w[q].I;
+      gptr<const double> v = arr(I, v_arr);
+      kb[q] = glb((const uint8_t*)I.known)[w[q].id];
+      vc[q] = v[w[q].id];
+      for (int d = 0; d < DIM; ++d) {
+        vm[q][d] = v[im[q][d]];
+        vp[q][d] = v[ip[q][d]];
+        nd[q][d] = arr(I, A_NX + d)[w[q].id];
+      }
+      sr[q] = (src_arr >= 0) ? arr(I, src_arr)[w[q].id] : 0.0;
+      rr[q] = sign_rho ? glb((const double*)I.rho)[w[q].id] : 1.0;
+    }
+    double res[NPT];
+  #pragma unroll
+    for (int q = 0; q < NPT; ++q) {
+      res[q] = 0.0;
+      if (!act[q]) continue;
+      const LsInst& I = *w[q].I;
+      const double sg = (rr[q] > 0.0) ? 1.0 : ((rr[q] < 0.0) ? -1.0 : 0.0);
+      double up = 0.0;
+      for (int d = 0; d < DIM; ++d) {
+        const double a = sg * nd[q][d];
+        up += fmax(a, 0.0) * (vc[q] - vm[q][d]) + fmin(a, 0.0) * (vp[q][d] - vc[q]);
+      }
+      up = up / I.h;
+      const double upd = vc[q] - (0.5 * I.h) * (up - sr[q]);
+      res[q] = ((kb[q] >> bit) & 1) ? vc[q] : upd;
+    }
+  #pragma unroll
+    for (int q = 0; q < NPT; ++q) {
+      if (!w[q].in) continue;
+      const LsInst& I = *w[q].I;
+      if (act[q]) arr(I, out_arr)[w[q].id] = res[q];
+      if (dil) glb(I.dist)[w[q].id] = (uint8_t)min(m[q], 255);
+    }
+    if (do_max) {
+      // per tile (each tile belongs to one instance)
+      __shared__ double sm[256];
+      for (int q = 0; q < NPT; ++q) {
+        if (bx * NPT + q >= total) break;   // uniform over the block
+        sm[threadIdx.x] = act[q] ? res[q] : 0.0;
+        __syncthreads();
+        for (int st = 128; st > 0; st >>= 1) {
+          if ((int)threadIdx.x < st) sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + st]);
+          __syncthreads();
+        }
+        // max of non-negative doubles: integer order equals value order
+        if (threadIdx.x == 0)
+          atomicMax((unsigned long long*)w[q].I->vmax, (unsigned long long)__double_as_longlong(sm[0]));
         __syncthreads();
       }
-      // max of non-negative doubles: integer order equals value order
-      if (threadIdx.x == 0)
-        atomicMax((unsigned long long*)w[q].I->vmax, (unsigned long long)__double_as_longlong(sm[0]));
-      __syncthreads();
     }
   }
 }
@@ -354,89 +370,92 @@ __global__ __launch_bounds__(256) void extend_group_kernel(const LsInst* __restr
   __shared__ uint8_t sfl[RN];   // bit 0: in the box, bit 1: known, bits 2-3: sign(rho) + 1
   __shared__ uint8_t sd[2][RN]; // dil: the distance to the computational points (dilated with the sweeps)
   __shared__ double sm[256];
-  const Where w = locate<2>(insts, off, count, row);
-  const LsInst& I = *w.I;
-  const int ox = w.i - (int)(threadIdx.x % X), oy = w.j - (int)(threadIdx.x / X);   // tile origin
-  gptr<const double> v = arr(I, v_arr);
-  gptr<const double> nxg = arr(I, A_NX);
-  gptr<const double> nyg = arr(I, A_NY);
-  gptr<const uint8_t> kn = glb((const uint8_t*)I.known);
-  gptr<const double> rho = glb((const double*)I.rho);
-  for (int r = threadIdx.x; r < RN; r += blockDim.x) {
-    const int gi = ox - K + r % RW, gj = oy - K + r / RW;
-    uint8_t f = 0;
-    double x = 0.0, a = 0.0, b = 0.0, sc = 0.0;
-    if (gi >= 0 && gi < I.nx && gj >= 0 && gj < I.ny) {
-      const size_t id = (size_t)gj * I.nx + gi;
-      x = v[id];
-      a = nxg[id];
-      b = nyg[id];
-      sc = (src_arr >= 0) ? arr(I, src_arr)[id] : 0.0;
-      f = 1 | ((((kn[id] >> bit) & 1) != 0) ? 2 : 0);
-      if (sign_rho) {
-        const double rr = rho[id];
-        f |= (uint8_t)(((rr > 0.0) ? 2 : ((rr < 0.0) ? 0 : 1)) << 2);
-      } else {
-        f |= (uint8_t)(2 << 2);
-      }
-    }
-    va[r] = x;
-    snx[r] = a;
-    sny[r] = b;
-    ssrc[r] = sc;
-    sfl[r] = f;
-    if (dil) sd[0][r] = (f & 1) ? glb((const uint8_t*)I.dist)[(size_t)gj * I.nx + gi] : (uint8_t)255;
-  }
-  __syncthreads();
-  const double dt = 0.5 * I.h;
-  double* cur = va;
-  double* nxt = vb;
-  for (int s = 0; s < nsweep; ++s) {
+  FOR_VBLOCKS(row) {
+    const Where w = locate_at<2>(insts, off, count, row, vb_);
+    const LsInst& I = *w.I;
+    const int ox = w.i - (int)(threadIdx.x % X), oy = w.j - (int)(threadIdx.x / X);   // tile origin
+    gptr<const double> v = arr(I, v_arr);
+    gptr<const double> nxg = arr(I, A_NX);
+    gptr<const double> nyg = arr(I, A_NY);
+    gptr<const uint8_t> kn = glb((const uint8_t*)I.known);
+    gptr<const double> rho = glb((const double*)I.rho);
     for (int r = threadIdx.x; r < RN; r += blockDim.x) {
-      const uint8_t f = sfl[r];
-      const double vc = cur[r];
-      double res = vc;
-      const int x = r % RW, y = r / RW;
-      const int gi = ox - K + x, gj = oy - K + y;
-      // neighbours, clamped at the box edge; outside the region: the node itself
-      // (such nodes are beyond the valid region of this sweep)
-      const int rxm = (gi == 0 || x == 0) ? r : r - 1;
-      const int rxp = (gi == I.nx - 1 || x == RW - 1) ? r : r + 1;
-      const int rym = (gj == 0 || y == 0) ? r : r - RW;
-      const int ryp = (gj == I.ny - 1 || y == RH - 1) ? r : r + RW;
-      if (dil) {
-        const uint8_t* dc = sd[s & 1];
-        int m = dc[r];
-        m = min(m, min(min((int)dc[rxm], (int)dc[rxp]), min((int)dc[rym], (int)dc[ryp])) + 1);
-        sd[(s + 1) & 1][r] = (uint8_t)min(m, 255);
+      const int gi = ox - K + r % RW, gj = oy - K + r / RW;
+      uint8_t f = 0;
+      double x = 0.0, a = 0.0, b = 0.0, sc = 0.0;
+      if (gi >= 0 && gi < I.nx && gj >= 0 && gj < I.ny) {
+        const size_t id = (size_t)gj * I.nx + gi;
+        x = v[id];
+        a = nxg[id];
+        b = nyg[id];
+        sc = (src_arr >= 0) ? arr(I, src_arr)[id] : 0.0;
+        f = 1 | ((((kn[id] >> bit) & 1) != 0) ? 2 : 0);
+        if (sign_rho) {
+          const double rr = rho[id];
+          f |= (uint8_t)(((rr > 0.0) ? 2 : ((rr < 0.0) ? 0 : 1)) << 2);
+        } else {
+          f |= (uint8_t)(2 << 2);
+        }
       }
-      if ((f & 1) && !(f & 2)) {
-        const double sg = (double)((f >> 2) & 3) - 1.0;
-        const double ax = sg * snx[r], ay = sg * sny[r];
-        double up = fmax(ax, 0.0) * (vc - cur[rxm]) + fmin(ax, 0.0) * (cur[rxp] - vc);
-        up += fmax(ay, 0.0) * (vc - cur[rym]) + fmin(ay, 0.0) * (cur[ryp] - vc);
-        up = up / I.h;
-        res = vc - dt * (up - ssrc[r]);
-      }
-      nxt[r] = res;
+      va[r] = x;
+      snx[r] = a;
+      sny[r] = b;
+      ssrc[r] = sc;
+      sfl[r] = f;
+      if (dil) sd[0][r] = (f & 1) ? glb((const uint8_t*)I.dist)[(size_t)gj * I.nx + gi] : (uint8_t)255;
     }
     __syncthreads();
-    double* t = cur; cur = nxt; nxt = t;
-  }
-  const int l = threadIdx.x;
-  const int rl = (l / X + K) * RW + (l % X + K);
-  const double res = cur[rl];
-  if (w.in) arr(I, out_arr)[w.id] = res;
-  if (w.in && dil) glb(I.dist)[w.id] = sd[nsweep & 1][rl];
-  if (do_max) {
-    sm[threadIdx.x] = w.in ? res : 0.0;
-    __syncthreads();
-    for (int st = 128; st > 0; st >>= 1) {
-      if ((int)threadIdx.x < st) sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + st]);
+    const double dt = 0.5 * I.h;
+    double* cur = va;
+    double* nxt = vb;
+    for (int s = 0; s < nsweep; ++s) {
+      for (int r = threadIdx.x; r < RN; r += blockDim.x) {
+        const uint8_t f = sfl[r];
+        const double vc = cur[r];
+        double res = vc;
+        const int x = r % RW, y = r / RW;
+        const int gi = ox - K + x, gj = oy - K + y;
+        // neighbours, clamped at the box edge; outside the region: the node itself
+        // (such nodes are beyond the valid region of this sweep)
+        const int rxm = (gi == 0 || x == 0) ? r : r - 1;
+        const int rxp = (gi == I.nx - 1 || x == RW - 1) ? r : r + 1;
+        const int rym = (gj == 0 || y == 0) ? r : r - RW;
+        const int ryp = (gj == I.ny - 1 || y == RH - 1) ? r : r + RW;
+        if (dil) {
+          const uint8_t* dc = sd[s & 1];
+          int m = dc[r];
+          m = min(m, min(min((int)dc[rxm], (int)dc[rxp]), min((int)dc[rym], (int)dc[ryp])) + 1);
+          sd[(s + 1) & 1][r] = (uint8_t)min(m, 255);
+        }
+        if ((f & 1) && !(f & 2)) {
+          const double sg = (double)((f >> 2) & 3) - 1.0;
+          const double ax = sg * snx[r], ay = sg * sny[r];
+          double up = fmax(ax, 0.0) * (vc - cur[rxm]) + fmin(ax, 0.0) * (cur[rxp] - vc);
+          up += fmax(ay, 0.0) * (vc - cur[rym]) + fmin(ay, 0.0) * (cur[ryp] - vc);
+          up = up / I.h;
+          res = vc - dt * (up - ssrc[r]);
+        }
+        nxt[r] = res;
+      }
       __syncthreads();
+      double* t = cur; cur = nxt; nxt = t;
     }
-    if (threadIdx.x == 0)
-      atomicMax((unsigned long long*)I.vmax, (unsigned long long)__double_as_longlong(sm[0]));
+    const int l = threadIdx.x;
+    const int rl = (l / X + K) * RW + (l % X + K);
+    const double res = cur[rl];
+    if (w.in) arr(I, out_arr)[w.id] = res;
+    if (w.in && dil) glb(I.dist)[w.id] = sd[nsweep & 1][rl];
+    if (do_max) {
+      sm[threadIdx.x] = w.in ? res : 0.0;
+      __syncthreads();
+      for (int st = 128; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + st]);
+        __syncthreads();
+      }
+      if (threadIdx.x == 0)
+        atomicMax((unsigned long long*)I.vmax, (unsigned long long)__double_as_longlong(sm[0]));
+    }
+    __syncthreads();   // LDS is restaged by the next virtual block
   }
 }
 
@@ -446,52 +465,56 @@ __global__ __launch_bounds__(256) void extend_group_kernel(const LsInst* __restr
 template <int DIM>
 __global__ __launch_bounds__(256) void reinit_check_kernel(const LsInst* __restrict__ insts,
                                                            const int* __restrict__ off, int count) {
-  const Where w = locate<DIM>(insts, off, count, LS_ROW_FULL);
-  if (!w.in) return;
-  const LsInst& I = *w.I;
-  if (!(fabs(glb((const double*)I.rho)[w.id]) < REINIT_BAND * I.h)) return;
-  constexpr int X = TileShape<DIM>::X, Y = TileShape<DIM>::Y, Z = TileShape<DIM>::Z;
-  const int ext[3] = {X, Y, Z};
-  const int n[3] = {I.nx, I.ny, I.nz};
-  bool ok = true;
-  for (int d = 0; d < DIM; ++d)
-    for (int s = -3; s <= 3; s += 6) {
-      int c[3] = {w.i, w.j, w.k};
-      c[d] = clampi(c[d] + s, n[d]);
-      const int t = ((c[2] / Z) * I.nty + c[1] / Y) * I.ntx + c[0] / X;
-      ok = ok && (I.tdist[t] >> 16) <= I.rr;
-      (void)ext;
-    }
-  if (!ok) atomicCAS(I.status, 0, ST_FRONT);
+  FOR_VBLOCKS(LS_ROW_FULL) {
+    const Where w = locate_at<DIM>(insts, off, count, LS_ROW_FULL, vb_);
+    if (!w.in) continue;
+    const LsInst& I = *w.I;
+    if (!(fabs(glb((const double*)I.rho)[w.id]) < REINIT_BAND * I.h)) continue;
+    constexpr int X = TileShape<DIM>::X, Y = TileShape<DIM>::Y, Z = TileShape<DIM>::Z;
+    const int ext[3] = {X, Y, Z};
+    const int n[3] = {I.nx, I.ny, I.nz};
+    bool ok = true;
+    for (int d = 0; d < DIM; ++d)
+      for (int s = -3; s <= 3; s += 6) {
+        int c[3] = {w.i, w.j, w.k};
+        c[d] = clampi(c[d] + s, n[d]);
+        const int t = ((c[2] / Z) * I.nty + c[1] / Y) * I.ntx + c[0] / X;
+        ok = ok && (I.tdist[t] >> 16) <= I.rr;
+        (void)ext;
+      }
+    if (!ok) atomicCAS(I.status, 0, ST_FRONT);
+  }
 }
 
 // list V: V = (|rho| < h) ? mu |central grad u_ext| : 0; speed band into bit 3
 template <int DIM>
 __global__ __launch_bounds__(256) void velocity_kernel(const LsInst* __restrict__ insts,
                                                        const int* __restrict__ off, int count, int uext_arr) {
-  const Where w = locate<DIM>(insts, off, count, LS_ROW_V + VEL_ITERS + 1);
-  if (!w.in) return;
-  const LsInst& I = *w.I;
-  gptr<const double> ue = arr(I, uext_arr);
-  gptr<uint8_t> kn = glb(I.known);
-  const bool band = fabs(glb((const double*)I.rho)[w.id]) < I.h;
-  double v = 0.0;
-  if (band) {
-    double s = 0.0;
-    bool reach = true;
-    for (int d = 0; d < DIM; ++d) {
-      const size_t ip = shifted(I, w, d, 1), im = shifted(I, w, d, -1);
-      reach = reach && in_reach(I, ip) && in_reach(I, im);
-      const double g = (ue[ip] - ue[im]) / (2.0 * I.h);
-      s += g * g;
+  FOR_VBLOCKS(LS_ROW_V + VEL_ITERS + 1) {
+    const Where w = locate_at<DIM>(insts, off, count, LS_ROW_V + VEL_ITERS + 1, vb_);
+    if (!w.in) continue;
+    const LsInst& I = *w.I;
+    gptr<const double> ue = arr(I, uext_arr);
+    gptr<uint8_t> kn = glb(I.known);
+    const bool band = fabs(glb((const double*)I.rho)[w.id]) < I.h;
+    double v = 0.0;
+    if (band) {
+      double s = 0.0;
+      bool reach = true;
+      for (int d = 0; d < DIM; ++d) {
+        const size_t ip = shifted(I, w, d, 1), im = shifted(I, w, d, -1);
+        reach = reach && in_reach(I, ip) && in_reach(I, im);
+        const double g = (ue[ip] - ue[im]) / (2.0 * I.h);
+        s += g * g;
+      }
+      if (!reach) atomicCAS(I.status, 0, ST_FRONT);
+      v = I.mu * sqrt(s);
+      kn[w.id] |= (uint8_t)8;
+    } else {
+      kn[w.id] &= (uint8_t)~8u;
     }
-    if (!reach) atomicCAS(I.status, 0, ST_FRONT);
-    v = I.mu * sqrt(s);
-    kn[w.id] |= (uint8_t)8;
-  } else {
-    kn[w.id] &= (uint8_t)~8u;
+    arr(I, A_V)[w.id] = v;
   }
-  arr(I, A_V)[w.id] = v;
 }
 
 // ------------------------------------------------------------ Step 2: WENO
@@ -556,83 +579,124 @@ __device__ __forceinline__ int substeps(const LsInst& I, double dt) {
 template <int DIM>
 __global__ __launch_bounds__(256) void rk_kernel(const LsInst* __restrict__ insts, const int* __restrict__ off,
                                                  int count, int reinit, int stage, int q, double dt, int first) {
-  const Where w = locate<DIM>(insts, off, count, LS_ROW_V + LS_V_MAX);
-  if (!w.in) return;
-  const LsInst& I = *w.I;
-  double step;
-  if (reinit) {
-    step = 0.5 * I.h;
-  } else {
-    const int ns = substeps(I, dt);
-    if (q >= ns) return;
-    step = dt / ns;
-  }
-  gptr<double> rho = glb(I.rho);
-  gptr<const double> in = (stage == 1) ? (gptr<const double>)rho : arr(I, stage == 2 ? A_R1 : A_R2);
-  double L = 0.0;
-  bool upd = true;
-  if (reinit) {
-    gptr<uint8_t> kn = glb(I.known);
-    if (first) {
-      const double r = rho[w.id];
-      arr(I, A_S)[w.id] = r / sqrt(r * r + I.h * I.h);
-      const bool inb = fabs(r) < REINIT_BAND * I.h;
-      kn[w.id] = inb ? (uint8_t)(kn[w.id] | 16) : (uint8_t)(kn[w.id] & ~16u);
-      upd = inb;
+  FOR_VBLOCKS(LS_ROW_V + LS_V_MAX) {
+    const Where w = locate_at<DIM>(insts, off, count, LS_ROW_V + LS_V_MAX, vb_);
+    if (!w.in) continue;
+    const LsInst& I = *w.I;
+    double step;
+    if (reinit) {
+      step = 0.5 * I.h;
     } else {
-      upd = (kn[w.id] >> 4) & 1;
+      const int ns = substeps(I, dt);
+      if (q >= ns) continue;
+      step = dt / ns;
     }
-    if (upd) {
-      const double s = arr(I, A_S)[w.id];
-      const double sg = (s > 0.0) ? 1.0 : ((s < 0.0) ? -1.0 : 0.0);
-      L = s * (godunov<DIM>(I, w, in, sg) - 1.0);
+    gptr<double> rho = glb(I.rho);
+    gptr<const double> in = (stage == 1) ? (gptr<const double>)rho : arr(I, stage == 2 ? A_R1 : A_R2);
+    double L = 0.0;
+    bool upd = true;
+    if (reinit) {
+      gptr<uint8_t> kn = glb(I.known);
+      if (first) {
+        const double r = rho[w.id];
+        arr(I, A_S)[w.id] = r / sqrt(r * r + I.h * I.h);
+        const bool inb = fabs(r) < REINIT_BAND * I.h;
+        kn[w.id] = inb ? (uint8_t)(kn[w.id] | 16) : (uint8_t)(kn[w.id] & ~16u);
+        upd = inb;
+      } else {
+        upd = (kn[w.id] >> 4) & 1;
+      }
+      if (upd) {
+        const double s = arr(I, A_S)[w.id];
+        const double sg = (s > 0.0) ? 1.0 : ((s < 0.0) ? -1.0 : 0.0);
+        L = s * (godunov<DIM>(I, w, in, sg) - 1.0);
+      }
+    } else {
+      const double V = arr(I, A_V)[w.id];
+      L = (V != 0.0) ? V * godunov<DIM>(I, w, in, 1.0) : 0.0;
     }
-  } else {
-    const double V = arr(I, A_V)[w.id];
-    L = (V != 0.0) ? V * godunov<DIM>(I, w, in, 1.0) : 0.0;
-  }
-  const double cur = in[w.id];
-  const double st = cur - step * L;
-  if (stage == 1) {
-    arr(I, A_R0)[w.id] = cur;
-    arr(I, A_R1)[w.id] = upd ? st : cur;
-  } else if (stage == 2) {
-    arr(I, A_R2)[w.id] = upd ? 0.75 * arr(I, A_R0)[w.id] + 0.25 * st : cur;
-  } else if (upd) {
-    rho[w.id] = (1.0 / 3.0) * arr(I, A_R0)[w.id] + (2.0 / 3.0) * st;
+    const double cur = in[w.id];
+    const double st = cur - step * L;
+    if (stage == 1) {
+      arr(I, A_R0)[w.id] = cur;
+      arr(I, A_R1)[w.id] = upd ? st : cur;
+    } else if (stage == 2) {
+      arr(I, A_R2)[w.id] = upd ? 0.75 * arr(I, A_R0)[w.id] + 0.25 * st : cur;
+    } else if (upd) {
+      rho[w.id] = (1.0 / 3.0) * arr(I, A_R0)[w.id] + (2.0 / 3.0) * st;
+    }
   }
 }
 
 // whole box: u = comp(rho_new) ? u_ext : 0 (a computational point beyond
 // the reach of the extension: ST_FRONT), or (all) u = u_ext within the reach
-// of the extension and 0 beyond (what the step reads of it).  Then the
-// pass's own writes are cleared: on the tiles of list U (Dc <= LS_C_MAX or
-// Dv <= LS_V_MAX) the extension arrays, the speed and its partner go to 0
-// and the distance to 255 (each thread reads and clears its own node only),
-// and the maximum speed to 0.
+// of the extension and 0 beyond (what the step reads of it).  Outside list U
+// (Dc > LS_C_MAX and Dv > LS_V_MAX) both are 0 without a read: rho changes
+// only on list R, inside U, so a tile outside U holds no computational point
+// of the new rho, and no node within the reach.  Then the pass's own writes
+// are cleared: on the tiles of U the extension arrays, the speed and its
+// partner go to 0 and the distance to 255 (each thread reads and clears its
+// own node only), and the maximum speed to 0.
 template <int DIM>
 __global__ __launch_bounds__(256) void restrict_kernel(const LsInst* __restrict__ insts,
                                                        const int* __restrict__ off, int count, int uext_arr,
                                                        int all) {
-  const Where w = locate<DIM>(insts, off, count, LS_ROW_FULL);
-  const LsInst& I = *w.I;
-  if (w.local == 0 && threadIdx.x == 0) *glb(I.vmax) = 0.0;
-  if (!w.in) return;
-  const bool reach = in_reach(I, w.id);
-  bool c;
-  if (all) {
-    c = reach;
-  } else {
-    c = comp_point<DIM>(I, w, glb((const double*)I.rho));
-    if (c && !reach) atomicCAS(I.status, 0, ST_FRONT);
-  }
-  glb(I.u)[w.id] = c ? arr(I, uext_arr)[w.id] : 0.0;
-  const int td = I.tdist[w.local];
-  if ((td & 0xFFFF) <= LS_C_MAX || (td >> 16) <= LS_V_MAX) {
+  FOR_VBLOCKS(LS_ROW_FULL) {
+    const Where w = locate_at<DIM>(insts, off, count, LS_ROW_FULL, vb_);
+    const LsInst& I = *w.I;
+    if (w.local == 0 && threadIdx.x == 0) *glb(I.vmax) = 0.0;
+    if (!w.in) continue;
+    const int td = I.tdist[w.local];
+    if ((td & 0xFFFF) > LS_C_MAX && (td >> 16) > LS_V_MAX) {
+      glb(I.u)[w.id] = 0.0;
+      continue;
+    }
+    const bool reach = in_reach(I, w.id);
+    bool c;
+    if (all) {
+      c = reach;
+    } else {
+      c = comp_point<DIM>(I, w, glb((const double*)I.rho));
+      if (c && !reach) atomicCAS(I.status, 0, ST_FRONT);
+    }
+    glb(I.u)[w.id] = c ? arr(I, uext_arr)[w.id] : 0.0;
     for (int a = A_E0; a <= A_V; ++a) arr(I, a)[w.id] = 0.0;
     arr(I, A_S)[w.id] = 0.0;
     glb(I.dist)[w.id] = 255;
   }
+}
+
+// Device-sized mode: the launch rows' offsets from the geometry counters of
+// every instance (thread q: row q).
+__global__ void ls_rows_kernel(const LsInst* __restrict__ insts, int* __restrict__ off, int count) {
+  const int q = (int)threadIdx.x;
+  if (q >= LS_NROWS) return;
+  int acc = 0;
+  for (int i = 0; i < count; ++i) {
+    const LsInst& I = insts[i];
+    off[(size_t)q * (count + 1) + i] = acc;
+    if (q == LS_ROW_FULL) acc += I.ntx * I.nty * I.ntz;
+    else if (q == LS_ROW_U) acc += I.cnt[LS_CNT_U];
+    else if (q >= LS_ROW_V) acc += I.cnt[LS_CNT_V + q - LS_ROW_V];
+    else acc += I.cnt[LS_CNT_C + q - LS_ROW_C];
+  }
+  off[(size_t)q * (count + 1) + count] = acc;
+}
+
+// Device-sized mode: the front guard (max V dt <= LS_MAX_FRONT_NODES h, the
+// host's test) per instance; a violation latches ST_FRONT.
+__global__ void front_check_kernel(const LsInst* __restrict__ insts, int count, double dt) {
+  const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (i >= count) return;
+  const LsInst& I = insts[i];
+  if (!(*glb((const double*)I.vmax) * dt <= LS_MAX_FRONT_NODES * I.h)) atomicCAS(I.status, 0, ST_FRONT);
+}
+
+// Fixed grid of a device-sized launch (a multiple of 8, see extend_kernel).
+constexpr int LS_DEVICE_GRID = 2048;
+int device_grid(const LevelsetBatch& b) {
+  const int g = 8 * ((b.max_tiles + 7) / 8);
+  return g < LS_DEVICE_GRID ? (g > 0 ? g : 8) : LS_DEVICE_GRID;
 }
 
 // The restriction that clears every instance's list U is enqueued.
@@ -647,10 +711,14 @@ hipError_t begin_dim(LevelsetBatch& b, hipStream_t st, bool speed) {
   const LsInst* I = b.d_inst;
   const int* off = b.d_off;
   const dim3 B(256);
+  // grid of a launch on `row`: its size (host counts), or the fixed grid
+  const bool dev = b.device_sized;
+  const int dgrid = dev ? device_grid(b) : 0;
+  auto grid = [&](int row) { return dev ? dgrid : b.total[row]; };
 #define LL(row, kernel, ...)                                                                 \
   do {                                                                                       \
-    if (b.total[row] > 0) {                                                                  \
-      hipLaunchKernelGGL(kernel<DIM>, dim3(b.total[row]), B, 0, st, I, off, n, ##__VA_ARGS__); \
+    if (grid(row) > 0) {                                                                     \
+      hipLaunchKernelGGL(kernel<DIM>, dim3(grid(row)), B, 0, st, I, off, n, ##__VA_ARGS__);  \
       hipError_t _e = hipGetLastError();                                                     \
       if (_e != hipSuccess) return _e;                                                       \
     }                                                                                        \
@@ -677,13 +745,13 @@ hipError_t begin_dim(LevelsetBatch& b, hipStream_t st, bool speed) {
       const int ns = (sweeps - done < group) ? sweeps - done : group;
       const int mx = (do_max && done + ns == sweeps) ? 1 : 0;
       const int r = row(done + 1, done + ns);
-      if (b.total[r] > 0) {
+      if (grid(r) > 0) {
         if (DIM == 2)
-          hipLaunchKernelGGL(extend_group_kernel, dim3(b.total[r]), B, 0, st, I, off, n, r, v, t, src, bit, sign_rho,
-                             mx, ns, dil);
+          hipLaunchKernelGGL(extend_group_kernel, dim3(grid(r)), B, 0, st, I, off, n, r, v, t, src, bit, sign_rho, mx,
+                             ns, dil);
         else
-          hipLaunchKernelGGL((extend_kernel<DIM, EXT_NPT>), dim3(ext_grid(b.total[r])), B, 0, st, I, off, n, r, v, t,
-                             src, bit, sign_rho, mx, dil, cone(done + 1));
+          hipLaunchKernelGGL((extend_kernel<DIM, EXT_NPT>), dim3(dev ? dgrid : ext_grid(b.total[r])), B, 0, st, I, off,
+                             n, r, v, t, src, bit, sign_rho, mx, dil, cone(done + 1));
         if (hipGetLastError() != hipSuccess) return -1;
       }
       done += ns;
@@ -732,37 +800,54 @@ hipError_t end_dim(LevelsetBatch& b, hipStream_t st) {
   const LsInst* I = b.d_inst;
   const int* off = b.d_off;
   const dim3 B(256);
+  const bool dev = b.device_sized;
+  const int dgrid = dev ? device_grid(b) : 0;
+  auto grid = [&](int row) { return dev ? dgrid : b.total[row]; };
+  // advection substeps: from the maximum speeds on the host, or the most
+  // the front guard allows (each instance skips those beyond its own count)
   int nsub = 1;
-  for (int i = 0; i < n; ++i) {
-    int ns = (int)ceil(b.h_vmax[i] * b.dt / (0.5 * b.h_inst[i].h));
-    if (ns < 1) ns = 1;
-    if (ns > nsub) nsub = ns;
+  if (dev) {
+    nsub = LS_MAX_SUBSTEPS;
+  } else {
+    for (int i = 0; i < n; ++i) {
+      int ns = (int)ceil(b.h_vmax[i] * b.dt / (0.5 * b.h_inst[i].h));
+      if (ns < 1) ns = 1;
+      if (ns > nsub) nsub = ns;
+    }
   }
   hipError_t e;
   const int rrow = LS_ROW_V + LS_V_MAX;
-  if (b.total[rrow] > 0) {
+  if (grid(rrow) > 0) {
     for (int q = 0; q < nsub; ++q)
       for (int s = 1; s <= 3; ++s) {
-        hipLaunchKernelGGL(rk_kernel<DIM>, dim3(b.total[rrow]), B, 0, st, I, off, n, 0, s, q, b.dt, 0);
+        hipLaunchKernelGGL(rk_kernel<DIM>, dim3(grid(rrow)), B, 0, st, I, off, n, 0, s, q, b.dt, 0);
         if ((e = hipGetLastError()) != hipSuccess) return e;
       }
   }
   if (b.reinit) {
-    hipLaunchKernelGGL(reinit_check_kernel<DIM>, dim3(b.total[LS_ROW_FULL]), B, 0, st, I, off, n);
+    hipLaunchKernelGGL(reinit_check_kernel<DIM>, dim3(grid(LS_ROW_FULL)), B, 0, st, I, off, n);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    if (b.total[rrow] > 0) {
+    if (grid(rrow) > 0) {
       for (int it = 0; it < REINIT_ITERS; ++it)
         for (int s = 1; s <= 3; ++s) {
-          hipLaunchKernelGGL(rk_kernel<DIM>, dim3(b.total[rrow]), B, 0, st, I, off, n, 1, s, 0, 0.0,
+          hipLaunchKernelGGL(rk_kernel<DIM>, dim3(grid(rrow)), B, 0, st, I, off, n, 1, s, 0, 0.0,
                              (it == 0 && s == 1) ? 1 : 0);
           if ((e = hipGetLastError()) != hipSuccess) return e;
         }
     }
   }
-  hipLaunchKernelGGL(restrict_kernel<DIM>, dim3(b.total[LS_ROW_FULL]), B, 0, st, I, off, n, b.uext, 0);
+  hipLaunchKernelGGL(restrict_kernel<DIM>, dim3(grid(LS_ROW_FULL)), B, 0, st, I, off, n, b.uext, 0);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   mark_clean(b);
   return hipSuccess;
+}
+
+// The whole-box clear of the dirty instances alone (exact grid).
+template <int DIM>
+hipError_t zero_only(LevelsetBatch& b, hipStream_t st) {
+  if (b.total[LS_ROW_FULL] > 0)
+    hipLaunchKernelGGL(zero_kernel<DIM>, dim3(b.total[LS_ROW_FULL]), dim3(256), 0, st, b.d_inst, b.d_off, b.count);
+  return hipGetLastError();
 }
 
 template <int DIM>
@@ -866,11 +951,46 @@ hipError_t upload(LevelsetBatch& b, hipStream_t st) {
 hipError_t levelset_begin(LevelsetBatch& b, double dt, int reinit, hipStream_t st) {
   b.dt = dt;
   b.reinit = reinit;
-  hipError_t e = upload(b, st);
-  if (e != hipSuccess) return e;
+  hipError_t e;
+  if (b.device_sized) {
+    // the table is on the device (levelset_upload); the rows from the
+    // geometry counters
+    hipLaunchKernelGGL(ls_rows_kernel, dim3(1), dim3(128), 0, st, b.d_inst, b.d_off, b.count);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  } else if ((e = upload(b, st)) != hipSuccess) {
+    return e;
+  }
   e = (b.dim == 2) ? begin_dim<2>(b, st, true) : begin_dim<3>(b, st, true);
   if (e != hipSuccess) return e;
+  if (b.device_sized) {
+    hipLaunchKernelGGL(front_check_kernel, dim3((b.count + 63) / 64), dim3(64), 0, st, b.d_inst, b.count, dt);
+    return hipGetLastError();
+  }
   return hipMemcpyAsync(b.h_vmax, b.d_vmax, sizeof(double) * b.count, hipMemcpyDeviceToHost, st);
+}
+
+hipError_t levelset_upload(LevelsetBatch& b, hipStream_t st) {
+  const int n = b.count;
+  b.max_tiles = 0;
+  for (int i = 0; i < n; ++i) b.max_tiles += b.h_inst[i].ntx * b.h_inst[i].nty * b.h_inst[i].ntz;
+  hipError_t e = upload(b, st);   // table, dirty flags, offsets of the current lists
+  if (e != hipSuccess) return e;
+  if (b.any_dirty) {
+    // clear the dirty scratch now, with exact grids: the captured passes
+    // then start from clean arrays, and their restrictions keep them so
+    const bool dev = b.device_sized;
+    b.device_sized = false;
+    e = (b.dim == 2) ? zero_only<2>(b, st) : zero_only<3>(b, st);
+    b.device_sized = dev;
+    if (e != hipSuccess) return e;
+    for (int i = 0; i < n; ++i) {
+      b.h_inst[i].dirty = 0;
+      if (b.h_inst[i].host_dirty) *b.h_inst[i].host_dirty = false;
+    }
+    b.any_dirty = false;
+    e = hipMemcpyAsync(b.d_inst, b.h_inst, sizeof(LsInst) * n, hipMemcpyHostToDevice, st);
+  }
+  return e;
 }
 
 hipError_t levelset_extend(LevelsetBatch& b, hipStream_t st) {

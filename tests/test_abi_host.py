@@ -98,4 +98,6 @@ def test_batch_host_argument_checks(lib):
     assert lib.etd_batch_geometry_build(None, None) == L.ETD_ERR_INVALID
     assert lib.etd_batch_set_group_limit(None, 1) == L.ETD_ERR_INVALID
     assert lib.etd_batch_graph_steps(None, 2, 0.1, None, 1) == L.ETD_ERR_INVALID
-    assert lib.etd_batch_autotune(None, 2, 0.1, None, 1, None, None) == L.ETD_ERR_INVALID
+    assert lib.etd_batch_autotune(None, 2, 0.1, None, 1, None, None, None) == L.ETD_ERR_INVALID
+    assert lib.etd_batch_set_stage_min(None, 0) == L.ETD_ERR_INVALID
+    assert lib.etd_batch_graph_free_steps(None, 2, 0.1, None, None, 5, 0, 1) == L.ETD_ERR_INVALID

@@ -6,7 +6,9 @@ ETD2RK h = 0.005, mu = 1) is advanced on the GPU for two free-boundary steps;
 every instance is compared with the oracle run instance by instance (1e-9
 relative L2 over computational points, level set to 1e-10, masks equal).  The one-block-per-instance launch (group limit 1)
 must agree with the grouped launch to rounding, and a batch of one with
-etd_step.
+etd_step.  Free-boundary steps replayed from recorded graphs (launch sizes
+found on the device) must match eager steps, and a front beyond the guard
+must latch its error for its instance only.
 """
 import sys
 
@@ -115,11 +117,13 @@ def test_batch_of_one_matches_etd_step():
     assert rel_l2(out[0][1], u.cpu().numpy()) <= 1e-10
 
 
-def _frozen_batch(ws, limit=None):
+def _frozen_batch(ws, limit=None, stage_min=None):
     from paper_2209_15095_amd.api import Batch
     b = Batch([w.grid for w in ws], [dict(beta=w.beta, mu=0.0) for w in ws])
     if limit is not None:
         b.set_group_limit(limit)
+    if stage_min is not None:
+        b.set_stage_min(stage_min)
     b.geometry_build([dev(w.rho0) for w in ws])
     return b, [dev(w.u0) for w in ws]
 
@@ -159,12 +163,12 @@ def test_autotune_leaves_state_and_chooses_a_limit():
     before = [u.cpu().numpy() for u in uc]
     res = c.autotune("etd2rk", h, uc, trials=2)
     say(f"autotune: {res}")
-    assert res["limit"] in c.AUTOTUNE_LIMITS
-    assert all(ms > 0.0 for ms in res["ms"].values())
-    assert res["ms"][res["limit"]] == min(res["ms"].values())
+    assert res["limit"] in c.AUTOTUNE_LIMITS and res["stage_min"] in c.AUTOTUNE_STAGES
+    assert len(res["ms"]) == 18 and all(ms > 0.0 for ms in res["ms"].values())
+    assert res["ms"][(res["limit"], res["stage_min"])] == min(res["ms"].values())
     assert all(np.array_equal(u.cpu().numpy(), v) for u, v in zip(uc, before))
-    # the tuned batch steps exactly as a fresh batch with that limit
-    d, ud = _frozen_batch(ws, limit=res["limit"])
+    # the tuned batch steps exactly as a fresh batch with that schedule
+    d, ud = _frozen_batch(ws, limit=res["limit"], stage_min=res["stage_min"])
     for _ in range(2):
         c.step("etd2rk", h, uc)
         d.step("etd2rk", h, ud)
@@ -249,3 +253,84 @@ def test_batch_higher_order_frozen_match_oracle(scheme):
         assert np.array_equal(x.cpu().numpy(), y.cpu().numpy())
     b.close()
     g.close()
+
+
+def _free_batch(ws, limit=0, mu=None):
+    from paper_2209_15095_amd.api import Batch
+    b = Batch([w.grid for w in ws], [dict(beta=w.beta, mu=(w.mu if mu is None else mu[i]))
+                                     for i, w in enumerate(ws)])
+    b.set_group_limit(limit)
+    rhos = [dev(w.rho0) for w in ws]
+    us = [dev(w.u0) for w in ws]
+    b.geometry_build(rhos)
+    return b, rhos, us
+
+
+def test_graph_free_steps_match_eager_steps():
+    """etd_batch_graph_free_steps (level set, geometry and ETD2RK step
+    recorded as graphs whose launch sizes are found on the device) against
+    eager etd_batch_step on 8 batch64 instances: 10 free-boundary steps with
+    reinitialisation every 5 (both recordings replayed), in two calls
+    (steps 0-5, then 6-9) with an eager step on another batch and a
+    synchronisation in between.  rho to 1e-12, u to 1e-10 relative L2 (the
+    graph keeps the block schedule of the recording, so its reductions may
+    be ordered differently), masks equal; nothing latched."""
+    ws = inputs.batch64()[:8]
+    h = ws[0].h
+    steps = 10
+    say(f"graph free steps: {len(ws)} instances, {steps} steps, reinit every 5")
+    a, ra, ua = _free_batch(ws, limit=2)
+    for m in range(steps):
+        a.step("etd2rk", h, ua, ra, reinit=(m + 1) % 5 == 0)
+    torch.cuda.synchronize()
+    b, rb, ub = _free_batch(ws, limit=2)
+    b.graph_free_steps("etd2rk", h, ub, rb, reinit_every=5, step0=0, nsteps=6)
+    torch.cuda.synchronize()
+    c, rc, uc = _free_batch(ws[:2])
+    c.step("etd2rk", h, uc, rc)   # eager work of another batch between the replays
+    torch.cuda.synchronize()
+    b.graph_free_steps("etd2rk", h, ub, rb, reinit_every=5, step0=6, nsteps=4)
+    b.sync()
+    a.sync()
+    for i, w in enumerate(ws):
+        og = ogrid(w.grid)
+        rg, ug = rb[i].cpu().numpy(), ub[i].cpu().numpy()
+        re, ue = ra[i].cpu().numpy(), ua[i].cpu().numpy()
+        _, cg, _ = classify(og, rg)
+        _, ce, _ = classify(og, re)
+        assert np.array_equal(cg, ce), i
+        assert np.abs(rg - re).max() <= 1e-12, (i, np.abs(rg - re).max())
+        err = rel_l2(ug[ce], ue[ce])
+        assert err <= 1e-10, (i, err)
+        assert np.all(ug[~cg] == 0.0)
+    say("  graph steps equal the eager steps")
+    # an eager step after the replays (the host re-reads the moved lists)
+    b.step("etd2rk", h, ub, rb, reinit=False)
+    a.step("etd2rk", h, ua, ra, reinit=False)
+    torch.cuda.synchronize()
+    for i in range(len(ws)):
+        assert rel_l2(ub[i].cpu().numpy(), ua[i].cpu().numpy()) <= 1e-10
+    for x in (a, b, c):
+        x.close()
+
+
+def test_graph_free_steps_front_error_latched():
+    """A replayed free-boundary step whose front would move farther than the
+    guard allows latches ETD_ERR_FRONT for its instance (reported by
+    etd_batch_sync); the other instance of the batch matches eager steps."""
+    from paper_2209_15095_amd._lib import ETD_ERR_FRONT, EtdError
+    ws = inputs.batch64()[:2]
+    h = ws[0].h
+    b, rb, ub = _free_batch(ws, mu=[ws[0].mu, 500.0])
+    b.graph_free_steps("etd2rk", h, ub, rb, reinit_every=5, step0=0, nsteps=2)
+    with pytest.raises(EtdError) as ei:
+        b.sync()
+    assert ei.value.code == ETD_ERR_FRONT
+    a, ra, ua = _free_batch(ws[:1])
+    for m in range(2):
+        a.step("etd2rk", h, ua, ra, reinit=False)
+    torch.cuda.synchronize()
+    assert np.abs(rb[0].cpu().numpy() - ra[0].cpu().numpy()).max() <= 1e-12
+    assert rel_l2(ub[0].cpu().numpy(), ua[0].cpu().numpy()) <= 1e-10
+    a.close()
+    b.close()
