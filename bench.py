@@ -147,6 +147,11 @@ def cpu_baseline_batch(ws, steps: int, count: int):
 
 
 def bench_batch(args):
+    """The 64 free-boundary instances of batch64: the block and tile schedule
+    chosen by the autotuner, then ETD2RK free-boundary steps (reinitialising
+    every 5) replayed from recorded HIP graphs whose launch sizes are found
+    on the device (the value), with the same steps taken eagerly (one host
+    synchronisation per level set and per geometry build) timed beside it."""
     import numpy as np
     import torch
 
@@ -154,6 +159,8 @@ def bench_batch(args):
     from paper_2209_15095_amd.api import Batch
 
     ws = inputs.batch64()
+    h = ws[0].h
+    every = ws[0].reinit_every
     pts = sum(int(np.prod(w.grid.n[:2])) for w in ws)
     log(f"[bench] batch64: {len(ws)} instances, {pts} grid points, steps {args.steps}")
     b = Batch([w.grid for w in ws], [dict(beta=w.beta, a=w.a, b=w.b, mu=w.mu) for w in ws])
@@ -162,27 +169,44 @@ def bench_batch(args):
     rhos = [r.clone() for r in rho0]
     us = [u.clone() for u in u0]
 
+    def reset():
+        for r, r0 in zip(rhos, rho0):
+            r.copy_(r0)
+        for u, v0 in zip(us, u0):
+            u.copy_(v0)
+        b.geometry_build(rhos)
+
     def run(n):
         for m in range(n):
-            b.step("etd2rk", ws[0].h, us, rhos, reinit=(m + 1) % ws[0].reinit_every == 0)
+            b.step("etd2rk", h, us, rhos, reinit=(m + 1) % every == 0)
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
 
     b.geometry_build(rhos)
+    tune = b.autotune("etd2rk", h, us, trials=3)
+    log(f"[bench] autotune: limit {tune['limit']}, stage_min {tune['stage_min']}")
     run(args.warmup)
     b.sync()
-    for r, r0 in zip(rhos, rho0):
-        r.copy_(r0)
-    for u, v0 in zip(us, u0):
-        u.copy_(v0)
-    b.geometry_build(rhos)
+    reset()
     b.profile_enable(True)
     b.profile_read(reset=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    run(args.steps)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
+    t_eager = timed(lambda: run(args.steps))
     b.sync()
-    prof = b.profile_read()
+    prof = b.profile_read(reset=True)
+    # graph replays: recorded on the first call (warm-up), then timed from
+    # the initial state
+    reset()
+    b.graph_free_steps("etd2rk", h, us, rhos, reinit_every=every, step0=0, nsteps=max(args.warmup, 1))
+    b.sync()
+    reset()
+    wall = timed(lambda: b.graph_free_steps("etd2rk", h, us, rhos, reinit_every=every, step0=0,
+                                            nsteps=args.steps))
+    b.sync()
     b.close()
     out = {
         "metric": "grid-point ETD steps/s at Krylov tol 1e-10",
@@ -193,12 +217,15 @@ def bench_batch(args):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64", "data": "synthetic",
         "config": {"workload": "batch64", "instances": len(ws), "grid_points": pts,
-                   "scheme": "etd2rk", "h": ws[0].h, "mu": ws[0].mu, "free_boundary": True,
-                   "reinit_every": ws[0].reinit_every, "krylov_tol": 1e-10},
+                   "scheme": "etd2rk", "h": h, "mu": ws[0].mu, "free_boundary": True,
+                   "reinit_every": every, "krylov_tol": 1e-10, "graph_replay": True},
+        "eager_ms_per_step": 1e3 * t_eager / max(args.steps, 1),
+        "autotune": {"group_limit": tune["limit"], "stage_min": tune["stage_min"],
+                     "ms_per_launch": {f"{k[0]}/{k[1]}": v for k, v in tune["ms"].items()}},
         "unknown_steps_per_s": prof["n_unknowns"] * args.steps / wall,
-        "breakdown_ms_per_step": {k: prof[k + "_ms"] / max(args.steps, 1)
-                                  for k in ("krylov", "levelset", "geometry")},
-        "roofline": roofline_obj(prof, "krylov_group_kernel<2> (batched persistent ETD2RK step)"),
+        "eager_breakdown_ms_per_step": {k: prof[k + "_ms"] / max(args.steps, 1)
+                                        for k in ("krylov", "levelset", "geometry")},
+        "roofline": roofline_obj(prof, "krylov_group_kernel<2> (batched persistent ETD2RK step, eager steps)"),
     }
     out["roofline"]["traffic"] = None
     if not args.no_cpu_baseline:

@@ -142,9 +142,8 @@ struct LevelsetBatch {
   // front guard is checked on the device (ST_FRONT latched, the step goes
   // on), LS_MAX_SUBSTEPS advection substeps are launched, and nothing is
   // copied to or from the host.  The instance table must be on the device
-  // (levelset_upload) before.
+  // (levelset_upload) before; the grids are sized from the lists then.
   bool device_sized = false;
-  int max_tiles = 0;          // sum of the instances' box tiles (device-sized grids)
 };
 
 hipError_t levelset_alloc(LevelsetScratch& s, size_t nodes);

@@ -74,6 +74,19 @@ __device__ __forceinline__ Where locate_at(const LsInst* __restrict__ insts, con
   return w;
 }
 
+// Instance of virtual block b of a launch row (largest i with off[i] <= b).
+__device__ __forceinline__ const LsInst& inst_at(const LsInst* __restrict__ insts, const int* __restrict__ off,
+                                                 int count, int row, int b) {
+  const int* o = off + (size_t)row * (count + 1);
+  int lo = 0, hi = count - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (o[mid] <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  return insts[lo];
+}
+
 // Virtual blocks of a launch row (the row's total, read on the device); a
 // launch's blocks loop over them, so any grid serves any list size.
 __device__ __forceinline__ int row_total(const int* __restrict__ off, int count, int row) {
@@ -580,17 +593,20 @@ template <int DIM>
 __global__ __launch_bounds__(256) void rk_kernel(const LsInst* __restrict__ insts, const int* __restrict__ off,
                                                  int count, int reinit, int stage, int q, double dt, int first) {
   FOR_VBLOCKS(LS_ROW_V + LS_V_MAX) {
-    const Where w = locate_at<DIM>(insts, off, count, LS_ROW_V + LS_V_MAX, vb_);
-    if (!w.in) continue;
-    const LsInst& I = *w.I;
     double step;
     if (reinit) {
-      step = 0.5 * I.h;
+      step = 0.5 * inst_at(insts, off, count, LS_ROW_V + LS_V_MAX, vb_).h;
     } else {
-      const int ns = substeps(I, dt);
+      // substeps beyond the instance's count: nothing to do (checked before
+      // the tile lookup)
+      const LsInst& J = inst_at(insts, off, count, LS_ROW_V + LS_V_MAX, vb_);
+      const int ns = substeps(J, dt);
       if (q >= ns) continue;
       step = dt / ns;
     }
+    const Where w = locate_at<DIM>(insts, off, count, LS_ROW_V + LS_V_MAX, vb_);
+    if (!w.in) continue;
+    const LsInst& I = *w.I;
     gptr<double> rho = glb(I.rho);
     gptr<const double> in = (stage == 1) ? (gptr<const double>)rho : arr(I, stage == 2 ? A_R1 : A_R2);
     double L = 0.0;
@@ -692,11 +708,15 @@ __global__ void front_check_kernel(const LsInst* __restrict__ insts, int count, 
   if (!(*glb((const double*)I.vmax) * dt <= LS_MAX_FRONT_NODES * I.h)) atomicCAS(I.status, 0, ST_FRONT);
 }
 
-// Fixed grid of a device-sized launch (a multiple of 8, see extend_kernel).
+// Fixed grid of a device-sized launch on `row` (a multiple of 8, see
+// extend_kernel): the row's size when recorded (b.total, from the host
+// counts of levelset_upload) with half again as headroom for a growing
+// domain, at most LS_DEVICE_GRID (the blocks loop over any larger list).
 constexpr int LS_DEVICE_GRID = 2048;
-int device_grid(const LevelsetBatch& b) {
-  const int g = 8 * ((b.max_tiles + 7) / 8);
-  return g < LS_DEVICE_GRID ? (g > 0 ? g : 8) : LS_DEVICE_GRID;
+int device_grid(const LevelsetBatch& b, int row) {
+  const int want = b.total[row] + b.total[row] / 2 + 8;
+  const int g = 8 * ((want + 7) / 8);
+  return g < LS_DEVICE_GRID ? g : LS_DEVICE_GRID;
 }
 
 // The restriction that clears every instance's list U is enqueued.
@@ -713,8 +733,7 @@ hipError_t begin_dim(LevelsetBatch& b, hipStream_t st, bool speed) {
   const dim3 B(256);
   // grid of a launch on `row`: its size (host counts), or the fixed grid
   const bool dev = b.device_sized;
-  const int dgrid = dev ? device_grid(b) : 0;
-  auto grid = [&](int row) { return dev ? dgrid : b.total[row]; };
+  auto grid = [&](int row) { return dev ? device_grid(b, row) : b.total[row]; };
 #define LL(row, kernel, ...)                                                                 \
   do {                                                                                       \
     if (grid(row) > 0) {                                                                     \
@@ -750,8 +769,8 @@ hipError_t begin_dim(LevelsetBatch& b, hipStream_t st, bool speed) {
           hipLaunchKernelGGL(extend_group_kernel, dim3(grid(r)), B, 0, st, I, off, n, r, v, t, src, bit, sign_rho, mx,
                              ns, dil);
         else
-          hipLaunchKernelGGL((extend_kernel<DIM, EXT_NPT>), dim3(dev ? dgrid : ext_grid(b.total[r])), B, 0, st, I, off,
-                             n, r, v, t, src, bit, sign_rho, mx, dil, cone(done + 1));
+          hipLaunchKernelGGL((extend_kernel<DIM, EXT_NPT>), dim3(dev ? device_grid(b, r) : ext_grid(b.total[r])), B, 0,
+                             st, I, off, n, r, v, t, src, bit, sign_rho, mx, dil, cone(done + 1));
         if (hipGetLastError() != hipSuccess) return -1;
       }
       done += ns;
@@ -801,8 +820,7 @@ hipError_t end_dim(LevelsetBatch& b, hipStream_t st) {
   const int* off = b.d_off;
   const dim3 B(256);
   const bool dev = b.device_sized;
-  const int dgrid = dev ? device_grid(b) : 0;
-  auto grid = [&](int row) { return dev ? dgrid : b.total[row]; };
+  auto grid = [&](int row) { return dev ? device_grid(b, row) : b.total[row]; };
   // advection substeps: from the maximum speeds on the host, or the most
   // the front guard allows (each instance skips those beyond its own count)
   int nsub = 1;
@@ -971,8 +989,6 @@ hipError_t levelset_begin(LevelsetBatch& b, double dt, int reinit, hipStream_t s
 
 hipError_t levelset_upload(LevelsetBatch& b, hipStream_t st) {
   const int n = b.count;
-  b.max_tiles = 0;
-  for (int i = 0; i < n; ++i) b.max_tiles += b.h_inst[i].ntx * b.h_inst[i].nty * b.h_inst[i].ntz;
   hipError_t e = upload(b, st);   // table, dirty flags, offsets of the current lists
   if (e != hipSuccess) return e;
   if (b.any_dirty) {
