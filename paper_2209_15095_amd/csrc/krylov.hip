@@ -933,12 +933,21 @@ struct Engine {
   // --------------------------------------------------------- small expm
 
   // E = exp(X) in R, X the augmented matrix of size N = m + p + 1 built
-  // from tau, alpha[0..m-1], nrm[1..m-1].
+  // from tau, alpha[0..m-1], nrm[1..m-1], by the whole block (one wave alone
+  // was measured 2.5x slower: too few loads in flight per Horner step).
   __device__ __forceinline__ void expm_aug(int m, int p, double tau) {
     const unsigned long long t_in = wall_clock64();
+    expm_run(m, p, tau, (int)threadIdx.x, (int)blockDim.x);
+    __syncthreads();
+    if (threadIdx.x == 0 && lb == 0) c.st.tk_expm += wall_clock64() - t_in;
+  }
+
+  // Scaling, Taylor-Horner and squaring by threads first, first + stride, ...
+  __device__ __forceinline__ void expm_run(int m, int p, double tau, int first, int stride) {
+    auto step_sync = [&]() { __syncthreads(); };
     const int N = m + p + 1;
     // 1-norm of X (column sums)
-    if (threadIdx.x == 0) {
+    if (first == 0) {
       double nx = 1.0;
       for (int j = 0; j < m; ++j) {
         double s = fabs(c.alpha[j]);
@@ -948,20 +957,20 @@ struct Engine {
       }
       c.red[0] = nx;
     }
-    __syncthreads();
+    step_sync();
     const double nx = c.red[0];
     int sq = 0;
     if (nx > 1.0) sq = (int)ceil(log2(nx));
     const double scale = ldexp(1.0, -sq);
     const int NN = N * N;
-    for (int e = threadIdx.x; e < NN; e += blockDim.x) R[e] = ((e / N) == (e % N)) ? 1.0 : 0.0;
-    __syncthreads();
+    for (int e = first; e < NN; e += stride) R[e] = ((e / N) == (e % N)) ? 1.0 : 0.0;
+    step_sync();
     double* A = R;
     double* B = S;
     constexpr int K = 20;
     for (int k = K; k >= 1; --k) {
       const double f = scale / (double)k;
-      for (int e = threadIdx.x; e < NN; e += blockDim.x) {
+      for (int e = first; e < NN; e += stride) {
         const int i = e / N, j = e % N;
         double xr;
         if (i < m) {
@@ -977,11 +986,11 @@ struct Engine {
         }
         B[e] = ((i == j) ? 1.0 : 0.0) + f * xr;
       }
-      __syncthreads();
+      step_sync();
       double* t = A; A = B; B = t;
     }
     for (int s = 0; s < sq; ++s) {
-      for (int e = threadIdx.x; e < NN; e += blockDim.x) {
+      for (int e = first; e < NN; e += stride) {
         const int i = e / N, j = e % N;
         double acc = 0.0;
         // lower-left block (rows >= m, cols < m) of every power is zero
@@ -989,14 +998,13 @@ struct Engine {
         for (int l = l0; l < N; ++l) acc += A[i * N + l] * A[l * N + j];
         B[e] = acc;
       }
-      __syncthreads();
+      step_sync();
       double* t = A; A = B; B = t;
     }
     if (A != R) {
-      for (int e = threadIdx.x; e < NN; e += blockDim.x) R[e] = A[e];
-      __syncthreads();
+      for (int e = first; e < NN; e += stride) R[e] = A[e];
+      step_sync();
     }
-    if (threadIdx.x == 0 && lb == 0) c.st.tk_expm += wall_clock64() - t_in;
   }
 
   // ------------------------------------------------------------ phi combo
@@ -1147,7 +1155,7 @@ struct Engine {
           const double nb = sqrt(o[0]);
           const double alpha_next = (o[0] > 0.0) ? o[1] / o[0] : 0.0;
           anorm = fmax(anorm, fabs(c.alpha[m]) + nb + (m > 0 ? c.nrm[m] : 0.0));
-          __syncthreads();
+          // entries m + 1 are read by no thread before the barrier below
           if (threadIdx.x == 0) {
             c.nrm[m + 1] = nb;
             c.alpha[m + 1] = alpha_next;
