@@ -537,8 +537,10 @@ def main():
             "in_expm": prof["krylov_expm_ms"] / steps,
             "in_passes": prof["krylov_pass_ms"] / steps,
             "in_prologue": prof["krylov_prologue_ms"] / steps,
+            "after_syncs": prof["krylov_gap_ms"] / steps,
             "other_control": (prof["krylov_device_ms"] - prof["krylov_sync_ms"] - prof["krylov_expm_ms"]
-                              - prof["krylov_pass_ms"] - prof["krylov_prologue_ms"]) / steps,
+                              - prof["krylov_pass_ms"] - prof["krylov_prologue_ms"]
+                              - prof["krylov_gap_ms"]) / steps,
             "syncs": prof["krylov_syncs"] / steps,
             "expms": prof["krylov_expms"] / steps,
         },

@@ -138,8 +138,10 @@ typedef struct {
    * launches, grid synchronisations (waiting included), small exponentials,
    * passes over the tiles (from the start of a tile loop until every wave
    * of the block has finished it and the block has reduced its partials),
-   * launch prologue (tile metadata into LDS); the rest is control between
-   * passes */
+   * launch prologue (tile metadata into LDS), and from the end of each grid
+   * synchronisation to the start of the next pass or exponential
+   * (krylov_gap_ms); the rest is the control that follows passes and
+   * exponentials without a synchronisation */
   double krylov_device_ms;
   double krylov_sync_ms;
   double krylov_expm_ms;
@@ -147,6 +149,7 @@ typedef struct {
   double krylov_prologue_ms;
   int32_t krylov_syncs;
   int32_t krylov_expms;
+  double krylov_gap_ms;
 } etd_profile;
 
 typedef struct etd_ctx etd_ctx;

@@ -69,7 +69,7 @@ class EtdProfile(C.Structure):
                 ("geometry_calls", C.c_int32), ("n_unknowns", C.c_int32),
                 ("krylov_device_ms", C.c_double), ("krylov_sync_ms", C.c_double), ("krylov_expm_ms", C.c_double),
                 ("krylov_pass_ms", C.c_double), ("krylov_prologue_ms", C.c_double),
-                ("krylov_syncs", C.c_int32), ("krylov_expms", C.c_int32)]
+                ("krylov_syncs", C.c_int32), ("krylov_expms", C.c_int32), ("krylov_gap_ms", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

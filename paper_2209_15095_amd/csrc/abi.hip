@@ -984,6 +984,7 @@ int etd_ctx_profile_read(etd_ctx* c, etd_profile* out, int32_t reset) {
   out->krylov_expm_ms = c->h_state->ticks_expm / c->clock_khz;
   out->krylov_pass_ms = c->h_state->ticks_pass / c->clock_khz;
   out->krylov_prologue_ms = c->h_state->ticks_pro / c->clock_khz;
+  out->krylov_gap_ms = c->h_state->ticks_gap / c->clock_khz;
   out->krylov_syncs = c->h_state->syncs;
   out->krylov_expms = c->h_state->expm_calls;
   if (reset) {
@@ -1656,6 +1657,7 @@ int etd_batch_profile_read(etd_batch* B, etd_profile* out, int32_t reset) {
   out->krylov_expm_ms = c0->h_state->ticks_expm / c0->clock_khz;
   out->krylov_pass_ms = c0->h_state->ticks_pass / c0->clock_khz;
   out->krylov_prologue_ms = c0->h_state->ticks_pro / c0->clock_khz;
+  out->krylov_gap_ms = c0->h_state->ticks_gap / c0->clock_khz;
   out->krylov_syncs = c0->h_state->syncs;
   out->krylov_expms = c0->h_state->expm_calls;
   if (reset) {

@@ -84,7 +84,7 @@ struct KrylovStateDev {
   // device-clock ticks accumulated over launches (block 0 of the group):
   // whole launch, grid synchronisations, small exponentials, passes (tile
   // loops and block reductions), launch prologue
-  double ticks_total, ticks_sync, ticks_expm, ticks_pass, ticks_pro;
+  double ticks_total, ticks_sync, ticks_expm, ticks_pass, ticks_pro, ticks_gap;
   int syncs, expm_calls;
 };
 

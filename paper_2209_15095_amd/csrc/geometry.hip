@@ -106,10 +106,11 @@ __global__ __launch_bounds__(256) void classify_kernel(const GeomInst* __restric
 
 // One block of 1024 threads per instance: exclusive scan of tile flags, in
 // chunks of SCAN_CHUNK tiles: the chunk's flags are loaded coalesced into
-// LDS (bytes), thread t counts the flags of its contiguous run of
-// SCAN_CHUNK / 1024 tiles there, one block scan gives each run its first
-// slot, and the run's slots are written in order.
-constexpr int SCAN_CHUNK = 32768;
+// LDS (bytes), thread t counts the flags of its run of SCAN_CHUNK / 1024
+// consecutive tiles there, one block scan gives each run its first slot,
+// the runs write their slots into LDS, and the chunk's tile map is stored
+// coalesced (the slot -> tile entries at the active tiles only).
+constexpr int SCAN_CHUNK = 8192;
 
 __global__ __launch_bounds__(1024) void scan_tiles_kernel(const GeomInst* __restrict__ tab) {
   constexpr int RUN = SCAN_CHUNK / 1024;
@@ -119,17 +120,19 @@ __global__ __launch_bounds__(1024) void scan_tiles_kernel(const GeomInst* __rest
   int* __restrict__ tile_map = I.tile_map;
   int* __restrict__ slot_tile = I.slot_tile;
   __shared__ uint8_t fl[SCAN_CHUNK];
+  __shared__ int sl[SCAN_CHUNK];
   __shared__ int wave_tot[16];
   __shared__ int carry;
   if (threadIdx.x == 0) carry = 0;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   for (int base = 0; base < ntiles; base += SCAN_CHUNK) {
     const int n = min(SCAN_CHUNK, ntiles - base);
-#pragma unroll 8
+#pragma unroll
     for (int k = threadIdx.x; k < SCAN_CHUNK; k += 1024) fl[k] = (k < n && tile_flag[base + k] != 0) ? 1 : 0;
     __syncthreads();
     const int r0 = (int)threadIdx.x * RUN;
     int cnt = 0;
+#pragma unroll
     for (int k = 0; k < RUN; ++k) cnt += fl[r0 + k];
     int x = cnt;
     for (int o = 1; o < 64; o <<= 1) {
@@ -145,11 +148,13 @@ __global__ __launch_bounds__(1024) void scan_tiles_kernel(const GeomInst* __rest
     }
     __syncthreads();
     int slot = wave_tot[w] + x - cnt;
-    for (int k = 0; k < RUN && r0 + k < n; ++k) {
-      const int t = base + r0 + k;
-      const bool f = fl[r0 + k] != 0;
-      tile_map[t] = f ? slot : -1;
-      if (f) slot_tile[slot++] = t;
+#pragma unroll
+    for (int k = 0; k < RUN; ++k) sl[r0 + k] = fl[r0 + k] ? slot++ : -1;
+    __syncthreads();
+    for (int k = threadIdx.x; k < n; k += 1024) {
+      const int v = sl[k];
+      tile_map[base + k] = v;
+      if (v >= 0) slot_tile[v] = base + k;
     }
     __syncthreads();
   }

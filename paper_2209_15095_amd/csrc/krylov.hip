@@ -72,7 +72,10 @@ struct Ctl {
   struct Stats {
     int substeps, rejected, matvecs, m_last, expms, n_sync;
     double err_est, ratio_last, t_done, bpu;   // ratio_last: error / tolerance of the last accepted substep
-    unsigned long long tk_sync, tk_expm, tk_pass, tk_pro, t_mark;
+    // tk_gap: from the end of a synchronisation to the start of the next
+    // timed region (pass or exponential); t_free: end of the last
+    // synchronisation not yet followed by one (0: none)
+    unsigned long long tk_sync, tk_expm, tk_pass, tk_pro, t_mark, tk_gap, t_free;
   } st;
   int abort;
 };
@@ -283,6 +286,11 @@ struct Engine {
   __device__ __forceinline__ void add_bytes(double b) {
     if (threadIdx.x == 0) c.st.bpu += b;
   }
+  // block 0, thread 0: a timed region starts at `now` (closes a pending gap)
+  __device__ __forceinline__ void region_start(unsigned long long now) {
+    if (c.st.t_free) c.st.tk_gap += now - c.st.t_free;
+    c.st.t_free = 0;
+  }
 
   __device__ __forceinline__ gptr<double> V(int i) const { return glb(P.ws) + (size_t)i * P.ld; }
 
@@ -355,7 +363,9 @@ struct Engine {
     const int ab = c.abort;
     __syncthreads();
     if (threadIdx.x == 0 && lb == 0) {
-      c.st.tk_sync += wall_clock64() - t_in;
+      const unsigned long long t_out = wall_clock64();
+      c.st.tk_sync += t_out - t_in;
+      c.st.t_free = t_out;
       ++c.st.n_sync;
     }
     return ab == 0;
@@ -371,6 +381,7 @@ struct Engine {
     if (threadIdx.x == 0 && lb == 0) c.st.tk_pass += wall_clock64() - c.st.t_mark;
     if (G == 1) {
       for (int k = 0; k < NR; ++k) out[k] = acc[k];
+      if (threadIdx.x == 0 && lb == 0) c.st.t_free = wall_clock64();
     } else if (!grid_sync<NR>(acc, out)) {
       if (threadIdx.x == 0) atomicCAS(P.status, 0, ST_BARRIER);
       failed = true;
@@ -386,7 +397,10 @@ struct Engine {
 
   __device__ __forceinline__ bool barrier() {
     __syncthreads();
-    if (threadIdx.x == 0 && lb == 0) c.st.tk_pass += wall_clock64() - c.st.t_mark;
+    if (threadIdx.x == 0 && lb == 0) {
+      c.st.tk_pass += wall_clock64() - c.st.t_mark;
+      if (G == 1) c.st.t_free = wall_clock64();
+    }
     if (G == 1) return true;
     double a[1] = {0.0}, o[1];
     if (!grid_sync<1>(a, o)) {
@@ -502,7 +516,7 @@ struct Engine {
     const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int stride = G * KTILES;
     int slot = tile_block() * KTILES + sub;
-    if (threadIdx.x == 0 && lb == 0) c.st.t_mark = wall_clock64();
+    if (threadIdx.x == 0 && lb == 0) { c.st.t_mark = wall_clock64(); region_start(c.st.t_mark); }
     Meta m;
     if (slot < nact) trip_meta(m, 0, slot, sub, w);
     for (int r = 0; slot < nact; ++r) {
@@ -758,7 +772,7 @@ struct Engine {
     const int stride = G * KTILES;
     const int base0 = tile_block() * KTILES;
     double acc[2] = {0.0, 0.0};
-    if (threadIdx.x == 0 && lb == 0) c.st.t_mark = wall_clock64();
+    if (threadIdx.x == 0 && lb == 0) { c.st.t_mark = wall_clock64(); region_start(c.st.t_mark); }
     // loads of trip r: the point and the halo nodes (0 where no tile)
     double pz, p1, p2, hz[HR], h1[HR], h2[HR];
     // metadata of trip r from the LDS cache (the caller uses this pass only
@@ -871,7 +885,7 @@ struct Engine {
   // (NOT_COMP elsewhere).  The q_k buffer alternates between two LDS halves
   // by trip parity, so two block barriers per trip suffice.
   __device__ __forceinline__ bool lanczos_zf2(int k, double (&out)[2]) {
-    if (threadIdx.x == 0 && lb == 0) c.st.t_mark = wall_clock64();
+    if (threadIdx.x == 0 && lb == 0) { c.st.t_mark = wall_clock64(); region_start(c.st.t_mark); }
     double acc[2];
     zf2_loop(uniform<const double>(V(V_Q0 + k - 1)), uniform<const double>(V(V_Q0 + (k >= 2 ? k - 2 : 0))),
              uniform<double>(V(V_Q0 + k)), uniform<const double>(glb(P.g.cdiag)), P.g.coef, c.alpha[k - 1],
@@ -937,6 +951,7 @@ struct Engine {
   // was measured 2.5x slower: too few loads in flight per Horner step).
   __device__ __forceinline__ void expm_aug(int m, int p, double tau) {
     const unsigned long long t_in = wall_clock64();
+    if (threadIdx.x == 0 && lb == 0) region_start(t_in);
     expm_run(m, p, tau, (int)threadIdx.x, (int)blockDim.x);
     __syncthreads();
     if (threadIdx.x == 0 && lb == 0) c.st.tk_expm += wall_clock64() - t_in;
@@ -1640,6 +1655,7 @@ __device__ __forceinline__ void krylov_body(const KrylovDev& P, int lb, int G, C
     P.st->ticks_expm += (double)s.tk_expm;
     P.st->ticks_pass += (double)s.tk_pass;
     P.st->ticks_pro += (double)s.tk_pro;
+    P.st->ticks_gap += (double)s.tk_gap;
     P.st->syncs += s.n_sync;
     P.st->expm_calls += s.expms;
   }
