@@ -13,7 +13,15 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libetdfb.so")
-SOURCES = ["abi.hip", "geometry.hip", "krylov.hip", "levelset.hip"]
+# (source, object, extra flags): the persistent Krylov kernels are built
+# twice, with blocks of 1024 and of 512 threads
+SOURCES = [
+    ("abi.hip", "abi.o", []),
+    ("geometry.hip", "geometry.o", []),
+    ("krylov.hip", "krylov_kb1024.o", ["-DKRYLOV_KBLOCK=1024"]),
+    ("krylov.hip", "krylov_kb512.o", ["-DKRYLOV_KBLOCK=512"]),
+    ("levelset.hip", "levelset.o", []),
+]
 ARCH = "gfx950"
 FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-fPIC", "-std=c++17",
@@ -23,9 +31,10 @@ FLAGS = [
 ]
 
 
-def _compile(src: str) -> str:
-    obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = ["hipcc", *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+def _compile(item) -> str:
+    src, name, extra = item
+    obj = os.path.join(BUILD, name)
+    cmd = ["hipcc", *FLAGS, *extra, "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr}")

@@ -55,7 +55,10 @@ struct etd_ctx {
   double clock_khz = 1.0;   // device wall clock (ticks per millisecond)
   int tmax = 1;
   KrylovStateDev* st = nullptr;
-  int max_grid = 0;
+  int max_grid = 0;                 // co-resident blocks, the larger of the two builds (array sizes)
+  int max_grid_kb[2] = {0, 0};      // co-resident blocks of each Krylov build (KrylovBuild)
+  int kb_fixed = -1;                // a build this context always uses (-1: chosen per geometry)
+  int kb = KB_LARGE;                // the build of the next Krylov launch
   int grid_blocks = 1;
   int n_active_host = 0;
   bool have_geometry = false;
@@ -274,16 +277,27 @@ KrylovDev krylov_params(const etd_ctx* c, int mode) {
 }
 
 // Grid of the persistent kernel: enough blocks for one loop trip over the
-// active tiles (KTILES tiles per block and trip), at most the number of
+// active tiles (KB_TILES tiles per block and trip), at most the number of
 // co-resident blocks.  ETDFB_GRID in the environment overrides the count.
 void choose_launch(etd_ctx* c) {
   const int nact = c->n_active_host > 0 ? c->n_active_host * c->species : 1;
-  int g = (nact + KTILES - 1) / KTILES;
-  if (g > c->max_grid) g = c->max_grid;
+  // 512-thread blocks when every active tile fits one loop trip of them
+  // (more blocks on more CUs, twice the registers per thread), else 1024;
+  // ETDFB_KBLOCK (512 or 1024) in the environment forces a build
+  int kb = (nact <= KB_TILES[KB_SMALL] * c->max_grid_kb[KB_SMALL]) ? KB_SMALL : KB_LARGE;
+  if (const char* env = getenv("ETDFB_KBLOCK")) {
+    const int v = atoi(env);
+    if (v == KB_THREADS[KB_SMALL]) kb = KB_SMALL;
+    if (v == KB_THREADS[KB_LARGE]) kb = KB_LARGE;
+  }
+  if (c->kb_fixed >= 0) kb = c->kb_fixed;
+  int g = (nact + KB_TILES[kb] - 1) / KB_TILES[kb];
+  if (g > c->max_grid_kb[kb]) g = c->max_grid_kb[kb];
   if (const char* env = getenv("ETDFB_GRID")) {
     const int v = atoi(env);
-    if (v >= 1 && v <= c->max_grid) g = v;
+    if (v >= 1 && v <= c->max_grid_kb[kb]) g = v;
   }
+  c->kb = kb;
   c->grid_blocks = g < 1 ? 1 : g;
   c->tmax = 1;
 }
@@ -291,7 +305,7 @@ void choose_launch(etd_ctx* c) {
 int run_krylov(etd_ctx* c, const KrylovDev& P) {
   if (!c->have_geometry) return ETD_ERR_NO_GEOMETRY;
   if (timer_begin(c->profiling, c->stream, c->t_krylov) != hipSuccess) return ETD_ERR_HIP;
-  hipError_t e = launch_krylov(c->box.dim, P, c->grid_blocks, c->stream);
+  hipError_t e = launch_krylov(c->kb, c->box.dim, P, c->grid_blocks, c->stream);
   if (e != hipSuccess) return ETD_ERR_HIP;
   return check_hip(timer_end(c->profiling, c->stream, c->t_krylov));
 }
@@ -540,9 +554,10 @@ int ctx_create(const etd_grid* grid, const etd_physics* phys, const etd_krylov_o
     if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, c->device) == hipSuccess && khz > 0)
       c->clock_khz = khz;
   }
-  const int per_cu = krylov_max_blocks_per_cu(b.dim, 1);
-  c->max_grid = per_cu * prop.multiProcessorCount;
-  if (c->max_grid < 1) { delete c; return ETD_ERR_HIP; }
+  for (int k = 0; k < 2; ++k)
+    c->max_grid_kb[k] = krylov_max_blocks_per_cu(k, b.dim) * prop.multiProcessorCount;
+  c->max_grid = c->max_grid_kb[0] > c->max_grid_kb[1] ? c->max_grid_kb[0] : c->max_grid_kb[1];
+  if (c->max_grid_kb[KB_LARGE] < 1 || c->max_grid_kb[KB_SMALL] < 1) { delete c; return ETD_ERR_HIP; }
   bool ok = true;
   ok &= hipMalloc(&c->mask, c->nodes) == hipSuccess;
   ok &= hipMalloc(&c->tile_flag, sizeof(int) * c->ntiles) == hipSuccess;
@@ -1050,7 +1065,7 @@ int batch_schedule(const etd_batch* B, int ch, int mode, double h, KrylovDev* pa
   long total_want = 0;
   for (int i = 0; i < n; ++i) {
     const int nact = B->inst[i0 + i]->n_active_host > 0 ? B->inst[i0 + i]->n_active_host : 1;
-    int w = (nact + KTILES - 1) / KTILES;
+    int w = (nact + KB_TILES[KB_LARGE] - 1) / KB_TILES[KB_LARGE];
     if (B->group_limit > 0 && w > B->group_limit) w = B->group_limit;
     want[i] = w;
     total_want += w - 1;
@@ -1096,7 +1111,7 @@ int batch_run_krylov(etd_batch* B, int mode, double h) {
                            B->stream));
     HIP_TRY(hipMemcpyAsync(B->d_blk + (size_t)ch * C, blk, sizeof(int) * blocks, hipMemcpyHostToDevice,
                            B->stream));
-    HIP_TRY(launch_krylov_group(B->dim, B->d_params + i0, n, B->d_blk + (size_t)ch * C, blocks, coop,
+    HIP_TRY(launch_krylov_group(KB_LARGE, B->dim, B->d_params + i0, n, B->d_blk + (size_t)ch * C, blocks, coop,
                                 B->stream));
   }
   HIP_TRY(hipEventRecord(B->staged, B->stream));
@@ -1136,7 +1151,7 @@ int graph_record(etd_batch* B, int scheme, double h, double* const* u) {
   hipStream_t cs = B->cap_stream;
   HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
   hipError_t e = launch_gather_batch(B->gb, B->d_guptr, V_X0, cs);
-  if (e == hipSuccess) e = launch_krylov_group(B->dim, B->d_gparams, n, B->d_gblk, blocks, false, cs);
+  if (e == hipSuccess) e = launch_krylov_group(KB_LARGE, B->dim, B->d_gparams, n, B->d_gblk, blocks, false, cs);
   if (e == hipSuccess) e = launch_scatter_batch(B->gb, (double* const*)B->d_guptr, V_U, cs);
   hipGraph_t g = nullptr;
   const hipError_t e2 = hipStreamEndCapture(cs, &g);
@@ -1215,7 +1230,7 @@ int graph_free_record(etd_batch* B, int scheme, double h, double* const* u, doub
     if (e == hipSuccess) e = levelset_end(B->flsb, cs);
     if (e == hipSuccess) e = launch_geometry(B->fgb, GEOM_RADII, cs, true);
     if (e == hipSuccess) e = launch_gather_batch(B->fgb, B->d_fuptr, V_X0, cs);
-    if (e == hipSuccess) e = launch_krylov_group(B->dim, B->d_fparams, n, B->d_fblk, blocks, false, cs);
+    if (e == hipSuccess) e = launch_krylov_group(KB_LARGE, B->dim, B->d_fparams, n, B->d_fblk, blocks, false, cs);
     if (e == hipSuccess) e = launch_scatter_batch(B->fgb, (double* const*)B->d_fuptr, V_U, cs);
     hipGraph_t g = nullptr;
     const hipError_t e2 = hipStreamEndCapture(cs, &g);
@@ -1281,7 +1296,7 @@ int etd_batch_create(int32_t count, const etd_grid* grids, const etd_physics* ph
       return r;
     }
   }
-  B->capacity = B->inst[0]->max_grid;
+  B->capacity = B->inst[0]->max_grid_kb[KB_LARGE];   // batches run the 1024-thread build
   B->nchunks = (count + B->capacity - 1) / B->capacity;
   bool ok = true;
   ok &= hipMalloc(&B->d_params, sizeof(KrylovDev) * count) == hipSuccess;
@@ -1682,7 +1697,7 @@ namespace {
 
 constexpr int ST_TILES = ETD_STATIC_MAX_TILES;              // box tiles at most
 constexpr size_t ST_LD = (size_t)ST_TILES * TILE_PTS;        // doubles per vector
-constexpr int ST_GMAX = (ST_TILES + KTILES - 1) / KTILES;   // blocks of the persistent launch at most
+constexpr int ST_GMAX = (ST_TILES + KB_TILES[KB_LARGE] - 1) / KB_TILES[KB_LARGE];   // blocks of the persistent launch at most (1024-thread build)
 
 // Byte offsets of the carved buffers (256-byte aligned).
 struct StaticLayout {
@@ -1744,7 +1759,7 @@ int static_scratch(int dev, char** out, int* max_grid) {
     if (strncmp(prop.gcnArchName, "gfx950", 6) != 0) return ETD_ERR_NO_DEVICE;
     void* p = nullptr;
     if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return ETD_ERR_HIP;
-    g_static_grid[dev] = krylov_max_blocks_per_cu(2, 1) * prop.multiProcessorCount;
+    g_static_grid[dev] = krylov_max_blocks_per_cu(KB_LARGE, 2) * prop.multiProcessorCount;
     g_static_ptr[dev] = p;
   }
   *out = (char*)g_static_ptr[dev];
@@ -1835,6 +1850,8 @@ extern "C" int phi_combination_apply_static(const etd_grid* grid, double beta, c
   c.bar = (BarrierDev*)(base + SL.bar);
   c.st = (KrylovStateDev*)(base + SL.st);
   c.max_grid = max_grid < ST_GMAX ? max_grid : ST_GMAX;
+  c.max_grid_kb[KB_LARGE] = c.max_grid;
+  c.kb_fixed = KB_LARGE;
   // host-side mirrors on this call's stack (pageable: every copy into or
   // out of them is complete at the synchronisations below)
   int h_counters[NCOUNTERS] = {};

@@ -11,9 +11,13 @@ constexpr int PART_STRIDE = 8;      // doubles per block in the partial-sum buff
 constexpr int MMAX_LIMIT = 64;      // largest Krylov dimension
 constexpr int PMAX = 3;             // largest phi index in one combination
 constexpr int EXPM_NMAX = MMAX_LIMIT + PMAX + 2;   // augmented matrix bound
-constexpr int KBLOCK = 1024;        // threads per block of the persistent kernels
+// The persistent kernels are built twice (krylov.hip, namespaces kb1024 and
+// kb512): blocks of 1024 threads for large instances and of 512 threads for
+// small ones (more blocks on more CUs, twice the registers per thread).
+enum KrylovBuild { KB_LARGE = 0, KB_SMALL = 1 };
+constexpr int KB_THREADS[2] = {1024, 512};
+constexpr int KB_TILES[2] = {1024 / TILE_PTS, 512 / TILE_PTS};   // tiles per block and loop trip
 constexpr int NBR_STRIDE = 8;       // ints per slot in the face-neighbour table
-constexpr int KTILES = KBLOCK / TILE_PTS;  // tiles a block works on per loop trip
 constexpr double NOT_COMP = -1e300; // coefficient sentinel of non-computational points
 constexpr int MAX_SPECIES = 4;      // components of u in a multi-species context
 

@@ -43,6 +43,23 @@
 
 namespace etdfb {
 
+// This file is compiled once per block size (KRYLOV_KBLOCK = 1024 or 512),
+// each build in a namespace of its own.
+#ifndef KRYLOV_KBLOCK
+#define KRYLOV_KBLOCK 1024
+#endif
+#if KRYLOV_KBLOCK == 1024
+#define KRYLOV_NS kb1024
+#elif KRYLOV_KBLOCK == 512
+#define KRYLOV_NS kb512
+#else
+#error "KRYLOV_KBLOCK must be 1024 or 512"
+#endif
+namespace KRYLOV_NS {
+
+constexpr int KBLOCK = KRYLOV_KBLOCK;            // threads per block of the persistent kernels
+constexpr int KTILES = KBLOCK / TILE_PTS;        // tiles a block works on per loop trip
+
 constexpr int META_TRIPS = 128;         // loop trips whose tile metadata a block keeps in LDS
 constexpr int NWAVE = KBLOCK / 64;
 
@@ -1768,4 +1785,5 @@ hipError_t launch_krylov(int dim, const KrylovDev& P, int grid, hipStream_t s) {
   return hipLaunchCooperativeKernel(fn, dim3(grid), dim3(KBLOCK), args, 0, s);
 }
 
+}  // namespace KRYLOV_NS
 }  // namespace etdfb

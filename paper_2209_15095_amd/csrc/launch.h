@@ -121,11 +121,27 @@ hipError_t launch_scatter_tiles(const BoxHost& b, const double* vec, const int* 
                                 const uint64_t* comp_bits, const int* n_active, double* box, int grid,
                                 hipStream_t s);
 
-// krylov.hip
-hipError_t launch_krylov(int dim, const KrylovDev& P, int grid, hipStream_t s);
-int krylov_max_blocks_per_cu(int dim, int tmax);
-size_t krylov_dyn_lds(int dim, int tmax);
-hipError_t launch_krylov_group(int dim, const KrylovDev* Ps, int count, const int* blk_inst, int blocks,
-                               bool cooperative, hipStream_t s);
+// krylov.hip, one build per block size (KrylovBuild)
+#define ETDFB_KRYLOV_DECLS                                                                              \
+  hipError_t launch_krylov(int dim, const KrylovDev& P, int grid, hipStream_t s);                       \
+  int krylov_max_blocks_per_cu(int dim, int tmax);                                                       \
+  size_t krylov_dyn_lds(int dim, int tmax);                                                              \
+  hipError_t launch_krylov_group(int dim, const KrylovDev* Ps, int count, const int* blk_inst, int blocks, \
+                                 bool cooperative, hipStream_t s);
+namespace kb1024 { ETDFB_KRYLOV_DECLS }
+namespace kb512 { ETDFB_KRYLOV_DECLS }
+#undef ETDFB_KRYLOV_DECLS
+
+inline hipError_t launch_krylov(int kb, int dim, const KrylovDev& P, int grid, hipStream_t s) {
+  return kb == KB_SMALL ? kb512::launch_krylov(dim, P, grid, s) : kb1024::launch_krylov(dim, P, grid, s);
+}
+inline int krylov_max_blocks_per_cu(int kb, int dim) {
+  return kb == KB_SMALL ? kb512::krylov_max_blocks_per_cu(dim, 1) : kb1024::krylov_max_blocks_per_cu(dim, 1);
+}
+inline hipError_t launch_krylov_group(int kb, int dim, const KrylovDev* Ps, int count, const int* blk_inst,
+                                      int blocks, bool cooperative, hipStream_t s) {
+  return kb == KB_SMALL ? kb512::launch_krylov_group(dim, Ps, count, blk_inst, blocks, cooperative, s)
+                        : kb1024::launch_krylov_group(dim, Ps, count, blk_inst, blocks, cooperative, s);
+}
 
 }  // namespace etdfb

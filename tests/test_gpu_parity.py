@@ -333,3 +333,43 @@ def test_domain_error_and_no_geometry():
         ctx.geometry_build(dev(rho))
     assert e.value.code == ETD_ERR_DOMAIN
     ctx.close()
+
+
+@pytest.mark.parametrize("case", ["fisher64", "ellipsoid3d"])
+def test_both_krylov_builds_match_oracle(case):
+    """The persistent kernels are built with 512-thread blocks (used when
+    every active tile fits one loop trip of them) and 1024-thread blocks;
+    each build, forced through ETDFB_KBLOCK, takes three frozen ETD2RK steps
+    against the oracle (1e-9) and against the other build (1e-12)."""
+    import os
+    if case == "fisher64":
+        w = inputs.fisher64()
+        g, rho, u0 = w.grid, w.rho0, w.u0
+    else:
+        g, rho = small_ellipsoid3d()
+        u0 = np.where(rho < 0, np.random.default_rng(4).uniform(0.2, 0.8, rho.shape), 0.0)
+    op = build_operator(ogrid(g), rho, 1.0)
+    f, _ = logistic(1.0, 1.0)
+    h = 0.05
+    U = op.gather(u0)
+    for _ in range(3):
+        U = oracle_etd_step(op.A, h, U, f, "etd2rk", method="dense" if op.n < 2500 else "krylov")
+    outs = {}
+    for kblock in (512, 1024):
+        old = os.environ.get("ETDFB_KBLOCK")
+        os.environ["ETDFB_KBLOCK"] = str(kblock)
+        try:
+            ctx = ctx_for(g, beta=1.0)
+            ctx.geometry_build(dev(rho))
+        finally:
+            os.environ.pop("ETDFB_KBLOCK", None)
+            if old is not None:
+                os.environ["ETDFB_KBLOCK"] = old
+        ud = dev(u0)
+        for _ in range(3):
+            st = ctx.etd_step("etd2rk", h, ud, stats=True)
+        outs[kblock] = host(ud)
+        say(f"  {case} {kblock}-thread blocks: {st}  rel {rel_l2(outs[kblock][op.comp], U):.3e}")
+        ctx.close()
+        assert rel_l2(outs[kblock][op.comp], U) <= 1e-9
+    assert rel_l2(outs[512], outs[1024]) <= 1e-12

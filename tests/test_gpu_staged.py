@@ -8,7 +8,8 @@ at the bandwidth-scale sizes.  Here the size threshold is taken to 0
 (ETDFB_GRID, read when the geometry is built) so that small problems take
 that path: phi-combinations and frozen ETD2RK steps against
 the oracle at 1e-9 relative L2 (Krylov tolerance 1e-10), and the staged
-launch against the one-trip launch of the same problem to 1e-12.
+launch against the one-trip launch of the same problem to 1e-12, with each
+build of the persistent kernels (blocks of 512 and of 1024 threads).
 """
 import os
 import sys
@@ -57,19 +58,24 @@ def staged_from_any_size():
         os.environ["ETDFB_STAGE_MIN"] = old
 
 
-def ctx_with_blocks(g, rho, blocks, **kw):
-    """A context whose persistent launches use `blocks` blocks (None: default)."""
+def ctx_with_blocks(g, rho, blocks, kblock=None, **kw):
+    """A context whose persistent launches use `blocks` blocks (None:
+    default) of the Krylov build with `kblock` threads per block (None: the
+    library's choice); both are read when the geometry is built."""
     from paper_2209_15095_amd.api import Context
-    old = os.environ.pop("ETDFB_GRID", None)
+    old = {k: os.environ.pop(k, None) for k in ("ETDFB_GRID", "ETDFB_KBLOCK")}
     try:
         if blocks is not None:
             os.environ["ETDFB_GRID"] = str(blocks)
+        if kblock is not None:
+            os.environ["ETDFB_KBLOCK"] = str(kblock)
         ctx = Context(g.dim, g.n, g.lo, g.hi, **kw)
         ctx.geometry_build(dev(rho))
     finally:
-        os.environ.pop("ETDFB_GRID", None)
-        if old is not None:
-            os.environ["ETDFB_GRID"] = old
+        for k, v in old.items():
+            os.environ.pop(k, None)
+            if v is not None:
+                os.environ[k] = v
     return ctx
 
 
@@ -85,9 +91,10 @@ def ellipsoid3d(n):
     return g, inputs.sdf_prolate_spheroid(X, Y, Z, 3.0, 2.0)
 
 
+@pytest.mark.parametrize("kblock", [512, 1024])
 @pytest.mark.parametrize("blocks", [1, 3])
 @pytest.mark.parametrize("case", ["disk2d", "ellipsoid3d"])
-def test_staged_phi_combination_parity(case, blocks):
+def test_staged_phi_combination_parity(case, blocks, kblock):
     if case == "disk2d":
         g, rho = disk2d(97)
     else:
@@ -97,18 +104,19 @@ def test_staged_phi_combination_parity(case, blocks):
     bs = [np.where(op.comp, rng.standard_normal(rho.shape), 0.0) for _ in range(3)]
     t = 0.2
     ref = phi_combination(op.A, t, [op.gather(b) for b in bs])
-    ctx = ctx_with_blocks(g, rho, blocks)
+    ctx = ctx_with_blocks(g, rho, blocks, kblock)
     out, st = ctx.phi_combination_apply(t, [dev(b) for b in bs], stats=True)
     o = out.cpu().numpy()
-    say(f"{case} blocks {blocks}: active tiles {st['n_active_tiles']} m {st['m_last']} "
+    say(f"{case} blocks {blocks} x {kblock}: active tiles {st['n_active_tiles']} m {st['m_last']} "
         f"rel {rel_l2(o[op.comp], ref):.3e}")
-    assert st["n_active_tiles"] > 4 * blocks   # several loop trips per block
+    assert st["n_active_tiles"] > (kblock // 256) * blocks   # several loop trips per block
     assert np.all(o[~op.comp] == 0.0)
     assert rel_l2(o[op.comp], ref) <= 1e-9
     ctx.close()
 
 
-def test_staged_etd2rk_steps_disk257():
+@pytest.mark.parametrize("kblock", [512, 1024])
+def test_staged_etd2rk_steps_disk257(kblock):
     g, rho = disk2d(257)
     op = build_operator(ogrid(g), rho, 1.0)
     u0 = np.where(op.comp, np.random.default_rng(2).uniform(0.2, 0.8, rho.shape), 0.0)
@@ -120,7 +128,7 @@ def test_staged_etd2rk_steps_disk257():
         U = oracle_etd_step(op.A, h, U, f, "etd2rk", method="krylov")
     outs = []
     for blocks in (8, None):
-        ctx = ctx_with_blocks(g, rho, blocks)
+        ctx = ctx_with_blocks(g, rho, blocks, kblock)
         ud = dev(u0)
         for _ in range(2):
             st = ctx.etd_step("etd2rk", h, ud, stats=True)
