@@ -350,10 +350,20 @@ struct Engine {
       }
       long spins = 0;
       int ab = 0;
+      // a lane's flags and partials (b = lane + 64 q) are loaded four at a
+      // time, all in flight before the first is used
       while (true) {
         bool mine = true;
-        for (int b = lane; b < G; b += 64)
-          mine &= (__hip_atomic_load(&P.flags[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= gen);
+        for (int b0 = lane; b0 < G; b0 += 256) {
+          unsigned f[4];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int b = b0 + 64 * q;
+            f[q] = (b < G) ? __hip_atomic_load(&P.flags[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : gen;
+          }
+#pragma unroll
+          for (int q = 0; q < 4; ++q) mine &= f[q] >= gen;
+        }
         if (__ballot(!mine) == 0ull) break;
         __builtin_amdgcn_s_sleep(1);
         if ((++spins & 255) == 0) {
@@ -367,11 +377,25 @@ struct Engine {
         }
       }
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      double t[NR];
+#pragma unroll
+      for (int k = 0; k < NR; ++k) t[k] = 0.0;
+      for (int b0 = lane; b0 < G; b0 += 256) {
+        double v[4][NR];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int b = b0 + 64 * q;
+#pragma unroll
+          for (int k = 0; k < NR; ++k) v[q][k] = (b < G) ? part[(size_t)b * PART_STRIDE + k] : 0.0;
+        }
+        // fixed order: every block sums the same values the same way
+#pragma unroll
+        for (int k = 0; k < NR; ++k) t[k] += ((v[0][k] + v[1][k]) + v[2][k]) + v[3][k];
+      }
+#pragma unroll
       for (int k = 0; k < NR; ++k) {
-        double t = 0.0;
-        for (int b = lane; b < G; b += 64) t += part[(size_t)b * PART_STRIDE + k];
-        t = wave_sum_lane0(t);
-        if (lane == 0) c.red[k] = t;
+        const double r = wave_sum_lane0(t[k]);
+        if (lane == 0) c.red[k] = r;
       }
       if (lane == 0) c.abort = ab;
     }
