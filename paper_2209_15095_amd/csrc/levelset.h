@@ -82,6 +82,11 @@ constexpr int LS_CNT_C = 16;                          // ncum_c[0..LS_C_MAX]
 constexpr int LS_CNT_V = LS_CNT_C + LS_C_MAX + 1;     // ncum_v[0..LS_V_MAX]
 constexpr int LS_CNT_U = LS_CNT_V + LS_V_MAX + 1;     // size of U
 constexpr int LS_NCOUNTERS = LS_CNT_U + 1;
+// The maximum of the extended speed is gathered over this many slots per
+// instance (one device-scope atomic per tile, spread over the slots by
+// block, so that thousands of tiles do not queue on one address), then
+// folded into the instance's maximum by one small launch.
+constexpr int LS_VMAX_SLOTS = 64;
 
 // Box-sized scratch arrays of one instance.  Between passes the extension
 // arrays hold 0 and the distance 255 at every node (the whole-box values the
@@ -118,6 +123,7 @@ struct LsInst {
   int* status;                // latched device error of the instance
   const int* cnt;             // the instance's geometry counters (list sizes, on the device)
   double* vmax;               // set by levelset_begin
+  double* vslot;              // LS_VMAX_SLOTS partial maxima (0 between passes)
   int dirty;                  // set by levelset_begin / levelset_extend: clear the whole box first
   bool* host_dirty;           // LevelsetScratch::dirty (host address, never read on the device)
 };
@@ -131,6 +137,7 @@ struct LevelsetBatch {
   int* d_off = nullptr;       // LS_NROWS * (count + 1): block offsets of each launch row
   int* h_off = nullptr;       // pinned
   double* d_vmax = nullptr;   // count maximum speeds
+  double* d_vslot = nullptr;  // count * LS_VMAX_SLOTS partial maxima
   double* h_vmax = nullptr;   // pinned mirror
   int total[LS_NROWS] = {};
   double dt = 0.0;

@@ -133,6 +133,7 @@ __global__ __launch_bounds__(256) void zero_kernel(const LsInst* __restrict__ in
     const LsInst& I = *w.I;
     if (!I.dirty) continue;
     if (w.local == 0 && threadIdx.x == 0) *glb(I.vmax) = 0.0;
+    if (w.local == 0 && threadIdx.x < LS_VMAX_SLOTS) glb(I.vslot)[threadIdx.x] = 0.0;
     if (!w.in) continue;
     for (int a = A_E0; a <= A_V; ++a) arr(I, a)[w.id] = 0.0;
     arr(I, A_S)[w.id] = 0.0;
@@ -242,7 +243,8 @@ inline int ext_grid(int total) {
 
 // one Jacobi sweep on `list`: out = v - dtau (a.grad v - src) off the known set
 // (bit), a = sgn * n, sgn = 1 or sign(rho) (speed extension); with
-// do_max, also the instance's maximum of out (non-negative values).  With
+// do_max, also the maximum of out (non-negative values) into the instance's
+// slots (vmax_fold_kernel takes their maximum).  With
 // dil, the sweep also dilates the L1 distance to the computational points
 // by one node, in place (a value only decreases, never below the true
 // distance; after k such sweeps every node within k holds its exact
@@ -358,7 +360,8 @@ __global__ __launch_bounds__(256) void extend_kernel(const LsInst* __restrict__ 
         }
         // max of non-negative doubles: integer order equals value order
         if (threadIdx.x == 0)
-          atomicMax((unsigned long long*)w[q].I->vmax, (unsigned long long)__double_as_longlong(sm[0]));
+          atomicMax((unsigned long long*)(w[q].I->vslot + (vx & (LS_VMAX_SLOTS - 1))),
+                    (unsigned long long)__double_as_longlong(sm[0]));
         __syncthreads();
       }
     }
@@ -466,7 +469,8 @@ __global__ __launch_bounds__(256) void extend_group_kernel(const LsInst* __restr
         __syncthreads();
       }
       if (threadIdx.x == 0)
-        atomicMax((unsigned long long*)I.vmax, (unsigned long long)__double_as_longlong(sm[0]));
+        atomicMax((unsigned long long*)(I.vslot + (vb_ & (LS_VMAX_SLOTS - 1))),
+                  (unsigned long long)__double_as_longlong(sm[0]));
     }
     __syncthreads();   // LDS is restaged by the next virtual block
   }
@@ -708,6 +712,19 @@ __global__ void front_check_kernel(const LsInst* __restrict__ insts, int count, 
   if (!(*glb((const double*)I.vmax) * dt <= LS_MAX_FRONT_NODES * I.h)) atomicCAS(I.status, 0, ST_FRONT);
 }
 
+// The instance's maximum speed from its slots, which go back to 0 (block i:
+// instance i; lane l: slot l).
+__global__ __launch_bounds__(LS_VMAX_SLOTS) void vmax_fold_kernel(const LsInst* __restrict__ insts) {
+  static_assert(LS_VMAX_SLOTS == 64, "one slot per lane of a wave");
+  const LsInst& I = insts[blockIdx.x];
+  const int l = (int)threadIdx.x;
+  gptr<double> sl = glb(I.vslot);
+  double m = sl[l];
+  for (int o = LS_VMAX_SLOTS / 2; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o));
+  sl[l] = 0.0;
+  if (l == 0) *glb(I.vmax) = m;
+}
+
 // Fixed grid of a device-sized launch on `row` (a multiple of 8, see
 // extend_kernel): the row's size when recorded (b.total, from the host
 // counts of levelset_upload) with half again as headroom for a growing
@@ -809,6 +826,8 @@ hipError_t begin_dim(LevelsetBatch& b, hipStream_t st, bool speed) {
   auto vcap = [](int r) { return r < LS_V_MAX ? r : LS_V_MAX; };
   if (stage([&](int, int s1) { return LS_ROW_V + vcap(s1); }, no_cone, A_V, A_S, -1, 3, 1, VEL_ITERS, 1, 0) != A_V)
     return hipErrorUnknown;
+  hipLaunchKernelGGL(vmax_fold_kernel, dim3(n), dim3(LS_VMAX_SLOTS), 0, st, I);
+  if (hipGetLastError() != hipSuccess) return hipErrorUnknown;
 #undef LL
   return hipSuccess;
 }
@@ -917,6 +936,8 @@ hipError_t levelset_batch_alloc(LevelsetBatch& b, int count, int dim) {
   if ((e = hipMalloc(&b.d_vmax, sizeof(double) * count)) != hipSuccess) return e;
   if ((e = hipHostMalloc(&b.h_vmax, sizeof(double) * count)) != hipSuccess) return e;
   if ((e = hipMemset(b.d_vmax, 0, sizeof(double) * count)) != hipSuccess) return e;
+  if ((e = hipMalloc(&b.d_vslot, sizeof(double) * LS_VMAX_SLOTS * count)) != hipSuccess) return e;
+  if ((e = hipMemset(b.d_vslot, 0, sizeof(double) * LS_VMAX_SLOTS * count)) != hipSuccess) return e;
   for (int i = 0; i < count; ++i) b.h_inst[i] = LsInst{};
   return hipSuccess;
 }
@@ -927,6 +948,7 @@ void levelset_batch_free(LevelsetBatch& b) {
   if (b.d_off) (void)hipFree(b.d_off);
   if (b.h_off) (void)hipHostFree(b.h_off);
   if (b.d_vmax) (void)hipFree(b.d_vmax);
+  if (b.d_vslot) (void)hipFree(b.d_vslot);
   if (b.h_vmax) (void)hipHostFree(b.h_vmax);
   b = LevelsetBatch{};
 }
@@ -953,6 +975,7 @@ hipError_t upload(LevelsetBatch& b, hipStream_t st) {
   for (int i = 0; i < n; ++i) {
     LsInst& I = b.h_inst[i];
     I.vmax = b.d_vmax + i;
+    I.vslot = b.d_vslot + (size_t)LS_VMAX_SLOTS * i;
     // an instance without a host flag is always cleared first
     I.dirty = (!I.host_dirty || *I.host_dirty) ? 1 : 0;
     b.any_dirty = b.any_dirty || I.dirty;
