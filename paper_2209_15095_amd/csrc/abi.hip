@@ -273,6 +273,10 @@ KrylovDev krylov_params(const etd_ctx* c, int mode) {
   // LDS-staged Lanczos pass is used (tests take it down to small problems)
   P.stage_min = STAGE_MIN_TILES;
   if (const char* env = getenv("ETDFB_STAGE_MIN")) P.stage_min = atoi(env);
+  // ETDFB_SYNC_MASTER overrides the block count from which block 0 alone
+  // reduces at a grid synchronisation (tests force either form)
+  P.sync_master_min = SYNC_MASTER_MIN_BLOCKS;
+  if (const char* env = getenv("ETDFB_SYNC_MASTER")) P.sync_master_min = atoi(env);
   return P;
 }
 

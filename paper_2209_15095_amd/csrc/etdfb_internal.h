@@ -49,7 +49,7 @@ enum VecIndex {
 
 struct BarrierDev {
   unsigned count;
-  unsigned gen;
+  unsigned gen;               // last generation whose sums block 0 has released (single-reducer form)
   int abort;
   int pad;
 };
@@ -128,6 +128,7 @@ struct KrylovDev {
   double h;                   // ETD step
   int g_first, g_size;        // blocks of this instance in the launch grid
   int stage_min;              // fewest active tiles for the LDS-staged Lanczos pass
+  int sync_master_min;        // blocks (of the grid or group) from which block 0 alone reduces at a grid synchronisation
   int first;                  // JOB_ETD2: no F(U_{n-1}) yet, take one ETD2RK step
   int forced;                 // F(U, t) = f(U) + G(t), G of the stage times in V_FG0..V_FG2
   // m > 1 species: the active tiles are repeated m times (species s in
@@ -142,6 +143,16 @@ struct KrylovDev {
 // the vectors outgrow the L2 (2048 active tiles, 4 MiB per vector); below,
 // its two block barriers per loop trip cost more than the misses it saves.
 constexpr int STAGE_MIN_TILES = 2048;
+
+// Default of KrylovDev::sync_master_min.  At a grid synchronisation every
+// block publishes its partial sums and an arrival flag.  Below this many
+// blocks every block polls all flags and sums all partials itself (one
+// memory round trip after the last arrival); from it on, block 0 alone does
+// so and publishes the sums in one word the others poll: one round trip
+// more, but without every block hammering the same few cache lines, which
+// costs more once there are many blocks (ellipsoid192, about 150 blocks:
+// 7.8 -> 5.8 us per synchronisation; star512, 24 blocks: 3.4 -> 3.6 us).
+constexpr int SYNC_MASTER_MIN_BLOCKS = 64;
 
 // Status codes (mirror include/etdfb.h).
 enum {

@@ -329,12 +329,20 @@ struct Engine {
   // Grid synchronisation fused with the reduction of NR per-block partials.
   // Every wave waits for its own stores; lane 0 writes the block's partials,
   // one agent-scope release publishes them with the pass's stores, then it
-  // writes its arrival generation into its own flag; wave 0 polls every flag
-  // (no contended atomic), acquires, and sums the partials in block order, so
-  // every block obtains bit-identical results.  Polls are bounded: past SPIN_LIMIT the
-  // abort flag goes up and every block leaves.
+  // writes its arrival generation into its own flag.  Below
+  // P.sync_master_min blocks, wave 0 of every block polls every flag (no
+  // contended atomic), acquires, and sums the partials in block order; from
+  // it on, block 0 alone does so, writes the sums and the abort state into
+  // its own row of the partial buffer (entries 4..6, past every block's
+  // partials) and releases them with the generation word of the barrier,
+  // which the other blocks poll before they acquire and read the sums.
+  // Either way every block obtains the same bits (one summation order), and
+  // the release/acquire chain through block 0 orders every block's stores
+  // before the next pass.  Polls are bounded: past SPIN_LIMIT the abort flag
+  // goes up and every block leaves.
   template <int NR>
   __device__ __forceinline__ bool grid_sync(const double (&acc)[NR], double (&out)[NR]) {
+    static_assert(NR <= 4 && PART_STRIDE >= 7, "partials, sums and abort state share block 0's row");
     const unsigned long long t_in = wall_clock64();
     ++pass_no;
     const unsigned gen = (unsigned)pass_no;
@@ -348,54 +356,87 @@ struct Engine {
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         __hip_atomic_store(&P.flags[lb], gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }
-      long spins = 0;
+      const bool master = G >= P.sync_master_min;
       int ab = 0;
-      // a lane's flags and partials (b = lane + 64 q) are loaded four at a
-      // time, all in flight before the first is used
-      while (true) {
-        bool mine = true;
+      if (!master || lb == 0) {
+        long spins = 0;
+        // a lane's flags and partials (b = lane + 64 q) are loaded four at a
+        // time, all in flight before the first is used
+        while (true) {
+          bool mine = true;
+          for (int b0 = lane; b0 < G; b0 += 256) {
+            unsigned f[4];
+  #pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              const int b = b0 + 64 * q;
+              f[q] = (b < G) ? __hip_atomic_load(&P.flags[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : gen;
+            }
+  #pragma unroll
+            for (int q = 0; q < 4; ++q) mine &= f[q] >= gen;
+          }
+          if (__ballot(!mine) == 0ull) break;
+          __builtin_amdgcn_s_sleep(1);
+          if ((++spins & 255) == 0) {
+            ab = __hip_atomic_load(&P.bar->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (ab) break;
+            if (spins > SPIN_LIMIT) {
+              if (lane == 0) __hip_atomic_store(&P.bar->abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+              ab = 1;
+              break;
+            }
+          }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        double t[NR];
+  #pragma unroll
+        for (int k = 0; k < NR; ++k) t[k] = 0.0;
         for (int b0 = lane; b0 < G; b0 += 256) {
-          unsigned f[4];
-#pragma unroll
+          double v[4][NR];
+  #pragma unroll
           for (int q = 0; q < 4; ++q) {
             const int b = b0 + 64 * q;
-            f[q] = (b < G) ? __hip_atomic_load(&P.flags[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : gen;
+  #pragma unroll
+            for (int k = 0; k < NR; ++k) v[q][k] = (b < G) ? part[(size_t)b * PART_STRIDE + k] : 0.0;
           }
-#pragma unroll
-          for (int q = 0; q < 4; ++q) mine &= f[q] >= gen;
+          // fixed order: every block sums the same values the same way
+  #pragma unroll
+          for (int k = 0; k < NR; ++k) t[k] += ((v[0][k] + v[1][k]) + v[2][k]) + v[3][k];
         }
-        if (__ballot(!mine) == 0ull) break;
-        __builtin_amdgcn_s_sleep(1);
-        if ((++spins & 255) == 0) {
-          ab = __hip_atomic_load(&P.bar->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          if (ab) break;
-          if (spins > SPIN_LIMIT) {
-            if (lane == 0) __hip_atomic_store(&P.bar->abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            ab = 1;
-            break;
+  #pragma unroll
+        for (int k = 0; k < NR; ++k) {
+          const double r = wave_sum_lane0(t[k]);
+          if (lane == 0) c.red[k] = r;
+        }
+        if (master && lane == 0) {
+          // publish the sums and the abort state for the other blocks
+          gptr<double> res = part + 4;
+          for (int k = 0; k < NR; ++k) res[k] = c.red[k];
+          res[2] = ab ? 1.0 : 0.0;
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+          __hip_atomic_store(&P.bar->gen, gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+      } else {
+        // wait for block 0's sums
+        long spins = 0;
+        while (true) {
+          if (__hip_atomic_load(&P.bar->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= gen) break;
+          __builtin_amdgcn_s_sleep(1);
+          if ((++spins & 255) == 0) {
+            ab = __hip_atomic_load(&P.bar->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (ab) break;
+            if (spins > SPIN_LIMIT) {
+              if (lane == 0) __hip_atomic_store(&P.bar->abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+              ab = 1;
+              break;
+            }
           }
         }
-      }
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-      double t[NR];
-#pragma unroll
-      for (int k = 0; k < NR; ++k) t[k] = 0.0;
-      for (int b0 = lane; b0 < G; b0 += 256) {
-        double v[4][NR];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int b = b0 + 64 * q;
-#pragma unroll
-          for (int k = 0; k < NR; ++k) v[q][k] = (b < G) ? part[(size_t)b * PART_STRIDE + k] : 0.0;
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        if (lane == 0 && !ab) {
+          gptr<const double> res = part + 4;
+          for (int k = 0; k < NR; ++k) c.red[k] = res[k];
+          ab = res[2] != 0.0 ? 1 : 0;
         }
-        // fixed order: every block sums the same values the same way
-#pragma unroll
-        for (int k = 0; k < NR; ++k) t[k] += ((v[0][k] + v[1][k]) + v[2][k]) + v[3][k];
-      }
-#pragma unroll
-      for (int k = 0; k < NR; ++k) {
-        const double r = wave_sum_lane0(t[k]);
-        if (lane == 0) c.red[k] = r;
       }
       if (lane == 0) c.abort = ab;
     }
