@@ -52,12 +52,43 @@ __device__ __forceinline__ int tile_of(const BoxDev& b, int i, int j, int k) {
   return ((k / b.tz) * b.nty + (j / b.ty)) * b.ntx + (i / b.tx);
 }
 
+// Node coordinates of a box index: 32-bit divisions where the box has
+// fewer than 2^32 nodes (a 64-bit division costs several times as many
+// instructions, and the whole-box kernels do one per node).
+__device__ __forceinline__ void node_coords(const BoxDev& b, size_t id, int& i, int& j, int& k) {
+  if ((size_t)b.nx * b.ny * b.nz <= 0xFFFFFFFFull) {
+    const unsigned u = (unsigned)id, nx = (unsigned)b.nx, ny = (unsigned)b.ny;
+    const unsigned q = u / nx;
+    i = (int)(u - q * nx);
+    k = (int)(q / ny);
+    j = (int)(q - (unsigned)k * ny);
+  } else {
+    i = (int)(id % b.nx);
+    j = (int)((id / b.nx) % b.ny);
+    k = (int)(id / ((size_t)b.nx * b.ny));
+  }
+}
+
+// Tile of a node: the tile extents are the fixed shapes (powers of two).
+__device__ __forceinline__ int tile_of_node(const BoxDev& b, int i, int j, int k) {
+  if (b.dim == 2)
+    return ((unsigned)j / TileShape<2>::Y) * b.ntx + (unsigned)i / TileShape<2>::X;
+  return (((unsigned)k / TileShape<3>::Z) * b.nty + (unsigned)j / TileShape<3>::Y) * b.ntx +
+         (unsigned)i / TileShape<3>::X;
+}
+
+// Index of a node within its tile (x fastest).
+__device__ __forceinline__ int tile_local(const BoxDev& b, int i, int j, int k) {
+  if (b.dim == 2) return ((unsigned)j % TileShape<2>::Y) * TileShape<2>::X + (unsigned)i % TileShape<2>::X;
+  return (((unsigned)k % TileShape<3>::Z) * TileShape<3>::Y + (unsigned)j % TileShape<3>::Y) * TileShape<3>::X +
+         (unsigned)i % TileShape<3>::X;
+}
+
 __device__ __forceinline__ void classify_node(const BoxDev& b, const double* __restrict__ rho,
                                               uint8_t* __restrict__ mask, int* __restrict__ tile_flag,
                                               int* __restrict__ tile_vb, int* __restrict__ status, size_t id) {
-  const int i = (int)(id % b.nx);
-  const int j = (int)((id / b.nx) % b.ny);
-  const int k = (int)(id / ((size_t)b.nx * b.ny));
+  int i, j, k;
+  node_coords(b, id, i, j, k);
   const bool inside = rho[id] < 0.0;
   bool comp = inside;
   if (comp) {
@@ -72,9 +103,9 @@ __device__ __forceinline__ void classify_node(const BoxDev& b, const double* __r
     }
   }
   mask[id] = comp ? 2 : (inside ? 1 : 0);
-  if (fabs(rho[id]) < b.dx) tile_vb[tile_of(b, i, j, k)] = 1;   // a node of the speed band
+  if (fabs(rho[id]) < b.dx) tile_vb[tile_of_node(b, i, j, k)] = 1;   // a node of the speed band
   if (comp) {
-    tile_flag[tile_of(b, i, j, k)] = 1;
+    tile_flag[tile_of_node(b, i, j, k)] = 1;
     bool edge = i < 2 || i > b.nx - 3 || j < 2 || j > b.ny - 3;
     if (b.dim == 3) edge = edge || k < 2 || k > b.nz - 3;
     if (edge) atomicCAS(status, 0, ST_DOMAIN);
@@ -643,13 +674,12 @@ __device__ __forceinline__ void scatter_node(const BoxDev& b, const double* __re
                                              const int* __restrict__ tile_map,
                                              const uint64_t* __restrict__ comp_bits, double* __restrict__ box,
                                              size_t id) {
-  const int i = (int)(id % b.nx);
-  const int j = (int)((id / b.nx) % b.ny);
-  const int k = (int)(id / ((size_t)b.nx * b.ny));
-  const int slot = tile_map[tile_of(b, i, j, k)];
+  int i, j, k;
+  node_coords(b, id, i, j, k);
+  const int slot = tile_map[tile_of_node(b, i, j, k)];
   double v = 0.0;
   if (slot >= 0) {
-    const int l = (i % b.tx) + b.tx * ((j % b.ty) + b.ty * (k % b.tz));
+    const int l = tile_local(b, i, j, k);
     if (bit_of(comp_bits, slot, l)) v = vec[(size_t)slot * TILE_PTS + l];
   }
   box[id] = v;
