@@ -422,7 +422,7 @@ int geometry_finish(etd_ctx* c, const int* cnt) {
 }
 
 // The level-set view of a context (its scratch, band and the user arrays).
-LsInst levelset_inst(etd_ctx* c, double* rho, double* u) {
+LsInst levelset_inst(etd_ctx* c, double* rho, double* u, double* f = nullptr) {
   LsInst I{};
   I.dim = c->box.dim;
   I.nx = c->box.nx; I.ny = c->box.ny; I.nz = c->box.nz;
@@ -434,6 +434,7 @@ LsInst levelset_inst(etd_ctx* c, double* rho, double* u) {
   I.mu = c->phys.mu;
   I.rho = rho;
   I.u = u;
+  I.f = f;
   I.buf = c->ls.buf;
   I.nodes = c->ls.nodes;
   I.known = c->ls.known;
@@ -830,14 +831,15 @@ int phi_combination_apply_multi(etd_ctx* c, double t, int32_t p, const double* c
   return ETD_OK;
 }
 
-int levelset_advance(etd_ctx* c, double* rho, double* u, double dt, int32_t reinit) {
-  if (!c || !rho || !u || !(dt >= 0.0) || !isfinite(dt)) return ETD_ERR_INVALID;
-  if (c->var_mode || c->species > 1) return ETD_ERR_INVALID;
+// Steps 1-2 of a context, u (and f, when given: extended from the same
+// computational points in the same launches) updated in place; nothing
+// changes when the front guard refuses the step.
+static int advance_fields(etd_ctx* c, double* rho, double* u, double* f, double dt, int32_t reinit) {
   if (!c->have_geometry) {
     int r = etd_geometry_build(c, rho);
     if (r) return r;
   }
-  c->lsb.h_inst[0] = levelset_inst(c, rho, u);
+  c->lsb.h_inst[0] = levelset_inst(c, rho, u, f);
   HIP_TRY(timer_begin(c->profiling, c->stream, c->t_levelset));
   HIP_TRY(levelset_begin(c->lsb, dt, reinit, c->stream));
   HIP_TRY(hipStreamSynchronize(c->stream));
@@ -845,6 +847,12 @@ int levelset_advance(etd_ctx* c, double* rho, double* u, double dt, int32_t rein
   HIP_TRY(levelset_end(c->lsb, c->stream));
   HIP_TRY(timer_end(c->profiling, c->stream, c->t_levelset));
   return etd_geometry_build(c, rho);
+}
+
+int levelset_advance(etd_ctx* c, double* rho, double* u, double dt, int32_t reinit) {
+  if (!c || !rho || !u || !(dt >= 0.0) || !isfinite(dt)) return ETD_ERR_INVALID;
+  if (c->var_mode || c->species > 1) return ETD_ERR_INVALID;
+  return advance_fields(c, rho, u, nullptr, dt, reinit);
 }
 
 int etd_step(etd_ctx* c, int32_t scheme, double h, double* u, double* rho, int32_t reinit,
@@ -908,19 +916,9 @@ int etd_multistep_step(etd_ctx* c, double h, double* u, double* f_prev, int32_t 
   if (!c || !u || !f_prev || f_prev == u || f_prev == rho || !(h >= 0.0) || !isfinite(h)) return ETD_ERR_INVALID;
   if ((rho && c->var_mode) || c->species > 1) return ETD_ERR_INVALID;
   if (rho) {
-    if (!c->have_geometry) {
-      int r = etd_geometry_build(c, rho);
-      if (r) return r;
-    }
-    if (!first) {
-      // F_{n-1} extended from the computational points of the current rho
-      c->lsb.h_inst[0] = levelset_inst(c, rho, f_prev);
-      HIP_TRY(timer_begin(c->profiling, c->stream, c->t_levelset));
-      HIP_TRY(levelset_extend(c->lsb, c->stream));
-      HIP_TRY(timer_end(c->profiling, c->stream, c->t_levelset));
-      HIP_TRY(hipStreamSynchronize(c->stream));   // h_inst is refilled next
-    }
-    int r = levelset_advance(c, rho, u, h, reinit);
+    // F_{n-1} extended with u from the computational points of the current
+    // rho, in the same launches
+    int r = advance_fields(c, rho, u, first ? nullptr : f_prev, h, reinit);
     if (r) return r;
   }
   if (!c->have_geometry) return ETD_ERR_NO_GEOMETRY;
@@ -1397,8 +1395,10 @@ static int upload_ptrs(etd_batch* B, double* const* u, double* const* f) {
 
 // Level-set Steps 1-2a of every instance in shared launches (one
 // synchronisation), then the geometry of the moved boundaries.
-static int batch_levelset(etd_batch* B, double h, double* const* u, double* const* rho, int32_t reinit) {
-  for (int i = 0; i < B->count; ++i) B->lsb.h_inst[i] = levelset_inst(B->inst[i], rho[i], u[i]);
+static int batch_levelset(etd_batch* B, double h, double* const* u, double* const* rho, int32_t reinit,
+                          double* const* f = nullptr) {
+  for (int i = 0; i < B->count; ++i)
+    B->lsb.h_inst[i] = levelset_inst(B->inst[i], rho[i], u[i], f ? f[i] : nullptr);
   HIP_TRY(timer_begin(B->profiling, B->stream, B->t_levelset));
   HIP_TRY(levelset_begin(B->lsb, h, reinit, B->stream));
   HIP_TRY(hipStreamSynchronize(B->stream));
@@ -1454,16 +1454,9 @@ int etd_batch_multistep_step(etd_batch* B, double h, double* const* u, double* c
     bool all = true;
     for (etd_ctx* c : B->inst) all &= c->have_geometry;
     if (!all && (r = etd_batch_geometry_build(B, rho))) return r;
-    if (!first) {
-      // F_{n-1} of every instance extended from the computational points of
-      // its current rho, in shared launches
-      for (int i = 0; i < B->count; ++i) B->lsb.h_inst[i] = levelset_inst(B->inst[i], rho[i], f_prev[i]);
-      HIP_TRY(timer_begin(B->profiling, B->stream, B->t_levelset));
-      HIP_TRY(levelset_extend(B->lsb, B->stream));
-      HIP_TRY(timer_end(B->profiling, B->stream, B->t_levelset));
-      HIP_TRY(hipStreamSynchronize(B->stream));   // h_inst is refilled next
-    }
-    if ((r = batch_levelset(B, h, u, rho, reinit))) return r;
+    // F_{n-1} of every instance extended with its u from the computational
+    // points of its current rho, in the same launches
+    if ((r = batch_levelset(B, h, u, rho, reinit, first ? nullptr : f_prev))) return r;
   }
   for (etd_ctx* c : B->inst)
     if (!c->have_geometry) return ETD_ERR_NO_GEOMETRY;

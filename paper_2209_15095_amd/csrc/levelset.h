@@ -97,7 +97,7 @@ constexpr int LS_VMAX_SLOTS = 64;
 // whole box first.
 struct LevelsetScratch {
   size_t nodes = 0;
-  double* buf = nullptr;      // 12 box arrays of doubles
+  double* buf = nullptr;      // 16 box arrays of doubles
   uint8_t* known = nullptr;   // bit 0: K0, bit 1: K1, bit 2: K2, bit 3: speed band, bit 4: reinit band
   uint8_t* dist = nullptr;    // L1 distance to the computational points, capped (LS_READ_REACH + 1 beyond)
   bool dirty = true;          // host flag: some node outside its list U may hold a nonzero value
@@ -113,6 +113,10 @@ struct LsInst {
   double h, mu;
   double* rho;                // user arrays (updated in place)
   double* u;
+  // A second box field extended with u in the same launches, or null:
+  // F(U_{n-1}) of ETD2 multistep, known on the same computational points;
+  // replaced by its extension within the reach of those points, 0 beyond.
+  double* f;
   double* buf;                // LevelsetScratch::buf
   size_t nodes;
   uint8_t* known;
@@ -124,7 +128,7 @@ struct LsInst {
   const int* cnt;             // the instance's geometry counters (list sizes, on the device)
   double* vmax;               // set by levelset_begin
   double* vslot;              // LS_VMAX_SLOTS partial maxima (0 between passes)
-  int dirty;                  // set by levelset_begin / levelset_extend: clear the whole box first
+  int dirty;                  // set by levelset_begin (and levelset_upload): clear the whole box first
   bool* host_dirty;           // LevelsetScratch::dirty (host address, never read on the device)
 };
 
@@ -143,6 +147,7 @@ struct LevelsetBatch {
   double dt = 0.0;
   int reinit = 0;
   int uext = 0;               // scratch array holding u_ext after levelset_begin
+  int nf = 1;                 // fields extended: 2 when some instance has f
   bool any_dirty = false;     // some instance's scratch is cleared over the whole box first
   // Device-sized mode (for graph capture): the launch rows come from the
   // geometry counters on the device, every launch has a fixed grid, the
@@ -159,21 +164,17 @@ hipError_t levelset_batch_alloc(LevelsetBatch& b, int count, int dim);
 void levelset_batch_free(LevelsetBatch& b);
 
 // Steps 1 + 2a for every instance of b (h_inst filled by the caller; rho and
-// u updated in place): levelset_begin enqueues everything up to the maximum
-// speeds and their asynchronous copy to pinned memory; after the caller has
-// synchronised the stream, levelset_end enqueues the advection substeps, the
-// reinitialisation (if reinit) and the restriction of u.
+// u, and f where given, updated in place): levelset_begin enqueues
+// everything up to the maximum speeds and their asynchronous copy to pinned
+// memory; after the caller has synchronised the stream, levelset_end
+// enqueues the advection substeps, the reinitialisation (if reinit) and the
+// restriction of u (and of f).  Nothing the caller passed changes before
+// levelset_end.
 hipError_t levelset_begin(LevelsetBatch& b, double dt, int reinit, hipStream_t stream);
 // Device-sized mode: copy the instance table (h_inst, with dirty flags
 // taken as for a pass) to the device and clear every dirty scratch; the
 // caller synchronises the stream before capturing levelset_begin/end.
 hipError_t levelset_upload(LevelsetBatch& b, hipStream_t stream);
 hipError_t levelset_end(LevelsetBatch& b, hipStream_t stream);
-// The extrapolation of Step 2 alone (the same sweeps as for u): each
-// instance's u (any box field known on the computational points of rho) is
-// replaced, over the whole box, by its quadratic normal extrapolation from
-// those points; rho is not changed.  The caller synchronises the stream
-// before it refills h_inst.
-hipError_t levelset_extend(LevelsetBatch& b, hipStream_t stream);
 
 }  // namespace etdfb

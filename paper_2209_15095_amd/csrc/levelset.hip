@@ -30,9 +30,11 @@ namespace {
 
 constexpr double WENO_EPS = 1e-6;
 
-// box arrays of LevelsetScratch::buf
+// box arrays of LevelsetScratch::buf; the second field's extension arrays
+// (LsInst::f) sit FOFF after the first's (F0..F3 for E0..E3)
 enum { A_NX = 0, A_NY = 1, A_NZ = 2, A_E0 = 3, A_E1 = 4, A_E2 = 5, A_E3 = 6, A_V = 7,
-       A_R0 = 8, A_R1 = 9, A_R2 = 10, A_S = 11, A_COUNT = 12 };
+       A_R0 = 8, A_R1 = 9, A_R2 = 10, A_S = 11, A_F0 = 12, A_F1 = 13, A_F2 = 14, A_F3 = 15, A_COUNT = 16 };
+constexpr int FOFF = A_F0 - A_E0;
 
 struct Where {
   const LsInst* I;
@@ -137,11 +139,13 @@ __global__ __launch_bounds__(256) void zero_kernel(const LsInst* __restrict__ in
     if (!w.in) continue;
     for (int a = A_E0; a <= A_V; ++a) arr(I, a)[w.id] = 0.0;
     arr(I, A_S)[w.id] = 0.0;
+    for (int a = A_F0; a <= A_F3; ++a) arr(I, a)[w.id] = 0.0;
     glb(I.dist)[w.id] = 255;
   }
 }
 
-// list U: normals, K0 (bit 0, other bits cleared), E0 = K0 ? u : 0
+// list U: normals, K0 (bit 0, other bits cleared), E0 = K0 ? u : 0 (and
+// F0 = K0 ? f : 0)
 template <int DIM>
 __global__ __launch_bounds__(256) void init_kernel(const LsInst* __restrict__ insts, const int* __restrict__ off,
                                                    int count) {
@@ -160,6 +164,7 @@ __global__ __launch_bounds__(256) void init_kernel(const LsInst* __restrict__ in
     glb(I.known)[w.id] = c ? 1 : 0;
     glb(I.dist)[w.id] = c ? 0 : 255;
     arr(I, A_E0)[w.id] = c ? glb((const double*)I.u)[w.id] : 0.0;
+    if (I.f) arr(I, A_F0)[w.id] = c ? glb((const double*)I.f)[w.id] : 0.0;
   }
 }
 
@@ -201,7 +206,7 @@ __global__ __launch_bounds__(256) void known1_kernel(const LsInst* __restrict__ 
   }
 }
 
-// list A1: K2 (bit 2) and E1 = K1 ? n . grad E0 : 0
+// list A1: K2 (bit 2) and E1 = K1 ? n . grad E0 : 0 (F1 likewise)
 template <int DIM>
 __global__ __launch_bounds__(256) void known2_un_kernel(const LsInst* __restrict__ insts,
                                                         const int* __restrict__ off, int count) {
@@ -212,10 +217,11 @@ __global__ __launch_bounds__(256) void known2_un_kernel(const LsInst* __restrict
     const bool k1 = (glb((const uint8_t*)I.known)[w.id] >> 1) & 1;
     if (known_all<DIM>(I, w, 1)) glb(I.known)[w.id] |= (uint8_t)4;
     arr(I, A_E1)[w.id] = k1 ? dir_deriv<DIM>(I, w, arr(I, A_E0)) : 0.0;
+    if (I.f) arr(I, A_F1)[w.id] = k1 ? dir_deriv<DIM>(I, w, arr(I, A_F0)) : 0.0;
   }
 }
 
-// list A1: E2 = K2 ? n . grad E1 : 0
+// list A1: E2 = K2 ? n . grad E1 : 0 (F2 likewise)
 template <int DIM>
 __global__ __launch_bounds__(256) void unn_kernel(const LsInst* __restrict__ insts, const int* __restrict__ off,
                                                   int count) {
@@ -225,6 +231,7 @@ __global__ __launch_bounds__(256) void unn_kernel(const LsInst* __restrict__ ins
     const LsInst& I = *w.I;
     const bool k2 = (glb((const uint8_t*)I.known)[w.id] >> 2) & 1;
     arr(I, A_E2)[w.id] = k2 ? dir_deriv<DIM>(I, w, arr(I, A_E1)) : 0.0;
+    if (I.f) arr(I, A_F2)[w.id] = k2 ? dir_deriv<DIM>(I, w, arr(I, A_F1)) : 0.0;
   }
 }
 
@@ -254,8 +261,10 @@ inline int ext_grid(int total) {
 // is already exact that far.  A block serves NPT consecutive tiles of the
 // launch row (one node of each per thread); the loads of all of them are
 // issued before the arithmetic (the update is computed everywhere and
-// selected off the known set).
-template <int DIM, int NPT>
+// selected off the known set).  With NF == 2 the instances with a second
+// field (LsInst::f) sweep it in the same launch, on the arrays FOFF after
+// v, out and src, with the same normals, known set and cone.
+template <int DIM, int NPT, int NF>
 __global__ __launch_bounds__(256) void extend_kernel(const LsInst* __restrict__ insts, const int* __restrict__ off,
                                                      int count, int row, int v_arr, int out_arr, int src_arr,
                                                      int bit, int sign_rho, int do_max, int dil, int cone) {
@@ -308,43 +317,58 @@ __global__ __launch_bounds__(256) void extend_kernel(const LsInst* __restrict__ 
       act[q] = cone < 0 || m[q] <= cone;
     }
     uint8_t kb[NPT];
-    double vc[NPT], vm[NPT][DIM], vp[NPT][DIM], nd[NPT][DIM], sr[NPT], rr[NPT];
+    double vc[NF][NPT], vm[NF][NPT][DIM], vp[NF][NPT][DIM], nd[NPT][DIM], sr[NF][NPT], rr[NPT];
+    bool two[NPT];
   #pragma unroll
     for (int q = 0; q < NPT; ++q) {
+      two[q] = false;
       if (!act[q]) continue;
       const LsInst& I = *w[q].I;
-      gptr<const double> v = arr(I, v_arr);
+      two[q] = NF == 2 && I.f != nullptr;
       kb[q] = glb((const uint8_t*)I.known)[w[q].id];
-      vc[q] = v[w[q].id];
-      for (int d = 0; d < DIM; ++d) {
-        vm[q][d] = v[im[q][d]];
-        vp[q][d] = v[ip[q][d]];
-        nd[q][d] = arr(I, A_NX + d)[w[q].id];
-      }
-      sr[q] = (src_arr >= 0) ? arr(I, src_arr)[w[q].id] : 0.0;
+      for (int d = 0; d < DIM; ++d) nd[q][d] = arr(I, A_NX + d)[w[q].id];
       rr[q] = sign_rho ? glb((const double*)I.rho)[w[q].id] : 1.0;
+  #pragma unroll
+      for (int fi = 0; fi < NF; ++fi) {
+        if (fi == 1 && !two[q]) break;
+        gptr<const double> v = arr(I, v_arr + fi * FOFF);
+        vc[fi][q] = v[w[q].id];
+        for (int d = 0; d < DIM; ++d) {
+          vm[fi][q][d] = v[im[q][d]];
+          vp[fi][q][d] = v[ip[q][d]];
+        }
+        sr[fi][q] = (src_arr >= 0) ? arr(I, src_arr + fi * FOFF)[w[q].id] : 0.0;
+      }
     }
-    double res[NPT];
+    double res[NF][NPT];
   #pragma unroll
     for (int q = 0; q < NPT; ++q) {
-      res[q] = 0.0;
+  #pragma unroll
+      for (int fi = 0; fi < NF; ++fi) res[fi][q] = 0.0;
       if (!act[q]) continue;
       const LsInst& I = *w[q].I;
       const double sg = (rr[q] > 0.0) ? 1.0 : ((rr[q] < 0.0) ? -1.0 : 0.0);
-      double up = 0.0;
-      for (int d = 0; d < DIM; ++d) {
-        const double a = sg * nd[q][d];
-        up += fmax(a, 0.0) * (vc[q] - vm[q][d]) + fmin(a, 0.0) * (vp[q][d] - vc[q]);
+  #pragma unroll
+      for (int fi = 0; fi < NF; ++fi) {
+        if (fi == 1 && !two[q]) break;
+        double up = 0.0;
+        for (int d = 0; d < DIM; ++d) {
+          const double a = sg * nd[q][d];
+          up += fmax(a, 0.0) * (vc[fi][q] - vm[fi][q][d]) + fmin(a, 0.0) * (vp[fi][q][d] - vc[fi][q]);
+        }
+        up = up / I.h;
+        const double upd = vc[fi][q] - (0.5 * I.h) * (up - sr[fi][q]);
+        res[fi][q] = ((kb[q] >> bit) & 1) ? vc[fi][q] : upd;
       }
-      up = up / I.h;
-      const double upd = vc[q] - (0.5 * I.h) * (up - sr[q]);
-      res[q] = ((kb[q] >> bit) & 1) ? vc[q] : upd;
     }
   #pragma unroll
     for (int q = 0; q < NPT; ++q) {
       if (!w[q].in) continue;
       const LsInst& I = *w[q].I;
-      if (act[q]) arr(I, out_arr)[w[q].id] = res[q];
+      if (act[q]) {
+        arr(I, out_arr)[w[q].id] = res[0][q];
+        if (two[q]) arr(I, out_arr + FOFF)[w[q].id] = res[NF - 1][q];
+      }
       if (dil) glb(I.dist)[w[q].id] = (uint8_t)min(m[q], 255);
     }
     if (do_max) {
@@ -352,7 +376,7 @@ __global__ __launch_bounds__(256) void extend_kernel(const LsInst* __restrict__ 
       __shared__ double sm[256];
       for (int q = 0; q < NPT; ++q) {
         if (bx * NPT + q >= total) break;   // uniform over the block
-        sm[threadIdx.x] = act[q] ? res[q] : 0.0;
+        sm[threadIdx.x] = act[q] ? res[0][q] : 0.0;
         __syncthreads();
         for (int st = 128; st > 0; st >>= 1) {
           if ((int)threadIdx.x < st) sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + st]);
@@ -373,24 +397,27 @@ __global__ __launch_bounds__(256) void extend_kernel(const LsInst* __restrict__ 
 // normals, source, known bit, sign of rho), sweeps there (the valid region
 // shrinks by one node per sweep) and writes the tile.  Halo nodes outside the
 // stage's list hold their whole-box values (0, see levelset.h), so the tile
-// gets exactly the values of `nsweep` single sweeps.
+// gets exactly the values of `nsweep` single sweeps.  With NF == 2 the
+// instances with a second field sweep it alongside (arrays FOFF after v,
+// out and src; the same normals, known set and signs).
 constexpr int SWEEP_GROUP = 5;
 
+template <int NF>
 __global__ __launch_bounds__(256) void extend_group_kernel(const LsInst* __restrict__ insts,
                                                            const int* __restrict__ off, int count, int row,
                                                            int v_arr, int out_arr, int src_arr, int bit,
                                                            int sign_rho, int do_max, int nsweep, int dil) {
   constexpr int X = TileShape<2>::X, Y = TileShape<2>::Y, K = SWEEP_GROUP;
   constexpr int RW = X + 2 * K, RH = Y + 2 * K, RN = RW * RH;
-  __shared__ double va[RN], vb[RN], snx[RN], sny[RN], ssrc[RN];
+  __shared__ double va[NF][RN], vb[NF][RN], ssrc[NF][RN], snx[RN], sny[RN];
   __shared__ uint8_t sfl[RN];   // bit 0: in the box, bit 1: known, bits 2-3: sign(rho) + 1
   __shared__ uint8_t sd[2][RN]; // dil: the distance to the computational points (dilated with the sweeps)
   __shared__ double sm[256];
   FOR_VBLOCKS(row) {
     const Where w = locate_at<2>(insts, off, count, row, vb_);
     const LsInst& I = *w.I;
+    const int nf = (NF == 2 && I.f != nullptr) ? 2 : 1;   // uniform over the block
     const int ox = w.i - (int)(threadIdx.x % X), oy = w.j - (int)(threadIdx.x / X);   // tile origin
-    gptr<const double> v = arr(I, v_arr);
     gptr<const double> nxg = arr(I, A_NX);
     gptr<const double> nyg = arr(I, A_NY);
     gptr<const uint8_t> kn = glb((const uint8_t*)I.known);
@@ -398,13 +425,19 @@ __global__ __launch_bounds__(256) void extend_group_kernel(const LsInst* __restr
     for (int r = threadIdx.x; r < RN; r += blockDim.x) {
       const int gi = ox - K + r % RW, gj = oy - K + r / RW;
       uint8_t f = 0;
-      double x = 0.0, a = 0.0, b = 0.0, sc = 0.0;
+      double x[NF], sc[NF], a = 0.0, b = 0.0;
+#pragma unroll
+      for (int fi = 0; fi < NF; ++fi) { x[fi] = 0.0; sc[fi] = 0.0; }
       if (gi >= 0 && gi < I.nx && gj >= 0 && gj < I.ny) {
         const size_t id = (size_t)gj * I.nx + gi;
-        x = v[id];
+#pragma unroll
+        for (int fi = 0; fi < NF; ++fi) {
+          if (fi >= nf) break;
+          x[fi] = arr(I, v_arr + fi * FOFF)[id];
+          sc[fi] = (src_arr >= 0) ? arr(I, src_arr + fi * FOFF)[id] : 0.0;
+        }
         a = nxg[id];
         b = nyg[id];
-        sc = (src_arr >= 0) ? arr(I, src_arr)[id] : 0.0;
         f = 1 | ((((kn[id] >> bit) & 1) != 0) ? 2 : 0);
         if (sign_rho) {
           const double rr = rho[id];
@@ -413,22 +446,23 @@ __global__ __launch_bounds__(256) void extend_group_kernel(const LsInst* __restr
           f |= (uint8_t)(2 << 2);
         }
       }
-      va[r] = x;
+#pragma unroll
+      for (int fi = 0; fi < NF; ++fi) {
+        va[fi][r] = x[fi];
+        ssrc[fi][r] = sc[fi];
+      }
       snx[r] = a;
       sny[r] = b;
-      ssrc[r] = sc;
       sfl[r] = f;
       if (dil) sd[0][r] = (f & 1) ? glb((const uint8_t*)I.dist)[(size_t)gj * I.nx + gi] : (uint8_t)255;
     }
     __syncthreads();
     const double dt = 0.5 * I.h;
-    double* cur = va;
-    double* nxt = vb;
+    double (*cur)[RN] = va;
+    double (*nxt)[RN] = vb;
     for (int s = 0; s < nsweep; ++s) {
       for (int r = threadIdx.x; r < RN; r += blockDim.x) {
         const uint8_t f = sfl[r];
-        const double vc = cur[r];
-        double res = vc;
         const int x = r % RW, y = r / RW;
         const int gi = ox - K + x, gj = oy - K + y;
         // neighbours, clamped at the box edge; outside the region: the node itself
@@ -443,23 +477,30 @@ __global__ __launch_bounds__(256) void extend_group_kernel(const LsInst* __restr
           m = min(m, min(min((int)dc[rxm], (int)dc[rxp]), min((int)dc[rym], (int)dc[ryp])) + 1);
           sd[(s + 1) & 1][r] = (uint8_t)min(m, 255);
         }
-        if ((f & 1) && !(f & 2)) {
-          const double sg = (double)((f >> 2) & 3) - 1.0;
-          const double ax = sg * snx[r], ay = sg * sny[r];
-          double up = fmax(ax, 0.0) * (vc - cur[rxm]) + fmin(ax, 0.0) * (cur[rxp] - vc);
-          up += fmax(ay, 0.0) * (vc - cur[rym]) + fmin(ay, 0.0) * (cur[ryp] - vc);
-          up = up / I.h;
-          res = vc - dt * (up - ssrc[r]);
+#pragma unroll
+        for (int fi = 0; fi < NF; ++fi) {
+          if (fi >= nf) break;
+          const double vc = cur[fi][r];
+          double res = vc;
+          if ((f & 1) && !(f & 2)) {
+            const double sg = (double)((f >> 2) & 3) - 1.0;
+            const double ax = sg * snx[r], ay = sg * sny[r];
+            double up = fmax(ax, 0.0) * (vc - cur[fi][rxm]) + fmin(ax, 0.0) * (cur[fi][rxp] - vc);
+            up += fmax(ay, 0.0) * (vc - cur[fi][rym]) + fmin(ay, 0.0) * (cur[fi][ryp] - vc);
+            up = up / I.h;
+            res = vc - dt * (up - ssrc[fi][r]);
+          }
+          nxt[fi][r] = res;
         }
-        nxt[r] = res;
       }
       __syncthreads();
-      double* t = cur; cur = nxt; nxt = t;
+      double (*t)[RN] = cur; cur = nxt; nxt = t;
     }
     const int l = threadIdx.x;
     const int rl = (l / X + K) * RW + (l % X + K);
-    const double res = cur[rl];
+    const double res = cur[0][rl];
     if (w.in) arr(I, out_arr)[w.id] = res;
+    if (w.in && nf == 2) arr(I, out_arr + FOFF)[w.id] = cur[NF - 1][rl];
     if (w.in && dil) glb(I.dist)[w.id] = sd[nsweep & 1][rl];
     if (do_max) {
       sm[threadIdx.x] = w.in ? res : 0.0;
@@ -533,6 +574,7 @@ __global__ __launch_bounds__(256) void velocity_kernel(const LsInst* __restrict_
     arr(I, A_V)[w.id] = v;
   }
 }
+
 
 // ------------------------------------------------------------ Step 2: WENO
 
@@ -649,18 +691,18 @@ __global__ __launch_bounds__(256) void rk_kernel(const LsInst* __restrict__ inst
 }
 
 // whole box: u = comp(rho_new) ? u_ext : 0 (a computational point beyond
-// the reach of the extension: ST_FRONT), or (all) u = u_ext within the reach
-// of the extension and 0 beyond (what the step reads of it).  Outside list U
-// (Dc > LS_C_MAX and Dv > LS_V_MAX) both are 0 without a read: rho changes
-// only on list R, inside U, so a tile outside U holds no computational point
-// of the new rho, and no node within the reach.  Then the pass's own writes
-// are cleared: on the tiles of U the extension arrays, the speed and its
-// partner go to 0 and the distance to 255 (each thread reads and clears its
-// own node only), and the maximum speed to 0.
+// the reach of the extension: ST_FRONT), and a second field f = f_ext
+// within the reach of the extension and 0 beyond (what the step reads of
+// it).  Outside list U (Dc > LS_C_MAX and Dv > LS_V_MAX) both are 0
+// without a read: rho changes only on list R, inside U, so a tile outside U
+// holds no computational point of the new rho, and no node within the
+// reach.  Then the pass's own writes are cleared: on the tiles of U the
+// extension arrays, the speed and its partner go to 0 and the distance to
+// 255 (each thread reads and clears its own node only), and the maximum
+// speed to 0.
 template <int DIM>
 __global__ __launch_bounds__(256) void restrict_kernel(const LsInst* __restrict__ insts,
-                                                       const int* __restrict__ off, int count, int uext_arr,
-                                                       int all) {
+                                                       const int* __restrict__ off, int count, int uext_arr) {
   FOR_VBLOCKS(LS_ROW_FULL) {
     const Where w = locate_at<DIM>(insts, off, count, LS_ROW_FULL, vb_);
     const LsInst& I = *w.I;
@@ -669,19 +711,19 @@ __global__ __launch_bounds__(256) void restrict_kernel(const LsInst* __restrict_
     const int td = I.tdist[w.local];
     if ((td & 0xFFFF) > LS_C_MAX && (td >> 16) > LS_V_MAX) {
       glb(I.u)[w.id] = 0.0;
+      if (I.f) glb(I.f)[w.id] = 0.0;
       continue;
     }
     const bool reach = in_reach(I, w.id);
-    bool c;
-    if (all) {
-      c = reach;
-    } else {
-      c = comp_point<DIM>(I, w, glb((const double*)I.rho));
-      if (c && !reach) atomicCAS(I.status, 0, ST_FRONT);
-    }
+    const bool c = comp_point<DIM>(I, w, glb((const double*)I.rho));
+    if (c && !reach) atomicCAS(I.status, 0, ST_FRONT);
     glb(I.u)[w.id] = c ? arr(I, uext_arr)[w.id] : 0.0;
     for (int a = A_E0; a <= A_V; ++a) arr(I, a)[w.id] = 0.0;
     arr(I, A_S)[w.id] = 0.0;
+    if (I.f) {
+      glb(I.f)[w.id] = reach ? arr(I, uext_arr + FOFF)[w.id] : 0.0;
+      for (int a = A_F0; a <= A_F3; ++a) arr(I, a)[w.id] = 0.0;
+    }
     glb(I.dist)[w.id] = 255;
   }
 }
@@ -743,7 +785,7 @@ void mark_clean(LevelsetBatch& b) {
 }
 
 template <int DIM>
-hipError_t begin_dim(LevelsetBatch& b, hipStream_t st, bool speed) {
+hipError_t begin_dim(LevelsetBatch& b, hipStream_t st) {
   const int n = b.count;
   const LsInst* I = b.d_inst;
   const int* off = b.d_off;
@@ -774,20 +816,29 @@ hipError_t begin_dim(LevelsetBatch& b, hipStream_t st, bool speed) {
   //   u shrinks to the read region:  radius LS_READ_REACH + ASLAM_ITERS - s0 + 1
   //   the speed grows from |rho| < h: SV radius s1
   const int group = (DIM == 2) ? SWEEP_GROUP : 1;
+  // nf: fields swept (2: also the second field of the instances that have
+  // one, on the arrays FOFF after a0, a1, src)
   auto stage = [&](auto row, auto cone, int a0, int a1, int src, int bit, int sign_rho, int sweeps, int do_max,
-                   int dil) -> int {
+                   int dil, int nf) -> int {
     int v = a0, t = a1;
     for (int done = 0; done < sweeps;) {
       const int ns = (sweeps - done < group) ? sweeps - done : group;
       const int mx = (do_max && done + ns == sweeps) ? 1 : 0;
       const int r = row(done + 1, done + ns);
       if (grid(r) > 0) {
-        if (DIM == 2)
-          hipLaunchKernelGGL(extend_group_kernel, dim3(grid(r)), B, 0, st, I, off, n, r, v, t, src, bit, sign_rho, mx,
-                             ns, dil);
+        const dim3 g3(dev ? device_grid(b, r) : ext_grid(b.total[r]));
+        if (DIM == 2 && nf == 2)
+          hipLaunchKernelGGL(extend_group_kernel<2>, dim3(grid(r)), B, 0, st, I, off, n, r, v, t, src, bit, sign_rho,
+                             mx, ns, dil);
+        else if (DIM == 2)
+          hipLaunchKernelGGL(extend_group_kernel<1>, dim3(grid(r)), B, 0, st, I, off, n, r, v, t, src, bit, sign_rho,
+                             mx, ns, dil);
+        else if (nf == 2)
+          hipLaunchKernelGGL((extend_kernel<DIM, EXT_NPT, 2>), g3, B, 0, st, I, off, n, r, v, t, src, bit, sign_rho, mx,
+                             dil, cone(done + 1));
         else
-          hipLaunchKernelGGL((extend_kernel<DIM, EXT_NPT>), dim3(dev ? device_grid(b, r) : ext_grid(b.total[r])), B, 0,
-                             st, I, off, n, r, v, t, src, bit, sign_rho, mx, dil, cone(done + 1));
+          hipLaunchKernelGGL((extend_kernel<DIM, EXT_NPT, 1>), g3, B, 0, st, I, off, n, r, v, t, src, bit, sign_rho, mx,
+                             dil, cone(done + 1));
         if (hipGetLastError() != hipSuccess) return -1;
       }
       done += ns;
@@ -810,21 +861,21 @@ hipError_t begin_dim(LevelsetBatch& b, hipStream_t st, bool speed) {
   auto cap = [](int r) { return r < LS_C_MAX ? r : LS_C_MAX; };
   const bool nc = DIM == 3;
   auto no_cone = [](int) { return -1; };
+  const int nf = b.nf;
   const int unn = stage([&](int, int s1) { return LS_ROW_C + cap(s1); }, [&](int s) { return nc ? s : -1; }, A_E2, A_E3,
-                        -1, 2, 0, ASLAM_ITERS, 0, 1);
+                        -1, 2, 0, ASLAM_ITERS, 0, 1, nf);
   const int un = stage([&](int, int s1) { return LS_ROW_C + cap(ASLAM_ITERS + s1); },
                        [&](int s) { return nc ? ASLAM_ITERS + s : -1; }, A_E1, A_E2, A_E3, 1, 0, ASLAM_ITERS, 0,
-                       nc ? 1 : 0);
+                       nc ? 1 : 0, nf);
   const int uext = stage([&](int s0, int) { return LS_ROW_C + cap(LS_READ_REACH + ASLAM_ITERS - s0 + 1); },
                          [&](int s) { return nc ? LS_READ_REACH + ASLAM_ITERS - s + 1 : -1; }, A_E0, A_E1, A_E2, 0, 0,
-                         ASLAM_ITERS, 0, 0);
+                         ASLAM_ITERS, 0, 0, nf);
   if (unn != A_E3 || un != A_E2 || uext != A_E1) return hipErrorUnknown;
   b.uext = uext;
-  if (!speed) return hipSuccess;
   // Stefan speed, extension V <-> S (ends in V), maximum on the last sweep
   LL(LS_ROW_V + VEL_ITERS + 1, velocity_kernel, b.uext);
   auto vcap = [](int r) { return r < LS_V_MAX ? r : LS_V_MAX; };
-  if (stage([&](int, int s1) { return LS_ROW_V + vcap(s1); }, no_cone, A_V, A_S, -1, 3, 1, VEL_ITERS, 1, 0) != A_V)
+  if (stage([&](int, int s1) { return LS_ROW_V + vcap(s1); }, no_cone, A_V, A_S, -1, 3, 1, VEL_ITERS, 1, 0, 1) != A_V)
     return hipErrorUnknown;
   hipLaunchKernelGGL(vmax_fold_kernel, dim3(n), dim3(LS_VMAX_SLOTS), 0, st, I);
   if (hipGetLastError() != hipSuccess) return hipErrorUnknown;
@@ -873,7 +924,7 @@ hipError_t end_dim(LevelsetBatch& b, hipStream_t st) {
         }
     }
   }
-  hipLaunchKernelGGL(restrict_kernel<DIM>, dim3(grid(LS_ROW_FULL)), B, 0, st, I, off, n, b.uext, 0);
+  hipLaunchKernelGGL(restrict_kernel<DIM>, dim3(grid(LS_ROW_FULL)), B, 0, st, I, off, n, b.uext);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   mark_clean(b);
   return hipSuccess;
@@ -885,17 +936,6 @@ hipError_t zero_only(LevelsetBatch& b, hipStream_t st) {
   if (b.total[LS_ROW_FULL] > 0)
     hipLaunchKernelGGL(zero_kernel<DIM>, dim3(b.total[LS_ROW_FULL]), dim3(256), 0, st, b.d_inst, b.d_off, b.count);
   return hipGetLastError();
-}
-
-template <int DIM>
-hipError_t extend_dim(LevelsetBatch& b, hipStream_t st) {
-  hipError_t e = begin_dim<DIM>(b, st, false);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(restrict_kernel<DIM>, dim3(b.total[LS_ROW_FULL]), dim3(256), 0, st, b.d_inst, b.d_off, b.count,
-                     b.uext, 1);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
-  mark_clean(b);
-  return hipSuccess;
 }
 
 }  // namespace
@@ -972,8 +1012,10 @@ hipError_t upload(LevelsetBatch& b, hipStream_t st) {
     b.total[q] = acc;
   }
   b.any_dirty = false;
+  b.nf = 1;
   for (int i = 0; i < n; ++i) {
     LsInst& I = b.h_inst[i];
+    if (I.f) b.nf = 2;
     I.vmax = b.d_vmax + i;
     I.vslot = b.d_vslot + (size_t)LS_VMAX_SLOTS * i;
     // an instance without a host flag is always cleared first
@@ -1001,7 +1043,7 @@ hipError_t levelset_begin(LevelsetBatch& b, double dt, int reinit, hipStream_t s
   } else if ((e = upload(b, st)) != hipSuccess) {
     return e;
   }
-  e = (b.dim == 2) ? begin_dim<2>(b, st, true) : begin_dim<3>(b, st, true);
+  e = (b.dim == 2) ? begin_dim<2>(b, st) : begin_dim<3>(b, st);
   if (e != hipSuccess) return e;
   if (b.device_sized) {
     hipLaunchKernelGGL(front_check_kernel, dim3((b.count + 63) / 64), dim3(64), 0, st, b.d_inst, b.count, dt);
@@ -1030,12 +1072,6 @@ hipError_t levelset_upload(LevelsetBatch& b, hipStream_t st) {
     e = hipMemcpyAsync(b.d_inst, b.h_inst, sizeof(LsInst) * n, hipMemcpyHostToDevice, st);
   }
   return e;
-}
-
-hipError_t levelset_extend(LevelsetBatch& b, hipStream_t st) {
-  hipError_t e = upload(b, st);
-  if (e != hipSuccess) return e;
-  return (b.dim == 2) ? extend_dim<2>(b, st) : extend_dim<3>(b, st);
 }
 
 hipError_t levelset_end(LevelsetBatch& b, hipStream_t st) {
