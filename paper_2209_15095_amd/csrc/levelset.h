@@ -85,8 +85,13 @@ constexpr int LS_NCOUNTERS = LS_CNT_U + 1;
 // The maximum of the extended speed is gathered over this many slots per
 // instance (one device-scope atomic per tile, spread over the slots by
 // block, so that thousands of tiles do not queue on one address), then
-// folded into the instance's maximum by one small launch.
+// folded into the instance's maximum by one small launch; for short speed
+// lists (below LS_VMAX_SLOT_MIN tiles in every instance) the atomics go to
+// the maximum directly.
 constexpr int LS_VMAX_SLOTS = 64;
+// Below this many tiles in every instance's speed list the atomics go to
+// the maximum itself (no queue to speak of, and no fold launch).
+constexpr int LS_VMAX_SLOT_MIN = 512;
 
 // Box-sized scratch arrays of one instance.  Between passes the extension
 // arrays hold 0 and the distance 255 at every node (the whole-box values the
@@ -113,10 +118,6 @@ struct LsInst {
   double h, mu;
   double* rho;                // user arrays (updated in place)
   double* u;
-  // A second box field extended with u in the same launches, or null:
-  // F(U_{n-1}) of ETD2 multistep, known on the same computational points;
-  // replaced by its extension within the reach of those points, 0 beyond.
-  double* f;
   double* buf;                // LevelsetScratch::buf
   size_t nodes;
   uint8_t* known;
@@ -130,6 +131,10 @@ struct LsInst {
   double* vslot;              // LS_VMAX_SLOTS partial maxima (0 between passes)
   int dirty;                  // set by levelset_begin (and levelset_upload): clear the whole box first
   bool* host_dirty;           // LevelsetScratch::dirty (host address, never read on the device)
+  // A second box field extended with u in the same launches, or null:
+  // F(U_{n-1}) of ETD2 multistep, known on the same computational points;
+  // replaced by its extension within the reach of those points, 0 beyond.
+  double* f;
 };
 
 // Instance table and launch offsets of a batch of `count` instances.
@@ -148,6 +153,7 @@ struct LevelsetBatch {
   int reinit = 0;
   int uext = 0;               // scratch array holding u_ext after levelset_begin
   int nf = 1;                 // fields extended: 2 when some instance has f
+  int vmax_tiles = 0;         // largest speed list of an instance (tiles of the last speed sweep)
   bool any_dirty = false;     // some instance's scratch is cleared over the whole box first
   // Device-sized mode (for graph capture): the launch rows come from the
   // geometry counters on the device, every launch has a fixed grid, the

@@ -267,7 +267,8 @@ inline int ext_grid(int total) {
 template <int DIM, int NPT, int NF>
 __global__ __launch_bounds__(256) void extend_kernel(const LsInst* __restrict__ insts, const int* __restrict__ off,
                                                      int count, int row, int v_arr, int out_arr, int src_arr,
-                                                     int bit, int sign_rho, int do_max, int dil, int cone) {
+                                                     int bit, int sign_rho, int do_max, int dil, int cone,
+                                                     int nslot) {
   const int total = row_total(off, count, row);
   // XCD-contiguous ranges: workgroups go to the 8 XCDs in turn, so virtual
   // block v takes entry (v % 8) * chunk + v / 8 of the row (8 * chunk
@@ -384,7 +385,7 @@ __global__ __launch_bounds__(256) void extend_kernel(const LsInst* __restrict__ 
         }
         // max of non-negative doubles: integer order equals value order
         if (threadIdx.x == 0)
-          atomicMax((unsigned long long*)(w[q].I->vslot + (vx & (LS_VMAX_SLOTS - 1))),
+          atomicMax((unsigned long long*)(nslot > 1 ? w[q].I->vslot + (vx & (nslot - 1)) : w[q].I->vmax),
                     (unsigned long long)__double_as_longlong(sm[0]));
         __syncthreads();
       }
@@ -406,7 +407,8 @@ template <int NF>
 __global__ __launch_bounds__(256) void extend_group_kernel(const LsInst* __restrict__ insts,
                                                            const int* __restrict__ off, int count, int row,
                                                            int v_arr, int out_arr, int src_arr, int bit,
-                                                           int sign_rho, int do_max, int nsweep, int dil) {
+                                                           int sign_rho, int do_max, int nsweep, int dil,
+                                                           int nslot) {
   constexpr int X = TileShape<2>::X, Y = TileShape<2>::Y, K = SWEEP_GROUP;
   constexpr int RW = X + 2 * K, RH = Y + 2 * K, RN = RW * RH;
   __shared__ double va[NF][RN], vb[NF][RN], ssrc[NF][RN], snx[RN], sny[RN];
@@ -422,6 +424,12 @@ __global__ __launch_bounds__(256) void extend_group_kernel(const LsInst* __restr
     gptr<const double> nyg = arr(I, A_NY);
     gptr<const uint8_t> kn = glb((const uint8_t*)I.known);
     gptr<const double> rho = glb((const double*)I.rho);
+    gptr<const double> vg[NF], sg_[NF];
+#pragma unroll
+    for (int fi = 0; fi < NF; ++fi) {
+      vg[fi] = arr(I, v_arr + fi * FOFF);
+      sg_[fi] = arr(I, (src_arr >= 0 ? src_arr : v_arr) + fi * FOFF);
+    }
     for (int r = threadIdx.x; r < RN; r += blockDim.x) {
       const int gi = ox - K + r % RW, gj = oy - K + r / RW;
       uint8_t f = 0;
@@ -433,8 +441,8 @@ __global__ __launch_bounds__(256) void extend_group_kernel(const LsInst* __restr
 #pragma unroll
         for (int fi = 0; fi < NF; ++fi) {
           if (fi >= nf) break;
-          x[fi] = arr(I, v_arr + fi * FOFF)[id];
-          sc[fi] = (src_arr >= 0) ? arr(I, src_arr + fi * FOFF)[id] : 0.0;
+          x[fi] = vg[fi][id];
+          sc[fi] = (src_arr >= 0) ? sg_[fi][id] : 0.0;
         }
         a = nxg[id];
         b = nyg[id];
@@ -510,7 +518,7 @@ __global__ __launch_bounds__(256) void extend_group_kernel(const LsInst* __restr
         __syncthreads();
       }
       if (threadIdx.x == 0)
-        atomicMax((unsigned long long*)(I.vslot + (vb_ & (LS_VMAX_SLOTS - 1))),
+        atomicMax((unsigned long long*)(nslot > 1 ? I.vslot + (vb_ & (nslot - 1)) : I.vmax),
                   (unsigned long long)__double_as_longlong(sm[0]));
     }
     __syncthreads();   // LDS is restaged by the next virtual block
@@ -816,6 +824,9 @@ hipError_t begin_dim(LevelsetBatch& b, hipStream_t st) {
   //   u shrinks to the read region:  radius LS_READ_REACH + ASLAM_ITERS - s0 + 1
   //   the speed grows from |rho| < h: SV radius s1
   const int group = (DIM == 2) ? SWEEP_GROUP : 1;
+  // the maximum speed through the slots (and a fold) where some speed list
+  // is long, or its size is unknown when recorded
+  const int nslot = (dev || b.vmax_tiles >= LS_VMAX_SLOT_MIN) ? LS_VMAX_SLOTS : 1;
   // nf: fields swept (2: also the second field of the instances that have
   // one, on the arrays FOFF after a0, a1, src)
   auto stage = [&](auto row, auto cone, int a0, int a1, int src, int bit, int sign_rho, int sweeps, int do_max,
@@ -829,16 +840,16 @@ hipError_t begin_dim(LevelsetBatch& b, hipStream_t st) {
         const dim3 g3(dev ? device_grid(b, r) : ext_grid(b.total[r]));
         if (DIM == 2 && nf == 2)
           hipLaunchKernelGGL(extend_group_kernel<2>, dim3(grid(r)), B, 0, st, I, off, n, r, v, t, src, bit, sign_rho,
-                             mx, ns, dil);
+                             mx, ns, dil, nslot);
         else if (DIM == 2)
           hipLaunchKernelGGL(extend_group_kernel<1>, dim3(grid(r)), B, 0, st, I, off, n, r, v, t, src, bit, sign_rho,
-                             mx, ns, dil);
+                             mx, ns, dil, nslot);
         else if (nf == 2)
           hipLaunchKernelGGL((extend_kernel<DIM, EXT_NPT, 2>), g3, B, 0, st, I, off, n, r, v, t, src, bit, sign_rho, mx,
-                             dil, cone(done + 1));
+                             dil, cone(done + 1), nslot);
         else
           hipLaunchKernelGGL((extend_kernel<DIM, EXT_NPT, 1>), g3, B, 0, st, I, off, n, r, v, t, src, bit, sign_rho, mx,
-                             dil, cone(done + 1));
+                             dil, cone(done + 1), nslot);
         if (hipGetLastError() != hipSuccess) return -1;
       }
       done += ns;
@@ -877,8 +888,10 @@ hipError_t begin_dim(LevelsetBatch& b, hipStream_t st) {
   auto vcap = [](int r) { return r < LS_V_MAX ? r : LS_V_MAX; };
   if (stage([&](int, int s1) { return LS_ROW_V + vcap(s1); }, no_cone, A_V, A_S, -1, 3, 1, VEL_ITERS, 1, 0, 1) != A_V)
     return hipErrorUnknown;
-  hipLaunchKernelGGL(vmax_fold_kernel, dim3(n), dim3(LS_VMAX_SLOTS), 0, st, I);
-  if (hipGetLastError() != hipSuccess) return hipErrorUnknown;
+  if (nslot > 1) {
+    hipLaunchKernelGGL(vmax_fold_kernel, dim3(n), dim3(LS_VMAX_SLOTS), 0, st, I);
+    if (hipGetLastError() != hipSuccess) return hipErrorUnknown;
+  }
 #undef LL
   return hipSuccess;
 }
@@ -1013,9 +1026,12 @@ hipError_t upload(LevelsetBatch& b, hipStream_t st) {
   }
   b.any_dirty = false;
   b.nf = 1;
+  b.vmax_tiles = 0;
   for (int i = 0; i < n; ++i) {
     LsInst& I = b.h_inst[i];
     if (I.f) b.nf = 2;
+    const int nv = I.ncum_v[VEL_ITERS < LS_V_MAX ? VEL_ITERS : LS_V_MAX];
+    if (nv > b.vmax_tiles) b.vmax_tiles = nv;
     I.vmax = b.d_vmax + i;
     I.vslot = b.d_vslot + (size_t)LS_VMAX_SLOTS * i;
     // an instance without a host flag is always cleared first
