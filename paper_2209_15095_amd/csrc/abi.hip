@@ -247,7 +247,7 @@ GeomDev geom_view(const etd_ctx* c) {
   return g;
 }
 
-KrylovDev krylov_params(const etd_ctx* c, int mode) {
+KrylovDev krylov_params(const etd_ctx* c, int mode, int sync_master_min = SYNC_MASTER_MIN_BLOCKS) {
   KrylovDev P{};
   P.g = geom_view(c);
   P.ws = c->ws;
@@ -275,7 +275,7 @@ KrylovDev krylov_params(const etd_ctx* c, int mode) {
   if (const char* env = getenv("ETDFB_STAGE_MIN")) P.stage_min = atoi(env);
   // ETDFB_SYNC_MASTER overrides the block count from which block 0 alone
   // reduces at a grid synchronisation (tests force either form)
-  P.sync_master_min = SYNC_MASTER_MIN_BLOCKS;
+  P.sync_master_min = sync_master_min;
   if (const char* env = getenv("ETDFB_SYNC_MASTER")) P.sync_master_min = atoi(env);
   return P;
 }
@@ -1080,7 +1080,9 @@ int batch_schedule(const etd_batch* B, int ch, int mode, double h, KrylovDev* pa
   int blocks = 0;
   *coop = false;
   for (int i = 0; i < n; ++i) {
-    KrylovDev P = krylov_params(B->inst[i0 + i], mode);
+    // the groups of a batch keep the all-to-all synchronisation (measured
+    // faster on batch64 in every group size it has)
+    KrylovDev P = krylov_params(B->inst[i0 + i], mode, INT32_MAX);
     P.h = h;
     P.first = B->ms_first;
     if (B->stage_min >= 0) P.stage_min = B->stage_min;

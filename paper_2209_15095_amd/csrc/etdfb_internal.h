@@ -152,6 +152,7 @@ constexpr int STAGE_MIN_TILES = 2048;
 // more, but without every block hammering the same few cache lines, which
 // costs more once there are many blocks (ellipsoid192, about 150 blocks:
 // 7.8 -> 5.8 us per synchronisation; star512, 24 blocks: 3.4 -> 3.6 us).
+// The groups of a batched launch keep the all-to-all form.
 constexpr int SYNC_MASTER_MIN_BLOCKS = 64;
 
 // Status codes (mirror include/etdfb.h).
