@@ -297,9 +297,9 @@ int etd_step_forced(etd_ctx* ctx, int32_t scheme, double h, double* u, const dou
  * domain.  rho != NULL: free boundary as in etd_step; F_{n-1} is carried to
  * the points that join the domain by the quadratic normal extrapolation
  * from the old computational points that carries u (Section 4.3, Step 2,
- * the same sweeps), then levelset_advance(ctx, rho, u, h, reinit) runs
- * (ETD_ERR_FRONT as there; f_prev then holds the extension).  u: device box array,
- * updated in place.  ETD_ERR_INVALID (nothing done) for a NULL ctx, u or
+ * the same sweeps, in the same launches as u's within the level-set step
+ * of levelset_advance(ctx, rho, u, h, reinit); ETD_ERR_FRONT as there, with
+ * rho, u and f_prev unchanged).  u: device box array, updated in place.  ETD_ERR_INVALID (nothing done) for a NULL ctx, u or
  * f_prev, f_prev aliasing u or rho, or h negative or not finite;
  * ETD_ERR_NO_GEOMETRY for a frozen step before any geometry build. */
 int etd_multistep_step(etd_ctx* ctx, double h, double* u, double* f_prev, int32_t first, double* rho,

@@ -9,7 +9,8 @@
   and leave u untouched.
 * All-zero inputs: exactly 0 (the Krylov term vanishes, W_p = 0).
 * A free-boundary step refused for its front speed (2D and 3D) changes
-  nothing, and the steps after it match the oracle.
+  nothing, and the steps after it match the oracle; the same for an ETD2
+  multistep step, whose F(U_{n-1}) also stays unchanged.
 """
 import sys
 
@@ -169,3 +170,43 @@ def test_refused_step_then_steps_match_oracle(dim):
     assert np.abs(rg - rho).max() <= 1e-10
     assert err <= 1e-9
     assert np.all(ug[~op.comp] == 0.0)
+
+
+def test_refused_multistep_step_leaves_rho_u_f_unchanged():
+    """An ETD2 multistep free-boundary step whose speed would move the
+    front more than LS_MAX_FRONT_NODES nodes is refused (ETD_ERR_FRONT) with
+    rho, u and F(U_{n-1}) unchanged (F is extended with u in the level-set
+    pass and written only by its last launch); the steps that follow match
+    the oracle's multistep steps (fisher64, mu = 2, h = 0.05)."""
+    from oracle.freeboundary import multistep_step
+    from paper_2209_15095_amd._lib import ETD_ERR_FRONT, EtdError
+    from paper_2209_15095_amd.api import Context
+    w = inputs.fisher64()
+    g, rho, u, beta = w.grid, w.rho0.copy(), w.u0.copy(), w.beta
+    mu, h = 2.0, 0.05
+    og = Grid(g.dim, tuple(g.n), tuple(g.lo), tuple(g.hi))
+    ctx = Context(g.dim, g.n, g.lo, g.hi, beta=beta, mu=mu)
+    rd, ud, fd = dev(rho), dev(u), dev(np.zeros_like(u))
+    ctx.geometry_build(rd)
+    rho, u, fp, _ = multistep_step(og, rho, u, np.zeros_like(u), h, beta, mu, first=True, method="krylov")
+    ctx.multistep_step(h, ud, fd, True, rho=rd)
+    torch.cuda.synchronize()
+    before = [t.cpu().numpy() for t in (rd, ud, fd)]
+    say("refused multistep step (dt 2.0), then 2 steps of dt 0.05")
+    with pytest.raises(EtdError) as ei:
+        ctx.multistep_step(2.0, ud, fd, False, rho=rd)
+    assert ei.value.code == ETD_ERR_FRONT
+    torch.cuda.synchronize()
+    for t, b in zip((rd, ud, fd), before):
+        assert np.array_equal(t.cpu().numpy(), b)
+    for _ in range(2):
+        rho, u, fp, op = multistep_step(og, rho, u, fp, h, beta, mu, first=False, method="krylov")
+        ctx.multistep_step(h, ud, fd, False, rho=rd)
+    torch.cuda.synchronize()
+    rg, ug, fg = rd.cpu().numpy(), ud.cpu().numpy(), fd.cpu().numpy()
+    ctx.close()
+    erru = np.linalg.norm(ug[op.comp] - u[op.comp]) / np.linalg.norm(u[op.comp])
+    errf = np.linalg.norm(fg[op.comp] - fp[op.comp]) / np.linalg.norm(fp[op.comp])
+    say(f"  N {op.n} rho diff {np.abs(rg - rho).max():.3e}  u rel {erru:.3e}  f rel {errf:.3e}")
+    assert np.abs(rg - rho).max() <= 1e-10
+    assert erru <= 1e-9 and errf <= 1e-9
