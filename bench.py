@@ -49,9 +49,9 @@ PEAK_HBM_GBS = 8000.0
 # kernel has no entry, and its traffic is reported as null.
 MEASURED_TRAFFIC = {
     ("ellipsoid192", "909992ad4a5993c4"): 132.94e6,
-    ("star512", "2d3ed19dc73c5097"): 32.19e6,
-    ("disk4097", "2d3ed19dc73c5097"): 25.97e9,
-    ("sphere385", "2d3ed19dc73c5097"): 33.93e9,
+    ("star512", "909992ad4a5993c4"): 14.86e6,
+    ("disk4097", "909992ad4a5993c4"): 24.88e9,
+    ("sphere385", "909992ad4a5993c4"): 33.98e9,
 }
 
 
