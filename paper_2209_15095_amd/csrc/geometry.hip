@@ -779,6 +779,12 @@ hipError_t geom_batch_alloc(GeomBatch& gb, int count, int ncnt) {
 }
 
 void geom_batch_free(GeomBatch& gb) {
+  if (gb.side) {
+    (void)hipStreamSynchronize(gb.side);
+    (void)hipStreamDestroy(gb.side);
+  }
+  if (gb.fork) (void)hipEventDestroy(gb.fork);
+  if (gb.join) (void)hipEventDestroy(gb.join);
   if (gb.h_tab) (void)hipHostFree(gb.h_tab);
   if (gb.d_tab) (void)hipFree(gb.d_tab);
   if (gb.h_pre) (void)hipHostFree(gb.h_pre);
@@ -808,6 +814,10 @@ hipError_t geom_upload(GeomBatch& gb, hipStream_t s) {
   return hipMemcpyAsync(gb.d_tab, gb.h_tab, sizeof(GeomInst) * gb.count, hipMemcpyHostToDevice, s);
 }
 
+// Fewest tiles (summed over a table's instances) for which an eager build
+// runs the distance chain beside the scan chain.
+constexpr size_t GEOM_FORK_MIN_TILES = 16384;
+
 hipError_t launch_geometry(GeomBatch& gb, const int* radii, hipStream_t s, bool device_sized) {
   const int n = gb.count;
   hipError_t e = hipSuccess;
@@ -816,9 +826,27 @@ hipError_t launch_geometry(GeomBatch& gb, const int* radii, hipStream_t s, bool 
                      pre_of(gb, GEOM_PRE_T256), n);
   hipLaunchKernelGGL(classify_kernel, dim3(gb.blocks[GEOM_PRE_NODE]), dim3(256), 0, s, gb.d_tab,
                      pre_of(gb, GEOM_PRE_NODE), n);
-  hipLaunchKernelGGL(scan_tiles_kernel, dim3(n), dim3(1024), 0, s, gb.d_tab);
-  hipLaunchKernelGGL(tile_coeff_kernel, dim3(gb.blocks[GEOM_PRE_TILE]), dim3(256), 0, s, gb.d_tab,
-                     pre_of(gb, GEOM_PRE_TILE), n);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  // The two chains that follow the classification touch disjoint data (the
+  // scan and coefficients: tile map, slots, masks, diagonal weights,
+  // counters 0 and 2-4; the distances and lists: their scratch, the lists,
+  // the list counters).  Eager builds of large tables run the second on the
+  // side stream, joined before the counters are collected (the fork and
+  // join cost about 20 us, more than the overlap saves on small boxes);
+  // device-sized builds (graph capture) keep one stream.
+  size_t tiles = 0;
+  for (int i = 0; i < n; ++i) tiles += (size_t)gb.h_tab[i].ntiles;
+  hipStream_t s2 = s;
+  if (!device_sized && tiles >= GEOM_FORK_MIN_TILES) {
+    if (!gb.side) {
+      if ((e = hipStreamCreateWithFlags(&gb.side, hipStreamNonBlocking)) != hipSuccess) return e;
+      if ((e = hipEventCreateWithFlags(&gb.fork, hipEventDisableTiming)) != hipSuccess) return e;
+      if ((e = hipEventCreateWithFlags(&gb.join, hipEventDisableTiming)) != hipSuccess) return e;
+    }
+    if ((e = hipEventRecord(gb.fork, s)) != hipSuccess) return e;
+    if ((e = hipStreamWaitEvent(gb.side, gb.fork, 0)) != hipSuccess) return e;
+    s2 = gb.side;
+  }
   // tile radii of the distance passes: tiles k apart are >= (k-1) t + 1 nodes apart
   const int rmax = radii[0] > radii[1] ? radii[0] : radii[1];
   const BoxHost& b0 = gb.h_tab[0].b;
@@ -827,11 +855,20 @@ hipError_t launch_geometry(GeomBatch& gb, const int* radii, hipStream_t s, bool 
   int r[3];
   for (int a = 0; a < 3; ++a) r[a] = (rmax - 1) / t[a] + 1;
   for (int axis = 0; axis < dim; ++axis)
-    hipLaunchKernelGGL(band_dist_kernel, dim3(gb.blocks[GEOM_PRE_T256]), dim3(256), 0, s, gb.d_tab,
+    hipLaunchKernelGGL(band_dist_kernel, dim3(gb.blocks[GEOM_PRE_T256]), dim3(256), 0, s2, gb.d_tab,
                        pre_of(gb, GEOM_PRE_T256), n, axis, r[0], r[1], r[2], 1000);
-  hipLaunchKernelGGL(band_lists_kernel, dim3(n), dim3(1024), 0, s, gb.d_tab, dim - 1, radii[0], radii[1], radii[2],
+  hipLaunchKernelGGL(band_lists_kernel, dim3(n), dim3(1024), 0, s2, gb.d_tab, dim - 1, radii[0], radii[1], radii[2],
                      radii[3], radii[4]);
-  if ((e = hipGetLastError()) != hipSuccess || device_sized) return e;
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(scan_tiles_kernel, dim3(n), dim3(1024), 0, s, gb.d_tab);
+  hipLaunchKernelGGL(tile_coeff_kernel, dim3(gb.blocks[GEOM_PRE_TILE]), dim3(256), 0, s, gb.d_tab,
+                     pre_of(gb, GEOM_PRE_TILE), n);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if (s2 != s) {
+    if ((e = hipEventRecord(gb.join, s2)) != hipSuccess) return e;
+    if ((e = hipStreamWaitEvent(s, gb.join, 0)) != hipSuccess) return e;
+  }
+  if (device_sized) return hipSuccess;
   hipLaunchKernelGGL(collect_counters_kernel, dim3(blocks_for((size_t)n * gb.ncnt, 256)), dim3(256), 0, s,
                      gb.d_tab, n, gb.ncnt, gb.d_cnt);
   if ((e = hipGetLastError()) != hipSuccess) return e;

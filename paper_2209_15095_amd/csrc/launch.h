@@ -76,6 +76,12 @@ struct GeomBatch {
   int blocks[GEOM_NPRE] = {};    // launch sizes
   int* h_cnt = nullptr;          // collected counters (pinned), ncnt per instance
   int* d_cnt = nullptr;
+  // Eager builds of large tables run the level-set distance passes and
+  // lists on a stream of their own beside the tile scan and coefficients
+  // (both read only the classification); created on the first such build,
+  // default priority.
+  hipStream_t side = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
 };
 
 hipError_t geom_batch_alloc(GeomBatch& gb, int count, int ncnt);
